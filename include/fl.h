@@ -1,0 +1,173 @@
+/*
+ * fl.h -- C-ABI of the MI355X (gfx950) finite-difference integral fractional
+ * Laplacian library.
+ *
+ * Method: Duo & Zhang, "Accurate numerical methods for two and three
+ * dimensional integral fractional Laplacian with applications"
+ * (arXiv:1804.02718).  The operator (-Delta)^{alpha/2}, 0 < alpha < 2, on the
+ * box (a, a + N h)^d, d = 2 or 3, with u = 0 outside the box (the extended
+ * homogeneous Dirichlet condition of Sec. 2), is discretised by the paper's
+ * weighted-trapezoid scheme with splitting parameter gamma = 2 (the choice of
+ * its Sec. 5): the 2D scheme of Sec. 2 and the 3D scheme of Sec. 4.  The
+ * stiffness matrix A is symmetric positive definite multilevel Toeplitz
+ * (Sec. 2 block form, Sec. 4 three-level form) and is applied by circulant
+ * embedding and FFT.
+ *
+ * Conventions shared by every call:
+ *   - N >= 2 intervals per axis, n = N - 1 interior nodes per axis,
+ *     M = n^d unknowns.  A grid vector holds the values at the interior nodes
+ *     x_i = a + i h, i in [1, N-1]^d, flattened with the x index fastest (the
+ *     ordering of the paper's matrix form).  Boundary and exterior values are
+ *     0 and are not stored.
+ *   - Vector pointers are DEVICE pointers (hipMalloc'ed or torch CUDA
+ *     tensors) owned by the caller; the library never frees them.  Host
+ *     pointers are marked as such.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is ordered on that stream.  fl_apply returns without waiting for
+ *     the GPU; the solvers return after convergence, with `info` filled.
+ *   - An fl_op owns device workspaces: calls on one fl_op must not overlap
+ *     (use one fl_op per concurrent stream).
+ *   - Every call returns an fl_status; on error, fl_last_error() gives a
+ *     message (per thread) and no output has been modified unless stated.
+ */
+#ifndef FL_H
+#define FL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fl_op_s *fl_op;
+
+typedef enum {
+    FL_OK = 0,
+    FL_E_INVAL = 1,       /* invalid argument (nothing changed)                  */
+    FL_E_NOMEM = 2,       /* device allocation failed                            */
+    FL_E_DEVICE = 3,      /* a HIP runtime error                                 */
+    FL_E_NOCONV = 4,      /* iteration limit reached; output holds best iterate  */
+    FL_E_BREAKDOWN = 5,   /* NaN/Inf or p^T A p <= 0 in CG                       */
+    FL_E_UNSUPPORTED = 6  /* size outside the built kernel range                 */
+} fl_status;
+
+typedef enum { FL_FP64 = 0, FL_FP32 = 1 } fl_prec;
+
+typedef enum {
+    FL_SOLVE_AUTO = 0,    /* mixed-precision refinement                          */
+    FL_SOLVE_CG64 = 1,    /* plain conjugate gradients, FP64 matvec and vectors  */
+    FL_SOLVE_REFINE = 2,  /* FP64 residual refinement around FP32-matvec CG      */
+    FL_SOLVE_FPCG = 3     /* flexible PCG with the learned preconditioner        */
+} fl_solver;
+
+typedef struct {
+    int iters;            /* CG iterations (all inner iterations for REFINE)     */
+    int outer_iters;      /* FP64 residual evaluations / refinement steps        */
+    int fell_back;        /* 1 if the requested method fell back to FP64 CG      */
+    int status;           /* fl_status of the solve                              */
+    double relres;        /* final ||f - A u||_2 / ||f||_2, FP64 matvec          */
+    double seconds;       /* host wall time of the call                          */
+} fl_info;
+
+typedef struct {
+    int solver;           /* fl_solver                                           */
+    int max_iter;         /* total CG iteration cap; <= 0 selects 50 M^{1/d}+1000 */
+    int use_x0;           /* nonzero: u holds the initial guess on entry          */
+    int check_every;      /* iterations between host convergence checks; <= 0 auto */
+    double inner_tol;     /* REFINE: relative tolerance of each inner solve; <= 0 auto */
+} fl_solve_opts;
+
+typedef struct {
+    int d, N, n, P, Q;    /* dimension, intervals, interior nodes, FFT length, P/2+1 */
+    int64_t M;            /* unknowns n^d                                        */
+    double alpha, h, c;   /* fractional order, mesh size, c_{d,alpha}            */
+    double a0;            /* diagonal coefficient a_0 (A_ii = -c a_0)            */
+} fl_op_desc;
+
+/*
+ * fl_coeffs -- build the operator for (d, alpha, h, N).
+ * Computes on the GPU, in FP64: the element integrals of |xi|^{-(d+alpha-2)}
+ * (Sec. 2 elements I_ij, Sec. 4 elements I_ijk), the coefficients a_v of the
+ * scheme (Sec. 2 a_mn and a_00; Sec. 4 a_mns and a_000, the (1,1,1) origin
+ * correction read as -1 times the origin element as the gamma = 2 limit rule
+ * implies), the generator -c a_{|m|} of the Toeplitz matrix embedded in a
+ * circulant of length P >= 2n - 1 per axis (a power of two, zeros in the gap),
+ * and its FFT eigenvalues lambda (FP64 master, FP32 copy).
+ *   d: 2 or 3.  alpha: in (0, 2).  h > 0, finite.  N: 2 <= N <= 1024 (d = 2),
+ *   2 <= N <= 256 (d = 3).  *out receives a new handle (free with
+ *   fl_op_destroy).  Uses the current HIP device; synchronises before
+ *   returning.  Errors: FL_E_INVAL, FL_E_UNSUPPORTED, FL_E_NOMEM, FL_E_DEVICE.
+ */
+fl_status fl_coeffs(int d, double alpha, double h, int N, fl_op *out);
+
+/*
+ * fl_apply -- y = A u, the discrete fractional Laplacian (Sec. 2 2D scheme /
+ * Sec. 4 3D scheme), by zero-padded embedding, FFT, multiplication by lambda,
+ * inverse FFT and crop.  prec = FL_FP64: u, y are double*; FL_FP32: float*.
+ * u and y are device vectors of M entries and must not overlap.  Asynchronous
+ * on `stream`.  Errors: FL_E_INVAL (null/overlap/prec), FL_E_DEVICE.
+ */
+fl_status fl_apply(fl_op op, const void *u, void *y, int prec, void *stream);
+
+/*
+ * fl_poisson_solve -- solve A u = f (the fractional Poisson problem of
+ * Sec. 5.2 with u = 0 outside the box) to ||f - A u||_2 <= tol ||f||_2,
+ * checked with an FP64 residual.  f, u: device double vectors of M entries
+ * (u is overwritten; the initial guess is 0).  Uses FL_SOLVE_AUTO.
+ * tol > 0.  info (host, may be NULL) receives iteration counts and the
+ * final FP64 relative residual.  Returns FL_E_NOCONV if the cap is reached
+ * (u holds the last iterate), FL_E_BREAKDOWN on NaN/Inf.
+ */
+fl_status fl_poisson_solve(fl_op op, const double *f, double tol, double *u,
+                           fl_info *info, void *stream);
+
+/* As fl_poisson_solve, with explicit options (host pointer, may be NULL). */
+fl_status fl_poisson_solve_ex(fl_op op, const double *f, double tol, double *u,
+                              const fl_solve_opts *opts, fl_info *info, void *stream);
+
+/*
+ * fl_allen_cahn_step -- one semi-implicit step of
+ *     u_t = -eps^2 (-Delta)^{alpha/2} u + u - u^3,  u = 0 outside the box,
+ * Crank--Nicolson on the linear term (the time discretisation of Sec. 5.3),
+ * the cubic term explicit:
+ *     (I + tau eps^2 A / 2) u+ = u - tau eps^2 A u / 2 + tau (u - u^3),
+ * solved by CG with initial guess u (FP32-matvec CG inside FP64 residual
+ * refinement) to a relative FP64 residual of 1e-8.  u: device double vector
+ * of M entries, updated in place.  tau > 0, eps > 0.
+ */
+fl_status fl_allen_cahn_step(fl_op op, double *u, double tau, double eps,
+                             fl_info *info, void *stream);
+
+/* As fl_allen_cahn_step with theta in (0, 1] weighting the implicit part
+ * (theta = 1/2 Crank--Nicolson, theta = 1 backward Euler), solver tolerance
+ * tol > 0 and solver choice (FL_SOLVE_AUTO/REFINE or FL_SOLVE_CG64). */
+fl_status fl_allen_cahn_step_ex(fl_op op, double *u, double tau, double eps,
+                                double theta, double tol, int solver,
+                                fl_info *info, void *stream);
+
+/* Free the operator and its device workspaces.  NULL is accepted. */
+fl_status fl_op_destroy(fl_op op);
+
+/* Sizes and scalars of the operator (host struct). */
+fl_status fl_op_describe(fl_op op, fl_op_desc *desc);
+
+/* Copy a_v, v in [0,N]^d (x index fastest, a_host[0] = a_0) to the host
+ * buffer a_host of (N+1)^d doubles. */
+fl_status fl_get_coeffs(fl_op op, double *a_host);
+
+/* Copy the FP64 eigenvalues lambda(k), k in [0,Q)^d (x index fastest; the
+ * full spectrum is even in every axis), scaled by 1/P^d, to the host buffer
+ * lam_host of Q^d doubles. */
+fl_status fl_get_symbol(fl_op op, double *lam_host);
+
+/* Human-readable name of a status code. */
+const char *fl_status_string(fl_status s);
+
+/* Message of the last error raised on the calling thread ("" if none). */
+const char *fl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FL_H */

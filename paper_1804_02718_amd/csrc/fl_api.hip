@@ -1,0 +1,216 @@
+// fl_api.hip -- the C-ABI entry points: argument checks, operator lifetime,
+// the matvec entry and host copies of the coefficients and eigenvalues.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <vector>
+
+#include "fl_internal.hpp"
+
+namespace fl {
+
+static thread_local char g_err[512] = {0};
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+fl_status build_coeffs(fl_op op, hipStream_t s);
+
+static int next_pow2(long x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// exp(-2 pi i m / P) for m < P, computed in long double and rounded
+static fl_status make_twiddles(fl_op op) {
+    const int P = op->P;
+    std::vector<double2> t64(P);
+    std::vector<float2> t32(P);
+    const long double tau = 6.283185307179586476925286766559005768L;
+    for (int m = 0; m < P; ++m) {
+        long double ang = tau * (long double)m / (long double)P;
+        long double c = cosl(ang), s = -sinl(ang);
+        // exact values at the quarter turns
+        if (m * 4 % P == 0) {
+            int q = m * 4 / P;
+            c = q == 0 ? 1.0L : q == 2 ? -1.0L : 0.0L;
+            s = q == 1 ? -1.0L : q == 3 ? 1.0L : 0.0L;
+        }
+        t64[m].x = (double)c;
+        t64[m].y = (double)s;
+        t32[m].x = (float)c;
+        t32[m].y = (float)s;
+    }
+    FL_HIP_TRY(hipMalloc((void **)&op->tw64, sizeof(double2) * P));
+    FL_HIP_TRY(hipMalloc((void **)&op->tw32, sizeof(float2) * P));
+    FL_HIP_TRY(hipMemcpy(op->tw64, t64.data(), sizeof(double2) * P, hipMemcpyHostToDevice));
+    FL_HIP_TRY(hipMemcpy(op->tw32, t32.data(), sizeof(float2) * P, hipMemcpyHostToDevice));
+    return FL_OK;
+}
+
+void free_solver_workspace(fl_op op);
+
+static void destroy(fl_op op) {
+    if (!op) return;
+    (void)hipFree(op->a);
+    (void)hipFree(op->lam64);
+    (void)hipFree(op->lam32);
+    (void)hipFree(op->tw64);
+    (void)hipFree(op->tw32);
+    (void)hipFree(op->T1);
+    (void)hipFree(op->T2);
+    free_solver_workspace(op);
+    delete op;
+}
+
+static fl_status create(int d, double alpha, double h, int N, fl_op *out) {
+    fl_op op = new (std::nothrow) fl_op_s();
+    if (!op) {
+        set_error("host allocation failed");
+        return FL_E_NOMEM;
+    }
+    op->d = d;
+    op->N = N;
+    op->n = N - 1;
+    op->alpha = alpha;
+    op->h = h;
+    op->c = std::pow(2.0, alpha - 1.0) * alpha * std::tgamma(0.5 * (d + alpha)) /
+            (std::pow(M_PI, 0.5 * d) * std::tgamma(1.0 - 0.5 * alpha));
+    op->P = next_pow2(2L * op->n - 1);
+    if (op->P < 8) op->P = 8;
+    op->Q = op->P / 2 + 1;
+    op->Qp = ((op->Q + 15) / 16) * 16;
+    op->M = d == 2 ? (int64_t)op->n * op->n : (int64_t)op->n * op->n * op->n;
+    (void)hipGetDevice(&op->device);
+    const long V = N + 1;
+    const long nv = d == 2 ? V * V : V * V * V;
+    const long ql = d == 2 ? (long)op->Q * op->Q : (long)op->Q * op->Q * op->Q;
+    const long n = op->n;
+    op->T1_bytes = sizeof(double2) * (size_t)(d == 2 ? n : n * n) * op->Qp;
+    op->T2_bytes = d == 2 ? 0 : sizeof(double2) * (size_t)n * op->P * op->Qp;
+    fl_status st = FL_OK;
+    auto fail = [&](fl_status s) {
+        destroy(op);
+        return s;
+    };
+    hipError_t e;
+    if ((e = hipMalloc((void **)&op->a, sizeof(double) * nv)) != hipSuccess ||
+        (e = hipMalloc((void **)&op->lam64, sizeof(double) * ql)) != hipSuccess ||
+        (e = hipMalloc((void **)&op->lam32, sizeof(float) * ql)) != hipSuccess ||
+        (e = hipMalloc(&op->T1, op->T1_bytes)) != hipSuccess ||
+        (op->T2_bytes && (e = hipMalloc(&op->T2, op->T2_bytes)) != hipSuccess)) {
+        set_error("device allocation: %s", hipGetErrorString(e));
+        return fail(e == hipErrorOutOfMemory ? FL_E_NOMEM : FL_E_DEVICE);
+    }
+    if ((st = make_twiddles(op)) != FL_OK) return fail(st);
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+        set_error("stream creation failed");
+        return fail(FL_E_DEVICE);
+    }
+    st = build_coeffs(op, s);
+    if (st == FL_OK) st = build_symbol(op, s);
+    if (st == FL_OK) {
+        e = hipMemcpyAsync(&op->a0, op->a, sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            set_error("reading a_0: %s", hipGetErrorString(e));
+            st = FL_E_DEVICE;
+        }
+    }
+    (void)hipStreamDestroy(s);
+    if (st != FL_OK) return fail(st);
+    *out = op;
+    return FL_OK;
+}
+
+static bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + nb && y < x + na;
+}
+
+}  // namespace fl
+
+using namespace fl;
+
+extern "C" {
+
+const char *fl_last_error(void) { return g_err; }
+
+const char *fl_status_string(fl_status s) {
+    switch (s) {
+        case FL_OK: return "FL_OK";
+        case FL_E_INVAL: return "FL_E_INVAL";
+        case FL_E_NOMEM: return "FL_E_NOMEM";
+        case FL_E_DEVICE: return "FL_E_DEVICE";
+        case FL_E_NOCONV: return "FL_E_NOCONV";
+        case FL_E_BREAKDOWN: return "FL_E_BREAKDOWN";
+        case FL_E_UNSUPPORTED: return "FL_E_UNSUPPORTED";
+    }
+    return "unknown status";
+}
+
+fl_status fl_coeffs(int d, double alpha, double h, int N, fl_op *out) {
+    g_err[0] = 0;
+    if (!out) { set_error("out is NULL"); return FL_E_INVAL; }
+    if (d != 2 && d != 3) { set_error("d must be 2 or 3 (got %d)", d); return FL_E_INVAL; }
+    if (!(alpha > 0.0 && alpha < 2.0)) { set_error("alpha must lie in (0,2) (got %g)", alpha); return FL_E_INVAL; }
+    if (!(h > 0.0) || !std::isfinite(h)) { set_error("h must be positive and finite"); return FL_E_INVAL; }
+    if (N < 2) { set_error("N must be >= 2 (got %d)", N); return FL_E_INVAL; }
+    const int nmax = d == 2 ? 1025 : 513;
+    if (N > nmax) { set_error("N=%d exceeds the built range (N <= %d for d=%d)", N, nmax, d); return FL_E_UNSUPPORTED; }
+    return create(d, alpha, h, N, out);
+}
+
+fl_status fl_op_destroy(fl_op op) {
+    destroy(op);
+    return FL_OK;
+}
+
+fl_status fl_op_describe(fl_op op, fl_op_desc *desc) {
+    if (!op || !desc) { set_error("NULL argument"); return FL_E_INVAL; }
+    desc->d = op->d;
+    desc->N = op->N;
+    desc->n = op->n;
+    desc->P = op->P;
+    desc->Q = op->Q;
+    desc->M = op->M;
+    desc->alpha = op->alpha;
+    desc->h = op->h;
+    desc->c = op->c;
+    desc->a0 = op->a0;
+    return FL_OK;
+}
+
+fl_status fl_apply(fl_op op, const void *u, void *y, int prec, void *stream) {
+    if (!op || !u || !y) { set_error("NULL argument"); return FL_E_INVAL; }
+    if (prec != FL_FP64 && prec != FL_FP32) { set_error("prec must be FL_FP64 or FL_FP32"); return FL_E_INVAL; }
+    const size_t es = prec == FL_FP64 ? sizeof(double) : sizeof(float);
+    if (overlap(u, es * op->M, y, es * op->M)) { set_error("u and y overlap"); return FL_E_INVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == FL_FP64) return matvec<double>(op, (const double *)u, (double *)y, s);
+    return matvec<float>(op, (const float *)u, (float *)y, s);
+}
+
+fl_status fl_get_coeffs(fl_op op, double *a_host) {
+    if (!op || !a_host) { set_error("NULL argument"); return FL_E_INVAL; }
+    const long V = op->N + 1;
+    const long nv = op->d == 2 ? V * V : V * V * V;
+    FL_HIP_TRY(hipMemcpy(a_host, op->a, sizeof(double) * nv, hipMemcpyDeviceToHost));
+    return FL_OK;
+}
+
+fl_status fl_get_symbol(fl_op op, double *lam_host) {
+    if (!op || !lam_host) { set_error("NULL argument"); return FL_E_INVAL; }
+    const long Q = op->Q;
+    const long ql = op->d == 2 ? Q * Q : Q * Q * Q;
+    FL_HIP_TRY(hipMemcpy(lam_host, op->lam64, sizeof(double) * ql, hipMemcpyDeviceToHost));
+    return FL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,251 @@
+"""Thin ctypes binding of ``libfl.so`` (C-ABI in ``include/fl.h``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device vectors are torch CUDA tensors (torch supplies device memory
+and streams); the functions below pass their data pointers and the current
+stream to the C entry points of the same names.  The library is required:
+importing works without it, but the first call raises ``FlLibraryMissing``.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfl.so")
+
+FL_OK, FL_E_INVAL, FL_E_NOMEM, FL_E_DEVICE, FL_E_NOCONV, FL_E_BREAKDOWN, FL_E_UNSUPPORTED = range(7)
+FL_FP64, FL_FP32 = 0, 1
+SOLVERS = {"auto": 0, "cg64": 1, "refine": 2, "fpcg": 3}
+
+EXPORTED = ["fl_coeffs", "fl_apply", "fl_poisson_solve", "fl_poisson_solve_ex", "fl_allen_cahn_step",
+            "fl_allen_cahn_step_ex", "fl_op_destroy", "fl_op_describe", "fl_get_coeffs", "fl_get_symbol",
+            "fl_status_string", "fl_last_error"]
+
+
+class FlLibraryMissing(RuntimeError):
+    pass
+
+
+class FlError(RuntimeError):
+    def __init__(self, status, message, info=None):
+        super().__init__("%s: %s" % (_STATUS_NAMES.get(status, status), message))
+        self.status = status
+        self.info = info
+
+
+_STATUS_NAMES = {0: "FL_OK", 1: "FL_E_INVAL", 2: "FL_E_NOMEM", 3: "FL_E_DEVICE", 4: "FL_E_NOCONV",
+                 5: "FL_E_BREAKDOWN", 6: "FL_E_UNSUPPORTED"}
+
+
+class fl_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int), ("fell_back", ctypes.c_int),
+                ("status", ctypes.c_int), ("relres", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class fl_solve_opts(ctypes.Structure):
+    _fields_ = [("solver", ctypes.c_int), ("max_iter", ctypes.c_int), ("use_x0", ctypes.c_int),
+                ("check_every", ctypes.c_int), ("inner_tol", ctypes.c_double)]
+
+
+class fl_op_desc(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("N", ctypes.c_int), ("n", ctypes.c_int), ("P", ctypes.c_int),
+                ("Q", ctypes.c_int), ("M", ctypes.c_int64), ("alpha", ctypes.c_double),
+                ("h", ctypes.c_double), ("c", ctypes.c_double), ("a0", ctypes.c_double)]
+
+
+_LIB = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libfl.so and declare its signatures (raises FlLibraryMissing if absent)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise FlLibraryMissing("HIP library %s is not built (run __graft_entry__.build())" % path)
+    lib = ctypes.CDLL(path)
+    vp, dp, ip = ctypes.c_void_p, ctypes.c_double, ctypes.c_int
+    lib.fl_coeffs.argtypes = [ip, dp, dp, ip, ctypes.POINTER(vp)]
+    lib.fl_apply.argtypes = [vp, vp, vp, ip, vp]
+    lib.fl_poisson_solve.argtypes = [vp, vp, dp, vp, ctypes.POINTER(fl_info), vp]
+    lib.fl_poisson_solve_ex.argtypes = [vp, vp, dp, vp, ctypes.POINTER(fl_solve_opts), ctypes.POINTER(fl_info), vp]
+    lib.fl_allen_cahn_step.argtypes = [vp, vp, dp, dp, ctypes.POINTER(fl_info), vp]
+    lib.fl_allen_cahn_step_ex.argtypes = [vp, vp, dp, dp, dp, dp, ip, ctypes.POINTER(fl_info), vp]
+    lib.fl_op_destroy.argtypes = [vp]
+    lib.fl_op_describe.argtypes = [vp, ctypes.POINTER(fl_op_desc)]
+    lib.fl_get_coeffs.argtypes = [vp, vp]
+    lib.fl_get_symbol.argtypes = [vp, vp]
+    lib.fl_status_string.argtypes = [ip]
+    lib.fl_status_string.restype = ctypes.c_char_p
+    lib.fl_last_error.argtypes = []
+    lib.fl_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name not in ("fl_status_string", "fl_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _LIB = lib
+    return lib
+
+
+def _check(status, info=None):
+    if status != FL_OK:
+        raise FlError(status, load().fl_last_error().decode(), info)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _ptr(t, dtype=None, numel=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("expected dtype %s, got %s" % (dtype, t.dtype))
+    if numel is not None and t.numel() != numel:
+        raise ValueError("expected %d entries, got %d" % (numel, t.numel()))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# C entry points under their own names
+# ---------------------------------------------------------------------------
+def fl_coeffs(d: int, alpha: float, h: float, N: int) -> ctypes.c_void_p:
+    op = ctypes.c_void_p()
+    _check(load().fl_coeffs(int(d), float(alpha), float(h), int(N), ctypes.byref(op)))
+    return op
+
+
+def fl_op_describe(op) -> dict:
+    desc = fl_op_desc()
+    _check(load().fl_op_describe(op, ctypes.byref(desc)))
+    return {k: getattr(desc, k) for k, _ in desc._fields_}
+
+
+def fl_apply(op, u, y, stream=None):
+    import torch
+    prec = FL_FP64 if u.dtype == torch.float64 else FL_FP32
+    if u.dtype not in (torch.float32, torch.float64) or y.dtype != u.dtype:
+        raise TypeError("u and y must both be float32 or both float64")
+    _check(load().fl_apply(op, _ptr(u), _ptr(y), prec, _stream(stream)))
+    return y
+
+
+def fl_poisson_solve(op, f, tol, u, stream=None):
+    info = fl_info()
+    st = load().fl_poisson_solve(op, _ptr(f), float(tol), _ptr(u), ctypes.byref(info), _stream(stream))
+    _check(st, info.as_dict())
+    return info.as_dict()
+
+
+def fl_poisson_solve_ex(op, f, tol, u, solver="auto", max_iter=0, use_x0=False, check_every=0, inner_tol=0.0,
+                        stream=None, raise_on_error=True):
+    opts = fl_solve_opts(SOLVERS[solver] if isinstance(solver, str) else int(solver), int(max_iter),
+                         int(bool(use_x0)), int(check_every), float(inner_tol))
+    info = fl_info()
+    st = load().fl_poisson_solve_ex(op, _ptr(f), float(tol), _ptr(u), ctypes.byref(opts), ctypes.byref(info),
+                                    _stream(stream))
+    if raise_on_error:
+        _check(st, info.as_dict())
+    return info.as_dict()
+
+
+def fl_allen_cahn_step(op, u, tau, eps, stream=None):
+    info = fl_info()
+    st = load().fl_allen_cahn_step(op, _ptr(u), float(tau), float(eps), ctypes.byref(info), _stream(stream))
+    _check(st, info.as_dict())
+    return info.as_dict()
+
+
+def fl_allen_cahn_step_ex(op, u, tau, eps, theta=0.5, tol=1e-8, solver="auto", stream=None):
+    info = fl_info()
+    st = load().fl_allen_cahn_step_ex(op, _ptr(u), float(tau), float(eps), float(theta), float(tol),
+                                      SOLVERS[solver] if isinstance(solver, str) else int(solver),
+                                      ctypes.byref(info), _stream(stream))
+    _check(st, info.as_dict())
+    return info.as_dict()
+
+
+def fl_get_coeffs(op) -> np.ndarray:
+    desc = fl_op_describe(op)
+    a = np.zeros((desc["N"] + 1) ** desc["d"])
+    _check(load().fl_get_coeffs(op, a.ctypes.data_as(ctypes.c_void_p)))
+    return a.reshape((desc["N"] + 1,) * desc["d"])
+
+
+def fl_get_symbol(op) -> np.ndarray:
+    desc = fl_op_describe(op)
+    lam = np.zeros(desc["Q"] ** desc["d"])
+    _check(load().fl_get_symbol(op, lam.ctypes.data_as(ctypes.c_void_p)))
+    return lam.reshape((desc["Q"],) * desc["d"])
+
+
+def fl_op_destroy(op):
+    if op:
+        load().fl_op_destroy(op)
+
+
+# ---------------------------------------------------------------------------
+# convenience wrapper owning one fl_op
+# ---------------------------------------------------------------------------
+class Operator:
+    """The discrete fractional Laplacian on (a, a + N h)^d, zero outside (one fl_op)."""
+
+    def __init__(self, d: int, alpha: float, h: float, N: int):
+        self._op = fl_coeffs(d, alpha, h, N)
+        self.desc = fl_op_describe(self._op)
+        for k, v in self.desc.items():
+            setattr(self, k, v)
+
+    @property
+    def handle(self):
+        return self._op
+
+    def apply(self, u, y=None, stream=None):
+        import torch
+        if y is None:
+            y = torch.empty_like(u)
+        return fl_apply(self._op, u, y, stream)
+
+    def poisson_solve(self, f, tol=1e-8, u=None, stream=None, **kw):
+        import torch
+        if u is None:
+            u = torch.zeros_like(f)
+        info = fl_poisson_solve_ex(self._op, f, tol, u, stream=stream, **kw)
+        return u, info
+
+    def allen_cahn_step(self, u, tau, eps, theta=0.5, tol=1e-8, solver="auto", stream=None):
+        return fl_allen_cahn_step_ex(self._op, u, tau, eps, theta, tol, solver, stream)
+
+    def coeffs(self):
+        return fl_get_coeffs(self._op)
+
+    def symbol(self):
+        return fl_get_symbol(self._op)
+
+    def close(self):
+        if getattr(self, "_op", None):
+            fl_op_destroy(self._op)
+            self._op = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
