@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Benchmark of the FFT matvec of the FD integral fractional Laplacian on one MI355X.
+
+Workload (timed "step"): one y = A u of the 2D operator with N = 1024 intervals
+per axis (1023^2 = 1,046,529 unknowns, FFT length 2048 per axis), alpha = 1.5,
+on the Gaussian u = exp(-|x|^2) sampled on (-4,4)^2, FP32 FFT path (the
+path's arithmetic type), inputs resident in HBM.  value = unknowns * steps /
+seconds (Gdof/s).
+
+Also reported on the same JSON line:
+  roofline      -- the dominant pass's algorithmic bytes over its average
+                   duration (HIP events on the launch stream), against 8 TB/s;
+                   `traffic` from committed rocprofv3 FETCH/WRITE counters when
+                   they were taken on the current kernel source, else null.
+  cpu_baseline  -- the FP64 oracle's explicit sum on a bounded sample of rows
+                   of the same workload, on this host's cores.
+  extra         -- FP64 matvec rate, per-pass times and the Poisson
+                   time-to-1e-8 of the solvers (outside the timed region).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2_fp32.json")
+KERNEL_SOURCES = ["paper_1804_02718_amd/csrc/fl_fft.hip", "paper_1804_02718_amd/csrc/fl_internal.hpp"]
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def pass_bytes(d, n, Q, P, s):
+    """Algorithmic bytes per pass (pass model: each pass reads its input once and
+    writes its output once; lambda read once).  s = bytes per real."""
+    if d == 2:
+        return [s * (n * n + 2 * Q * n),            # X-fwd: u in, half spectra out
+                s * (4 * Q * n + Q * Q),            # Y fused: spectra in/out, lambda
+                s * (2 * Q * n + n * n)]            # X-inv: spectra in, y out
+    return [s * (n ** 3 + 2 * Q * n * n),           # X-fwd
+            s * (2 * Q * n * n + 2 * Q * P * n),    # Y-fwd
+            s * (4 * Q * P * n + Q ** 3),           # Z fused
+            s * (2 * Q * P * n + 2 * Q * n * n),    # Y-inv
+            s * (2 * Q * n * n + n ** 3)]           # X-inv
+
+
+PASS_NAMES = {2: ["x_fwd", "y_fused", "x_inv"], 3: ["x_fwd", "y_fwd", "z_fused", "y_inv", "x_inv"]}
+KERNEL_NAMES = {"x_fwd": "k_xfwd", "x_inv": "k_xinv", "y_fused": "k_strided<MODE=2>",
+                "z_fused": "k_strided<MODE=2>", "y_fwd": "k_strided<MODE=0>", "y_inv": "k_strided<MODE=1>"}
+
+
+def time_matvec(op, u, y, steps, warmup, torch):
+    for _ in range(warmup):
+        op.apply(u, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        op.apply(u, y)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def traffic_entry(dominant_kernel):
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        rec = json.load(f)
+    if rec.get("source_sha") != kernel_source_sha():
+        return None
+    k = rec.get("kernels", {}).get(dominant_kernel)
+    if not k:
+        return None
+    return k.get("bytes_per_launch")
+
+
+def cpu_baseline(N, alpha, h, u_np, seconds):
+    import numpy as np
+
+    import oracle
+    a = oracle.coeffs(2, alpha, h, N)
+    M = (N - 1) ** 2
+    rng = np.random.default_rng(12345)
+    order = rng.permutation(M)
+    done = 0
+    batch = 256
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds and done < M:
+        rows = order[done:done + batch]
+        oracle.apply_rows(2, N, alpha, a, u_np, rows)
+        done += rows.size
+        batch = min(batch * 2, 8192)
+    dt = time.perf_counter() - t0
+    return {"value": done / dt / 1e9, "unit": "Gdof/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "explicit O(M^2) FP64 sum (long-double accumulation) on %d seeded random rows of the "
+                      "%d-row N=1024 matvec in %.1f s, rate = rows/s (coefficient setup excluded)"
+                      % (done, M, dt)}
+
+
+def poisson_extra(torch, fl, inputs, N=1024, alpha=1.5):
+    """Time-to-1e-8 relative residual for the 2D N=1024 Poisson problem, f = 8 Gaussians."""
+    h = 2.0 / N
+    f = torch.as_tensor(inputs.gauss_sum(2, N, 8, seed=2), dtype=torch.float64, device="cuda:0")
+    op = fl.Operator(2, alpha, h, N)
+    out = {}
+    for solver in ("cg64", "refine"):
+        u = torch.zeros_like(f)
+        op.poisson_solve(f, tol=1e-8, u=u, solver=solver)  # warm (workspace allocation)
+        torch.cuda.synchronize()
+        u.zero_()
+        t0 = time.perf_counter()
+        _, info = op.poisson_solve(f, tol=1e-8, u=u, solver=solver)
+        torch.cuda.synchronize()
+        out[solver] = {"seconds": time.perf_counter() - t0, "iters": info["iters"],
+                       "outer": info["outer_iters"], "relres": info["relres"]}
+    op.close()
+    return {"workload": "2D N=1024 alpha=%.2f, f = sum of 8 seeded Gaussians on (-1,1)^2, tol 1e-8" % alpha,
+            **out}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="before timing, copy a buffer of this many MiB three times (a plain copy kernel "
+                         "whose known traffic calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(no sharding or inter-GPU collectives); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1804_02718_amd import fl, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    d, N, alpha = 2, 1024, 1.5
+    lo, hi = -4.0, 4.0
+    h = (hi - lo) / N
+    M = (N - 1) ** d
+    op = fl.Operator(d, alpha, h, N)
+    u_np = inputs.gaussian(d, N, lo, hi)
+    u32 = torch.as_tensor(u_np, dtype=torch.float32, device="cuda:0")
+    y32 = torch.empty_like(u32)
+    print("bench: workload 2D N=%d fp32, %d warmup + %d timed steps" % (N, args.warmup, args.steps),
+          file=sys.stderr, flush=True)
+    if args.calib_copy_mb > 0:
+        src = torch.ones(args.calib_copy_mb * 262144, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    dt = time_matvec(op, u32, y32, args.steps, args.warmup, torch)
+    value = M * args.steps / dt / 1e9
+    ms_per_step = dt / args.steps * 1e3
+
+    # per-pass durations, HIP events on the stream the passes are launched on
+    pass_ms = fl.fl_apply_profiled(op.handle, u32, y32, reps=max(50, min(args.steps, 500)))
+    names = PASS_NAMES[d]
+    pb = pass_bytes(d, op.n, op.Q, op.P, 4)
+    dom = int(np.argmax(pass_ms))
+    achieved = pb[dom] / (pass_ms[dom] * 1e-3) / 1e9
+    dom_kernel = KERNEL_NAMES[names[dom]]
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_entry(names[dom]),
+                "kernel": dom_kernel, "pass": names[dom], "algorithmic_bytes": pb[dom],
+                "avg_ms": round(pass_ms[dom], 5)}
+
+    extra = {"passes": {names[i]: {"avg_ms": round(pass_ms[i], 5), "algorithmic_bytes": pb[i],
+                                   "GB_per_s": round(pb[i] / (pass_ms[i] * 1e-3) / 1e9, 1)}
+                        for i in range(len(names))},
+             "chain_model_bytes": sum(pb),
+             "chain_GB_per_s": round(sum(pb) / (dt / args.steps) / 1e9, 1),
+             "chain_roofline_frac": round(sum(pb) / (dt / args.steps) / 1e9 / HBM_PEAK_GBS, 4)}
+    if not args.no_extra:
+        u64 = u32.double()
+        y64 = torch.empty_like(u64)
+        dt64 = time_matvec(op, u64, y64, max(100, args.steps // 4), 10, torch)
+        extra["fp64_gdof_s"] = round(M * max(100, args.steps // 4) / dt64 / 1e9, 3)
+        print("bench: poisson solves", file=sys.stderr, flush=True)
+        extra["poisson"] = poisson_extra(torch, fl, inputs)
+    op.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(N, alpha, h, u_np, args.cpu_seconds)
+
+    line = {"metric": "Toeplitz matvec Gdof/s", "value": round(value, 3), "unit": "Gdof/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "2D fractional Laplacian FFT matvec, N=1024 (1023^2 unknowns, 2048^2 "
+                                   "embedding), alpha=1.5, Gaussian u on (-4,4)^2", "d": d, "N": N,
+                       "unknowns": M, "precision": "fp32"},
+            "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

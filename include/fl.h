@@ -93,8 +93,8 @@ typedef struct {
  * implies), the generator -c a_{|m|} of the Toeplitz matrix embedded in a
  * circulant of length P >= 2n - 1 per axis (a power of two, zeros in the gap),
  * and its FFT eigenvalues lambda (FP64 master, FP32 copy).
- *   d: 2 or 3.  alpha: in (0, 2).  h > 0, finite.  N: 2 <= N <= 1024 (d = 2),
- *   2 <= N <= 256 (d = 3).  *out receives a new handle (free with
+ *   d: 2 or 3.  alpha: in (0, 2).  h > 0, finite.  N: 2 <= N <= 1025 (d = 2),
+ *   2 <= N <= 513 (d = 3) (FFT lengths up to 2048 and 1024).  *out receives a new handle (free with
  *   fl_op_destroy).  Uses the current HIP device; synchronises before
  *   returning.  Errors: FL_E_INVAL, FL_E_UNSUPPORTED, FL_E_NOMEM, FL_E_DEVICE.
  */
@@ -144,6 +144,18 @@ fl_status fl_allen_cahn_step(fl_op op, double *u, double tau, double eps,
 fl_status fl_allen_cahn_step_ex(fl_op op, double *u, double tau, double eps,
                                 double theta, double tol, int solver,
                                 fl_info *info, void *stream);
+
+/*
+ * fl_apply_profiled -- fl_apply instrumented for measurement: runs `reps`
+ * matvecs y = A u back to back on `stream` with a HIP event before the first
+ * pass and after every pass, synchronises, and writes the average time per
+ * pass in milliseconds to pass_ms (host, >= 5 floats) and the number of
+ * passes (3 for d = 2: X-forward, Y forward*lambda*inverse, X-inverse; 5 for
+ * d = 3: X-forward, Y-forward, Z forward*lambda*inverse, Y-inverse,
+ * X-inverse) to *npass.  The result in y is that of fl_apply.
+ */
+fl_status fl_apply_profiled(fl_op op, const void *u, void *y, int prec, int reps, void *stream,
+                            float *pass_ms, int *npass);
 
 /* Free the operator and its device workspaces.  NULL is accepted. */
 fl_status fl_op_destroy(fl_op op);

@@ -117,13 +117,16 @@ double orc_J(int d, double p)
 /* Element integrals                                                    */
 /* ------------------------------------------------------------------ */
 
-/* Quadrature order for an element whose largest index is m (unit h).  */
+/* Quadrature order for an element whose largest index is m (unit h): the
+ * integrand's nearest singularity (the origin) lies about 4m half-widths from
+ * the element, so n points give a relative error near (4m)^{-2n}. */
 static int elem_order(int m)
 {
     if (m <= 3) return 24;
     if (m <= 15) return 16;
     if (m <= 63) return 10;
-    return 6;
+    if (m <= 127) return 6;
+    return 4;
 }
 
 /* int over [e1,e1+1]x[e2,e2+1](x[e3,e3+1]) of |xi|^{-q}, unit spacing. */
@@ -135,24 +138,25 @@ static long double elem_unit(int d, double q, const int *e)
     int n = elem_order(m);
     gl_rule(n, x, w);
     long double acc = 0.0L;
-    long double hq = -0.5L * q;
+    double hq = -0.5 * q;
+    /* integrand in FP64 (pow), sums in long double */
     if (d == 2) {
         for (int i = 0; i < n; ++i) {
-            long double a = e[0] + 0.5L * (x[i] + 1.0L);
+            double a = (double)(e[0] + 0.5L * (x[i] + 1.0L));
             for (int j = 0; j < n; ++j) {
-                long double b = e[1] + 0.5L * (x[j] + 1.0L);
-                acc += w[i] * w[j] * powl(a * a + b * b, hq);
+                double b = (double)(e[1] + 0.5L * (x[j] + 1.0L));
+                acc += w[i] * w[j] * (long double)pow(a * a + b * b, hq);
             }
         }
         return 0.25L * acc;
     }
     for (int i = 0; i < n; ++i) {
-        long double a = e[0] + 0.5L * (x[i] + 1.0L);
+        double a = (double)(e[0] + 0.5L * (x[i] + 1.0L));
         for (int j = 0; j < n; ++j) {
-            long double b = e[1] + 0.5L * (x[j] + 1.0L);
+            double b = (double)(e[1] + 0.5L * (x[j] + 1.0L));
             for (int k = 0; k < n; ++k) {
-                long double c = e[2] + 0.5L * (x[k] + 1.0L);
-                acc += w[i] * w[j] * w[k] * powl(a * a + b * b + c * c, hq);
+                double c = (double)(e[2] + 0.5L * (x[k] + 1.0L));
+                acc += w[i] * w[j] * w[k] * (long double)pow(a * a + b * b + c * c, hq);
             }
         }
     }

@@ -197,6 +197,43 @@ fl_status fl_apply(fl_op op, const void *u, void *y, int prec, void *stream) {
     return matvec<float>(op, (const float *)u, (float *)y, s);
 }
 
+fl_status fl_apply_profiled(fl_op op, const void *u, void *y, int prec, int reps, void *stream, float *pass_ms,
+                            int *npass) {
+    if (!op || !u || !y || !pass_ms || !npass || reps < 1) { set_error("bad argument"); return FL_E_INVAL; }
+    if (prec != FL_FP64 && prec != FL_FP32) { set_error("prec must be FL_FP64 or FL_FP32"); return FL_E_INVAL; }
+    const size_t es = prec == FL_FP64 ? sizeof(double) : sizeof(float);
+    if (overlap(u, es * op->M, y, es * op->M)) { set_error("u and y overlap"); return FL_E_INVAL; }
+    const int np = op->d == 2 ? 3 : 5;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t ev[6 * 64];
+    const int chunk = reps < 64 ? reps : 64;
+    for (int i = 0; i < (np + 1) * chunk; ++i) FL_HIP_TRY(hipEventCreate(&ev[i]));
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    fl_status st = FL_OK;
+    for (int done = 0; done < reps && st == FL_OK; done += chunk) {
+        const int k = reps - done < chunk ? reps - done : chunk;
+        for (int r = 0; r < k && st == FL_OK; ++r) {
+            hipEvent_t *e = ev + (np + 1) * r;
+            st = prec == FL_FP64 ? matvec_ex<double>(op, (const double *)u, (double *)y, Epi<double>{}, nullptr, s, e)
+                                 : matvec_ex<float>(op, (const float *)u, (float *)y, Epi<float>{}, nullptr, s, e);
+        }
+        if (hipStreamSynchronize(s) != hipSuccess) st = FL_E_DEVICE;
+        for (int r = 0; r < k && st == FL_OK; ++r) {
+            hipEvent_t *e = ev + (np + 1) * r;
+            for (int p = 0; p < np; ++p) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, e[p], e[p + 1]) != hipSuccess) st = FL_E_DEVICE;
+                acc[p] += ms;
+            }
+        }
+    }
+    for (int i = 0; i < (np + 1) * chunk; ++i) (void)hipEventDestroy(ev[i]);
+    if (st != FL_OK) { set_error("profiled apply failed"); return st; }
+    for (int p = 0; p < np; ++p) pass_ms[p] = (float)(acc[p] / reps);
+    *npass = np;
+    return FL_OK;
+}
+
 fl_status fl_get_coeffs(fl_op op, double *a_host) {
     if (!op || !a_host) { set_error("NULL argument"); return FL_E_INVAL; }
     const long V = op->N + 1;

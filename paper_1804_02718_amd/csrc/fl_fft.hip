@@ -273,39 +273,54 @@ template <> const float *lamb<float>(fl_op op) { return op->lam32; }
 template <> const double *lamb<double>(fl_op op) { return op->lam64; }
 
 template <typename T, int P>
-static void matvec_p(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s) {
+static void matvec_p(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
+                     hipEvent_t *ev) {
     const int n = op->n, Q = op->Q;
     const long Qp = op->Qp;
     C2<T> *T1 = (C2<T> *)op->T1;
     C2<T> *T2 = (C2<T> *)op->T2;
     const C2<T> *tw = twid<T>(op);
     const T *lam = lamb<T>(op);
+    // ev (optional): ev[0] before the first pass, ev[i+1] after pass i
+    auto mark = [&](int i) {
+        if (ev) (void)hipEventRecord(ev[i], s);
+    };
+    mark(0);
     if (op->d == 2) {
         launch_xfwd<T, P>(u, T1, n, n, n, Qp, tw, done, s);
+        mark(1);
         launch_strided<T, P, 2>(T1, T1, Q, 1, n, n, Qp, 0, 0, tw, lam, Q, 0, done, s);
+        mark(2);
         launch_xinv<T, P>(T1, y, n, n, Qp, n, tw, ep, done, s);
+        mark(3);
     } else {
         const long nn = (long)n * n;
         launch_xfwd<T, P>(u, T1, (int)nn, n, n, Qp, tw, done, s);
+        mark(1);
         launch_strided<T, P, 0>(T1, T2, Q, n, n, P, Qp, n * Qp, (long)P * Qp, tw, nullptr, 0, 0, done, s);
+        mark(2);
         launch_strided<T, P, 2>(T2, T2, Q, P, n, n, (long)P * Qp, Qp, Qp, tw, lam, (long)Q * Q, Q, done, s);
+        mark(3);
         launch_strided<T, P, 1>(T2, T1, Q, n, P, n, Qp, (long)P * Qp, n * Qp, tw, nullptr, 0, 0, done, s);
+        mark(4);
         launch_xinv<T, P>(T1, y, (int)nn, n, Qp, n, tw, ep, done, s);
+        mark(5);
     }
 }
 
 template <typename T>
-fl_status matvec_ex(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s) {
+fl_status matvec_ex(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
+                    hipEvent_t *ev) {
     switch (op->P) {
-        case 8: matvec_p<T, 8>(op, u, y, ep, done, s); break;
-        case 16: matvec_p<T, 16>(op, u, y, ep, done, s); break;
-        case 32: matvec_p<T, 32>(op, u, y, ep, done, s); break;
-        case 64: matvec_p<T, 64>(op, u, y, ep, done, s); break;
-        case 128: matvec_p<T, 128>(op, u, y, ep, done, s); break;
-        case 256: matvec_p<T, 256>(op, u, y, ep, done, s); break;
-        case 512: matvec_p<T, 512>(op, u, y, ep, done, s); break;
-        case 1024: matvec_p<T, 1024>(op, u, y, ep, done, s); break;
-        case 2048: matvec_p<T, 2048>(op, u, y, ep, done, s); break;
+        case 8: matvec_p<T, 8>(op, u, y, ep, done, s, ev); break;
+        case 16: matvec_p<T, 16>(op, u, y, ep, done, s, ev); break;
+        case 32: matvec_p<T, 32>(op, u, y, ep, done, s, ev); break;
+        case 64: matvec_p<T, 64>(op, u, y, ep, done, s, ev); break;
+        case 128: matvec_p<T, 128>(op, u, y, ep, done, s, ev); break;
+        case 256: matvec_p<T, 256>(op, u, y, ep, done, s, ev); break;
+        case 512: matvec_p<T, 512>(op, u, y, ep, done, s, ev); break;
+        case 1024: matvec_p<T, 1024>(op, u, y, ep, done, s, ev); break;
+        case 2048: matvec_p<T, 2048>(op, u, y, ep, done, s, ev); break;
         default: set_error("FFT length %d not built", op->P); return FL_E_UNSUPPORTED;
     }
     FL_HIP_TRY(hipGetLastError());
@@ -318,9 +333,10 @@ fl_status matvec(fl_op op, const T *u, T *y, hipStream_t s) {
 }
 template fl_status matvec<float>(fl_op, const float *, float *, hipStream_t);
 template fl_status matvec<double>(fl_op, const double *, double *, hipStream_t);
-template fl_status matvec_ex<float>(fl_op, const float *, float *, const Epi<float> &, const double *, hipStream_t);
+template fl_status matvec_ex<float>(fl_op, const float *, float *, const Epi<float> &, const double *, hipStream_t,
+                                    hipEvent_t *);
 template fl_status matvec_ex<double>(fl_op, const double *, double *, const Epi<double> &, const double *,
-                                     hipStream_t);
+                                     hipStream_t, hipEvent_t *);
 
 int kernel_p_supported(int P) { return P >= 8 && P <= 2048 && (P & (P - 1)) == 0; }
 

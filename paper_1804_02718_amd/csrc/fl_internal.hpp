@@ -254,7 +254,8 @@ template <typename T>
 fl_status matvec(fl_op op, const T *u, T *y, hipStream_t s);
 // `done`: optional device flag; when it holds a nonzero value every pass returns at once
 template <typename T>
-fl_status matvec_ex(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s);
+fl_status matvec_ex(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
+                    hipEvent_t *ev = nullptr);
 fl_status build_symbol(fl_op op, hipStream_t s);
 int kernel_p_supported(int P);
 }  // namespace fl

@@ -18,7 +18,7 @@ FL_OK, FL_E_INVAL, FL_E_NOMEM, FL_E_DEVICE, FL_E_NOCONV, FL_E_BREAKDOWN, FL_E_UN
 FL_FP64, FL_FP32 = 0, 1
 SOLVERS = {"auto": 0, "cg64": 1, "refine": 2, "fpcg": 3}
 
-EXPORTED = ["fl_coeffs", "fl_apply", "fl_poisson_solve", "fl_poisson_solve_ex", "fl_allen_cahn_step",
+EXPORTED = ["fl_coeffs", "fl_apply", "fl_apply_profiled", "fl_poisson_solve", "fl_poisson_solve_ex", "fl_allen_cahn_step",
             "fl_allen_cahn_step_ex", "fl_op_destroy", "fl_op_describe", "fl_get_coeffs", "fl_get_symbol",
             "fl_status_string", "fl_last_error"]
 
@@ -71,6 +71,8 @@ def load(path: str = LIB_PATH):
     vp, dp, ip = ctypes.c_void_p, ctypes.c_double, ctypes.c_int
     lib.fl_coeffs.argtypes = [ip, dp, dp, ip, ctypes.POINTER(vp)]
     lib.fl_apply.argtypes = [vp, vp, vp, ip, vp]
+    lib.fl_apply_profiled.argtypes = [vp, vp, vp, ip, ip, vp, ctypes.POINTER(ctypes.c_float),
+                                      ctypes.POINTER(ctypes.c_int)]
     lib.fl_poisson_solve.argtypes = [vp, vp, dp, vp, ctypes.POINTER(fl_info), vp]
     lib.fl_poisson_solve_ex.argtypes = [vp, vp, dp, vp, ctypes.POINTER(fl_solve_opts), ctypes.POINTER(fl_info), vp]
     lib.fl_allen_cahn_step.argtypes = [vp, vp, dp, dp, ctypes.POINTER(fl_info), vp]
@@ -139,6 +141,17 @@ def fl_apply(op, u, y, stream=None):
         raise TypeError("u and y must both be float32 or both float64")
     _check(load().fl_apply(op, _ptr(u), _ptr(y), prec, _stream(stream)))
     return y
+
+
+def fl_apply_profiled(op, u, y, reps, stream=None):
+    """Average per-pass milliseconds over `reps` matvecs (HIP events on the given stream)."""
+    import torch
+    prec = FL_FP64 if u.dtype == torch.float64 else FL_FP32
+    ms = (ctypes.c_float * 8)()
+    npass = ctypes.c_int()
+    _check(load().fl_apply_profiled(op, _ptr(u), _ptr(y), prec, int(reps), _stream(stream), ms,
+                                    ctypes.byref(npass)))
+    return [ms[i] for i in range(npass.value)]
 
 
 def fl_poisson_solve(op, f, tol, u, stream=None):

@@ -178,6 +178,31 @@ def test_apply_c2_full_size_sampled(dev, alpha):
         op.close()
 
 
+@pytest.mark.parametrize("N,alpha,nrows", [(130, 0.7, 24), (256, 1.2, 12)])
+def test_apply_3d_p512_sampled(dev, N, alpha, nrows):
+    # 3D with FFT length 512 per axis: N = 130 (n = 129) and the full N = 256 (255^3 unknowns)
+    # of the Allen--Cahn workload, seeded uniform u in [-0.9, 0.9], FP64 and FP32, sampled rows
+    fl = _fl()
+    h = 2.0 / N
+    M = (N - 1) ** 3
+    op = fl.Operator(3, alpha, h, N)
+    assert op.P == 512
+    u = inputs.ac_initial(M, seed=3)
+    rows = _sample_rows(M, nrows, seed=8)
+    a = oracle.coeffs(3, alpha, h, N)
+    ref = oracle.apply_rows(3, N, alpha, a, u, rows)
+    absref = oracle.apply_rows(3, N, alpha, a, u, rows, absmode=True)
+    y = op.apply(_t(u)).cpu().numpy()[rows]
+    e_rel, e_sc = _errs(y, ref, absref)
+    assert e_sc < 1e-14 and e_rel < 1e-12, (e_rel, e_sc)
+    u32 = u.astype(np.float32)
+    ref32 = oracle.apply_rows(3, N, alpha, a, u32.astype(np.float64), rows)
+    y32 = op.apply(_t(u32, torch.float32)).cpu().numpy()[rows].astype(np.float64)
+    e_rel32, e_sc32 = _errs(y32, ref32, absref)
+    assert e_sc32 < 1e-6 and e_rel32 < 1e-5, (e_rel32, e_sc32)
+    op.close()
+
+
 def test_apply_deterministic_and_stream_ordered(dev):
     fl = _fl()
     N = 256
