@@ -107,6 +107,33 @@ def cpu_baseline(N, alpha, h, u_np, seconds):
                       % (done, M, dt)}
 
 
+def c3_extra(torch, fl, inputs, autotune, N=256, alpha=1.2):
+    """3D N=256 matvec (255^3 unknowns, FFT length 512): Gdof/s and per-pass times, FP32 and FP64."""
+    import numpy as np
+    h = 2.0 / N
+    M = (N - 1) ** 3
+    op = fl.Operator(3, alpha, h, N)
+    out = {"workload": "3D N=256 (255^3 unknowns, 512^3 embedding), alpha=1.2, uniform u in [-0.9,0.9]"}
+    u64 = torch.as_tensor(inputs.ac_initial(M, seed=3), device="cuda:0")
+    for prec, dtype, s in (("fp32", torch.float32, 4), ("fp64", torch.float64, 8)):
+        u = u64.to(dtype)
+        y = torch.empty_like(u)
+        if autotune:
+            best, ms = op.autotune(prec, reps=10)
+            out[prec + "_variant"] = {"chosen": best, "ms_per_variant": [round(m, 4) for m in ms]}
+        steps = 60
+        dt = time_matvec(op, u, y, steps, 5, torch)
+        pm = fl.fl_apply_profiled(op.handle, u, y, reps=20)
+        pb = pass_bytes(3, op.n, op.Q, op.P, s)
+        out[prec] = {"gdof_s": round(M * steps / dt / 1e9, 3), "ms_per_step": round(dt / steps * 1e3, 4),
+                     "chain_roofline_frac": round(sum(pb) / (dt / steps) / 1e9 / HBM_PEAK_GBS, 4),
+                     "passes": {PASS_NAMES[3][i]: {"avg_ms": round(pm[i], 4),
+                                                   "GB_per_s": round(pb[i] / (pm[i] * 1e-3) / 1e9, 1)}
+                                for i in range(5)}}
+    op.close()
+    return out
+
+
 def poisson_extra(torch, fl, inputs, N=1024, alpha=1.5):
     """Time-to-1e-8 relative residual for the 2D N=1024 Poisson problem, f = 8 Gaussians."""
     h = 2.0 / N
@@ -136,6 +163,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the built-in default kernel variant instead of the autotuned one")
+    ap.add_argument("--c3", action="store_true",
+                    help="also time the 3D N=256 matvec (FP32 and FP64) of the Allen--Cahn workload")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before timing, copy a buffer of this many MiB three times (a plain copy kernel "
                          "whose known traffic calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -169,6 +200,16 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    tune = {}
+    if not args.no_autotune:
+        best, ms = op.autotune("fp32", reps=50)
+        tune["fp32"] = {"chosen": best, "variant": op.variants("fp32")[best],
+                        "ms_per_variant": [round(m, 5) for m in ms]}
+        best64, ms64 = op.autotune("fp64", reps=30)
+        tune["fp64"] = {"chosen": best64, "variant": op.variants("fp64")[best64],
+                        "ms_per_variant": [round(m, 5) for m in ms64]}
+        torch.cuda.synchronize()
+
     dt = time_matvec(op, u32, y32, args.steps, args.warmup, torch)
     value = M * args.steps / dt / 1e9
     ms_per_step = dt / args.steps * 1e3
@@ -190,7 +231,8 @@ def main():
                         for i in range(len(names))},
              "chain_model_bytes": sum(pb),
              "chain_GB_per_s": round(sum(pb) / (dt / args.steps) / 1e9, 1),
-             "chain_roofline_frac": round(sum(pb) / (dt / args.steps) / 1e9 / HBM_PEAK_GBS, 4)}
+             "chain_roofline_frac": round(sum(pb) / (dt / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+             "autotune": tune}
     if not args.no_extra:
         u64 = u32.double()
         y64 = torch.empty_like(u64)
@@ -199,6 +241,9 @@ def main():
         print("bench: poisson solves", file=sys.stderr, flush=True)
         extra["poisson"] = poisson_extra(torch, fl, inputs)
     op.close()
+    if args.c3:
+        print("bench: 3D N=256 matvec", file=sys.stderr, flush=True)
+        extra["c3_matvec"] = c3_extra(torch, fl, inputs, not args.no_autotune)
 
     cpu = None
     if not args.no_cpu_baseline:

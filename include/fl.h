@@ -147,15 +147,35 @@ fl_status fl_allen_cahn_step_ex(fl_op op, double *u, double tau, double eps,
 
 /*
  * fl_apply_profiled -- fl_apply instrumented for measurement: runs `reps`
- * matvecs y = A u back to back on `stream` with a HIP event before the first
- * pass and after every pass, synchronises, and writes the average time per
- * pass in milliseconds to pass_ms (host, >= 5 floats) and the number of
- * passes (3 for d = 2: X-forward, Y forward*lambda*inverse, X-inverse; 5 for
- * d = 3: X-forward, Y-forward, Z forward*lambda*inverse, Y-inverse,
- * X-inverse) to *npass.  The result in y is that of fl_apply.
+ * matvecs y = A u back to back on `stream`, each kernel launched with HIP
+ * events recorded at its start and stop, synchronises, and writes the average
+ * kernel time per pass in milliseconds to pass_ms (host, >= 5 floats) and the
+ * number of passes (3 for d = 2: X-forward, Y forward*lambda*inverse,
+ * X-inverse; 5 for d = 3: X-forward, Y-forward, Z forward*lambda*inverse,
+ * Y-inverse, X-inverse) to *npass.  The result in y is that of fl_apply.
  */
 fl_status fl_apply_profiled(fl_op op, const void *u, void *y, int prec, int reps, void *stream,
                             float *pass_ms, int *npass);
+
+/*
+ * Kernel variants.  Every (precision, FFT length, d) has one or more compiled
+ * variants of the matvec kernels, differing in points per thread of the row
+ * and strided passes (radix plan), spectrum tile width and rows per block;
+ * variant 0 is the built-in default.  They all compute the same y = A u.
+ *   fl_variant_count  -- number of variants for prec (host int).
+ *   fl_variant_info   -- desc4 (host, 4 ints) = {row points per thread,
+ *                        strided points per thread, tile width, row pairs per block}.
+ *   fl_select_variant -- use variant k for prec on this operator (synchronises).
+ *   fl_autotune       -- time every variant (reps matvecs each, HIP events, on
+ *                        `stream`, scratch vectors allocated and freed inside),
+ *                        select the fastest, return its index in *best and, if
+ *                        ms_per_variant (host, count floats) is non-null, the
+ *                        average milliseconds per matvec of each variant.
+ */
+fl_status fl_variant_count(fl_op op, int prec, int *count);
+fl_status fl_variant_info(fl_op op, int prec, int k, int *desc4);
+fl_status fl_select_variant(fl_op op, int prec, int k);
+fl_status fl_autotune(fl_op op, int prec, int reps, void *stream, int *best, float *ms_per_variant);
 
 /* Free the operator and its device workspaces.  NULL is accepted. */
 fl_status fl_op_destroy(fl_op op);

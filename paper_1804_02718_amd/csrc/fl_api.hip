@@ -2,6 +2,7 @@
 // the matvec entry and host copies of the coefficients and eigenvalues.
 #include <cmath>
 #include <cstdarg>
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -59,7 +60,8 @@ static void destroy(fl_op op) {
     if (!op) return;
     (void)hipFree(op->a);
     (void)hipFree(op->lam64);
-    (void)hipFree(op->lam32);
+    (void)hipFree(op->lam64t);
+    (void)hipFree(op->lam32t);
     (void)hipFree(op->tw64);
     (void)hipFree(op->tw32);
     (void)hipFree(op->T1);
@@ -91,8 +93,13 @@ static fl_status create(int d, double alpha, double h, int N, fl_op *out) {
     const long nv = d == 2 ? V * V : V * V * V;
     const long ql = d == 2 ? (long)op->Q * op->Q : (long)op->Q * op->Q * op->Q;
     const long n = op->n;
-    op->T1_bytes = sizeof(double2) * (size_t)(d == 2 ? n : n * n) * op->Qp;
-    op->T2_bytes = d == 2 ? 0 : sizeof(double2) * (size_t)n * op->P * op->Qp;
+    // tiled spectra: ntiles * C <= Q + C - 1 columns per line, sized for the
+    // widest tile and 16-byte (FP64) values
+    const long w32 = op->Q + kMaxTile - 1, w64 = op->Q + kMaxTile - 1;
+    const size_t colb = sizeof(double2) * w64;
+    op->T1_bytes = colb * (size_t)(d == 2 ? n : n * n);
+    op->T2_bytes = d == 2 ? 0 : colb * (size_t)n * op->P;
+    const long qrest = d == 2 ? (long)op->Q : (long)op->Q * op->Q;
     fl_status st = FL_OK;
     auto fail = [&](fl_status s) {
         destroy(op);
@@ -101,7 +108,8 @@ static fl_status create(int d, double alpha, double h, int N, fl_op *out) {
     hipError_t e;
     if ((e = hipMalloc((void **)&op->a, sizeof(double) * nv)) != hipSuccess ||
         (e = hipMalloc((void **)&op->lam64, sizeof(double) * ql)) != hipSuccess ||
-        (e = hipMalloc((void **)&op->lam32, sizeof(float) * ql)) != hipSuccess ||
+        (e = hipMalloc((void **)&op->lam64t, sizeof(double) * qrest * w64)) != hipSuccess ||
+        (e = hipMalloc((void **)&op->lam32t, sizeof(float) * qrest * w32)) != hipSuccess ||
         (e = hipMalloc(&op->T1, op->T1_bytes)) != hipSuccess ||
         (op->T2_bytes && (e = hipMalloc(&op->T2, op->T2_bytes)) != hipSuccess)) {
         set_error("device allocation: %s", hipGetErrorString(e));
@@ -205,32 +213,105 @@ fl_status fl_apply_profiled(fl_op op, const void *u, void *y, int prec, int reps
     if (overlap(u, es * op->M, y, es * op->M)) { set_error("u and y overlap"); return FL_E_INVAL; }
     const int np = op->d == 2 ? 3 : 5;
     hipStream_t s = (hipStream_t)stream;
-    hipEvent_t ev[6 * 64];
-    const int chunk = reps < 64 ? reps : 64;
-    for (int i = 0; i < (np + 1) * chunk; ++i) FL_HIP_TRY(hipEventCreate(&ev[i]));
-    double acc[6] = {0, 0, 0, 0, 0, 0};
+    constexpr int kChunk = 64;
+    std::vector<hipEvent_t> ev(2 * 5 * kChunk);
+    const int chunk = reps < kChunk ? reps : kChunk;
+    for (int i = 0; i < 2 * np * chunk; ++i) FL_HIP_TRY(hipEventCreate(&ev[i]));
+    double acc[5] = {0, 0, 0, 0, 0};
     fl_status st = FL_OK;
     for (int done = 0; done < reps && st == FL_OK; done += chunk) {
         const int k = reps - done < chunk ? reps - done : chunk;
         for (int r = 0; r < k && st == FL_OK; ++r) {
-            hipEvent_t *e = ev + (np + 1) * r;
+            hipEvent_t *e = ev.data() + 2 * np * r;
             st = prec == FL_FP64 ? matvec_ex<double>(op, (const double *)u, (double *)y, Epi<double>{}, nullptr, s, e)
                                  : matvec_ex<float>(op, (const float *)u, (float *)y, Epi<float>{}, nullptr, s, e);
         }
         if (hipStreamSynchronize(s) != hipSuccess) st = FL_E_DEVICE;
         for (int r = 0; r < k && st == FL_OK; ++r) {
-            hipEvent_t *e = ev + (np + 1) * r;
+            hipEvent_t *e = ev.data() + 2 * np * r;
             for (int p = 0; p < np; ++p) {
                 float ms = 0.f;
-                if (hipEventElapsedTime(&ms, e[p], e[p + 1]) != hipSuccess) st = FL_E_DEVICE;
+                if (hipEventElapsedTime(&ms, e[2 * p], e[2 * p + 1]) != hipSuccess) st = FL_E_DEVICE;
                 acc[p] += ms;
             }
         }
     }
-    for (int i = 0; i < (np + 1) * chunk; ++i) (void)hipEventDestroy(ev[i]);
+    for (int i = 0; i < 2 * np * chunk; ++i) (void)hipEventDestroy(ev[i]);
     if (st != FL_OK) { set_error("profiled apply failed"); return st; }
     for (int p = 0; p < np; ++p) pass_ms[p] = (float)(acc[p] / reps);
     *npass = np;
+    return FL_OK;
+}
+
+fl_status fl_variant_count(fl_op op, int prec, int *count) {
+    if (!op || !count || (prec != FL_FP64 && prec != FL_FP32)) { set_error("bad argument"); return FL_E_INVAL; }
+    *count = variant_count(op, prec);
+    return FL_OK;
+}
+
+fl_status fl_variant_info(fl_op op, int prec, int k, int *desc4) {
+    if (!op || !desc4 || (prec != FL_FP64 && prec != FL_FP32)) { set_error("bad argument"); return FL_E_INVAL; }
+    if (k < 0 || k >= variant_count(op, prec)) { set_error("variant %d out of range", k); return FL_E_INVAL; }
+    const VariantDesc v = variant_desc(op, prec, k);
+    desc4[0] = v.ex;
+    desc4[1] = v.ey;
+    desc4[2] = v.c;
+    desc4[3] = v.lpb;
+    return FL_OK;
+}
+
+fl_status fl_select_variant(fl_op op, int prec, int k) {
+    if (!op || (prec != FL_FP64 && prec != FL_FP32)) { set_error("bad argument"); return FL_E_INVAL; }
+    hipStream_t s = nullptr;
+    FL_HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    fl_status st = select_variant(op, prec, k, s);
+    hipError_t e = hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+    FL_TRY(st);
+    FL_HIP_TRY(e);
+    return FL_OK;
+}
+
+fl_status fl_autotune(fl_op op, int prec, int reps, void *stream, int *best, float *ms_out) {
+    if (!op || reps < 1 || (prec != FL_FP64 && prec != FL_FP32)) { set_error("bad argument"); return FL_E_INVAL; }
+    const int nv = variant_count(op, prec);
+    const size_t es = prec == FL_FP64 ? sizeof(double) : sizeof(float);
+    hipStream_t s = (hipStream_t)stream;
+    void *buf = nullptr;
+    FL_HIP_TRY(hipMalloc(&buf, 2 * es * (size_t)op->M));
+    fl_status st = FL_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipMemsetAsync(buf, 0, 2 * es * (size_t)op->M, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess)
+        st = FL_E_DEVICE;
+    void *u = buf, *y = (char *)buf + es * op->M;
+    int bi = 0;
+    float bms = 1e30f;
+    for (int k = 0; k < nv && st == FL_OK; ++k) {
+        st = select_variant(op, prec, k, s);
+        for (int r = 0; r < 3 + reps && st == FL_OK; ++r) {
+            if (r == 3 && hipEventRecord(e0, s) != hipSuccess) st = FL_E_DEVICE;
+            st = prec == FL_FP64 ? matvec<double>(op, (const double *)u, (double *)y, s)
+                                 : matvec<float>(op, (const float *)u, (float *)y, s);
+        }
+        float ms = 0.f;
+        if (st == FL_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            st = FL_E_DEVICE;
+        ms /= reps;
+        if (ms_out) ms_out[k] = ms;
+        if (st == FL_OK && ms < bms) {
+            bms = ms;
+            bi = k;
+        }
+    }
+    if (st == FL_OK) st = select_variant(op, prec, bi, s);
+    (void)hipStreamSynchronize(s);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(buf);
+    if (st != FL_OK) return st;
+    if (best) *best = bi;
     return FL_OK;
 }
 

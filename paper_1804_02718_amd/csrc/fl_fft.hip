@@ -7,74 +7,117 @@
 // y = A u is then: zero-pad u to P^d, FFT, multiply by lambda, inverse FFT,
 // keep the first n points per axis.
 //
-// Passes (x fastest, kx the half-spectrum index 0..Q-1, Q = P/2+1):
+// Passes (x fastest; kx the half-spectrum index 0..Q-1, Q = P/2+1):
 //   2D: X-fwd (real rows -> half spectra) | Y fused (fwd, x lambda, inv, crop) | X-inv
 //   3D: X-fwd | Y-fwd | Z fused | Y-inv | X-inv
-// Row passes pack two real rows into one complex line.  Strided passes keep
-// C neighbouring columns per workgroup so that every global access is a run
-// of C consecutive complex values.
-#include <type_traits>
+// Half spectra are stored in tiles of C consecutive kx: element (slab k,
+// tile t, line position j, column c) sits at ((k*ntiles + t)*nj + j)*C + c, so a
+// strided pass reads each tile as one contiguous block and a row pass writes
+// runs of C values for each of its rows.  Row passes pack two real rows into
+// one complex line.  The inverse transforms are the adjoints of the forward
+// stages in reverse order, so every pass loads its twiddles once.
+#include <hip/hip_ext.h>
 
 #include "fl_internal.hpp"
 
 namespace fl {
 
-// LDS index maps: row passes store each line contiguously, strided passes
-// interleave the C columns of a workgroup (column index fastest).
-struct LineMajor {
-    int base;
-    __device__ __forceinline__ int operator()(int pos) const { return base + pos; }
-};
-template <int C> struct ColInterleaved {
-    int c;
-    __device__ __forceinline__ int operator()(int pos) const { return pos * C + c; }
+template <int P> __device__ __forceinline__ int fold(int k) { return k <= P / 2 ? k : P - k; }
+
+// default launch shape of each (precision, length, dimension); the autotuner
+// can replace it by one of the variants listed further down
+template <typename T, int P, int D> struct Shape {
+    static constexpr int E = P >= 128 ? 16 : (P >= 16 ? 8 : P);
+    static constexpr int TL = P / E;
+    static constexpr int SZ = (int)sizeof(C2<T>);
+    // tile width: columns per strided workgroup
+    static constexpr int C32 = D == 3 ? (P >= 1024 ? 8 : 16) : (P >= 1024 ? 4 : (P >= 256 ? 8 : 16));
+    static constexpr int C = sizeof(T) == 8 ? (C32 / 2 < 2 ? 2 : C32 / 2) : C32;
+    // row passes: line pairs per block (>= 128-byte runs per tile, ~256 threads)
+    static constexpr int lp_bytes = (128 + 2 * C * SZ - 1) / (2 * C * SZ);
+    static constexpr int lp_thr = TL >= 256 ? 1 : 256 / TL;
+    static constexpr int lp_max = TL >= 512 ? 1 : 512 / TL;
+    static constexpr int LPB0 = lp_bytes > lp_thr ? lp_bytes : lp_thr;
+    static constexpr int LPB = LPB0 > lp_max ? lp_max : LPB0;
 };
 
-template <int P> __device__ __forceinline__ int fold(int k) { return k <= P / 2 ? k : P - k; }
+// tiled layout: row r of slab k = r / nj, line j = r mod nj, column kx = t*C + c
+// at ((k*ntiles + t)*nj + j)*C + c = rowbase(r) + t*(nj*C) + c (element offsets
+// stay below 2^31 for every supported size)
+__device__ __forceinline__ int tiled_rowbase(int r, int nj, int ntiles, int C) {
+    const int k = r / nj, j = r - k * nj;
+    return (k * ntiles * nj + j) * C;
+}
 
 // ---------------------------------------------------------------------------
 // row pass, forward: pairs of real rows (n_in values each, zero-padded to P)
-// -> Q complex half-spectrum values per row.
+// -> Q half-spectrum values per row, written tiled.
 // ---------------------------------------------------------------------------
-template <typename T, int P, int LPB>
-__global__ __launch_bounds__(LPB *(P / Plan<P>::E)) void k_xfwd(
-    const T *__restrict__ u, C2<T> *__restrict__ out, int nrows, int n_in, long in_pitch,
-    long out_pitch, const C2<T> *__restrict__ tw, const double *__restrict__ done) {
+template <typename T, int P, int E, int C, int LPB>
+__global__ __launch_bounds__(LPB * (P / E)) void k_xfwd(
+    const T *__restrict__ u, C2<T> *__restrict__ out, int nrows, int n_in, long in_pitch, int nj, int ntiles,
+    const C2<T> *__restrict__ table, const double *__restrict__ done) {
     if (done && *done != 0.0) return;
-    using PL = Plan<P>;
-    constexpr int E = PL::E, TL = P / E;
-    constexpr int R1 = Front<typename PL::Fwd>::value;
-    constexpr int RL = Back<typename PL::Fwd>::value;
-    __shared__ C2<T> lds[LPB * P];
+    using PN = Plan<P, E>;
+    constexpr int TL = P / E, L = PN::L;
+    constexpr int PL = padded_len<P>();
+    __shared__ C2<T> lds[LPB * PL];
     const int tl = threadIdx.x % TL;
-    const int c = threadIdx.x / TL;
-    const long pair = (long)blockIdx.x * LPB + c;
-    const long ra = 2 * pair, rb = 2 * pair + 1;
+    const int lp = threadIdx.x / TL;
+    const int ra = 2 * (blockIdx.x * LPB + lp), rb = ra + 1;
     const bool va = ra < nrows, vb = rb < nrows;
-    const T *ua = u + ra * in_pitch;
-    const T *ub = u + rb * in_pitch;
+    C2<T> tws[num_tw<PN>()];
+    load_twiddles<T, P, PN>(tws, table, tl);
     C2<T> v[E];
+    // loads from clamped, always valid addresses; out-of-range values replaced by 0
+    const T *ua = u + (long)(va ? ra : 0) * in_pitch, *ub = u + (long)(vb ? rb : 0) * in_pitch;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-        const int pos = slot_pos<P, E, R1>(tl, j);
-        const T xa = (va && pos < n_in) ? ua[pos] : T(0);
-        const T xb = (vb && pos < n_in) ? ub[pos] : T(0);
-        v[j] = mk<T>(xa, xb);
+        const int pos = in_pos<P, PN, 0>(tl, j);
+        const bool in = pos < n_in;
+        const int pc = in ? pos : 0;
+        const T xa = ua[pc], xb = ub[pc];
+        v[j] = mk<T>((va && in) ? xa : T(0), (vb && in) ? xb : T(0));
     }
-    LineMajor lidx{c * P};
-    Stages<T, P, E, -1, 1, typename PL::Fwd>::run(v, lds, tl, tw, lidx);
+    const int base = lp * PL;
+    auto lidx = [base](int pos) { return base + padpos(pos); };
+    fwd_stages<T, P, PN, 0>(v, lds, tl, tws, lidx);
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < E; ++j) lds[lidx(slot_pos<P, E, RL>(tl, j))] = v[j];
+    for (int j = 0; j < E; ++j) lds[lidx(out_pos<P, PN, L - 1>(tl, j))] = v[j];
     __syncthreads();
-    if (!va) return;
-    C2<T> *oa = out + ra * out_pitch;
-    C2<T> *ob = out + rb * out_pitch;
-    for (int k = tl; k <= P / 2; k += TL) {
-        const C2<T> zk = lds[lidx(k)];
-        const C2<T> zm = lds[lidx((P - k) & (P - 1))];
-        oa[k] = mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
-        if (vb) ob[k] = mk<T>(T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x));
+    // Hermitian split, written tile by tile: consecutive threads cover the
+    // block's rows of one tile, which are contiguous in the tiled layout
+    constexpr int RW = 2 * LPB, NTH = LPB * TL;
+    const int r0 = 2 * blockIdx.x * LPB;
+    const int tstride = nj * C;
+    if constexpr (NTH % (C * RW) == 0) {
+        // a thread keeps one (row, column) and walks the tiles
+        const int c = threadIdx.x % C, rr = (threadIdx.x / C) % RW;
+        const int row = r0 + rr;
+        if (row >= nrows) return;
+        const int pb = (rr >> 1) * PL;
+        C2<T> *orow = out + tiled_rowbase(row, nj, ntiles, C) + c;
+        for (int t = threadIdx.x / (C * RW); t < ntiles; t += NTH / (C * RW)) {
+            const int kx = t * C + c;
+            if (kx > P / 2) continue;
+            const C2<T> zk = lds[pb + padpos(kx)];
+            const C2<T> zm = lds[pb + padpos((P - kx) & (P - 1))];
+            orow[t * tstride] = (rr & 1) ? mk<T>(T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x))
+                                         : mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < ntiles * RW * C; idx += NTH) {
+            const int c = idx % C, rr = (idx / C) % RW, t = idx / (C * RW);
+            const int kx = t * C + c, row = r0 + rr;
+            if (kx > P / 2 || row >= nrows) continue;
+            const int pb = (rr >> 1) * PL;
+            const C2<T> zk = lds[pb + padpos(kx)];
+            const C2<T> zm = lds[pb + padpos((P - kx) & (P - 1))];
+            out[tiled_rowbase(row, nj, ntiles, C) + t * tstride + c] =
+                (rr & 1) ? mk<T>(T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x))
+                         : mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
+        }
     }
 }
 
@@ -84,46 +127,76 @@ __global__ __launch_bounds__(LPB *(P / Plan<P>::E)) void k_xfwd(
 // at the same position when non-null (shifted operators and residuals of the
 // solvers).  A non-null `done` flag that is set makes the kernel a no-op.
 // ---------------------------------------------------------------------------
-template <typename T, int P, int LPB, bool EPI>
-__global__ __launch_bounds__(LPB *(P / Plan<P>::E)) void k_xinv(
-    const C2<T> *__restrict__ in, T *__restrict__ y, int nrows, int n_out, long in_pitch,
-    long out_pitch, const C2<T> *__restrict__ tw, Epi<T> ep, const double *__restrict__ done) {
+template <typename T, int P, int E, int C, int LPB, bool EPI>
+__global__ __launch_bounds__(LPB * (P / E)) void k_xinv(
+    const C2<T> *__restrict__ in, T *__restrict__ y, int nrows, int n_out, long out_pitch, int nj, int ntiles,
+    const C2<T> *__restrict__ table, Epi<T> ep, const double *__restrict__ done) {
     if (done && *done != 0.0) return;
-    using PL = Plan<P>;
-    constexpr int E = PL::E, TL = P / E;
-    constexpr int R1 = Front<typename PL::Inv>::value;
-    constexpr int RL = Back<typename PL::Inv>::value;
-    __shared__ C2<T> lds[LPB * P];
+    using PN = Plan<P, E>;
+    constexpr int TL = P / E, L = PN::L;
+    constexpr int PL = padded_len<P>();
+    constexpr int Q = P / 2 + 1;
+    constexpr int LL = PL > 2 * Q ? PL : 2 * Q;  // LDS per line pair
+    __shared__ C2<T> lds[LPB * LL];
     const int tl = threadIdx.x % TL;
-    const int c = threadIdx.x / TL;
-    const long pair = (long)blockIdx.x * LPB + c;
-    const long ra = 2 * pair, rb = 2 * pair + 1;
+    const int lp = threadIdx.x / TL;
+    const int ra = 2 * (blockIdx.x * LPB + lp), rb = ra + 1;
     const bool va = ra < nrows, vb = rb < nrows;
-    const C2<T> *ia = in + ra * in_pitch;
-    const C2<T> *ib = in + rb * in_pitch;
+    C2<T> tws[num_tw<PN>()];
+    load_twiddles<T, P, PN>(tws, table, tl);
+    // the block's rows, tile by tile (contiguous runs), into LDS: row pair p,
+    // member w at p*LL + w*Q + kx
+    constexpr int RW = 2 * LPB, NTH = LPB * TL;
+    {
+        const int r0 = 2 * blockIdx.x * LPB;
+        const int tstride = nj * C;
+        if constexpr (NTH % (C * RW) == 0) {
+            const int c = threadIdx.x % C, rr = (threadIdx.x / C) % RW;
+            const int row = r0 + rr;
+            const bool rv = row < nrows;
+            const C2<T> *irow = in + tiled_rowbase(rv ? row : 0, nj, ntiles, C) + c;
+            C2<T> *lrow = lds + (rr >> 1) * LL + (rr & 1) * Q;
+            for (int t = threadIdx.x / (C * RW); t < ntiles; t += NTH / (C * RW)) {
+                const int kx = t * C + c;
+                if (kx >= Q) continue;
+                const C2<T> x = irow[t * tstride];
+                lrow[kx] = rv ? x : mk<T>(0, 0);
+            }
+        } else {
+            for (int idx = threadIdx.x; idx < ntiles * RW * C; idx += NTH) {
+                const int c = idx % C, rr = (idx / C) % RW, t = idx / (C * RW);
+                const int kx = t * C + c, row = r0 + rr;
+                if (kx >= Q) continue;
+                lds[(rr >> 1) * LL + (rr & 1) * Q + kx] =
+                    row < nrows ? in[tiled_rowbase(row, nj, ntiles, C) + t * tstride + c] : mk<T>(0, 0);
+            }
+        }
+    }
+    __syncthreads();
     C2<T> v[E];
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-        const int pos = slot_pos<P, E, R1>(tl, j);
-        const int kk = pos <= P / 2 ? pos : P - pos;
-        C2<T> xa = va ? ia[kk] : mk<T>(0, 0);
-        C2<T> xb = vb ? ib[kk] : mk<T>(0, 0);
+        const int pos = out_pos<P, PN, L - 1>(tl, j);
+        const int kk = fold<P>(pos);
+        C2<T> xa = lds[lp * LL + kk];
+        C2<T> xb = lds[lp * LL + Q + kk];
         if (pos > P / 2) { xa.y = -xa.y; xb.y = -xb.y; }
         if (pos == 0 || pos == P / 2) { xa.y = T(0); xb.y = T(0); }
         v[j] = mk<T>(xa.x - xb.y, xa.y + xb.x);
     }
-    LineMajor lidx{c * P};
-    Stages<T, P, E, +1, 1, typename PL::Inv>::run(v, lds, tl, tw, lidx);
+    __syncthreads();
+    const int base = lp * LL;
+    auto lidx = [base](int pos) { return base + padpos(pos); };
+    adj_stages<T, P, PN, L - 1>(v, lds, tl, tws, lidx);
     if (!va) return;
-    T *ya = y + ra * out_pitch;
-    T *yb = y + rb * out_pitch;
+    T *ya = y + (long)ra * out_pitch, *yb = y + (long)rb * out_pitch;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-        const int pos = slot_pos<P, E, RL>(tl, j);
+        const int pos = in_pos<P, PN, 0>(tl, j);
         if (pos < n_out) {
             T a = v[j].x, b = v[j].y;
             if constexpr (EPI) {
-                const long ia2 = ra * out_pitch + pos, ib2 = rb * out_pitch + pos;
+                const long ia2 = (long)ra * out_pitch + pos, ib2 = (long)rb * out_pitch + pos;
                 a = ep.scale * a;
                 if (ep.w1) a += ep.a1 * ep.w1[ia2];
                 if (ep.w2) a += ep.a2 * ep.w2[ia2];
@@ -140,189 +213,285 @@ __global__ __launch_bounds__(LPB *(P / Plan<P>::E)) void k_xinv(
 }
 
 // ---------------------------------------------------------------------------
-// strided pass over lines along a non-contiguous axis.  Line (o, kx) starts at
-// o*outer + kx and steps by line_stride.  MODE 0: forward; 1: inverse;
-// 2: forward, multiply by lambda, inverse.  n_in values are read (the rest
-// taken as zero), n_out values written.  In-place use is allowed: a
-// workgroup reads all of its lines before writing any of them.
+// strided pass: the C lines of tile t for outer index o, line position p at
+// o*outer + t*tile + p*line + c.  MODE 0: forward; 1: inverse; 2: forward,
+// multiply by lambda (tiled: t*lam_tile + fold(o)*lam_outer + fold(p)*C + c),
+// inverse.  n_in values read (the rest zero), n_out written; in place allowed.
 // ---------------------------------------------------------------------------
-template <typename T, int P, int C, int MODE>
-__global__ __launch_bounds__(C *(P / Plan<P>::E)) void k_strided(
-    const C2<T> *in, C2<T> *out, int ncols, int n_in, int n_out, long line_stride, long in_outer,
-    long out_outer, const C2<T> *__restrict__ tw, const T *__restrict__ lam, long lam_line,
-    long lam_outer, const double *__restrict__ done) {
-    if (done && *done != 0.0) return;
-    using PL = Plan<P>;
-    constexpr int E = PL::E, TL = P / E;
-    using First = typename std::conditional<MODE == 1, typename PL::Inv, typename PL::Fwd>::type;
-    constexpr int R1 = Front<First>::value;
-    static_assert(Back<typename PL::Fwd>::value == Front<typename PL::Inv>::value,
-                  "inverse plan must start with the forward plan's last radix");
-    __shared__ C2<T> lds[C * P];
-    const int c = threadIdx.x % C;
-    const int tl = threadIdx.x / C;
-    const int kx = blockIdx.x * C + c;
-    const bool valid = kx < ncols;
-    const long o = blockIdx.y;
-    const C2<T> *src = in + o * in_outer + kx;
-    C2<T> *dst = out + o * out_outer + kx;
-    C2<T> v[E];
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-        const int pos = slot_pos<P, E, R1>(tl, j);
-        v[j] = (valid && pos < n_in) ? src[pos * line_stride] : mk<T>(0, 0);
-    }
-    ColInterleaved<C> lidx{c};
-    if constexpr (MODE == 0) {
-        Stages<T, P, E, -1, 1, typename PL::Fwd>::run(v, lds, tl, tw, lidx);
-        constexpr int RL = Back<typename PL::Fwd>::value;
-        if (!valid) return;
-#pragma unroll
-        for (int j = 0; j < E; ++j) {
-            const int pos = slot_pos<P, E, RL>(tl, j);
-            if (pos < n_out) dst[pos * line_stride] = v[j];
-        }
-    } else if constexpr (MODE == 1) {
-        Stages<T, P, E, +1, 1, typename PL::Inv>::run(v, lds, tl, tw, lidx);
-        constexpr int RL = Back<typename PL::Inv>::value;
-        if (!valid) return;
-#pragma unroll
-        for (int j = 0; j < E; ++j) {
-            const int pos = slot_pos<P, E, RL>(tl, j);
-            if (pos < n_out) dst[pos * line_stride] = v[j];
-        }
-    } else {
-        Stages<T, P, E, -1, 1, typename PL::Fwd>::run(v, lds, tl, tw, lidx);
-        constexpr int RM = Back<typename PL::Fwd>::value;
-        const T *lo = lam + (long)fold<P>((int)o) * lam_outer + kx;
-#pragma unroll
-        for (int j = 0; j < E; ++j) {
-            const int pos = slot_pos<P, E, RM>(tl, j);
-            const T l = valid ? lo[(long)fold<P>(pos) * lam_line] : T(0);
-            v[j] = cscale<T>(v[j], l);
-        }
-        __syncthreads();
-        Stages<T, P, E, +1, 1, typename PL::Inv>::run(v, lds, tl, tw, lidx);
-        constexpr int RL = Back<typename PL::Inv>::value;
-        if (!valid) return;
-#pragma unroll
-        for (int j = 0; j < E; ++j) {
-            const int pos = slot_pos<P, E, RL>(tl, j);
-            if (pos < n_out) dst[pos * line_stride] = v[j];
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// launch shapes
-// ---------------------------------------------------------------------------
-template <typename T, int P> struct Shape {
-    static constexpr int TL = P / Plan<P>::E;
-    static constexpr int LPB = TL >= 256 ? 1 : 256 / TL;  // row passes: line pairs per block
-    static constexpr int CB = (int)sizeof(C2<T>) * P;     // bytes per column line
-    // strided passes: columns per block, at most 32, at most 512 threads
-    // (1024 at P >= 2048) and at most 64 KB of LDS (128 KB at P >= 2048)
-    static constexpr int thr = P >= 2048 ? 1024 : 512;
-    static constexpr int cth = thr / TL < 1 ? 1 : (thr / TL > 32 ? 32 : thr / TL);
-    static constexpr int clds = (P >= 2048 ? 131072 : 65536) / CB;
-    static constexpr int C = cth < clds ? cth : (clds < 1 ? 1 : clds);
+struct Strides {  // element offsets (below 2^31 for every supported size)
+    int in_outer, in_tile, out_outer, out_tile, line;
+    int lam_tile, lam_outer;
 };
 
-static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
-
-template <typename T, int P>
-static void launch_xfwd(const T *u, C2<T> *out, int nrows, int n_in, long in_pitch, long out_pitch,
-                        const C2<T> *tw, const double *done, hipStream_t s) {
-    using S = Shape<T, P>;
-    const int pairs = (nrows + 1) / 2;
-    hipLaunchKernelGGL((k_xfwd<T, P, S::LPB>), dim3(cdiv(pairs, S::LPB)), dim3(S::LPB * S::TL), 0, s,
-                       u, out, nrows, n_in, in_pitch, out_pitch, tw, done);
-}
-
-template <typename T, int P>
-static void launch_xinv(const C2<T> *in, T *y, int nrows, int n_out, long in_pitch, long out_pitch,
-                        const C2<T> *tw, const Epi<T> &ep, const double *done, hipStream_t s) {
-    using S = Shape<T, P>;
-    const int pairs = (nrows + 1) / 2;
-    if (ep.active())
-        hipLaunchKernelGGL((k_xinv<T, P, S::LPB, true>), dim3(cdiv(pairs, S::LPB)), dim3(S::LPB * S::TL),
-                           0, s, in, y, nrows, n_out, in_pitch, out_pitch, tw, ep, done);
-    else
-        hipLaunchKernelGGL((k_xinv<T, P, S::LPB, false>), dim3(cdiv(pairs, S::LPB)), dim3(S::LPB * S::TL),
-                           0, s, in, y, nrows, n_out, in_pitch, out_pitch, tw, ep, done);
-}
-
-template <typename T, int P, int MODE>
-static void launch_strided(const C2<T> *in, C2<T> *out, int ncols, int nouter, int n_in, int n_out,
-                           long line_stride, long in_outer, long out_outer, const C2<T> *tw,
-                           const T *lam, long lam_line, long lam_outer, const double *done, hipStream_t s) {
-    using S = Shape<T, P>;
-    hipLaunchKernelGGL((k_strided<T, P, S::C, MODE>), dim3(cdiv(ncols, S::C), nouter), dim3(S::C * S::TL),
-                       0, s, in, out, ncols, n_in, n_out, line_stride, in_outer, out_outer, tw, lam,
-                       lam_line, lam_outer, done);
+template <typename T, int P, int E, int C, int MODE>
+__global__ __launch_bounds__(C * (P / E)) void k_strided(
+    const C2<T> *in, C2<T> *out, int ncols, int n_in, int n_out, Strides st, const C2<T> *__restrict__ table,
+    const T *__restrict__ lam, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    using PN = Plan<P, E>;
+    constexpr int L = PN::L;
+    constexpr int PL = padded_len<P>();
+    __shared__ C2<T> lds[C * PL];
+    const int c = threadIdx.x % C;
+    const int tl = threadIdx.x / C;
+    const int t = blockIdx.x;
+    const bool valid = t * C + c < ncols;
+    const int o = blockIdx.y;
+    // columns past ncols still lie inside the tile; their loads are discarded
+    const C2<T> *src = in + (o * st.in_outer + t * st.in_tile + c);
+    C2<T> *dst = out + (o * st.out_outer + t * st.out_tile + c);
+    C2<T> tws[num_tw<PN>()];
+    load_twiddles<T, P, PN>(tws, table, tl);
+    C2<T> v[E];
+    auto lidx = [c](int pos) { return padpos(pos) * C + c; };
+    if constexpr (MODE == 1) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int pos = out_pos<P, PN, L - 1>(tl, j);
+            const bool in = pos < n_in;
+            const C2<T> x = src[(in ? pos : 0) * st.line];
+            v[j] = (valid && in) ? x : mk<T>(0, 0);
+        }
+        adj_stages<T, P, PN, L - 1>(v, lds, tl, tws, lidx);
+    } else {
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int pos = in_pos<P, PN, 0>(tl, j);
+            const bool in = pos < n_in;
+            const C2<T> x = src[(in ? pos : 0) * st.line];
+            v[j] = (valid && in) ? x : mk<T>(0, 0);
+        }
+        if constexpr (MODE == 2) {
+            // lambda at this thread's spectral positions, fetched with the data
+            T lv[E];
+            const T *lo = lam + (t * st.lam_tile + fold<P>(o) * st.lam_outer + c);
+#pragma unroll
+            for (int j = 0; j < E; ++j) lv[j] = lo[fold<P>(out_pos<P, PN, L - 1>(tl, j)) * C];
+            fwd_stages<T, P, PN, 0>(v, lds, tl, tws, lidx);
+#pragma unroll
+            for (int j = 0; j < E; ++j) v[j] = cscale<T>(v[j], lv[j]);
+            adj_stages<T, P, PN, L - 1>(v, lds, tl, tws, lidx);
+        } else {
+            fwd_stages<T, P, PN, 0>(v, lds, tl, tws, lidx);
+        }
+    }
+    if (!valid) return;
+    if constexpr (MODE == 0) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int pos = out_pos<P, PN, L - 1>(tl, j);
+            if (pos < n_out) dst[pos * st.line] = v[j];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int pos = in_pos<P, PN, 0>(tl, j);
+            if (pos < n_out) dst[pos * st.line] = v[j];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
-// the matvec
+// launches
+// ---------------------------------------------------------------------------
+static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+// ev (optional): kernel start / stop events
+template <typename K, typename... Args>
+static void launch(K kernel, dim3 g, dim3 b, hipStream_t s, const hipEvent_t *ev, Args... args) {
+    if (ev)
+        hipExtLaunchKernelGGL(kernel, g, b, 0, s, ev[0], ev[1], 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, g, b, 0, s, args...);
+}
+
+template <typename T, int P, int E, int C, int LPB>
+static void launch_xfwd(const T *u, C2<T> *out, int nrows, int n_in, long in_pitch, int nj, int ntiles,
+                        const C2<T> *tw, const double *done, hipStream_t s, const hipEvent_t *ev) {
+    const int pairs = (nrows + 1) / 2;
+    launch(k_xfwd<T, P, E, C, LPB>, dim3(cdiv(pairs, LPB)), dim3(LPB * (P / E)), s, ev, u, out, nrows, n_in,
+           in_pitch, nj, ntiles, tw, done);
+}
+
+template <typename T, int P, int E, int C, int LPB>
+static void launch_xinv(const C2<T> *in, T *y, int nrows, int n_out, long out_pitch, int nj, int ntiles,
+                        const C2<T> *tw, const Epi<T> &ep, const double *done, hipStream_t s, const hipEvent_t *ev) {
+    const int pairs = (nrows + 1) / 2;
+    if (ep.active())
+        launch(k_xinv<T, P, E, C, LPB, true>, dim3(cdiv(pairs, LPB)), dim3(LPB * (P / E)), s, ev, in, y, nrows,
+               n_out, out_pitch, nj, ntiles, tw, ep, done);
+    else
+        launch(k_xinv<T, P, E, C, LPB, false>, dim3(cdiv(pairs, LPB)), dim3(LPB * (P / E)), s, ev, in, y, nrows,
+               n_out, out_pitch, nj, ntiles, tw, ep, done);
+}
+
+template <typename T, int P, int E, int C, int MODE>
+static void launch_strided(const C2<T> *in, C2<T> *out, int ncols, int nouter, int n_in, int n_out,
+                           const Strides &st, const C2<T> *tw, const T *lam, const double *done, hipStream_t s,
+                           const hipEvent_t *ev) {
+    launch(k_strided<T, P, E, C, MODE>, dim3(cdiv(ncols, C), nouter), dim3(C * (P / E)), s, ev, in, out, ncols,
+           n_in, n_out, st, tw, lam, done);
+}
+
+// ---------------------------------------------------------------------------
+// the matvec: one variant = (EX points per thread in the row passes, EY in
+// the strided passes, tile width C, line pairs per row block LPB)
 // ---------------------------------------------------------------------------
 template <typename T> static const C2<T> *twid(fl_op op);
 template <> const float2 *twid<float>(fl_op op) { return op->tw32; }
 template <> const double2 *twid<double>(fl_op op) { return op->tw64; }
-template <typename T> static const T *lamb(fl_op op);
-template <> const float *lamb<float>(fl_op op) { return op->lam32; }
-template <> const double *lamb<double>(fl_op op) { return op->lam64; }
+template <typename T> static const T *lamt(fl_op op);
+template <> const float *lamt<float>(fl_op op) { return op->lam32t; }
+template <> const double *lamt<double>(fl_op op) { return op->lam64t; }
 
-template <typename T, int P>
-static void matvec_p(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
-                     hipEvent_t *ev) {
+template <typename T, int P, int D, int EX, int EY, int C, int LPB>
+static void matvec_v(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
+                     const hipEvent_t *ev) {
     const int n = op->n, Q = op->Q;
-    const long Qp = op->Qp;
+    const int nt = cdiv(Q, C);
     C2<T> *T1 = (C2<T> *)op->T1;
     C2<T> *T2 = (C2<T> *)op->T2;
     const C2<T> *tw = twid<T>(op);
-    const T *lam = lamb<T>(op);
-    // ev (optional): ev[0] before the first pass, ev[i+1] after pass i
-    auto mark = [&](int i) {
-        if (ev) (void)hipEventRecord(ev[i], s);
-    };
-    mark(0);
-    if (op->d == 2) {
-        launch_xfwd<T, P>(u, T1, n, n, n, Qp, tw, done, s);
-        mark(1);
-        launch_strided<T, P, 2>(T1, T1, Q, 1, n, n, Qp, 0, 0, tw, lam, Q, 0, done, s);
-        mark(2);
-        launch_xinv<T, P>(T1, y, n, n, Qp, n, tw, ep, done, s);
-        mark(3);
+    const T *lam = lamt<T>(op);
+    auto E = [&](int i) { return ev ? ev + 2 * i : nullptr; };
+    if constexpr (D == 2) {
+        launch_xfwd<T, P, EX, C, LPB>(u, T1, n, n, n, n, nt, tw, done, s, E(0));
+        Strides sy{0, n * C, 0, n * C, C, Q * C, 0};
+        launch_strided<T, P, EY, C, 2>(T1, T1, Q, 1, n, n, sy, tw, lam, done, s, E(1));
+        launch_xinv<T, P, EX, C, LPB>(T1, y, n, n, n, n, nt, tw, ep, done, s, E(2));
     } else {
         const long nn = (long)n * n;
-        launch_xfwd<T, P>(u, T1, (int)nn, n, n, Qp, tw, done, s);
-        mark(1);
-        launch_strided<T, P, 0>(T1, T2, Q, n, n, P, Qp, n * Qp, (long)P * Qp, tw, nullptr, 0, 0, done, s);
-        mark(2);
-        launch_strided<T, P, 2>(T2, T2, Q, P, n, n, (long)P * Qp, Qp, Qp, tw, lam, (long)Q * Q, Q, done, s);
-        mark(3);
-        launch_strided<T, P, 1>(T2, T1, Q, n, P, n, Qp, (long)P * Qp, n * Qp, tw, nullptr, 0, 0, done, s);
-        mark(4);
-        launch_xinv<T, P>(T1, y, (int)nn, n, Qp, n, tw, ep, done, s);
-        mark(5);
+        launch_xfwd<T, P, EX, C, LPB>(u, T1, (int)nn, n, n, n, nt, tw, done, s, E(0));
+        Strides s1{nt * n * C, n * C, nt * P * C, P * C, C, 0, 0};
+        launch_strided<T, P, EY, C, 0>(T1, T2, Q, n, n, P, s1, tw, nullptr, done, s, E(1));
+        Strides s2{C, P * C, C, P * C, nt * P * C, Q * Q * C, Q * C};
+        launch_strided<T, P, EY, C, 2>(T2, T2, Q, P, n, n, s2, tw, lam, done, s, E(2));
+        Strides s3{nt * P * C, P * C, nt * n * C, n * C, C, 0, 0};
+        launch_strided<T, P, EY, C, 1>(T2, T1, Q, n, P, n, s3, tw, nullptr, done, s, E(3));
+        launch_xinv<T, P, EX, C, LPB>(T1, y, (int)nn, n, n, n, nt, tw, ep, done, s, E(4));
     }
 }
+
+template <typename T> struct Variant {
+    VariantDesc desc;
+    void (*fn)(fl_op, const T *, T *, const Epi<T> &, const double *, hipStream_t, const hipEvent_t *);
+};
+
+#define FL_VAR(T, P, D, EX, EY, C, LPB) \
+    { {EX, EY, C, LPB}, &matvec_v<T, P, D, EX, EY, C, LPB> }
+#define FL_DEF(T, P, D)                                                                      \
+    FL_VAR(T, P, D, (Shape<T, P, D>::E), (Shape<T, P, D>::E), (Shape<T, P, D>::C), (Shape<T, P, D>::LPB))
+
+// candidate variants per (precision, P, d); the first is the default
+template <typename T> static const Variant<T> *variants(int P, int d, int *count);
+
+template <> const Variant<float> *variants<float>(int P, int d, int *count) {
+    using T = float;
+    static const Variant<T> v2_8[] = {FL_DEF(T, 8, 2)};
+    static const Variant<T> v2_16[] = {FL_DEF(T, 16, 2)};
+    static const Variant<T> v2_32[] = {FL_DEF(T, 32, 2)};
+    static const Variant<T> v2_64[] = {FL_DEF(T, 64, 2)};
+    static const Variant<T> v2_128[] = {FL_DEF(T, 128, 2), FL_VAR(T, 128, 2, 8, 8, 8, 4)};
+    static const Variant<T> v2_256[] = {FL_DEF(T, 256, 2), FL_VAR(T, 256, 2, 8, 8, 8, 2),
+                                        FL_VAR(T, 256, 2, 8, 8, 4, 2)};
+    static const Variant<T> v2_512[] = {FL_DEF(T, 512, 2), FL_VAR(T, 512, 2, 8, 8, 8, 2),
+                                        FL_VAR(T, 512, 2, 8, 8, 4, 2), FL_VAR(T, 512, 2, 4, 4, 4, 1)};
+    static const Variant<T> v2_1024[] = {FL_DEF(T, 1024, 2), FL_VAR(T, 1024, 2, 8, 8, 4, 2),
+                                         FL_VAR(T, 1024, 2, 8, 8, 2, 2), FL_VAR(T, 1024, 2, 4, 4, 2, 1),
+                                         FL_VAR(T, 1024, 2, 8, 16, 4, 2)};
+    static const Variant<T> v2_2048[] = {FL_DEF(T, 2048, 2),          FL_VAR(T, 2048, 2, 8, 8, 4, 1),
+                                         FL_VAR(T, 2048, 2, 8, 8, 2, 1), FL_VAR(T, 2048, 2, 8, 8, 2, 4),
+                                         FL_VAR(T, 2048, 2, 4, 4, 2, 1), FL_VAR(T, 2048, 2, 4, 8, 2, 1),
+                                         FL_VAR(T, 2048, 2, 8, 16, 4, 1), FL_VAR(T, 2048, 2, 16, 8, 2, 2)};
+    static const Variant<T> v3_8[] = {FL_DEF(T, 8, 3)};
+    static const Variant<T> v3_16[] = {FL_DEF(T, 16, 3)};
+    static const Variant<T> v3_32[] = {FL_DEF(T, 32, 3)};
+    static const Variant<T> v3_64[] = {FL_DEF(T, 64, 3)};
+    static const Variant<T> v3_128[] = {FL_DEF(T, 128, 3)};
+    static const Variant<T> v3_256[] = {FL_DEF(T, 256, 3), FL_VAR(T, 256, 3, 8, 8, 16, 2)};
+    static const Variant<T> v3_512[] = {FL_DEF(T, 512, 3), FL_VAR(T, 512, 3, 8, 8, 16, 4),
+                                        FL_VAR(T, 512, 3, 8, 8, 8, 4), FL_VAR(T, 512, 3, 16, 8, 16, 8),
+                                        FL_VAR(T, 512, 3, 8, 16, 16, 4)};
+    static const Variant<T> v3_1024[] = {FL_DEF(T, 1024, 3)};
+#define FL_PICK(arr)                                  \
+    do {                                              \
+        *count = (int)(sizeof(arr) / sizeof(arr[0])); \
+        return arr;                                   \
+    } while (0)
+    if (d == 2) {
+        switch (P) {
+            case 8: FL_PICK(v2_8); case 16: FL_PICK(v2_16); case 32: FL_PICK(v2_32); case 64: FL_PICK(v2_64);
+            case 128: FL_PICK(v2_128); case 256: FL_PICK(v2_256); case 512: FL_PICK(v2_512);
+            case 1024: FL_PICK(v2_1024); case 2048: FL_PICK(v2_2048);
+        }
+    } else {
+        switch (P) {
+            case 8: FL_PICK(v3_8); case 16: FL_PICK(v3_16); case 32: FL_PICK(v3_32); case 64: FL_PICK(v3_64);
+            case 128: FL_PICK(v3_128); case 256: FL_PICK(v3_256); case 512: FL_PICK(v3_512);
+            case 1024: FL_PICK(v3_1024);
+        }
+    }
+    *count = 0;
+    return nullptr;
+}
+
+template <> const Variant<double> *variants<double>(int P, int d, int *count) {
+    using T = double;
+    static const Variant<T> v2_8[] = {FL_DEF(T, 8, 2)};
+    static const Variant<T> v2_16[] = {FL_DEF(T, 16, 2)};
+    static const Variant<T> v2_32[] = {FL_DEF(T, 32, 2)};
+    static const Variant<T> v2_64[] = {FL_DEF(T, 64, 2)};
+    static const Variant<T> v2_128[] = {FL_DEF(T, 128, 2)};
+    static const Variant<T> v2_256[] = {FL_DEF(T, 256, 2), FL_VAR(T, 256, 2, 8, 8, 4, 2)};
+    static const Variant<T> v2_512[] = {FL_DEF(T, 512, 2), FL_VAR(T, 512, 2, 8, 8, 4, 2),
+                                        FL_VAR(T, 512, 2, 8, 8, 2, 2)};
+    static const Variant<T> v2_1024[] = {FL_DEF(T, 1024, 2), FL_VAR(T, 1024, 2, 8, 8, 2, 2),
+                                         FL_VAR(T, 1024, 2, 4, 4, 2, 1)};
+    static const Variant<T> v2_2048[] = {FL_DEF(T, 2048, 2), FL_VAR(T, 2048, 2, 8, 8, 2, 1),
+                                         FL_VAR(T, 2048, 2, 8, 8, 2, 2), FL_VAR(T, 2048, 2, 4, 4, 2, 1),
+                                         FL_VAR(T, 2048, 2, 8, 16, 2, 1)};
+    static const Variant<T> v3_8[] = {FL_DEF(T, 8, 3)};
+    static const Variant<T> v3_16[] = {FL_DEF(T, 16, 3)};
+    static const Variant<T> v3_32[] = {FL_DEF(T, 32, 3)};
+    static const Variant<T> v3_64[] = {FL_DEF(T, 64, 3)};
+    static const Variant<T> v3_128[] = {FL_DEF(T, 128, 3)};
+    static const Variant<T> v3_256[] = {FL_DEF(T, 256, 3)};
+    static const Variant<T> v3_512[] = {FL_DEF(T, 512, 3), FL_VAR(T, 512, 3, 8, 8, 8, 2),
+                                        FL_VAR(T, 512, 3, 8, 8, 4, 2)};
+    static const Variant<T> v3_1024[] = {FL_DEF(T, 1024, 3)};
+    if (d == 2) {
+        switch (P) {
+            case 8: FL_PICK(v2_8); case 16: FL_PICK(v2_16); case 32: FL_PICK(v2_32); case 64: FL_PICK(v2_64);
+            case 128: FL_PICK(v2_128); case 256: FL_PICK(v2_256); case 512: FL_PICK(v2_512);
+            case 1024: FL_PICK(v2_1024); case 2048: FL_PICK(v2_2048);
+        }
+    } else {
+        switch (P) {
+            case 8: FL_PICK(v3_8); case 16: FL_PICK(v3_16); case 32: FL_PICK(v3_32); case 64: FL_PICK(v3_64);
+            case 128: FL_PICK(v3_128); case 256: FL_PICK(v3_256); case 512: FL_PICK(v3_512);
+            case 1024: FL_PICK(v3_1024);
+        }
+    }
+#undef FL_PICK
+    *count = 0;
+    return nullptr;
+}
+
+template <typename T> static int &chosen(fl_op op);
+template <> int &chosen<float>(fl_op op) { return op->var32; }
+template <> int &chosen<double>(fl_op op) { return op->var64; }
 
 template <typename T>
 fl_status matvec_ex(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
                     hipEvent_t *ev) {
-    switch (op->P) {
-        case 8: matvec_p<T, 8>(op, u, y, ep, done, s, ev); break;
-        case 16: matvec_p<T, 16>(op, u, y, ep, done, s, ev); break;
-        case 32: matvec_p<T, 32>(op, u, y, ep, done, s, ev); break;
-        case 64: matvec_p<T, 64>(op, u, y, ep, done, s, ev); break;
-        case 128: matvec_p<T, 128>(op, u, y, ep, done, s, ev); break;
-        case 256: matvec_p<T, 256>(op, u, y, ep, done, s, ev); break;
-        case 512: matvec_p<T, 512>(op, u, y, ep, done, s, ev); break;
-        case 1024: matvec_p<T, 1024>(op, u, y, ep, done, s, ev); break;
-        case 2048: matvec_p<T, 2048>(op, u, y, ep, done, s, ev); break;
-        default: set_error("FFT length %d not built", op->P); return FL_E_UNSUPPORTED;
+    int count = 0;
+    const Variant<T> *vs = variants<T>(op->P, op->d, &count);
+    const int k = chosen<T>(op);
+    if (!vs || k < 0 || k >= count) {
+        set_error("no kernel variant for FFT length %d, d=%d", op->P, op->d);
+        return FL_E_UNSUPPORTED;
     }
+    vs[k].fn(op, u, y, ep, done, s, ev);
     FL_HIP_TRY(hipGetLastError());
     return FL_OK;
 }
@@ -339,6 +508,69 @@ template fl_status matvec_ex<double>(fl_op, const double *, double *, const Epi<
                                      hipStream_t, hipEvent_t *);
 
 int kernel_p_supported(int P) { return P >= 8 && P <= 2048 && (P & (P - 1)) == 0; }
+
+int variant_count(fl_op op, int prec) {
+    int n = 0;
+    if (prec == FL_FP32) variants<float>(op->P, op->d, &n);
+    else variants<double>(op->P, op->d, &n);
+    return n;
+}
+
+VariantDesc variant_desc(fl_op op, int prec, int k) {
+    int n = 0;
+    if (prec == FL_FP32) {
+        const Variant<float> *v = variants<float>(op->P, op->d, &n);
+        return k >= 0 && k < n ? v[k].desc : VariantDesc{0, 0, 0, 0};
+    }
+    const Variant<double> *v = variants<double>(op->P, op->d, &n);
+    return k >= 0 && k < n ? v[k].desc : VariantDesc{0, 0, 0, 0};
+}
+
+// tiled lambda for the fused pass: 2D [t][ky][c], 3D [t][ky][kz][c]; zero past Q
+template <typename T>
+__global__ void k_tile_lambda(const double *__restrict__ lam64, T *__restrict__ lt, int d, int Q, int C, int ntiles) {
+    const long total = d == 2 ? (long)ntiles * Q * C : (long)ntiles * Q * Q * C;
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (long)gridDim.x * blockDim.x) {
+        const int c = (int)(idx % C);
+        long rest = idx / C;
+        double v = 0.0;
+        if (d == 2) {
+            const long ky = rest % Q, t = rest / Q;
+            const long kx = t * C + c;
+            if (kx < Q) v = lam64[ky * Q + kx];
+        } else {
+            const long kz = rest % Q;
+            rest /= Q;
+            const long ky = rest % Q, t = rest / Q;
+            const long kx = t * C + c;
+            if (kx < Q) v = lam64[(kz * Q + ky) * Q + kx];
+        }
+        lt[idx] = (T)v;
+    }
+}
+
+// select variant k for a precision: re-tile lambda to the variant's tile width
+fl_status select_variant(fl_op op, int prec, int k, hipStream_t s) {
+    const int n = variant_count(op, prec);
+    if (k < 0 || k >= n) {
+        set_error("variant %d out of range (%d available)", k, n);
+        return FL_E_INVAL;
+    }
+    const VariantDesc vd = variant_desc(op, prec, k);
+    const int Q = op->Q, nt = cdiv(Q, vd.c);
+    const long len = (op->d == 2 ? (long)Q : (long)Q * Q) * nt * vd.c;
+    const int g = cdiv(len, 256) > 65536 ? 65536 : cdiv(len, 256);
+    if (prec == FL_FP32)
+        hipLaunchKernelGGL(k_tile_lambda<float>, dim3(g), dim3(256), 0, s, op->lam64, op->lam32t, op->d, Q, vd.c, nt);
+    else
+        hipLaunchKernelGGL(k_tile_lambda<double>, dim3(g), dim3(256), 0, s, op->lam64, op->lam64t, op->d, Q, vd.c,
+                           nt);
+    FL_HIP_TRY(hipGetLastError());
+    if (prec == FL_FP32) op->var32 = k;
+    else op->var64 = k;
+    return FL_OK;
+}
 
 // ---------------------------------------------------------------------------
 // eigenvalues of the circulant embedding (FP64)
@@ -366,75 +598,89 @@ __global__ void k_embed(const double *__restrict__ a, double *__restrict__ cemb,
     }
 }
 
-__global__ void k_extract(const double2 *__restrict__ spec, double *__restrict__ lam64, float *__restrict__ lam32,
-                          int d, int P, int Q, long Qp, double inv) {
+// natural-order lambda (x fastest, Q^d) from the tiled spectrum of width C
+__global__ void k_extract(const double2 *__restrict__ spec, double *__restrict__ lam64, int d, int P, int Q,
+                          int C, int ntiles, double inv) {
     const long total = d == 2 ? (long)Q * Q : (long)Q * Q * Q;
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (long)gridDim.x * blockDim.x) {
-        const long kx = idx % Q;
+        const int kx = (int)(idx % Q);
         const long rest = idx / Q;
         long src;
-        if (d == 2) src = rest * Qp + kx;
+        if (d == 2) src = ((long)(kx / C) * P + rest) * C + kx % C;
         else {
             const long ky = rest % Q, kz = rest / Q;
-            src = (kz * P + ky) * Qp + kx;
+            src = (((kz * ntiles + kx / C) * P) + ky) * C + kx % C;
         }
-        const double l = spec[src].x * inv;
-        lam64[idx] = l;
-        lam32[idx] = (float)l;
+        lam64[idx] = spec[src].x * inv;
     }
 }
 
-template <int P>
-static void symbol_fft(double *cemb, double2 *T, int d, const double2 *tw, hipStream_t s) {
-    const int Q = P / 2 + 1;
-    const long Qp = ((Q + 15) / 16) * 16;
-    if (d == 2) {
-        launch_xfwd<double, P>(cemb, T, P, P, P, Qp, tw, nullptr, s);
-        launch_strided<double, P, 0>(T, T, Q, 1, P, P, Qp, 0, 0, tw, nullptr, 0, 0, nullptr, s);
+template <int P, int D>
+static void symbol_fft(double *cemb, double2 *T, const double2 *tw, hipStream_t s) {
+    using S = Shape<double, P, D>;
+    constexpr int E = S::E, C = S::C, LPB = S::LPB;
+    const int Q = P / 2 + 1, nt = cdiv(Q, C);
+    if constexpr (D == 2) {
+        launch_xfwd<double, P, E, C, LPB>(cemb, T, P, P, P, P, nt, tw, nullptr, s, nullptr);
+        Strides sy{0, P * C, 0, P * C, C, 0, 0};
+        launch_strided<double, P, E, C, 0>(T, T, Q, 1, P, P, sy, tw, nullptr, nullptr, s, nullptr);
     } else {
-        launch_xfwd<double, P>(cemb, T, P * P, P, P, Qp, tw, nullptr, s);
-        launch_strided<double, P, 0>(T, T, Q, P, P, P, Qp, (long)P * Qp, (long)P * Qp, tw, nullptr, 0, 0, nullptr, s);
-        launch_strided<double, P, 0>(T, T, Q, P, P, P, (long)P * Qp, Qp, Qp, tw, nullptr, 0, 0, nullptr, s);
+        launch_xfwd<double, P, E, C, LPB>(cemb, T, P * P, P, P, P, nt, tw, nullptr, s, nullptr);
+        Strides sy{nt * P * C, P * C, nt * P * C, P * C, C, 0, 0};
+        launch_strided<double, P, E, C, 0>(T, T, Q, P, P, P, sy, tw, nullptr, nullptr, s, nullptr);
+        Strides sz{C, P * C, C, P * C, nt * P * C, 0, 0};
+        launch_strided<double, P, E, C, 0>(T, T, Q, P, P, P, sz, tw, nullptr, nullptr, s, nullptr);
     }
 }
+
+template <int P, int D> constexpr int sym_c() { return Shape<double, P, D>::C; }
 
 fl_status build_symbol(fl_op op, hipStream_t s) {
     const int d = op->d, P = op->P, Q = op->Q;
-    const long Qp = op->Qp;
+    int C = 0;
+#define FL_SYC(PP)                                           \
+    case PP: C = d == 2 ? sym_c<PP, 2>() : sym_c<PP, 3>(); break;
+    switch (P) {
+        FL_SYC(8) FL_SYC(16) FL_SYC(32) FL_SYC(64) FL_SYC(128) FL_SYC(256) FL_SYC(512) FL_SYC(1024)
+        case 2048: C = sym_c<2048, 2>(); break;
+        default: set_error("FFT length %d not built", P); return FL_E_UNSUPPORTED;
+    }
+#undef FL_SYC
+    const int nt = cdiv(Q, C);
     const long total = d == 2 ? (long)P * P : (long)P * P * P;
     const long rows = total / P;
     double *cemb = nullptr;
     double2 *T = nullptr;
     FL_HIP_TRY(hipMalloc((void **)&cemb, sizeof(double) * total));
-    hipError_t e = hipMalloc((void **)&T, sizeof(double2) * rows * Qp);
+    hipError_t e = hipMalloc((void **)&T, sizeof(double2) * rows * nt * C);
     if (e != hipSuccess) {
         (void)hipFree(cemb);
         set_error("workspace for the symbol: %s", hipGetErrorString(e));
         return FL_E_NOMEM;
     }
-    hipLaunchKernelGGL(k_embed, dim3(cdiv(total, 256) > 65536 ? 65536 : cdiv(total, 256)), dim3(256), 0, s,
-                       op->a, cemb, d, op->N, P, -op->c);
+    auto grid = [](long n) { return cdiv(n, 256) > 65536 ? 65536 : cdiv(n, 256); };
+    hipLaunchKernelGGL(k_embed, dim3(grid(total)), dim3(256), 0, s, op->a, cemb, d, op->N, P, -op->c);
+#define FL_SY(PP)                                                          \
+    case PP:                                                               \
+        if (d == 2) symbol_fft<PP, 2>(cemb, T, op->tw64, s);               \
+        else symbol_fft<PP, 3>(cemb, T, op->tw64, s);                      \
+        break;
     switch (P) {
-        case 8: symbol_fft<8>(cemb, T, d, op->tw64, s); break;
-        case 16: symbol_fft<16>(cemb, T, d, op->tw64, s); break;
-        case 32: symbol_fft<32>(cemb, T, d, op->tw64, s); break;
-        case 64: symbol_fft<64>(cemb, T, d, op->tw64, s); break;
-        case 128: symbol_fft<128>(cemb, T, d, op->tw64, s); break;
-        case 256: symbol_fft<256>(cemb, T, d, op->tw64, s); break;
-        case 512: symbol_fft<512>(cemb, T, d, op->tw64, s); break;
-        case 1024: symbol_fft<1024>(cemb, T, d, op->tw64, s); break;
-        case 2048: symbol_fft<2048>(cemb, T, d, op->tw64, s); break;
-        default: break;
+        FL_SY(8) FL_SY(16) FL_SY(32) FL_SY(64) FL_SY(128) FL_SY(256) FL_SY(512) FL_SY(1024)
+        case 2048: symbol_fft<2048, 2>(cemb, T, op->tw64, s); break;
     }
+#undef FL_SY
     const long ql = d == 2 ? (long)Q * Q : (long)Q * Q * Q;
-    const double inv = 1.0 / (double)total;
-    hipLaunchKernelGGL(k_extract, dim3(cdiv(ql, 256) > 65536 ? 65536 : cdiv(ql, 256)), dim3(256), 0, s, T,
-                       op->lam64, op->lam32, d, P, Q, Qp, inv);
+    hipLaunchKernelGGL(k_extract, dim3(grid(ql)), dim3(256), 0, s, T, op->lam64, d, P, Q, C, nt,
+                       1.0 / (double)total);
+    fl_status st = select_variant(op, FL_FP32, op->var32, s);
+    if (st == FL_OK) st = select_variant(op, FL_FP64, op->var64, s);
     hipError_t le = hipGetLastError();
     hipError_t se = hipStreamSynchronize(s);
     (void)hipFree(cemb);
     (void)hipFree(T);
+    FL_TRY(st);
     FL_HIP_TRY(le);
     FL_HIP_TRY(se);
     return FL_OK;

@@ -118,101 +118,135 @@ template <typename T, int DIR> struct Dft<T, 2, DIR> {
 };
 
 // ---------------------------------------------------------------------------
-// FFT plans: radix sequence per power-of-two length P.  E = registers (points)
-// per thread, TL = P / E threads per line.  Every radix divides E.
+// FFT plans: length P (a power of two), E points per thread (TL = P / E
+// threads per line).  Radices greedily as large as E: R[0..L-1], product P.
 // ---------------------------------------------------------------------------
-template <int... Rs> struct Radices {};
-
-template <int P> struct Plan;
-template <> struct Plan<8>    { static constexpr int E = 8;  using Fwd = Radices<8>;          using Inv = Radices<8>; };
-template <> struct Plan<16>   { static constexpr int E = 16; using Fwd = Radices<16>;         using Inv = Radices<16>; };
-template <> struct Plan<32>   { static constexpr int E = 8;  using Fwd = Radices<8, 4>;       using Inv = Radices<4, 8>; };
-template <> struct Plan<64>   { static constexpr int E = 8;  using Fwd = Radices<8, 8>;       using Inv = Radices<8, 8>; };
-template <> struct Plan<128>  { static constexpr int E = 16; using Fwd = Radices<16, 8>;      using Inv = Radices<8, 16>; };
-template <> struct Plan<256>  { static constexpr int E = 16; using Fwd = Radices<16, 16>;     using Inv = Radices<16, 16>; };
-template <> struct Plan<512>  { static constexpr int E = 16; using Fwd = Radices<16, 8, 4>;   using Inv = Radices<4, 8, 16>; };
-template <> struct Plan<1024> { static constexpr int E = 16; using Fwd = Radices<16, 16, 4>;  using Inv = Radices<4, 16, 16>; };
-template <> struct Plan<2048> { static constexpr int E = 16; using Fwd = Radices<16, 16, 8>;  using Inv = Radices<8, 16, 16>; };
-
-template <int First, int... Rest> struct FirstOf { static constexpr int value = First; };
-template <typename L> struct Front;
-template <int... Rs> struct Front<Radices<Rs...>> { static constexpr int value = FirstOf<Rs...>::value; };
-template <typename L> struct Back;
-template <int R> struct Back<Radices<R>> { static constexpr int value = R; };
-template <int R, int R2, int... Rs> struct Back<Radices<R, R2, Rs...>> { static constexpr int value = Back<Radices<R2, Rs...>>::value; };
-
-// ---------------------------------------------------------------------------
-// Stockham stages over one line of P points held E per thread.
-// Before a radix-R stage, thread tl holds v[i*R + r] = x[b + r*(P/R)],
-// b = tl + i*TL, i < E/R.  After the butterfly the value belongs at position
-// (b/Ns)*Ns*R + b%Ns + r*Ns.  Exchanges go through LDS with the index
-// functor Lidx(pos).
-// ---------------------------------------------------------------------------
-template <typename T, int P, int E, int DIR, int Ns, int R>
-__device__ __forceinline__ void butterflies(C2<T> *v, int tl, const C2<T> *__restrict__ tw) {
-    constexpr int TL = P / E;
-#pragma unroll
-    for (int i = 0; i < E / R; ++i) {
-        const int b = tl + i * TL;
-        if constexpr (Ns > 1) {
-            const int k = b % Ns;
-#pragma unroll
-            for (int r = 1; r < R; ++r) {
-                C2<T> w = tw[k * r * (P / (Ns * R))];
-                if (DIR > 0) w.y = -w.y;
-                v[i * R + r] = cmul<T>(v[i * R + r], w);
-            }
-        }
-        Dft<T, R, DIR>::run(v + i * R);
+template <int P, int E_> struct Plan {
+    static_assert((P & (P - 1)) == 0 && (E_ & (E_ - 1)) == 0 && E_ <= P && E_ >= 2, "bad plan");
+    static constexpr int E = E_;
+    static constexpr int count() {
+        int l = 0;
+        for (int rem = P; rem > 1; rem /= (rem < E ? rem : E)) ++l;
+        return l;
     }
-}
-
-template <typename T, int P, int E, int Ns, int R, typename Lidx>
-__device__ __forceinline__ void stage_store(const C2<T> *v, C2<T> *lds, int tl, Lidx lidx) {
-    constexpr int TL = P / E;
-#pragma unroll
-    for (int i = 0; i < E / R; ++i) {
-        const int b = tl + i * TL;
-        const int base = (b / Ns) * Ns * R + (b % Ns);
-#pragma unroll
-        for (int r = 0; r < R; ++r) lds[lidx(base + r * Ns)] = v[i * R + r];
+    static constexpr int L = count();
+    static constexpr int radix(int s) {
+        int rem = P;
+        for (int i = 0; i < s; ++i) rem /= (rem < E ? rem : E);
+        return rem < E ? rem : E;
     }
-}
+    static constexpr int R[6] = {radix(0), L > 1 ? radix(1) : 1, L > 2 ? radix(2) : 1,
+                                 L > 3 ? radix(3) : 1, L > 4 ? radix(4) : 1, L > 5 ? radix(5) : 1};
+    static_assert(L <= 6, "plan too long");
+};
 
-template <typename T, int P, int E, int R, typename Lidx>
-__device__ __forceinline__ void stage_load(C2<T> *v, const C2<T> *lds, int tl, Lidx lidx) {
-    constexpr int TL = P / E;
-#pragma unroll
-    for (int i = 0; i < E / R; ++i) {
-        const int b = tl + i * TL;
-#pragma unroll
-        for (int r = 0; r < R; ++r) v[i * R + r] = lds[lidx(b + r * (P / R))];
-    }
+// product of the radices before stage s
+template <typename PL> constexpr int stage_ns(int s) {
+    int ns = 1;
+    for (int i = 0; i < s; ++i) ns *= PL::R[i];
+    return ns;
 }
+// offset of stage s's twiddles in a thread's twiddle registers (stage 0 has none)
+template <typename PL> constexpr int stage_tw(int s) {
+    int o = 0;
+    for (int i = 1; i < s; ++i) o += PL::E - PL::E / PL::R[i];
+    return o;
+}
+template <typename PL> constexpr int num_tw() { return stage_tw<PL>(PL::L) > 0 ? stage_tw<PL>(PL::L) : 1; }
 
-// position of register slot j (= i*R + r) for a layout "ready for radix R"
-template <int P, int E, int R>
-__device__ __forceinline__ int slot_pos(int tl, int j) {
-    constexpr int TL = P / E;
+// Stage s of the Stockham (decimation-in-time) forward transform, thread tl,
+// register slot j = i*R + r for butterfly b = tl + i*TL:
+//   reads x[b + r*(P/R)], multiplies by w^{(b mod Ns) r}, w = exp(-2 pi i/(Ns R)),
+//   takes the R-point DFT, writes position (b/Ns)*Ns*R + (b mod Ns) + r*Ns.
+template <int P, typename PL, int S> __device__ __forceinline__ int in_pos(int tl, int j) {
+    constexpr int R = PL::R[S], TL = P / PL::E;
     return tl + (j / R) * TL + (j % R) * (P / R);
 }
+template <int P, typename PL, int S> __device__ __forceinline__ int out_pos(int tl, int j) {
+    constexpr int R = PL::R[S], TL = P / PL::E, Ns = stage_ns<PL>(S);
+    const int b = tl + (j / R) * TL;
+    return (b / Ns) * Ns * R + (b % Ns) + (j % R) * Ns;
+}
 
-template <typename T, int P, int E, int DIR, int Ns, typename L> struct Stages;
-template <typename T, int P, int E, int DIR, int Ns, int R, int... Rest>
-struct Stages<T, P, E, DIR, Ns, Radices<R, Rest...>> {
-    template <typename Lidx>
-    __device__ __forceinline__ static void run(C2<T> *v, C2<T> *lds, int tl, const C2<T> *tw, Lidx lidx) {
-        butterflies<T, P, E, DIR, Ns, R>(v, tl, tw);
-        if constexpr (sizeof...(Rest) > 0) {
-            constexpr int R2 = FirstOf<Rest...>::value;
-            stage_store<T, P, E, Ns, R>(v, lds, tl, lidx);
-            __syncthreads();
-            stage_load<T, P, E, R2>(v, lds, tl, lidx);
-            __syncthreads();
-            Stages<T, P, E, DIR, Ns * R, Radices<Rest...>>::run(v, lds, tl, tw, lidx);
+// every twiddle a thread uses, loaded once from the table exp(-2 pi i m / P)
+template <typename T, int P, typename PL, int S = 1>
+__device__ __forceinline__ void load_twiddles(C2<T> *tws, const C2<T> *__restrict__ table, int tl) {
+    if constexpr (S < PL::L) {
+        constexpr int R = PL::R[S], E = PL::E, TL = P / E, Ns = stage_ns<PL>(S), TW = stage_tw<PL>(S);
+#pragma unroll
+        for (int i = 0; i < E / R; ++i) {
+            const int k = (tl + i * TL) % Ns;
+#pragma unroll
+            for (int r = 1; r < R; ++r) tws[TW + i * (R - 1) + r - 1] = table[k * r * (P / (Ns * R))];
+        }
+        load_twiddles<T, P, PL, S + 1>(tws, table, tl);
+    }
+}
+
+// forward butterflies of stage S (twiddle, then DFT with exp(-2 pi i ...))
+template <typename T, typename PL, int S>
+__device__ __forceinline__ void fwd_bfly(C2<T> *v, const C2<T> *tws) {
+    constexpr int R = PL::R[S], E = PL::E, TW = stage_tw<PL>(S);
+#pragma unroll
+    for (int i = 0; i < E / R; ++i) {
+        if constexpr (S > 0) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[i * R + r] = cmul<T>(v[i * R + r], tws[TW + i * (R - 1) + r - 1]);
+        }
+        Dft<T, R, -1>::run(v + i * R);
+    }
+}
+// adjoint of stage S (DFT with exp(+2 pi i ...), then conjugate twiddle): applying
+// the adjoints of stages L-1..0 gives the unnormalised inverse DFT
+template <typename T, typename PL, int S>
+__device__ __forceinline__ void adj_bfly(C2<T> *v, const C2<T> *tws) {
+    constexpr int R = PL::R[S], E = PL::E, TW = stage_tw<PL>(S);
+#pragma unroll
+    for (int i = 0; i < E / R; ++i) {
+        Dft<T, R, +1>::run(v + i * R);
+        if constexpr (S > 0) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[i * R + r] = cmul<T>(v[i * R + r], cconj<T>(tws[TW + i * (R - 1) + r - 1]));
         }
     }
-};
+}
+
+// forward transform: v enters at in_pos<0>, leaves at out_pos<L-1> = natural
+// positions b + r*(P/R_last)
+template <typename T, int P, typename PL, int S, typename Lidx>
+__device__ __forceinline__ void fwd_stages(C2<T> *v, C2<T> *lds, int tl, const C2<T> *tws, Lidx lidx) {
+    fwd_bfly<T, PL, S>(v, tws);
+    if constexpr (S + 1 < PL::L) {
+        constexpr int E = PL::E;
+#pragma unroll
+        for (int j = 0; j < E; ++j) lds[lidx(out_pos<P, PL, S>(tl, j))] = v[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < E; ++j) v[j] = lds[lidx(in_pos<P, PL, S + 1>(tl, j))];
+        __syncthreads();
+        fwd_stages<T, P, PL, S + 1>(v, lds, tl, tws, lidx);
+    }
+}
+// inverse transform (adjoint stages L-1..0): v enters at out_pos<L-1>, leaves at in_pos<0>
+template <typename T, int P, typename PL, int S, typename Lidx>
+__device__ __forceinline__ void adj_stages(C2<T> *v, C2<T> *lds, int tl, const C2<T> *tws, Lidx lidx) {
+    adj_bfly<T, PL, S>(v, tws);
+    if constexpr (S > 0) {
+        constexpr int E = PL::E;
+#pragma unroll
+        for (int j = 0; j < E; ++j) lds[lidx(in_pos<P, PL, S>(tl, j))] = v[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < E; ++j) v[j] = lds[lidx(out_pos<P, PL, S - 1>(tl, j))];
+        __syncthreads();
+        adj_stages<T, P, PL, S - 1>(v, lds, tl, tws, lidx);
+    }
+}
+
+// LDS padding: one slot per 16 positions breaks the stride-R bank pattern of
+// the early stages' stores
+__device__ __forceinline__ int padpos(int pos) { return pos + (pos >> 4); }
+template <int P> constexpr int padded_len() { return P + P / 16; }
 
 }  // namespace fl
 
@@ -225,8 +259,10 @@ struct fl_op_s {
     double alpha = 0, h = 0, c = 0, a0 = 0;
     int device = 0;
     double *a = nullptr;          // (N+1)^d coefficients, a[0] = a_0
-    double *lam64 = nullptr;      // Q^d eigenvalues / P^d
-    float *lam32 = nullptr;
+    double *lam64 = nullptr;      // Q^d eigenvalues / P^d, natural order
+    double *lam64t = nullptr;     // the same, tiled for the FP64 fused pass
+    float *lam32t = nullptr;      // FP32 copy, tiled for the FP32 fused pass
+    int var32 = 0, var64 = 0;     // selected kernel variants (0 = default)
     double2 *tw64 = nullptr;      // exp(-2 pi i m / P), m < P
     float2 *tw32 = nullptr;
     void *T1 = nullptr;           // spectra workspaces (sized for FP64)
@@ -253,9 +289,19 @@ template <typename T> struct Epi {
 template <typename T>
 fl_status matvec(fl_op op, const T *u, T *y, hipStream_t s);
 // `done`: optional device flag; when it holds a nonzero value every pass returns at once
+// ev (optional): 2 events per pass, recorded at each kernel's start and stop
 template <typename T>
 fl_status matvec_ex(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
                     hipEvent_t *ev = nullptr);
 fl_status build_symbol(fl_op op, hipStream_t s);
 int kernel_p_supported(int P);
+// kernel variants of a matvec: points per thread in the row / strided passes,
+// spectrum tile width, line pairs per row block
+struct VariantDesc {
+    int ex, ey, c, lpb;
+};
+int variant_count(fl_op op, int prec);
+VariantDesc variant_desc(fl_op op, int prec, int k);
+fl_status select_variant(fl_op op, int prec, int k, hipStream_t s);
+constexpr int kMaxTile = 16;  // largest tile width of any variant
 }  // namespace fl

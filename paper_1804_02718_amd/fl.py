@@ -18,7 +18,8 @@ FL_OK, FL_E_INVAL, FL_E_NOMEM, FL_E_DEVICE, FL_E_NOCONV, FL_E_BREAKDOWN, FL_E_UN
 FL_FP64, FL_FP32 = 0, 1
 SOLVERS = {"auto": 0, "cg64": 1, "refine": 2, "fpcg": 3}
 
-EXPORTED = ["fl_coeffs", "fl_apply", "fl_apply_profiled", "fl_poisson_solve", "fl_poisson_solve_ex", "fl_allen_cahn_step",
+EXPORTED = ["fl_coeffs", "fl_apply", "fl_apply_profiled", "fl_variant_count", "fl_variant_info",
+            "fl_select_variant", "fl_autotune", "fl_poisson_solve", "fl_poisson_solve_ex", "fl_allen_cahn_step",
             "fl_allen_cahn_step_ex", "fl_op_destroy", "fl_op_describe", "fl_get_coeffs", "fl_get_symbol",
             "fl_status_string", "fl_last_error"]
 
@@ -73,6 +74,10 @@ def load(path: str = LIB_PATH):
     lib.fl_apply.argtypes = [vp, vp, vp, ip, vp]
     lib.fl_apply_profiled.argtypes = [vp, vp, vp, ip, ip, vp, ctypes.POINTER(ctypes.c_float),
                                       ctypes.POINTER(ctypes.c_int)]
+    lib.fl_variant_count.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int)]
+    lib.fl_variant_info.argtypes = [vp, ip, ip, ctypes.POINTER(ctypes.c_int)]
+    lib.fl_select_variant.argtypes = [vp, ip, ip]
+    lib.fl_autotune.argtypes = [vp, ip, ip, vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float)]
     lib.fl_poisson_solve.argtypes = [vp, vp, dp, vp, ctypes.POINTER(fl_info), vp]
     lib.fl_poisson_solve_ex.argtypes = [vp, vp, dp, vp, ctypes.POINTER(fl_solve_opts), ctypes.POINTER(fl_info), vp]
     lib.fl_allen_cahn_step.argtypes = [vp, vp, dp, dp, ctypes.POINTER(fl_info), vp]
@@ -152,6 +157,35 @@ def fl_apply_profiled(op, u, y, reps, stream=None):
     _check(load().fl_apply_profiled(op, _ptr(u), _ptr(y), prec, int(reps), _stream(stream), ms,
                                     ctypes.byref(npass)))
     return [ms[i] for i in range(npass.value)]
+
+
+def _prec(prec):
+    return {"fp64": FL_FP64, "fp32": FL_FP32}.get(prec, prec)
+
+
+def fl_variant_count(op, prec) -> int:
+    n = ctypes.c_int()
+    _check(load().fl_variant_count(op, _prec(prec), ctypes.byref(n)))
+    return n.value
+
+
+def fl_variant_info(op, prec, k) -> dict:
+    d = (ctypes.c_int * 4)()
+    _check(load().fl_variant_info(op, _prec(prec), int(k), d))
+    return {"ex": d[0], "ey": d[1], "tile": d[2], "row_pairs": d[3]}
+
+
+def fl_select_variant(op, prec, k):
+    _check(load().fl_select_variant(op, _prec(prec), int(k)))
+
+
+def fl_autotune(op, prec, reps=20, stream=None):
+    """Time every kernel variant, select the fastest; returns (best, [ms per variant])."""
+    n = fl_variant_count(op, prec)
+    ms = (ctypes.c_float * max(n, 1))()
+    best = ctypes.c_int()
+    _check(load().fl_autotune(op, _prec(prec), int(reps), _stream(stream), ctypes.byref(best), ms))
+    return best.value, [ms[i] for i in range(n)]
 
 
 def fl_poisson_solve(op, f, tol, u, stream=None):
@@ -242,6 +276,15 @@ class Operator:
 
     def coeffs(self):
         return fl_get_coeffs(self._op)
+
+    def variants(self, prec):
+        return [fl_variant_info(self._op, prec, k) for k in range(fl_variant_count(self._op, prec))]
+
+    def select_variant(self, prec, k):
+        fl_select_variant(self._op, prec, k)
+
+    def autotune(self, prec, reps=20, stream=None):
+        return fl_autotune(self._op, prec, reps, stream)
 
     def symbol(self):
         return fl_get_symbol(self._op)

@@ -203,6 +203,35 @@ def test_apply_3d_p512_sampled(dev, N, alpha, nrows):
     op.close()
 
 
+@pytest.mark.parametrize("d,N,alpha", [(2, 65, 1.1), (2, 129, 0.9), (2, 257, 1.6), (2, 513, 0.6), (2, 1024, 1.9),
+                                       (3, 129, 1.3), (3, 200, 0.8)])
+def test_every_kernel_variant_matches_oracle(dev, d, N, alpha):
+    # every compiled variant (points per thread, tile width, rows per block) computes
+    # the same operator: FP64 and FP32 against the oracle on sampled rows
+    fl = _fl()
+    h = 2.0 / N
+    M = (N - 1) ** d
+    op = fl.Operator(d, alpha, h, N)
+    u = inputs.uniform(M, seed=4)
+    u32 = u.astype(np.float32)
+    rows = _sample_rows(M, 24, seed=9)
+    a = oracle.coeffs(d, alpha, h, N)
+    ref = oracle.apply_rows(d, N, alpha, a, u, rows)
+    ref32 = oracle.apply_rows(d, N, alpha, a, u32.astype(np.float64), rows)
+    absref = oracle.apply_rows(d, N, alpha, a, u, rows, absmode=True)
+    for prec, uu, rr, gate in (("fp64", _t(u), ref, 1e-14), ("fp32", _t(u32, torch.float32), ref32, 1e-6)):
+        for k, desc in enumerate(op.variants(prec)):
+            op.select_variant(prec, k)
+            y = op.apply(uu).cpu().numpy()[rows].astype(np.float64)
+            e_rel, e_sc = _errs(y, rr, absref)
+            assert e_sc < gate, (prec, k, desc, e_rel, e_sc)
+    best, ms = op.autotune("fp32", reps=3)
+    assert 0 <= best < len(ms) and ms[best] == min(ms)
+    y = op.apply(_t(u32, torch.float32)).cpu().numpy()[rows].astype(np.float64)
+    assert _errs(y, ref32, absref)[1] < 1e-6
+    op.close()
+
+
 def test_apply_deterministic_and_stream_ordered(dev):
     fl = _fl()
     N = 256
