@@ -134,6 +134,41 @@ def c3_extra(torch, fl, inputs, autotune, N=256, alpha=1.2):
     return out
 
 
+def c4_extra(torch, fl, inputs):
+    """64 2D Poisson problems, N from {64,128,256,512}, alpha ~ U(0.2,1.95), tol 1e-8:
+    one batched solve against the same problems solved one after another."""
+    probs = inputs.batch_problems(64, seed=4)
+    fs = [torch.as_tensor(p["f"], device="cuda:0") for p in probs]
+    t0 = time.perf_counter()
+    b = fl.Batch(2, [p["N"] for p in probs], [p["alpha"] for p in probs], [p["h"] for p in probs])
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    b.solve(fs, tol=1e-8)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    us, infos = b.solve(fs, tol=1e-8)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    b.close()
+    ops = [fl.Operator(2, p["alpha"], p["h"], p["N"]) for p in probs]
+    for op, f in zip(ops, fs):
+        op.poisson_solve(f, tol=1e-8, solver="refine")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = [op.poisson_solve(f, tol=1e-8, solver="refine")[1] for op, f in zip(ops, fs)]
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    for op in ops:
+        op.close()
+    dofs = sum((p["N"] - 1) ** 2 for p in probs)
+    return {"workload": "64 problems, N in {64,128,256,512}, alpha~U(0.2,1.95), 4 Gaussians, tol 1e-8",
+            "unknowns": dofs, "batched_seconds": round(tb, 4), "sequential_seconds": round(ts, 4),
+            "speedup": round(ts / tb, 2), "setup_seconds": round(setup, 3),
+            "max_relres": max(i["relres"] for i in infos),
+            "max_inner_iters": max(i["iters"] for i in infos),
+            "sequential_max_relres": max(i["relres"] for i in seq)}
+
+
 def poisson_extra(torch, fl, inputs, N=1024, alpha=1.5):
     """Time-to-1e-8 relative residual for the 2D N=1024 Poisson problem, f = 8 Gaussians."""
     h = 2.0 / N
@@ -167,6 +202,8 @@ def main():
                     help="time the built-in default kernel variant instead of the autotuned one")
     ap.add_argument("--c3", action="store_true",
                     help="also time the 3D N=256 matvec (FP32 and FP64) of the Allen--Cahn workload")
+    ap.add_argument("--c4", action="store_true",
+                    help="also time the batch of 64 mixed-(N, alpha) Poisson solves, batched and one by one")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before timing, copy a buffer of this many MiB three times (a plain copy kernel "
                          "whose known traffic calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -244,6 +281,9 @@ def main():
     if args.c3:
         print("bench: 3D N=256 matvec", file=sys.stderr, flush=True)
         extra["c3_matvec"] = c3_extra(torch, fl, inputs, not args.no_autotune)
+    if args.c4:
+        print("bench: batched solves", file=sys.stderr, flush=True)
+        extra["c4_batch"] = c4_extra(torch, fl, inputs)
 
     cpu = None
     if not args.no_cpu_baseline:

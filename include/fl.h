@@ -177,6 +177,36 @@ fl_status fl_variant_info(fl_op op, int prec, int k, int *desc4);
 fl_status fl_select_variant(fl_op op, int prec, int k);
 fl_status fl_autotune(fl_op op, int prec, int reps, void *stream, int *best, float *ms_per_variant);
 
+/*
+ * Batched fractional Poisson solves: `count` problems of the same dimension d
+ * with their own N[i], alpha[i], h[i] (host arrays).
+ *   fl_batch_create         -- builds every operator (as fl_coeffs) and groups
+ *                              the problems into size classes of equal N; each
+ *                              class runs all of its problems in every kernel
+ *                              launch, and its inner CG iterations are replayed
+ *                              from a captured hipGraph.  Synchronises.
+ *   fl_batch_poisson_solve  -- solves A_i u_i = f_i to ||f_i - A_i u_i||_2 <=
+ *                              tol ||f_i||_2 (FP64 residual refinement around
+ *                              FP32 CG) for every i; f, u are host arrays of
+ *                              `count` device pointers (double, M_i entries;
+ *                              u overwritten, initial guess 0).  max_iter caps
+ *                              each problem's inner iterations (<= 0: none).
+ *                              infos (host, count entries, may be NULL) gets
+ *                              each problem's result.  Work runs on internal
+ *                              streams ordered after `stream`; `stream` waits
+ *                              for the solutions.  Returns FL_E_NOCONV if any
+ *                              problem missed the tolerance.
+ *   fl_batch_info           -- number of size classes and the largest class.
+ *   fl_batch_destroy        -- frees everything; NULL accepted.
+ */
+typedef struct fl_batch_s *fl_batch;
+fl_status fl_batch_create(int d, int count, const int *N, const double *alpha, const double *h,
+                          fl_batch *out);
+fl_status fl_batch_poisson_solve(fl_batch b, const double *const *f, double *const *u, double tol,
+                                 int max_iter, fl_info *infos, void *stream);
+fl_status fl_batch_info(fl_batch b, int *nclasses, int *max_batch);
+fl_status fl_batch_destroy(fl_batch b);
+
 /* Free the operator and its device workspaces.  NULL is accepted. */
 fl_status fl_op_destroy(fl_op op);
 

@@ -41,6 +41,13 @@ template <typename T, int P, int D> struct Shape {
     static constexpr int LPB = LPB0 > lp_max ? lp_max : LPB0;
 };
 
+// per-problem offsets of a batched launch (blockIdx.z = problem): input and
+// output elements, lambda entries, and done-flag slots
+struct BatchStrides {
+    long in = 0, out = 0, lam = 0;
+    int done = 0;
+};
+
 // tiled layout: row r of slab k = r / nj, line j = r mod nj, column kx = t*C + c
 // at ((k*ntiles + t)*nj + j)*C + c = rowbase(r) + t*(nj*C) + c (element offsets
 // stay below 2^31 for every supported size)
@@ -56,8 +63,11 @@ __device__ __forceinline__ int tiled_rowbase(int r, int nj, int ntiles, int C) {
 template <typename T, int P, int E, int C, int LPB>
 __global__ __launch_bounds__(LPB * (P / E)) void k_xfwd(
     const T *__restrict__ u, C2<T> *__restrict__ out, int nrows, int n_in, long in_pitch, int nj, int ntiles,
-    const C2<T> *__restrict__ table, const double *__restrict__ done) {
-    if (done && *done != 0.0) return;
+    const C2<T> *__restrict__ table, const double *__restrict__ done, BatchStrides bz) {
+    const int z = blockIdx.z;  // problem of a batch
+    if (done && done[z * bz.done] != 0.0) return;
+    u += z * bz.in;
+    out += z * bz.out;
     using PN = Plan<P, E>;
     constexpr int TL = P / E, L = PN::L;
     constexpr int PL = padded_len<P>();
@@ -130,8 +140,13 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xfwd(
 template <typename T, int P, int E, int C, int LPB, bool EPI>
 __global__ __launch_bounds__(LPB * (P / E)) void k_xinv(
     const C2<T> *__restrict__ in, T *__restrict__ y, int nrows, int n_out, long out_pitch, int nj, int ntiles,
-    const C2<T> *__restrict__ table, Epi<T> ep, const double *__restrict__ done) {
-    if (done && *done != 0.0) return;
+    const C2<T> *__restrict__ table, Epi<T> ep, const double *__restrict__ done, BatchStrides bz) {
+    const int z = blockIdx.z;
+    if (done && done[z * bz.done] != 0.0) return;
+    in += z * bz.in;
+    y += z * bz.out;
+    if (ep.w1) ep.w1 += z * bz.out;
+    if (ep.w2) ep.w2 += z * bz.out;
     using PN = Plan<P, E>;
     constexpr int TL = P / E, L = PN::L;
     constexpr int PL = padded_len<P>();
@@ -226,8 +241,12 @@ struct Strides {  // element offsets (below 2^31 for every supported size)
 template <typename T, int P, int E, int C, int MODE>
 __global__ __launch_bounds__(C * (P / E)) void k_strided(
     const C2<T> *in, C2<T> *out, int ncols, int n_in, int n_out, Strides st, const C2<T> *__restrict__ table,
-    const T *__restrict__ lam, const double *__restrict__ done) {
-    if (done && *done != 0.0) return;
+    const T *__restrict__ lam, const double *__restrict__ done, BatchStrides bz) {
+    const int zb = blockIdx.z;
+    if (done && done[zb * bz.done] != 0.0) return;
+    in += zb * bz.in;
+    out += zb * bz.out;
+    if (lam) lam += zb * bz.lam;
     using PN = Plan<P, E>;
     constexpr int L = PN::L;
     constexpr int PL = padded_len<P>();
@@ -307,30 +326,32 @@ static void launch(K kernel, dim3 g, dim3 b, hipStream_t s, const hipEvent_t *ev
 
 template <typename T, int P, int E, int C, int LPB>
 static void launch_xfwd(const T *u, C2<T> *out, int nrows, int n_in, long in_pitch, int nj, int ntiles,
-                        const C2<T> *tw, const double *done, hipStream_t s, const hipEvent_t *ev) {
+                        const C2<T> *tw, const double *done, hipStream_t s, const hipEvent_t *ev, int nb = 1,
+                        BatchStrides bz = BatchStrides{}) {
     const int pairs = (nrows + 1) / 2;
-    launch(k_xfwd<T, P, E, C, LPB>, dim3(cdiv(pairs, LPB)), dim3(LPB * (P / E)), s, ev, u, out, nrows, n_in,
-           in_pitch, nj, ntiles, tw, done);
+    launch(k_xfwd<T, P, E, C, LPB>, dim3(cdiv(pairs, LPB), 1, nb), dim3(LPB * (P / E)), s, ev, u, out, nrows, n_in,
+           in_pitch, nj, ntiles, tw, done, bz);
 }
 
 template <typename T, int P, int E, int C, int LPB>
 static void launch_xinv(const C2<T> *in, T *y, int nrows, int n_out, long out_pitch, int nj, int ntiles,
-                        const C2<T> *tw, const Epi<T> &ep, const double *done, hipStream_t s, const hipEvent_t *ev) {
+                        const C2<T> *tw, const Epi<T> &ep, const double *done, hipStream_t s, const hipEvent_t *ev,
+                        int nb = 1, BatchStrides bz = BatchStrides{}) {
     const int pairs = (nrows + 1) / 2;
     if (ep.active())
-        launch(k_xinv<T, P, E, C, LPB, true>, dim3(cdiv(pairs, LPB)), dim3(LPB * (P / E)), s, ev, in, y, nrows,
-               n_out, out_pitch, nj, ntiles, tw, ep, done);
+        launch(k_xinv<T, P, E, C, LPB, true>, dim3(cdiv(pairs, LPB), 1, nb), dim3(LPB * (P / E)), s, ev, in, y,
+               nrows, n_out, out_pitch, nj, ntiles, tw, ep, done, bz);
     else
-        launch(k_xinv<T, P, E, C, LPB, false>, dim3(cdiv(pairs, LPB)), dim3(LPB * (P / E)), s, ev, in, y, nrows,
-               n_out, out_pitch, nj, ntiles, tw, ep, done);
+        launch(k_xinv<T, P, E, C, LPB, false>, dim3(cdiv(pairs, LPB), 1, nb), dim3(LPB * (P / E)), s, ev, in, y,
+               nrows, n_out, out_pitch, nj, ntiles, tw, ep, done, bz);
 }
 
 template <typename T, int P, int E, int C, int MODE>
 static void launch_strided(const C2<T> *in, C2<T> *out, int ncols, int nouter, int n_in, int n_out,
                            const Strides &st, const C2<T> *tw, const T *lam, const double *done, hipStream_t s,
-                           const hipEvent_t *ev) {
-    launch(k_strided<T, P, E, C, MODE>, dim3(cdiv(ncols, C), nouter), dim3(C * (P / E)), s, ev, in, out, ncols,
-           n_in, n_out, st, tw, lam, done);
+                           const hipEvent_t *ev, int nb = 1, BatchStrides bz = BatchStrides{}) {
+    launch(k_strided<T, P, E, C, MODE>, dim3(cdiv(ncols, C), nouter, nb), dim3(C * (P / E)), s, ev, in, out, ncols,
+           n_in, n_out, st, tw, lam, done, bz);
 }
 
 // ---------------------------------------------------------------------------
@@ -344,37 +365,62 @@ template <typename T> static const T *lamt(fl_op op);
 template <> const float *lamt<float>(fl_op op) { return op->lam32t; }
 template <> const double *lamt<double>(fl_op op) { return op->lam64t; }
 
+template <typename T> MvCtx<T> single_ctx(fl_op op) {
+    MvCtx<T> c;
+    c.d = op->d;
+    c.n = op->n;
+    c.P = op->P;
+    c.Q = op->Q;
+    c.T1 = op->T1;
+    c.T2 = op->T2;
+    c.tw = twid<T>(op);
+    c.lam = lamt<T>(op);
+    return c;
+}
+template MvCtx<float> single_ctx<float>(fl_op);
+template MvCtx<double> single_ctx<double>(fl_op);
+
 template <typename T, int P, int D, int EX, int EY, int C, int LPB>
-static void matvec_v(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
+static void matvec_v(const MvCtx<T> &cx, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
                      const hipEvent_t *ev) {
-    const int n = op->n, Q = op->Q;
+    const int n = cx.n, Q = cx.Q;
     const int nt = cdiv(Q, C);
-    C2<T> *T1 = (C2<T> *)op->T1;
-    C2<T> *T2 = (C2<T> *)op->T2;
-    const C2<T> *tw = twid<T>(op);
-    const T *lam = lamt<T>(op);
+    C2<T> *T1 = (C2<T> *)cx.T1;
+    C2<T> *T2 = (C2<T> *)cx.T2;
+    const C2<T> *tw = cx.tw;
+    const T *lam = cx.lam;
+    const int nb = cx.batch;
+    // element strides between problems: vectors, tiled spectra (in complex values), lambda
+    const long zt1 = cx.zs_t1 / (long)sizeof(C2<T>), zt2 = cx.zs_t2 / (long)sizeof(C2<T>);
     auto E = [&](int i) { return ev ? ev + 2 * i : nullptr; };
+    BatchStrides b_in{cx.zs_vec, zt1, 0, cx.zs_done};
     if constexpr (D == 2) {
-        launch_xfwd<T, P, EX, C, LPB>(u, T1, n, n, n, n, nt, tw, done, s, E(0));
+        launch_xfwd<T, P, EX, C, LPB>(u, T1, n, n, n, n, nt, tw, done, s, E(0), nb, b_in);
         Strides sy{0, n * C, 0, n * C, C, Q * C, 0};
-        launch_strided<T, P, EY, C, 2>(T1, T1, Q, 1, n, n, sy, tw, lam, done, s, E(1));
-        launch_xinv<T, P, EX, C, LPB>(T1, y, n, n, n, n, nt, tw, ep, done, s, E(2));
+        launch_strided<T, P, EY, C, 2>(T1, T1, Q, 1, n, n, sy, tw, lam, done, s, E(1), nb,
+                                       BatchStrides{zt1, zt1, cx.zs_lam, cx.zs_done});
+        launch_xinv<T, P, EX, C, LPB>(T1, y, n, n, n, n, nt, tw, ep, done, s, E(2), nb,
+                                      BatchStrides{zt1, cx.zs_vec, 0, cx.zs_done});
     } else {
         const long nn = (long)n * n;
-        launch_xfwd<T, P, EX, C, LPB>(u, T1, (int)nn, n, n, n, nt, tw, done, s, E(0));
+        launch_xfwd<T, P, EX, C, LPB>(u, T1, (int)nn, n, n, n, nt, tw, done, s, E(0), nb, b_in);
         Strides s1{nt * n * C, n * C, nt * P * C, P * C, C, 0, 0};
-        launch_strided<T, P, EY, C, 0>(T1, T2, Q, n, n, P, s1, tw, nullptr, done, s, E(1));
+        launch_strided<T, P, EY, C, 0>(T1, T2, Q, n, n, P, s1, tw, nullptr, done, s, E(1), nb,
+                                       BatchStrides{zt1, zt2, 0, cx.zs_done});
         Strides s2{C, P * C, C, P * C, nt * P * C, Q * Q * C, Q * C};
-        launch_strided<T, P, EY, C, 2>(T2, T2, Q, P, n, n, s2, tw, lam, done, s, E(2));
+        launch_strided<T, P, EY, C, 2>(T2, T2, Q, P, n, n, s2, tw, lam, done, s, E(2), nb,
+                                       BatchStrides{zt2, zt2, cx.zs_lam, cx.zs_done});
         Strides s3{nt * P * C, P * C, nt * n * C, n * C, C, 0, 0};
-        launch_strided<T, P, EY, C, 1>(T2, T1, Q, n, P, n, s3, tw, nullptr, done, s, E(3));
-        launch_xinv<T, P, EX, C, LPB>(T1, y, (int)nn, n, n, n, nt, tw, ep, done, s, E(4));
+        launch_strided<T, P, EY, C, 1>(T2, T1, Q, n, P, n, s3, tw, nullptr, done, s, E(3), nb,
+                                       BatchStrides{zt2, zt1, 0, cx.zs_done});
+        launch_xinv<T, P, EX, C, LPB>(T1, y, (int)nn, n, n, n, nt, tw, ep, done, s, E(4), nb,
+                                      BatchStrides{zt1, cx.zs_vec, 0, cx.zs_done});
     }
 }
 
 template <typename T> struct Variant {
     VariantDesc desc;
-    void (*fn)(fl_op, const T *, T *, const Epi<T> &, const double *, hipStream_t, const hipEvent_t *);
+    void (*fn)(const MvCtx<T> &, const T *, T *, const Epi<T> &, const double *, hipStream_t, const hipEvent_t *);
 };
 
 #define FL_VAR(T, P, D, EX, EY, C, LPB) \
@@ -482,18 +528,27 @@ template <> int &chosen<float>(fl_op op) { return op->var32; }
 template <> int &chosen<double>(fl_op op) { return op->var64; }
 
 template <typename T>
-fl_status matvec_ex(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
-                    hipEvent_t *ev) {
+fl_status matvec_ctx(const MvCtx<T> &cx, int k, const T *u, T *y, const Epi<T> &ep, const double *done,
+                     hipStream_t s, hipEvent_t *ev) {
     int count = 0;
-    const Variant<T> *vs = variants<T>(op->P, op->d, &count);
-    const int k = chosen<T>(op);
+    const Variant<T> *vs = variants<T>(cx.P, cx.d, &count);
     if (!vs || k < 0 || k >= count) {
-        set_error("no kernel variant for FFT length %d, d=%d", op->P, op->d);
+        set_error("no kernel variant %d for FFT length %d, d=%d", k, cx.P, cx.d);
         return FL_E_UNSUPPORTED;
     }
-    vs[k].fn(op, u, y, ep, done, s, ev);
+    vs[k].fn(cx, u, y, ep, done, s, ev);
     FL_HIP_TRY(hipGetLastError());
     return FL_OK;
+}
+template fl_status matvec_ctx<float>(const MvCtx<float> &, int, const float *, float *, const Epi<float> &,
+                                     const double *, hipStream_t, hipEvent_t *);
+template fl_status matvec_ctx<double>(const MvCtx<double> &, int, const double *, double *, const Epi<double> &,
+                                      const double *, hipStream_t, hipEvent_t *);
+
+template <typename T>
+fl_status matvec_ex(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
+                    hipEvent_t *ev) {
+    return matvec_ctx<T>(single_ctx<T>(op), chosen<T>(op), u, y, ep, done, s, ev);
 }
 
 template <typename T>
@@ -514,6 +569,16 @@ int variant_count(fl_op op, int prec) {
     if (prec == FL_FP32) variants<float>(op->P, op->d, &n);
     else variants<double>(op->P, op->d, &n);
     return n;
+}
+
+VariantDesc variant_desc_pd(int P, int d, int prec, int k) {
+    int n = 0;
+    if (prec == FL_FP32) {
+        const Variant<float> *v = variants<float>(P, d, &n);
+        return k >= 0 && k < n ? v[k].desc : VariantDesc{0, 0, 0, 0};
+    }
+    const Variant<double> *v = variants<double>(P, d, &n);
+    return k >= 0 && k < n ? v[k].desc : VariantDesc{0, 0, 0, 0};
 }
 
 VariantDesc variant_desc(fl_op op, int prec, int k) {
@@ -548,6 +613,19 @@ __global__ void k_tile_lambda(const double *__restrict__ lam64, T *__restrict__ 
         }
         lt[idx] = (T)v;
     }
+}
+
+// lambda of one operator tiled to width C into lt (FP32 or FP64)
+fl_status tile_lambda(fl_op op, int prec, int C, void *lt, hipStream_t s) {
+    const int Q = op->Q, nt = cdiv(Q, C);
+    const long len = (op->d == 2 ? (long)Q : (long)Q * Q) * nt * C;
+    const int g = cdiv(len, 256) > 65536 ? 65536 : cdiv(len, 256);
+    if (prec == FL_FP32)
+        hipLaunchKernelGGL(k_tile_lambda<float>, dim3(g), dim3(256), 0, s, op->lam64, (float *)lt, op->d, Q, C, nt);
+    else
+        hipLaunchKernelGGL(k_tile_lambda<double>, dim3(g), dim3(256), 0, s, op->lam64, (double *)lt, op->d, Q, C, nt);
+    FL_HIP_TRY(hipGetLastError());
+    return FL_OK;
 }
 
 // select variant k for a precision: re-tile lambda to the variant's tile width

@@ -293,6 +293,24 @@ fl_status matvec(fl_op op, const T *u, T *y, hipStream_t s);
 template <typename T>
 fl_status matvec_ex(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
                     hipEvent_t *ev = nullptr);
+
+// what a matvec launch needs: sizes, workspaces, twiddles, tiled lambda, and for
+// a batch of same-size problems (blockIdx.z = problem) the per-problem strides
+template <typename T> struct MvCtx {
+    int d = 2, n = 0, P = 0, Q = 0;
+    void *T1 = nullptr, *T2 = nullptr;
+    const C2<T> *tw = nullptr;
+    const T *lam = nullptr;
+    int batch = 1;
+    long zs_vec = 0;           // elements between problems' vectors
+    long zs_t1 = 0, zs_t2 = 0; // bytes between problems' workspaces
+    long zs_lam = 0;           // elements between problems' tiled lambda
+    int zs_done = 0;           // doubles between problems' done flags
+};
+template <typename T> MvCtx<T> single_ctx(fl_op op);
+template <typename T>
+fl_status matvec_ctx(const MvCtx<T> &cx, int variant, const T *u, T *y, const Epi<T> &ep, const double *done,
+                     hipStream_t s, hipEvent_t *ev = nullptr);
 fl_status build_symbol(fl_op op, hipStream_t s);
 int kernel_p_supported(int P);
 // kernel variants of a matvec: points per thread in the row / strided passes,
@@ -302,6 +320,8 @@ struct VariantDesc {
 };
 int variant_count(fl_op op, int prec);
 VariantDesc variant_desc(fl_op op, int prec, int k);
+VariantDesc variant_desc_pd(int P, int d, int prec, int k);
+fl_status tile_lambda(fl_op op, int prec, int C, void *lt, hipStream_t s);
 fl_status select_variant(fl_op op, int prec, int k, hipStream_t s);
 constexpr int kMaxTile = 16;  // largest tile width of any variant
 }  // namespace fl

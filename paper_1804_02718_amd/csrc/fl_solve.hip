@@ -14,6 +14,8 @@
 // loop with an FP64 inner solve.
 #include <chrono>
 #include <cmath>
+#include <new>
+#include <vector>
 
 #include "fl_internal.hpp"
 
@@ -66,11 +68,17 @@ __device__ __forceinline__ double sum_parts(const double *__restrict__ part, int
     return block_sum(a, sh);
 }
 
+// Batched use: blockIdx.y = problem z; vectors of problem z start at z*n,
+// its partial sums at z*kMaxParts and its scalars at z*S_COUNT.
 template <typename V>
 __global__ __launch_bounds__(kVecBlock) void k_dot(const V *__restrict__ a, const V *__restrict__ b, long n, long chunk,
                                                    double *part, const double *done) {
     __shared__ double sh[kVecBlock];
-    if (done && *done != 0.0) return;
+    const int z = blockIdx.y;
+    if (done && done[z * S_COUNT] != 0.0) return;
+    a += z * n;
+    b += z * n;
+    part += z * kMaxParts;
     const long beg = (long)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
     double acc = 0.0;
     for (long i = beg + threadIdx.x; i < end; i += kVecBlock) acc += (double)a[i] * (double)b[i];
@@ -81,14 +89,27 @@ __global__ __launch_bounds__(kVecBlock) void k_dot(const V *__restrict__ a, cons
 // slot <- sum of partials (single block)
 __global__ __launch_bounds__(kVecBlock) void k_finish(const double *part, int np, double *scal, int slot) {
     __shared__ double sh[kVecBlock];
+    const int z = blockIdx.y;
+    part += z * kMaxParts;
+    scal += z * S_COUNT;
     double s = sum_parts(part, np, sh);
     if (threadIdx.x == 0) scal[slot] = s;
 }
 
-// start of a CG run: rr[0] = sum(part), flags cleared, target = rel^2 * rr
+// start of a CG run: rr[0] = sum(part), flags cleared, target = rel^2 * rr;
+// rel2z (optional, per problem) overrides rel2, a negative entry marks the
+// problem as already finished
 __global__ __launch_bounds__(kVecBlock) void k_cg_init(const double *part, int np, double *scal, double rel2,
-                                                       double abs2) {
+                                                       double abs2, const double *rel2z) {
     __shared__ double sh[kVecBlock];
+    const int z = blockIdx.y;
+    part += z * kMaxParts;
+    scal += z * S_COUNT;
+    bool skip = false;
+    if (rel2z) {
+        rel2 = rel2z[z];
+        skip = rel2 < 0.0;
+    }
     double s = sum_parts(part, np, sh);
     if (threadIdx.x == 0) {
         scal[S_RR0] = s;
@@ -97,7 +118,7 @@ __global__ __launch_bounds__(kVecBlock) void k_cg_init(const double *part, int n
         scal[S_BRK] = std::isfinite(s) ? 0.0 : 1.0;
         const double tgt = rel2 * s > abs2 ? rel2 * s : abs2;
         scal[S_TARGET] = tgt;
-        scal[S_DONE] = (s <= tgt || !std::isfinite(s)) ? 1.0 : 0.0;
+        scal[S_DONE] = (skip || s <= tgt || !std::isfinite(s)) ? 1.0 : 0.0;
     }
 }
 
@@ -108,7 +129,15 @@ __global__ __launch_bounds__(kVecBlock) void k_cg_xr(V *__restrict__ x, V *__res
                                                      const double *__restrict__ part_pkp, int np, double *part_rr,
                                                      double *scal, int parity) {
     __shared__ double sh[kVecBlock];
+    const int z = blockIdx.y;
+    scal += z * S_COUNT;
     if (scal[S_DONE] != 0.0) return;
+    x += z * n;
+    r += z * n;
+    p += z * n;
+    kp += z * n;
+    part_pkp += z * kMaxParts;
+    part_rr += z * kMaxParts;
     const double pkp = sum_parts(part_pkp, np, sh);
     const double rr = scal[parity ? S_RR1 : S_RR0];
     const double al = rr / pkp;
@@ -138,7 +167,12 @@ __global__ __launch_bounds__(kVecBlock) void k_cg_p(V *__restrict__ p, const V *
                                                     const double *__restrict__ part_rr, int np, double *scal,
                                                     int parity) {
     __shared__ double sh[kVecBlock];
+    const int z = blockIdx.y;
+    scal += z * S_COUNT;
     if (scal[S_DONE] != 0.0) return;
+    p += z * n;
+    r += z * n;
+    part_rr += z * kMaxParts;
     const double rr_new = sum_parts(part_rr, np, sh);
     const double rr = scal[parity ? S_RR1 : S_RR0];
     const double be = rr_new / rr;
@@ -292,7 +326,8 @@ static fl_status cg_run(fl_op op, double s0, double s1, V *d, V *r, V *p, V *kp,
     hipLaunchKernelGGL(k_zero<V>, dim3(ew_grid(M)), dim3(256), 0, s, d, M);
     hipLaunchKernelGGL((k_copy_cast<V, V>), dim3(ew_grid(M)), dim3(256), 0, s, p, r, M);
     hipLaunchKernelGGL(k_dot<V>, dim3(L.blocks), dim3(kVecBlock), 0, s, r, r, L.n, L.chunk, w.partB, nullptr);
-    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(kVecBlock), 0, s, w.partB, L.blocks, op->scal, rel * rel, 0.0);
+    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(kVecBlock), 0, s, w.partB, L.blocks, op->scal, rel * rel, 0.0,
+                       (const double *)nullptr);
     FL_HIP_TRY(hipGetLastError());
     const double *done = op->scal + S_DONE;
     int launched = 0;
@@ -474,6 +509,389 @@ fl_status fl_allen_cahn_step_ex(fl_op op, double *u, double tau, double eps, dou
 
 fl_status fl_allen_cahn_step(fl_op op, double *u, double tau, double eps, fl_info *info, void *stream) {
     return fl_allen_cahn_step_ex(op, u, tau, eps, 0.5, 1e-8, FL_SOLVE_AUTO, info, stream);
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched Poisson solves.  Problems are grouped into size classes (same N,
+// hence the same FFT length and kernels).  Each class keeps its problems'
+// vectors packed ([problem][M]) and runs every FFT pass and CG kernel of all
+// of them in one launch (blockIdx.z / blockIdx.y = problem).  The inner FP32
+// CG iterations of a class are captured once in a hipGraph (a chunk of
+// kGraphIters iterations) and replayed; classes run concurrently on their own
+// streams.  Each problem has its own device scalars and done flag, so a
+// converged problem turns its share of every later launch into a no-op.
+// ===========================================================================
+namespace fl {
+
+constexpr int kGraphIters = 16;  // inner CG iterations per captured graph (even: parity)
+
+struct BatchClass {
+    int N = 0, n = 0, P = 0, Q = 0, B = 0;
+    long M = 0;
+    std::vector<int> idx;    // user indices of the problems
+    std::vector<fl_op> ops;  // per-problem operators (coefficients, lambda)
+    int var32 = 0, var64 = 0;
+    void *buf = nullptr;     // all packed device buffers
+    double *x = nullptr, *b = nullptr, *r64 = nullptr, *rel2 = nullptr;
+    float *r32 = nullptr, *p32 = nullptr, *kp32 = nullptr, *d32 = nullptr;
+    double *partA = nullptr, *partB = nullptr, *scal = nullptr, *hscal = nullptr;
+    void *T1 = nullptr, *T2 = nullptr, *lam32 = nullptr, *lam64 = nullptr;
+    long zs_t = 0, zs_t2 = 0, lamlen32 = 0, lamlen64 = 0;
+    hipStream_t s = nullptr;
+    hipGraphExec_t chunk = nullptr;
+    MvCtx<float> c32;
+    MvCtx<double> c64;
+};
+
+}  // namespace fl
+
+struct fl_batch_s {
+    int d = 2, count = 0;
+    std::vector<fl::BatchClass> cls;
+};
+
+namespace fl {
+
+static void batch_free(fl_batch b) {
+    if (!b) return;
+    for (auto &c : b->cls) {
+        if (c.chunk) (void)hipGraphExecDestroy(c.chunk);
+        if (c.s) (void)hipStreamDestroy(c.s);
+        if (c.buf) (void)hipFree(c.buf);
+        if (c.hscal) (void)hipHostFree(c.hscal);
+        for (fl_op o : c.ops) fl_op_destroy(o);
+    }
+    delete b;
+}
+
+// carve the class's packed buffers out of one allocation
+static fl_status batch_alloc(BatchClass &c, int d) {
+    const long B = c.B, M = c.M;
+    const int C32 = variant_desc_pd(c.P, d, FL_FP32, c.var32).c, C64 = variant_desc_pd(c.P, d, FL_FP64, c.var64).c;
+    const long qrest = d == 2 ? c.Q : (long)c.Q * c.Q;
+    c.lamlen32 = qrest * ((c.Q + C32 - 1) / C32) * C32;
+    c.lamlen64 = qrest * ((c.Q + C64 - 1) / C64) * C64;
+    c.zs_t = c.ops[0]->T1_bytes;
+    c.zs_t2 = c.ops[0]->T2_bytes;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t off = 0;
+    const size_t o_x = off; off += al(sizeof(double) * B * M);
+    const size_t o_b = off; off += al(sizeof(double) * B * M);
+    const size_t o_r64 = off; off += al(sizeof(double) * B * M);
+    const size_t o_rel = off; off += al(sizeof(double) * B);
+    const size_t o_r32 = off; off += al(sizeof(float) * B * M);
+    const size_t o_p32 = off; off += al(sizeof(float) * B * M);
+    const size_t o_kp32 = off; off += al(sizeof(float) * B * M);
+    const size_t o_d32 = off; off += al(sizeof(float) * B * M);
+    const size_t o_pa = off; off += al(sizeof(double) * B * kMaxParts);
+    const size_t o_pb = off; off += al(sizeof(double) * B * kMaxParts);
+    const size_t o_sc = off; off += al(sizeof(double) * B * S_COUNT);
+    const size_t o_t1 = off; off += al((size_t)c.zs_t * B);
+    const size_t o_t2 = off; off += al((size_t)c.zs_t2 * B);
+    const size_t o_l32 = off; off += al(sizeof(float) * c.lamlen32 * B);
+    const size_t o_l64 = off; off += al(sizeof(double) * c.lamlen64 * B);
+    FL_HIP_TRY(hipMalloc(&c.buf, off));
+    char *base = (char *)c.buf;
+    c.x = (double *)(base + o_x);
+    c.b = (double *)(base + o_b);
+    c.r64 = (double *)(base + o_r64);
+    c.rel2 = (double *)(base + o_rel);
+    c.r32 = (float *)(base + o_r32);
+    c.p32 = (float *)(base + o_p32);
+    c.kp32 = (float *)(base + o_kp32);
+    c.d32 = (float *)(base + o_d32);
+    c.partA = (double *)(base + o_pa);
+    c.partB = (double *)(base + o_pb);
+    c.scal = (double *)(base + o_sc);
+    c.T1 = base + o_t1;
+    c.T2 = c.zs_t2 ? (void *)(base + o_t2) : nullptr;
+    c.lam32 = base + o_l32;
+    c.lam64 = base + o_l64;
+    FL_HIP_TRY(hipHostMalloc((void **)&c.hscal, sizeof(double) * B * S_COUNT, hipHostMallocDefault));
+    // per-problem lambda tiled for the class's variants
+    for (int z = 0; z < c.B; ++z) {
+        FL_TRY(tile_lambda(c.ops[z], FL_FP32, C32, (float *)c.lam32 + z * c.lamlen32, c.s));
+        FL_TRY(tile_lambda(c.ops[z], FL_FP64, C64, (double *)c.lam64 + z * c.lamlen64, c.s));
+    }
+    c.c32 = single_ctx<float>(c.ops[0]);
+    c.c64 = single_ctx<double>(c.ops[0]);
+    for (MvCtx<float> *cx : {&c.c32}) {
+        cx->T1 = c.T1; cx->T2 = c.T2; cx->lam = (const float *)c.lam32; cx->batch = c.B; cx->zs_vec = M;
+        cx->zs_t1 = c.zs_t; cx->zs_t2 = c.zs_t2; cx->zs_lam = c.lamlen32; cx->zs_done = S_COUNT;
+    }
+    for (MvCtx<double> *cx : {&c.c64}) {
+        cx->T1 = c.T1; cx->T2 = c.T2; cx->lam = (const double *)c.lam64; cx->batch = c.B; cx->zs_vec = M;
+        cx->zs_t1 = c.zs_t; cx->zs_t2 = c.zs_t2; cx->zs_lam = c.lamlen64; cx->zs_done = S_COUNT;
+    }
+    return FL_OK;
+}
+
+// launches of kGraphIters inner FP32 CG iterations of a class (captured once)
+static fl_status batch_chunk_launches(BatchClass &c) {
+    VecLayout L = layout(c.M);
+    const double *done = c.scal + S_DONE;
+    for (int i = 0; i < kGraphIters; ++i) {
+        const int parity = i & 1;
+        FL_TRY(matvec_ctx<float>(c.c32, c.var32, c.p32, c.kp32, Epi<float>{}, done, c.s));
+        hipLaunchKernelGGL(k_dot<float>, dim3(L.blocks, c.B), dim3(kVecBlock), 0, c.s, c.p32, c.kp32, L.n, L.chunk,
+                           c.partA, done);
+        hipLaunchKernelGGL(k_cg_xr<float>, dim3(L.blocks, c.B), dim3(kVecBlock), 0, c.s, c.d32, c.r32, c.p32,
+                           c.kp32, L.n, L.chunk, c.partA, L.blocks, c.partB, c.scal, parity);
+        hipLaunchKernelGGL(k_cg_p<float>, dim3(L.blocks, c.B), dim3(kVecBlock), 0, c.s, c.p32, c.r32, L.n, L.chunk,
+                           c.partB, L.blocks, c.scal, parity);
+    }
+    FL_HIP_TRY(hipGetLastError());
+    return FL_OK;
+}
+
+static fl_status batch_capture(BatchClass &c) {
+    hipGraph_t g = nullptr;
+    FL_HIP_TRY(hipStreamBeginCapture(c.s, hipStreamCaptureModeThreadLocal));
+    fl_status st = batch_chunk_launches(c);
+    hipError_t e = hipStreamEndCapture(c.s, &g);
+    FL_TRY(st);
+    FL_HIP_TRY(e);
+    e = hipGraphInstantiate(&c.chunk, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    FL_HIP_TRY(e);
+    return FL_OK;
+}
+
+static fl_status batch_sync_read(BatchClass &c) {
+    FL_HIP_TRY(hipMemcpyAsync(c.hscal, c.scal, sizeof(double) * c.B * S_COUNT, hipMemcpyDeviceToHost, c.s));
+    FL_HIP_TRY(hipStreamSynchronize(c.s));
+    return FL_OK;
+}
+
+}  // namespace fl
+
+extern "C" {
+
+fl_status fl_batch_create(int d, int count, const int *N, const double *alpha, const double *h, fl_batch *out) {
+    if (!out || !N || !alpha || !h || count < 1 || (d != 2 && d != 3)) {
+        set_error("bad argument");
+        return FL_E_INVAL;
+    }
+    fl_batch b = new (std::nothrow) fl_batch_s();
+    if (!b) return FL_E_NOMEM;
+    b->d = d;
+    b->count = count;
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    fl_status st = FL_OK;
+    for (int i = 0; i < count && st == FL_OK; ++i) {
+        BatchClass *c = nullptr;
+        for (auto &k : b->cls)
+            if (k.N == N[i]) c = &k;
+        if (!c) {
+            b->cls.emplace_back();
+            c = &b->cls.back();
+            c->N = N[i];
+        }
+        fl_op op = nullptr;
+        st = fl_coeffs(d, alpha[i], h[i], N[i], &op);
+        if (st != FL_OK) break;
+        c->idx.push_back(i);
+        c->ops.push_back(op);
+    }
+    for (auto &c : b->cls) {
+        if (st != FL_OK) break;
+        fl_op o = c.ops[0];
+        c.n = o->n;
+        c.P = o->P;
+        c.Q = o->Q;
+        c.M = o->M;
+        c.B = (int)c.ops.size();
+        c.var32 = o->var32;
+        c.var64 = o->var64;
+        if (hipStreamCreateWithFlags(&c.s, hipStreamNonBlocking) != hipSuccess) {
+            st = FL_E_DEVICE;
+            break;
+        }
+        st = batch_alloc(c, d);
+        if (st == FL_OK) st = batch_capture(c);
+        if (st == FL_OK && hipStreamSynchronize(c.s) != hipSuccess) st = FL_E_DEVICE;
+    }
+    if (st != FL_OK) {
+        batch_free(b);
+        return st;
+    }
+    *out = b;
+    return FL_OK;
+}
+
+fl_status fl_batch_destroy(fl_batch b) {
+    batch_free(b);
+    return FL_OK;
+}
+
+fl_status fl_batch_poisson_solve(fl_batch b, const double *const *f, double *const *u, double tol, int max_iter,
+                                 fl_info *infos, void *stream) {
+    if (!b || !f || !u || !(tol > 0.0)) { set_error("bad argument"); return FL_E_INVAL; }
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t us = (hipStream_t)stream;
+    hipEvent_t ready = nullptr;
+    FL_HIP_TRY(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    FL_HIP_TRY(hipEventRecord(ready, us));  // inputs written on the caller's stream
+    const double inner_tol = 1e-3;
+    std::vector<std::vector<double>> bn(b->cls.size()), rel(b->cls.size());
+    std::vector<std::vector<int>> iters(b->cls.size()), outer(b->cls.size()), fin(b->cls.size());
+    fl_status st = FL_OK;
+    // gather right-hand sides, zero solutions, norms of b
+    for (size_t ci = 0; ci < b->cls.size() && st == FL_OK; ++ci) {
+        BatchClass &c = b->cls[ci];
+        bn[ci].assign(c.B, 0.0);
+        rel[ci].assign(c.B, 1.0);
+        iters[ci].assign(c.B, 0);
+        outer[ci].assign(c.B, 0);
+        fin[ci].assign(c.B, 0);
+        if (hipStreamWaitEvent(c.s, ready, 0) != hipSuccess) st = FL_E_DEVICE;
+        for (int z = 0; z < c.B && st == FL_OK; ++z)
+            if (hipMemcpyAsync(c.b + z * c.M, f[c.idx[z]], sizeof(double) * c.M, hipMemcpyDeviceToDevice, c.s) !=
+                hipSuccess)
+                st = FL_E_DEVICE;
+        hipLaunchKernelGGL(k_zero<double>, dim3(ew_grid(c.B * c.M)), dim3(256), 0, c.s, c.x, c.B * c.M);
+        VecLayout L = layout(c.M);
+        hipLaunchKernelGGL(k_dot<double>, dim3(L.blocks, c.B), dim3(kVecBlock), 0, c.s, c.b, c.b, L.n, L.chunk,
+                           c.partA, (const double *)nullptr);
+        hipLaunchKernelGGL(k_finish, dim3(1, c.B), dim3(kVecBlock), 0, c.s, c.partA, L.blocks, c.scal, (int)S_DOT);
+    }
+    for (size_t ci = 0; ci < b->cls.size() && st == FL_OK; ++ci) {
+        BatchClass &c = b->cls[ci];
+        st = batch_sync_read(c);
+        for (int z = 0; z < c.B && st == FL_OK; ++z) {
+            bn[ci][z] = std::sqrt(c.hscal[z * S_COUNT + S_DOT]);
+            if (!std::isfinite(bn[ci][z])) st = FL_E_BREAKDOWN;
+            if (bn[ci][z] == 0.0) { fin[ci][z] = 1; rel[ci][z] = 0.0; }
+        }
+    }
+    const int cap = max_iter > 0 ? max_iter : 1 << 30;
+    for (int outer_it = 0; st == FL_OK && outer_it < 200; ++outer_it) {
+        // FP64 residuals of every class
+        for (size_t ci = 0; ci < b->cls.size() && st == FL_OK; ++ci) {
+            BatchClass &c = b->cls[ci];
+            Epi<double> ep;
+            ep.w1 = c.b;
+            ep.a1 = 1.0;
+            ep.scale = -1.0;
+            st = matvec_ctx<double>(c.c64, c.var64, c.x, c.r64, ep, nullptr, c.s);
+            VecLayout L = layout(c.M);
+            hipLaunchKernelGGL(k_dot<double>, dim3(L.blocks, c.B), dim3(kVecBlock), 0, c.s, c.r64, c.r64, L.n,
+                               L.chunk, c.partA, (const double *)nullptr);
+            hipLaunchKernelGGL(k_finish, dim3(1, c.B), dim3(kVecBlock), 0, c.s, c.partA, L.blocks, c.scal,
+                               (int)S_DOT);
+        }
+        bool all = true;
+        for (size_t ci = 0; ci < b->cls.size() && st == FL_OK; ++ci) {
+            BatchClass &c = b->cls[ci];
+            st = batch_sync_read(c);
+            std::vector<double> r2(c.B);
+            for (int z = 0; z < c.B; ++z) {
+                if (fin[ci][z]) { r2[z] = -1.0; continue; }
+                const double r = std::sqrt(c.hscal[z * S_COUNT + S_DOT]) / bn[ci][z];
+                rel[ci][z] = r;
+                outer[ci][z] += 1;
+                if (!std::isfinite(r)) { st = FL_E_BREAKDOWN; break; }
+                if (r <= tol || iters[ci][z] >= cap) { fin[ci][z] = 1; r2[z] = -1.0; continue; }
+                double want = 0.5 * tol / r;
+                double itol = want > inner_tol ? want : inner_tol;
+                if (itol >= 1.0) itol = 0.5;
+                r2[z] = itol * itol;
+                all = false;
+            }
+            if (st == FL_OK &&
+                hipMemcpyAsync(c.rel2, r2.data(), sizeof(double) * c.B, hipMemcpyHostToDevice, c.s) != hipSuccess)
+                st = FL_E_DEVICE;
+            if (st == FL_OK) st = batch_sync_read(c);  // r2 lives on the host stack
+        }
+        if (st != FL_OK || all) break;
+        // inner FP32 CG of every class: init, then captured chunks until done
+        for (size_t ci = 0; ci < b->cls.size(); ++ci) {
+            BatchClass &c = b->cls[ci];
+            VecLayout L = layout(c.M);
+            const long BM = (long)c.B * c.M;
+            hipLaunchKernelGGL((k_copy_cast<float, double>), dim3(ew_grid(BM)), dim3(256), 0, c.s, c.r32, c.r64, BM);
+            hipLaunchKernelGGL(k_zero<float>, dim3(ew_grid(BM)), dim3(256), 0, c.s, c.d32, BM);
+            hipLaunchKernelGGL((k_copy_cast<float, float>), dim3(ew_grid(BM)), dim3(256), 0, c.s, c.p32, c.r32, BM);
+            hipLaunchKernelGGL(k_dot<float>, dim3(L.blocks, c.B), dim3(kVecBlock), 0, c.s, c.r32, c.r32, L.n, L.chunk,
+                               c.partB, (const double *)nullptr);
+            hipLaunchKernelGGL(k_cg_init, dim3(1, c.B), dim3(kVecBlock), 0, c.s, c.partB, L.blocks, c.scal, 0.0, 0.0,
+                               (const double *)c.rel2);
+        }
+        std::vector<int> active(b->cls.size(), 1);
+        for (int chunk = 0; st == FL_OK; ++chunk) {
+            bool any = false;
+            for (size_t ci = 0; ci < b->cls.size(); ++ci)
+                if (active[ci]) {
+                    if (hipGraphLaunch(b->cls[ci].chunk, b->cls[ci].s) != hipSuccess) st = FL_E_DEVICE;
+                    any = true;
+                }
+            if (!any) break;
+            for (size_t ci = 0; ci < b->cls.size() && st == FL_OK; ++ci) {
+                if (!active[ci]) continue;
+                BatchClass &c = b->cls[ci];
+                st = batch_sync_read(c);
+                bool done = true;
+                for (int z = 0; z < c.B; ++z)
+                    if (c.hscal[z * S_COUNT + S_DONE] == 0.0 && iters[ci][z] + (chunk + 1) * kGraphIters < cap)
+                        done = false;
+                if (done) {
+                    active[ci] = 0;
+                    for (int z = 0; z < c.B; ++z)
+                        if (!fin[ci][z]) iters[ci][z] += (int)c.hscal[z * S_COUNT + S_ITER];
+                    const long BM = (long)c.B * c.M;
+                    hipLaunchKernelGGL(k_axpy_to64<float>, dim3(ew_grid(BM)), dim3(256), 0, c.s, c.x, c.d32, BM);
+                }
+            }
+        }
+    }
+    // scatter solutions
+    fl_status worst = st;
+    for (size_t ci = 0; ci < b->cls.size(); ++ci) {
+        BatchClass &c = b->cls[ci];
+        for (int z = 0; z < c.B && st == FL_OK; ++z)
+            if (hipMemcpyAsync(u[c.idx[z]], c.x + z * c.M, sizeof(double) * c.M, hipMemcpyDeviceToDevice, c.s) !=
+                hipSuccess)
+                st = FL_E_DEVICE;
+        (void)hipStreamSynchronize(c.s);
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        for (int z = 0; z < c.B; ++z) {
+            fl_status ps = st != FL_OK ? st : (rel[ci][z] <= tol ? FL_OK : FL_E_NOCONV);
+            if (ps != FL_OK && worst == FL_OK) worst = ps;
+            if (infos) {
+                fl_info &in = infos[c.idx[z]];
+                in = fl_info{};
+                in.iters = iters[ci][z];
+                in.outer_iters = outer[ci][z];
+                in.relres = rel[ci][z];
+                in.status = ps;
+                in.seconds = secs;
+            }
+        }
+    }
+    (void)hipEventDestroy(ready);
+    // the caller's stream sees the solutions
+    for (auto &c : b->cls) {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess) {
+            (void)hipEventRecord(e, c.s);
+            (void)hipStreamWaitEvent(us, e, 0);
+            (void)hipEventDestroy(e);
+        }
+    }
+    if (worst == FL_E_NOCONV) set_error("some problems did not reach the tolerance");
+    return worst;
+}
+
+fl_status fl_batch_info(fl_batch b, int *nclasses, int *max_batch) {
+    if (!b) { set_error("NULL batch"); return FL_E_INVAL; }
+    int mb = 0;
+    for (auto &c : b->cls) mb = c.B > mb ? c.B : mb;
+    if (nclasses) *nclasses = (int)b->cls.size();
+    if (max_batch) *max_batch = mb;
+    return FL_OK;
 }
 
 }  // extern "C"

@@ -19,7 +19,8 @@ FL_FP64, FL_FP32 = 0, 1
 SOLVERS = {"auto": 0, "cg64": 1, "refine": 2, "fpcg": 3}
 
 EXPORTED = ["fl_coeffs", "fl_apply", "fl_apply_profiled", "fl_variant_count", "fl_variant_info",
-            "fl_select_variant", "fl_autotune", "fl_poisson_solve", "fl_poisson_solve_ex", "fl_allen_cahn_step",
+            "fl_select_variant", "fl_autotune", "fl_batch_create", "fl_batch_poisson_solve", "fl_batch_info",
+            "fl_batch_destroy", "fl_poisson_solve", "fl_poisson_solve_ex", "fl_allen_cahn_step",
             "fl_allen_cahn_step_ex", "fl_op_destroy", "fl_op_describe", "fl_get_coeffs", "fl_get_symbol",
             "fl_status_string", "fl_last_error"]
 
@@ -78,6 +79,12 @@ def load(path: str = LIB_PATH):
     lib.fl_variant_info.argtypes = [vp, ip, ip, ctypes.POINTER(ctypes.c_int)]
     lib.fl_select_variant.argtypes = [vp, ip, ip]
     lib.fl_autotune.argtypes = [vp, ip, ip, vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float)]
+    lib.fl_batch_create.argtypes = [ip, ip, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(vp)]
+    lib.fl_batch_poisson_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), dp, ip,
+                                           ctypes.POINTER(fl_info), vp]
+    lib.fl_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.fl_batch_destroy.argtypes = [vp]
     lib.fl_poisson_solve.argtypes = [vp, vp, dp, vp, ctypes.POINTER(fl_info), vp]
     lib.fl_poisson_solve_ex.argtypes = [vp, vp, dp, vp, ctypes.POINTER(fl_solve_opts), ctypes.POINTER(fl_info), vp]
     lib.fl_allen_cahn_step.argtypes = [vp, vp, dp, dp, ctypes.POINTER(fl_info), vp]
@@ -240,6 +247,66 @@ def fl_get_symbol(op) -> np.ndarray:
 def fl_op_destroy(op):
     if op:
         load().fl_op_destroy(op)
+
+
+def fl_batch_create(d, Ns, alphas, hs):
+    n = len(Ns)
+    b = ctypes.c_void_p()
+    _check(load().fl_batch_create(int(d), n, (ctypes.c_int * n)(*[int(x) for x in Ns]),
+                                  (ctypes.c_double * n)(*[float(x) for x in alphas]),
+                                  (ctypes.c_double * n)(*[float(x) for x in hs]), ctypes.byref(b)))
+    return b
+
+
+def fl_batch_poisson_solve(b, fs, us, tol, max_iter=0, stream=None, raise_on_error=True):
+    n = len(fs)
+    fp = (ctypes.c_void_p * n)(*[_ptr(x, numel=None).value for x in fs])
+    up = (ctypes.c_void_p * n)(*[_ptr(x).value for x in us])
+    infos = (fl_info * n)()
+    st = load().fl_batch_poisson_solve(b, fp, up, float(tol), int(max_iter), infos, _stream(stream))
+    out = [infos[i].as_dict() for i in range(n)]
+    if raise_on_error:
+        _check(st, out)
+    return out
+
+
+def fl_batch_info(b):
+    nc, mb = ctypes.c_int(), ctypes.c_int()
+    _check(load().fl_batch_info(b, ctypes.byref(nc), ctypes.byref(mb)))
+    return {"classes": nc.value, "max_batch": mb.value}
+
+
+def fl_batch_destroy(b):
+    if b:
+        load().fl_batch_destroy(b)
+
+
+class Batch:
+    """Many Poisson problems of mixed (N, alpha) solved together (one fl_batch)."""
+
+    def __init__(self, d, Ns, alphas, hs):
+        self._b = fl_batch_create(d, Ns, alphas, hs)
+        self.count = len(Ns)
+
+    def solve(self, fs, us=None, tol=1e-8, max_iter=0, stream=None):
+        import torch
+        if us is None:
+            us = [torch.zeros_like(f) for f in fs]
+        return us, fl_batch_poisson_solve(self._b, fs, us, tol, max_iter, stream)
+
+    def info(self):
+        return fl_batch_info(self._b)
+
+    def close(self):
+        if getattr(self, "_b", None):
+            fl_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------------------

@@ -188,3 +188,53 @@ def test_c3_allen_cahn_full_size_sampled(fl):
     assert np.abs(b - lhs).max() <= 1.1e-8 * bnorm
     print("c3 step", info)
     op.close()
+
+
+def test_batched_mixed_sizes_match_single_solves_and_oracle(fl):
+    # mixed (N, alpha) batch of 2D problems on (-1,1)^2; every solution reaches the
+    # tolerance, equals the single-problem solve and (small N) the dense oracle
+    rng = np.random.default_rng(11)
+    Ns = [16, 32, 16, 64, 32, 16, 64, 8]
+    alphas = [float(a) for a in rng.uniform(0.2, 1.95, len(Ns))]
+    hs = [2.0 / N for N in Ns]
+    fs_np = [inputs.gauss_sum(2, N, 4, seed=100 + i) for i, N in enumerate(Ns)]
+    fs = [_t(f) for f in fs_np]
+    b = fl.Batch(2, Ns, alphas, hs)
+    assert b.info()["classes"] == 4
+    us, infos = b.solve(fs, tol=1e-10)
+    torch.cuda.synchronize()
+    for i, (N, al) in enumerate(zip(Ns, alphas)):
+        assert infos[i]["status"] == 0 and infos[i]["relres"] <= 1e-10, (i, infos[i])
+        op = fl.Operator(2, al, hs[i], N)
+        r = fs[i] - op.apply(us[i])
+        assert (torch.linalg.norm(r) / torch.linalg.norm(fs[i])).item() <= 1.05e-10
+        us1, _ = op.poisson_solve(fs[i], tol=1e-10, solver="refine")
+        assert torch.allclose(us[i], us1, rtol=1e-6, atol=1e-8 * us1.abs().max().item())
+        if N <= 32:
+            a = oracle.coeffs(2, al, hs[i], N)
+            uref = oracle.solve_dense(oracle.dense(2, N, al, a), fs_np[i])
+            assert np.abs(us[i].cpu().numpy() - uref).max() <= 1e-7 * np.abs(uref).max()
+        op.close()
+    # a second solve on the same batch (graphs replayed again) gives the same answers
+    us2, infos2 = b.solve(fs, tol=1e-10)
+    torch.cuda.synchronize()
+    for i in range(len(Ns)):
+        assert torch.equal(us[i], us2[i])
+    b.close()
+
+
+def test_batched_c4_workload(fl):
+    # 64 problems, N from {64, 128, 256, 512}, alpha ~ U(0.2, 1.95), 4 Gaussians each, tol 1e-8
+    probs = inputs.batch_problems(64, seed=4)
+    b = fl.Batch(2, [p["N"] for p in probs], [p["alpha"] for p in probs], [p["h"] for p in probs])
+    fs = [_t(p["f"]) for p in probs]
+    us, infos = b.solve(fs, tol=1e-8)
+    torch.cuda.synchronize()
+    assert all(i["status"] == 0 and i["relres"] <= 1e-8 for i in infos)
+    for k in (0, 17, 40, 63):
+        p = probs[k]
+        op = fl.Operator(2, p["alpha"], p["h"], p["N"])
+        r = fs[k] - op.apply(us[k])
+        assert (torch.linalg.norm(r) / torch.linalg.norm(fs[k])).item() <= 1.05e-8
+        op.close()
+    b.close()
