@@ -40,6 +40,7 @@ extern "C" {
 #endif
 
 typedef struct fl_op_s *fl_op;
+typedef struct fl_unet_s *fl_unet;
 
 typedef enum {
     FL_OK = 0,
@@ -206,6 +207,64 @@ fl_status fl_batch_poisson_solve(fl_batch b, const double *const *f, double *con
                                  int max_iter, fl_info *infos, void *stream);
 fl_status fl_batch_info(fl_batch b, int *nclasses, int *max_batch);
 fl_status fl_batch_destroy(fl_batch b);
+
+/*
+ * Learned preconditioner: a convolutional U-Net (3 levels, 16/32/64 channels,
+ * 3x3 bias-free convolutions with ReLU, 2x2 average pooling, nearest
+ * upsampling with skip concatenation, 1x1 output) on an H x H grid, input
+ * channels (r / ||r||, alpha), output an approximation of A^{-1} r / ||r||.
+ * Convolutions run on bf16 MFMA with FP32 accumulation; weights are kept in
+ * FP32 (Adam) with bf16 copies.  Not part of the paper's method: it feeds the
+ * flexible PCG of FL_SOLVE_FPCG, which falls back to plain CG.
+ *   fl_unet_create      -- H a multiple of 16 in [16, 2048], max_batch in
+ *                          [1, 256] samples per step, seeded initialisation;
+ *                          fp32_operands != 0 runs every GEMM on fp32
+ *                          operands (v_mfma_f32_16x16x4_f32) instead of bf16,
+ *                          a verification mode.
+ *   fl_unet_step        -- nb samples: x (device, [nb][H][H][2] floats, NHWC),
+ *                          y (device, [nb][H][H], may be NULL) receives the
+ *                          output; with targets t (device, [nb][H][H]) also the
+ *                          relative squared error per sample (loss_host) and
+ *                          the weight gradients (grad_host, fl_unet_num_params
+ *                          floats, may be NULL); lr > 0 takes one Adam step.
+ *   fl_unet_pack        -- count training samples from device pairs
+ *                          (r[z], sol[z]) of n x n doubles (host arrays of
+ *                          device pointers; sol may be NULL): x[z] =
+ *                          (r/||r||, alpha[z]) and t[z] = sol/||r|| on the
+ *                          top-left n x n of the H x H grid, zero elsewhere.
+ *   fl_unet_train       -- epochs over count device samples (x, t as in
+ *                          fl_unet_step): seeded shuffle each epoch, batches
+ *                          of `batch` (the ragged remainder is dropped), one
+ *                          Adam step per batch with the learning rate
+ *                          decaying from lr to lr_final on a cosine; mean
+ *                          training loss per epoch to epoch_loss (host, may
+ *                          be NULL).
+ *   fl_unet_get_weights / fl_unet_set_weights -- FP32 weights, layer by layer,
+ *                          each [cout][(ky*ks + kx)*cin + ci] (host).
+ *   fl_unet_apply       -- z = ||r|| Net(r/||r||, alpha) for a residual r on
+ *                          the n x n interior (device doubles, n <= H).
+ *   fl_set_preconditioner -- attach (or detach with NULL) a network to a 2D
+ *                          operator for FL_SOLVE_FPCG; not owned.
+ *   fl_gemm_test        -- C = A B^T (host arrays [M][K], [N][K], [M][N];
+ *                          M, N, K, kchunk multiples of 16) through the
+ *                          network's GEMM kernel, operands rounded to bf16
+ *                          (or fp32); kchunk < K takes the split-K path.
+ */
+fl_status fl_unet_create(int H, int max_batch, unsigned long long seed, int fp32_operands, fl_unet *out);
+fl_status fl_unet_destroy(fl_unet u);
+fl_status fl_unet_num_params(fl_unet u, long long *n);
+fl_status fl_unet_step(fl_unet u, int nb, const float *x, const float *t, float *y, float lr,
+                       float *loss_host, float *grad_host);
+fl_status fl_unet_pack(fl_unet u, int count, const double *const *r, const double *const *sol, const double *alpha,
+                       int n, float *x, float *t);
+fl_status fl_unet_train(fl_unet u, long count, const float *x, const float *t, int epochs, int batch, float lr,
+                        float lr_final, unsigned long long seed, float *epoch_loss);
+fl_status fl_unet_get_weights(fl_unet u, float *w_host);
+fl_status fl_unet_set_weights(fl_unet u, const float *w_host);
+fl_status fl_unet_apply(fl_unet u, const double *r, int n, double alpha, double *z, void *stream);
+fl_status fl_set_preconditioner(fl_op op, fl_unet net);
+fl_status fl_gemm_test(int M, int N, int K, int kchunk, int fp32_operands, const float *A_host, const float *B_host,
+                       float *C_host);
 
 /* Free the operator and its device workspaces.  NULL is accepted. */
 fl_status fl_op_destroy(fl_op op);

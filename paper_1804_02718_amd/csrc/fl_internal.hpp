@@ -273,6 +273,7 @@ struct fl_op_s {
     size_t sw_bytes = 0;
     double *scal = nullptr;       // device scalars of the solvers
     double *hscal = nullptr;      // pinned host mirror
+    fl_unet net = nullptr;        // learned preconditioner (not owned)
 };
 
 namespace fl {
@@ -313,6 +314,9 @@ fl_status matvec_ctx(const MvCtx<T> &cx, int variant, const T *u, T *y, const Ep
                      hipStream_t s, hipEvent_t *ev = nullptr);
 fl_status build_symbol(fl_op op, hipStream_t s);
 int kernel_p_supported(int P);
+fl_status unet_apply(fl_unet u, const double *r, int n, double alpha, double *z, const double *rr_dev,
+                     hipStream_t s);
+int unet_size(fl_unet u);
 // kernel variants of a matvec: points per thread in the row / strided passes,
 // spectrum tile width, line pairs per row block
 struct VariantDesc {

@@ -433,6 +433,96 @@ static fl_status refine(fl_op op, double s0, double s1, const double *b, double 
     }
 }
 
+// x += a p; rold = r; r -= a kp
+__global__ void k_fpcg_update(double *__restrict__ x, double *__restrict__ r, double *__restrict__ rold,
+                              const double *__restrict__ p, const double *__restrict__ kp, double a, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        x[i] += a * p[i];
+        const double ri = r[i];
+        rold[i] = ri;
+        r[i] = ri - a * kp[i];
+    }
+}
+// p = z + b p
+__global__ void k_fpcg_dir(double *__restrict__ p, const double *__restrict__ z, double b, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        p[i] = z[i] + b * p[i];
+}
+
+// Flexible PCG (Notay's flexible CG with the Polak--Ribiere beta) with the
+// learned preconditioner z = ||r|| Net(r/||r||, alpha).  Falls back to plain
+// FP64 CG from the current iterate when (r, z) <= 0, a scalar is not finite,
+// or the residual stops decreasing.
+static fl_status fpcg(fl_op op, const double *f, double *x, double tol, int max_iter, fl_info *info,
+                      hipStream_t s) {
+    FL_TRY(ensure_workspace(op));
+    Work w = work_of(op);
+    const long M = op->M;
+    double *r = w.r64, *z = w.d64, *p = w.p64, *kp = w.kp64, *rold = w.b64;
+    double bb = 0.0;
+    FL_TRY(dot<double>(op, f, f, w.partA, &bb, s));
+    const double bn = std::sqrt(bb);
+    if (!std::isfinite(bn)) { set_error("right-hand side is not finite"); return FL_E_BREAKDOWN; }
+    if (bn == 0.0) {
+        hipLaunchKernelGGL(k_zero<double>, dim3(ew_grid(M)), dim3(256), 0, s, x, M);
+        FL_HIP_TRY(hipStreamSynchronize(s));
+        return FL_OK;
+    }
+    FL_TRY(residual64(op, f, x, r, 0.0, 1.0, s));
+    double rr = 0.0, rz = 0.0, best = INFINITY;
+    int since_best = 0;
+    bool fallback = false;
+    FL_TRY(dot<double>(op, r, r, w.partA, &rr, s));  // leaves (r,r) in scal[S_DOT]
+    FL_TRY(unet_apply(op->net, r, op->n, op->alpha, z, op->scal + S_DOT, s));
+    FL_TRY(dot<double>(op, r, z, w.partA, &rz, s));
+    if (!(rz > 0.0) || !std::isfinite(rz)) fallback = true;
+    hipLaunchKernelGGL((k_copy_cast<double, double>), dim3(ew_grid(M)), dim3(256), 0, s, p, z, M);
+    int it = 0;
+    info->relres = std::sqrt(rr) / bn;
+    while (!fallback && it < max_iter && info->relres > tol) {
+        FL_TRY(matvec<double>(op, p, kp, s));
+        double pq = 0.0;
+        FL_TRY(dot<double>(op, p, kp, w.partA, &pq, s));
+        const double a = rz / pq;
+        if (!(pq > 0.0) || !std::isfinite(a)) { fallback = true; break; }
+        hipLaunchKernelGGL(k_fpcg_update, dim3(ew_grid(M)), dim3(256), 0, s, x, r, rold, p, kp, a, M);
+        FL_TRY(dot<double>(op, r, r, w.partA, &rr, s));
+        ++it;
+        info->relres = std::sqrt(rr) / bn;
+        if (!std::isfinite(info->relres)) { fallback = true; break; }
+        if (info->relres < 0.5 * best) { best = info->relres; since_best = 0; }
+        else if (++since_best > 50) { fallback = true; break; }
+        if (info->relres <= tol) break;
+        FL_TRY(unet_apply(op->net, r, op->n, op->alpha, z, op->scal + S_DOT, s));
+        double rzn = 0.0, zro = 0.0;
+        FL_TRY(dot<double>(op, r, z, w.partA, &rzn, s));
+        FL_TRY(dot<double>(op, rold, z, w.partA, &zro, s));
+        const double beta = (rzn - zro) / rz;  // Polak--Ribiere: (z, r - r_old) / (r_old, z_old)
+        if (!(rzn > 0.0) || !std::isfinite(beta)) { fallback = true; break; }
+        hipLaunchKernelGGL(k_fpcg_dir, dim3(ew_grid(M)), dim3(256), 0, s, p, z, beta, M);
+        rz = rzn;
+    }
+    info->iters = it;
+    FL_HIP_TRY(hipGetLastError());
+    if (!fallback) {
+        // verify with a fresh FP64 residual
+        FL_TRY(residual64(op, f, x, r, 0.0, 1.0, s));
+        FL_TRY(dot<double>(op, r, r, w.partA, &rr, s));
+        info->relres = std::sqrt(rr) / bn;
+        info->outer_iters = 1;
+        if (info->relres <= tol) return FL_OK;
+        if (it >= max_iter) { set_error("FPCG: no convergence"); return FL_E_NOCONV; }
+    }
+    // plain FP64 CG from the current iterate
+    info->fell_back = 1;
+    fl_info sub{};
+    fl_status st = refine(op, 0.0, 1.0, f, x, tol, true, 0.0, max_iter, 0, &sub, s);
+    info->iters += sub.iters;
+    info->outer_iters += sub.outer_iters;
+    info->relres = sub.relres;
+    return st;
+}
+
 static int default_max_iter(fl_op op) {
     return (int)(50.0 * std::pow((double)op->M, 1.0 / op->d) + 1000.0);
 }
@@ -451,8 +541,8 @@ fl_status fl_poisson_solve_ex(fl_op op, const double *f, double tol, double *u, 
     fl_solve_opts o = {FL_SOLVE_AUTO, 0, 0, 0, 0.0};
     if (opts) o = *opts;
     if (o.solver < FL_SOLVE_AUTO || o.solver > FL_SOLVE_FPCG) { set_error("unknown solver"); return FL_E_INVAL; }
-    if (o.solver == FL_SOLVE_FPCG) {
-        set_error("FPCG needs a preconditioner attached to the operator");
+    if (o.solver == FL_SOLVE_FPCG && (!op->net || op->d != 2 || op->n > unet_size(op->net))) {
+        set_error("FPCG needs a learned preconditioner attached to a 2D operator with n <= its grid size");
         return FL_E_INVAL;
     }
     fl_info local;
@@ -466,10 +556,18 @@ fl_status fl_poisson_solve_ex(fl_op op, const double *f, double tol, double *u, 
     const int max_iter = o.max_iter > 0 ? o.max_iter : default_max_iter(op);
     const bool inner64 = o.solver == FL_SOLVE_CG64;
     const double itol = o.inner_tol > 0.0 ? o.inner_tol : 1e-3;
-    fl_status st = refine(op, 0.0, 1.0, f, u, tol, inner64, itol, max_iter, o.check_every, inf, s);
+    fl_status st = o.solver == FL_SOLVE_FPCG ? fpcg(op, f, u, tol, max_iter, inf, s)
+                                             : refine(op, 0.0, 1.0, f, u, tol, inner64, itol, max_iter,
+                                                      o.check_every, inf, s);
     inf->status = st;
     inf->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return st;
+}
+
+fl_status fl_set_preconditioner(fl_op op, fl_unet net) {
+    if (!op) { set_error("NULL operator"); return FL_E_INVAL; }
+    op->net = net;
+    return FL_OK;
 }
 
 fl_status fl_poisson_solve(fl_op op, const double *f, double tol, double *u, fl_info *info, void *stream) {

@@ -1,0 +1,1000 @@
+// fl_unet.hip -- the learned preconditioner: a small convolutional U-Net with
+// hand-written forward, backward and Adam kernels; the convolutions run as
+// implicit GEMMs on bf16 MFMA (16x16x16) with FP32 accumulation.
+//
+// Network (all 3x3 convolutions bias-free, ReLU after every one but the last):
+//   level 1 @ H x W:      2 -> 16 -> 16            (skip s1)
+//   avg-pool 2x2, level 2 @ H/2: 16 -> 32 -> 32    (skip s2)
+//   avg-pool 2x2, level 3 @ H/4: 32 -> 64 -> 64
+//   nearest up x2, concat s2 (96), 96 -> 32 -> 32 @ H/2
+//   nearest up x2, concat s1 (48), 48 -> 16 -> 16 @ H
+//   1x1 convolution 16 -> 1
+// Input channels: the normalised residual and a constant alpha channel.
+// Activations are NHWC in FP32; GEMM operands are rounded to bf16.
+//
+// GEMM convention (every product below): C[m][n] = sum_k A[m][k] * B[n][k],
+// A and B bf16 with k contiguous ("NT").  Forward conv: A = im2row(X)
+// ([pixel][k], k = (ky*3 + kx)*Cin + ci), B = W ([cout][k]).  Backward data:
+// A = dY ([pixel][cout]), B = W^T ([k][cout]), then a gather col2im.  Weight
+// gradient: A = dY^T ([cout][pixel]), B = im2row(X)^T ([k][pixel]), split
+// over pixels with a fixed-order reduction of the partial products.
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <random>
+#include <type_traits>
+#include <vector>
+
+#include "fl_internal.hpp"
+
+namespace fl {
+
+using bf16 = unsigned short;
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bf16 to_bf16(float f) {
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (bf16)(u >> 16);  // inf / nan kept
+    u += 0x7fffu + ((u >> 16) & 1u);                               // round to nearest even
+    return (bf16)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(bf16 b) { return __uint_as_float(((unsigned)b) << 16); }
+
+// GEMM operand storage: bf16 (production) or fp32 (verification mode)
+template <typename T> __device__ __forceinline__ T to_op(float f);
+template <> __device__ __forceinline__ bf16 to_op<bf16>(float f) { return to_bf16(f); }
+template <> __device__ __forceinline__ float to_op<float>(float f) { return f; }
+template <typename T> __device__ __forceinline__ float op_to_f(T v);
+template <> __device__ __forceinline__ float op_to_f<bf16>(bf16 v) { return from_bf16(v); }
+template <> __device__ __forceinline__ float op_to_f<float>(float v) { return v; }
+
+static inline int cdiv_i(long a, long b) { return (int)((a + b - 1) / b); }
+static inline int grid1(long n) {
+    long g = (n + 255) / 256;
+    return (int)(g > 65535 ? 65535 : (g < 1 ? 1 : g));
+}
+
+// ---------------------------------------------------------------------------
+// NT GEMM on MFMA.  Block 256 threads = 4 waves in a 2 x 2 arrangement, block
+// tile 64 (m) x 64 (n), each wave 32 x 32 = 2 x 2 MFMA tiles of 16 x 16, k in
+// steps of 16.  Lane l = 16 q + r loads A[m0 + r][k0 + 4q .. 4q + 3] and
+// B[n0 + r][k0 + 4q .. 4q + 3].
+//  bf16: one v_mfma_f32_16x16x16_bf16 per tile, whose operand layout is
+//        exactly that (lane (r, q) supplies row r, k = 4q + i);
+//  fp32: four v_mfma_f32_16x16x4_f32, the j-th taking element j of every
+//        lane's 4-vector (lane (r, q) supplies row r, k = 4q + j), so the
+//        four products together cover the 16 k of the step.
+// Result layout of both: lane (r, q) holds D[4q + t][r], t = 0..3.
+// M, N, K multiples of 16 (callers pad).  Split-K: blockIdx.z = split s takes
+// k in [s*kchunk, (s+1)*kchunk) and, with PART, writes its partial product to
+// C + s*M*ldc.  RELU applies max(0, .); ACC adds to C.
+// ---------------------------------------------------------------------------
+template <typename T, bool RELU, bool ACC, bool PART>
+__global__ __launch_bounds__(256) void k_gemm_nt(const T *__restrict__ A, int lda, const T *__restrict__ B, int ldb,
+                                                 float *__restrict__ C, int ldc, int M, int N, int K, int kchunk) {
+    using V = typename std::conditional<sizeof(T) == 2, v4s, v4f>::type;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m0 = blockIdx.x * 64 + (wave & 1) * 32;
+    const int n0 = blockIdx.y * 64 + (wave >> 1) * 32;
+    const int kb = blockIdx.z * kchunk;
+    const int ke = kb + kchunk < K ? kb + kchunk : K;
+    const int r = lane & 15, q = lane >> 4;
+    v4f acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    const bool mv[2] = {m0 < M, m0 + 16 < M};
+    const bool nv[2] = {n0 < N, n0 + 16 < N};
+    if ((mv[0] || mv[1]) && (nv[0] || nv[1])) {
+        const T *ap[2], *bp[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int mm = mv[i] ? m0 + 16 * i + r : r;
+            const int nn = nv[i] ? n0 + 16 * i + r : r;
+            ap[i] = A + (long)mm * lda + 4 * q;
+            bp[i] = B + (long)nn * ldb + 4 * q;
+        }
+        for (int k0 = kb; k0 < ke; k0 += 16) {
+            V a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                a[i] = *(const V *)(ap[i] + k0);
+                b[i] = *(const V *)(bp[i] + k0);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    if constexpr (sizeof(T) == 2) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][e], b[j][e], acc[i][j], 0, 0, 0);
+                    }
+                }
+        }
+    }
+    float *Cb = PART ? C + (long)blockIdx.z * M * ldc : C;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        if (!mv[i]) continue;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            if (!nv[j]) continue;
+            const int col = n0 + 16 * j + r;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int row = m0 + 16 * i + 4 * q + t;
+                float v = acc[i][j][t];
+                float *dst = Cb + (long)row * ldc + col;
+                if (ACC) v += *dst;
+                if (RELU) v = v > 0.f ? v : 0.f;
+                *dst = v;
+            }
+        }
+    }
+}
+
+// C[i] (+)= sum over s of part[s*stride + i], fixed order
+__global__ void k_splitk_reduce(const float *__restrict__ part, int splits, long stride, long count,
+                                float *__restrict__ C, int acc) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x) {
+        float s = acc ? C[i] : 0.f;
+        for (int k = 0; k < splits; ++k) s += part[k * stride + i];
+        C[i] = s;
+    }
+}
+
+template <typename T>
+__global__ void k_cvt(const float *__restrict__ src, long n, T *__restrict__ dst) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        dst[i] = to_op<T>(src[i]);
+}
+
+// im2row: X NHWC fp32 [b][y][x][cin] (channel pitch cs) -> R [pixel][Kp] operands,
+// k = (ky*ks + kx)*cin + ci for a ks x ks window centred on the pixel, zero outside
+template <typename T>
+__global__ void k_im2row(const float *__restrict__ X, int cs, int cin, int H, int W, int nb, int ks,
+                         T *__restrict__ R, int Kp) {
+    const long total = (long)nb * H * W * Kp;
+    const int hk = ks / 2;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+        const int k = (int)(i % Kp);
+        const long p = i / Kp;
+        float v = 0.f;
+        if (k < ks * ks * cin) {
+            const int ci = k % cin, tap = k / cin, kx = tap % ks, ky = tap / ks;
+            const int x = (int)(p % W), y = (int)((p / W) % H);
+            const long b = p / ((long)W * H);
+            const int yy = y + ky - hk, xx = x + kx - hk;
+            if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = X[((b * H + yy) * W + xx) * cs + ci];
+        }
+        R[i] = to_op<T>(v);
+    }
+}
+
+// gather col2im: dX[b][y][x][ci] (+)= sum over taps of G[pixel y - ky + hk, x - kx + hk][k]
+__global__ void k_col2im(const float *__restrict__ G, int Kp, int cin, int H, int W, int nb, int ks,
+                         float *__restrict__ dX, int cs, int acc) {
+    const long total = (long)nb * H * W * cin;
+    const int hk = ks / 2;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+        const int ci = (int)(i % cin);
+        const long p = i / cin;
+        const int x = (int)(p % W), y = (int)((p / W) % H);
+        const long b = p / ((long)W * H);
+        float s = 0.f;
+        for (int ky = 0; ky < ks; ++ky)
+            for (int kx = 0; kx < ks; ++kx) {
+                const int yy = y - ky + hk, xx = x - kx + hk;
+                if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+                s += G[((b * H + yy) * W + xx) * Kp + (ky * ks + kx) * cin + ci];
+            }
+        float *d = dX + p * cs + ci;
+        *d = acc ? *d + s : s;
+    }
+}
+
+// transpose to operands: src [R][C] (row pitch sp, first `cols` columns) -> dst [C][R]
+template <typename S, typename T>
+__global__ void k_transpose_op(const S *__restrict__ src, long rows, int cols, int sp, T *__restrict__ dst) {
+    __shared__ float tile[32][33];
+    const long r0 = (long)blockIdx.x * 32;
+    const int c0 = blockIdx.y * 32;
+    for (int yy = threadIdx.y; yy < 32; yy += blockDim.y) {
+        const long r = r0 + yy;
+        const int c = c0 + threadIdx.x;
+        float v = 0.f;
+        if (r < rows && c < cols) {
+            if constexpr (std::is_same<S, float>::value) v = src[r * sp + c];
+            else v = op_to_f<S>(src[r * sp + c]);
+        }
+        tile[yy][threadIdx.x] = v;
+    }
+    __syncthreads();
+    for (int yy = threadIdx.y; yy < 32; yy += blockDim.y) {
+        const int c = c0 + yy;
+        const long r = r0 + threadIdx.x;
+        if (c < cols && r < rows) dst[(long)c * rows + r] = to_op<T>(tile[threadIdx.x][yy]);
+    }
+}
+
+// dY <- dY * (Y > 0) over the first c channels of pitch cs
+__global__ void k_relu_bwd(float *__restrict__ dY, const float *__restrict__ Y, long pix, int c, int cs) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < pix * c; i += (long)gridDim.x * blockDim.x) {
+        const long p = i / c;
+        const int ch = (int)(i % c);
+        if (!(Y[p * cs + ch] > 0.f)) dY[p * cs + ch] = 0.f;
+    }
+}
+
+// 2x2 average pool, NHWC: Y[b][y][x][c] = mean of X[b][2y+i][2x+j][c]
+__global__ void k_pool_fwd(const float *__restrict__ X, int H, int W, int c, int nb, float *__restrict__ Y) {
+    const int h = H / 2, w = W / 2;
+    const long total = (long)nb * h * w * c;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+        const int ch = (int)(i % c);
+        const long p = i / c;
+        const int x = (int)(p % w), y = (int)((p / w) % h);
+        const long b = p / ((long)w * h);
+        const float *s = X + ((b * H + 2 * y) * W + 2 * x) * c + ch;
+        Y[i] = 0.25f * (s[0] + s[c] + s[(long)W * c] + s[(long)W * c + c]);
+    }
+}
+// dX (+)= 1/4 dY spread over each 2x2 window
+__global__ void k_pool_bwd(const float *__restrict__ dY, int H, int W, int c, int nb, float *__restrict__ dX,
+                           int acc) {
+    const long total = (long)nb * H * W * c;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+        const int ch = (int)(i % c);
+        const long p = i / c;
+        const int x = (int)(p % W), y = (int)((p / W) % H);
+        const long b = p / ((long)W * H);
+        const float g = 0.25f * dY[((b * (H / 2) + y / 2) * (W / 2) + x / 2) * c + ch];
+        dX[i] = acc ? dX[i] + g : g;
+    }
+}
+// nearest x2 upsample of X (h x w, c channels) into channels [0, c) of Y (pitch cs)
+__global__ void k_up_fwd(const float *__restrict__ X, int h, int w, int c, int nb, float *__restrict__ Y, int cs) {
+    const int H = 2 * h, W = 2 * w;
+    const long total = (long)nb * H * W * c;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+        const int ch = (int)(i % c);
+        const long p = i / c;
+        const int x = (int)(p % W), y = (int)((p / W) % H);
+        const long b = p / ((long)W * H);
+        Y[p * cs + ch] = X[((b * h + y / 2) * w + x / 2) * c + ch];
+    }
+}
+// dX = sum of the 2x2 block of dY channels [0, c) (pitch cs)
+__global__ void k_up_bwd(const float *__restrict__ dY, int h, int w, int c, int cs, int nb, float *__restrict__ dX) {
+    const long total = (long)nb * h * w * c;
+    const int W = 2 * w;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+        const int ch = (int)(i % c);
+        const long p = i / c;
+        const int x = (int)(p % w), y = (int)((p / w) % h);
+        const long b = p / ((long)w * h);
+        const float *s = dY + ((b * 2 * h + 2 * y) * W + 2 * x) * cs + ch;
+        dX[i] = s[0] + s[cs] + s[(long)W * cs] + s[(long)W * cs + cs];
+    }
+}
+// copy channels: dst[p][doff + ch] (pitch ds) (+)= src[p][soff + ch] (pitch ss), ch < c
+__global__ void k_copy_ch(const float *__restrict__ src, int ss, int soff, float *__restrict__ dst, int ds, int doff,
+                          long pix, int c, int acc) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < pix * c; i += (long)gridDim.x * blockDim.x) {
+        const long p = i / c;
+        const int ch = (int)(i % c);
+        const float v = src[p * ss + soff + ch];
+        float *d = dst + p * ds + doff + ch;
+        *d = acc ? *d + v : v;
+    }
+}
+
+// per-sample sums of (y - t)^2 and t^2 over channel 0 of y (pitch ys): block b, sample z
+__global__ __launch_bounds__(256) void k_loss_sums(const float *__restrict__ Y, int ys, const float *__restrict__ T,
+                                                   long pix, float *__restrict__ part) {
+    __shared__ double s1[256], s2[256];
+    const int z = blockIdx.y;
+    double a = 0.0, b = 0.0;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < pix; i += (long)gridDim.x * 256) {
+        const double y = Y[(z * pix + i) * ys], t = T[z * pix + i];
+        a += (y - t) * (y - t);
+        b += t * t;
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = b;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) {
+            s1[threadIdx.x] += s1[threadIdx.x + k];
+            s2[threadIdx.x] += s2[threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * (z * gridDim.x + blockIdx.x)] = (float)s1[0];
+        part[2 * (z * gridDim.x + blockIdx.x) + 1] = (float)s2[0];
+    }
+}
+// per-sample totals: tot[2z] = sum (y-t)^2, tot[2z+1] = sum t^2, loss[z] = ratio
+__global__ void k_loss_total(const float *__restrict__ part, int nblk, int nb, float *__restrict__ tot,
+                             float *__restrict__ loss) {
+    const int z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= nb) return;
+    float e = 0.f, t2 = 0.f;
+    for (int k = 0; k < nblk; ++k) {
+        e += part[2 * (z * nblk + k)];
+        t2 += part[2 * (z * nblk + k) + 1];
+    }
+    tot[2 * z] = e;
+    tot[2 * z + 1] = t2;
+    loss[z] = e / t2;
+}
+// gradient of the mean over the batch of the relative squared errors:
+// dY = 2 (y - t) / (sum t^2 * nb) in channel 0, 0 in the other channels
+__global__ void k_loss_grad(const float *__restrict__ Y, int ys, const float *__restrict__ T, long pix, int nb,
+                            const float *__restrict__ tot, float *__restrict__ dY) {
+    const long total = (long)nb * pix * ys;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+        const int ch = (int)(i % ys);
+        const long p = i / ys;
+        dY[i] = ch == 0 ? 2.f * (Y[i] - T[p]) / (tot[2 * (p / pix) + 1] * nb) : 0.f;
+    }
+}
+// squared norm of x[0..n) into out[0] (one block, fixed order)
+__global__ __launch_bounds__(256) void k_sumsq(const double *__restrict__ x, long n, double *__restrict__ out) {
+    __shared__ double sh[256];
+    double a = 0.0;
+    for (long i = threadIdx.x; i < n; i += 256) a += x[i] * x[i];
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// Adam on FP32 master weights; refreshes the operand copies W [cout][Kp] and W^T [Kp][coutp]
+template <typename T>
+__global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v, const float *__restrict__ g,
+                       int cout, int K, int Kp, int coutp, float lr, float b1, float b2, float eps, float c1, float c2,
+                       T *__restrict__ wb, T *__restrict__ wt) {
+    const long total = (long)cout * K;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+        const int co = (int)(i / K), k = (int)(i % K);
+        const long gi = (long)co * Kp + k;
+        if (lr > 0.f) {
+            const float gg = g[gi];
+            const float mm = b1 * m[i] + (1.f - b1) * gg;
+            const float vv = b2 * v[i] + (1.f - b2) * gg * gg;
+            m[i] = mm;
+            v[i] = vv;
+            w[i] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+        }
+        const T b = to_op<T>(w[i]);
+        wb[(long)co * Kp + k] = b;
+        wt[(long)k * coutp + co] = b;
+    }
+}
+
+// network input from a residual: channel 0 = scale * r at the interior n x n
+// (zero in the padding), channel 1 = alpha; scale = 1 / ||r|| from `nrm`
+__global__ void k_net_input(const double *__restrict__ r, int n, int H, int W, float alpha, const double *nrm,
+                            float *__restrict__ X) {
+    const double s = (nrm && nrm[0] > 0.0) ? 1.0 / sqrt(nrm[0]) : 1.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)H * W; i += (long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % W), y = (int)(i / W);
+        X[2 * i] = (x < n && y < n) ? (float)(s * r[(long)y * n + x]) : 0.f;
+        X[2 * i + 1] = alpha;
+    }
+}
+// z = ||r|| * y (channel 0, pitch ys) at the interior
+__global__ void k_net_output(const float *__restrict__ Y, int ys, int n, int W, const double *nrm,
+                             double *__restrict__ z) {
+    const double s = (nrm && nrm[0] > 0.0) ? sqrt(nrm[0]) : 1.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)n * n; i += (long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % n), y = (int)(i / n);
+        z[i] = s * (double)Y[((long)y * W + x) * ys];
+    }
+}
+
+// training sample from a (residual, solution) pair: x = (r / ||r||, alpha) and
+// t = sol / ||r|| on the top-left n x n of the H x W grid, zero elsewhere
+__global__ void k_pack_sample(const double *__restrict__ r, const double *__restrict__ sol, int n, int H, int W,
+                              float alpha, const double *nrm, float *__restrict__ X, float *__restrict__ T) {
+    const double s = nrm[0] > 0.0 ? 1.0 / sqrt(nrm[0]) : 1.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)H * W; i += (long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % W), y = (int)(i / W);
+        const bool in = x < n && y < n;
+        X[2 * i] = in ? (float)(s * r[(long)y * n + x]) : 0.f;
+        X[2 * i + 1] = alpha;
+        if (T) T[i] = in && sol ? (float)(s * sol[(long)y * n + x]) : 0.f;
+    }
+}
+// minibatch gather: dst[j] = src[idx[j]] for blocks of `len` floats
+__global__ void k_gather(const float *__restrict__ src, const long *__restrict__ idx, int nb, long len,
+                         float *__restrict__ dst) {
+    const long total = (long)nb * len;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+        const long j = i / len, e = i % len;
+        dst[i] = src[idx[j] * len + e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct Conv {
+    int cin, cout, ks, K, Kp, coutp;   // K = ks*ks*cin, Kp padded to 16, coutp padded to 16
+    long woff;                          // offset of this layer in the parameter arrays
+};
+
+}  // namespace fl
+
+struct fl_unet_s {
+    int H = 0, W = 0, nb = 0;           // image size, batch capacity
+    std::vector<fl::Conv> conv;         // 11 layers
+    long nparam = 0;                    // sum cout*K
+    long nparam_pad = 0;                // sum cout*Kp (gradient layout)
+    int fp32 = 0;                       // GEMM operands in fp32 (verification mode) instead of bf16
+    size_t osz = 2;                     // bytes per GEMM operand
+    float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;  // fp32 master, Adam, gradient (padded)
+    void *wb = nullptr, *wt = nullptr;                             // operand copies W, W^T
+    long wb_len = 0, wt_len = 0;
+    std::vector<long> wb_off, wt_off;
+    int step = 0;
+    // activations and gradients (fp32 NHWC, batch nb)
+    float *act = nullptr;
+    size_t act_bytes = 0;
+    std::vector<float *> A, G;          // per tensor
+    void *rowbuf = nullptr, *tbuf = nullptr, *tbuf2 = nullptr;        // operand staging
+    float *colbuf = nullptr, *part = nullptr, *lossbuf = nullptr, *lpart = nullptr, *ltot = nullptr;
+    size_t row_elems = 0, col_elems = 0, part_elems = 0;
+    double *nrm = nullptr;
+    long *idx = nullptr;                // minibatch indices (device)
+    hipStream_t s = nullptr;
+};
+
+namespace fl {
+
+// tensor ids
+enum {
+    T_X0, T_A1, T_S1, T_P1, T_A2, T_S2, T_P2, T_A3, T_B3, T_C2, T_A4, T_B4, T_C1, T_A5, T_B5, T_Y, T_TGT, T_COUNT
+};
+
+struct TShape {
+    int h, c;  // side length (h = H, H/2, H/4) and channels
+};
+
+static TShape tshape(const fl_unet_s *u, int t) {
+    const int H = u->H;
+    switch (t) {
+        case T_X0: return {H, 2};
+        case T_A1: case T_S1: case T_A5: case T_B5: return {H, 16};
+        case T_P1: return {H / 2, 16};
+        case T_A2: case T_S2: case T_A4: case T_B4: return {H / 2, 32};
+        case T_P2: return {H / 4, 32};
+        case T_A3: case T_B3: return {H / 4, 64};
+        case T_C2: return {H / 2, 96};
+        case T_C1: return {H, 48};
+        case T_Y: return {H, 16};
+        case T_TGT: return {H, 1};
+    }
+    return {0, 0};
+}
+
+template <typename T>
+static void launch_gemm(bool relu, bool acc, const T *A, int lda, const T *B, int ldb, float *C, int ldc, int M, int N,
+                        int K, hipStream_t s) {
+    dim3 g(cdiv_i(M, 64), cdiv_i(N, 64), 1);
+    if (relu)
+        hipLaunchKernelGGL((k_gemm_nt<T, true, false, false>), g, dim3(256), 0, s, A, lda, B, ldb, C, ldc, M, N, K, K);
+    else if (acc)
+        hipLaunchKernelGGL((k_gemm_nt<T, false, true, false>), g, dim3(256), 0, s, A, lda, B, ldb, C, ldc, M, N, K, K);
+    else
+        hipLaunchKernelGGL((k_gemm_nt<T, false, false, false>), g, dim3(256), 0, s, A, lda, B, ldb, C, ldc, M, N, K, K);
+}
+template <typename T> static T *wb_of(fl_unet u, int li) { return (T *)u->wb + u->wb_off[li]; }
+template <typename T> static T *wt_of(fl_unet u, int li) { return (T *)u->wt + u->wt_off[li]; }
+
+// conv forward: Y[pix][cout] (pitch coutp) = relu?(im2row(X) W^T)
+template <typename T>
+static void conv_fwd(fl_unet u, int li, const float *X, int xcs, int h, int nb, float *Y, bool relu) {
+    const Conv &c = u->conv[li];
+    const long pix = (long)nb * h * h;
+    T *row = (T *)u->rowbuf;
+    hipLaunchKernelGGL(k_im2row<T>, dim3(grid1(pix * c.Kp)), dim3(256), 0, u->s, X, xcs, c.cin, h, h, nb, c.ks, row,
+                       c.Kp);
+    launch_gemm<T>(relu, false, row, c.Kp, wb_of<T>(u, li), c.Kp, Y, c.coutp, (int)pix, c.coutp, c.Kp, u->s);
+}
+
+// conv backward: dY (pitch coutp, already masked by the ReLU) -> gradient of the
+// weights (into u->g) and, if dX, the input gradient (+= when accx)
+template <typename T>
+static void conv_bwd(fl_unet u, int li, const float *X, int xcs, int h, int nb, const float *dY, float *dX, int dxcs,
+                     bool accx) {
+    const Conv &c = u->conv[li];
+    const long pix = (long)nb * h * h;
+    hipStream_t s = u->s;
+    T *row = (T *)u->rowbuf, *tb = (T *)u->tbuf, *tb2 = (T *)u->tbuf2;
+    // weight gradient: dW[cout][k] = sum_pix dY[pix][cout] R[pix][k]
+    hipLaunchKernelGGL(k_im2row<T>, dim3(grid1(pix * c.Kp)), dim3(256), 0, s, X, xcs, c.cin, h, h, nb, c.ks, row, c.Kp);
+    hipLaunchKernelGGL((k_transpose_op<T, T>), dim3(cdiv_i(pix, 32), cdiv_i(c.Kp, 32)), dim3(32, 8), 0, s, row, pix,
+                       c.Kp, c.Kp, tb);  // [Kp][pix]
+    hipLaunchKernelGGL((k_transpose_op<float, T>), dim3(cdiv_i(pix, 32), cdiv_i(c.coutp, 32)), dim3(32, 8), 0, s, dY,
+                       pix, c.coutp, c.coutp, tb2);  // [coutp][pix]
+    const int kchunk = 2048;
+    const int splits = cdiv_i(pix, kchunk);
+    dim3 g(cdiv_i(c.coutp, 64), cdiv_i(c.Kp, 64), splits);
+    hipLaunchKernelGGL((k_gemm_nt<T, false, false, true>), g, dim3(256), 0, s, tb2, (int)pix, tb, (int)pix, u->part,
+                       c.Kp, c.coutp, c.Kp, (int)pix, kchunk);
+    // partial products are [coutp][Kp]; the first cout rows are the real gradient
+    hipLaunchKernelGGL(k_splitk_reduce, dim3(grid1((long)c.cout * c.Kp)), dim3(256), 0, s, u->part, splits,
+                       (long)c.coutp * c.Kp, (long)c.cout * c.Kp, u->g + u->wb_off[li], 0);
+    if (!dX) return;
+    // input gradient: G[pix][k] = sum_cout dY[pix][cout] W[cout][k], then col2im
+    hipLaunchKernelGGL(k_cvt<T>, dim3(grid1(pix * c.coutp)), dim3(256), 0, s, dY, pix * c.coutp, tb);
+    launch_gemm<T>(false, false, tb, c.coutp, wt_of<T>(u, li), c.coutp, u->colbuf, c.Kp, (int)pix, c.Kp, c.coutp, s);
+    hipLaunchKernelGGL(k_col2im, dim3(grid1(pix * c.cin)), dim3(256), 0, s, u->colbuf, c.Kp, c.cin, h, h, nb, c.ks,
+                       dX, dxcs, accx ? 1 : 0);
+}
+
+template <typename T>
+static void net_forward_t(fl_unet u, int nb) {
+    const int H = u->H;
+    auto *A = u->A.data();
+    hipStream_t s = u->s;
+    conv_fwd<T>(u, 0, A[T_X0], 2, H, nb, A[T_A1], true);
+    conv_fwd<T>(u, 1, A[T_A1], 16, H, nb, A[T_S1], true);
+    hipLaunchKernelGGL(k_pool_fwd, dim3(grid1((long)nb * H * H / 4 * 16)), dim3(256), 0, s, A[T_S1], H, H, 16, nb,
+                       A[T_P1]);
+    conv_fwd<T>(u, 2, A[T_P1], 16, H / 2, nb, A[T_A2], true);
+    conv_fwd<T>(u, 3, A[T_A2], 32, H / 2, nb, A[T_S2], true);
+    hipLaunchKernelGGL(k_pool_fwd, dim3(grid1((long)nb * H * H / 16 * 32)), dim3(256), 0, s, A[T_S2], H / 2, H / 2, 32,
+                       nb, A[T_P2]);
+    conv_fwd<T>(u, 4, A[T_P2], 32, H / 4, nb, A[T_A3], true);
+    conv_fwd<T>(u, 5, A[T_A3], 64, H / 4, nb, A[T_B3], true);
+    const long p2 = (long)nb * (H / 2) * (H / 2), p1 = (long)nb * H * H;
+    hipLaunchKernelGGL(k_up_fwd, dim3(grid1(p2 * 64)), dim3(256), 0, s, A[T_B3], H / 4, H / 4, 64, nb, A[T_C2], 96);
+    hipLaunchKernelGGL(k_copy_ch, dim3(grid1(p2 * 32)), dim3(256), 0, s, A[T_S2], 32, 0, A[T_C2], 96, 64, p2, 32, 0);
+    conv_fwd<T>(u, 6, A[T_C2], 96, H / 2, nb, A[T_A4], true);
+    conv_fwd<T>(u, 7, A[T_A4], 32, H / 2, nb, A[T_B4], true);
+    hipLaunchKernelGGL(k_up_fwd, dim3(grid1(p1 * 32)), dim3(256), 0, s, A[T_B4], H / 2, H / 2, 32, nb, A[T_C1], 48);
+    hipLaunchKernelGGL(k_copy_ch, dim3(grid1(p1 * 16)), dim3(256), 0, s, A[T_S1], 16, 0, A[T_C1], 48, 32, p1, 16, 0);
+    conv_fwd<T>(u, 8, A[T_C1], 48, H, nb, A[T_A5], true);
+    conv_fwd<T>(u, 9, A[T_A5], 16, H, nb, A[T_B5], true);
+    conv_fwd<T>(u, 10, A[T_B5], 16, H, nb, A[T_Y], false);
+}
+
+// gradients of every weight from dY (in G[T_Y], pitch 16)
+template <typename T>
+static void net_backward_t(fl_unet u, int nb) {
+    const int H = u->H;
+    auto *A = u->A.data();
+    auto *G = u->G.data();
+    hipStream_t s = u->s;
+    const long p1 = (long)nb * H * H, p2 = p1 / 4, p3 = p1 / 16;
+    conv_bwd<T>(u, 10, A[T_B5], 16, H, nb, G[T_Y], G[T_B5], 16, false);
+    hipLaunchKernelGGL(k_relu_bwd, dim3(grid1(p1 * 16)), dim3(256), 0, s, G[T_B5], A[T_B5], p1, 16, 16);
+    conv_bwd<T>(u, 9, A[T_A5], 16, H, nb, G[T_B5], G[T_A5], 16, false);
+    hipLaunchKernelGGL(k_relu_bwd, dim3(grid1(p1 * 16)), dim3(256), 0, s, G[T_A5], A[T_A5], p1, 16, 16);
+    conv_bwd<T>(u, 8, A[T_C1], 48, H, nb, G[T_A5], G[T_C1], 48, false);
+    // concat 1: channels [0,32) from up(B4), [32,48) to S1
+    hipLaunchKernelGGL(k_up_bwd, dim3(grid1(p2 * 32)), dim3(256), 0, s, G[T_C1], H / 2, H / 2, 32, 48, nb, G[T_B4]);
+    hipLaunchKernelGGL(k_copy_ch, dim3(grid1(p1 * 16)), dim3(256), 0, s, G[T_C1], 48, 32, G[T_S1], 16, 0, p1, 16, 0);
+    hipLaunchKernelGGL(k_relu_bwd, dim3(grid1(p2 * 32)), dim3(256), 0, s, G[T_B4], A[T_B4], p2, 32, 32);
+    conv_bwd<T>(u, 7, A[T_A4], 32, H / 2, nb, G[T_B4], G[T_A4], 32, false);
+    hipLaunchKernelGGL(k_relu_bwd, dim3(grid1(p2 * 32)), dim3(256), 0, s, G[T_A4], A[T_A4], p2, 32, 32);
+    conv_bwd<T>(u, 6, A[T_C2], 96, H / 2, nb, G[T_A4], G[T_C2], 96, false);
+    hipLaunchKernelGGL(k_up_bwd, dim3(grid1(p3 * 64)), dim3(256), 0, s, G[T_C2], H / 4, H / 4, 64, 96, nb, G[T_B3]);
+    hipLaunchKernelGGL(k_copy_ch, dim3(grid1(p2 * 32)), dim3(256), 0, s, G[T_C2], 96, 64, G[T_S2], 32, 0, p2, 32, 0);
+    hipLaunchKernelGGL(k_relu_bwd, dim3(grid1(p3 * 64)), dim3(256), 0, s, G[T_B3], A[T_B3], p3, 64, 64);
+    conv_bwd<T>(u, 5, A[T_A3], 64, H / 4, nb, G[T_B3], G[T_A3], 64, false);
+    hipLaunchKernelGGL(k_relu_bwd, dim3(grid1(p3 * 64)), dim3(256), 0, s, G[T_A3], A[T_A3], p3, 64, 64);
+    conv_bwd<T>(u, 4, A[T_P2], 32, H / 4, nb, G[T_A3], G[T_P2], 32, false);
+    // pool 2 feeds S2, which also went to concat 2
+    hipLaunchKernelGGL(k_pool_bwd, dim3(grid1(p2 * 32)), dim3(256), 0, s, G[T_P2], H / 2, H / 2, 32, nb, G[T_S2], 1);
+    hipLaunchKernelGGL(k_relu_bwd, dim3(grid1(p2 * 32)), dim3(256), 0, s, G[T_S2], A[T_S2], p2, 32, 32);
+    conv_bwd<T>(u, 3, A[T_A2], 32, H / 2, nb, G[T_S2], G[T_A2], 32, false);
+    hipLaunchKernelGGL(k_relu_bwd, dim3(grid1(p2 * 32)), dim3(256), 0, s, G[T_A2], A[T_A2], p2, 32, 32);
+    conv_bwd<T>(u, 2, A[T_P1], 16, H / 2, nb, G[T_A2], G[T_P1], 16, false);
+    hipLaunchKernelGGL(k_pool_bwd, dim3(grid1(p1 * 16)), dim3(256), 0, s, G[T_P1], H, H, 16, nb, G[T_S1], 1);
+    hipLaunchKernelGGL(k_relu_bwd, dim3(grid1(p1 * 16)), dim3(256), 0, s, G[T_S1], A[T_S1], p1, 16, 16);
+    conv_bwd<T>(u, 1, A[T_A1], 16, H, nb, G[T_S1], G[T_A1], 16, false);
+    hipLaunchKernelGGL(k_relu_bwd, dim3(grid1(p1 * 16)), dim3(256), 0, s, G[T_A1], A[T_A1], p1, 16, 16);
+    conv_bwd<T>(u, 0, A[T_X0], 2, H, nb, G[T_A1], nullptr, 0, false);
+}
+
+template <typename T>
+static void refresh_t(fl_unet u, float lr) {
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - powf(b1, (float)u->step), c2 = 1.f - powf(b2, (float)u->step);
+    long off = 0;
+    for (size_t li = 0; li < u->conv.size(); ++li) {
+        const Conv &c = u->conv[li];
+        const long n = (long)c.cout * c.K;
+        hipLaunchKernelGGL(k_adam<T>, dim3(grid1(n)), dim3(256), 0, u->s, u->w + off, u->m + off, u->v + off,
+                           u->g + u->wb_off[li], c.cout, c.K, c.Kp, c.coutp, lr, b1, b2, 1e-8f,
+                           c1 > 0.f ? c1 : 1.f, c2 > 0.f ? c2 : 1.f, wb_of<T>(u, li), wt_of<T>(u, li));
+        off += n;
+    }
+}
+static void net_forward(fl_unet u, int nb) {
+    if (u->fp32) net_forward_t<float>(u, nb);
+    else net_forward_t<bf16>(u, nb);
+}
+static void net_backward(fl_unet u, int nb) {
+    if (u->fp32) net_backward_t<float>(u, nb);
+    else net_backward_t<bf16>(u, nb);
+}
+static void refresh_bf16(fl_unet u, float lr) {
+    if (u->fp32) refresh_t<float>(u, lr);
+    else refresh_t<bf16>(u, lr);
+}
+
+// forward on A[T_X0] (nb samples); with targets in A[T_TGT]: loss, backward and,
+// for lr > 0, one Adam step
+static void train_step(fl_unet u, int nb, bool with_target, float lr) {
+    const long pix = (long)u->H * u->W;
+    hipStream_t s = u->s;
+    net_forward(u, nb);
+    if (!with_target) return;
+    const int nblk = 64;
+    hipLaunchKernelGGL(k_loss_sums, dim3(nblk, nb), dim3(256), 0, s, u->A[T_Y], 16, u->A[T_TGT], pix, u->lpart);
+    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, s, u->lpart, nblk, nb, u->ltot, u->lossbuf);
+    hipLaunchKernelGGL(k_loss_grad, dim3(grid1(nb * pix * 16)), dim3(256), 0, s, u->A[T_Y], 16, u->A[T_TGT], pix, nb,
+                       u->ltot, u->G[T_Y]);
+    net_backward(u, nb);
+    if (lr > 0.f) {
+        u->step += 1;
+        refresh_bf16(u, lr);
+    }
+}
+
+}  // namespace fl
+
+using namespace fl;
+
+extern "C" {
+
+fl_status fl_unet_create(int H, int max_batch, unsigned long long seed, int fp32_operands, fl_unet *out) {
+    if (!out || H < 16 || H % 16 != 0 || H > 2048 || max_batch < 1 || max_batch > 256) {
+        set_error("fl_unet_create: H must be a multiple of 16 in [16, 2048] and max_batch in [1, 256]");
+        return FL_E_INVAL;
+    }
+    fl_unet u = new (std::nothrow) fl_unet_s();
+    if (!u) return FL_E_NOMEM;
+    u->H = u->W = H;
+    u->nb = max_batch;
+    u->fp32 = fp32_operands ? 1 : 0;
+    u->osz = u->fp32 ? sizeof(float) : sizeof(bf16);
+    const int spec[11][3] = {{2, 16, 3},  {16, 16, 3}, {16, 32, 3}, {32, 32, 3}, {32, 64, 3}, {64, 64, 3},
+                             {96, 32, 3}, {32, 32, 3}, {48, 16, 3}, {16, 16, 3}, {16, 1, 1}};
+    long wbo = 0, wto = 0;
+    for (auto &sp : spec) {
+        Conv c;
+        c.cin = sp[0];
+        c.cout = sp[1];
+        c.ks = sp[2];
+        c.K = c.ks * c.ks * c.cin;
+        c.Kp = (c.K + 15) / 16 * 16;
+        c.coutp = (c.cout + 15) / 16 * 16;
+        c.woff = u->nparam;
+        u->nparam += (long)c.cout * c.K;
+        u->wb_off.push_back(wbo);
+        u->wt_off.push_back(wto);
+        wbo += (long)c.coutp * c.Kp;
+        wto += (long)c.Kp * c.coutp;
+        u->conv.push_back(c);
+    }
+    u->wb_len = wbo;
+    u->wt_len = wto;
+    // He-style initialisation (seeded, host), kept in FP32 master copies
+    std::vector<float> w(u->nparam);
+    std::mt19937_64 rng(seed);
+    for (auto &c : u->conv) {
+        std::normal_distribution<float> nd(0.f, sqrtf(2.f / (float)c.K) * (c.ks == 1 ? 0.5f : 1.f));
+        for (long i = 0; i < (long)c.cout * c.K; ++i) w[c.woff + i] = nd(rng);
+    }
+    // activations
+    const long p1 = (long)max_batch * H * H;
+    size_t total = 0;
+    std::vector<size_t> sizes(T_COUNT);
+    for (int t = 0; t < T_COUNT; ++t) {
+        TShape sh = tshape(u, t);
+        sizes[t] = (size_t)max_batch * sh.h * sh.h * sh.c;
+        total += sizes[t];
+    }
+    u->act_bytes = sizeof(float) * total * 2;
+    size_t maxrow = 0, maxcol = 0, maxpart = 0;
+    for (size_t li = 0; li < u->conv.size(); ++li) {
+        const int h = li < 2 || li >= 8 ? H : (li < 4 || (li >= 6 && li < 8) ? H / 2 : H / 4);
+        const long pix = (long)max_batch * h * h;
+        const Conv &c = u->conv[li];
+        maxrow = std::max(maxrow, (size_t)(pix * c.Kp));
+        maxcol = std::max(maxcol, (size_t)(pix * c.Kp));
+        maxpart = std::max(maxpart, (size_t)(cdiv_i(pix, 2048)) * c.coutp * c.Kp);
+    }
+    u->row_elems = maxrow;
+    u->col_elems = maxcol;
+    u->part_elems = maxpart;
+    hipError_t e = hipSuccess;
+    auto AL = [&](void **p, size_t b) {
+        if (e == hipSuccess) e = hipMalloc(p, b);
+    };
+    AL((void **)&u->w, sizeof(float) * u->nparam);
+    AL((void **)&u->m, sizeof(float) * u->nparam);
+    AL((void **)&u->v, sizeof(float) * u->nparam);
+    AL((void **)&u->g, sizeof(float) * u->wb_len);
+    AL(&u->wb, u->osz * u->wb_len);
+    AL(&u->wt, u->osz * u->wt_len);
+    AL((void **)&u->act, u->act_bytes);
+    AL(&u->rowbuf, u->osz * maxrow);
+    AL(&u->tbuf, u->osz * std::max(maxrow, (size_t)p1 * 16));
+    AL(&u->tbuf2, u->osz * (size_t)p1 * 64);
+    AL((void **)&u->colbuf, sizeof(float) * maxcol);
+    AL((void **)&u->part, sizeof(float) * maxpart);
+    AL((void **)&u->lossbuf, sizeof(float) * max_batch);
+    AL((void **)&u->lpart, sizeof(float) * 2 * 64 * max_batch);
+    AL((void **)&u->ltot, sizeof(float) * 2 * max_batch);
+    AL((void **)&u->nrm, sizeof(double) * 8);
+    AL((void **)&u->idx, sizeof(long) * max_batch);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&u->s, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        set_error("fl_unet_create: %s", hipGetErrorString(e));
+        fl_unet_destroy(u);
+        return FL_E_NOMEM;
+    }
+    float *base = u->act;
+    for (int t = 0; t < T_COUNT; ++t) {
+        u->A.push_back(base);
+        base += sizes[t];
+    }
+    for (int t = 0; t < T_COUNT; ++t) {
+        u->G.push_back(base);
+        base += sizes[t];
+    }
+    if (hipMemcpy(u->w, w.data(), sizeof(float) * u->nparam, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemsetAsync(u->m, 0, sizeof(float) * u->nparam, u->s) != hipSuccess ||
+        hipMemsetAsync(u->v, 0, sizeof(float) * u->nparam, u->s) != hipSuccess ||
+        hipMemsetAsync(u->g, 0, sizeof(float) * u->wb_len, u->s) != hipSuccess ||
+        hipMemsetAsync(u->wb, 0, u->osz * u->wb_len, u->s) != hipSuccess ||
+        hipMemsetAsync(u->wt, 0, u->osz * u->wt_len, u->s) != hipSuccess ||
+        hipMemsetAsync(u->act, 0, u->act_bytes, u->s) != hipSuccess) {
+        fl_unet_destroy(u);
+        set_error("fl_unet_create: initialisation failed");
+        return FL_E_DEVICE;
+    }
+    refresh_bf16(u, 0.f);
+    if (hipStreamSynchronize(u->s) != hipSuccess) {
+        fl_unet_destroy(u);
+        return FL_E_DEVICE;
+    }
+    *out = u;
+    return FL_OK;
+}
+
+fl_status fl_unet_destroy(fl_unet u) {
+    if (!u) return FL_OK;
+    for (void *p : {(void *)u->w, (void *)u->m, (void *)u->v, (void *)u->g, (void *)u->wb, (void *)u->wt,
+                    (void *)u->act, (void *)u->rowbuf, (void *)u->tbuf, (void *)u->tbuf2, (void *)u->colbuf,
+                    (void *)u->part, (void *)u->lossbuf, (void *)u->lpart, (void *)u->ltot, (void *)u->nrm, (void *)u->idx})
+        if (p) (void)hipFree(p);
+    if (u->s) (void)hipStreamDestroy(u->s);
+    delete u;
+    return FL_OK;
+}
+
+fl_status fl_unet_num_params(fl_unet u, long long *n) {
+    if (!u || !n) return FL_E_INVAL;
+    *n = u->nparam;
+    return FL_OK;
+}
+
+// weights (fp32 master, layer by layer, each [cout][K] with k = (ky*ks + kx)*cin + ci)
+fl_status fl_unet_get_weights(fl_unet u, float *w_host) {
+    if (!u || !w_host) return FL_E_INVAL;
+    FL_HIP_TRY(hipStreamSynchronize(u->s));
+    FL_HIP_TRY(hipMemcpy(w_host, u->w, sizeof(float) * u->nparam, hipMemcpyDeviceToHost));
+    return FL_OK;
+}
+
+fl_status fl_unet_set_weights(fl_unet u, const float *w_host) {
+    if (!u || !w_host) return FL_E_INVAL;
+    FL_HIP_TRY(hipStreamSynchronize(u->s));
+    FL_HIP_TRY(hipMemcpy(u->w, w_host, sizeof(float) * u->nparam, hipMemcpyHostToDevice));
+    refresh_bf16(u, 0.f);
+    FL_HIP_TRY(hipStreamSynchronize(u->s));
+    return FL_OK;
+}
+
+// forward (and optionally backward) on nb samples: x [nb][H][W][2] fp32 NHWC
+// device input, y out [nb][H][W] (channel 0), t (may be NULL) targets
+// [nb][H][W]; with t: loss per sample to loss_host (may be NULL) and weight
+// gradients (fp32, layer by layer as the weights) to grad_host (may be NULL);
+// lr > 0 additionally takes one Adam step.
+fl_status fl_unet_step(fl_unet u, int nb, const float *x, const float *t, float *y, float lr, float *loss_host,
+                       float *grad_host) {
+    if (!u || !x || nb < 1 || nb > u->nb) { set_error("fl_unet_step: bad argument"); return FL_E_INVAL; }
+    const int H = u->H;
+    const long pix = (long)H * H;
+    hipStream_t s = u->s;
+    FL_HIP_TRY(hipMemcpyAsync(u->A[T_X0], x, sizeof(float) * nb * pix * 2, hipMemcpyDeviceToDevice, s));
+    if (t) FL_HIP_TRY(hipMemcpyAsync(u->A[T_TGT], t, sizeof(float) * nb * pix, hipMemcpyDeviceToDevice, s));
+    train_step(u, nb, t != nullptr, lr);
+    if (y)
+        hipLaunchKernelGGL(k_copy_ch, dim3(grid1(nb * pix)), dim3(256), 0, s, u->A[T_Y], 16, 0, y, 1, 0, nb * pix, 1, 0);
+    FL_HIP_TRY(hipGetLastError());
+    FL_HIP_TRY(hipStreamSynchronize(s));
+    if (t && loss_host) FL_HIP_TRY(hipMemcpy(loss_host, u->lossbuf, sizeof(float) * nb, hipMemcpyDeviceToHost));
+    if (t && grad_host) {
+        std::vector<float> gp(u->wb_len);
+        FL_HIP_TRY(hipMemcpy(gp.data(), u->g, sizeof(float) * u->wb_len, hipMemcpyDeviceToHost));
+        for (size_t li = 0; li < u->conv.size(); ++li) {
+            const Conv &c = u->conv[li];
+            for (int co = 0; co < c.cout; ++co)
+                for (int k = 0; k < c.K; ++k) grad_host[c.woff + (long)co * c.K + k] = gp[u->wb_off[li] + (long)co * c.Kp + k];
+        }
+    }
+    return FL_OK;
+}
+
+fl_status fl_unet_pack(fl_unet u, int count, const double *const *r, const double *const *sol, const double *alpha,
+                       int n, float *x, float *t) {
+    if (!u || count < 0 || (count > 0 && (!r || !alpha || !x)) || n < 1 || n > u->H) {
+        set_error("fl_unet_pack: bad argument");
+        return FL_E_INVAL;
+    }
+    const long pix = (long)u->H * u->W;
+    for (int z = 0; z < count; ++z) {
+        if (!r[z]) { set_error("fl_unet_pack: NULL residual"); return FL_E_INVAL; }
+        hipLaunchKernelGGL(k_sumsq, dim3(1), dim3(256), 0, u->s, r[z], (long)n * n, u->nrm);
+        hipLaunchKernelGGL(k_pack_sample, dim3(grid1(pix)), dim3(256), 0, u->s, r[z], sol ? sol[z] : nullptr, n, u->H,
+                           u->W, (float)alpha[z], u->nrm, x + z * pix * 2, t ? t + z * pix : nullptr);
+    }
+    FL_HIP_TRY(hipGetLastError());
+    FL_HIP_TRY(hipStreamSynchronize(u->s));
+    return FL_OK;
+}
+
+fl_status fl_unet_train(fl_unet u, long count, const float *x, const float *t, int epochs, int batch, float lr,
+                        float lr_final, unsigned long long seed, float *epoch_loss) {
+    if (!u || !x || !t || count < 1 || epochs < 1 || batch < 1 || batch > u->nb || !(lr > 0.f) || lr_final < 0.f) {
+        set_error("fl_unet_train: bad argument");
+        return FL_E_INVAL;
+    }
+    const long pix = (long)u->H * u->W;
+    const long steps_per_epoch = count / batch;  // the ragged remainder of a shuffled epoch is dropped
+    if (steps_per_epoch < 1) { set_error("fl_unet_train: fewer samples than one batch"); return FL_E_INVAL; }
+    std::mt19937_64 rng(seed);
+    std::vector<long> order(count);
+    std::vector<float> lossh(batch);
+    const long total_steps = steps_per_epoch * epochs;
+    long done = 0;
+    for (int e = 0; e < epochs; ++e) {
+        for (long i = 0; i < count; ++i) order[i] = i;
+        for (long i = count - 1; i > 0; --i) std::swap(order[i], order[(long)(rng() % (unsigned long long)(i + 1))]);
+        double acc = 0.0;
+        for (long b = 0; b < steps_per_epoch; ++b, ++done) {
+            // cosine decay from lr to lr_final over all steps
+            const double ph = (double)done / (double)total_steps;
+            const float lr_k = (float)(lr_final + 0.5 * (lr - lr_final) * (1.0 + std::cos(M_PI * ph)));
+            FL_HIP_TRY(hipMemcpyAsync(u->idx, order.data() + b * batch, sizeof(long) * batch, hipMemcpyHostToDevice,
+                                      u->s));
+            hipLaunchKernelGGL(k_gather, dim3(grid1(batch * pix * 2)), dim3(256), 0, u->s, x, u->idx, batch, pix * 2,
+                               u->A[T_X0]);
+            hipLaunchKernelGGL(k_gather, dim3(grid1(batch * pix)), dim3(256), 0, u->s, t, u->idx, batch, pix,
+                               u->A[T_TGT]);
+            train_step(u, batch, true, lr_k);
+            FL_HIP_TRY(hipMemcpyAsync(lossh.data(), u->lossbuf, sizeof(float) * batch, hipMemcpyDeviceToHost, u->s));
+            FL_HIP_TRY(hipStreamSynchronize(u->s));
+            for (int z = 0; z < batch; ++z) acc += lossh[z];
+        }
+        if (epoch_loss) epoch_loss[e] = (float)(acc / (double)(steps_per_epoch * batch));
+        if (!std::isfinite(acc)) { set_error("fl_unet_train: loss is not finite"); return FL_E_BREAKDOWN; }
+    }
+    FL_HIP_TRY(hipGetLastError());
+    return FL_OK;
+}
+
+}  // extern "C"
+
+namespace fl {
+int unet_size(fl_unet u) { return u->H; }
+// z = ||r|| * Net(r / ||r||, alpha) on the stream s (r, z: n x n, n <= H); the
+// squared norm of r is computed into u->nrm first.  Used inside flexible PCG.
+fl_status unet_apply(fl_unet u, const double *r, int n, double alpha, double *z, const double *rr_dev,
+                     hipStream_t s) {
+    const int H = u->H;
+    hipEvent_t e;
+    FL_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    FL_HIP_TRY(hipEventRecord(e, s));
+    FL_HIP_TRY(hipStreamWaitEvent(u->s, e, 0));
+    hipLaunchKernelGGL(k_net_input, dim3(grid1((long)H * H)), dim3(256), 0, u->s, r, n, H, H, (float)alpha, rr_dev,
+                       u->A[T_X0]);
+    net_forward(u, 1);
+    hipLaunchKernelGGL(k_net_output, dim3(grid1((long)n * n)), dim3(256), 0, u->s, u->A[T_Y], 16, n, H, rr_dev, z);
+    FL_HIP_TRY(hipEventRecord(e, u->s));
+    FL_HIP_TRY(hipStreamWaitEvent(s, e, 0));
+    (void)hipEventDestroy(e);
+    FL_HIP_TRY(hipGetLastError());
+    return FL_OK;
+}
+}  // namespace fl
+
+namespace fl {
+// GEMM check: C[M][N] = A[M][K] B[N][K]^T with operands rounded to the
+// operand type; kchunk < K runs the split-K path with its fixed-order reduction
+template <typename T>
+static fl_status gemm_test(int M, int N, int K, int kchunk, const float *A_host, const float *B_host, float *C_host) {
+    float *a = nullptr, *b = nullptr, *c = nullptr, *part = nullptr;
+    T *ab = nullptr, *bb = nullptr;
+    const int splits = (K + kchunk - 1) / kchunk;
+    hipError_t e = hipSuccess;
+    auto AL = [&](void **p, size_t n) {
+        if (e == hipSuccess) e = hipMalloc(p, n);
+    };
+    AL((void **)&a, sizeof(float) * M * K);
+    AL((void **)&b, sizeof(float) * N * K);
+    AL((void **)&c, sizeof(float) * M * N);
+    AL((void **)&part, sizeof(float) * M * N * splits);
+    AL((void **)&ab, sizeof(T) * M * K);
+    AL((void **)&bb, sizeof(T) * N * K);
+    if (e == hipSuccess) e = hipMemcpy(a, A_host, sizeof(float) * M * K, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b, B_host, sizeof(float) * N * K, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_cvt<T>, dim3(grid1((long)M * K)), dim3(256), 0, 0, a, (long)M * K, ab);
+        hipLaunchKernelGGL(k_cvt<T>, dim3(grid1((long)N * K)), dim3(256), 0, 0, b, (long)N * K, bb);
+        if (splits == 1) {
+            launch_gemm<T>(false, false, ab, K, bb, K, c, N, M, N, K, 0);
+        } else {
+            dim3 g(cdiv_i(M, 64), cdiv_i(N, 64), splits);
+            hipLaunchKernelGGL((k_gemm_nt<T, false, false, true>), g, dim3(256), 0, 0, ab, K, bb, K, part, N, M, N, K,
+                               kchunk);
+            hipLaunchKernelGGL(k_splitk_reduce, dim3(grid1((long)M * N)), dim3(256), 0, 0, part, splits, (long)M * N,
+                               (long)M * N, c, 0);
+        }
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(C_host, c, sizeof(float) * M * N, hipMemcpyDeviceToHost);
+    for (void *p : {(void *)a, (void *)b, (void *)c, (void *)part, (void *)ab, (void *)bb})
+        if (p) (void)hipFree(p);
+    if (e != hipSuccess) {
+        set_error("fl_gemm_test: %s", hipGetErrorString(e));
+        return FL_E_DEVICE;
+    }
+    return FL_OK;
+}
+
+}  // namespace fl
+
+extern "C" {
+
+fl_status fl_unet_apply(fl_unet u, const double *r, int n, double alpha, double *z, void *stream) {
+    if (!u || !r || !z || n < 1 || n > u->H) { set_error("fl_unet_apply: bad argument"); return FL_E_INVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_sumsq, dim3(1), dim3(256), 0, s, r, (long)n * n, u->nrm);
+    FL_TRY(unet_apply(u, r, n, alpha, z, u->nrm, s));
+    FL_HIP_TRY(hipStreamSynchronize(s));
+    return FL_OK;
+}
+
+fl_status fl_gemm_test(int M, int N, int K, int kchunk, int fp32_operands, const float *A_host, const float *B_host,
+                       float *C_host) {
+    if (M % 16 || N % 16 || K % 16 || M <= 0 || N <= 0 || K <= 0 || kchunk <= 0 || kchunk % 16 || !A_host ||
+        !B_host || !C_host || (long)M * K > (1L << 26) || (long)N * K > (1L << 26) || (long)M * N > (1L << 26)) {
+        set_error("fl_gemm_test: sizes must be positive multiples of 16 (at most 2^26 elements per matrix)");
+        return FL_E_INVAL;
+    }
+    return fp32_operands ? gemm_test<float>(M, N, K, kchunk, A_host, B_host, C_host)
+                         : gemm_test<bf16>(M, N, K, kchunk, A_host, B_host, C_host);
+}
+
+}  // extern "C"

@@ -22,7 +22,9 @@ EXPORTED = ["fl_coeffs", "fl_apply", "fl_apply_profiled", "fl_variant_count", "f
             "fl_select_variant", "fl_autotune", "fl_batch_create", "fl_batch_poisson_solve", "fl_batch_info",
             "fl_batch_destroy", "fl_poisson_solve", "fl_poisson_solve_ex", "fl_allen_cahn_step",
             "fl_allen_cahn_step_ex", "fl_op_destroy", "fl_op_describe", "fl_get_coeffs", "fl_get_symbol",
-            "fl_status_string", "fl_last_error"]
+            "fl_status_string", "fl_last_error", "fl_unet_create", "fl_unet_destroy", "fl_unet_num_params",
+            "fl_unet_step", "fl_unet_get_weights", "fl_unet_set_weights", "fl_unet_apply", "fl_set_preconditioner",
+            "fl_gemm_test", "fl_unet_pack", "fl_unet_train"]
 
 
 class FlLibraryMissing(RuntimeError):
@@ -93,6 +95,20 @@ def load(path: str = LIB_PATH):
     lib.fl_op_describe.argtypes = [vp, ctypes.POINTER(fl_op_desc)]
     lib.fl_get_coeffs.argtypes = [vp, vp]
     lib.fl_get_symbol.argtypes = [vp, vp]
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.fl_unet_create.argtypes = [ip, ip, ctypes.c_ulonglong, ip, ctypes.POINTER(vp)]
+    lib.fl_unet_destroy.argtypes = [vp]
+    lib.fl_unet_num_params.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong)]
+    lib.fl_unet_step.argtypes = [vp, ip, vp, vp, vp, ctypes.c_float, fp, fp]
+    lib.fl_unet_pack.argtypes = [vp, ip, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_double), ip,
+                                 vp, vp]
+    lib.fl_unet_train.argtypes = [vp, ctypes.c_long, vp, vp, ip, ip, ctypes.c_float, ctypes.c_float,
+                                  ctypes.c_ulonglong, fp]
+    lib.fl_unet_get_weights.argtypes = [vp, fp]
+    lib.fl_unet_set_weights.argtypes = [vp, fp]
+    lib.fl_unet_apply.argtypes = [vp, vp, ip, dp, vp, vp]
+    lib.fl_set_preconditioner.argtypes = [vp, vp]
+    lib.fl_gemm_test.argtypes = [ip, ip, ip, ip, ip, fp, fp, fp]
     lib.fl_status_string.argtypes = [ip]
     lib.fl_status_string.restype = ctypes.c_char_p
     lib.fl_last_error.argtypes = []
@@ -281,6 +297,142 @@ def fl_batch_destroy(b):
         load().fl_batch_destroy(b)
 
 
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def fl_unet_create(H, max_batch, seed, fp32_operands=False):
+    u = ctypes.c_void_p()
+    _check(load().fl_unet_create(int(H), int(max_batch), int(seed), int(bool(fp32_operands)), ctypes.byref(u)))
+    return u
+
+
+def fl_unet_destroy(u):
+    if u:
+        load().fl_unet_destroy(u)
+
+
+def fl_unet_num_params(u) -> int:
+    n = ctypes.c_longlong()
+    _check(load().fl_unet_num_params(u, ctypes.byref(n)))
+    return n.value
+
+
+def fl_unet_step(u, x, t=None, y=None, lr=0.0, want_loss=False, want_grad=False):
+    """x: device float32 [nb, H, H, 2]; t, y: device float32 [nb, H, H] or None.
+    Returns (loss per sample or None, gradient or None) as numpy float32."""
+    nb = x.shape[0]
+    loss = np.zeros(nb, np.float32) if (want_loss and t is not None) else None
+    grad = np.zeros(fl_unet_num_params(u), np.float32) if (want_grad and t is not None) else None
+    _check(load().fl_unet_step(u, int(nb), _ptr(x), _ptr(t) if t is not None else None,
+                               _ptr(y) if y is not None else None, float(lr),
+                               _fptr(loss) if loss is not None else None, _fptr(grad) if grad is not None else None))
+    return loss, grad
+
+
+def fl_unet_pack(u, rs, sols, alphas, n, x, t=None):
+    """Training samples from device pairs: rs, sols lists of float64 CUDA tensors (n*n each)."""
+    k = len(rs)
+    rp = (ctypes.c_void_p * k)(*[_ptr(r).value for r in rs])
+    sp = (ctypes.c_void_p * k)(*[_ptr(s).value for s in sols]) if sols is not None else None
+    al = (ctypes.c_double * k)(*[float(a) for a in alphas])
+    _check(load().fl_unet_pack(u, k, rp, sp, al, int(n), _ptr(x), _ptr(t) if t is not None else None))
+
+
+def fl_unet_train(u, x, t, epochs, batch, lr, lr_final=0.0, seed=0):
+    """Train on device samples x [count, H, H, 2], t [count, H, H]; returns the mean loss per epoch."""
+    losses = np.zeros(int(epochs), np.float32)
+    _check(load().fl_unet_train(u, int(x.shape[0]), _ptr(x), _ptr(t), int(epochs), int(batch), float(lr),
+                                float(lr_final), int(seed), _fptr(losses)))
+    return losses
+
+
+def fl_unet_get_weights(u) -> np.ndarray:
+    w = np.zeros(fl_unet_num_params(u), np.float32)
+    _check(load().fl_unet_get_weights(u, _fptr(w)))
+    return w
+
+
+def fl_unet_set_weights(u, w):
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    if w.size != fl_unet_num_params(u):
+        raise ValueError("expected %d weights" % fl_unet_num_params(u))
+    _check(load().fl_unet_set_weights(u, _fptr(w)))
+
+
+def fl_unet_apply(u, r, n, alpha, z, stream=None):
+    _check(load().fl_unet_apply(u, _ptr(r), int(n), float(alpha), _ptr(z), _stream(stream)))
+    return z
+
+
+def fl_set_preconditioner(op, u):
+    _check(load().fl_set_preconditioner(op, u))
+
+
+def fl_gemm_test(A, B, kchunk=None, fp32_operands=False):
+    A = np.ascontiguousarray(A, dtype=np.float32)
+    B = np.ascontiguousarray(B, dtype=np.float32)
+    M, K = A.shape
+    N = B.shape[0]
+    C = np.zeros((M, N), np.float32)
+    _check(load().fl_gemm_test(M, N, K, int(kchunk or K), int(bool(fp32_operands)), _fptr(A), _fptr(B), _fptr(C)))
+    return C
+
+
+class UNet:
+    """The learned preconditioner network (one fl_unet)."""
+
+    def __init__(self, H, max_batch=1, seed=0, fp32_operands=False):
+        self._u = fl_unet_create(H, max_batch, seed, fp32_operands)
+        self.H = H
+        self.max_batch = max_batch
+
+    @property
+    def handle(self):
+        return self._u
+
+    def num_params(self):
+        return fl_unet_num_params(self._u)
+
+    def weights(self):
+        return fl_unet_get_weights(self._u)
+
+    def set_weights(self, w):
+        fl_unet_set_weights(self._u, w)
+
+    def forward(self, x):
+        import torch
+        y = torch.empty(x.shape[:3], dtype=torch.float32, device=x.device)
+        fl_unet_step(self._u, x, None, y)
+        return y
+
+    def step(self, x, t, lr=0.0, want_grad=False, y=None):
+        return fl_unet_step(self._u, x, t, y, lr, True, want_grad)
+
+    def pack(self, rs, sols, alphas, n, x, t=None):
+        fl_unet_pack(self._u, rs, sols, alphas, n, x, t)
+
+    def train(self, x, t, epochs, batch, lr, lr_final=0.0, seed=0):
+        return fl_unet_train(self._u, x, t, epochs, batch, lr, lr_final, seed)
+
+    def apply(self, r, n, alpha, z=None, stream=None):
+        import torch
+        if z is None:
+            z = torch.empty_like(r)
+        return fl_unet_apply(self._u, r, n, alpha, z, stream)
+
+    def close(self):
+        if getattr(self, "_u", None):
+            fl_unet_destroy(self._u)
+            self._u = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Batch:
     """Many Poisson problems of mixed (N, alpha) solved together (one fl_batch)."""
 
@@ -343,6 +495,11 @@ class Operator:
 
     def coeffs(self):
         return fl_get_coeffs(self._op)
+
+    def set_preconditioner(self, net):
+        """Attach a UNet (kept alive by this operator) for solver='fpcg'; None detaches."""
+        fl_set_preconditioner(self._op, net.handle if net is not None else None)
+        self._net = net
 
     def variants(self, prec):
         return [fl_variant_info(self._op, prec, k) for k in range(fl_variant_count(self._op, prec))]

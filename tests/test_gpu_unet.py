@@ -1,0 +1,294 @@
+"""GPU U-Net of the learned preconditioner and flexible PCG, through the C-ABI,
+against the CPU U-Net (oracle/unet.py) and the FP64 oracle of the operator.
+
+Tolerances.  fp32-operand mode: the GPU sums in FP32 (MFMA accumulation,
+FP32 activations) what the oracle sums in FP64, so a K-term dot product
+carries about sqrt(K) * 2^-24 relative error per layer; over 11 layers with
+K <= 864 this stays below 1e-5 of the output norm.  bf16 mode: operands are
+rounded to 8 significant bits on both sides, but an FP32 activation and its
+FP64 counterpart can straddle a rounding boundary; each such flip moves one
+operand by up to 2^-8 relative, which leaves the outputs within a few 1e-3.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import unet as ounet
+from paper_1804_02718_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fl():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1804_02718_amd import fl as _fl
+    _fl.load()
+    return _fl
+
+
+def _f32(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda:0")
+
+
+def _f64(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda:0")
+
+
+def _weights(seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    parts = [rng.normal(0.0, scale * np.sqrt(2.0 / (ks * ks * cin)), cout * ks * ks * cin)
+             for cin, cout, ks in ounet.LAYERS]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def _samples(seed, nb, H, smooth=True):
+    rng = np.random.default_rng(seed)
+    x = np.zeros((nb, H, H, 2), np.float32)
+    for b in range(nb):
+        n = H - 1
+        r = inputs.gauss_sum(2, n + 1, 4, seed * 100 + b).reshape(n, n) if smooth else rng.normal(size=(n, n))
+        r = r / np.linalg.norm(r)
+        x[b, :n, :n, 0] = r
+        x[b, :, :, 1] = rng.uniform(0.3, 1.9)
+    t = rng.normal(size=(nb, H, H)).astype(np.float32)
+    return x, t
+
+
+def _bf16_round_np(a):
+    return torch.as_tensor(np.asarray(a, np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+# ---------------------------------------------------------------------------
+# GEMM kernel (MFMA operand/result layouts, split-K)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("M,N,K,kchunk", [(16, 16, 16, 16), (80, 48, 144, 144), (64, 128, 432, 432),
+                                          (48, 32, 4096, 1024), (208, 96, 4112, 2048)])
+def test_gemm_vs_numpy(fl, fp32, M, N, K, kchunk):
+    rng = np.random.default_rng(M * 7 + N + K)
+    A = rng.normal(size=(M, K)).astype(np.float32)
+    B = rng.normal(size=(N, K)).astype(np.float32)
+    C = fl.fl_gemm_test(A, B, kchunk=kchunk, fp32_operands=fp32)
+    if fp32:
+        Ar, Br = A.astype(np.float64), B.astype(np.float64)
+    else:
+        Ar, Br = _bf16_round_np(A), _bf16_round_np(B)
+    ref = Ar @ Br.T
+    bound = np.abs(Ar) @ np.abs(Br).T
+    assert np.all(np.abs(C - ref) <= 4e-7 * np.sqrt(K) * bound + 1e-30), np.abs(C - ref).max()
+
+
+def test_gemm_rejects(fl):
+    with pytest.raises(fl.FlError):
+        fl.fl_gemm_test(np.zeros((17, 16)), np.zeros((16, 16)))
+    with pytest.raises(fl.FlError):
+        fl.fl_gemm_test(np.zeros((16, 16)), np.zeros((16, 16)), kchunk=8)
+
+
+# ---------------------------------------------------------------------------
+# forward, loss, gradients, Adam
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("H,nb", [(16, 2), (32, 3), (64, 1)])
+def test_forward_fp32_mode(fl, H, nb):
+    net = fl.UNet(H, max_batch=nb, seed=1, fp32_operands=True)
+    w = _weights(20 + H)
+    net.set_weights(w)
+    x, _ = _samples(H + nb, nb, H)
+    y = net.forward(_f32(x)).cpu().numpy()
+    ref = ounet.forward(w.astype(np.float64), x)
+    assert np.linalg.norm(y - ref) <= 1e-6 * np.linalg.norm(ref)
+    assert np.abs(y - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("H,nb", [(16, 2), (32, 2)])
+def test_forward_bf16_mode(fl, H, nb):
+    net = fl.UNet(H, max_batch=nb, seed=1)
+    w = _weights(40 + H)
+    net.set_weights(w)
+    x, _ = _samples(3 * H + nb, nb, H)
+    y = net.forward(_f32(x)).cpu().numpy()
+    ref = ounet.forward(w.astype(np.float64), x, bf16=True)
+    plain = ounet.forward(w.astype(np.float64), x, bf16=False)
+    err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    assert err <= 5e-3, err
+    # and the bf16 network stays close to the unrounded one
+    assert np.linalg.norm(y - plain) <= 5e-2 * np.linalg.norm(plain)
+
+
+@pytest.mark.parametrize("H,nb", [(16, 2), (32, 2)])
+def test_loss_and_gradients_fp32_mode(fl, H, nb):
+    net = fl.UNet(H, max_batch=nb, seed=1, fp32_operands=True)
+    w = _weights(60 + H)
+    net.set_weights(w)
+    x, t = _samples(5 * H, nb, H)
+    loss, g = net.step(_f32(x), _f32(t), lr=0.0, want_grad=True)
+    L, per, gref = ounet.loss_and_grad(w.astype(np.float64), x, t.astype(np.float64))
+    assert np.allclose(loss, per, rtol=1e-5, atol=0)
+    offs = ounet.layer_offsets() + [ounet.num_params()]
+    for li in range(len(ounet.LAYERS)):
+        gl, rl = g[offs[li]:offs[li + 1]], gref[offs[li]:offs[li + 1]]
+        assert np.linalg.norm(gl - rl) <= 2e-5 * np.linalg.norm(rl), (li, np.linalg.norm(gl - rl) / np.linalg.norm(rl))
+
+
+def test_gradients_bf16_mode(fl):
+    H, nb = 32, 2
+    net = fl.UNet(H, max_batch=nb, seed=1)
+    w = _weights(77)
+    net.set_weights(w)
+    x, t = _samples(78, nb, H)
+    loss, g = net.step(_f32(x), _f32(t), lr=0.0, want_grad=True)
+    L, per, gref = ounet.loss_and_grad(w.astype(np.float64), x, t.astype(np.float64), bf16=True)
+    assert np.allclose(loss, per, rtol=1e-2, atol=0)
+    offs = ounet.layer_offsets() + [ounet.num_params()]
+    for li in range(len(ounet.LAYERS)):
+        gl, rl = g[offs[li]:offs[li + 1]], gref[offs[li]:offs[li + 1]]
+        assert np.linalg.norm(gl - rl) <= 3e-2 * np.linalg.norm(rl), (li, np.linalg.norm(gl - rl) / np.linalg.norm(rl))
+
+
+def test_adam_first_step(fl):
+    H, nb, lr = 16, 2, 1e-3
+    net = fl.UNet(H, max_batch=nb, seed=1, fp32_operands=True)
+    w = _weights(90)
+    net.set_weights(w)
+    x, t = _samples(91, nb, H)
+    net.step(_f32(x), _f32(t), lr=lr)
+    w1 = net.weights()
+    _, _, g = ounet.loss_and_grad(w.astype(np.float64), x, t.astype(np.float64))
+    wref, _, _ = ounet.adam_step(w.astype(np.float64), 0.0 * g, 0.0 * g, g, 1, lr)
+    big = np.abs(g) > 1e-3 * np.abs(g).max()
+    assert np.all(np.abs(w1 - wref)[big] <= 2e-6 * lr + 2e-7 * np.abs(w)[big])
+    assert np.all(np.abs(w1 - w) <= lr * (1 + 1e-6) + 2e-7 * np.abs(w))
+
+
+def test_training_lowers_loss(fl):
+    H, count = 32, 64
+    net = fl.UNet(H, max_batch=16, seed=3)
+    x, _ = _samples(100, count, H)
+    t = (0.3 * x[..., 0] + 0.1 * np.roll(x[..., 0], 1, axis=1)).astype(np.float32)
+    X, T = _f32(x), _f32(t)
+    losses = net.train(X, T, epochs=40, batch=16, lr=3e-3, lr_final=3e-4, seed=5)
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.25 * losses[0], losses
+
+
+# ---------------------------------------------------------------------------
+# preconditioner action and sample packing
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("H,n", [(16, 15), (32, 31), (32, 20)])
+def test_apply_vs_oracle(fl, H, n):
+    net = fl.UNet(H, max_batch=1, seed=1, fp32_operands=True)
+    w = _weights(110 + n)
+    net.set_weights(w)
+    r = inputs.gauss_sum(2, n + 1, 8, 111).reshape(n, n) * 3.7
+    z = net.apply(_f64(r.ravel()), n, 1.3).cpu().numpy().reshape(n, n)
+    ref = ounet.apply(w.astype(np.float64), r, 1.3, H)
+    assert np.linalg.norm(z - ref) <= 5e-6 * np.linalg.norm(ref)
+
+
+def test_pack_vs_oracle(fl):
+    H, n = 32, 31
+    net = fl.UNet(H, max_batch=4, seed=1)
+    rs = [inputs.gauss_sum(2, n + 1, 8, 120 + k) * (k + 1) for k in range(3)]
+    sols = [np.cos(np.arange(n * n) * (k + 1) * 0.01) for k in range(3)]
+    alphas = [0.4, 1.0, 1.8]
+    x = torch.zeros((3, H, H, 2), dtype=torch.float32, device="cuda:0")
+    t = torch.zeros((3, H, H), dtype=torch.float32, device="cuda:0")
+    net.pack([_f64(r) for r in rs], [_f64(s) for s in sols], alphas, n, x, t)
+    x, t = x.cpu().numpy(), t.cpu().numpy()
+    for k in range(3):
+        xr = ounet.net_input(rs[k].reshape(n, n), H, alphas[k])
+        assert np.abs(x[k] - xr).max() <= 1e-7 * np.abs(xr).max()
+        tr = np.zeros((H, H))
+        tr[:n, :n] = sols[k].reshape(n, n) / np.linalg.norm(rs[k])
+        assert np.abs(t[k] - tr).max() <= 1e-7 * np.abs(tr).max()
+
+
+def test_unet_rejects(fl):
+    with pytest.raises(fl.FlError):
+        fl.UNet(24)
+    with pytest.raises(fl.FlError):
+        fl.UNet(16, max_batch=0)
+    net = fl.UNet(16, max_batch=2)
+    with pytest.raises(fl.FlError):
+        net.forward(torch.zeros((3, 16, 16, 2), dtype=torch.float32, device="cuda:0"))
+    with pytest.raises(fl.FlError):
+        net.apply(torch.zeros(17 * 17, dtype=torch.float64, device="cuda:0"), 17, 1.0)
+
+
+# ---------------------------------------------------------------------------
+# flexible PCG with the learned preconditioner
+# ---------------------------------------------------------------------------
+def _train_small(fl, N, count, epochs, seed):
+    """Pairs (f, A^{-1} f) from the batched solver, then a short training run."""
+    n, H = N - 1, N
+    net = fl.UNet(H, max_batch=16, seed=seed)
+    fs, us, alphas = [], [], []
+    for k in range(0, count, 16):
+        probs = [inputs.learned_problem(seed * 1000 + k + j, N=N) for j in range(16)]
+        al = [p[0] for p in probs]
+        b = fl.Batch(2, [N] * 16, al, [2.0 / N] * 16)
+        f = [_f64(p[1]) for p in probs]
+        u, _ = b.solve(f, tol=1e-8)
+        b.close()
+        fs += f
+        us += u
+        alphas += al
+    x = torch.zeros((len(fs), H, H, 2), dtype=torch.float32, device="cuda:0")
+    t = torch.zeros((len(fs), H, H), dtype=torch.float32, device="cuda:0")
+    net.pack(fs, us, alphas, n, x, t)
+    losses = net.train(x, t, epochs=epochs, batch=16, lr=2e-3, lr_final=1e-4, seed=seed)
+    return net, losses
+
+
+def test_fpcg_trained_matches_oracle(fl):
+    N, alpha = 32, 1.5
+    h = 2.0 / N
+    net, losses = _train_small(fl, N, 256, 30, 7)
+    assert losses[-1] < losses[0]
+    op = fl.Operator(2, alpha, h, N)
+    op.set_preconditioner(net)
+    a = oracle.coeffs(2, alpha, h, N)
+    A = oracle.dense(2, N, alpha, a)
+    f = inputs.gauss_sum(2, N, 8, 900001)
+    uref = oracle.solve_dense(A, f)
+    u, info = op.poisson_solve(_f64(f), tol=1e-8, solver="fpcg")
+    ug = u.cpu().numpy()
+    assert info["relres"] <= 1e-8
+    assert np.linalg.norm(f - A @ ug) <= 1.05e-8 * np.linalg.norm(f)
+    assert np.linalg.norm(ug - uref) <= 1e-7 * np.linalg.norm(uref)
+    _, info_cg = op.poisson_solve(_f64(f), tol=1e-8, solver="cg64")
+    print("fpcg", info, "cg", info_cg["iters"], "losses", losses[0], losses[-1])
+
+
+def test_fpcg_fallback_with_zero_network(fl):
+    """A network that outputs zero fails the positivity guard; the solve falls back to plain CG."""
+    N, alpha = 32, 1.2
+    h = 2.0 / N
+    net = fl.UNet(N, max_batch=1, seed=1)
+    net.set_weights(np.zeros(net.num_params(), np.float32))
+    op = fl.Operator(2, alpha, h, N)
+    op.set_preconditioner(net)
+    a = oracle.coeffs(2, alpha, h, N)
+    A = oracle.dense(2, N, alpha, a)
+    f = inputs.gauss_sum(2, N, 8, 900002)
+    u, info = op.poisson_solve(_f64(f), tol=1e-8, solver="fpcg")
+    ug = u.cpu().numpy()
+    assert info["fell_back"] == 1
+    assert np.linalg.norm(f - A @ ug) <= 1.05e-8 * np.linalg.norm(f)
+
+
+def test_fpcg_rejects(fl):
+    op = fl.Operator(2, 1.0, 2.0 / 32, 32)
+    with pytest.raises(fl.FlError):
+        op.poisson_solve(_f64(np.ones(31 * 31)), tol=1e-8, solver="fpcg")  # no network attached
+    net = fl.UNet(16, max_batch=1)
+    op.set_preconditioner(net)
+    with pytest.raises(fl.FlError):
+        op.poisson_solve(_f64(np.ones(31 * 31)), tol=1e-8, solver="fpcg")  # grid too small
+    op3 = fl.Operator(3, 1.0, 2.0 / 16, 16)
+    op3.set_preconditioner(fl.UNet(16, max_batch=1))
+    with pytest.raises(fl.FlError):
+        op3.poisson_solve(_f64(np.ones(15 ** 3)), tol=1e-8, solver="fpcg")
