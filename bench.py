@@ -15,7 +15,10 @@ Also reported on the same JSON line:
   cpu_baseline  -- the FP64 oracle's explicit sum on a bounded sample of rows
                    of the same workload, on this host's cores.
   extra         -- FP64 matvec rate, per-pass times and the Poisson
-                   time-to-1e-8 of the solvers (outside the timed region).
+                   time-to-1e-8 of the solvers; the 3D N=256 matvec; the batch
+                   of 64 mixed Poisson solves; the learned-preconditioner
+                   workload (training pairs, training, flexible PCG against
+                   plain CG).  All outside the timed region.
 """
 import argparse
 import hashlib
@@ -190,6 +193,52 @@ def poisson_extra(torch, fl, inputs, N=1024, alpha=1.5):
             **out}
 
 
+def c5_extra(torch, fl, pairs, epochs, N=256):
+    """Learned preconditioner: pairs from the batched solver, a short training run, then flexible PCG
+    against plain FP64 CG on 4 held-out problems (tol 1e-8)."""
+    from paper_1804_02718_amd import learned
+    t0 = time.perf_counter()
+    net = fl.UNet(N, max_batch=16, seed=1)
+    x, t, alphas, mean_it = learned.make_pairs(net, N, pairs)
+    torch.cuda.synchronize()
+    tgen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    losses = learned.train(net, x, t, epochs)
+    torch.cuda.synchronize()
+    ttrain = time.perf_counter() - t0
+    del x, t
+    # one network application (3.66 GFLOP at 256^2) and one FP64 matvec, for scale
+    op = fl.Operator(2, 1.0, 2.0 / N, N)
+    r = torch.randn((N - 1) ** 2, dtype=torch.float64, device="cuda:0")
+    z = torch.empty_like(r)
+    for _ in range(3):
+        net.apply(r, N - 1, 1.0, z)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        net.apply(r, N - 1, 1.0, z)
+    torch.cuda.synchronize()
+    t_apply = (time.perf_counter() - t0) / 20
+    y = torch.empty_like(r)
+    for _ in range(3):
+        op.apply(r, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(100):
+        op.apply(r, y)
+    torch.cuda.synchronize()
+    t_mv = (time.perf_counter() - t0) / 100
+    op.close()
+    rows = learned.compare(net, N, [900000 + j for j in range(4)])
+    net.close()
+    return {"workload": "2D N=256 (255^2 interior on a 256^2 network grid), alpha~U(0.3,1.9), f = 8 Gaussians; "
+                        "%d training pairs (seeds 100000+i), %d epochs; held-out seeds 900000..900003" % (pairs, epochs),
+            "pair_generation_seconds": round(tgen, 2), "pair_solver_mean_iters": round(mean_it, 1),
+            "training_seconds": round(ttrain, 2), "epoch_loss": [round(float(l), 4) for l in losses],
+            "net_apply_ms": round(t_apply * 1e3, 4), "net_apply_TFLOP_s": round(3.66e9 / t_apply / 1e12, 2),
+            "fp64_matvec_ms": round(t_mv * 1e3, 4), "solves": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,10 +249,15 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the built-in default kernel variant instead of the autotuned one")
-    ap.add_argument("--c3", action="store_true",
-                    help="also time the 3D N=256 matvec (FP32 and FP64) of the Allen--Cahn workload")
-    ap.add_argument("--c4", action="store_true",
-                    help="also time the batch of 64 mixed-(N, alpha) Poisson solves, batched and one by one")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the 3D N=256 matvec (FP32 and FP64) of the Allen--Cahn workload")
+    ap.add_argument("--no-c4", action="store_true",
+                    help="skip the batch of 64 mixed-(N, alpha) Poisson solves, batched and one by one")
+    ap.add_argument("--no-c5", action="store_true",
+                    help="skip the learned-preconditioner workload (pairs, training, flexible PCG vs CG)")
+    ap.add_argument("--c5-pairs", type=int, default=1024,
+                    help="training pairs for the learned preconditioner (the full recipe uses 20000)")
+    ap.add_argument("--c5-epochs", type=int, default=4)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before timing, copy a buffer of this many MiB three times (a plain copy kernel "
                          "whose known traffic calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -278,12 +332,15 @@ def main():
         print("bench: poisson solves", file=sys.stderr, flush=True)
         extra["poisson"] = poisson_extra(torch, fl, inputs)
     op.close()
-    if args.c3:
+    if not args.no_extra and not args.no_c3:
         print("bench: 3D N=256 matvec", file=sys.stderr, flush=True)
         extra["c3_matvec"] = c3_extra(torch, fl, inputs, not args.no_autotune)
-    if args.c4:
+    if not args.no_extra and not args.no_c4:
         print("bench: batched solves", file=sys.stderr, flush=True)
         extra["c4_batch"] = c4_extra(torch, fl, inputs)
+    if not args.no_extra and not args.no_c5:
+        print("bench: learned preconditioner", file=sys.stderr, flush=True)
+        extra["c5_learned"] = c5_extra(torch, fl, args.c5_pairs, args.c5_epochs)
 
     cpu = None
     if not args.no_cpu_baseline:

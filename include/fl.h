@@ -212,7 +212,8 @@ fl_status fl_batch_destroy(fl_batch b);
  * Learned preconditioner: a convolutional U-Net (3 levels, 16/32/64 channels,
  * 3x3 bias-free convolutions with ReLU, 2x2 average pooling, nearest
  * upsampling with skip concatenation, 1x1 output) on an H x H grid, input
- * channels (r / ||r||, alpha), output an approximation of A^{-1} r / ||r||.
+ * channels (r / rms(r), alpha), rms(r) = ||r|| / n over the n x n interior,
+ * output an approximation of A^{-1} r / rms(r).
  * Convolutions run on bf16 MFMA with FP32 accumulation; weights are kept in
  * FP32 (Adam) with bf16 copies.  Not part of the paper's method: it feeds the
  * flexible PCG of FL_SOLVE_FPCG, which falls back to plain CG.
@@ -230,7 +231,7 @@ fl_status fl_batch_destroy(fl_batch b);
  *   fl_unet_pack        -- count training samples from device pairs
  *                          (r[z], sol[z]) of n x n doubles (host arrays of
  *                          device pointers; sol may be NULL): x[z] =
- *                          (r/||r||, alpha[z]) and t[z] = sol/||r|| on the
+ *                          (r/rms(r), alpha[z]) and t[z] = sol/rms(r) on the
  *                          top-left n x n of the H x H grid, zero elsewhere.
  *   fl_unet_train       -- epochs over count device samples (x, t as in
  *                          fl_unet_step): seeded shuffle each epoch, batches
@@ -238,10 +239,17 @@ fl_status fl_batch_destroy(fl_batch b);
  *                          Adam step per batch with the learning rate
  *                          decaying from lr to lr_final on a cosine; mean
  *                          training loss per epoch to epoch_loss (host, may
- *                          be NULL).
+ *                          be NULL).  ops NULL: relative L2 loss
+ *                          ||y - t||^2 / ||t||^2 over the grid.  ops (host
+ *                          array of count 2D operators, ops[i] the one whose
+ *                          pair made sample i, n <= H): energy-norm loss
+ *                          (y - t, A (y - t)) / (t, x0) on the interior, the
+ *                          relative A-norm error of the preconditioned
+ *                          residual (A t = x0 for an exact pair); one FP32
+ *                          matvec per sample and step.
  *   fl_unet_get_weights / fl_unet_set_weights -- FP32 weights, layer by layer,
  *                          each [cout][(ky*ks + kx)*cin + ci] (host).
- *   fl_unet_apply       -- z = ||r|| Net(r/||r||, alpha) for a residual r on
+ *   fl_unet_apply       -- z = rms(r) Net(r/rms(r), alpha) for a residual r on
  *                          the n x n interior (device doubles, n <= H).
  *   fl_set_preconditioner -- attach (or detach with NULL) a network to a 2D
  *                          operator for FL_SOLVE_FPCG; not owned.
@@ -257,8 +265,8 @@ fl_status fl_unet_step(fl_unet u, int nb, const float *x, const float *t, float 
                        float *loss_host, float *grad_host);
 fl_status fl_unet_pack(fl_unet u, int count, const double *const *r, const double *const *sol, const double *alpha,
                        int n, float *x, float *t);
-fl_status fl_unet_train(fl_unet u, long count, const float *x, const float *t, int epochs, int batch, float lr,
-                        float lr_final, unsigned long long seed, float *epoch_loss);
+fl_status fl_unet_train(fl_unet u, long count, const float *x, const float *t, const fl_op *ops, int epochs,
+                        int batch, float lr, float lr_final, unsigned long long seed, float *epoch_loss);
 fl_status fl_unet_get_weights(fl_unet u, float *w_host);
 fl_status fl_unet_set_weights(fl_unet u, const float *w_host);
 fl_status fl_unet_apply(fl_unet u, const double *r, int n, double alpha, double *z, void *stream);

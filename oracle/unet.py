@@ -131,20 +131,21 @@ def adam_step(w, m, v, g, step, lr, b1=0.9, b2=0.999, eps=1e-8):
 
 
 def net_input(r, H, alpha):
-    """Sample [H, H, 2] from an n x n residual: r / ||r|| at the top-left n x n, 0 elsewhere; alpha channel."""
+    """Sample [H, H, 2] from an n x n residual: r / rms(r) at the top-left n x n, 0 elsewhere; alpha channel.
+    rms(r) = ||r|| / n, the root mean square over the n x n interior."""
     r = np.asarray(r, np.float64)
     n = r.shape[0]
     x = np.zeros((H, H, 2))
-    nr = np.sqrt((r * r).sum())
-    x[:n, :n, 0] = r / nr if nr > 0 else r
+    rms = np.sqrt((r * r).sum()) / n
+    x[:n, :n, 0] = r / rms if rms > 0 else r
     x[:, :, 1] = alpha
     return x
 
 
 def apply(w, r, alpha, H, bf16=False):
-    """Preconditioner action z = ||r|| * Net(r / ||r||, alpha) on the n x n interior."""
+    """Preconditioner action z = rms(r) * Net(r / rms(r), alpha) on the n x n interior."""
     r = np.asarray(r, np.float64)
     n = r.shape[0]
-    nr = np.sqrt((r * r).sum())
+    rms = np.sqrt((r * r).sum()) / n
     y = forward(w, net_input(r, H, alpha)[None], bf16)[0]
-    return (nr if nr > 0 else 1.0) * y[:n, :n]
+    return (rms if rms > 0 else 1.0) * y[:n, :n]

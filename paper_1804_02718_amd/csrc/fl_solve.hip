@@ -475,7 +475,10 @@ static fl_status fpcg(fl_op op, const double *f, double *x, double tol, int max_
     FL_TRY(dot<double>(op, r, r, w.partA, &rr, s));  // leaves (r,r) in scal[S_DOT]
     FL_TRY(unet_apply(op->net, r, op->n, op->alpha, z, op->scal + S_DOT, s));
     FL_TRY(dot<double>(op, r, z, w.partA, &rz, s));
-    if (!(rz > 0.0) || !std::isfinite(rz)) fallback = true;
+    if (!(rz > 0.0) || !std::isfinite(rz)) {
+        fallback = true;
+        set_error("FPCG: (r, z) = %.3e at the start; plain CG takes over", rz);
+    }
     hipLaunchKernelGGL((k_copy_cast<double, double>), dim3(ew_grid(M)), dim3(256), 0, s, p, z, M);
     int it = 0;
     info->relres = std::sqrt(rr) / bn;
@@ -484,21 +487,37 @@ static fl_status fpcg(fl_op op, const double *f, double *x, double tol, int max_
         double pq = 0.0;
         FL_TRY(dot<double>(op, p, kp, w.partA, &pq, s));
         const double a = rz / pq;
-        if (!(pq > 0.0) || !std::isfinite(a)) { fallback = true; break; }
+        if (!(pq > 0.0) || !std::isfinite(a)) {
+            fallback = true;
+            set_error("FPCG: (p, A p) = %.3e at iteration %d; plain CG takes over", pq, it);
+            break;
+        }
         hipLaunchKernelGGL(k_fpcg_update, dim3(ew_grid(M)), dim3(256), 0, s, x, r, rold, p, kp, a, M);
         FL_TRY(dot<double>(op, r, r, w.partA, &rr, s));
         ++it;
         info->relres = std::sqrt(rr) / bn;
-        if (!std::isfinite(info->relres)) { fallback = true; break; }
+        if (!std::isfinite(info->relres)) {
+            fallback = true;
+            set_error("FPCG: residual not finite at iteration %d; plain CG takes over", it);
+            break;
+        }
         if (info->relres < 0.5 * best) { best = info->relres; since_best = 0; }
-        else if (++since_best > 50) { fallback = true; break; }
+        else if (++since_best > 50) {
+            fallback = true;
+            set_error("FPCG: residual %.3e not halved in 50 iterations (at %d); plain CG takes over", info->relres, it);
+            break;
+        }
         if (info->relres <= tol) break;
         FL_TRY(unet_apply(op->net, r, op->n, op->alpha, z, op->scal + S_DOT, s));
         double rzn = 0.0, zro = 0.0;
         FL_TRY(dot<double>(op, r, z, w.partA, &rzn, s));
         FL_TRY(dot<double>(op, rold, z, w.partA, &zro, s));
         const double beta = (rzn - zro) / rz;  // Polak--Ribiere: (z, r - r_old) / (r_old, z_old)
-        if (!(rzn > 0.0) || !std::isfinite(beta)) { fallback = true; break; }
+        if (!(rzn > 0.0) || !std::isfinite(beta)) {
+            fallback = true;
+            set_error("FPCG: (r, z) = %.3e at iteration %d; plain CG takes over", rzn, it);
+            break;
+        }
         hipLaunchKernelGGL(k_fpcg_dir, dim3(ew_grid(M)), dim3(256), 0, s, p, z, beta, M);
         rz = rzn;
     }

@@ -383,32 +383,32 @@ __global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__re
     }
 }
 
-// network input from a residual: channel 0 = scale * r at the interior n x n
-// (zero in the padding), channel 1 = alpha; scale = 1 / ||r|| from `nrm`
+// network input from a residual: channel 0 = r / rms(r) at the interior n x n
+// (zero in the padding), channel 1 = alpha; rms(r) = ||r|| / n from `nrm` = ||r||^2
 __global__ void k_net_input(const double *__restrict__ r, int n, int H, int W, float alpha, const double *nrm,
                             float *__restrict__ X) {
-    const double s = (nrm && nrm[0] > 0.0) ? 1.0 / sqrt(nrm[0]) : 1.0;
+    const double s = (nrm && nrm[0] > 0.0) ? (double)n / sqrt(nrm[0]) : 1.0;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)H * W; i += (long)gridDim.x * blockDim.x) {
         const int x = (int)(i % W), y = (int)(i / W);
         X[2 * i] = (x < n && y < n) ? (float)(s * r[(long)y * n + x]) : 0.f;
         X[2 * i + 1] = alpha;
     }
 }
-// z = ||r|| * y (channel 0, pitch ys) at the interior
+// z = rms(r) * y (channel 0, pitch ys) at the interior
 __global__ void k_net_output(const float *__restrict__ Y, int ys, int n, int W, const double *nrm,
                              double *__restrict__ z) {
-    const double s = (nrm && nrm[0] > 0.0) ? sqrt(nrm[0]) : 1.0;
+    const double s = (nrm && nrm[0] > 0.0) ? sqrt(nrm[0]) / (double)n : 1.0;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)n * n; i += (long)gridDim.x * blockDim.x) {
         const int x = (int)(i % n), y = (int)(i / n);
         z[i] = s * (double)Y[((long)y * W + x) * ys];
     }
 }
 
-// training sample from a (residual, solution) pair: x = (r / ||r||, alpha) and
-// t = sol / ||r|| on the top-left n x n of the H x W grid, zero elsewhere
+// training sample from a (residual, solution) pair: x = (r / rms(r), alpha) and
+// t = sol / rms(r) on the top-left n x n of the H x W grid, zero elsewhere
 __global__ void k_pack_sample(const double *__restrict__ r, const double *__restrict__ sol, int n, int H, int W,
                               float alpha, const double *nrm, float *__restrict__ X, float *__restrict__ T) {
-    const double s = nrm[0] > 0.0 ? 1.0 / sqrt(nrm[0]) : 1.0;
+    const double s = nrm[0] > 0.0 ? (double)n / sqrt(nrm[0]) : 1.0;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)H * W; i += (long)gridDim.x * blockDim.x) {
         const int x = (int)(i % W), y = (int)(i / W);
         const bool in = x < n && y < n;
@@ -417,6 +417,53 @@ __global__ void k_pack_sample(const double *__restrict__ r, const double *__rest
         if (T) T[i] = in && sol ? (float)(s * sol[(long)y * n + x]) : 0.f;
     }
 }
+// energy-norm loss, step 1: d = y - t on the n x n interior (compact, row-major)
+__global__ void k_energy_diff(const float *__restrict__ Y, int ys, const float *__restrict__ T, int n, int W,
+                              float *__restrict__ d) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)n * n; i += (long)gridDim.x * blockDim.x) {
+        const long p = (i / n) * W + i % n;
+        d[i] = Y[p * ys] - T[p];
+    }
+}
+// step 2 (one block): loss = (d, A d) / (t, x0) with x0 = channel 0 of the input;
+// since A t = x0 for an exact pair, the denominator is ||t||_A^2
+__global__ __launch_bounds__(256) void k_energy_loss(const float *__restrict__ d, const float *__restrict__ Ad,
+                                                     const float *__restrict__ T, const float *__restrict__ X, int n,
+                                                     int W, float *__restrict__ loss, float *__restrict__ den) {
+    __shared__ double s1[256], s2[256];
+    double a = 0.0, b = 0.0;
+    for (long i = threadIdx.x; i < (long)n * n; i += 256) {
+        const long p = (i / n) * W + i % n;
+        a += (double)d[i] * (double)Ad[i];
+        b += (double)T[p] * (double)X[2 * p];
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = b;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) {
+            s1[threadIdx.x] += s1[threadIdx.x + k];
+            s2[threadIdx.x] += s2[threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        loss[0] = (float)(s1[0] / s2[0]);
+        den[0] = (float)s2[0];
+    }
+}
+// step 3: dY = 2 A d / (den * nb) in channel 0 of the interior, 0 elsewhere
+__global__ void k_energy_grad(const float *__restrict__ Ad, const float *__restrict__ den, int n, int H, int W, int nb,
+                              float *__restrict__ dY, int ys) {
+    const float sc = 2.f / (den[0] * nb);
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)H * W * ys; i += (long)gridDim.x * blockDim.x) {
+        const int ch = (int)(i % ys);
+        const long p = i / ys;
+        const int x = (int)(p % W), y = (int)(p / W);
+        dY[i] = (ch == 0 && x < n && y < n) ? sc * Ad[(long)y * n + x] : 0.f;
+    }
+}
+
 // minibatch gather: dst[j] = src[idx[j]] for blocks of `len` floats
 __global__ void k_gather(const float *__restrict__ src, const long *__restrict__ idx, int nb, long len,
                          float *__restrict__ dst) {
@@ -458,6 +505,7 @@ struct fl_unet_s {
     size_t row_elems = 0, col_elems = 0, part_elems = 0;
     double *nrm = nullptr;
     long *idx = nullptr;                // minibatch indices (device)
+    float *ebuf = nullptr;              // energy loss: d and A d (2 x H*W floats)
     hipStream_t s = nullptr;
 };
 
@@ -639,22 +687,38 @@ static void refresh_bf16(fl_unet u, float lr) {
 }
 
 // forward on A[T_X0] (nb samples); with targets in A[T_TGT]: loss, backward and,
-// for lr > 0, one Adam step
-static void train_step(fl_unet u, int nb, bool with_target, float lr) {
+// for lr > 0, one Adam step.  ops (per sample, may be NULL) selects the
+// energy-norm loss ||y - t||_A^2 / ||t||_A^2 instead of the relative L2 loss.
+static fl_status train_step(fl_unet u, int nb, bool with_target, float lr, const fl_op *ops = nullptr) {
     const long pix = (long)u->H * u->W;
     hipStream_t s = u->s;
     net_forward(u, nb);
-    if (!with_target) return;
-    const int nblk = 64;
-    hipLaunchKernelGGL(k_loss_sums, dim3(nblk, nb), dim3(256), 0, s, u->A[T_Y], 16, u->A[T_TGT], pix, u->lpart);
-    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, s, u->lpart, nblk, nb, u->ltot, u->lossbuf);
-    hipLaunchKernelGGL(k_loss_grad, dim3(grid1(nb * pix * 16)), dim3(256), 0, s, u->A[T_Y], 16, u->A[T_TGT], pix, nb,
-                       u->ltot, u->G[T_Y]);
+    if (!with_target) return FL_OK;
+    if (ops) {
+        float *d = u->ebuf, *Ad = u->ebuf + pix;
+        for (int z = 0; z < nb; ++z) {
+            const int n = ops[z]->n;
+            const float *Yz = u->A[T_Y] + z * pix * 16, *Tz = u->A[T_TGT] + z * pix, *Xz = u->A[T_X0] + z * pix * 2;
+            hipLaunchKernelGGL(k_energy_diff, dim3(grid1((long)n * n)), dim3(256), 0, s, Yz, 16, Tz, n, u->W, d);
+            FL_TRY(matvec<float>(ops[z], d, Ad, s));
+            hipLaunchKernelGGL(k_energy_loss, dim3(1), dim3(256), 0, s, d, Ad, Tz, Xz, n, u->W, u->lossbuf + z,
+                               u->ltot + 2 * z + 1);
+            hipLaunchKernelGGL(k_energy_grad, dim3(grid1(pix * 16)), dim3(256), 0, s, Ad, u->ltot + 2 * z + 1, n,
+                               u->H, u->W, nb, u->G[T_Y] + z * pix * 16, 16);
+        }
+    } else {
+        const int nblk = 64;
+        hipLaunchKernelGGL(k_loss_sums, dim3(nblk, nb), dim3(256), 0, s, u->A[T_Y], 16, u->A[T_TGT], pix, u->lpart);
+        hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, s, u->lpart, nblk, nb, u->ltot, u->lossbuf);
+        hipLaunchKernelGGL(k_loss_grad, dim3(grid1(nb * pix * 16)), dim3(256), 0, s, u->A[T_Y], 16, u->A[T_TGT], pix,
+                           nb, u->ltot, u->G[T_Y]);
+    }
     net_backward(u, nb);
     if (lr > 0.f) {
         u->step += 1;
         refresh_bf16(u, lr);
     }
+    return FL_OK;
 }
 
 }  // namespace fl
@@ -699,7 +763,7 @@ fl_status fl_unet_create(int H, int max_batch, unsigned long long seed, int fp32
     std::vector<float> w(u->nparam);
     std::mt19937_64 rng(seed);
     for (auto &c : u->conv) {
-        std::normal_distribution<float> nd(0.f, sqrtf(2.f / (float)c.K) * (c.ks == 1 ? 0.5f : 1.f));
+        std::normal_distribution<float> nd(0.f, sqrtf(2.f / (float)c.K) * (c.ks == 1 ? 0.02f : 1.f));
         for (long i = 0; i < (long)c.cout * c.K; ++i) w[c.woff + i] = nd(rng);
     }
     // activations
@@ -745,6 +809,7 @@ fl_status fl_unet_create(int H, int max_batch, unsigned long long seed, int fp32
     AL((void **)&u->ltot, sizeof(float) * 2 * max_batch);
     AL((void **)&u->nrm, sizeof(double) * 8);
     AL((void **)&u->idx, sizeof(long) * max_batch);
+    AL((void **)&u->ebuf, sizeof(float) * 2 * (size_t)H * H);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&u->s, hipStreamNonBlocking);
     if (e != hipSuccess) {
         set_error("fl_unet_create: %s", hipGetErrorString(e));
@@ -784,7 +849,7 @@ fl_status fl_unet_destroy(fl_unet u) {
     if (!u) return FL_OK;
     for (void *p : {(void *)u->w, (void *)u->m, (void *)u->v, (void *)u->g, (void *)u->wb, (void *)u->wt,
                     (void *)u->act, (void *)u->rowbuf, (void *)u->tbuf, (void *)u->tbuf2, (void *)u->colbuf,
-                    (void *)u->part, (void *)u->lossbuf, (void *)u->lpart, (void *)u->ltot, (void *)u->nrm, (void *)u->idx})
+                    (void *)u->part, (void *)u->lossbuf, (void *)u->lpart, (void *)u->ltot, (void *)u->nrm, (void *)u->idx, (void *)u->ebuf})
         if (p) (void)hipFree(p);
     if (u->s) (void)hipStreamDestroy(u->s);
     delete u;
@@ -827,7 +892,7 @@ fl_status fl_unet_step(fl_unet u, int nb, const float *x, const float *t, float 
     hipStream_t s = u->s;
     FL_HIP_TRY(hipMemcpyAsync(u->A[T_X0], x, sizeof(float) * nb * pix * 2, hipMemcpyDeviceToDevice, s));
     if (t) FL_HIP_TRY(hipMemcpyAsync(u->A[T_TGT], t, sizeof(float) * nb * pix, hipMemcpyDeviceToDevice, s));
-    train_step(u, nb, t != nullptr, lr);
+    FL_TRY(train_step(u, nb, t != nullptr, lr));
     if (y)
         hipLaunchKernelGGL(k_copy_ch, dim3(grid1(nb * pix)), dim3(256), 0, s, u->A[T_Y], 16, 0, y, 1, 0, nb * pix, 1, 0);
     FL_HIP_TRY(hipGetLastError());
@@ -863,12 +928,19 @@ fl_status fl_unet_pack(fl_unet u, int count, const double *const *r, const doubl
     return FL_OK;
 }
 
-fl_status fl_unet_train(fl_unet u, long count, const float *x, const float *t, int epochs, int batch, float lr,
-                        float lr_final, unsigned long long seed, float *epoch_loss) {
+fl_status fl_unet_train(fl_unet u, long count, const float *x, const float *t, const fl_op *ops, int epochs,
+                        int batch, float lr, float lr_final, unsigned long long seed, float *epoch_loss) {
     if (!u || !x || !t || count < 1 || epochs < 1 || batch < 1 || batch > u->nb || !(lr > 0.f) || lr_final < 0.f) {
         set_error("fl_unet_train: bad argument");
         return FL_E_INVAL;
     }
+    if (ops)
+        for (long i = 0; i < count; ++i)
+            if (!ops[i] || ops[i]->d != 2 || ops[i]->n > u->H) {
+                set_error("fl_unet_train: sample %ld needs a 2D operator with n <= %d", i, u->H);
+                return FL_E_INVAL;
+            }
+    std::vector<fl_op> bops(batch);
     const long pix = (long)u->H * u->W;
     const long steps_per_epoch = count / batch;  // the ragged remainder of a shuffled epoch is dropped
     if (steps_per_epoch < 1) { set_error("fl_unet_train: fewer samples than one batch"); return FL_E_INVAL; }
@@ -891,7 +963,9 @@ fl_status fl_unet_train(fl_unet u, long count, const float *x, const float *t, i
                                u->A[T_X0]);
             hipLaunchKernelGGL(k_gather, dim3(grid1(batch * pix)), dim3(256), 0, u->s, t, u->idx, batch, pix,
                                u->A[T_TGT]);
-            train_step(u, batch, true, lr_k);
+            if (ops)
+                for (int z = 0; z < batch; ++z) bops[z] = ops[order[b * batch + z]];
+            FL_TRY(train_step(u, batch, true, lr_k, ops ? bops.data() : nullptr));
             FL_HIP_TRY(hipMemcpyAsync(lossh.data(), u->lossbuf, sizeof(float) * batch, hipMemcpyDeviceToHost, u->s));
             FL_HIP_TRY(hipStreamSynchronize(u->s));
             for (int z = 0; z < batch; ++z) acc += lossh[z];
@@ -907,7 +981,7 @@ fl_status fl_unet_train(fl_unet u, long count, const float *x, const float *t, i
 
 namespace fl {
 int unet_size(fl_unet u) { return u->H; }
-// z = ||r|| * Net(r / ||r||, alpha) on the stream s (r, z: n x n, n <= H); the
+// z = rms(r) * Net(r / rms(r), alpha) on the stream s (r, z: n x n, n <= H); the
 // squared norm of r is computed into u->nrm first.  Used inside flexible PCG.
 fl_status unet_apply(fl_unet u, const double *r, int n, double alpha, double *z, const double *rr_dev,
                      hipStream_t s) {

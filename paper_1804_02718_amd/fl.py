@@ -102,8 +102,8 @@ def load(path: str = LIB_PATH):
     lib.fl_unet_step.argtypes = [vp, ip, vp, vp, vp, ctypes.c_float, fp, fp]
     lib.fl_unet_pack.argtypes = [vp, ip, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_double), ip,
                                  vp, vp]
-    lib.fl_unet_train.argtypes = [vp, ctypes.c_long, vp, vp, ip, ip, ctypes.c_float, ctypes.c_float,
-                                  ctypes.c_ulonglong, fp]
+    lib.fl_unet_train.argtypes = [vp, ctypes.c_long, vp, vp, ctypes.POINTER(vp), ip, ip, ctypes.c_float,
+                                  ctypes.c_float, ctypes.c_ulonglong, fp]
     lib.fl_unet_get_weights.argtypes = [vp, fp]
     lib.fl_unet_set_weights.argtypes = [vp, fp]
     lib.fl_unet_apply.argtypes = [vp, vp, ip, dp, vp, vp]
@@ -339,10 +339,17 @@ def fl_unet_pack(u, rs, sols, alphas, n, x, t=None):
     _check(load().fl_unet_pack(u, k, rp, sp, al, int(n), _ptr(x), _ptr(t) if t is not None else None))
 
 
-def fl_unet_train(u, x, t, epochs, batch, lr, lr_final=0.0, seed=0):
-    """Train on device samples x [count, H, H, 2], t [count, H, H]; returns the mean loss per epoch."""
+def fl_unet_train(u, x, t, epochs, batch, lr, lr_final=0.0, seed=0, ops=None):
+    """Train on device samples x [count, H, H, 2], t [count, H, H]; returns the mean loss per epoch.
+    ops: None (relative L2 loss) or one operator handle per sample (energy-norm loss)."""
     losses = np.zeros(int(epochs), np.float32)
-    _check(load().fl_unet_train(u, int(x.shape[0]), _ptr(x), _ptr(t), int(epochs), int(batch), float(lr),
+    count = int(x.shape[0])
+    opa = None
+    if ops is not None:
+        if len(ops) != count:
+            raise ValueError("one operator per sample")
+        opa = (ctypes.c_void_p * count)(*[o.value if isinstance(o, ctypes.c_void_p) else o for o in ops])
+    _check(load().fl_unet_train(u, count, _ptr(x), _ptr(t), opa, int(epochs), int(batch), float(lr),
                                 float(lr_final), int(seed), _fptr(losses)))
     return losses
 
@@ -412,8 +419,11 @@ class UNet:
     def pack(self, rs, sols, alphas, n, x, t=None):
         fl_unet_pack(self._u, rs, sols, alphas, n, x, t)
 
-    def train(self, x, t, epochs, batch, lr, lr_final=0.0, seed=0):
-        return fl_unet_train(self._u, x, t, epochs, batch, lr, lr_final, seed)
+    def train(self, x, t, epochs, batch, lr, lr_final=0.0, seed=0, ops=None):
+        """ops: None, or per sample an Operator (or handle) for the energy-norm loss."""
+        if ops is not None:
+            ops = [o.handle if hasattr(o, "handle") else o for o in ops]
+        return fl_unet_train(self._u, x, t, epochs, batch, lr, lr_final, seed, ops)
 
     def apply(self, r, n, alpha, z=None, stream=None):
         import torch

@@ -50,7 +50,7 @@ def _samples(seed, nb, H, smooth=True):
     for b in range(nb):
         n = H - 1
         r = inputs.gauss_sum(2, n + 1, 4, seed * 100 + b).reshape(n, n) if smooth else rng.normal(size=(n, n))
-        r = r / np.linalg.norm(r)
+        r = r * n / np.linalg.norm(r)
         x[b, :n, :n, 0] = r
         x[b, :, :, 1] = rng.uniform(0.3, 1.9)
     t = rng.normal(size=(nb, H, H)).astype(np.float32)
@@ -202,7 +202,7 @@ def test_pack_vs_oracle(fl):
         xr = ounet.net_input(rs[k].reshape(n, n), H, alphas[k])
         assert np.abs(x[k] - xr).max() <= 1e-7 * np.abs(xr).max()
         tr = np.zeros((H, H))
-        tr[:n, :n] = sols[k].reshape(n, n) / np.linalg.norm(rs[k])
+        tr[:n, :n] = sols[k].reshape(n, n) * n / np.linalg.norm(rs[k])
         assert np.abs(t[k] - tr).max() <= 1e-7 * np.abs(tr).max()
 
 
@@ -292,3 +292,61 @@ def test_fpcg_rejects(fl):
     op3.set_preconditioner(fl.UNet(16, max_batch=1))
     with pytest.raises(fl.FlError):
         op3.poisson_solve(_f64(np.ones(15 ** 3)), tol=1e-8, solver="fpcg")
+
+
+def test_energy_loss_vs_oracle(fl):
+    """Energy-norm training loss (y - t, A (y - t)) / (t, x0) on exact pairs, against the oracle's dense A."""
+    N, H = 32, 32
+    n = N - 1
+    net = fl.UNet(H, max_batch=4, seed=1, fp32_operands=True)
+    w = _weights(130)
+    net.set_weights(w)
+    alphas = [0.6, 1.7]
+    ops, dense, xs, ts, sops = [], [], [], [], []
+    for a in alphas:
+        ops.append(fl.Operator(2, a, 2.0 / N, N))
+        dense.append(oracle.dense(2, N, a, oracle.coeffs(2, a, 2.0 / N, N)))
+    for k in range(4):
+        j = k % 2
+        f = inputs.gauss_sum(2, N, 8, 131 + k)
+        u = oracle.solve_dense(dense[j], f)
+        x = ounet.net_input(f.reshape(n, n), H, alphas[j])
+        rms = np.linalg.norm(f) / n
+        tt = np.zeros((H, H))
+        tt[:n, :n] = u.reshape(n, n) / rms
+        xs.append(x)
+        ts.append(tt)
+        sops.append(ops[j])
+    X, T = np.array(xs), np.array(ts)
+    losses = net.train(_f32(X), _f32(T), epochs=1, batch=4, lr=1e-30, ops=sops)
+    y = ounet.forward(w.astype(np.float64), X)
+    ref = []
+    for k in range(4):
+        d = (y[k, :n, :n] - T[k, :n, :n]).ravel()
+        den = np.sum(T[k, :n, :n] * X[k, :n, :n, 0])
+        ref.append(d @ dense[k % 2] @ d / den)
+    assert abs(losses[0] - np.mean(ref)) <= 1e-4 * np.mean(ref), (losses[0], np.mean(ref))
+
+
+def test_c5_workload_sampled_residual(fl):
+    """Learned-preconditioner workload at full size (N = 256): a short training run on solver pairs,
+    then flexible PCG on held-out problems.  The converged solution's residual is checked on
+    sampled rows with the oracle's explicit sums."""
+    from paper_1804_02718_amd import learned
+    N = 256
+    net = fl.UNet(N, max_batch=16, seed=1)
+    x, t, alphas, mean_it = learned.make_pairs(net, N, 128)
+    losses = learned.train(net, x, t, epochs=2)
+    assert np.all(np.isfinite(losses)) and losses[-1] < 1.0
+    for sd in (900000, 900001):
+        alpha, f = inputs.learned_problem(sd, N=N)
+        op = fl.Operator(2, alpha, 2.0 / N, N)
+        op.set_preconditioner(net)
+        u, info = op.poisson_solve(_f64(f), tol=1e-8, solver="fpcg")
+        assert info["relres"] <= 1e-8
+        ug = u.cpu().numpy()
+        a = oracle.coeffs(2, alpha, 2.0 / N, N)
+        rows = np.random.default_rng(sd).choice(ug.size, 48, replace=False)
+        Au = oracle.apply_rows(2, N, alpha, a, ug, rows)
+        # each sampled residual entry is bounded by the global residual norm
+        assert np.linalg.norm(f[rows] - Au) <= 1.1e-8 * np.linalg.norm(f)
