@@ -51,6 +51,16 @@ struct BatchStrides {
 // tiled layout: row r of slab k = r / nj, line j = r mod nj, column kx = t*C + c
 // at ((k*ntiles + t)*nj + j)*C + c = rowbase(r) + t*(nj*C) + c (element offsets
 // stay below 2^31 for every supported size)
+// Workgroups are dispatched to the 8 XCDs round-robin (hardware id h runs on
+// XCD h mod 8), and each XCD has its own L2.  The row passes map h to a
+// logical block so that every XCD takes one contiguous run of row groups:
+// neighbouring rows of the tiled spectra share cache lines, which are then
+// fetched and written once per line instead of once per XCD.
+__device__ __forceinline__ int xcd_block(int h, int G) {
+    const int base = G >> 3, r = G & 7, x = h & 7;
+    return x * base + (x < r ? x : r) + (h >> 3);
+}
+
 __device__ __forceinline__ int tiled_rowbase(int r, int nj, int ntiles, int C) {
     const int k = r / nj, j = r - k * nj;
     return (k * ntiles * nj + j) * C;
@@ -74,7 +84,8 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xfwd(
     __shared__ C2<T> lds[LPB * PL];
     const int tl = threadIdx.x % TL;
     const int lp = threadIdx.x / TL;
-    const int ra = 2 * (blockIdx.x * LPB + lp), rb = ra + 1;
+    const int bx = xcd_block(blockIdx.x, gridDim.x);
+    const int ra = 2 * (bx * LPB + lp), rb = ra + 1;
     const bool va = ra < nrows, vb = rb < nrows;
     C2<T> tws[num_tw<PN>()];
     load_twiddles<T, P, PN>(tws, table, tl);
@@ -99,7 +110,7 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xfwd(
     // Hermitian split, written tile by tile: consecutive threads cover the
     // block's rows of one tile, which are contiguous in the tiled layout
     constexpr int RW = 2 * LPB, NTH = LPB * TL;
-    const int r0 = 2 * blockIdx.x * LPB;
+    const int r0 = 2 * bx * LPB;
     const int tstride = nj * C;
     if constexpr (NTH % (C * RW) == 0) {
         // a thread keeps one (row, column) and walks the tiles
@@ -155,7 +166,8 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xinv(
     __shared__ C2<T> lds[LPB * LL];
     const int tl = threadIdx.x % TL;
     const int lp = threadIdx.x / TL;
-    const int ra = 2 * (blockIdx.x * LPB + lp), rb = ra + 1;
+    const int bx = xcd_block(blockIdx.x, gridDim.x);
+    const int ra = 2 * (bx * LPB + lp), rb = ra + 1;
     const bool va = ra < nrows, vb = rb < nrows;
     C2<T> tws[num_tw<PN>()];
     load_twiddles<T, P, PN>(tws, table, tl);
@@ -163,7 +175,7 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xinv(
     // member w at p*LL + w*Q + kx
     constexpr int RW = 2 * LPB, NTH = LPB * TL;
     {
-        const int r0 = 2 * blockIdx.x * LPB;
+        const int r0 = 2 * bx * LPB;
         const int tstride = nj * C;
         if constexpr (NTH % (C * RW) == 0) {
             const int c = threadIdx.x % C, rr = (threadIdx.x / C) % RW;
@@ -428,7 +440,8 @@ template <typename T> struct Variant {
 #define FL_DEF(T, P, D)                                                                      \
     FL_VAR(T, P, D, (Shape<T, P, D>::E), (Shape<T, P, D>::E), (Shape<T, P, D>::C), (Shape<T, P, D>::LPB))
 
-// candidate variants per (precision, P, d); the first is the default
+// candidate variants per (precision, P, d); the first is the default (for the
+// sizes measured so far, the fastest one)
 template <typename T> static const Variant<T> *variants(int P, int d, int *count);
 
 template <> const Variant<float> *variants<float>(int P, int d, int *count) {
@@ -445,8 +458,9 @@ template <> const Variant<float> *variants<float>(int P, int d, int *count) {
     static const Variant<T> v2_1024[] = {FL_DEF(T, 1024, 2), FL_VAR(T, 1024, 2, 8, 8, 4, 2),
                                          FL_VAR(T, 1024, 2, 8, 8, 2, 2), FL_VAR(T, 1024, 2, 4, 4, 2, 1),
                                          FL_VAR(T, 1024, 2, 8, 16, 4, 2)};
-    static const Variant<T> v2_2048[] = {FL_DEF(T, 2048, 2),          FL_VAR(T, 2048, 2, 8, 8, 4, 1),
-                                         FL_VAR(T, 2048, 2, 8, 8, 2, 1), FL_VAR(T, 2048, 2, 8, 8, 2, 4),
+    // measured fastest first (MI355X, 2D N=1024): 8 points per thread on both axes, tiles of 2
+    static const Variant<T> v2_2048[] = {FL_VAR(T, 2048, 2, 8, 8, 2, 1), FL_DEF(T, 2048, 2),
+                                         FL_VAR(T, 2048, 2, 8, 8, 4, 1), FL_VAR(T, 2048, 2, 8, 8, 2, 4),
                                          FL_VAR(T, 2048, 2, 4, 4, 2, 1), FL_VAR(T, 2048, 2, 4, 8, 2, 1),
                                          FL_VAR(T, 2048, 2, 8, 16, 4, 1), FL_VAR(T, 2048, 2, 16, 8, 2, 2)};
     static const Variant<T> v3_8[] = {FL_DEF(T, 8, 3)};
@@ -455,8 +469,9 @@ template <> const Variant<float> *variants<float>(int P, int d, int *count) {
     static const Variant<T> v3_64[] = {FL_DEF(T, 64, 3)};
     static const Variant<T> v3_128[] = {FL_DEF(T, 128, 3)};
     static const Variant<T> v3_256[] = {FL_DEF(T, 256, 3), FL_VAR(T, 256, 3, 8, 8, 16, 2)};
-    static const Variant<T> v3_512[] = {FL_DEF(T, 512, 3), FL_VAR(T, 512, 3, 8, 8, 16, 4),
-                                        FL_VAR(T, 512, 3, 8, 8, 8, 4), FL_VAR(T, 512, 3, 16, 8, 16, 8),
+    // measured fastest first (MI355X, 3D N=256)
+    static const Variant<T> v3_512[] = {FL_VAR(T, 512, 3, 8, 8, 8, 4), FL_DEF(T, 512, 3),
+                                        FL_VAR(T, 512, 3, 8, 8, 16, 4), FL_VAR(T, 512, 3, 16, 8, 16, 8),
                                         FL_VAR(T, 512, 3, 8, 16, 16, 4)};
     static const Variant<T> v3_1024[] = {FL_DEF(T, 1024, 3)};
 #define FL_PICK(arr)                                  \
@@ -493,9 +508,10 @@ template <> const Variant<double> *variants<double>(int P, int d, int *count) {
                                         FL_VAR(T, 512, 2, 8, 8, 2, 2)};
     static const Variant<T> v2_1024[] = {FL_DEF(T, 1024, 2), FL_VAR(T, 1024, 2, 8, 8, 2, 2),
                                          FL_VAR(T, 1024, 2, 4, 4, 2, 1)};
-    static const Variant<T> v2_2048[] = {FL_DEF(T, 2048, 2), FL_VAR(T, 2048, 2, 8, 8, 2, 1),
-                                         FL_VAR(T, 2048, 2, 8, 8, 2, 2), FL_VAR(T, 2048, 2, 4, 4, 2, 1),
-                                         FL_VAR(T, 2048, 2, 8, 16, 2, 1)};
+    // measured fastest first (MI355X, 2D N=1024)
+    static const Variant<T> v2_2048[] = {FL_VAR(T, 2048, 2, 8, 16, 2, 1), FL_DEF(T, 2048, 2),
+                                         FL_VAR(T, 2048, 2, 8, 8, 2, 1), FL_VAR(T, 2048, 2, 8, 8, 2, 2),
+                                         FL_VAR(T, 2048, 2, 4, 4, 2, 1)};
     static const Variant<T> v3_8[] = {FL_DEF(T, 8, 3)};
     static const Variant<T> v3_16[] = {FL_DEF(T, 16, 3)};
     static const Variant<T> v3_32[] = {FL_DEF(T, 32, 3)};
