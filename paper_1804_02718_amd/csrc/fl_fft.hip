@@ -250,8 +250,15 @@ struct Strides {  // element offsets (below 2^31 for every supported size)
     int lam_tile, lam_outer;
 };
 
+// occupancy target of the strided pass (waves per SIMD): enough resident
+// workgroups that one launch of Q/C tiles runs in a single round
+template <typename T, int P, int E, int C> constexpr int strided_waves() {
+    return (sizeof(T) == 4 && P <= 512 && C * (P / E) == 512) ? 6 : 1;
+}
+
 template <typename T, int P, int E, int C, int MODE>
-__global__ __launch_bounds__(C * (P / E)) void k_strided(
+__global__ __launch_bounds__(C * (P / E)) __attribute__((amdgpu_waves_per_eu(strided_waves<T, P, E, C>())))
+void k_strided(
     const C2<T> *in, C2<T> *out, int ncols, int n_in, int n_out, Strides st, const C2<T> *__restrict__ table,
     const T *__restrict__ lam, const double *__restrict__ done, BatchStrides bz) {
     const int zb = blockIdx.z;
