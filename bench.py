@@ -48,9 +48,10 @@ def pass_bytes(d, n, Q, P, s):
     """Algorithmic bytes per pass (pass model: each pass reads its input once and
     writes its output once; lambda read once).  s = bytes per real."""
     if d == 2:
-        return [s * (n * n + 2 * Q * n),            # X-fwd: u in, half spectra out
-                s * (4 * Q * n + Q * Q),            # Y fused: spectra in/out, lambda
-                s * (2 * Q * n + n * n)]            # X-inv: spectra in, y out
+        # half spectra of real rows: P reals per row (DC and Nyquist packed)
+        return [s * (n * n + P * n),                # X-fwd: u in, half spectra out
+                s * (2 * P * n + Q * Q),            # Y fused: spectra in/out, lambda
+                s * (P * n + n * n)]                # X-inv: spectra in, y out
     return [s * (n ** 3 + 2 * Q * n * n),           # X-fwd
             s * (2 * Q * n * n + 2 * Q * P * n),    # Y-fwd
             s * (4 * Q * P * n + Q ** 3),           # Z fused
@@ -61,15 +62,17 @@ def pass_bytes(d, n, Q, P, s):
 PASS_NAMES = {2: ["x_fwd", "y_fused", "x_inv"], 3: ["x_fwd", "y_fwd", "z_fused", "y_inv", "x_inv"]}
 
 
-def kernel_instance(pass_name, T, P, var):
-    """Template instance of the kernel that runs a pass for a variant (as rocprofv3 names it)."""
+def kernel_instance(pass_name, T, P, var, d=2):
+    """Template instance of the kernel that runs a pass for a variant (as rocprofv3 names it);
+    the 2D path keeps packed DC/Nyquist columns (last template argument true)."""
     ex, ey, c, lpb = var["ex"], var["ey"], var["tile"], var["row_pairs"]
+    pack = "true" if d == 2 else "false"
     if pass_name == "x_fwd":
-        return "k_xfwd<%s, %d, %d, %d, %d>" % (T, P, ex, c, lpb)
+        return "k_xfwd<%s, %d, %d, %d, %d, %s>" % (T, P, ex, c, lpb, pack)
     if pass_name == "x_inv":
-        return "k_xinv<%s, %d, %d, %d, %d, false>" % (T, P, ex, c, lpb)
+        return "k_xinv<%s, %d, %d, %d, %d, false, %s>" % (T, P, ex, c, lpb, pack)
     mode = {"y_fused": 2, "z_fused": 2, "y_fwd": 0, "y_inv": 1}[pass_name]
-    return "k_strided<%s, %d, %d, %d, %d>" % (T, P, ey, c, mode)
+    return "k_strided<%s, %d, %d, %d, %d, %s>" % (T, P, ey, c, mode, pack if mode == 2 else "false")
 
 
 def time_matvec(op, u, y, steps, warmup, torch):
@@ -317,7 +320,7 @@ def main():
     dom = int(np.argmax(pass_ms))
     achieved = pb[dom] / (pass_ms[dom] * 1e-3) / 1e9
     var = op.variants("fp32")[0]
-    dom_kernel = kernel_instance(names[dom], "float", op.P, var)
+    dom_kernel = kernel_instance(names[dom], "float", op.P, var, d)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_entry(dom_kernel),
                 "kernel": dom_kernel, "pass": names[dom], "algorithmic_bytes": pb[dom],

@@ -68,9 +68,11 @@ __device__ __forceinline__ int tiled_rowbase(int r, int nj, int ntiles, int C) {
 
 // ---------------------------------------------------------------------------
 // row pass, forward: pairs of real rows (n_in values each, zero-padded to P)
-// -> Q half-spectrum values per row, written tiled.
+// -> Q half-spectrum values per row, written tiled.  With PACK the real DC and
+// Nyquist values of a row share column 0 as (X_0, X_{P/2}), leaving P/2
+// columns (the 2D path: P/2 columns fill whole tiles).
 // ---------------------------------------------------------------------------
-template <typename T, int P, int E, int C, int LPB>
+template <typename T, int P, int E, int C, int LPB, bool PACK>
 __global__ __launch_bounds__(LPB * (P / E)) void k_xfwd(
     const T *__restrict__ u, C2<T> *__restrict__ out, int nrows, int n_in, long in_pitch, int nj, int ntiles,
     const C2<T> *__restrict__ table, const double *__restrict__ done, BatchStrides bz) {
@@ -121,9 +123,15 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xfwd(
         C2<T> *orow = out + tiled_rowbase(row, nj, ntiles, C) + c;
         for (int t = threadIdx.x / (C * RW); t < ntiles; t += NTH / (C * RW)) {
             const int kx = t * C + c;
-            if (kx > P / 2) continue;
+            if (kx > P / 2 || (PACK && kx == P / 2)) continue;
             const C2<T> zk = lds[pb + padpos(kx)];
             const C2<T> zm = lds[pb + padpos((P - kx) & (P - 1))];
+            if (PACK && kx == 0) {
+                // X_0 and X_{P/2} of a real row are real: (Re or Im of Z_0, of Z_{P/2})
+                const C2<T> zn = lds[pb + padpos(P / 2)];
+                orow[0] = (rr & 1) ? mk<T>(zk.y, zn.y) : mk<T>(zk.x, zn.x);
+                continue;
+            }
             orow[t * tstride] = (rr & 1) ? mk<T>(T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x))
                                          : mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
         }
@@ -131,13 +139,17 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xfwd(
         for (int idx = threadIdx.x; idx < ntiles * RW * C; idx += NTH) {
             const int c = idx % C, rr = (idx / C) % RW, t = idx / (C * RW);
             const int kx = t * C + c, row = r0 + rr;
-            if (kx > P / 2 || row >= nrows) continue;
+            if (kx > P / 2 || (PACK && kx == P / 2) || row >= nrows) continue;
             const int pb = (rr >> 1) * PL;
             const C2<T> zk = lds[pb + padpos(kx)];
             const C2<T> zm = lds[pb + padpos((P - kx) & (P - 1))];
-            out[tiled_rowbase(row, nj, ntiles, C) + t * tstride + c] =
-                (rr & 1) ? mk<T>(T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x))
-                         : mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
+            C2<T> o = (rr & 1) ? mk<T>(T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x))
+                               : mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
+            if (PACK && kx == 0) {
+                const C2<T> zn = lds[pb + padpos(P / 2)];
+                o = (rr & 1) ? mk<T>(zk.y, zn.y) : mk<T>(zk.x, zn.x);
+            }
+            out[tiled_rowbase(row, nj, ntiles, C) + t * tstride + c] = o;
         }
     }
 }
@@ -147,8 +159,9 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xfwd(
 // first n_out kept.  With EPI, y = a1 w1 + a2 w2 + scale (A u), w1 / w2 read
 // at the same position when non-null (shifted operators and residuals of the
 // solvers).  A non-null `done` flag that is set makes the kernel a no-op.
+// PACK: column 0 holds (X_0, X_{P/2}) as written by k_xfwd<PACK>.
 // ---------------------------------------------------------------------------
-template <typename T, int P, int E, int C, int LPB, bool EPI>
+template <typename T, int P, int E, int C, int LPB, bool EPI, bool PACK>
 __global__ __launch_bounds__(LPB * (P / E)) void k_xinv(
     const C2<T> *__restrict__ in, T *__restrict__ y, int nrows, int n_out, long out_pitch, int nj, int ntiles,
     const C2<T> *__restrict__ table, Epi<T> ep, const double *__restrict__ done, BatchStrides bz) {
@@ -185,17 +198,28 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xinv(
             C2<T> *lrow = lds + (rr >> 1) * LL + (rr & 1) * Q;
             for (int t = threadIdx.x / (C * RW); t < ntiles; t += NTH / (C * RW)) {
                 const int kx = t * C + c;
-                if (kx >= Q) continue;
-                const C2<T> x = irow[t * tstride];
-                lrow[kx] = rv ? x : mk<T>(0, 0);
+                if (kx >= (PACK ? P / 2 : Q)) continue;
+                const C2<T> x = rv ? irow[t * tstride] : mk<T>(0, 0);
+                if (PACK && kx == 0) {
+                    lrow[0] = mk<T>(x.x, 0);
+                    lrow[P / 2] = mk<T>(x.y, 0);
+                } else {
+                    lrow[kx] = x;
+                }
             }
         } else {
             for (int idx = threadIdx.x; idx < ntiles * RW * C; idx += NTH) {
                 const int c = idx % C, rr = (idx / C) % RW, t = idx / (C * RW);
                 const int kx = t * C + c, row = r0 + rr;
-                if (kx >= Q) continue;
-                lds[(rr >> 1) * LL + (rr & 1) * Q + kx] =
-                    row < nrows ? in[tiled_rowbase(row, nj, ntiles, C) + t * tstride + c] : mk<T>(0, 0);
+                if (kx >= (PACK ? P / 2 : Q)) continue;
+                const C2<T> x = row < nrows ? in[tiled_rowbase(row, nj, ntiles, C) + t * tstride + c] : mk<T>(0, 0);
+                C2<T> *lrow = lds + (rr >> 1) * LL + (rr & 1) * Q;
+                if (PACK && kx == 0) {
+                    lrow[0] = mk<T>(x.x, 0);
+                    lrow[P / 2] = mk<T>(x.y, 0);
+                } else {
+                    lrow[kx] = x;
+                }
             }
         }
     }
@@ -248,16 +272,26 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xinv(
 struct Strides {  // element offsets (below 2^31 for every supported size)
     int in_outer, in_tile, out_outer, out_tile, line;
     int lam_tile, lam_outer;
+    int lam_pack = 0;  // PACK: offset of the (lambda_0 - lambda_{P/2}) / 2 column
 };
 
 // occupancy target of the strided pass (waves per SIMD): enough resident
-// workgroups that one launch of Q/C tiles runs in a single round
-template <typename T, int P, int E, int C> constexpr int strided_waves() {
-    return (sizeof(T) == 4 && P <= 512 && C * (P / E) == 512) ? 6 : 1;
+// workgroups that one launch of all tiles runs in a single round (2D P=2048:
+// 512 tiles of 8 waves, two per CU)
+template <typename T, int P, int E, int C, bool PACK> constexpr int strided_waves() {
+    if (sizeof(T) != 4 || C * (P / E) != 512 || E != 8) return 1;
+    return P == 512 ? (PACK ? 1 : 6) : (P == 2048 ? 4 : 1);
 }
 
-template <typename T, int P, int E, int C, int MODE>
-__global__ __launch_bounds__(C * (P / E)) __attribute__((amdgpu_waves_per_eu(strided_waves<T, P, E, C>())))
+// PACK (2D fused pass): column 0 of tile 0 carries two real columns, z = a + i b
+// with a = DC and b = Nyquist column of the row transform.  Their spectra
+// A, B are the even and odd parts of Z: A(k) = (Z(k) + conj Z(-k)) / 2 and
+// i B(k) = (Z(k) - conj Z(-k)) / 2, so lambda_0 A + i lambda_N B =
+// s(k) Z(k) + d(k) conj Z(-k) with s = (lambda_0 + lambda_N) / 2 (stored in
+// the tile) and d = (lambda_0 - lambda_N) / 2 (at lam_pack).  Both products
+// stay Hermitian, so the inverse again gives two real columns.
+template <typename T, int P, int E, int C, int MODE, bool PACK = false>
+__global__ __launch_bounds__(C * (P / E)) __attribute__((amdgpu_waves_per_eu(strided_waves<T, P, E, C, PACK>())))
 void k_strided(
     const C2<T> *in, C2<T> *out, int ncols, int n_in, int n_out, Strides st, const C2<T> *__restrict__ table,
     const T *__restrict__ lam, const double *__restrict__ done, BatchStrides bz) {
@@ -306,8 +340,27 @@ void k_strided(
 #pragma unroll
             for (int j = 0; j < E; ++j) lv[j] = lo[fold<P>(out_pos<P, PN, L - 1>(tl, j)) * C];
             fwd_stages<T, P, PN, 0>(v, lds, tl, tws, lidx);
+            if (PACK && t == 0) {  // block-uniform: the tile holding the packed column
+                T ldv[E];
 #pragma unroll
-            for (int j = 0; j < E; ++j) v[j] = cscale<T>(v[j], lv[j]);
+                for (int j = 0; j < E; ++j)
+                    ldv[j] = c == 0 ? lam[st.lam_pack + fold<P>(out_pos<P, PN, L - 1>(tl, j))] : T(0);
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < E; ++j) lds[lidx(out_pos<P, PN, L - 1>(tl, j))] = v[j];
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < E; ++j) {
+                    const int pos = out_pos<P, PN, L - 1>(tl, j);
+                    const C2<T> zm = lds[lidx((P - pos) & (P - 1))];
+                    v[j] = c == 0 ? mk<T>(lv[j] * v[j].x + ldv[j] * zm.x, lv[j] * v[j].y - ldv[j] * zm.y)
+                                  : cscale<T>(v[j], lv[j]);
+                }
+                __syncthreads();
+            } else {
+#pragma unroll
+                for (int j = 0; j < E; ++j) v[j] = cscale<T>(v[j], lv[j]);
+            }
             adj_stages<T, P, PN, L - 1>(v, lds, tl, tws, lidx);
         } else {
             fwd_stages<T, P, PN, 0>(v, lds, tl, tws, lidx);
@@ -343,33 +396,33 @@ static void launch(K kernel, dim3 g, dim3 b, hipStream_t s, const hipEvent_t *ev
         hipLaunchKernelGGL(kernel, g, b, 0, s, args...);
 }
 
-template <typename T, int P, int E, int C, int LPB>
+template <typename T, int P, int E, int C, int LPB, bool PACK = false>
 static void launch_xfwd(const T *u, C2<T> *out, int nrows, int n_in, long in_pitch, int nj, int ntiles,
                         const C2<T> *tw, const double *done, hipStream_t s, const hipEvent_t *ev, int nb = 1,
                         BatchStrides bz = BatchStrides{}) {
     const int pairs = (nrows + 1) / 2;
-    launch(k_xfwd<T, P, E, C, LPB>, dim3(cdiv(pairs, LPB), 1, nb), dim3(LPB * (P / E)), s, ev, u, out, nrows, n_in,
+    launch(k_xfwd<T, P, E, C, LPB, PACK>, dim3(cdiv(pairs, LPB), 1, nb), dim3(LPB * (P / E)), s, ev, u, out, nrows, n_in,
            in_pitch, nj, ntiles, tw, done, bz);
 }
 
-template <typename T, int P, int E, int C, int LPB>
+template <typename T, int P, int E, int C, int LPB, bool PACK = false>
 static void launch_xinv(const C2<T> *in, T *y, int nrows, int n_out, long out_pitch, int nj, int ntiles,
                         const C2<T> *tw, const Epi<T> &ep, const double *done, hipStream_t s, const hipEvent_t *ev,
                         int nb = 1, BatchStrides bz = BatchStrides{}) {
     const int pairs = (nrows + 1) / 2;
     if (ep.active())
-        launch(k_xinv<T, P, E, C, LPB, true>, dim3(cdiv(pairs, LPB), 1, nb), dim3(LPB * (P / E)), s, ev, in, y,
-               nrows, n_out, out_pitch, nj, ntiles, tw, ep, done, bz);
+        launch(k_xinv<T, P, E, C, LPB, true, PACK>, dim3(cdiv(pairs, LPB), 1, nb), dim3(LPB * (P / E)), s, ev, in,
+               y, nrows, n_out, out_pitch, nj, ntiles, tw, ep, done, bz);
     else
-        launch(k_xinv<T, P, E, C, LPB, false>, dim3(cdiv(pairs, LPB), 1, nb), dim3(LPB * (P / E)), s, ev, in, y,
-               nrows, n_out, out_pitch, nj, ntiles, tw, ep, done, bz);
+        launch(k_xinv<T, P, E, C, LPB, false, PACK>, dim3(cdiv(pairs, LPB), 1, nb), dim3(LPB * (P / E)), s, ev, in,
+               y, nrows, n_out, out_pitch, nj, ntiles, tw, ep, done, bz);
 }
 
-template <typename T, int P, int E, int C, int MODE>
+template <typename T, int P, int E, int C, int MODE, bool PACK = false>
 static void launch_strided(const C2<T> *in, C2<T> *out, int ncols, int nouter, int n_in, int n_out,
                            const Strides &st, const C2<T> *tw, const T *lam, const double *done, hipStream_t s,
                            const hipEvent_t *ev, int nb = 1, BatchStrides bz = BatchStrides{}) {
-    launch(k_strided<T, P, E, C, MODE>, dim3(cdiv(ncols, C), nouter, nb), dim3(C * (P / E)), s, ev, in, out, ncols,
+    launch(k_strided<T, P, E, C, MODE, PACK>, dim3(cdiv(ncols, C), nouter, nb), dim3(C * (P / E)), s, ev, in, out, ncols,
            n_in, n_out, st, tw, lam, done, bz);
 }
 
@@ -403,7 +456,7 @@ template <typename T, int P, int D, int EX, int EY, int C, int LPB>
 static void matvec_v(const MvCtx<T> &cx, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
                      const hipEvent_t *ev) {
     const int n = cx.n, Q = cx.Q;
-    const int nt = cdiv(Q, C);
+    const int nt = cdiv(spec_cols(D, P), C);
     C2<T> *T1 = (C2<T> *)cx.T1;
     C2<T> *T2 = (C2<T> *)cx.T2;
     const C2<T> *tw = cx.tw;
@@ -414,12 +467,12 @@ static void matvec_v(const MvCtx<T> &cx, const T *u, T *y, const Epi<T> &ep, con
     auto E = [&](int i) { return ev ? ev + 2 * i : nullptr; };
     BatchStrides b_in{cx.zs_vec, zt1, 0, cx.zs_done};
     if constexpr (D == 2) {
-        launch_xfwd<T, P, EX, C, LPB>(u, T1, n, n, n, n, nt, tw, done, s, E(0), nb, b_in);
-        Strides sy{0, n * C, 0, n * C, C, Q * C, 0};
-        launch_strided<T, P, EY, C, 2>(T1, T1, Q, 1, n, n, sy, tw, lam, done, s, E(1), nb,
-                                       BatchStrides{zt1, zt1, cx.zs_lam, cx.zs_done});
-        launch_xinv<T, P, EX, C, LPB>(T1, y, n, n, n, n, nt, tw, ep, done, s, E(2), nb,
-                                      BatchStrides{zt1, cx.zs_vec, 0, cx.zs_done});
+        launch_xfwd<T, P, EX, C, LPB, true>(u, T1, n, n, n, n, nt, tw, done, s, E(0), nb, b_in);
+        Strides sy{0, n * C, 0, n * C, C, Q * C, 0, nt * Q * C};
+        launch_strided<T, P, EY, C, 2, true>(T1, T1, P / 2, 1, n, n, sy, tw, lam, done, s, E(1), nb,
+                                             BatchStrides{zt1, zt1, cx.zs_lam, cx.zs_done});
+        launch_xinv<T, P, EX, C, LPB, true>(T1, y, n, n, n, n, nt, tw, ep, done, s, E(2), nb,
+                                            BatchStrides{zt1, cx.zs_vec, 0, cx.zs_done});
     } else {
         const long nn = (long)n * n;
         launch_xfwd<T, P, EX, C, LPB>(u, T1, (int)nn, n, n, n, nt, tw, done, s, E(0), nb, b_in);
@@ -614,19 +667,28 @@ VariantDesc variant_desc(fl_op op, int prec, int k) {
     return k >= 0 && k < n ? v[k].desc : VariantDesc{0, 0, 0, 0};
 }
 
-// tiled lambda for the fused pass: 2D [t][ky][c], 3D [t][ky][kz][c]; zero past Q
+// tiled lambda for the fused pass: 2D [t][ky][c], 3D [t][ky][kz][c]; zero past
+// the stored columns.  2D (packed columns): column 0 holds (lambda_0 +
+// lambda_{P/2}) / 2 and Q more entries after the tiles hold
+// (lambda_0 - lambda_{P/2}) / 2, per ky.
 template <typename T>
 __global__ void k_tile_lambda(const double *__restrict__ lam64, T *__restrict__ lt, int d, int Q, int C, int ntiles) {
-    const long total = d == 2 ? (long)ntiles * Q * C : (long)ntiles * Q * Q * C;
+    const long tiles = d == 2 ? (long)ntiles * Q * C : (long)ntiles * Q * Q * C;
+    const long total = d == 2 ? tiles + Q : tiles;
+    const int N2 = Q - 1;  // P / 2
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (long)gridDim.x * blockDim.x) {
         const int c = (int)(idx % C);
         long rest = idx / C;
         double v = 0.0;
-        if (d == 2) {
+        if (d == 2 && idx >= tiles) {
+            const long ky = idx - tiles;
+            v = 0.5 * (lam64[ky * Q] - lam64[ky * Q + N2]);
+        } else if (d == 2) {
             const long ky = rest % Q, t = rest / Q;
             const long kx = t * C + c;
-            if (kx < Q) v = lam64[ky * Q + kx];
+            if (kx == 0) v = 0.5 * (lam64[ky * Q] + lam64[ky * Q + N2]);
+            else if (kx < N2) v = lam64[ky * Q + kx];
         } else {
             const long kz = rest % Q;
             rest /= Q;
@@ -640,8 +702,8 @@ __global__ void k_tile_lambda(const double *__restrict__ lam64, T *__restrict__ 
 
 // lambda of one operator tiled to width C into lt (FP32 or FP64)
 fl_status tile_lambda(fl_op op, int prec, int C, void *lt, hipStream_t s) {
-    const int Q = op->Q, nt = cdiv(Q, C);
-    const long len = (op->d == 2 ? (long)Q : (long)Q * Q) * nt * C;
+    const int Q = op->Q, nt = cdiv(spec_cols(op->d, op->P), C);
+    const long len = lam_tiled_len(op->d, op->P, C);
     const int g = cdiv(len, 256) > 65536 ? 65536 : cdiv(len, 256);
     if (prec == FL_FP32)
         hipLaunchKernelGGL(k_tile_lambda<float>, dim3(g), dim3(256), 0, s, op->lam64, (float *)lt, op->d, Q, C, nt);
@@ -659,8 +721,8 @@ fl_status select_variant(fl_op op, int prec, int k, hipStream_t s) {
         return FL_E_INVAL;
     }
     const VariantDesc vd = variant_desc(op, prec, k);
-    const int Q = op->Q, nt = cdiv(Q, vd.c);
-    const long len = (op->d == 2 ? (long)Q : (long)Q * Q) * nt * vd.c;
+    const int Q = op->Q, nt = cdiv(spec_cols(op->d, op->P), vd.c);
+    const long len = lam_tiled_len(op->d, op->P, vd.c);
     const int g = cdiv(len, 256) > 65536 ? 65536 : cdiv(len, 256);
     if (prec == FL_FP32)
         hipLaunchKernelGGL(k_tile_lambda<float>, dim3(g), dim3(256), 0, s, op->lam64, op->lam32t, op->d, Q, vd.c, nt);

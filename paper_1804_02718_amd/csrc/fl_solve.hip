@@ -687,9 +687,8 @@ static void batch_free(fl_batch b) {
 static fl_status batch_alloc(BatchClass &c, int d) {
     const long B = c.B, M = c.M;
     const int C32 = variant_desc_pd(c.P, d, FL_FP32, c.var32).c, C64 = variant_desc_pd(c.P, d, FL_FP64, c.var64).c;
-    const long qrest = d == 2 ? c.Q : (long)c.Q * c.Q;
-    c.lamlen32 = qrest * ((c.Q + C32 - 1) / C32) * C32;
-    c.lamlen64 = qrest * ((c.Q + C64 - 1) / C64) * C64;
+    c.lamlen32 = lam_tiled_len(d, c.P, C32);
+    c.lamlen64 = lam_tiled_len(d, c.P, C64);
     c.zs_t = c.ops[0]->T1_bytes;
     c.zs_t2 = c.ops[0]->T2_bytes;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
