@@ -306,9 +306,17 @@ void k_strided(
     __shared__ C2<T> lds[C * PL];
     const int c = threadIdx.x % C;
     const int tl = threadIdx.x / C;
-    const int t = blockIdx.x;
+    // 3D: (tile, outer) from the XCD-aware order with the outer index fastest,
+    // since the C-wide chunks of neighbouring outer indices share cache lines
+    // (Z pass); a single outer index (2D) keeps the launch order
+    const int G = gridDim.x * gridDim.y;
+    int t = blockIdx.x, o = 0;
+    if (gridDim.y > 1) {
+        const int lb = xcd_block(blockIdx.x + gridDim.x * blockIdx.y, G);
+        t = lb / gridDim.y;
+        o = lb - t * gridDim.y;
+    }
     const bool valid = t * C + c < ncols;
-    const int o = blockIdx.y;
     // columns past ncols still lie inside the tile; their loads are discarded
     const C2<T> *src = in + (o * st.in_outer + t * st.in_tile + c);
     C2<T> *dst = out + (o * st.out_outer + t * st.out_tile + c);
@@ -518,11 +526,12 @@ template <> const Variant<float> *variants<float>(int P, int d, int *count) {
     static const Variant<T> v2_1024[] = {FL_DEF(T, 1024, 2), FL_VAR(T, 1024, 2, 8, 8, 4, 2),
                                          FL_VAR(T, 1024, 2, 8, 8, 2, 2), FL_VAR(T, 1024, 2, 4, 4, 2, 1),
                                          FL_VAR(T, 1024, 2, 8, 16, 4, 2)};
-    // measured fastest first (MI355X, 2D N=1024): 8 points per thread on both axes, tiles of 2
-    static const Variant<T> v2_2048[] = {FL_VAR(T, 2048, 2, 8, 8, 2, 1), FL_DEF(T, 2048, 2),
-                                         FL_VAR(T, 2048, 2, 8, 8, 4, 1), FL_VAR(T, 2048, 2, 8, 8, 2, 4),
-                                         FL_VAR(T, 2048, 2, 4, 4, 2, 1), FL_VAR(T, 2048, 2, 4, 8, 2, 1),
-                                         FL_VAR(T, 2048, 2, 8, 16, 4, 1), FL_VAR(T, 2048, 2, 16, 8, 2, 2)};
+    // measured fastest first (MI355X, 2D N=1024): 8 points per thread in the row
+    // passes, 16 in the fused pass over 256 tiles of 4 columns (one per CU)
+    static const Variant<T> v2_2048[] = {FL_VAR(T, 2048, 2, 8, 16, 4, 1), FL_VAR(T, 2048, 2, 8, 8, 2, 1),
+                                         FL_DEF(T, 2048, 2),             FL_VAR(T, 2048, 2, 8, 8, 4, 1),
+                                         FL_VAR(T, 2048, 2, 8, 8, 2, 4), FL_VAR(T, 2048, 2, 4, 4, 2, 1),
+                                         FL_VAR(T, 2048, 2, 4, 8, 2, 1), FL_VAR(T, 2048, 2, 16, 8, 2, 2)};
     static const Variant<T> v3_8[] = {FL_DEF(T, 8, 3)};
     static const Variant<T> v3_16[] = {FL_DEF(T, 16, 3)};
     static const Variant<T> v3_32[] = {FL_DEF(T, 32, 3)};
