@@ -121,9 +121,14 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xfwd(
         if (row >= nrows) return;
         const int pb = (rr >> 1) * PL;
         C2<T> *orow = out + tiled_rowbase(row, nj, ntiles, C) + c;
-        for (int t = threadIdx.x / (C * RW); t < ntiles; t += NTH / (C * RW)) {
+        // tile count and walk are compile-time: the loop unrolls to constant offsets
+        constexpr int NT = ((PACK ? P / 2 : P / 2 + 1) + C - 1) / C, ST = NTH / (C * RW);
+        const int t0 = threadIdx.x / (C * RW);
+#pragma unroll
+        for (int it = 0; it < (NT + ST - 1) / ST; ++it) {
+            const int t = t0 + it * ST;
             const int kx = t * C + c;
-            if (kx > P / 2 || (PACK && kx == P / 2)) continue;
+            if (t >= NT || kx > P / 2 || (PACK && kx == P / 2)) continue;
             const C2<T> zk = lds[pb + padpos(kx)];
             const C2<T> zm = lds[pb + padpos((P - kx) & (P - 1))];
             if (PACK && kx == 0) {
@@ -196,9 +201,13 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xinv(
             const bool rv = row < nrows;
             const C2<T> *irow = in + tiled_rowbase(rv ? row : 0, nj, ntiles, C) + c;
             C2<T> *lrow = lds + (rr >> 1) * LL + (rr & 1) * Q;
-            for (int t = threadIdx.x / (C * RW); t < ntiles; t += NTH / (C * RW)) {
+            constexpr int NT = ((PACK ? P / 2 : P / 2 + 1) + C - 1) / C, ST = NTH / (C * RW);
+            const int t0 = threadIdx.x / (C * RW);
+#pragma unroll
+            for (int it = 0; it < (NT + ST - 1) / ST; ++it) {
+                const int t = t0 + it * ST;
                 const int kx = t * C + c;
-                if (kx >= (PACK ? P / 2 : Q)) continue;
+                if (t >= NT || kx >= (PACK ? P / 2 : Q)) continue;
                 const C2<T> x = rv ? irow[t * tstride] : mk<T>(0, 0);
                 if (PACK && kx == 0) {
                     lrow[0] = mk<T>(x.x, 0);
