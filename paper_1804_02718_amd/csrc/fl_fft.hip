@@ -176,6 +176,7 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xinv(
     y += z * bz.out;
     if (ep.w1) ep.w1 += z * bz.out;
     if (ep.w2) ep.w2 += z * bz.out;
+    if (ep.dotw) ep.dotw += z * bz.out;
     using PN = Plan<P, E>;
     constexpr int TL = P / E, L = PN::L;
     constexpr int PL = padded_len<P>();
@@ -248,26 +249,46 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xinv(
     const int base = lp * LL;
     auto lidx = [base](int pos) { return base + padpos(pos); };
     adj_stages<T, P, PN, L - 1>(v, lds, tl, tws, lidx);
-    if (!va) return;
-    T *ya = y + (long)ra * out_pitch, *yb = y + (long)rb * out_pitch;
+    double acc = 0.0;  // epilogue dot (dotw, y) over this thread's outputs
+    if (va) {
+        T *ya = y + (long)ra * out_pitch, *yb = y + (long)rb * out_pitch;
 #pragma unroll
-    for (int j = 0; j < E; ++j) {
-        const int pos = in_pos<P, PN, 0>(tl, j);
-        if (pos < n_out) {
-            T a = v[j].x, b = v[j].y;
-            if constexpr (EPI) {
-                const long ia2 = (long)ra * out_pitch + pos, ib2 = (long)rb * out_pitch + pos;
-                a = ep.scale * a;
-                if (ep.w1) a += ep.a1 * ep.w1[ia2];
-                if (ep.w2) a += ep.a2 * ep.w2[ia2];
-                if (vb) {
-                    b = ep.scale * b;
-                    if (ep.w1) b += ep.a1 * ep.w1[ib2];
-                    if (ep.w2) b += ep.a2 * ep.w2[ib2];
+        for (int j = 0; j < E; ++j) {
+            const int pos = in_pos<P, PN, 0>(tl, j);
+            if (pos < n_out) {
+                T a = v[j].x, b = v[j].y;
+                if constexpr (EPI) {
+                    const long ia2 = (long)ra * out_pitch + pos, ib2 = (long)rb * out_pitch + pos;
+                    a = ep.scale * a;
+                    if (ep.w1) a += ep.a1 * ep.w1[ia2];
+                    if (ep.w2) a += ep.a2 * ep.w2[ia2];
+                    if (vb) {
+                        b = ep.scale * b;
+                        if (ep.w1) b += ep.a1 * ep.w1[ib2];
+                        if (ep.w2) b += ep.a2 * ep.w2[ib2];
+                    }
+                    if (ep.dpart) {
+                        acc += (double)a * (double)ep.dotw[ia2];
+                        if (vb) acc += (double)b * (double)ep.dotw[ib2];
+                    }
                 }
+                ya[pos] = a;
+                if (vb) yb[pos] = b;
             }
-            ya[pos] = a;
-            if (vb) yb[pos] = b;
+        }
+    }
+    if constexpr (EPI) {
+        if (ep.dpart) {  // block-uniform
+            __shared__ double wsum[(LPB * (P / E) + 63) / 64];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+            if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = acc;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double t = 0.0;
+                for (int w = 0; w < (NTH + 63) / 64; ++w) t += wsum[w];
+                ep.dpart[z * ep.dpart_stride + bx] = t;
+            }
         }
     }
 }
@@ -657,6 +678,12 @@ template fl_status matvec_ex<double>(fl_op, const double *, double *, const Epi<
                                      hipStream_t, hipEvent_t *);
 
 int kernel_p_supported(int P) { return P >= 8 && P <= 2048 && (P & (P - 1)) == 0; }
+
+int xinv_parts(int d, int n, int P, int prec, int variant) {
+    const VariantDesc vd = variant_desc_pd(P, d, prec, variant);
+    const long nrows = d == 2 ? (long)n : (long)n * n;
+    return vd.lpb > 0 ? cdiv((nrows + 1) / 2, vd.lpb) : 0;
+}
 
 int variant_count(fl_op op, int prec) {
     int n = 0;

@@ -285,8 +285,16 @@ template <typename T> struct Epi {
     const T *w2 = nullptr;
     T a2 = T(0);
     T scale = T(1);
-    bool active() const { return w1 != nullptr || w2 != nullptr || scale != T(1); }
+    // with dpart: each X-inverse workgroup b writes sum (dotw, y) over its rows,
+    // in FP64 and a fixed order, to dpart[z * dpart_stride + b] (z = problem)
+    const T *dotw = nullptr;
+    double *dpart = nullptr;
+    long dpart_stride = 0;
+    bool active() const { return w1 != nullptr || w2 != nullptr || scale != T(1) || dpart != nullptr; }
 };
+// number of X-inverse workgroups of a matvec (the partial sums an epilogue
+// dot writes): d, n, P, precision, kernel variant
+int xinv_parts(int d, int n, int P, int prec, int variant);
 template <typename T>
 fl_status matvec(fl_op op, const T *u, T *y, hipStream_t s);
 // `done`: optional device flag; when it holds a nonzero value every pass returns at once

@@ -285,14 +285,20 @@ static fl_status dot(fl_op op, const V *a, const V *b, double *part, double *out
     return FL_OK;
 }
 
-// K v = s0 v + s1 A v (epilogue of the last pass when s0 != 0 or s1 != 1)
+// K v = s0 v + s1 A v (epilogue of the last pass when s0 != 0 or s1 != 1);
+// with dpart, the last pass also leaves per-workgroup partials of (v, K v)
 template <typename V>
-static fl_status apply_K(fl_op op, const V *v, V *kv, double s0, double s1, const double *done, hipStream_t s) {
+static fl_status apply_K(fl_op op, const V *v, V *kv, double s0, double s1, const double *done, hipStream_t s,
+                         double *dpart = nullptr) {
     Epi<V> ep;
     ep.scale = (V)s1;
     if (s0 != 0.0) {
         ep.w1 = v;
         ep.a1 = (V)s0;
+    }
+    if (dpart) {
+        ep.dotw = v;
+        ep.dpart = dpart;
     }
     return matvec_ex<V>(op, v, kv, ep, done, s);
 }
@@ -330,6 +336,10 @@ static fl_status cg_run(fl_op op, double s0, double s1, V *d, V *r, V *p, V *kp,
                        (const double *)nullptr);
     FL_HIP_TRY(hipGetLastError());
     const double *done = op->scal + S_DONE;
+    // (p, Kp) from the matvec's last pass when its workgroups fit the partials array
+    const int np_x = xinv_parts(op->d, op->n, op->P, sizeof(V) == 8 ? FL_FP64 : FL_FP32,
+                                sizeof(V) == 8 ? op->var64 : op->var32);
+    const bool fused = np_x > 0 && np_x <= kMaxParts;
     int launched = 0;
     int chunk = check_every > 0 ? check_every : 8;
     res->iters = 0;
@@ -338,10 +348,12 @@ static fl_status cg_run(fl_op op, double s0, double s1, V *d, V *r, V *p, V *kp,
         const int k = chunk < max_it - launched ? chunk : max_it - launched;
         for (int i = 0; i < k; ++i) {
             const int parity = (launched + i) & 1;
-            FL_TRY(apply_K<V>(op, p, kp, s0, s1, done, s));
-            hipLaunchKernelGGL(k_dot<V>, dim3(L.blocks), dim3(kVecBlock), 0, s, p, kp, L.n, L.chunk, w.partA, done);
+            FL_TRY(apply_K<V>(op, p, kp, s0, s1, done, s, fused ? w.partA : nullptr));
+            if (!fused)
+                hipLaunchKernelGGL(k_dot<V>, dim3(L.blocks), dim3(kVecBlock), 0, s, p, kp, L.n, L.chunk, w.partA,
+                                   done);
             hipLaunchKernelGGL(k_cg_xr<V>, dim3(L.blocks), dim3(kVecBlock), 0, s, d, r, p, kp, L.n, L.chunk,
-                               w.partA, L.blocks, w.partB, op->scal, parity);
+                               w.partA, fused ? np_x : L.blocks, w.partB, op->scal, parity);
             hipLaunchKernelGGL(k_cg_p<V>, dim3(L.blocks), dim3(kVecBlock), 0, s, p, r, L.n, L.chunk, w.partB,
                                L.blocks, op->scal, parity);
         }
