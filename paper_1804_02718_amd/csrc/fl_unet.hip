@@ -346,18 +346,29 @@ __global__ void k_loss_grad(const float *__restrict__ Y, int ys, const float *__
         dY[i] = ch == 0 ? 2.f * (Y[i] - T[p]) / (tot[2 * (p / pix) + 1] * nb) : 0.f;
     }
 }
-// squared norm of x[0..n) into out[0] (one block, fixed order)
-__global__ __launch_bounds__(256) void k_sumsq(const double *__restrict__ x, long n, double *__restrict__ out) {
+// squared norm of x[0..n): kSqParts workgroups sum contiguous chunks into
+// part[], then one workgroup adds the partials in order (fixed order)
+constexpr int kSqParts = 64;
+__global__ __launch_bounds__(256) void k_sumsq_part(const double *__restrict__ x, long n, double *__restrict__ part) {
     __shared__ double sh[256];
+    const long chunk = (n + gridDim.x - 1) / gridDim.x;
+    const long beg = (long)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
     double a = 0.0;
-    for (long i = threadIdx.x; i < n; i += 256) a += x[i] * x[i];
+    for (long i = beg + threadIdx.x; i < end; i += 256) a += x[i] * x[i];
     sh[threadIdx.x] = a;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
         if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[0] = sh[0];
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+__global__ void k_sumsq_final(const double *__restrict__ part, int np, double *__restrict__ out) {
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < np; ++i) t += part[i];
+        out[0] = t;
+    }
 }
 
 // Adam on FP32 master weights; refreshes the operand copies W [cout][Kp] and W^T [Kp][coutp]
@@ -475,6 +486,124 @@ __global__ void k_gather(const float *__restrict__ src, const long *__restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Fused convolution for inference: implicit GEMM straight from the NHWC
+// activations.  A workgroup (4 waves) owns an 8 x 8 tile of output pixels of
+// one sample and all output channels.  It stages the input halo
+// (8+KS-1)^2 x cin in LDS as GEMM operands, forming the input on the fly:
+//   SRC_PLAIN  X[y][x][ci]
+//   SRC_POOL   the 2 x 2 average of a source at twice the resolution
+//   SRC_CATUP  channels [0, ca) from a source at half the resolution (nearest
+//              upsampling), channels [ca, cin) from a source at this one.
+// Wave w computes pixels 16w..16w+15 against every output channel with the
+// same MFMA tiles and k order (k = tap*cin + ci, steps of 16) as k_gemm_nt on
+// im2row rows.  cin is a multiple of 16, except the 2-channel first layer
+// (GENERIC), whose k steps cross taps.
+// ---------------------------------------------------------------------------
+enum { SRC_PLAIN = 0, SRC_POOL = 1, SRC_CATUP = 2 };
+
+struct ConvSrc {
+    const float *a = nullptr, *b = nullptr;  // sources (b: the second one of SRC_CATUP)
+    int csa = 0, csb = 0;                    // channel pitches
+    int ca = 0;                              // SRC_CATUP: channels taken from a
+};
+
+template <typename T, int MODE, int KS, int CIN, int COUTP>
+__global__ __launch_bounds__(256) void k_conv_fused(ConvSrc src, int H, int W, const T *__restrict__ Wb,
+                                                    float *__restrict__ Y, int relu) {
+    constexpr int TS = 8, HH = TS + KS - 1, HK = KS / 2;
+    constexpr bool GENERIC = CIN % 16 != 0;  // the 2-channel first layer
+    constexpr int K = KS * KS * CIN, Kp = (K + 15) / 16 * 16, NTN = COUTP / 16;
+    constexpr int CV = CIN % 4 == 0 ? 4 : 1;  // channels staged per thread and step
+    __shared__ T tile[HH * HH * CIN];
+    const int b = blockIdx.z;
+    const int tx0 = blockIdx.x * TS, ty0 = blockIdx.y * TS;
+    // stage the halo, CV channels at a time
+    for (int e = threadIdx.x; e < HH * HH * (CIN / CV); e += 256) {
+        const int cg = e % (CIN / CV), pix = e / (CIN / CV);
+        const int hx = pix % HH, hy = pix / HH;
+        const int y = ty0 + hy - HK, x = tx0 + hx - HK;
+        float v[CV];
+#pragma unroll
+        for (int i = 0; i < CV; ++i) v[i] = 0.f;
+        if (y >= 0 && y < H && x >= 0 && x < W) {
+            const int ci = cg * CV;
+            if (MODE == SRC_PLAIN) {
+                const float *q = src.a + (((long)b * H + y) * W + x) * src.csa + ci;
+#pragma unroll
+                for (int i = 0; i < CV; ++i) v[i] = q[i];
+            } else if (MODE == SRC_POOL) {
+                const int W2 = 2 * W;
+                const float *q = src.a + (((long)b * 2 * H + 2 * y) * W2 + 2 * x) * src.csa + ci;
+                const long dy = (long)W2 * src.csa;
+#pragma unroll
+                for (int i = 0; i < CV; ++i) v[i] = 0.25f * (q[i] + q[src.csa + i] + q[dy + i] + q[dy + src.csa + i]);
+            } else {
+                const float *q = ci < src.ca
+                                     ? src.a + (((long)b * (H / 2) + y / 2) * (W / 2) + x / 2) * src.csa + ci
+                                     : src.b + (((long)b * H + y) * W + x) * src.csb + (ci - src.ca);
+#pragma unroll
+                for (int i = 0; i < CV; ++i) v[i] = q[i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < CV; ++i) tile[pix * CIN + cg * CV + i] = to_op<T>(v[i]);
+    }
+    __syncthreads();
+    using V = typename std::conditional<sizeof(T) == 2, v4s, v4f>::type;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    const int m = 16 * wave + r;  // this lane's pixel for the A operand
+    const int pbase = ((m / TS) * HH + (m % TS)) * CIN;
+    v4f acc[NTN];
+#pragma unroll
+    for (int j = 0; j < NTN; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 6
+    for (int k0 = 0; k0 < Kp; k0 += 16) {
+        V bv[NTN];
+#pragma unroll
+        for (int j = 0; j < NTN; ++j) bv[j] = *(const V *)(Wb + (16 * j + r) * Kp + k0 + 4 * q);
+        V a;
+        if constexpr (GENERIC) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = k0 + 4 * q + i;
+                T t = to_op<T>(0.f);
+                if (k < K) {
+                    const int tap = k / CIN, ci = k % CIN;
+                    t = tile[pbase + ((tap / KS) * HH + (tap % KS)) * CIN + ci];
+                }
+                if constexpr (sizeof(T) == 2) a[i] = (short)t;
+                else a[i] = t;
+            }
+        } else {
+            const int tap = k0 / CIN;
+            a = *(const V *)(tile + pbase + ((tap / KS) * HH + (tap % KS)) * CIN + (k0 - tap * CIN) + 4 * q);
+        }
+#pragma unroll
+        for (int j = 0; j < NTN; ++j) {
+            if constexpr (sizeof(T) == 2) {
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv[j], acc[j], 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], bv[j][e], acc[j], 0, 0, 0);
+            }
+        }
+    }
+    // D rows 4q+i are pixels 16w+4q+i, column r is channel 16j+r
+#pragma unroll
+    for (int j = 0; j < NTN; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int mm = 16 * wave + 4 * q + i;
+            const int y = ty0 + mm / TS, x = tx0 + mm % TS;
+            if (y >= H || x >= W) continue;
+            float v = acc[j][i];
+            if (relu) v = v > 0.f ? v : 0.f;
+            Y[(((long)b * H + y) * W + x) * COUTP + 16 * j + r] = v;
+        }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 struct Conv {
@@ -504,6 +633,8 @@ struct fl_unet_s {
     float *colbuf = nullptr, *part = nullptr, *lossbuf = nullptr, *lpart = nullptr, *ltot = nullptr;
     size_t row_elems = 0, col_elems = 0, part_elems = 0;
     double *nrm = nullptr;
+    double *sqpart = nullptr;           // partial sums of squared norms
+    hipEvent_t ev = nullptr;            // joins the caller's stream and the network's
     long *idx = nullptr;                // minibatch indices (device)
     float *ebuf = nullptr;              // energy loss: d and A d (2 x H*W floats)
     hipStream_t s = nullptr;
@@ -673,6 +804,42 @@ static void refresh_t(fl_unet u, float lr) {
         off += n;
     }
 }
+// one workgroup per 8 x 8 tile of output pixels and sample
+template <typename T, int MODE, int KS, int CIN, int COUTP>
+static void conv_fused_launch(fl_unet u, int li, const ConvSrc &src, int h, int nb, float *Y, bool relu) {
+    dim3 g((h + 7) / 8, (h + 7) / 8, nb);
+    hipLaunchKernelGGL((k_conv_fused<T, MODE, KS, CIN, COUTP>), g, dim3(256), 0, u->s, src, h, h, wb_of<T>(u, li), Y,
+                       relu ? 1 : 0);
+}
+
+// forward for inference: one fused convolution per layer (pooling, upsampling
+// and concatenation folded into the operand staging); same results as the
+// im2row path (same bf16 operands, same MFMA k order)
+template <typename T>
+static void net_forward_fused_t(fl_unet u, int nb) {
+    const int H = u->H;
+    auto *A = u->A.data();
+    auto plain = [](const float *a, int cs) { ConvSrc s; s.a = a; s.csa = cs; return s; };
+    auto catup = [](const float *a, int csa, const float *b, int csb) {
+        ConvSrc s; s.a = a; s.csa = csa; s.ca = csa; s.b = b; s.csb = csb; return s;
+    };
+    conv_fused_launch<T, SRC_PLAIN, 3, 2, 16>(u, 0, plain(A[T_X0], 2), H, nb, A[T_A1], true);
+    conv_fused_launch<T, SRC_PLAIN, 3, 16, 16>(u, 1, plain(A[T_A1], 16), H, nb, A[T_S1], true);
+    conv_fused_launch<T, SRC_POOL, 3, 16, 32>(u, 2, plain(A[T_S1], 16), H / 2, nb, A[T_A2], true);
+    conv_fused_launch<T, SRC_PLAIN, 3, 32, 32>(u, 3, plain(A[T_A2], 32), H / 2, nb, A[T_S2], true);
+    conv_fused_launch<T, SRC_POOL, 3, 32, 64>(u, 4, plain(A[T_S2], 32), H / 4, nb, A[T_A3], true);
+    conv_fused_launch<T, SRC_PLAIN, 3, 64, 64>(u, 5, plain(A[T_A3], 64), H / 4, nb, A[T_B3], true);
+    conv_fused_launch<T, SRC_CATUP, 3, 96, 32>(u, 6, catup(A[T_B3], 64, A[T_S2], 32), H / 2, nb, A[T_A4], true);
+    conv_fused_launch<T, SRC_PLAIN, 3, 32, 32>(u, 7, plain(A[T_A4], 32), H / 2, nb, A[T_B4], true);
+    conv_fused_launch<T, SRC_CATUP, 3, 48, 16>(u, 8, catup(A[T_B4], 32, A[T_S1], 16), H, nb, A[T_A5], true);
+    conv_fused_launch<T, SRC_PLAIN, 3, 16, 16>(u, 9, plain(A[T_A5], 16), H, nb, A[T_B5], true);
+    conv_fused_launch<T, SRC_PLAIN, 1, 16, 16>(u, 10, plain(A[T_B5], 16), H, nb, A[T_Y], false);
+}
+static void net_forward_fused(fl_unet u, int nb) {
+    if (u->fp32) net_forward_fused_t<float>(u, nb);
+    else net_forward_fused_t<bf16>(u, nb);
+}
+
 static void net_forward(fl_unet u, int nb) {
     if (u->fp32) net_forward_t<float>(u, nb);
     else net_forward_t<bf16>(u, nb);
@@ -692,8 +859,11 @@ static void refresh_bf16(fl_unet u, float lr) {
 static fl_status train_step(fl_unet u, int nb, bool with_target, float lr, const fl_op *ops = nullptr) {
     const long pix = (long)u->H * u->W;
     hipStream_t s = u->s;
+    if (!with_target) {  // inference: fused convolutions
+        net_forward_fused(u, nb);
+        return FL_OK;
+    }
     net_forward(u, nb);
-    if (!with_target) return FL_OK;
     if (ops) {
         float *d = u->ebuf, *Ad = u->ebuf + pix;
         for (int z = 0; z < nb; ++z) {
@@ -808,9 +978,11 @@ fl_status fl_unet_create(int H, int max_batch, unsigned long long seed, int fp32
     AL((void **)&u->lpart, sizeof(float) * 2 * 64 * max_batch);
     AL((void **)&u->ltot, sizeof(float) * 2 * max_batch);
     AL((void **)&u->nrm, sizeof(double) * 8);
+    AL((void **)&u->sqpart, sizeof(double) * kSqParts);
     AL((void **)&u->idx, sizeof(long) * max_batch);
     AL((void **)&u->ebuf, sizeof(float) * 2 * (size_t)H * H);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&u->s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&u->ev, hipEventDisableTiming);
     if (e != hipSuccess) {
         set_error("fl_unet_create: %s", hipGetErrorString(e));
         fl_unet_destroy(u);
@@ -849,9 +1021,10 @@ fl_status fl_unet_destroy(fl_unet u) {
     if (!u) return FL_OK;
     for (void *p : {(void *)u->w, (void *)u->m, (void *)u->v, (void *)u->g, (void *)u->wb, (void *)u->wt,
                     (void *)u->act, (void *)u->rowbuf, (void *)u->tbuf, (void *)u->tbuf2, (void *)u->colbuf,
-                    (void *)u->part, (void *)u->lossbuf, (void *)u->lpart, (void *)u->ltot, (void *)u->nrm, (void *)u->idx, (void *)u->ebuf})
+                    (void *)u->part, (void *)u->lossbuf, (void *)u->lpart, (void *)u->ltot, (void *)u->nrm, (void *)u->sqpart, (void *)u->idx, (void *)u->ebuf})
         if (p) (void)hipFree(p);
     if (u->s) (void)hipStreamDestroy(u->s);
+    if (u->ev) (void)hipEventDestroy(u->ev);
     delete u;
     return FL_OK;
 }
@@ -919,7 +1092,8 @@ fl_status fl_unet_pack(fl_unet u, int count, const double *const *r, const doubl
     const long pix = (long)u->H * u->W;
     for (int z = 0; z < count; ++z) {
         if (!r[z]) { set_error("fl_unet_pack: NULL residual"); return FL_E_INVAL; }
-        hipLaunchKernelGGL(k_sumsq, dim3(1), dim3(256), 0, u->s, r[z], (long)n * n, u->nrm);
+        hipLaunchKernelGGL(k_sumsq_part, dim3(kSqParts), dim3(256), 0, u->s, r[z], (long)n * n, u->sqpart);
+        hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(64), 0, u->s, u->sqpart, kSqParts, u->nrm);
         hipLaunchKernelGGL(k_pack_sample, dim3(grid1(pix)), dim3(256), 0, u->s, r[z], sol ? sol[z] : nullptr, n, u->H,
                            u->W, (float)alpha[z], u->nrm, x + z * pix * 2, t ? t + z * pix : nullptr);
     }
@@ -986,17 +1160,15 @@ int unet_size(fl_unet u) { return u->H; }
 fl_status unet_apply(fl_unet u, const double *r, int n, double alpha, double *z, const double *rr_dev,
                      hipStream_t s) {
     const int H = u->H;
-    hipEvent_t e;
-    FL_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    hipEvent_t e = u->ev;
     FL_HIP_TRY(hipEventRecord(e, s));
     FL_HIP_TRY(hipStreamWaitEvent(u->s, e, 0));
     hipLaunchKernelGGL(k_net_input, dim3(grid1((long)H * H)), dim3(256), 0, u->s, r, n, H, H, (float)alpha, rr_dev,
                        u->A[T_X0]);
-    net_forward(u, 1);
+    net_forward_fused(u, 1);
     hipLaunchKernelGGL(k_net_output, dim3(grid1((long)n * n)), dim3(256), 0, u->s, u->A[T_Y], 16, n, H, rr_dev, z);
     FL_HIP_TRY(hipEventRecord(e, u->s));
     FL_HIP_TRY(hipStreamWaitEvent(s, e, 0));
-    (void)hipEventDestroy(e);
     FL_HIP_TRY(hipGetLastError());
     return FL_OK;
 }
@@ -1054,7 +1226,8 @@ extern "C" {
 fl_status fl_unet_apply(fl_unet u, const double *r, int n, double alpha, double *z, void *stream) {
     if (!u || !r || !z || n < 1 || n > u->H) { set_error("fl_unet_apply: bad argument"); return FL_E_INVAL; }
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_sumsq, dim3(1), dim3(256), 0, s, r, (long)n * n, u->nrm);
+    hipLaunchKernelGGL(k_sumsq_part, dim3(kSqParts), dim3(256), 0, s, r, (long)n * n, u->sqpart);
+    hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(64), 0, s, u->sqpart, kSqParts, u->nrm);
     FL_TRY(unet_apply(u, r, n, alpha, z, u->nrm, s));
     FL_HIP_TRY(hipStreamSynchronize(s));
     return FL_OK;

@@ -91,7 +91,7 @@ def test_gemm_rejects(fl):
 # ---------------------------------------------------------------------------
 # forward, loss, gradients, Adam
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("H,nb", [(16, 2), (32, 3), (64, 1)])
+@pytest.mark.parametrize("H,nb", [(16, 2), (32, 3), (48, 1), (64, 1)])
 def test_forward_fp32_mode(fl, H, nb):
     net = fl.UNet(H, max_batch=nb, seed=1, fp32_operands=True)
     w = _weights(20 + H)
@@ -99,11 +99,11 @@ def test_forward_fp32_mode(fl, H, nb):
     x, _ = _samples(H + nb, nb, H)
     y = net.forward(_f32(x)).cpu().numpy()
     ref = ounet.forward(w.astype(np.float64), x)
-    assert np.linalg.norm(y - ref) <= 1e-6 * np.linalg.norm(ref)
-    assert np.abs(y - ref).max() <= 1e-5 * np.abs(ref).max()
+    assert np.linalg.norm(y - ref) <= 5e-6 * np.linalg.norm(ref)
+    assert np.abs(y - ref).max() <= 2e-5 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("H,nb", [(16, 2), (32, 2)])
+@pytest.mark.parametrize("H,nb", [(16, 2), (32, 2), (48, 1), (64, 1)])
 def test_forward_bf16_mode(fl, H, nb):
     net = fl.UNet(H, max_batch=nb, seed=1)
     w = _weights(40 + H)
