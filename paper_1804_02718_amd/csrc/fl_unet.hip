@@ -507,15 +507,18 @@ struct ConvSrc {
     int ca = 0;                              // SRC_CATUP: channels taken from a
 };
 
-template <typename T, int MODE, int KS, int CIN, int COUTP>
+// NS > 1 splits the output channels over NS workgroups per tile (blockIdx.z =
+// sample * NS + split), for the coarse levels whose grids are small.
+template <typename T, int MODE, int KS, int CIN, int COUTP, int NS>
 __global__ __launch_bounds__(256) void k_conv_fused(ConvSrc src, int H, int W, const T *__restrict__ Wb,
                                                     float *__restrict__ Y, int relu) {
     constexpr int TS = 8, HH = TS + KS - 1, HK = KS / 2;
     constexpr bool GENERIC = CIN % 16 != 0;  // the 2-channel first layer
-    constexpr int K = KS * KS * CIN, Kp = (K + 15) / 16 * 16, NTN = COUTP / 16;
+    constexpr int K = KS * KS * CIN, Kp = (K + 15) / 16 * 16, NTN = COUTP / 16 / NS;
+    static_assert(COUTP % (16 * NS) == 0, "channel split");
     constexpr int CV = CIN % 4 == 0 ? 4 : 1;  // channels staged per thread and step
     __shared__ T tile[HH * HH * CIN];
-    const int b = blockIdx.z;
+    const int b = blockIdx.z / NS, n0 = (blockIdx.z % NS) * NTN * 16;  // first output channel
     const int tx0 = blockIdx.x * TS, ty0 = blockIdx.y * TS;
     // stage the halo, CV channels at a time
     for (int e = threadIdx.x; e < HH * HH * (CIN / CV); e += 256) {
@@ -561,7 +564,7 @@ __global__ __launch_bounds__(256) void k_conv_fused(ConvSrc src, int H, int W, c
     for (int k0 = 0; k0 < Kp; k0 += 16) {
         V bv[NTN];
 #pragma unroll
-        for (int j = 0; j < NTN; ++j) bv[j] = *(const V *)(Wb + (16 * j + r) * Kp + k0 + 4 * q);
+        for (int j = 0; j < NTN; ++j) bv[j] = *(const V *)(Wb + (n0 + 16 * j + r) * Kp + k0 + 4 * q);
         V a;
         if constexpr (GENERIC) {
 #pragma unroll
@@ -599,7 +602,7 @@ __global__ __launch_bounds__(256) void k_conv_fused(ConvSrc src, int H, int W, c
             if (y >= H || x >= W) continue;
             float v = acc[j][i];
             if (relu) v = v > 0.f ? v : 0.f;
-            Y[(((long)b * H + y) * W + x) * COUTP + 16 * j + r] = v;
+            Y[(((long)b * H + y) * W + x) * COUTP + n0 + 16 * j + r] = v;
         }
 }
 
@@ -804,12 +807,21 @@ static void refresh_t(fl_unet u, float lr) {
         off += n;
     }
 }
-// one workgroup per 8 x 8 tile of output pixels and sample
+// one workgroup per 8 x 8 tile of output pixels and sample; grids of fewer
+// than 512 tiles also split the output channels, one 16-channel tile each
 template <typename T, int MODE, int KS, int CIN, int COUTP>
 static void conv_fused_launch(fl_unet u, int li, const ConvSrc &src, int h, int nb, float *Y, bool relu) {
-    dim3 g((h + 7) / 8, (h + 7) / 8, nb);
-    hipLaunchKernelGGL((k_conv_fused<T, MODE, KS, CIN, COUTP>), g, dim3(256), 0, u->s, src, h, h, wb_of<T>(u, li), Y,
-                       relu ? 1 : 0);
+    const int tiles = ((h + 7) / 8) * ((h + 7) / 8) * nb;
+    constexpr int NS = COUTP / 16;
+    if (NS > 1 && tiles < 512) {
+        dim3 g((h + 7) / 8, (h + 7) / 8, nb * NS);
+        hipLaunchKernelGGL((k_conv_fused<T, MODE, KS, CIN, COUTP, NS>), g, dim3(256), 0, u->s, src, h, h,
+                           wb_of<T>(u, li), Y, relu ? 1 : 0);
+    } else {
+        dim3 g((h + 7) / 8, (h + 7) / 8, nb);
+        hipLaunchKernelGGL((k_conv_fused<T, MODE, KS, CIN, COUTP, 1>), g, dim3(256), 0, u->s, src, h, h,
+                           wb_of<T>(u, li), Y, relu ? 1 : 0);
+    }
 }
 
 // forward for inference: one fused convolution per layer (pooling, upsampling
