@@ -760,13 +760,23 @@ static fl_status batch_alloc(BatchClass &c, int d) {
 static fl_status batch_chunk_launches(BatchClass &c) {
     VecLayout L = layout(c.M);
     const double *done = c.scal + S_DONE;
+    // (p, Kp) from the matvec's last pass when its workgroups fit the partials array
+    const int np_x = xinv_parts(c.c32.d, c.c32.n, c.P, FL_FP32, c.var32);
+    const bool fused = np_x > 0 && np_x <= kMaxParts;
+    Epi<float> ep;
+    if (fused) {
+        ep.dotw = c.p32;
+        ep.dpart = c.partA;
+        ep.dpart_stride = kMaxParts;
+    }
     for (int i = 0; i < kGraphIters; ++i) {
         const int parity = i & 1;
-        FL_TRY(matvec_ctx<float>(c.c32, c.var32, c.p32, c.kp32, Epi<float>{}, done, c.s));
-        hipLaunchKernelGGL(k_dot<float>, dim3(L.blocks, c.B), dim3(kVecBlock), 0, c.s, c.p32, c.kp32, L.n, L.chunk,
-                           c.partA, done);
+        FL_TRY(matvec_ctx<float>(c.c32, c.var32, c.p32, c.kp32, ep, done, c.s));
+        if (!fused)
+            hipLaunchKernelGGL(k_dot<float>, dim3(L.blocks, c.B), dim3(kVecBlock), 0, c.s, c.p32, c.kp32, L.n,
+                               L.chunk, c.partA, done);
         hipLaunchKernelGGL(k_cg_xr<float>, dim3(L.blocks, c.B), dim3(kVecBlock), 0, c.s, c.d32, c.r32, c.p32,
-                           c.kp32, L.n, L.chunk, c.partA, L.blocks, c.partB, c.scal, parity);
+                           c.kp32, L.n, L.chunk, c.partA, fused ? np_x : L.blocks, c.partB, c.scal, parity);
         hipLaunchKernelGGL(k_cg_p<float>, dim3(L.blocks, c.B), dim3(kVecBlock), 0, c.s, c.p32, c.r32, L.n, L.chunk,
                            c.partB, L.blocks, c.scal, parity);
     }
