@@ -206,12 +206,15 @@ __global__ void k_zero(V *__restrict__ x, long n) {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) x[i] = V(0);
 }
 
-// Allen--Cahn right-hand side b = u - (1-theta) s A u + tau (u - u^3)
-__global__ void k_ac_rhs(const double *__restrict__ u, const double *__restrict__ au, double *__restrict__ b, long n,
-                         double tau, double s, double theta) {
+// Allen--Cahn right-hand side b = u - (1-theta) s A u + tau (u - u^3), and the
+// residual of the initial guess u for (I + theta s A) u+ = b from the same A u:
+// r = b - u - theta s A u = tau (u - u^3) - s A u
+__global__ void k_ac_rhs(const double *__restrict__ u, const double *__restrict__ au, double *__restrict__ b,
+                         double *__restrict__ r, long n, double tau, double s, double theta) {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        const double ui = u[i];
-        b[i] = ui - (1.0 - theta) * s * au[i] + tau * (ui - ui * ui * ui);
+        const double ui = u[i], ai = au[i], g = tau * (ui - ui * ui * ui);
+        b[i] = ui - (1.0 - theta) * s * ai + g;
+        r[i] = g - s * ai;
     }
 }
 
@@ -371,8 +374,10 @@ static fl_status cg_run(fl_op op, double s0, double s1, V *d, V *r, V *p, V *kp,
 
 // Solve K x = b to ||b - K x|| <= tol ||b||; x holds the initial guess.
 // inner64: FP64 inner solves (plain CG), else FP32 inner solves.
+// r_given: w.r64 already holds b - K x for the initial x (saves the first FP64 matvec)
 static fl_status refine(fl_op op, double s0, double s1, const double *b, double *x, double tol, bool inner64,
-                        double inner_tol, int max_iter, int check_every, fl_info *info, hipStream_t s) {
+                        double inner_tol, int max_iter, int check_every, fl_info *info, hipStream_t s,
+                        bool r_given = false) {
     FL_TRY(ensure_workspace(op));
     Work w = work_of(op);
     const long M = op->M;
@@ -397,7 +402,7 @@ static fl_status refine(fl_op op, double s0, double s1, const double *b, double 
     double last = INFINITY;
     int stalls = 0;
     for (int outer = 0;; ++outer) {
-        FL_TRY(residual64(op, b, x, w.r64, s0, s1, s));
+        if (!(r_given && outer == 0)) FL_TRY(residual64(op, b, x, w.r64, s0, s1, s));
         double rr = 0.0;
         FL_TRY(dot<double>(op, w.r64, w.r64, w.partA, &rr, s));
         const double rel = std::sqrt(rr) / bn;
@@ -626,11 +631,12 @@ fl_status fl_allen_cahn_step_ex(fl_op op, double *u, double tau, double eps, dou
     const double sc = tau * eps * eps;
     // b = u - (1-theta) s A u + tau (u - u^3), A u in FP64
     FL_TRY(matvec<double>(op, u, w.kp64, s));
-    hipLaunchKernelGGL(k_ac_rhs, dim3(ew_grid(op->M)), dim3(256), 0, s, u, w.kp64, w.b64, op->M, tau, sc, theta);
+    hipLaunchKernelGGL(k_ac_rhs, dim3(ew_grid(op->M)), dim3(256), 0, s, u, w.kp64, w.b64, w.r64, op->M, tau, sc,
+                       theta);
     FL_HIP_TRY(hipGetLastError());
-    // (I + theta s A) u+ = b, initial guess u
+    // (I + theta s A) u+ = b, initial guess u, whose residual k_ac_rhs left in r64
     fl_status st = refine(op, 1.0, theta * sc, w.b64, u, tol, solver == FL_SOLVE_CG64, 1e-4,
-                          default_max_iter(op), 0, inf, s);
+                          default_max_iter(op), 0, inf, s, true);
     inf->status = st;
     inf->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return st;
