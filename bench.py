@@ -269,6 +269,43 @@ def c5_extra(torch, fl, pairs, epochs, N=256):
             "fp64_matvec_ms": round(t_mv * 1e3, 4), "solves": rows}
 
 
+# CPU seconds the paper reports for its two-bubble Allen--Cahn run to t = 0.015 (Sec. 5.3,
+# table of CPU times; hardware, language and CG tolerance not stated), by alpha and N
+PAPER_AC_SECONDS = {1.9: {1024: 25728, 512: 4497, 256: 456, 128: 86},
+                    1.5: {1024: 4896, 512: 974, 256: 112, 128: 27},
+                    1.0: {1024: 648, 512: 170, 256: 30, 128: 9},
+                    0.7: {1024: 430, 512: 107, 256: 24, 128: 7}}
+
+
+def paper_ac_extra(torch, fl, inputs, sizes=(128, 256, 512, 1024), alphas=(1.9, 1.5, 1.0, 0.7)):
+    """The paper's two kissing bubbles: u_t = -(-Delta)^{alpha/2} u - delta^-alpha u (u^2 - 1) on (0,1)^2,
+    u = -1 outside, delta = 0.03, h = 1/N, tau = 5e-4, 30 Crank--Nicolson steps to t = 0.015 (stepped as
+    ubar = u + 1), each solved to an FP64 residual of 1e-8.  The paper's CPU seconds are context."""
+    delta, tau, steps = 0.03, 5e-4, 30
+    out = {"workload": "two kissing bubbles on (0,1)^2, delta=0.03, tau=5e-4, 30 steps to t=0.015, tol 1e-8",
+           "runs": []}
+    for alpha in alphas:
+        for N in sizes:
+            h = 1.0 / N
+            op = fl.Operator(2, alpha, h, N)
+            ub = torch.as_tensor(inputs.kissing_bubbles(N, delta), device="cuda:0")
+            gamma = delta ** -alpha
+            op.allen_cahn_step_gen(ub.clone(), tau, 1.0, gamma, 1.0)  # warm (workspaces)
+            torch.cuda.synchronize()
+            iters = 0
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                iters += op.allen_cahn_step_gen(ub, tau, 1.0, gamma, 1.0)["iters"]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            mass = float((ub - 1.0).abs().sum()) * h * h  # integral of |u| over the box
+            out["runs"].append({"alpha": alpha, "N": N, "seconds": round(dt, 4), "cg_iters": iters,
+                                "mass_in_box": round(mass, 6),
+                                "paper_cpu_seconds": PAPER_AC_SECONDS[alpha][N]})
+            op.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -286,6 +323,8 @@ def main():
                     help="skip the batch of 64 mixed-(N, alpha) Poisson solves, batched and one by one")
     ap.add_argument("--no-c5", action="store_true",
                     help="skip the learned-preconditioner workload (pairs, training, flexible PCG vs CG)")
+    ap.add_argument("--no-paper-ac", action="store_true",
+                    help="skip the paper's two-bubble Allen--Cahn run (timed against its CPU table as context)")
     ap.add_argument("--c5-pairs", type=int, default=1024,
                     help="training pairs for the learned preconditioner (the full recipe uses 20000)")
     ap.add_argument("--c5-epochs", type=int, default=4)
@@ -378,6 +417,9 @@ def main():
     if not args.no_extra and not args.no_c4:
         print("bench: batched solves", file=sys.stderr, flush=True)
         extra["c4_batch"] = c4_extra(torch, fl, inputs)
+    if not args.no_extra and not args.no_paper_ac:
+        print("bench: paper Allen--Cahn workload", file=sys.stderr, flush=True)
+        extra["paper_allen_cahn"] = paper_ac_extra(torch, fl, inputs)
     if not args.no_extra and not args.no_c5:
         print("bench: learned preconditioner", file=sys.stderr, flush=True)
         extra["c5_learned"] = c5_extra(torch, fl, args.c5_pairs, args.c5_epochs)

@@ -147,6 +147,24 @@ fl_status fl_allen_cahn_step_ex(fl_op op, double *u, double tau, double eps,
                                 fl_info *info, void *stream);
 
 /*
+ * fl_allen_cahn_step_gen -- one step of the general form
+ *     u_t = -kappa (-Delta)^{alpha/2} u + gamma (w - w^3),  w = u - shift,
+ * u = 0 outside the box, with the same theta-scheme on the linear term and
+ * the explicit reaction term:
+ *     (I + theta tau kappa A) u+ = u - (1-theta) tau kappa A u + tau gamma (w - w^3).
+ * fl_allen_cahn_step_ex is kappa = eps^2, gamma = 1, shift = 0.  The
+ * equation of Sec. 5.3 (u_t = -(-Delta)^{alpha/2} u - delta^{-alpha} u (u^2-1)
+ * on (0,1)^d with u = -1 outside) is this form for ubar = u + 1, which is 0
+ * outside: kappa = 1, gamma = delta^{-alpha}, shift = 1.  kappa >= 0 (0
+ * leaves only the explicit reaction step), gamma and shift finite; other
+ * arguments as in fl_allen_cahn_step_ex.
+ */
+fl_status fl_allen_cahn_step_gen(fl_op op, double *u, double tau, double kappa,
+                                 double gamma, double shift, double theta,
+                                 double tol, int solver, fl_info *info,
+                                 void *stream);
+
+/*
  * fl_apply_profiled -- fl_apply instrumented for measurement: runs `reps`
  * matvecs y = A u back to back on `stream`, each kernel launched with HIP
  * events recorded at its start and stop, synchronises, and writes the average

@@ -231,11 +231,23 @@ def ac_step(d: int, N: int, alpha: float, a: np.ndarray, u: np.ndarray, tau: flo
     Dense Cholesky solve (small grids only).  ``reaction=False`` drops the
     u - u^3 term (used to pin the linear part).
     """
+    return ac_step_gen(d, N, alpha, a, u, tau, eps * eps, 1.0 if reaction else 0.0, 0.0, theta, A)
+
+
+def ac_step_gen(d: int, N: int, alpha: float, a: np.ndarray, u: np.ndarray, tau: float,
+                kappa: float, gamma: float, shift: float, theta: float = 0.5,
+                A: np.ndarray = None) -> np.ndarray:
+    """One step of u_t = -kappa (-Delta)^{alpha/2} u + gamma (w - w^3), w = u - shift,
+    zero exterior, with the theta-scheme on the linear term and the reaction explicit:
+      (I + theta tau kappa A) u+ = u - (1-theta) tau kappa A u + tau gamma (w - w^3).
+    Sec. 5.3's equation (u = -1 outside (0,1)^d, reaction -delta^{-alpha} u (u^2 - 1))
+    is this form for ubar = u + 1: kappa = 1, gamma = delta^{-alpha}, shift = 1.
+    """
     if A is None:
         A = dense(d, N, alpha, a)
-    s = tau * eps * eps
-    b = u - (1.0 - theta) * s * (A @ u)
-    if reaction:
-        b = b + tau * (u - u ** 3)
+    u = np.asarray(u, dtype=np.float64)
+    s = tau * kappa
+    w = u - shift
+    b = u - (1.0 - theta) * s * (A @ u) + tau * gamma * (w - w ** 3)
     K = np.eye(A.shape[0]) + theta * s * A
     return solve_dense(K, b)

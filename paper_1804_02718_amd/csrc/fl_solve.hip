@@ -206,13 +206,14 @@ __global__ void k_zero(V *__restrict__ x, long n) {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) x[i] = V(0);
 }
 
-// Allen--Cahn right-hand side b = u - (1-theta) s A u + tau (u - u^3), and the
-// residual of the initial guess u for (I + theta s A) u+ = b from the same A u:
-// r = b - u - theta s A u = tau (u - u^3) - s A u
+// Allen--Cahn right-hand side b = u - (1-theta) s A u + tau gamma (w - w^3),
+// w = u - shift, and the residual of the initial guess u for
+// (I + theta s A) u+ = b from the same A u: r = b - u - theta s A u
 __global__ void k_ac_rhs(const double *__restrict__ u, const double *__restrict__ au, double *__restrict__ b,
-                         double *__restrict__ r, long n, double tau, double s, double theta) {
+                         double *__restrict__ r, long n, double tau, double s, double theta, double gamma,
+                         double shift) {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        const double ui = u[i], ai = au[i], g = tau * (ui - ui * ui * ui);
+        const double ui = u[i], ai = au[i], wi = ui - shift, g = tau * gamma * (wi - wi * wi * wi);
         b[i] = ui - (1.0 - theta) * s * ai + g;
         r[i] = g - s * ai;
     }
@@ -610,11 +611,12 @@ fl_status fl_poisson_solve(fl_op op, const double *f, double tol, double *u, fl_
     return fl_poisson_solve_ex(op, f, tol, u, nullptr, info, stream);
 }
 
-fl_status fl_allen_cahn_step_ex(fl_op op, double *u, double tau, double eps, double theta, double tol, int solver,
-                                fl_info *info, void *stream) {
+fl_status fl_allen_cahn_step_gen(fl_op op, double *u, double tau, double kappa, double gamma, double shift,
+                                 double theta, double tol, int solver, fl_info *info, void *stream) {
     if (!op || !u) { set_error("NULL argument"); return FL_E_INVAL; }
     if (!(tau > 0.0) || !std::isfinite(tau)) { set_error("tau must be positive"); return FL_E_INVAL; }
-    if (!(eps > 0.0) || !std::isfinite(eps)) { set_error("eps must be positive"); return FL_E_INVAL; }
+    if (!(kappa >= 0.0) || !std::isfinite(kappa)) { set_error("kappa must be >= 0"); return FL_E_INVAL; }
+    if (!std::isfinite(gamma) || !std::isfinite(shift)) { set_error("gamma and shift must be finite"); return FL_E_INVAL; }
     if (!(theta > 0.0 && theta <= 1.0)) { set_error("theta must lie in (0,1]"); return FL_E_INVAL; }
     if (!(tol > 0.0)) { set_error("tol must be positive"); return FL_E_INVAL; }
     if (solver != FL_SOLVE_AUTO && solver != FL_SOLVE_REFINE && solver != FL_SOLVE_CG64) {
@@ -628,11 +630,11 @@ fl_status fl_allen_cahn_step_ex(fl_op op, double *u, double tau, double eps, dou
     hipStream_t s = (hipStream_t)stream;
     FL_TRY(ensure_workspace(op));
     Work w = work_of(op);
-    const double sc = tau * eps * eps;
-    // b = u - (1-theta) s A u + tau (u - u^3), A u in FP64
+    const double sc = tau * kappa;
+    // b = u - (1-theta) s A u + tau gamma (w - w^3), A u in FP64
     FL_TRY(matvec<double>(op, u, w.kp64, s));
     hipLaunchKernelGGL(k_ac_rhs, dim3(ew_grid(op->M)), dim3(256), 0, s, u, w.kp64, w.b64, w.r64, op->M, tau, sc,
-                       theta);
+                       theta, gamma, shift);
     FL_HIP_TRY(hipGetLastError());
     // (I + theta s A) u+ = b, initial guess u, whose residual k_ac_rhs left in r64
     fl_status st = refine(op, 1.0, theta * sc, w.b64, u, tol, solver == FL_SOLVE_CG64, 1e-4,
@@ -640,6 +642,12 @@ fl_status fl_allen_cahn_step_ex(fl_op op, double *u, double tau, double eps, dou
     inf->status = st;
     inf->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return st;
+}
+
+fl_status fl_allen_cahn_step_ex(fl_op op, double *u, double tau, double eps, double theta, double tol, int solver,
+                                fl_info *info, void *stream) {
+    if (!(eps > 0.0) || !std::isfinite(eps)) { set_error("eps must be positive"); return FL_E_INVAL; }
+    return fl_allen_cahn_step_gen(op, u, tau, eps * eps, 1.0, 0.0, theta, tol, solver, info, stream);
 }
 
 fl_status fl_allen_cahn_step(fl_op op, double *u, double tau, double eps, fl_info *info, void *stream) {

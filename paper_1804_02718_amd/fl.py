@@ -24,7 +24,7 @@ EXPORTED = ["fl_coeffs", "fl_apply", "fl_apply_profiled", "fl_variant_count", "f
             "fl_allen_cahn_step_ex", "fl_op_destroy", "fl_op_describe", "fl_get_coeffs", "fl_get_symbol",
             "fl_status_string", "fl_last_error", "fl_unet_create", "fl_unet_destroy", "fl_unet_num_params",
             "fl_unet_step", "fl_unet_get_weights", "fl_unet_set_weights", "fl_unet_apply", "fl_set_preconditioner",
-            "fl_gemm_test", "fl_unet_pack", "fl_unet_train"]
+            "fl_gemm_test", "fl_unet_pack", "fl_unet_train", "fl_allen_cahn_step_gen"]
 
 
 class FlLibraryMissing(RuntimeError):
@@ -91,6 +91,7 @@ def load(path: str = LIB_PATH):
     lib.fl_poisson_solve_ex.argtypes = [vp, vp, dp, vp, ctypes.POINTER(fl_solve_opts), ctypes.POINTER(fl_info), vp]
     lib.fl_allen_cahn_step.argtypes = [vp, vp, dp, dp, ctypes.POINTER(fl_info), vp]
     lib.fl_allen_cahn_step_ex.argtypes = [vp, vp, dp, dp, dp, dp, ip, ctypes.POINTER(fl_info), vp]
+    lib.fl_allen_cahn_step_gen.argtypes = [vp, vp, dp, dp, dp, dp, dp, dp, ip, ctypes.POINTER(fl_info), vp]
     lib.fl_op_destroy.argtypes = [vp]
     lib.fl_op_describe.argtypes = [vp, ctypes.POINTER(fl_op_desc)]
     lib.fl_get_coeffs.argtypes = [vp, vp]
@@ -242,6 +243,16 @@ def fl_allen_cahn_step_ex(op, u, tau, eps, theta=0.5, tol=1e-8, solver="auto", s
     st = load().fl_allen_cahn_step_ex(op, _ptr(u), float(tau), float(eps), float(theta), float(tol),
                                       SOLVERS[solver] if isinstance(solver, str) else int(solver),
                                       ctypes.byref(info), _stream(stream))
+    _check(st, info.as_dict())
+    return info.as_dict()
+
+
+def fl_allen_cahn_step_gen(op, u, tau, kappa, gamma, shift, theta=0.5, tol=1e-8, solver="auto", stream=None):
+    info = fl_info()
+    st = load().fl_allen_cahn_step_gen(op, _ptr(u), float(tau), float(kappa), float(gamma), float(shift),
+                                       float(theta), float(tol),
+                                       SOLVERS[solver] if isinstance(solver, str) else int(solver),
+                                       ctypes.byref(info), _stream(stream))
     _check(st, info.as_dict())
     return info.as_dict()
 
@@ -502,6 +513,9 @@ class Operator:
 
     def allen_cahn_step(self, u, tau, eps, theta=0.5, tol=1e-8, solver="auto", stream=None):
         return fl_allen_cahn_step_ex(self._op, u, tau, eps, theta, tol, solver, stream)
+
+    def allen_cahn_step_gen(self, u, tau, kappa, gamma, shift, theta=0.5, tol=1e-8, solver="auto", stream=None):
+        return fl_allen_cahn_step_gen(self._op, u, tau, kappa, gamma, shift, theta, tol, solver, stream)
 
     def coeffs(self):
         return fl_get_coeffs(self._op)

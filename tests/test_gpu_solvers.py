@@ -238,3 +238,34 @@ def test_batched_c4_workload(fl):
         assert (torch.linalg.norm(r) / torch.linalg.norm(fs[k])).item() <= 1.05e-8
         op.close()
     b.close()
+
+
+@pytest.mark.parametrize("alpha", [0.7, 1.5])
+def test_allen_cahn_general_paper_form(fl, alpha):
+    # Sec. 5.3's equation on (0,1)^2 with u = -1 outside, as the shifted field ubar = u + 1:
+    # kappa = 1, gamma = delta^-alpha, shift = 1, Crank--Nicolson on the linear term.
+    N, delta, tau = 32, 0.03, 5e-4
+    h = 1.0 / N
+    op = fl.Operator(2, alpha, h, N)
+    a = oracle.coeffs(2, alpha, h, N)
+    A = oracle.dense(2, N, alpha, a)
+    ub0 = inputs.kissing_bubbles(N, delta)
+    gamma = delta ** -alpha
+    ref = ub0.copy()
+    u = _t(ub0)
+    for _ in range(3):
+        info = op.allen_cahn_step_gen(u, tau, 1.0, gamma, 1.0)
+        assert info["relres"] <= 1e-8
+        ref = oracle.ac_step_gen(2, N, alpha, a, ref, tau, 1.0, gamma, 1.0, 0.5, A=A)
+    assert np.abs(u.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max()
+
+
+def test_allen_cahn_general_rejects(fl):
+    op = fl.Operator(2, 1.0, 1.0 / 16, 16)
+    u = _t(np.zeros(15 * 15))
+    with pytest.raises(fl.FlError):
+        op.allen_cahn_step_gen(u, 1e-3, -1.0, 1.0, 0.0)
+    with pytest.raises(fl.FlError):
+        op.allen_cahn_step_gen(u, 1e-3, 1.0, float("nan"), 0.0)
+    with pytest.raises(fl.FlError):
+        op.allen_cahn_step_gen(u, 0.0, 1.0, 1.0, 0.0)

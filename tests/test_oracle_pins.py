@@ -367,3 +367,47 @@ def test_allen_cahn_full_step_first_order_in_time():
     e2 = np.abs(run(T / 32) - ref).max()
     assert e1 / e2 == pytest.approx(2.0, rel=0.15)
     assert np.abs(run(1e-3)).max() <= 1.0
+
+
+def test_allen_cahn_general_reaction_only_closed_form():
+    # kappa = 0 leaves the explicit reaction step u+ = u + tau gamma (w - w^3), w = u - shift;
+    # with shift = 1 and gamma = delta^-alpha it is the Sec. 5.3 reaction -delta^-alpha u (u^2 - 1)
+    # of u = ubar - 1.
+    N, alpha, tau, delta = 8, 1.5, 5e-4, 0.03
+    a = oracle.coeffs(2, alpha, 1.0 / N, N)
+    ub = inputs.kissing_bubbles(N, delta)
+    gamma = delta ** -alpha
+    up = oracle.ac_step_gen(2, N, alpha, a, ub, tau, 0.0, gamma, 1.0)
+    u = ub - 1.0
+    assert np.allclose(up - 1.0, u - tau * gamma * u * (u * u - 1.0), rtol=0, atol=1e-14)
+    # fixed points of the reaction: ubar = 0 (u = -1) and ubar = 2 (u = 1)
+    for c in (0.0, 2.0):
+        assert np.all(oracle.ac_step_gen(2, N, alpha, a, np.full((N - 1) ** 2, c), tau, 0.0, gamma, 1.0) == c)
+
+
+def test_allen_cahn_general_matches_standard_form():
+    # kappa = eps^2, gamma = 1, shift = 0 is the standard step, and the linear part keeps the
+    # modal factor with s = tau kappa for any kappa.
+    N, alpha, tau = 8, 1.2, 1e-3
+    a = oracle.coeffs(2, alpha, 2.0 / N, N)
+    A = oracle.dense(2, N, alpha, a)
+    u0 = inputs.ac_initial((N - 1) ** 2, seed=3)
+    assert np.array_equal(oracle.ac_step(2, N, alpha, a, u0, tau, 0.05, 0.5, A=A),
+                          oracle.ac_step_gen(2, N, alpha, a, u0, tau, 0.05 ** 2, 1.0, 0.0, 0.5, A=A))
+    lam, V = np.linalg.eigh(A)
+    kappa = 0.7
+    up = oracle.ac_step_gen(2, N, alpha, a, V[:, 5], tau, kappa, 0.0, 0.0, 0.5, A=A)
+    s = tau * kappa
+    assert np.allclose(up, (1 - 0.5 * s * lam[5]) / (1 + 0.5 * s * lam[5]) * V[:, 5], rtol=1e-12, atol=1e-13)
+
+
+def test_kissing_bubbles_initial_state():
+    # u0 = 1 - tanh(d1/delta) - tanh(d2/delta), d_i = |x - x_i| - 0.12: at the node (0.4, 0.4)
+    # (N = 10, index 3) d1 = -0.12 and d2 = |(0.2, 0.2)| - 0.12
+    ub = inputs.kissing_bubbles(10, 0.03).reshape(9, 9)
+    u = 1.0 - np.tanh(-0.12 / 0.03) - np.tanh((np.hypot(0.2, 0.2) - 0.12) / 0.03)
+    assert ub[3, 3] == pytest.approx(u + 1.0, rel=1e-14)
+    ub = inputs.kissing_bubbles(64, 0.03).reshape(63, 63)
+    assert ub[0, 0] < 0.01 and ub[-1, -1] < 0.01
+    # symmetric about the diagonal and under (x, y) -> (1 - y, 1 - x)
+    assert np.allclose(ub, ub.T, atol=0) and np.allclose(ub, ub[::-1, ::-1].T, atol=1e-14)
