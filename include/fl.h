@@ -83,6 +83,7 @@ typedef struct {
     int64_t M;            /* unknowns n^d                                        */
     double alpha, h, c;   /* fractional order, mesh size, c_{d,alpha}            */
     double a0;            /* diagonal coefficient a_0 (A_ii = -c a_0)            */
+    double gamma;         /* splitting parameter of the scheme                   */
 } fl_op_desc;
 
 /*
@@ -100,6 +101,20 @@ typedef struct {
  *   returning.  Errors: FL_E_INVAL, FL_E_UNSUPPORTED, FL_E_NOMEM, FL_E_DEVICE.
  */
 fl_status fl_coeffs(int d, double alpha, double h, int N, fl_op *out);
+
+/*
+ * fl_coeffs_gamma -- as fl_coeffs with the splitting parameter gamma of
+ * Sec. 2 (the kernel |xi|^{-(d+alpha)} split into |xi|^{-gamma} on the
+ * central difference quotient and the weight |xi|^{gamma-(d+alpha)}), gamma in
+ * (alpha, 2].  gamma = 2 is fl_coeffs.  For gamma < 2 the origin limit of the
+ * difference quotient is 0, so the origin-element corrections of a_mn
+ * (weighted by floor(gamma/2)) vanish; the elements integrate
+ * |xi|^{-(d+alpha-gamma)} and a_v = 2^sigma W_v / (2^d |xi_v|^gamma).  The
+ * paper reports this choice as accurate to O(h^{2-alpha}) against O(h^2) for
+ * gamma = 2 (Sec. 5.1, Example 5.1.2).  Errors as fl_coeffs; FL_E_INVAL when
+ * gamma is outside (alpha, 2].
+ */
+fl_status fl_coeffs_gamma(int d, double alpha, double gamma, double h, int N, fl_op *out);
 
 /*
  * fl_apply -- y = A u, the discrete fractional Laplacian (Sec. 2 2D scheme /

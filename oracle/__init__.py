@@ -59,6 +59,9 @@ def _lib():
         lib.orc_elements.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
         lib.orc_coeffs.restype = ctypes.c_int
         lib.orc_coeffs.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp]
+        lib.orc_coeffs_g.restype = ctypes.c_int
+        lib.orc_coeffs_g.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_int, dp, dp]
         lib.orc_apply_rows.restype = ctypes.c_int
         lib.orc_apply_rows.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp,
                                        i64p, ctypes.c_int64, dp, ctypes.c_int]
@@ -115,19 +118,24 @@ def elements(d: int, alpha: float, h: float, N: int) -> np.ndarray:
     return E.reshape((N,) * d)
 
 
-def coeffs(d: int, alpha: float, h: float, N: int, return_elements: bool = False):
+def coeffs(d: int, alpha: float, h: float, N: int, return_elements: bool = False, gamma: float = 2.0):
     """Scheme coefficients a_v, v in [0,N]^d, numpy index order (v_d, ..., v_1); a[0,..,0] = a_0.
 
     Sec. 2: a_mn and a_00; Sec. 4: a_mns and a_000 (origin correction for
-    (1,1,1) read as +1, the value the gamma = 2 limit rule implies).
+    (1,1,1) read as +1, the value the gamma = 2 limit rule implies).  gamma is
+    the splitting parameter of Sec. 2, in (alpha, 2]; for gamma < 2 the
+    origin-element corrections vanish (their weight is floor(gamma/2)).
     """
     if d not in (2, 3):
         raise ValueError("d must be 2 or 3")
-    if not (0.0 < alpha < 2.0) or N < 2 or not (h > 0):
+    if not (0.0 < alpha < 2.0) or N < 2 or not (h > 0) or not (alpha < gamma <= 2.0):
         raise ValueError("bad parameters")
     a = np.zeros((N + 1) ** d)
     E = np.zeros(N ** d)
-    rc = _lib().orc_coeffs(d, alpha, h, N, _dp(a), _dp(E))
+    if gamma == 2.0:
+        rc = _lib().orc_coeffs(d, alpha, h, N, _dp(a), _dp(E))
+    else:
+        rc = _lib().orc_coeffs_g(d, alpha, gamma, h, N, _dp(a), _dp(E))
     if rc:
         raise ValueError("orc_coeffs failed (%d)" % rc)
     a = a.reshape((N + 1,) * d)

@@ -10,11 +10,12 @@
  * benchmark may load this library.  It shares no code, header, table or
  * constant generator with the GPU library.
  *
- * What is computed (gamma = 2 throughout, as the paper's experiments use):
+ * What is computed (splitting parameter gamma in (alpha, 2], gamma = 2 the
+ * paper's default):
  *   - J_d(p) = int_{[0,1]^{d-1}} (1+|s|^2)^{-p/2} ds, the angular factor of
  *     a radial power integrated over a cube corner (pyramid split of the
  *     cube along its diagonal planes).
- *   - element integrals E_e = int_{I_e} |xi|^{-q} dxi, q = d + alpha - 2,
+ *   - element integrals E_e = int_{I_e} |xi|^{-q} dxi, q = d + alpha - gamma,
  *     over the elements I_e of Sec. 2 (2D) and Sec. 4 (3D).  The origin
  *     element is the closed form d h^{d-q} J_d(q)/(d-q) (in 2D this is the
  *     polar identity the paper uses in the proof of Theorem 1); every other
@@ -22,7 +23,7 @@
  *     plain table of the element's distance from the origin.
  *   - coefficients a_v of the scheme (Sec. 2, formulas for a_mn and a_00;
  *     Sec. 4, formulas for a_mns and a_000), with the origin-element
- *     corrections of the limit rules for gamma = 2.
+ *     corrections of the limit rules for gamma = 2 (none for gamma < 2).
  *   - the scheme itself as an explicit O(M^2) sum (Sec. 2 scheme for the
  *     2D operator, Sec. 4 scheme for the 3D operator), in long double.
  *
@@ -176,11 +177,11 @@ double orc_D2(int d, double alpha, double L)
     return d * pow(L, -alpha) * orc_J(d, d + alpha) / alpha;
 }
 
-/* E[e] for e in [0,N-1]^d, x-index fastest.  q = d + alpha - 2. */
-int orc_elements(int d, double alpha, double h, int N, double *E)
+/* E[e] for e in [0,N-1]^d, x-index fastest.  q = d + alpha - gamma. */
+int orc_elements_g(int d, double alpha, double gamma, double h, int N, double *E)
 {
     if (d != 2 && d != 3) return 1;
-    double q = d + alpha - 2.0;
+    double q = d + alpha - gamma;
     long double scale = powl((long double)h, (long double)(d - q));
     int64_t total = 1;
     for (int i = 0; i < d; ++i) total *= N;
@@ -207,16 +208,26 @@ int orc_elements(int d, double alpha, double h, int N, double *E)
 /* a_0 = -sum_{v != 0} W'_v/|xi_v|^2 - 2^d D2, identical to the a_00 and */
 /* a_000 formulas.                                                      */
 /* ------------------------------------------------------------------ */
-int orc_coeffs(int d, double alpha, double h, int N, double *a, double *E_out)
+int orc_elements(int d, double alpha, double h, int N, double *E)
+{
+    return orc_elements_g(d, alpha, 2.0, h, N, E);
+}
+
+/* Sec. 2 with general gamma: a_mn = 2^sigma/(4|xi_mn|^gamma) (int_{T_mn} w    */
+/* + cbar floor(gamma/2) int_{I_00} w), w = |xi|^{gamma-(2+alpha)}; the same */
+/* in 3D with 8 and the 3D cbar.  floor(gamma/2) is 1 only for gamma = 2.    */
+int orc_coeffs_g(int d, double alpha, double gamma, double h, int N, double *a, double *E_out)
 {
     if (d != 2 && d != 3) return 1;
     if (!(alpha > 0.0 && alpha < 2.0) || N < 2 || !(h > 0.0)) return 2;
+    if (!(gamma > alpha && gamma <= 2.0)) return 2;
     int64_t ne = 1, nv = 1;
     for (int i = 0; i < d; ++i) { ne *= N; nv *= (N + 1); }
     double *E = E_out ? E_out : (double *)malloc(sizeof(double) * ne);
     if (!E) return 3;
-    orc_elements(d, alpha, h, N, E);
-    double q = d + alpha - 2.0;
+    orc_elements_g(d, alpha, gamma, h, N, E);
+    double q = d + alpha - gamma;
+    int fl_g = gamma == 2.0 ? 1 : 0;  /* floor(gamma/2) on (alpha, 2] */
     double E0 = E[0];
     int V = N + 1;
     long double twod = (d == 2) ? 4.0L : 8.0L;
@@ -251,7 +262,7 @@ int orc_coeffs(int d, double alpha, double h, int N, double *a, double *E_out)
             if (v[i] > maxv) maxv = v[i];
         }
         /* origin-element correction of the gamma = 2 limit rule */
-        if (maxv == 1) {
+        if (maxv == 1 && fl_g) {
             int nonzero = d - nz;
             if (d == 2)
                 W += (nonzero == 1) ? (long double)E0 : -(long double)E0;
@@ -261,8 +272,9 @@ int orc_coeffs(int d, double alpha, double h, int N, double *a, double *E_out)
         long double r2 = 0.0L;
         for (int i = 0; i < d; ++i) r2 += (long double)v[i] * v[i];
         r2 *= (long double)h * h;
+        long double rg = fl_g ? r2 : powl(r2, 0.5L * (long double)gamma);  /* |xi_v|^gamma */
         long double pw = (long double)(1 << nz);
-        a[idx] = (double)(pw * W / (twod * r2));
+        a[idx] = (double)(pw * W / (twod * rg));
     }
     /* a_0: sum of 2^d a_v / 2^sigma(v) over v != 0, compensated by long double */
     long double s = 0.0L;
@@ -277,6 +289,11 @@ int orc_coeffs(int d, double alpha, double h, int N, double *a, double *E_out)
     (void)q;
     if (!E_out) free(E);
     return 0;
+}
+
+int orc_coeffs(int d, double alpha, double h, int N, double *a, double *E_out)
+{
+    return orc_coeffs_g(d, alpha, 2.0, h, N, a, E_out);
 }
 
 /* c_{d,alpha} = 2^{alpha-1} alpha Gamma((d+alpha)/2) / (pi^{d/2} Gamma(1-alpha/2)) (Sec. 1) */

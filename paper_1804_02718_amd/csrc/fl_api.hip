@@ -70,7 +70,7 @@ static void destroy(fl_op op) {
     delete op;
 }
 
-static fl_status create(int d, double alpha, double h, int N, fl_op *out) {
+static fl_status create(int d, double alpha, double gamma, double h, int N, fl_op *out) {
     fl_op op = new (std::nothrow) fl_op_s();
     if (!op) {
         set_error("host allocation failed");
@@ -80,6 +80,7 @@ static fl_status create(int d, double alpha, double h, int N, fl_op *out) {
     op->N = N;
     op->n = N - 1;
     op->alpha = alpha;
+    op->gamma = gamma;
     op->h = h;
     op->c = std::pow(2.0, alpha - 1.0) * alpha * std::tgamma(0.5 * (d + alpha)) /
             (std::pow(M_PI, 0.5 * d) * std::tgamma(1.0 - 0.5 * alpha));
@@ -163,8 +164,12 @@ const char *fl_status_string(fl_status s) {
     return "unknown status";
 }
 
-fl_status fl_coeffs(int d, double alpha, double h, int N, fl_op *out) {
+fl_status fl_coeffs_gamma(int d, double alpha, double gamma, double h, int N, fl_op *out) {
     g_err[0] = 0;
+    if (!(gamma > alpha && gamma <= 2.0)) {
+        set_error("gamma must lie in (alpha, 2] (got gamma=%g, alpha=%g)", gamma, alpha);
+        return FL_E_INVAL;
+    }
     if (!out) { set_error("out is NULL"); return FL_E_INVAL; }
     if (d != 2 && d != 3) { set_error("d must be 2 or 3 (got %d)", d); return FL_E_INVAL; }
     if (!(alpha > 0.0 && alpha < 2.0)) { set_error("alpha must lie in (0,2) (got %g)", alpha); return FL_E_INVAL; }
@@ -172,7 +177,16 @@ fl_status fl_coeffs(int d, double alpha, double h, int N, fl_op *out) {
     if (N < 2) { set_error("N must be >= 2 (got %d)", N); return FL_E_INVAL; }
     const int nmax = d == 2 ? 1025 : 513;
     if (N > nmax) { set_error("N=%d exceeds the built range (N <= %d for d=%d)", N, nmax, d); return FL_E_UNSUPPORTED; }
-    return create(d, alpha, h, N, out);
+    return create(d, alpha, gamma, h, N, out);
+}
+
+fl_status fl_coeffs(int d, double alpha, double h, int N, fl_op *out) {
+    if (!(alpha > 0.0 && alpha < 2.0)) {
+        g_err[0] = 0;
+        set_error("alpha must lie in (0,2) (got %g)", alpha);
+        return FL_E_INVAL;
+    }
+    return fl_coeffs_gamma(d, alpha, 2.0, h, N, out);
 }
 
 fl_status fl_op_destroy(fl_op op) {
@@ -192,6 +206,7 @@ fl_status fl_op_describe(fl_op op, fl_op_desc *desc) {
     desc->h = op->h;
     desc->c = op->c;
     desc->a0 = op->a0;
+    desc->gamma = op->gamma;
     return FL_OK;
 }
 

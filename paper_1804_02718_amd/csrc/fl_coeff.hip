@@ -1,15 +1,17 @@
 // fl_coeff.hip -- FP64 coefficients of the scheme on the GPU.
 //
-// With splitting parameter gamma = 2 (the paper's default, Sec. 5) and
-// q = d + alpha - 2, the scheme needs (Sec. 2 for d = 2, Sec. 4 for d = 3):
+// With splitting parameter gamma in (alpha, 2] (2 is the paper's default,
+// Sec. 5) and q = d + alpha - gamma, the scheme needs (Sec. 2 for d = 2,
+// Sec. 4 for d = 3):
 //   * element integrals E_e = int_{I_e} |xi|^{-q}, I_e = prod [e_i h, (e_i+1) h];
 //   * vertex weights W_v = sum of E_e over the elements having xi_v as a vertex
 //     (the patch T_v, restricted to (0, L)^d, vertices 0..N per axis), plus the
-//     origin-element correction of the gamma = 2 limit rule: in 2D +E_0 on
-//     (1,0), (0,1) and -E_0 on (1,1); in 3D +5/3 E_0 on the axis unit vectors
-//     and -E_0 on every other vertex of the unit cube;
-//   * a_v = 2^{sigma(v)} W_v / (2^d |xi_v|^2), sigma = number of zero indices;
-//   * a_0 = -sum_{v != 0} W_v / |xi_v|^2 - 2^d D2, D2 the integral of
+//     origin-element correction of the gamma = 2 limit rule (none for
+//     gamma < 2, where the limit of psi_gamma at the origin is 0): in 2D +E_0
+//     on (1,0), (0,1) and -E_0 on (1,1); in 3D +5/3 E_0 on the axis unit
+//     vectors and -E_0 on every other vertex of the unit cube;
+//   * a_v = 2^{sigma(v)} W_v / (2^d |xi_v|^gamma), sigma = number of zero indices;
+//   * a_0 = -sum_{v != 0} W_v / |xi_v|^gamma - 2^d D2, D2 the integral of
 //     |xi|^{-(d+alpha)} over R^d_+ minus (0, L)^d, L = N h.
 // Closed forms (pyramid split of the cube corner along its diagonal planes):
 //   E_0 = d h^{d-q} J(q) / (d - q),   D2 = d L^{-alpha} J(d + alpha) / alpha,
@@ -108,12 +110,13 @@ __device__ __forceinline__ int rule_for(int m) {
 }
 
 // J(p1), J(p2) and the closed forms E_0, D2 -> scal[0], scal[1]
-__global__ __launch_bounds__(256) void k_closed_forms(int d, double alpha, double h, int N, double *scal) {
+__global__ __launch_bounds__(256) void k_closed_forms(int d, double alpha, double gamma, double h, int N,
+                                                      double *scal) {
     __shared__ double s1[256], s2[256];
     const int r = 5;  // 40-point rule
     const int n = order_of(r);
     const int off = c_gloff[r];
-    const double q = d + alpha - 2.0, p2 = d + alpha;
+    const double q = d + alpha - gamma, p2 = d + alpha;
     double a1 = 0.0, a2 = 0.0;
     const int total = d == 2 ? n : n * n;
     for (int t = threadIdx.x; t < total; t += blockDim.x) {
@@ -149,9 +152,10 @@ __global__ __launch_bounds__(256) void k_closed_forms(int d, double alpha, doubl
 }
 
 template <int D>
-__global__ __launch_bounds__(256) void k_elements(double alpha, double h, int N, const double *scal, double *E) {
+__global__ __launch_bounds__(256) void k_elements(double alpha, double gamma, double h, int N, const double *scal,
+                                                  double *E) {
     const long total = D == 2 ? (long)N * N : (long)N * N * N;
-    const double q = D + alpha - 2.0;
+    const double q = D + alpha - gamma;
     const double hq = pow(h, D - q);
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (long)gridDim.x * blockDim.x) {
@@ -202,9 +206,10 @@ __global__ __launch_bounds__(256) void k_elements(double alpha, double h, int N,
     }
 }
 
-// a_v and the a_0 summand W_v / |xi_v|^2 for every vertex v != 0
+// a_v and the a_0 summand W_v / |xi_v|^gamma for every vertex v != 0
 template <int D>
-__global__ __launch_bounds__(256) void k_vertex(const double *__restrict__ E, int N, double h, double *a, double *term) {
+__global__ __launch_bounds__(256) void k_vertex(const double *__restrict__ E, int N, double h, double gamma, double *a,
+                                                double *term) {
     const int V = N + 1;
     const long total = D == 2 ? (long)V * V : (long)V * V * V;
     const double E0 = E[0];
@@ -237,11 +242,11 @@ __global__ __launch_bounds__(256) void k_vertex(const double *__restrict__ E, in
                 for (int j = lo[1]; j <= hi[1]; ++j)
                     for (int i = lo[0]; i <= hi[0]; ++i) W += E[i + (long)N * (j + (long)N * k)];
         }
-        if (mx == 1) {
+        if (mx == 1 && gamma == 2.0) {  // floor(gamma/2) = 1 only for gamma = 2
             const bool axis = (D - nz) == 1;
             W += axis ? (D == 2 ? E0 : (5.0 / 3.0) * E0) : -E0;
         }
-        const double den = r2 * h * h;
+        const double den = gamma == 2.0 ? r2 * h * h : pow(r2 * h * h, 0.5 * gamma);
         term[idx] = W / den;
         a[idx] = (double)(1 << nz) * W / ((D == 2 ? 4.0 : 8.0) * den);
     }
@@ -298,13 +303,14 @@ fl_status build_coeffs(fl_op op, hipStream_t s) {
     term = E + ne;
     part = term + nv;
     scal = part + np;
-    hipLaunchKernelGGL(k_closed_forms, dim3(1), dim3(256), 0, s, d, op->alpha, op->h, N, scal);
+    const double g = op->gamma;
+    hipLaunchKernelGGL(k_closed_forms, dim3(1), dim3(256), 0, s, d, op->alpha, g, op->h, N, scal);
     if (d == 2) {
-        hipLaunchKernelGGL(k_elements<2>, dim3(grid_for(ne)), dim3(256), 0, s, op->alpha, op->h, N, scal, E);
-        hipLaunchKernelGGL(k_vertex<2>, dim3(grid_for(nv)), dim3(256), 0, s, E, N, op->h, op->a, term);
+        hipLaunchKernelGGL(k_elements<2>, dim3(grid_for(ne)), dim3(256), 0, s, op->alpha, g, op->h, N, scal, E);
+        hipLaunchKernelGGL(k_vertex<2>, dim3(grid_for(nv)), dim3(256), 0, s, E, N, op->h, g, op->a, term);
     } else {
-        hipLaunchKernelGGL(k_elements<3>, dim3(grid_for(ne)), dim3(256), 0, s, op->alpha, op->h, N, scal, E);
-        hipLaunchKernelGGL(k_vertex<3>, dim3(grid_for(nv)), dim3(256), 0, s, E, N, op->h, op->a, term);
+        hipLaunchKernelGGL(k_elements<3>, dim3(grid_for(ne)), dim3(256), 0, s, op->alpha, g, op->h, N, scal, E);
+        hipLaunchKernelGGL(k_vertex<3>, dim3(grid_for(nv)), dim3(256), 0, s, E, N, op->h, g, op->a, term);
     }
     hipLaunchKernelGGL(k_sum_partial, dim3(np), dim3(256), 0, s, term, nv, chunk, part);
     hipLaunchKernelGGL(k_a0_final, dim3(1), dim3(256), 0, s, part, np, scal, d, op->a);

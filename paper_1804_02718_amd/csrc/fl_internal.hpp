@@ -257,6 +257,7 @@ struct fl_op_s {
     int d = 0, N = 0, n = 0, P = 0, Q = 0, Qp = 0;
     int64_t M = 0;
     double alpha = 0, h = 0, c = 0, a0 = 0;
+    double gamma = 2.0;           // splitting parameter of the scheme, in (alpha, 2]
     int device = 0;
     double *a = nullptr;          // (N+1)^d coefficients, a[0] = a_0
     double *lam64 = nullptr;      // Q^d eigenvalues / P^d, natural order

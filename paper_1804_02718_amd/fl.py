@@ -24,7 +24,8 @@ EXPORTED = ["fl_coeffs", "fl_apply", "fl_apply_profiled", "fl_variant_count", "f
             "fl_allen_cahn_step_ex", "fl_op_destroy", "fl_op_describe", "fl_get_coeffs", "fl_get_symbol",
             "fl_status_string", "fl_last_error", "fl_unet_create", "fl_unet_destroy", "fl_unet_num_params",
             "fl_unet_step", "fl_unet_get_weights", "fl_unet_set_weights", "fl_unet_apply", "fl_set_preconditioner",
-            "fl_gemm_test", "fl_unet_pack", "fl_unet_train", "fl_allen_cahn_step_gen"]
+            "fl_gemm_test", "fl_unet_pack", "fl_unet_train", "fl_allen_cahn_step_gen",
+            "fl_coeffs_gamma"]
 
 
 class FlLibraryMissing(RuntimeError):
@@ -58,7 +59,8 @@ class fl_solve_opts(ctypes.Structure):
 class fl_op_desc(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int), ("N", ctypes.c_int), ("n", ctypes.c_int), ("P", ctypes.c_int),
                 ("Q", ctypes.c_int), ("M", ctypes.c_int64), ("alpha", ctypes.c_double),
-                ("h", ctypes.c_double), ("c", ctypes.c_double), ("a0", ctypes.c_double)]
+                ("h", ctypes.c_double), ("c", ctypes.c_double), ("a0", ctypes.c_double),
+                ("gamma", ctypes.c_double)]
 
 
 _LIB = None
@@ -74,6 +76,7 @@ def load(path: str = LIB_PATH):
     lib = ctypes.CDLL(path)
     vp, dp, ip = ctypes.c_void_p, ctypes.c_double, ctypes.c_int
     lib.fl_coeffs.argtypes = [ip, dp, dp, ip, ctypes.POINTER(vp)]
+    lib.fl_coeffs_gamma.argtypes = [ip, dp, dp, dp, ip, ctypes.POINTER(vp)]
     lib.fl_apply.argtypes = [vp, vp, vp, ip, vp]
     lib.fl_apply_profiled.argtypes = [vp, vp, vp, ip, ip, vp, ctypes.POINTER(ctypes.c_float),
                                       ctypes.POINTER(ctypes.c_int)]
@@ -154,6 +157,12 @@ def _ptr(t, dtype=None, numel=None):
 def fl_coeffs(d: int, alpha: float, h: float, N: int) -> ctypes.c_void_p:
     op = ctypes.c_void_p()
     _check(load().fl_coeffs(int(d), float(alpha), float(h), int(N), ctypes.byref(op)))
+    return op
+
+
+def fl_coeffs_gamma(d: int, alpha: float, gamma: float, h: float, N: int) -> ctypes.c_void_p:
+    op = ctypes.c_void_p()
+    _check(load().fl_coeffs_gamma(int(d), float(alpha), float(gamma), float(h), int(N), ctypes.byref(op)))
     return op
 
 
@@ -488,8 +497,8 @@ class Batch:
 class Operator:
     """The discrete fractional Laplacian on (a, a + N h)^d, zero outside (one fl_op)."""
 
-    def __init__(self, d: int, alpha: float, h: float, N: int):
-        self._op = fl_coeffs(d, alpha, h, N)
+    def __init__(self, d: int, alpha: float, h: float, N: int, gamma: float = 2.0):
+        self._op = fl_coeffs(d, alpha, h, N) if gamma == 2.0 else fl_coeffs_gamma(d, alpha, gamma, h, N)
         self.desc = fl_op_describe(self._op)
         for k, v in self.desc.items():
             setattr(self, k, v)

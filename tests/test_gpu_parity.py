@@ -255,3 +255,30 @@ def test_apply_rejects_overlap_and_dtype_mix(dev):
     with pytest.raises(TypeError):
         fl.fl_apply(op.handle, u, torch.zeros(49, dtype=torch.float32, device="cuda:0"))
     op.close()
+
+
+@pytest.mark.parametrize("d,N,alpha,gamma", [(2, 33, 0.7, 1.35), (2, 64, 1.5, 1.75), (3, 9, 1.2, 1.6)])
+def test_gamma_below_two_coeffs_and_apply(dev, d, N, alpha, gamma):
+    """Splitting parameter gamma < 2 (Sec. 2): coefficients and the FP64 matvec against the oracle."""
+    fl = _fl()
+    h = 2.0 / N
+    op = fl.Operator(d, alpha, h, N, gamma=gamma)
+    assert op.desc["gamma"] == gamma
+    a_ref = oracle.coeffs(d, alpha, h, N, gamma=gamma)
+    a_gpu = op.coeffs()
+    rel = np.abs(a_gpu - a_ref) / np.abs(a_ref)
+    assert rel.max() < 1e-13, rel.max()
+    u = inputs.uniform((N - 1) ** d, 7)
+    y = op.apply(torch.as_tensor(u, device="cuda:0")).cpu().numpy()
+    ref = oracle.apply(d, N, alpha, a_ref, u)
+    absref = oracle.apply(d, N, alpha, a_ref, u, absmode=True)
+    assert np.abs(y - ref).max() <= 1e-14 * np.abs(absref).max()
+    assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_gamma_rejects(dev):
+    fl = _fl()
+    with pytest.raises(fl.FlError):
+        fl.Operator(2, 1.5, 0.1, 20, gamma=1.4)  # gamma <= alpha
+    with pytest.raises(fl.FlError):
+        fl.Operator(2, 1.5, 0.1, 20, gamma=2.1)

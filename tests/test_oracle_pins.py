@@ -411,3 +411,46 @@ def test_kissing_bubbles_initial_state():
     assert ub[0, 0] < 0.01 and ub[-1, -1] < 0.01
     # symmetric about the diagonal and under (x, y) -> (1 - y, 1 - x)
     assert np.allclose(ub, ub.T, atol=0) and np.allclose(ub, ub[::-1, ::-1].T, atol=1e-14)
+
+
+@pytest.mark.parametrize("alpha,gamma", [(0.7, 1.35), (1.0, 1.5), (1.5, 1.75)])
+def test_gamma_below_two_rate(alpha, gamma):
+    # Sec. 5.1, Example 5.1.2: a splitting parameter gamma in (alpha, 2) gives O(h^{2-alpha})
+    # (1.3 for alpha = 0.7, 0.5 for alpha = 1.5) against O(h^2) for gamma = 2.  With gamma < 2 the
+    # origin element drops the limit of the difference quotient (0 instead of the second-order
+    # term), so the leading error is proportional to Delta u(x): on the Gaussian it vanishes at
+    # r = 1, where the error stays second order.
+    errs = []
+    for N in (64, 128, 256):
+        h = 8.0 / N
+        n = N - 1
+        u = inputs.gaussian(2, N)
+        a = oracle.coeffs(2, alpha, h, N, gamma=gamma)
+        ic = N // 2 - 1
+        y = oracle.apply_rows(2, N, alpha, a, u, [ic * n + ic, ic * n + ic + N // 8])
+        errs.append([abs(y[0] - _gauss_exact(2, alpha, 0.0)), abs(y[1] - _gauss_exact(2, alpha, 1.0))])
+    errs = np.array(errs)
+    rates = np.log2(errs[:-1] / errs[1:])
+    assert abs(rates[-1, 0] - (2.0 - alpha)) < 0.08, rates
+    assert rates[-1, 1] > 1.9, rates
+
+
+@pytest.mark.parametrize("d,alpha,gamma", [(2, 0.6, 1.2), (3, 1.1, 1.6)])
+def test_gamma_below_two_invariants(d, alpha, gamma):
+    # elements integrate |xi|^{-(d+alpha-gamma)}: their sum is the closed form over (0, L)^d;
+    # a_v > 0 off the origin, symmetric under index permutation, and no origin correction:
+    # a_v 2^d |xi_v|^gamma / 2^sigma equals the plain patch sum W_v on the unit cube's vertices
+    N, h = 6, 0.25
+    a, E = oracle.coeffs(d, alpha, h, N, return_elements=True, gamma=gamma)
+    q = d + alpha - gamma
+    L = N * h
+    assert E.sum() == pytest.approx(d * L ** (d - q) * oracle.J(d, q) / (d - q), rel=1e-12)
+    flat = a.ravel()
+    assert np.all(flat[1:] > 0)
+    assert np.allclose(a, np.swapaxes(a, 0, 1), rtol=1e-14, atol=0)
+    if d == 2:
+        # vertex (1, 0): the elements (0, 0) and (1, 0) (numpy order (e_y, e_x)), sigma = 1
+        assert a[0, 1] == pytest.approx(2.0 * (E[0, 0] + E[0, 1]) / (4.0 * h ** gamma), rel=1e-13)
+        # vertex (1, 1): the four elements around it, sigma = 0, |xi| = sqrt(2) h
+        W = E[0, 0] + E[0, 1] + E[1, 0] + E[1, 1]
+        assert a[1, 1] == pytest.approx(W / (4.0 * (np.sqrt(2.0) * h) ** gamma), rel=1e-13)
