@@ -18,7 +18,8 @@
  *     M = n^d unknowns.  A grid vector holds the values at the interior nodes
  *     x_i = a + i h, i in [1, N-1]^d, flattened with the x index fastest (the
  *     ordering of the paper's matrix form).  Boundary and exterior values are
- *     0 and are not stored.
+ *     0 and are not stored.  An operator built by fl_coeffs_box has its own
+ *     node count per axis instead (fl_op_desc.nk) and M = their product.
  *   - Vector pointers are DEVICE pointers (hipMalloc'ed or torch CUDA
  *     tensors) owned by the caller; the library never frees them.  Host
  *     pointers are marked as such.
@@ -80,10 +81,11 @@ typedef struct {
 
 typedef struct {
     int d, N, n, P, Q;    /* dimension, intervals, interior nodes, FFT length, P/2+1 */
-    int64_t M;            /* unknowns n^d                                        */
+    int64_t M;            /* unknowns nk[0] nk[1] nk[2] (n^d on the square)       */
     double alpha, h, c;   /* fractional order, mesh size, c_{d,alpha}            */
     double a0;            /* diagonal coefficient a_0 (A_ii = -c a_0)            */
     double gamma;         /* splitting parameter of the scheme                   */
+    int nk[3];            /* interior nodes per axis, x first (1 past d)         */
 } fl_op_desc;
 
 /*
@@ -115,6 +117,24 @@ fl_status fl_coeffs(int d, double alpha, double h, int N, fl_op *out);
  * gamma is outside (alpha, 2].
  */
 fl_status fl_coeffs_gamma(int d, double alpha, double gamma, double h, int N, fl_op *out);
+
+/*
+ * fl_coeffs_box -- the operator on a box (a_x, b_x) x (a_y, b_y) [x (a_z, b_z)]
+ * (Sec. 2 for d = 2, Sec. 4 for d = 3).  Nk[k] is the number of intervals of
+ * width h along axis k (x first), the smallest with a_k + Nk[k] h >= b_k.  The
+ * scheme takes L as the longest side and N = max Nk intervals along it, so
+ * the coefficients a_v, v in [0, N]^d, and lambda are those of the square
+ * (0, L)^d of fl_coeffs_gamma(d, alpha, gamma, h, N); the box keeps Nk[k] - 1
+ * interior nodes per axis (the sums of the scheme stop at N_x - 1, N_y - 1,
+ * N_z - 1), M = prod (Nk[k] - 1) unknowns, x index fastest.  Every call that
+ * takes the handle works on the box's vectors of M entries, except the
+ * learned-preconditioner solver (square grids only: FL_E_INVAL) and the
+ * batched solver (which builds its own square operators).
+ *   Nk: host array of d ints, each >= 2, max Nk within the range of
+ *   fl_coeffs.  Errors as fl_coeffs_gamma; FL_E_INVAL when Nk is NULL or an
+ *   entry is below 2.
+ */
+fl_status fl_coeffs_box(int d, double alpha, double gamma, double h, const int *Nk, fl_op *out);
 
 /*
  * fl_apply -- y = A u, the discrete fractional Laplacian (Sec. 2 2D scheme /

@@ -65,6 +65,9 @@ def _lib():
         lib.orc_apply_rows.restype = ctypes.c_int
         lib.orc_apply_rows.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp,
                                        i64p, ctypes.c_int64, dp, ctypes.c_int]
+        lib.orc_apply_rows_box.restype = ctypes.c_int
+        lib.orc_apply_rows_box.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_double,
+                                           dp, dp, i64p, ctypes.c_int64, dp, ctypes.c_int]
         lib.orc_gl_rule.restype = None
         lib.orc_gl_rule.argtypes = [ctypes.c_int, dp, dp]
         lib.orc_num_threads.restype = ctypes.c_int
@@ -145,54 +148,61 @@ def coeffs(d: int, alpha: float, h: float, N: int, return_elements: bool = False
 
 
 def apply_rows(d: int, N: int, alpha: float, a: np.ndarray, u: np.ndarray, rows=None,
-               absmode: bool = False) -> np.ndarray:
+               absmode: bool = False, shape=None) -> np.ndarray:
     """(A u)_i = -c sum_j a_{|i-j|} u_j for the interior rows i (Sec. 2 / Sec. 4 scheme).
 
-    ``u`` has (N-1)^d entries, x index fastest.  ``rows`` are flat interior
+    ``u`` has (N-1)^d entries, x index fastest, or on a box (``shape`` = interior
+    nodes per axis, x first, each <= N-1; the coefficient table is the one of
+    the square of side L = N h, the longest side).  ``rows`` are flat interior
     indices (all rows when None).  ``absmode`` gives c sum_j |a_{|i-j|} u_j|.
     """
     c = const(d, alpha)
     a = np.ascontiguousarray(a, dtype=np.float64).ravel()
     u = np.ascontiguousarray(u, dtype=np.float64).ravel()
-    n = N - 1
-    if u.size != n ** d or a.size != (N + 1) ** d:
+    nk = [N - 1] * d if shape is None else [int(x) for x in shape]
+    if len(nk) != d or min(nk) < 1 or max(nk) > N - 1:
+        raise ValueError("bad shape")
+    M = int(np.prod(nk))
+    if u.size != M or a.size != (N + 1) ** d:
         raise ValueError("size mismatch")
+    nka = (ctypes.c_int * 3)(*(nk + [1] * (3 - d)))
     if rows is None:
-        y = np.zeros(n ** d)
-        rc = _lib().orc_apply_rows(d, N, c, _dp(a), _dp(u), None, 0, _dp(y), int(absmode))
+        y = np.zeros(M)
+        rc = _lib().orc_apply_rows_box(d, N, nka, c, _dp(a), _dp(u), None, 0, _dp(y), int(absmode))
     else:
         r = np.ascontiguousarray(rows, dtype=np.int64).ravel()
-        if r.size and (r.min() < 0 or r.max() >= n ** d):
+        if r.size and (r.min() < 0 or r.max() >= M):
             raise ValueError("row index out of range")
         y = np.zeros(r.size)
-        rc = _lib().orc_apply_rows(d, N, c, _dp(a), _dp(u),
-                                   r.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                                   r.size, _dp(y), int(absmode))
+        rc = _lib().orc_apply_rows_box(d, N, nka, c, _dp(a), _dp(u),
+                                       r.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                       r.size, _dp(y), int(absmode))
     if rc:
-        raise ValueError("orc_apply_rows failed (%d)" % rc)
+        raise ValueError("orc_apply_rows_box failed (%d)" % rc)
     return y
 
 
-def apply(d, N, alpha, a, u, absmode=False):
-    return apply_rows(d, N, alpha, a, u, None, absmode)
+def apply(d, N, alpha, a, u, absmode=False, shape=None):
+    return apply_rows(d, N, alpha, a, u, None, absmode, shape)
 
 
-def dense(d: int, N: int, alpha: float, a: np.ndarray) -> np.ndarray:
-    """Dense matrix A_{ij} = -c a_{|i-j|} (Sec. 2 block Toeplitz / Sec. 4 three-level Toeplitz)."""
+def dense(d: int, N: int, alpha: float, a: np.ndarray, shape=None) -> np.ndarray:
+    """Dense matrix A_{ij} = -c a_{|i-j|} (Sec. 2 block Toeplitz / Sec. 4 three-level Toeplitz),
+    on the square grid or on a box of ``shape`` interior nodes per axis (x first)."""
     c = const(d, alpha)
-    n = N - 1
-    idx = np.arange(n)
-    D = np.abs(idx[:, None] - idx[None, :])
+    nk = [N - 1] * d if shape is None else [int(x) for x in shape]
+    Ds = [np.abs(np.arange(m)[:, None] - np.arange(m)[None, :]) for m in nk]
     a = np.asarray(a)
+    M = int(np.prod(nk))
     if d == 2:
-        # a is indexed [v1, v0]; row i = i1*n + i0, column j = j1*n + j0
-        A = a[D[:, None, :, None], D[None, :, None, :]]  # [i1, i0, j1, j0]
-        A = A.reshape(n * n, n * n)
+        # a is indexed [v1, v0]; row i = i1*n0 + i0, column j = j1*n0 + j0
+        D0, D1 = Ds
+        A = a[D1[:, None, :, None], D0[None, :, None, :]]  # [i1, i0, j1, j0]
     else:
-        A = a[D[:, None, None, :, None, None], D[None, :, None, None, :, None],
-              D[None, None, :, None, None, :]]  # [i2, i1, i0, j2, j1, j0]
-        A = A.reshape(n ** 3, n ** 3)
-    return -c * A
+        D0, D1, D2 = Ds
+        A = a[D2[:, None, None, :, None, None], D1[None, :, None, None, :, None],
+              D0[None, None, :, None, None, :]]  # [i2, i1, i0, j2, j1, j0]
+    return -c * A.reshape(M, M)
 
 
 def solve_dense(A: np.ndarray, f: np.ndarray) -> np.ndarray:

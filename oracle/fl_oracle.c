@@ -310,51 +310,48 @@ double orc_const(int d, double alpha)
 /* rows == NULL evaluates every row.  absmode != 0 returns             */
 /* c sum_j |a_{|i-j|}| |u_j| instead (the size of the sum's terms).     */
 /* ------------------------------------------------------------------ */
-int orc_apply_rows(int d, int N, double c, const double *a, const double *u,
-                   const int64_t *rows, int64_t nrows, double *y, int absmode)
+/* The scheme on a box of nk[k] interior nodes per axis (x first), nk[k] <= N-1:
+ * (A u)_i = -c sum_j a_{|i-j|} u_j over the box (Sec. 2 scheme, whose sums run
+ * to N_x - 1 and N_y - 1; Sec. 4 likewise).  a is the (N+1)^d table of the
+ * square (0, L)^d, L = N h, the longest side. */
+int orc_apply_rows_box(int d, int N, const int *nk, double c, const double *a, const double *u,
+                       const int64_t *rows, int64_t nrows, double *y, int absmode)
 {
     if (d != 2 && d != 3) return 1;
-    int n = N - 1;
     int V = N + 1;
-    int64_t M = 1;
-    for (int i = 0; i < d; ++i) M *= n;
+    int n0 = nk[0], n1 = nk[1], n2 = d == 3 ? nk[2] : 1;
+    for (int k = 0; k < d; ++k)
+        if (nk[k] < 1 || nk[k] > N - 1) return 2;
+    int64_t M = (int64_t)n0 * n1 * n2;
     int64_t R = rows ? nrows : M;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t r = 0; r < R; ++r) {
         int64_t i = rows ? rows[r] : r;
-        int ii[3] = {0, 0, 0};
-        int64_t t = i;
-        for (int k = 0; k < d; ++k) { ii[k] = (int)(t % n); t /= n; }
+        int i0 = (int)(i % n0), i1 = (int)((i / n0) % n1), i2 = (int)(i / ((int64_t)n0 * n1));
         long double acc = 0.0L;
-        if (d == 2) {
-            for (int j1 = 0; j1 < n; ++j1) {
-                int m1 = abs(ii[1] - j1);
-                const double *arow = a + (int64_t)V * m1;
-                const double *urow = u + (int64_t)n * j1;
-                for (int j0 = 0; j0 < n; ++j0) {
-                    int m0 = abs(ii[0] - j0);
+        for (int j2 = 0; j2 < n2; ++j2) {
+            int m2 = abs(i2 - j2);
+            for (int j1 = 0; j1 < n1; ++j1) {
+                int m1 = abs(i1 - j1);
+                const double *arow = a + (int64_t)V * (m1 + (int64_t)V * m2);
+                const double *urow = u + (int64_t)n0 * (j1 + (int64_t)n1 * j2);
+                for (int j0 = 0; j0 < n0; ++j0) {
+                    int m0 = abs(i0 - j0);
                     if (absmode) acc += fabsl((long double)arow[m0] * urow[j0]);
                     else acc += (long double)arow[m0] * urow[j0];
-                }
-            }
-        } else {
-            for (int j2 = 0; j2 < n; ++j2) {
-                int m2 = abs(ii[2] - j2);
-                for (int j1 = 0; j1 < n; ++j1) {
-                    int m1 = abs(ii[1] - j1);
-                    const double *arow = a + (int64_t)V * (m1 + (int64_t)V * m2);
-                    const double *urow = u + (int64_t)n * (j1 + (int64_t)n * j2);
-                    for (int j0 = 0; j0 < n; ++j0) {
-                        int m0 = abs(ii[0] - j0);
-                        if (absmode) acc += fabsl((long double)arow[m0] * urow[j0]);
-                        else acc += (long double)arow[m0] * urow[j0];
-                    }
                 }
             }
         }
         y[r] = absmode ? (double)(fabs(c) * acc) : (double)(-(long double)c * acc);
     }
     return 0;
+}
+
+int orc_apply_rows(int d, int N, double c, const double *a, const double *u,
+                   const int64_t *rows, int64_t nrows, double *y, int absmode)
+{
+    int nk[3] = {N - 1, N - 1, N - 1};
+    return orc_apply_rows_box(d, N, nk, c, a, u, rows, nrows, y, absmode);
 }
 
 int orc_num_threads(void)

@@ -70,7 +70,11 @@ static void destroy(fl_op op) {
     delete op;
 }
 
-static fl_status create(int d, double alpha, double gamma, double h, int N, fl_op *out) {
+// Nk: intervals per axis (x first) of a box; nullptr for the square of N per axis.
+// The coefficients and the symbol are those of the square of side L = N h,
+// N = max Nk (Sec. 2 takes L as the longest side and N_x = N); the box keeps
+// Nk - 1 interior nodes per axis.
+static fl_status create(int d, double alpha, double gamma, double h, int N, const int *Nk, fl_op *out) {
     fl_op op = new (std::nothrow) fl_op_s();
     if (!op) {
         set_error("host allocation failed");
@@ -88,18 +92,19 @@ static fl_status create(int d, double alpha, double gamma, double h, int N, fl_o
     if (op->P < 8) op->P = 8;
     op->Q = op->P / 2 + 1;
     op->Qp = ((op->Q + 15) / 16) * 16;
-    op->M = d == 2 ? (int64_t)op->n * op->n : (int64_t)op->n * op->n * op->n;
+    for (int k = 0; k < 3; ++k) op->nk[k] = k >= d ? 1 : (Nk ? Nk[k] - 1 : op->n);
+    op->M = (int64_t)op->nk[0] * op->nk[1] * op->nk[2];
     (void)hipGetDevice(&op->device);
     const long V = N + 1;
     const long nv = d == 2 ? V * V : V * V * V;
     const long ql = d == 2 ? (long)op->Q * op->Q : (long)op->Q * op->Q * op->Q;
-    const long n = op->n;
     // tiled spectra: ntiles * C <= Q + C - 1 columns per line, sized for the
-    // widest tile and 16-byte (FP64) values
+    // widest tile and 16-byte (FP64) values; lines: the x pass's rows (T1),
+    // the z lines times P y frequencies (T2, 3D)
     const long w32 = op->Q + kMaxTile - 1, w64 = op->Q + kMaxTile - 1;
     const size_t colb = sizeof(double2) * w64;
-    op->T1_bytes = colb * (size_t)(d == 2 ? n : n * n);
-    op->T2_bytes = d == 2 ? 0 : colb * (size_t)n * op->P;
+    op->T1_bytes = colb * (size_t)op->nk[1] * op->nk[2];
+    op->T2_bytes = d == 2 ? 0 : colb * (size_t)op->nk[2] * op->P;
     const long qrest = d == 2 ? (long)op->Q : (long)op->Q * op->Q;
     fl_status st = FL_OK;
     auto fail = [&](fl_status s) {
@@ -164,8 +169,7 @@ const char *fl_status_string(fl_status s) {
     return "unknown status";
 }
 
-fl_status fl_coeffs_gamma(int d, double alpha, double gamma, double h, int N, fl_op *out) {
-    g_err[0] = 0;
+static fl_status check_args(int d, double alpha, double gamma, double h, fl_op *out) {
     if (!(gamma > alpha && gamma <= 2.0)) {
         set_error("gamma must lie in (alpha, 2] (got gamma=%g, alpha=%g)", gamma, alpha);
         return FL_E_INVAL;
@@ -174,10 +178,35 @@ fl_status fl_coeffs_gamma(int d, double alpha, double gamma, double h, int N, fl
     if (d != 2 && d != 3) { set_error("d must be 2 or 3 (got %d)", d); return FL_E_INVAL; }
     if (!(alpha > 0.0 && alpha < 2.0)) { set_error("alpha must lie in (0,2) (got %g)", alpha); return FL_E_INVAL; }
     if (!(h > 0.0) || !std::isfinite(h)) { set_error("h must be positive and finite"); return FL_E_INVAL; }
+    return FL_OK;
+}
+
+static fl_status check_N(int d, int N) {
     if (N < 2) { set_error("N must be >= 2 (got %d)", N); return FL_E_INVAL; }
     const int nmax = d == 2 ? 1025 : 513;
     if (N > nmax) { set_error("N=%d exceeds the built range (N <= %d for d=%d)", N, nmax, d); return FL_E_UNSUPPORTED; }
-    return create(d, alpha, gamma, h, N, out);
+    return FL_OK;
+}
+
+fl_status fl_coeffs_gamma(int d, double alpha, double gamma, double h, int N, fl_op *out) {
+    g_err[0] = 0;
+    fl_status st = check_args(d, alpha, gamma, h, out);
+    if (st == FL_OK) st = check_N(d, N);
+    return st == FL_OK ? create(d, alpha, gamma, h, N, nullptr, out) : st;
+}
+
+fl_status fl_coeffs_box(int d, double alpha, double gamma, double h, const int *Nk, fl_op *out) {
+    g_err[0] = 0;
+    fl_status st = check_args(d, alpha, gamma, h, out);
+    if (st != FL_OK) return st;
+    if (!Nk) { set_error("Nk is NULL"); return FL_E_INVAL; }
+    int N = 0;
+    for (int k = 0; k < d; ++k) {
+        if (Nk[k] < 2) { set_error("Nk[%d] must be >= 2 (got %d)", k, Nk[k]); return FL_E_INVAL; }
+        N = Nk[k] > N ? Nk[k] : N;
+    }
+    st = check_N(d, N);
+    return st == FL_OK ? create(d, alpha, gamma, h, N, Nk, out) : st;
 }
 
 fl_status fl_coeffs(int d, double alpha, double h, int N, fl_op *out) {
@@ -207,6 +236,7 @@ fl_status fl_op_describe(fl_op op, fl_op_desc *desc) {
     desc->c = op->c;
     desc->a0 = op->a0;
     desc->gamma = op->gamma;
+    for (int k = 0; k < 3; ++k) desc->nk[k] = op->nk[k];
     return FL_OK;
 }
 

@@ -479,6 +479,7 @@ template <typename T> MvCtx<T> single_ctx(fl_op op) {
     MvCtx<T> c;
     c.d = op->d;
     c.n = op->n;
+    for (int k = 0; k < 3; ++k) c.nk[k] = op->nk[k];
     c.P = op->P;
     c.Q = op->Q;
     c.T1 = op->T1;
@@ -493,7 +494,9 @@ template MvCtx<double> single_ctx<double>(fl_op);
 template <typename T, int P, int D, int EX, int EY, int C, int LPB>
 static void matvec_v(const MvCtx<T> &cx, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
                      const hipEvent_t *ev) {
-    const int n = cx.n, Q = cx.Q;
+    // interior nodes per axis: the box's own sizes, all below P / 2 + 1, so the
+    // same embedding (period P per axis) holds every pair of nodes of the box
+    const int nx = cx.nk[0], ny = cx.nk[1], nz = cx.nk[2], Q = cx.Q;
     const int nt = cdiv(spec_cols(D, P), C);
     C2<T> *T1 = (C2<T> *)cx.T1;
     C2<T> *T2 = (C2<T> *)cx.T2;
@@ -505,25 +508,25 @@ static void matvec_v(const MvCtx<T> &cx, const T *u, T *y, const Epi<T> &ep, con
     auto E = [&](int i) { return ev ? ev + 2 * i : nullptr; };
     BatchStrides b_in{cx.zs_vec, zt1, 0, cx.zs_done};
     if constexpr (D == 2) {
-        launch_xfwd<T, P, EX, C, LPB, true>(u, T1, n, n, n, n, nt, tw, done, s, E(0), nb, b_in);
-        Strides sy{0, n * C, 0, n * C, C, Q * C, 0, nt * Q * C};
-        launch_strided<T, P, EY, C, 2, true>(T1, T1, P / 2, 1, n, n, sy, tw, lam, done, s, E(1), nb,
+        launch_xfwd<T, P, EX, C, LPB, true>(u, T1, ny, nx, nx, ny, nt, tw, done, s, E(0), nb, b_in);
+        Strides sy{0, ny * C, 0, ny * C, C, Q * C, 0, nt * Q * C};
+        launch_strided<T, P, EY, C, 2, true>(T1, T1, P / 2, 1, ny, ny, sy, tw, lam, done, s, E(1), nb,
                                              BatchStrides{zt1, zt1, cx.zs_lam, cx.zs_done});
-        launch_xinv<T, P, EX, C, LPB, true>(T1, y, n, n, n, n, nt, tw, ep, done, s, E(2), nb,
+        launch_xinv<T, P, EX, C, LPB, true>(T1, y, ny, nx, nx, ny, nt, tw, ep, done, s, E(2), nb,
                                             BatchStrides{zt1, cx.zs_vec, 0, cx.zs_done});
     } else {
-        const long nn = (long)n * n;
-        launch_xfwd<T, P, EX, C, LPB>(u, T1, (int)nn, n, n, n, nt, tw, done, s, E(0), nb, b_in);
-        Strides s1{nt * n * C, n * C, nt * P * C, P * C, C, 0, 0};
-        launch_strided<T, P, EY, C, 0>(T1, T2, Q, n, n, P, s1, tw, nullptr, done, s, E(1), nb,
+        const long rows = (long)ny * nz;
+        launch_xfwd<T, P, EX, C, LPB>(u, T1, (int)rows, nx, nx, ny, nt, tw, done, s, E(0), nb, b_in);
+        Strides s1{nt * ny * C, ny * C, nt * P * C, P * C, C, 0, 0};
+        launch_strided<T, P, EY, C, 0>(T1, T2, Q, nz, ny, P, s1, tw, nullptr, done, s, E(1), nb,
                                        BatchStrides{zt1, zt2, 0, cx.zs_done});
         Strides s2{C, P * C, C, P * C, nt * P * C, Q * Q * C, Q * C};
-        launch_strided<T, P, EY, C, 2>(T2, T2, Q, P, n, n, s2, tw, lam, done, s, E(2), nb,
+        launch_strided<T, P, EY, C, 2>(T2, T2, Q, P, nz, nz, s2, tw, lam, done, s, E(2), nb,
                                        BatchStrides{zt2, zt2, cx.zs_lam, cx.zs_done});
-        Strides s3{nt * P * C, P * C, nt * n * C, n * C, C, 0, 0};
-        launch_strided<T, P, EY, C, 1>(T2, T1, Q, n, P, n, s3, tw, nullptr, done, s, E(3), nb,
+        Strides s3{nt * P * C, P * C, nt * ny * C, ny * C, C, 0, 0};
+        launch_strided<T, P, EY, C, 1>(T2, T1, Q, nz, P, ny, s3, tw, nullptr, done, s, E(3), nb,
                                        BatchStrides{zt2, zt1, 0, cx.zs_done});
-        launch_xinv<T, P, EX, C, LPB>(T1, y, (int)nn, n, n, n, nt, tw, ep, done, s, E(4), nb,
+        launch_xinv<T, P, EX, C, LPB>(T1, y, (int)rows, nx, nx, ny, nt, tw, ep, done, s, E(4), nb,
                                       BatchStrides{zt1, cx.zs_vec, 0, cx.zs_done});
     }
 }
@@ -679,10 +682,9 @@ template fl_status matvec_ex<double>(fl_op, const double *, double *, const Epi<
 
 int kernel_p_supported(int P) { return P >= 8 && P <= 2048 && (P & (P - 1)) == 0; }
 
-int xinv_parts(int d, int n, int P, int prec, int variant) {
+int xinv_parts(int d, long rows, int P, int prec, int variant) {
     const VariantDesc vd = variant_desc_pd(P, d, prec, variant);
-    const long nrows = d == 2 ? (long)n : (long)n * n;
-    return vd.lpb > 0 ? cdiv((nrows + 1) / 2, vd.lpb) : 0;
+    return vd.lpb > 0 ? cdiv((rows + 1) / 2, vd.lpb) : 0;
 }
 
 int variant_count(fl_op op, int prec) {

@@ -255,6 +255,7 @@ template <int P> constexpr int padded_len() { return P + P / 16; }
 // ---------------------------------------------------------------------------
 struct fl_op_s {
     int d = 0, N = 0, n = 0, P = 0, Q = 0, Qp = 0;
+    int nk[3] = {0, 0, 0};        // interior nodes per axis (x first; 1 past d); n each on the square
     int64_t M = 0;
     double alpha = 0, h = 0, c = 0, a0 = 0;
     double gamma = 2.0;           // splitting parameter of the scheme, in (alpha, 2]
@@ -294,8 +295,8 @@ template <typename T> struct Epi {
     bool active() const { return w1 != nullptr || w2 != nullptr || scale != T(1) || dpart != nullptr; }
 };
 // number of X-inverse workgroups of a matvec (the partial sums an epilogue
-// dot writes): d, n, P, precision, kernel variant
-int xinv_parts(int d, int n, int P, int prec, int variant);
+// dot writes): d, rows of the x pass (M / nk[0]), P, precision, kernel variant
+int xinv_parts(int d, long rows, int P, int prec, int variant);
 template <typename T>
 fl_status matvec(fl_op op, const T *u, T *y, hipStream_t s);
 // `done`: optional device flag; when it holds a nonzero value every pass returns at once
@@ -308,6 +309,7 @@ fl_status matvec_ex(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *
 // a batch of same-size problems (blockIdx.z = problem) the per-problem strides
 template <typename T> struct MvCtx {
     int d = 2, n = 0, P = 0, Q = 0;
+    int nk[3] = {0, 0, 0};     // interior nodes per axis, x first
     void *T1 = nullptr, *T2 = nullptr;
     const C2<T> *tw = nullptr;
     const T *lam = nullptr;

@@ -341,7 +341,7 @@ static fl_status cg_run(fl_op op, double s0, double s1, V *d, V *r, V *p, V *kp,
     FL_HIP_TRY(hipGetLastError());
     const double *done = op->scal + S_DONE;
     // (p, Kp) from the matvec's last pass when its workgroups fit the partials array
-    const int np_x = xinv_parts(op->d, op->n, op->P, sizeof(V) == 8 ? FL_FP64 : FL_FP32,
+    const int np_x = xinv_parts(op->d, (long)(op->M / op->nk[0]), op->P, sizeof(V) == 8 ? FL_FP64 : FL_FP32,
                                 sizeof(V) == 8 ? op->var64 : op->var32);
     const bool fused = np_x > 0 && np_x <= kMaxParts;
     int launched = 0;
@@ -578,8 +578,9 @@ fl_status fl_poisson_solve_ex(fl_op op, const double *f, double tol, double *u, 
     fl_solve_opts o = {FL_SOLVE_AUTO, 0, 0, 0, 0.0};
     if (opts) o = *opts;
     if (o.solver < FL_SOLVE_AUTO || o.solver > FL_SOLVE_FPCG) { set_error("unknown solver"); return FL_E_INVAL; }
-    if (o.solver == FL_SOLVE_FPCG && (!op->net || op->d != 2 || op->n > unet_size(op->net))) {
-        set_error("FPCG needs a learned preconditioner attached to a 2D operator with n <= its grid size");
+    if (o.solver == FL_SOLVE_FPCG && (!op->net || op->d != 2 || op->n > unet_size(op->net) ||
+                                      op->nk[0] != op->n || op->nk[1] != op->n)) {
+        set_error("FPCG needs a learned preconditioner attached to a 2D square operator with n <= its grid size");
         return FL_E_INVAL;
     }
     fl_info local;
@@ -775,7 +776,7 @@ static fl_status batch_chunk_launches(BatchClass &c) {
     VecLayout L = layout(c.M);
     const double *done = c.scal + S_DONE;
     // (p, Kp) from the matvec's last pass when its workgroups fit the partials array
-    const int np_x = xinv_parts(c.c32.d, c.c32.n, c.P, FL_FP32, c.var32);
+    const int np_x = xinv_parts(c.c32.d, (long)(c.M / c.n), c.P, FL_FP32, c.var32);
     const bool fused = np_x > 0 && np_x <= kMaxParts;
     Epi<float> ep;
     if (fused) {

@@ -7,6 +7,7 @@ stream to the C entry points of the same names.  The library is required:
 importing works without it, but the first call raises ``FlLibraryMissing``.
 """
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -25,7 +26,7 @@ EXPORTED = ["fl_coeffs", "fl_apply", "fl_apply_profiled", "fl_variant_count", "f
             "fl_status_string", "fl_last_error", "fl_unet_create", "fl_unet_destroy", "fl_unet_num_params",
             "fl_unet_step", "fl_unet_get_weights", "fl_unet_set_weights", "fl_unet_apply", "fl_set_preconditioner",
             "fl_gemm_test", "fl_unet_pack", "fl_unet_train", "fl_allen_cahn_step_gen",
-            "fl_coeffs_gamma"]
+            "fl_coeffs_gamma", "fl_coeffs_box"]
 
 
 class FlLibraryMissing(RuntimeError):
@@ -60,7 +61,7 @@ class fl_op_desc(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int), ("N", ctypes.c_int), ("n", ctypes.c_int), ("P", ctypes.c_int),
                 ("Q", ctypes.c_int), ("M", ctypes.c_int64), ("alpha", ctypes.c_double),
                 ("h", ctypes.c_double), ("c", ctypes.c_double), ("a0", ctypes.c_double),
-                ("gamma", ctypes.c_double)]
+                ("gamma", ctypes.c_double), ("nk", ctypes.c_int * 3)]
 
 
 _LIB = None
@@ -77,6 +78,7 @@ def load(path: str = LIB_PATH):
     vp, dp, ip = ctypes.c_void_p, ctypes.c_double, ctypes.c_int
     lib.fl_coeffs.argtypes = [ip, dp, dp, ip, ctypes.POINTER(vp)]
     lib.fl_coeffs_gamma.argtypes = [ip, dp, dp, dp, ip, ctypes.POINTER(vp)]
+    lib.fl_coeffs_box.argtypes = [ip, dp, dp, dp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(vp)]
     lib.fl_apply.argtypes = [vp, vp, vp, ip, vp]
     lib.fl_apply_profiled.argtypes = [vp, vp, vp, ip, ip, vp, ctypes.POINTER(ctypes.c_float),
                                       ctypes.POINTER(ctypes.c_int)]
@@ -166,10 +168,28 @@ def fl_coeffs_gamma(d: int, alpha: float, gamma: float, h: float, N: int) -> cty
     return op
 
 
+def fl_coeffs_box(d: int, alpha: float, gamma: float, h: float, Nk) -> ctypes.c_void_p:
+    """Operator on a box with Nk[k] intervals of width h along axis k (x first)."""
+    Nk = [int(x) for x in Nk]
+    if len(Nk) != d:
+        raise ValueError("Nk needs %d entries" % d)
+    op = ctypes.c_void_p()
+    _check(load().fl_coeffs_box(int(d), float(alpha), float(gamma), float(h), (ctypes.c_int * d)(*Nk),
+                                ctypes.byref(op)))
+    return op
+
+
+def box_intervals(sides, h):
+    """Intervals per axis of a box of the given side lengths: the smallest N_k with N_k h >= side (Sec. 2)."""
+    return [max(2, int(math.ceil(s / h * (1.0 - 1e-12)))) for s in sides]
+
+
 def fl_op_describe(op) -> dict:
     desc = fl_op_desc()
     _check(load().fl_op_describe(op, ctypes.byref(desc)))
-    return {k: getattr(desc, k) for k, _ in desc._fields_}
+    out = {k: getattr(desc, k) for k, _ in desc._fields_}
+    out["nk"] = list(out["nk"])[:desc.d]
+    return out
 
 
 def fl_apply(op, u, y, stream=None):
@@ -495,10 +515,22 @@ class Batch:
 # convenience wrapper owning one fl_op
 # ---------------------------------------------------------------------------
 class Operator:
-    """The discrete fractional Laplacian on (a, a + N h)^d, zero outside (one fl_op)."""
+    """The discrete fractional Laplacian on (a, a + N h)^d, zero outside (one fl_op).
 
-    def __init__(self, d: int, alpha: float, h: float, N: int, gamma: float = 2.0):
-        self._op = fl_coeffs(d, alpha, h, N) if gamma == 2.0 else fl_coeffs_gamma(d, alpha, gamma, h, N)
+    With ``Nk`` (intervals per axis, x first) it is the operator of the box
+    prod_k (a_k, a_k + Nk[k] h): N = max(Nk) (``N`` may be None), and vectors
+    hold prod_k (Nk[k] - 1) entries, x index fastest.
+    """
+
+    def __init__(self, d: int, alpha: float, h: float, N, gamma: float = 2.0, Nk=None):
+        if Nk is not None:
+            if N is not None and int(N) != max(int(x) for x in Nk):
+                raise ValueError("N must equal max(Nk)")
+            self._op = fl_coeffs_box(d, alpha, gamma, h, Nk)
+        elif gamma == 2.0:
+            self._op = fl_coeffs(d, alpha, h, N)
+        else:
+            self._op = fl_coeffs_gamma(d, alpha, gamma, h, N)
         self.desc = fl_op_describe(self._op)
         for k, v in self.desc.items():
             setattr(self, k, v)
@@ -509,8 +541,12 @@ class Operator:
 
     def apply(self, u, y=None, stream=None):
         import torch
+        if u.numel() != self.M:
+            raise ValueError("expected %d entries, got %d" % (self.M, u.numel()))
         if y is None:
             y = torch.empty_like(u)
+        elif y.numel() != self.M:
+            raise ValueError("expected %d entries, got %d" % (self.M, y.numel()))
         return fl_apply(self._op, u, y, stream)
 
     def poisson_solve(self, f, tol=1e-8, u=None, stream=None, **kw):

@@ -282,3 +282,124 @@ def test_gamma_rejects(dev):
         fl.Operator(2, 1.5, 0.1, 20, gamma=1.4)  # gamma <= alpha
     with pytest.raises(fl.FlError):
         fl.Operator(2, 1.5, 0.1, 20, gamma=2.1)
+
+
+# ---------------------------------------------------------------------------
+# boxes: Nk intervals per axis, the square's coefficients (N = max Nk), the
+# scheme's sums bounded by each axis's own node count (Sec. 2, Sec. 4)
+# ---------------------------------------------------------------------------
+BOX_CASES = [(2, (40, 17), 1.3), (2, (17, 40), 0.5), (2, (2, 9), 1.9), (2, (33, 2), 1.0), (2, (100, 64), 1.5),
+             (2, (130, 7), 0.8), (3, (9, 5, 7), 1.2), (3, (5, 9, 2), 0.6), (3, (2, 2, 9), 1.7),
+             (3, (17, 12, 6), 1.9), (3, (12, 17, 17), 0.4), (3, (33, 3, 20), 1.5)]
+
+
+@pytest.mark.parametrize("d,Nk,alpha", BOX_CASES)
+def test_box_apply_fp64_fp32(dev, d, Nk, alpha):
+    fl = _fl()
+    N = max(Nk)
+    h = 1.0 / N
+    op = fl.Operator(d, alpha, h, None, Nk=Nk)
+    shape = [k - 1 for k in Nk]
+    M = int(np.prod(shape))
+    assert op.desc["nk"] == shape and op.M == M and op.N == N
+    a = oracle.coeffs(d, alpha, h, N)
+    u = inputs.uniform(M, seed=21)
+    ref = oracle.apply(d, N, alpha, a, u, shape=shape)
+    absref = oracle.apply(d, N, alpha, a, u, absmode=True, shape=shape)
+    y = op.apply(_t(u)).cpu().numpy()
+    e_rel, e_sc = _errs(y, ref, absref)
+    assert e_sc < 1e-14 and e_rel < 1e-12, (e_rel, e_sc)
+    u32 = u.astype(np.float32)
+    ref32 = oracle.apply(d, N, alpha, a, u32.astype(np.float64), shape=shape)
+    y32 = op.apply(_t(u32, torch.float32)).cpu().numpy().astype(np.float64)
+    e_rel, e_sc = _errs(y32, ref32, absref)
+    assert e_sc < 1e-6 and e_rel < 1e-5, (e_rel, e_sc)
+    op.close()
+
+
+@pytest.mark.parametrize("d,Nk,alpha", [(2, (1025, 300), 1.5), (2, (257, 1024), 0.7), (3, (257, 100, 40), 1.2),
+                                        (3, (60, 200, 129), 1.9)])
+def test_box_apply_large_sampled_every_variant(dev, d, Nk, alpha):
+    fl = _fl()
+    N = max(Nk)
+    h = 1.0 / N
+    op = fl.Operator(d, alpha, h, None, Nk=Nk)
+    shape = [k - 1 for k in Nk]
+    M = int(np.prod(shape))
+    u = inputs.uniform(M, seed=5)
+    u32 = u.astype(np.float32)
+    rows = _sample_rows(M, 16, seed=17)
+    a = oracle.coeffs(d, alpha, h, N)
+    ref = oracle.apply_rows(d, N, alpha, a, u, rows, shape=shape)
+    ref32 = oracle.apply_rows(d, N, alpha, a, u32.astype(np.float64), rows, shape=shape)
+    absref = oracle.apply_rows(d, N, alpha, a, u, rows, absmode=True, shape=shape)
+    for prec, uu, rr, gate in (("fp64", _t(u), ref, 1e-14), ("fp32", _t(u32, torch.float32), ref32, 1e-6)):
+        for k, desc in enumerate(op.variants(prec)):
+            op.select_variant(prec, k)
+            y = op.apply(uu).cpu().numpy()[rows].astype(np.float64)
+            e_rel, e_sc = _errs(y, rr, absref)
+            assert e_sc < gate, (prec, k, desc, e_rel, e_sc)
+    op.close()
+
+
+@pytest.mark.parametrize("d,Nk,alpha", [(2, (60, 25), 1.4), (3, (14, 9, 6), 0.9)])
+@pytest.mark.parametrize("solver", ["cg64", "refine"])
+def test_box_poisson_vs_dense(dev, d, Nk, alpha, solver):
+    fl = _fl()
+    N = max(Nk)
+    h = 1.0 / N
+    op = fl.Operator(d, alpha, h, None, Nk=Nk)
+    shape = [k - 1 for k in Nk]
+    a = oracle.coeffs(d, alpha, h, N)
+    A = oracle.dense(d, N, alpha, a, shape=shape)
+    f = inputs.uniform(A.shape[0], seed=8) + 0.5
+    uref = oracle.solve_dense(A, f)
+    u, info = op.poisson_solve(_t(f), tol=1e-11, solver=solver)
+    ug = u.cpu().numpy()
+    assert np.linalg.norm(f - A @ ug) <= 1.05e-11 * np.linalg.norm(f)
+    assert np.abs(ug - uref).max() <= 2e-11 * np.linalg.cond(A) * np.abs(uref).max()
+    op.close()
+
+
+def test_box_allen_cahn_general_vs_oracle(dev):
+    # (0, 1) x (0, 0.4) with u = -1 outside, shifted field ubar = u + 1 (Sec. 5.3 form)
+    fl = _fl()
+    N, alpha, delta, tau = 40, 1.3, 0.05, 5e-4
+    h = 1.0 / N
+    Nk = fl.box_intervals([1.0, 0.4], h)
+    assert Nk == [40, 16]
+    op = fl.Operator(2, alpha, h, None, Nk=Nk)
+    shape = [k - 1 for k in Nk]
+    a = oracle.coeffs(2, alpha, h, N)
+    A = oracle.dense(2, N, alpha, a, shape=shape)
+    x = h * np.arange(1, Nk[0])
+    y = h * np.arange(1, Nk[1])
+    r = np.sqrt((x[None, :] - 0.5) ** 2 + (y[:, None] - 0.2) ** 2)
+    ub = (np.tanh((0.12 - r) / (np.sqrt(2) * delta)) + 1.0).ravel()
+    gamma = delta ** -alpha
+    ref = ub.copy()
+    u = _t(ub)
+    for _ in range(3):
+        info = op.allen_cahn_step_gen(u, tau, 1.0, gamma, 1.0)
+        assert info["relres"] <= 1e-8
+        ref = oracle.ac_step_gen(2, N, alpha, a, ref, tau, 1.0, gamma, 1.0, 0.5, A=A)
+    assert np.abs(u.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max()
+    op.close()
+
+
+def test_box_rejects(dev):
+    fl = _fl()
+    with pytest.raises(fl.FlError):
+        fl.fl_coeffs_box(2, 1.0, 2.0, 0.1, [10, 1])
+    with pytest.raises(fl.FlError):
+        fl.fl_coeffs_box(3, 1.0, 2.0, 0.1, [10, 600, 4])
+    with pytest.raises(fl.FlError):
+        fl.fl_coeffs_box(2, 1.0, 0.9, 0.1, [10, 5])
+    op = fl.Operator(2, 1.0, 0.1, None, Nk=[10, 5])
+    with pytest.raises(ValueError):
+        op.apply(torch.zeros(81, dtype=torch.float64, device="cuda:0"))
+    net = fl.UNet(16, seed=1)
+    op.set_preconditioner(net)
+    with pytest.raises(fl.FlError):
+        op.poisson_solve(torch.ones(36, dtype=torch.float64, device="cuda:0"), solver="fpcg")
+    op.close()

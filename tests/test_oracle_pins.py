@@ -188,7 +188,7 @@ def test_dense_matrix_spd_and_dominant(d, N, alpha):
     assert np.all(a.ravel()[1:] > 0)
 
 
-def _scheme_2d_literal(a, c, u2, N):
+def _scheme_2d_literal(a, c, u2, Nx, Ny=None):
     """The 2D scheme written with its four quadrant sums (Sec. 2), pure Python loops.
 
     Reading: the second m-sum starts at m = 1.  Printed with m = 0 it counts the
@@ -196,11 +196,10 @@ def _scheme_2d_literal(a, c, u2, N):
     neighbour on an axis enters once) and the block Toeplitz matrix form, whose
     diagonal block entries carry a_0j once.
     """
-    n = N - 1
-    Nx = Ny = N
-    y = np.zeros((n, n))
-    U = np.zeros((N + 1, N + 1))  # U[i, j] with i the x index 0..N
-    U[1:N, 1:N] = u2.T
+    Ny = Nx if Ny is None else Ny
+    y = np.zeros((Ny - 1, Nx - 1))
+    U = np.zeros((Nx + 1, Ny + 1))  # U[i, j] with i the x index 0..Nx
+    U[1:Nx, 1:Ny] = u2.T
     for i in range(1, Nx):
         for j in range(1, Ny):
             s = a[0, 0] * U[i, j]
@@ -227,7 +226,7 @@ def test_apply_matches_literal_quadrant_sums(N):
     c = oracle.const(2, alpha)
     u = inputs.uniform((N - 1) ** 2, seed=11)
     y = oracle.apply(2, N, alpha, a, u)
-    ref = _scheme_2d_literal(a, c, u.reshape(N - 1, N - 1), N)
+    ref = _scheme_2d_literal(a, c, u.reshape(N - 1, N - 1), N, N)
     assert np.allclose(y, ref, rtol=1e-14, atol=1e-14 * np.abs(ref).max())
     if N == 2:
         assert y[0] == pytest.approx(-c * a[0, 0] * u[0], rel=1e-15)
@@ -454,3 +453,69 @@ def test_gamma_below_two_invariants(d, alpha, gamma):
         # vertex (1, 1): the four elements around it, sigma = 0, |xi| = sqrt(2) h
         W = E[0, 0] + E[0, 1] + E[1, 0] + E[1, 1]
         assert a[1, 1] == pytest.approx(W / (4.0 * (np.sqrt(2.0) * h) ** gamma), rel=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# boxes (Sec. 2: L the longest side, N_x = N, N_y the fewest intervals that
+# cover the short side; Sec. 4 likewise with N_z)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("Nx,Ny", [(5, 2), (5, 3), (7, 4), (4, 7), (6, 6)])
+def test_box_apply_matches_literal_quadrant_sums(Nx, Ny):
+    alpha, h = 0.8, 0.2
+    N = max(Nx, Ny)
+    a = oracle.coeffs(2, alpha, h, N)
+    c = oracle.const(2, alpha)
+    u = inputs.uniform((Nx - 1) * (Ny - 1), seed=13)
+    y = oracle.apply(2, N, alpha, a, u, shape=(Nx - 1, Ny - 1))
+    ref = _scheme_2d_literal(a, c, u.reshape(Ny - 1, Nx - 1), Nx, Ny)
+    assert np.allclose(y, ref, rtol=1e-14, atol=1e-14 * np.abs(ref).max())
+    A = oracle.dense(2, N, alpha, a, shape=(Nx - 1, Ny - 1))
+    assert np.allclose(A @ u, y, rtol=1e-13, atol=1e-14 * np.abs(y).max())
+
+
+@pytest.mark.parametrize("shape", [(3, 1, 2), (1, 4, 2), (2, 3, 4), (4, 4, 1)])
+def test_box_3d_is_zero_extension_of_the_cube(shape):
+    # a box vector extended by zero to the cube: A_box u = (A_cube u_ext) on the box
+    # nodes (the exterior of the box contributes nothing); SPD like the cube matrix
+    N, alpha, h = 5, 1.4, 0.3
+    a = oracle.coeffs(3, alpha, h, N)
+    n = N - 1
+    u = inputs.uniform(int(np.prod(shape)), seed=3)
+    ext = np.zeros((n, n, n))  # [z, y, x]
+    ext[:shape[2], :shape[1], :shape[0]] = u.reshape(shape[2], shape[1], shape[0])
+    full = oracle.apply(3, N, alpha, a, ext.ravel()).reshape(n, n, n)
+    y = oracle.apply(3, N, alpha, a, u, shape=shape)
+    ref = full[:shape[2], :shape[1], :shape[0]].ravel()
+    assert np.allclose(y, ref, rtol=1e-14, atol=1e-15 * np.abs(ref).max())
+    A = oracle.dense(3, N, alpha, a, shape=shape)
+    assert np.allclose(A @ u, y, rtol=1e-13, atol=1e-14 * np.abs(y).max())
+    np.linalg.cholesky(A)
+    # one node: the box matrix is the diagonal entry -c a_0
+    if int(np.prod(shape)) == 1:
+        assert A[0, 0] == pytest.approx(-oracle.const(3, alpha) * a[0, 0, 0], rel=1e-15)
+
+
+@pytest.mark.parametrize("alpha", [0.6, 1.4])
+def test_box_gaussian_second_order_2d(alpha):
+    # (-6, 6) x (-4, 4): L = 12, h = 12 / N, N_y = 2 N / 3; exp(-|x|^2) is below 1.2e-7
+    # on the boundary, so the box scheme approximates the whole-plane value at the
+    # origin (Sec. 1 Fourier form) to O(h^2) (Thm 2).  The square (-6, 6)^2 agrees up to
+    # the Gaussian's mass beyond |y| = 4.
+    errs, gap = [], []
+    for N in (48, 96, 192):
+        h = 12.0 / N
+        Ny = 2 * N // 3
+        x = -6.0 + h * np.arange(1, N)
+        yv = -4.0 + h * np.arange(1, Ny)
+        u = np.exp(-(x[None, :] ** 2 + yv[:, None] ** 2)).ravel()
+        a = oracle.coeffs(2, alpha, h, N)
+        row = (Ny // 2 - 1) * (N - 1) + (N // 2 - 1)
+        yb = oracle.apply_rows(2, N, alpha, a, u, [row], shape=(N - 1, Ny - 1))[0]
+        errs.append(abs(yb - _gauss_exact(2, alpha, 0.0)))
+        ys = -6.0 + h * np.arange(1, N)
+        us = np.exp(-(x[None, :] ** 2 + ys[:, None] ** 2)).ravel()
+        rs = (N // 2 - 1) * (N - 1) + (N // 2 - 1)
+        gap.append(abs(yb - oracle.apply_rows(2, N, alpha, a, us, [rs])[0]))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 1.8) and np.all(rates < 2.3), rates
+    assert max(gap) < 1e-5 * abs(_gauss_exact(2, alpha, 0.0)), gap
