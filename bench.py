@@ -277,12 +277,13 @@ PAPER_AC_SECONDS = {1.9: {1024: 25728, 512: 4497, 256: 456, 128: 86},
                     0.7: {1024: 430, 512: 107, 256: 24, 128: 7}}
 
 
-def paper_ac_extra(torch, fl, inputs, sizes=(128, 256, 512, 1024), alphas=(1.9, 1.5, 1.0, 0.7)):
-    """The paper's two kissing bubbles: u_t = -(-Delta)^{alpha/2} u - delta^-alpha u (u^2 - 1) on (0,1)^2,
+def paper_ac_extra(torch, fl, inputs, sizes=(128, 256, 512, 1024), alphas=(1.9, 1.5, 1.0, 0.7),
+                   sizes3d=(128, 256)):
+    """The paper's two kissing bubbles: u_t = -(-Delta)^{alpha/2} u - delta^-alpha u (u^2 - 1) on (0,1)^d,
     u = -1 outside, delta = 0.03, h = 1/N, tau = 5e-4, 30 Crank--Nicolson steps to t = 0.015 (stepped as
-    ubar = u + 1), each solved to an FP64 residual of 1e-8.  The paper's CPU seconds are context."""
+    ubar = u + 1), each solved to an FP64 residual of 1e-8.  The paper's CPU seconds (2D) are context."""
     delta, tau, steps = 0.03, 5e-4, 30
-    out = {"workload": "two kissing bubbles on (0,1)^2, delta=0.03, tau=5e-4, 30 steps to t=0.015, tol 1e-8",
+    out = {"workload": "two kissing bubbles on (0,1)^d, delta=0.03, tau=5e-4, 30 steps to t=0.015, tol 1e-8",
            "runs": []}
     for alpha in alphas:
         for N in sizes:
@@ -299,10 +300,30 @@ def paper_ac_extra(torch, fl, inputs, sizes=(128, 256, 512, 1024), alphas=(1.9, 
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             mass = float((ub - 1.0).abs().sum()) * h * h  # integral of |u| over the box
-            out["runs"].append({"alpha": alpha, "N": N, "seconds": round(dt, 4), "cg_iters": iters,
+            out["runs"].append({"d": 2, "alpha": alpha, "N": N, "seconds": round(dt, 4), "cg_iters": iters,
                                 "mass_in_box": round(mass, 6),
                                 "paper_cpu_seconds": PAPER_AC_SECONDS[alpha][N]})
             op.close()
+    # the 3D run (alpha = 1.9): the paper states neither its 3D mesh nor a time for
+    # it; h = 1/N at the sizes3d, same delta, tau and end time
+    alpha, gamma = 1.9, delta ** -1.9
+    for N in sizes3d:
+        h = 1.0 / N
+        op = fl.Operator(3, alpha, h, N)
+        ub = torch.as_tensor(inputs.kissing_bubbles(N, delta, ((0.4, 0.6, 0.5), (0.6, 0.4, 0.5))),
+                             device="cuda:0")
+        op.allen_cahn_step_gen(ub.clone(), tau, 1.0, gamma, 1.0)
+        torch.cuda.synchronize()
+        iters = 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            iters += op.allen_cahn_step_gen(ub, tau, 1.0, gamma, 1.0)["iters"]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        mass = float((ub - 1.0).abs().sum()) * h ** 3
+        out["runs"].append({"d": 3, "alpha": alpha, "N": N, "seconds": round(dt, 4), "cg_iters": iters,
+                            "mass_in_box": round(mass, 6), "paper_cpu_seconds": None})
+        op.close()
     return out
 
 

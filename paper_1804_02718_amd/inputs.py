@@ -113,11 +113,14 @@ def learned_problem(seed: int, N: int = 256, alpha_range=(0.3, 1.9), gaussians: 
 
 
 def kissing_bubbles(N: int, delta: float = 0.03, centres=((0.4, 0.4), (0.6, 0.6)), radius: float = 0.12):
-    """Two touching bubbles on (0, 1)^2 (Sec. 5.3): u0 = 1 - tanh(d1/delta) - tanh(d2/delta) with
-    d_i = |x - x_i| - radius, at the interior nodes x = i/N, returned as ubar0 = u0 + 1 (the
-    shifted field that is 0 outside the box, where u = -1)."""
-    xs = grid(2, N, 0.0, 1.0)
+    """Two touching bubbles on (0, 1)^d (Sec. 5.3; d = len of a centre, 2 or 3): u0 = 1 - tanh(d1/delta)
+    - tanh(d2/delta) with d_i = |x - x_i| - radius, at the interior nodes x = i/N, returned as
+    ubar0 = u0 + 1 (the shifted field that is 0 outside the box, where u = -1).  The paper's 3D
+    run takes the centres (0.4, 0.6, 0.5) and (0.6, 0.4, 0.5)."""
+    d = len(centres[0])
+    xs = grid(d, N, 0.0, 1.0)
     u = np.ones_like(xs[0])
-    for cx, cy in centres:
-        u -= np.tanh((np.sqrt((xs[0] - cx) ** 2 + (xs[1] - cy) ** 2) - radius) / delta)
+    for c in centres:
+        r = np.sqrt(sum((xs[k] - c[k]) ** 2 for k in range(d)))
+        u -= np.tanh((r - radius) / delta)
     return u + 1.0

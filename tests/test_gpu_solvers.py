@@ -260,6 +260,25 @@ def test_allen_cahn_general_paper_form(fl, alpha):
     assert np.abs(u.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max()
 
 
+def test_allen_cahn_general_paper_form_3d(fl):
+    # the 3D two-bubble run (centres (0.4, 0.6, 0.5), (0.6, 0.4, 0.5), alpha = 1.9) on a coarse grid
+    N, alpha, delta, tau = 10, 1.9, 0.03, 5e-4
+    h = 1.0 / N
+    op = fl.Operator(3, alpha, h, N)
+    a = oracle.coeffs(3, alpha, h, N)
+    A = oracle.dense(3, N, alpha, a)
+    ub0 = inputs.kissing_bubbles(N, delta, ((0.4, 0.6, 0.5), (0.6, 0.4, 0.5)))
+    gamma = delta ** -alpha
+    ref = ub0.copy()
+    u = _t(ub0)
+    for _ in range(3):
+        info = op.allen_cahn_step_gen(u, tau, 1.0, gamma, 1.0)
+        assert info["relres"] <= 1e-8
+        ref = oracle.ac_step_gen(3, N, alpha, a, ref, tau, 1.0, gamma, 1.0, 0.5, A=A)
+    assert np.abs(u.cpu().numpy() - ref).max() <= 1e-7 * np.abs(ref).max()
+    op.close()
+
+
 def test_allen_cahn_general_rejects(fl):
     op = fl.Operator(2, 1.0, 1.0 / 16, 16)
     u = _t(np.zeros(15 * 15))

@@ -412,6 +412,21 @@ def test_kissing_bubbles_initial_state():
     assert np.allclose(ub, ub.T, atol=0) and np.allclose(ub, ub[::-1, ::-1].T, atol=1e-14)
 
 
+def test_kissing_bubbles_initial_state_3d():
+    # the 3D run: centres (0.4, 0.6, 0.5) and (0.6, 0.4, 0.5); at the node (0.4, 0.6, 0.5)
+    # (N = 10, indices x 3, y 5, z 4) d1 = -0.12 and d2 = |(0.2, 0.2, 0)| - 0.12
+    c3 = ((0.4, 0.6, 0.5), (0.6, 0.4, 0.5))
+    ub = inputs.kissing_bubbles(10, 0.03, c3).reshape(9, 9, 9)  # [z, y, x]
+    u = 1.0 - np.tanh(-0.12 / 0.03) - np.tanh((np.hypot(0.2, 0.2) - 0.12) / 0.03)
+    assert ub[4, 5, 3] == pytest.approx(u + 1.0, rel=1e-14)
+    # mirror in z about 0.5, and the swap (x, y) -> (y, x) exchanges the bubbles
+    assert np.allclose(ub, ub[::-1], atol=1e-14)
+    assert np.allclose(ub, ub.transpose(0, 2, 1), atol=1e-14)
+    # the z = 0.5 plane of the 3D field is the 2D field of the same centres
+    ub2 = inputs.kissing_bubbles(10, 0.03, ((0.4, 0.6), (0.6, 0.4))).reshape(9, 9)
+    assert np.allclose(ub[4], ub2, atol=1e-15)
+
+
 @pytest.mark.parametrize("alpha,gamma", [(0.7, 1.35), (1.0, 1.5), (1.5, 1.75)])
 def test_gamma_below_two_rate(alpha, gamma):
     # Sec. 5.1, Example 5.1.2: a splitting parameter gamma in (alpha, 2) gives O(h^{2-alpha})
