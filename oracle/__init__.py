@@ -125,12 +125,14 @@ def coeffs(d: int, alpha: float, h: float, N: int, return_elements: bool = False
     """Scheme coefficients a_v, v in [0,N]^d, numpy index order (v_d, ..., v_1); a[0,..,0] = a_0.
 
     Sec. 2: a_mn and a_00; Sec. 4: a_mns and a_000 (origin correction for
-    (1,1,1) read as +1, the value the gamma = 2 limit rule implies).  gamma is
+    (1,1,1) read as +1, the value the gamma = 2 limit rule implies); d = 1 is
+    the one-dimensional case of the general-d scheme (Sec. 4, Theorems 3-4):
+    a_m = (int_{T_m} w + floor(gamma/2) [m = 1] E_0) / (2 |xi_m|^gamma).  gamma is
     the splitting parameter of Sec. 2, in (alpha, 2]; for gamma < 2 the
     origin-element corrections vanish (their weight is floor(gamma/2)).
     """
-    if d not in (2, 3):
-        raise ValueError("d must be 2 or 3")
+    if d not in (1, 2, 3):
+        raise ValueError("d must be 1, 2 or 3")
     if not (0.0 < alpha < 2.0) or N < 2 or not (h > 0) or not (alpha < gamma <= 2.0):
         raise ValueError("bad parameters")
     a = np.zeros((N + 1) ** d)
@@ -194,6 +196,8 @@ def dense(d: int, N: int, alpha: float, a: np.ndarray, shape=None) -> np.ndarray
     Ds = [np.abs(np.arange(m)[:, None] - np.arange(m)[None, :]) for m in nk]
     a = np.asarray(a)
     M = int(np.prod(nk))
+    if d == 1:
+        return -c * a[Ds[0]]
     if d == 2:
         # a is indexed [v1, v0]; row i = i1*n0 + i0, column j = j1*n0 + j0
         D0, D1 = Ds

@@ -16,7 +16,9 @@
  *     a radial power integrated over a cube corner (pyramid split of the
  *     cube along its diagonal planes).
  *   - element integrals E_e = int_{I_e} |xi|^{-q} dxi, q = d + alpha - gamma,
- *     over the elements I_e of Sec. 2 (2D) and Sec. 4 (3D).  The origin
+ *     over the elements I_e of Sec. 2 (2D) and Sec. 4 (3D), and over the
+ *     intervals of the d = 1 case of the general-d scheme (Sec. 4, the
+ *     theorems for any d >= 1), where every integral has a closed form.  The origin
  *     element is the closed form d h^{d-q} J_d(q)/(d-q) (in 2D this is the
  *     polar identity the paper uses in the proof of Theorem 1); every other
  *     element by tensor Gauss-Legendre quadrature, whose order is fixed by a
@@ -164,6 +166,15 @@ static long double elem_unit(int d, double q, const int *e)
     return 0.125L * acc;
 }
 
+/* int_e^{e+1} x^{-q} dx for e >= 1, as e^{1-q} expm1((1-q) log1p(1/e)) / (1-q)
+ * (no cancellation between the two endpoint powers). */
+static long double interval_unit(double q, int e)
+{
+    long double p = 1.0L - (long double)q;
+    long double le = logl((long double)e);
+    return expl(p * le) * expm1l(p * log1pl(1.0L / (long double)e)) / p;
+}
+
 /* Origin element, closed form: d h^{d-q} J_d(q) / (d-q). */
 double orc_E0(int d, double q, double h)
 {
@@ -180,7 +191,7 @@ double orc_D2(int d, double alpha, double L)
 /* E[e] for e in [0,N-1]^d, x-index fastest.  q = d + alpha - gamma. */
 int orc_elements_g(int d, double alpha, double gamma, double h, int N, double *E)
 {
-    if (d != 2 && d != 3) return 1;
+    if (d < 1 || d > 3) return 1;
     double q = d + alpha - gamma;
     long double scale = powl((long double)h, (long double)(d - q));
     int64_t total = 1;
@@ -192,6 +203,8 @@ int orc_elements_g(int d, double alpha, double gamma, double h, int N, double *E
         for (int i = 0; i < d; ++i) { e[i] = (int)(t % N); t /= N; }
         if (idx == 0)
             E[idx] = orc_E0(d, q, h);
+        else if (d == 1)
+            E[idx] = (double)(scale * interval_unit(q, e[0]));
         else
             E[idx] = (double)(scale * elem_unit(d, q, e));
     }
@@ -218,7 +231,7 @@ int orc_elements(int d, double alpha, double h, int N, double *E)
 /* in 3D with 8 and the 3D cbar.  floor(gamma/2) is 1 only for gamma = 2.    */
 int orc_coeffs_g(int d, double alpha, double gamma, double h, int N, double *a, double *E_out)
 {
-    if (d != 2 && d != 3) return 1;
+    if (d < 1 || d > 3) return 1;
     if (!(alpha > 0.0 && alpha < 2.0) || N < 2 || !(h > 0.0)) return 2;
     if (!(gamma > alpha && gamma <= 2.0)) return 2;
     int64_t ne = 1, nv = 1;
@@ -230,7 +243,7 @@ int orc_coeffs_g(int d, double alpha, double gamma, double h, int N, double *a, 
     int fl_g = gamma == 2.0 ? 1 : 0;  /* floor(gamma/2) on (alpha, 2] */
     double E0 = E[0];
     int V = N + 1;
-    long double twod = (d == 2) ? 4.0L : 8.0L;
+    long double twod = (long double)(1 << d);
 
 #pragma omp parallel for schedule(static)
     for (int64_t idx = 1; idx < nv; ++idx) {
@@ -245,7 +258,9 @@ int orc_coeffs_g(int d, double alpha, double gamma, double h, int N, double *a, 
             lo[i] = v[i] - 1 < 0 ? 0 : v[i] - 1;
             hi[i] = v[i] > N - 1 ? N - 1 : v[i];
         }
-        if (d == 2) {
+        if (d == 1) {
+            for (int e0 = lo[0]; e0 <= hi[0]; ++e0) W += E[e0];
+        } else if (d == 2) {
             for (int e1 = lo[1]; e1 <= hi[1]; ++e1)
                 for (int e0 = lo[0]; e0 <= hi[0]; ++e0)
                     W += E[e0 + (int64_t)N * e1];
@@ -261,10 +276,12 @@ int orc_coeffs_g(int d, double alpha, double gamma, double h, int N, double *a, 
             if (v[i] == 1) ++ones;
             if (v[i] > maxv) maxv = v[i];
         }
-        /* origin-element correction of the gamma = 2 limit rule */
+        /* origin-element correction of the gamma = 2 limit rule (1D: the limit of
+         * psi_2 at the origin is u'', taken as psi_2 at xi = h, so the origin's
+         * share moves to vertex 1 as in the 2D axis rule) */
         if (maxv == 1 && fl_g) {
             int nonzero = d - nz;
-            if (d == 2)
+            if (d <= 2)
                 W += (nonzero == 1) ? (long double)E0 : -(long double)E0;
             else
                 W += (nonzero == 1) ? (5.0L / 3.0L) * E0 : -(long double)E0;
@@ -317,9 +334,9 @@ double orc_const(int d, double alpha)
 int orc_apply_rows_box(int d, int N, const int *nk, double c, const double *a, const double *u,
                        const int64_t *rows, int64_t nrows, double *y, int absmode)
 {
-    if (d != 2 && d != 3) return 1;
+    if (d < 1 || d > 3) return 1;
     int V = N + 1;
-    int n0 = nk[0], n1 = nk[1], n2 = d == 3 ? nk[2] : 1;
+    int n0 = nk[0], n1 = d >= 2 ? nk[1] : 1, n2 = d == 3 ? nk[2] : 1;
     for (int k = 0; k < d; ++k)
         if (nk[k] < 1 || nk[k] > N - 1) return 2;
     int64_t M = (int64_t)n0 * n1 * n2;

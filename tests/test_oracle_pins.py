@@ -61,7 +61,8 @@ def test_origin_element_matches_polar_identity(alpha):
     assert oracle.E0(2, alpha, h) == pytest.approx(float(ref), rel=1e-14)
 
 
-@pytest.mark.parametrize("d,alpha,N", [(2, 0.4, 12), (2, 1.9, 9), (3, 0.7, 6), (3, 1.6, 5)])
+@pytest.mark.parametrize("d,alpha,N", [(1, 0.4, 12), (1, 1.9, 300), (2, 0.4, 12), (2, 1.9, 9), (3, 0.7, 6),
+                                       (3, 1.6, 5)])
 def test_element_sum_equals_big_cube(d, alpha, N):
     # sum_e E_e over [0,N-1]^d tiles (0, Nh)^d, whose integral is the origin-element closed
     # form scaled by N^{d-q}; checks the non-origin quadrature against the closed form.
@@ -164,7 +165,7 @@ def test_alpha_to_two_collapses_to_seven_point_3d():
 
 def test_alpha_to_zero_gives_identity():
     # Derived: c_{d,a} 2^d D2 -> 1 and c a_v -> 0 as alpha -> 0+, i.e. A -> I.
-    for d in (2, 3):
+    for d in (1, 2, 3):
         for al, tol in ((1e-2, 0.05), (1e-3, 0.006)):
             a = oracle.coeffs(d, al, 0.1, 6)
             c = oracle.const(d, al)
@@ -172,7 +173,7 @@ def test_alpha_to_zero_gives_identity():
             assert np.abs(c * a.ravel()[1:]).max() < tol
 
 
-@pytest.mark.parametrize("d,N,alpha", [(2, 9, 0.6), (2, 12, 1.7), (3, 6, 1.2)])
+@pytest.mark.parametrize("d,N,alpha", [(1, 7, 0.3), (1, 40, 1.8), (2, 9, 0.6), (2, 12, 1.7), (3, 6, 1.2)])
 def test_dense_matrix_spd_and_dominant(d, N, alpha):
     # Sec. 2/4: A is symmetric multilevel Toeplitz and positive definite.  The origin
     # row sum identity gives strict diagonal dominance with margin 2^d c D2.
@@ -449,7 +450,7 @@ def test_gamma_below_two_rate(alpha, gamma):
     assert rates[-1, 1] > 1.9, rates
 
 
-@pytest.mark.parametrize("d,alpha,gamma", [(2, 0.6, 1.2), (3, 1.1, 1.6)])
+@pytest.mark.parametrize("d,alpha,gamma", [(1, 0.9, 1.4), (2, 0.6, 1.2), (3, 1.1, 1.6)])
 def test_gamma_below_two_invariants(d, alpha, gamma):
     # elements integrate |xi|^{-(d+alpha-gamma)}: their sum is the closed form over (0, L)^d;
     # a_v > 0 off the origin, symmetric under index permutation, and no origin correction:
@@ -461,7 +462,11 @@ def test_gamma_below_two_invariants(d, alpha, gamma):
     assert E.sum() == pytest.approx(d * L ** (d - q) * oracle.J(d, q) / (d - q), rel=1e-12)
     flat = a.ravel()
     assert np.all(flat[1:] > 0)
-    assert np.allclose(a, np.swapaxes(a, 0, 1), rtol=1e-14, atol=0)
+    if d > 1:
+        assert np.allclose(a, np.swapaxes(a, 0, 1), rtol=1e-14, atol=0)
+    if d == 1:
+        # vertex 1: the intervals 0 and 1, no correction
+        assert a[1] == pytest.approx((E[0] + E[1]) / (2.0 * h ** gamma), rel=1e-13)
     if d == 2:
         # vertex (1, 0): the elements (0, 0) and (1, 0) (numpy order (e_y, e_x)), sigma = 1
         assert a[0, 1] == pytest.approx(2.0 * (E[0, 0] + E[0, 1]) / (4.0 * h ** gamma), rel=1e-13)
@@ -534,3 +539,81 @@ def test_box_gaussian_second_order_2d(alpha):
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(rates > 1.8) and np.all(rates < 2.3), rates
     assert max(gap) < 1e-5 * abs(_gauss_exact(2, alpha, 0.0)), gap
+
+
+# ---------------------------------------------------------------------------
+# d = 1: the one-dimensional case of the general-d scheme (Sec. 4, Theorems 3
+# and 4 hold for any d >= 1)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("alpha", [0.3, 1.0, 1.7])
+def test_1d_elements_vs_high_precision(alpha):
+    h, N = 0.05, 700
+    q = 1.0 + alpha - 2.0
+    E = oracle.elements(1, alpha, h, N)
+    for e in (0, 1, 2, 7, 100, 699):
+        with mp.workdps(40):
+            lo, hi = mp.mpf(e) * mp.mpf(h), mp.mpf(e + 1) * mp.mpf(h)
+            pts = [lo, hi] if e else [0] + [hi * mp.mpf(10) ** -k for k in range(12, -1, -1)]
+            ref = mp.quad(lambda x: x ** (-q), pts)
+        assert E[e] == pytest.approx(float(ref), rel=2e-15), e
+
+
+def test_1d_alpha_to_two_collapses_to_three_point():
+    # c a_1 -> 1/h^2, c a_0 -> -2/h^2, c a_m -> 0 for m > 1: the 3-point Laplacian,
+    # with an O(2 - alpha) approach
+    for delta in (1e-3, 1e-4):
+        ca = _lim(1, delta)
+        tol = 40 * delta
+        assert ca[1] == pytest.approx(1.0, abs=tol)
+        assert ca[0] == pytest.approx(-2.0, abs=2 * tol)
+        assert np.abs(ca[2:]).max() < tol
+
+
+@pytest.mark.parametrize("alpha", [0.5, 1.0, 1.5, 1.9])
+def test_1d_gaussian_second_order(alpha):
+    # Thm 4 with d = 1: O(h^2) on exp(-x^2), whose fractional Laplacian is the
+    # Sec. 1 Fourier form in closed form; origin and x = 1 on (-8, 8).  At alpha = 1
+    # the weight is constant and psi is even in xi, so the trapezoid sum gains an
+    # order (observed: 3); the theorem's bound is the lower one
+    errs = []
+    for N in (128, 256, 512):
+        h = 16.0 / N
+        x = -8.0 + h * np.arange(1, N)
+        u = np.exp(-x * x)
+        a = oracle.coeffs(1, alpha, h, N)
+        rows = [N // 2 - 1, N // 2 - 1 + N // 16]
+        y = oracle.apply_rows(1, N, alpha, a, u, rows)
+        errs.append([abs(y[0] - _gauss_exact(1, alpha, 0.0)), abs(y[1] - _gauss_exact(1, alpha, 1.0))])
+    errs = np.array(errs)
+    rates = np.log2(errs[:-1] / errs[1:])
+    assert np.all(rates > 1.85) and np.all(rates < (3.2 if alpha == 1.0 else 2.3)), rates
+
+
+def test_1d_bump_closed_form():
+    # (-Delta)^{a/2} (1 - x^2)_+^{a/2} = 2^a G(1 + a/2) G((1 + a)/2) / G(1/2) on (-1, 1)
+    alpha = 1.2
+    exact = float(2 ** mp.mpf(alpha) * mp.gamma(1 + alpha / 2) * mp.gamma((1 + alpha) / 2) / mp.gamma(0.5))
+    errs = []
+    for N in (64, 256, 1024):
+        h = 2.0 / N
+        x = -1.0 + h * np.arange(1, N)
+        u = np.maximum(0.0, 1.0 - x * x) ** (alpha / 2)
+        a = oracle.coeffs(1, alpha, h, N)
+        rows = np.nonzero(np.abs(x) <= 0.5 + 1e-12)[0]
+        y = oracle.apply_rows(1, N, alpha, a, u, rows)
+        errs.append(np.abs(y - exact).max() / exact)
+    assert errs[0] < 0.05 and errs[1] < errs[0] and errs[2] < errs[1], errs
+
+
+def test_1d_apply_is_the_toeplitz_sum():
+    # the scheme for d = 1: (A u)_i = -c (a_0 u_i + sum_{m >= 1} a_m (u_{i-m} + u_{i+m})), zero outside
+    N, alpha, h = 9, 0.8, 0.1
+    a = oracle.coeffs(1, alpha, h, N)
+    c = oracle.const(1, alpha)
+    u = inputs.uniform(N - 1, seed=4)
+    U = np.zeros(3 * N)
+    U[N + 1:2 * N] = u
+    ref = np.array([-c * (a[0] * U[N + i] + sum(a[m] * (U[N + i - m] + U[N + i + m]) for m in range(1, N)))
+                    for i in range(1, N)])
+    y = oracle.apply(1, N, alpha, a, u)
+    assert np.allclose(y, ref, rtol=1e-14, atol=1e-14 * np.abs(ref).max())
