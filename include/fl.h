@@ -5,13 +5,14 @@
  * Method: Duo & Zhang, "Accurate numerical methods for two and three
  * dimensional integral fractional Laplacian with applications"
  * (arXiv:1804.02718).  The operator (-Delta)^{alpha/2}, 0 < alpha < 2, on the
- * box (a, a + N h)^d, d = 2 or 3, with u = 0 outside the box (the extended
+ * box (a, a + N h)^d, d = 1, 2 or 3, with u = 0 outside the box (the extended
  * homogeneous Dirichlet condition of Sec. 2), is discretised by the paper's
  * weighted-trapezoid scheme with splitting parameter gamma = 2 (the choice of
- * its Sec. 5): the 2D scheme of Sec. 2 and the 3D scheme of Sec. 4.  The
- * stiffness matrix A is symmetric positive definite multilevel Toeplitz
- * (Sec. 2 block form, Sec. 4 three-level form) and is applied by circulant
- * embedding and FFT.
+ * its Sec. 5): the 2D scheme of Sec. 2, the 3D scheme of Sec. 4, and the
+ * one-dimensional case of the general-d scheme that Sec. 4 closes with (its
+ * Theorems 3 and 4 hold for any d >= 1).  The stiffness matrix A is symmetric
+ * positive definite multilevel Toeplitz (Toeplitz in 1D; Sec. 2 block form,
+ * Sec. 4 three-level form) and is applied by circulant embedding and FFT.
  *
  * Conventions shared by every call:
  *   - N >= 2 intervals per axis, n = N - 1 interior nodes per axis,
@@ -97,8 +98,11 @@ typedef struct {
  * implies), the generator -c a_{|m|} of the Toeplitz matrix embedded in a
  * circulant of length P >= 2n - 1 per axis (a power of two, zeros in the gap),
  * and its FFT eigenvalues lambda (FP64 master, FP32 copy).
- *   d: 2 or 3.  alpha: in (0, 2).  h > 0, finite.  N: 2 <= N <= 1025 (d = 2),
- *   2 <= N <= 513 (d = 3) (FFT lengths up to 2048 and 1024).  *out receives a new handle (free with
+ *   d: 1, 2 or 3.  alpha: in (0, 2).  h > 0, finite.  N: 2 <= N <= 1025
+ *   (d = 1, 2), 2 <= N <= 513 (d = 3) (FFT lengths up to 2048 and 1024).
+ *   For d = 1 every element integral is one-dimensional, the correction of
+ *   gamma = 2 moves the origin element's share to vertex 1, and a_0 =
+ *   -sum_{m>=1} W_m / (m h)^2 - 2 L^{-alpha} / alpha.  *out receives a new handle (free with
  *   fl_op_destroy).  Uses the current HIP device; synchronises before
  *   returning.  Errors: FL_E_INVAL, FL_E_UNSUPPORTED, FL_E_NOMEM, FL_E_DEVICE.
  */
@@ -204,9 +208,9 @@ fl_status fl_allen_cahn_step_gen(fl_op op, double *u, double tau, double kappa,
  * matvecs y = A u back to back on `stream`, each kernel launched with HIP
  * events recorded at its start and stop, synchronises, and writes the average
  * kernel time per pass in milliseconds to pass_ms (host, >= 5 floats) and the
- * number of passes (3 for d = 2: X-forward, Y forward*lambda*inverse,
- * X-inverse; 5 for d = 3: X-forward, Y-forward, Z forward*lambda*inverse,
- * Y-inverse, X-inverse) to *npass.  The result in y is that of fl_apply.
+ * number of passes (1 for d = 1: forward*lambda*inverse; 3 for d = 2:
+ * X-forward, Y forward*lambda*inverse, X-inverse; 5 for d = 3: X-forward,
+ * Y-forward, Z forward*lambda*inverse, Y-inverse, X-inverse) to *npass.  The result in y is that of fl_apply.
  */
 fl_status fl_apply_profiled(fl_op op, const void *u, void *y, int prec, int reps, void *stream,
                             float *pass_ms, int *npass);

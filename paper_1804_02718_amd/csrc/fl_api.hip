@@ -96,16 +96,19 @@ static fl_status create(int d, double alpha, double gamma, double h, int N, cons
     op->M = (int64_t)op->nk[0] * op->nk[1] * op->nk[2];
     (void)hipGetDevice(&op->device);
     const long V = N + 1;
-    const long nv = d == 2 ? V * V : V * V * V;
-    const long ql = d == 2 ? (long)op->Q * op->Q : (long)op->Q * op->Q * op->Q;
+    long nv = 1, ql = 1;
+    for (int k = 0; k < d; ++k) {
+        nv *= V;
+        ql *= op->Q;
+    }
     // tiled spectra: ntiles * C <= Q + C - 1 columns per line, sized for the
     // widest tile and 16-byte (FP64) values; lines: the x pass's rows (T1),
     // the z lines times P y frequencies (T2, 3D)
     const long w32 = op->Q + kMaxTile - 1, w64 = op->Q + kMaxTile - 1;
     const size_t colb = sizeof(double2) * w64;
     op->T1_bytes = colb * (size_t)op->nk[1] * op->nk[2];
-    op->T2_bytes = d == 2 ? 0 : colb * (size_t)op->nk[2] * op->P;
-    const long qrest = d == 2 ? (long)op->Q : (long)op->Q * op->Q;
+    op->T2_bytes = d != 3 ? 0 : colb * (size_t)op->nk[2] * op->P;
+    const long qrest = ql / op->Q;
     fl_status st = FL_OK;
     auto fail = [&](fl_status s) {
         destroy(op);
@@ -175,7 +178,7 @@ static fl_status check_args(int d, double alpha, double gamma, double h, fl_op *
         return FL_E_INVAL;
     }
     if (!out) { set_error("out is NULL"); return FL_E_INVAL; }
-    if (d != 2 && d != 3) { set_error("d must be 2 or 3 (got %d)", d); return FL_E_INVAL; }
+    if (d < 1 || d > 3) { set_error("d must be 1, 2 or 3 (got %d)", d); return FL_E_INVAL; }
     if (!(alpha > 0.0 && alpha < 2.0)) { set_error("alpha must lie in (0,2) (got %g)", alpha); return FL_E_INVAL; }
     if (!(h > 0.0) || !std::isfinite(h)) { set_error("h must be positive and finite"); return FL_E_INVAL; }
     return FL_OK;
@@ -183,7 +186,7 @@ static fl_status check_args(int d, double alpha, double gamma, double h, fl_op *
 
 static fl_status check_N(int d, int N) {
     if (N < 2) { set_error("N must be >= 2 (got %d)", N); return FL_E_INVAL; }
-    const int nmax = d == 2 ? 1025 : 513;
+    const int nmax = d == 3 ? 513 : 1025;
     if (N > nmax) { set_error("N=%d exceeds the built range (N <= %d for d=%d)", N, nmax, d); return FL_E_UNSUPPORTED; }
     return FL_OK;
 }
@@ -256,7 +259,7 @@ fl_status fl_apply_profiled(fl_op op, const void *u, void *y, int prec, int reps
     if (prec != FL_FP64 && prec != FL_FP32) { set_error("prec must be FL_FP64 or FL_FP32"); return FL_E_INVAL; }
     const size_t es = prec == FL_FP64 ? sizeof(double) : sizeof(float);
     if (overlap(u, es * op->M, y, es * op->M)) { set_error("u and y overlap"); return FL_E_INVAL; }
-    const int np = op->d == 2 ? 3 : 5;
+    const int np = op->d == 1 ? 1 : op->d == 2 ? 3 : 5;
     hipStream_t s = (hipStream_t)stream;
     constexpr int kChunk = 64;
     std::vector<hipEvent_t> ev(2 * 5 * kChunk);
@@ -363,7 +366,8 @@ fl_status fl_autotune(fl_op op, int prec, int reps, void *stream, int *best, flo
 fl_status fl_get_coeffs(fl_op op, double *a_host) {
     if (!op || !a_host) { set_error("NULL argument"); return FL_E_INVAL; }
     const long V = op->N + 1;
-    const long nv = op->d == 2 ? V * V : V * V * V;
+    long nv = 1;
+    for (int k = 0; k < op->d; ++k) nv *= V;
     FL_HIP_TRY(hipMemcpy(a_host, op->a, sizeof(double) * nv, hipMemcpyDeviceToHost));
     return FL_OK;
 }
@@ -371,7 +375,8 @@ fl_status fl_get_coeffs(fl_op op, double *a_host) {
 fl_status fl_get_symbol(fl_op op, double *lam_host) {
     if (!op || !lam_host) { set_error("NULL argument"); return FL_E_INVAL; }
     const long Q = op->Q;
-    const long ql = op->d == 2 ? Q * Q : Q * Q * Q;
+    long ql = 1;
+    for (int k = 0; k < op->d; ++k) ql *= Q;
     FL_HIP_TRY(hipMemcpy(lam_host, op->lam64, sizeof(double) * ql, hipMemcpyDeviceToHost));
     return FL_OK;
 }

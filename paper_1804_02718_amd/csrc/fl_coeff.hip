@@ -2,14 +2,16 @@
 //
 // With splitting parameter gamma in (alpha, 2] (2 is the paper's default,
 // Sec. 5) and q = d + alpha - gamma, the scheme needs (Sec. 2 for d = 2,
-// Sec. 4 for d = 3):
+// Sec. 4 for d = 3 and for d = 1, the one-dimensional case of its general-d
+// scheme):
 //   * element integrals E_e = int_{I_e} |xi|^{-q}, I_e = prod [e_i h, (e_i+1) h];
 //   * vertex weights W_v = sum of E_e over the elements having xi_v as a vertex
 //     (the patch T_v, restricted to (0, L)^d, vertices 0..N per axis), plus the
 //     origin-element correction of the gamma = 2 limit rule (none for
 //     gamma < 2, where the limit of psi_gamma at the origin is 0): in 2D +E_0
 //     on (1,0), (0,1) and -E_0 on (1,1); in 3D +5/3 E_0 on the axis unit
-//     vectors and -E_0 on every other vertex of the unit cube;
+//     vectors and -E_0 on every other vertex of the unit cube; in 1D +E_0 on
+//     vertex 1 (psi_2 tends to u'' at the origin, taken as psi_2 at xi = h);
 //   * a_v = 2^{sigma(v)} W_v / (2^d |xi_v|^gamma), sigma = number of zero indices;
 //   * a_0 = -sum_{v != 0} W_v / |xi_v|^gamma - 2^d D2, D2 the integral of
 //     |xi|^{-(d+alpha)} over R^d_+ minus (0, L)^d, L = N h.
@@ -118,11 +120,15 @@ __global__ __launch_bounds__(256) void k_closed_forms(int d, double alpha, doubl
     const int off = c_gloff[r];
     const double q = d + alpha - gamma, p2 = d + alpha;
     double a1 = 0.0, a2 = 0.0;
-    const int total = d == 2 ? n : n * n;
+    // d = 1: J = 1 (no angular integral); one thread adds it
+    const int total = d == 1 ? 1 : d == 2 ? n : n * n;
     for (int t = threadIdx.x; t < total; t += blockDim.x) {
         const int i = t % n, j = t / n;
         double s2sum, wt;
-        if (d == 2) {
+        if (d == 1) {
+            s2sum = 0.0;
+            wt = 1.0;
+        } else if (d == 2) {
             const double s = 0.5 * (c_glx[off + i] + 1.0);
             s2sum = s * s;
             wt = 0.5 * c_glw[off + i];
@@ -154,7 +160,7 @@ __global__ __launch_bounds__(256) void k_closed_forms(int d, double alpha, doubl
 template <int D>
 __global__ __launch_bounds__(256) void k_elements(double alpha, double gamma, double h, int N, const double *scal,
                                                   double *E) {
-    const long total = D == 2 ? (long)N * N : (long)N * N * N;
+    const long total = D == 1 ? (long)N : D == 2 ? (long)N * N : (long)N * N * N;
     const double q = D + alpha - gamma;
     const double hq = pow(h, D - q);
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -175,7 +181,13 @@ __global__ __launch_bounds__(256) void k_elements(double alpha, double gamma, do
         const int r = rule_for(m);
         const int n = order_of(r), off = c_gloff[r];
         double acc = 0.0;
-        if (D == 2) {
+        if (D == 1) {
+            for (int i = 0; i < n; ++i) {
+                const double x = e[0] + 0.5 * (c_glx[off + i] + 1.0);
+                acc += c_glw[off + i] * pow(x, -q);
+            }
+            E[idx] = 0.5 * hq * acc;
+        } else if (D == 2) {
             for (int i = 0; i < n; ++i) {
                 const double x = e[0] + 0.5 * (c_glx[off + i] + 1.0);
                 double row = 0.0;
@@ -211,7 +223,7 @@ template <int D>
 __global__ __launch_bounds__(256) void k_vertex(const double *__restrict__ E, int N, double h, double gamma, double *a,
                                                 double *term) {
     const int V = N + 1;
-    const long total = D == 2 ? (long)V * V : (long)V * V * V;
+    const long total = D == 1 ? (long)V : D == 2 ? (long)V * V : (long)V * V * V;
     const double E0 = E[0];
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (long)gridDim.x * blockDim.x) {
@@ -234,7 +246,9 @@ __global__ __launch_bounds__(256) void k_vertex(const double *__restrict__ E, in
             r2 += (double)v[k] * v[k];
         }
         double W = 0.0;
-        if (D == 2) {
+        if (D == 1) {
+            for (int i = lo[0]; i <= hi[0]; ++i) W += E[i];
+        } else if (D == 2) {
             for (int j = lo[1]; j <= hi[1]; ++j)
                 for (int i = lo[0]; i <= hi[0]; ++i) W += E[i + (long)N * j];
         } else {
@@ -244,11 +258,11 @@ __global__ __launch_bounds__(256) void k_vertex(const double *__restrict__ E, in
         }
         if (mx == 1 && gamma == 2.0) {  // floor(gamma/2) = 1 only for gamma = 2
             const bool axis = (D - nz) == 1;
-            W += axis ? (D == 2 ? E0 : (5.0 / 3.0) * E0) : -E0;
+            W += axis ? (D == 3 ? (5.0 / 3.0) * E0 : E0) : -E0;
         }
         const double den = gamma == 2.0 ? r2 * h * h : pow(r2 * h * h, 0.5 * gamma);
         term[idx] = W / den;
-        a[idx] = (double)(1 << nz) * W / ((D == 2 ? 4.0 : 8.0) * den);
+        a[idx] = (double)(1 << nz) * W / ((double)(1 << D) * den);
     }
 }
 
@@ -279,7 +293,7 @@ __global__ __launch_bounds__(256) void k_a0_final(const double *__restrict__ par
         if (threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
         __syncthreads();
     }
-    if (threadIdx.x == 0) a[0] = -s[0] - (d == 2 ? 4.0 : 8.0) * scal[1];
+    if (threadIdx.x == 0) a[0] = -s[0] - (double)(1 << d) * scal[1];
 }
 
 static inline int grid_for(long total, int block = 256, int cap = 65536) {
@@ -291,8 +305,11 @@ static inline int grid_for(long total, int block = 256, int cap = 65536) {
 fl_status build_coeffs(fl_op op, hipStream_t s) {
     FL_TRY(upload_rules());
     const int d = op->d, N = op->N;
-    const long ne = d == 2 ? (long)N * N : (long)N * N * N;
-    const long nv = d == 2 ? (long)(N + 1) * (N + 1) : (long)(N + 1) * (N + 1) * (N + 1);
+    long ne = 1, nv = 1;
+    for (int k = 0; k < d; ++k) {
+        ne *= N;
+        nv *= N + 1;
+    }
     const long chunk = 4096;
     const int np = (int)((nv + chunk - 1) / chunk);
     double *E = nullptr, *term = nullptr, *part = nullptr, *scal = nullptr;
@@ -305,7 +322,10 @@ fl_status build_coeffs(fl_op op, hipStream_t s) {
     scal = part + np;
     const double g = op->gamma;
     hipLaunchKernelGGL(k_closed_forms, dim3(1), dim3(256), 0, s, d, op->alpha, g, op->h, N, scal);
-    if (d == 2) {
+    if (d == 1) {
+        hipLaunchKernelGGL(k_elements<1>, dim3(grid_for(ne)), dim3(256), 0, s, op->alpha, g, op->h, N, scal, E);
+        hipLaunchKernelGGL(k_vertex<1>, dim3(grid_for(nv)), dim3(256), 0, s, E, N, op->h, g, op->a, term);
+    } else if (d == 2) {
         hipLaunchKernelGGL(k_elements<2>, dim3(grid_for(ne)), dim3(256), 0, s, op->alpha, g, op->h, N, scal, E);
         hipLaunchKernelGGL(k_vertex<2>, dim3(grid_for(nv)), dim3(256), 0, s, E, N, op->h, g, op->a, term);
     } else {

@@ -8,6 +8,7 @@
 // keep the first n points per axis.
 //
 // Passes (x fastest; kx the half-spectrum index 0..Q-1, Q = P/2+1):
+//   1D: one fused pass (fwd, x lambda, inv, crop) per pair of vectors
 //   2D: X-fwd (real rows -> half spectra) | Y fused (fwd, x lambda, inv, crop) | X-inv
 //   3D: X-fwd | Y-fwd | Z fused | Y-inv | X-inv
 // Half spectra are stored in tiles of C consecutive kx: element (slab k,
@@ -294,6 +295,110 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xinv(
 }
 
 // ---------------------------------------------------------------------------
+// d = 1: the whole matvec in one pass.  Two real vectors share one complex
+// line z = a + i b; lambda is real and even, so the inverse transform of
+// lambda * FFT(z) is (A a) + i (A b): forward transform, multiply, inverse and
+// crop, all in LDS.  Rows are the vectors of a batch along blockIdx.x (one
+// vector per problem along blockIdx.z for a batch of operators).  Epilogue as
+// in k_xinv: y = a1 w1 + a2 w2 + scale (A u), and the workgroup's (dotw, y).
+// ---------------------------------------------------------------------------
+template <typename T, int P, int E, int LPB, bool EPI>
+__global__ __launch_bounds__(LPB * (P / E)) void k_conv1d(
+    const T *__restrict__ u, T *__restrict__ y, int nrows, int n, const T *__restrict__ lam,
+    const C2<T> *__restrict__ table, Epi<T> ep, const double *__restrict__ done, BatchStrides bz) {
+    const int z = blockIdx.z;
+    if (done && done[z * bz.done] != 0.0) return;
+    u += z * bz.in;
+    y += z * bz.out;
+    lam += z * bz.lam;
+    if (ep.w1) ep.w1 += z * bz.out;
+    if (ep.w2) ep.w2 += z * bz.out;
+    if (ep.dotw) ep.dotw += z * bz.out;
+    using PN = Plan<P, E>;
+    constexpr int TL = P / E, L = PN::L;
+    constexpr int PL = padded_len<P>();
+    __shared__ C2<T> lds[LPB * PL];
+    const int tl = threadIdx.x % TL;
+    const int lp = threadIdx.x / TL;
+    const int bx = blockIdx.x;
+    const int ra = 2 * (bx * LPB + lp), rb = ra + 1;
+    const bool va = ra < nrows, vb = rb < nrows;
+    C2<T> tws[num_tw<PN>()];
+    load_twiddles<T, P, PN>(tws, table, tl);
+    C2<T> v[E];
+    // loads from clamped, always valid addresses; out-of-range values replaced by 0
+    const T *ua = u + (long)(va ? ra : 0) * n, *ub = u + (long)(vb ? rb : 0) * n;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int pos = in_pos<P, PN, 0>(tl, j);
+        const bool in = pos < n;
+        const int pc = in ? pos : 0;
+        const T xa = ua[pc], xb = ub[pc];
+        v[j] = mk<T>((va && in) ? xa : T(0), (vb && in) ? xb : T(0));
+    }
+    const int base = lp * PL;
+    auto lidx = [base](int pos) { return base + padpos(pos); };
+    fwd_stages<T, P, PN, 0>(v, lds, tl, tws, lidx);
+#pragma unroll
+    for (int j = 0; j < E; ++j) v[j] = cscale<T>(v[j], lam[fold<P>(out_pos<P, PN, L - 1>(tl, j))]);
+    adj_stages<T, P, PN, L - 1>(v, lds, tl, tws, lidx);
+    double acc = 0.0;  // epilogue dot (dotw, y) over this thread's outputs
+    if (va) {
+        T *ya = y + (long)ra * n, *yb = y + (long)rb * n;
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int pos = in_pos<P, PN, 0>(tl, j);
+            if (pos < n) {
+                T a = v[j].x, b = v[j].y;
+                if constexpr (EPI) {
+                    const long ia2 = (long)ra * n + pos, ib2 = (long)rb * n + pos;
+                    a = ep.scale * a;
+                    if (ep.w1) a += ep.a1 * ep.w1[ia2];
+                    if (ep.w2) a += ep.a2 * ep.w2[ia2];
+                    if (vb) {
+                        b = ep.scale * b;
+                        if (ep.w1) b += ep.a1 * ep.w1[ib2];
+                        if (ep.w2) b += ep.a2 * ep.w2[ib2];
+                    }
+                    if (ep.dpart) {
+                        acc += (double)a * (double)ep.dotw[ia2];
+                        if (vb) acc += (double)b * (double)ep.dotw[ib2];
+                    }
+                }
+                ya[pos] = a;
+                if (vb) yb[pos] = b;
+            }
+        }
+    }
+    if constexpr (EPI) {
+        if (ep.dpart) {  // block-uniform
+            constexpr int NTH = LPB * TL;
+            if constexpr (NTH >= 64) {  // whole wavefronts: shuffles see only active lanes
+                __shared__ double wsum[NTH / 64];
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+                if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = acc;
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    double t = 0.0;
+                    for (int w = 0; w < NTH / 64; ++w) t += wsum[w];
+                    ep.dpart[z * ep.dpart_stride + bx] = t;
+                }
+            } else {  // a partial wavefront: through LDS, in thread order
+                __shared__ double wsum[NTH];
+                wsum[threadIdx.x] = acc;
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    double t = 0.0;
+                    for (int w = 0; w < NTH; ++w) t += wsum[w];
+                    ep.dpart[z * ep.dpart_stride + bx] = t;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // strided pass: the C lines of tile t for outer index o, line position p at
 // o*outer + t*tile + p*line + c.  MODE 0: forward; 1: inverse; 2: forward,
 // multiply by lambda (tiled: t*lam_tile + fold(o)*lam_outer + fold(p)*C + c),
@@ -464,6 +569,18 @@ static void launch_strided(const C2<T> *in, C2<T> *out, int ncols, int nouter, i
            n_in, n_out, st, tw, lam, done, bz);
 }
 
+template <typename T, int P, int E, int LPB>
+static void launch_conv1d(const T *u, T *y, int nrows, int n, const T *lam, const C2<T> *tw, const Epi<T> &ep,
+                          const double *done, hipStream_t s, const hipEvent_t *ev, int nb, BatchStrides bz) {
+    const int pairs = (nrows + 1) / 2;
+    if (ep.active())
+        launch(k_conv1d<T, P, E, LPB, true>, dim3(cdiv(pairs, LPB), 1, nb), dim3(LPB * (P / E)), s, ev, u, y, nrows,
+               n, lam, tw, ep, done, bz);
+    else
+        launch(k_conv1d<T, P, E, LPB, false>, dim3(cdiv(pairs, LPB), 1, nb), dim3(LPB * (P / E)), s, ev, u, y,
+               nrows, n, lam, tw, ep, done, bz);
+}
+
 // ---------------------------------------------------------------------------
 // the matvec: one variant = (EX points per thread in the row passes, EY in
 // the strided passes, tile width C, line pairs per row block LPB)
@@ -507,7 +624,11 @@ static void matvec_v(const MvCtx<T> &cx, const T *u, T *y, const Epi<T> &ep, con
     const long zt1 = cx.zs_t1 / (long)sizeof(C2<T>), zt2 = cx.zs_t2 / (long)sizeof(C2<T>);
     auto E = [&](int i) { return ev ? ev + 2 * i : nullptr; };
     BatchStrides b_in{cx.zs_vec, zt1, 0, cx.zs_done};
-    if constexpr (D == 2) {
+    if constexpr (D == 1) {
+        (void)T1; (void)T2; (void)nt; (void)ny; (void)nz; (void)Q; (void)zt2; (void)b_in;
+        launch_conv1d<T, P, EX, LPB>(u, y, 1, nx, lam, tw, ep, done, s, E(0), nb,
+                                     BatchStrides{cx.zs_vec, cx.zs_vec, cx.zs_lam, cx.zs_done});
+    } else if constexpr (D == 2) {
         launch_xfwd<T, P, EX, C, LPB, true>(u, T1, ny, nx, nx, ny, nt, tw, done, s, E(0), nb, b_in);
         Strides sy{0, ny * C, 0, ny * C, C, Q * C, 0, nt * Q * C};
         launch_strided<T, P, EY, C, 2, true>(T1, T1, P / 2, 1, ny, ny, sy, tw, lam, done, s, E(1), nb,
@@ -547,6 +668,16 @@ template <typename T> static const Variant<T> *variants(int P, int d, int *count
 
 template <> const Variant<float> *variants<float>(int P, int d, int *count) {
     using T = float;
+    // 1D: one fused pass, one vector pair per workgroup
+    static const Variant<T> v1_8[] = {FL_VAR(T, 8, 1, 8, 8, 1, 1)};
+    static const Variant<T> v1_16[] = {FL_VAR(T, 16, 1, 8, 8, 1, 1)};
+    static const Variant<T> v1_32[] = {FL_VAR(T, 32, 1, 8, 8, 1, 1)};
+    static const Variant<T> v1_64[] = {FL_VAR(T, 64, 1, 8, 8, 1, 1)};
+    static const Variant<T> v1_128[] = {FL_VAR(T, 128, 1, 8, 8, 1, 1)};
+    static const Variant<T> v1_256[] = {FL_VAR(T, 256, 1, 8, 8, 1, 1)};
+    static const Variant<T> v1_512[] = {FL_VAR(T, 512, 1, 8, 8, 1, 1)};
+    static const Variant<T> v1_1024[] = {FL_VAR(T, 1024, 1, 8, 8, 1, 1)};
+    static const Variant<T> v1_2048[] = {FL_VAR(T, 2048, 1, 8, 8, 1, 1)};
     static const Variant<T> v2_8[] = {FL_DEF(T, 8, 2)};
     static const Variant<T> v2_16[] = {FL_DEF(T, 16, 2)};
     static const Variant<T> v2_32[] = {FL_DEF(T, 32, 2)};
@@ -581,7 +712,13 @@ template <> const Variant<float> *variants<float>(int P, int d, int *count) {
         *count = (int)(sizeof(arr) / sizeof(arr[0])); \
         return arr;                                   \
     } while (0)
-    if (d == 2) {
+    if (d == 1) {
+        switch (P) {
+            case 8: FL_PICK(v1_8); case 16: FL_PICK(v1_16); case 32: FL_PICK(v1_32); case 64: FL_PICK(v1_64);
+            case 128: FL_PICK(v1_128); case 256: FL_PICK(v1_256); case 512: FL_PICK(v1_512);
+            case 1024: FL_PICK(v1_1024); case 2048: FL_PICK(v1_2048);
+        }
+    } else if (d == 2) {
         switch (P) {
             case 8: FL_PICK(v2_8); case 16: FL_PICK(v2_16); case 32: FL_PICK(v2_32); case 64: FL_PICK(v2_64);
             case 128: FL_PICK(v2_128); case 256: FL_PICK(v2_256); case 512: FL_PICK(v2_512);
@@ -600,6 +737,16 @@ template <> const Variant<float> *variants<float>(int P, int d, int *count) {
 
 template <> const Variant<double> *variants<double>(int P, int d, int *count) {
     using T = double;
+    // 1D: one fused pass, one vector pair per workgroup
+    static const Variant<T> v1_8[] = {FL_VAR(T, 8, 1, 8, 8, 1, 1)};
+    static const Variant<T> v1_16[] = {FL_VAR(T, 16, 1, 8, 8, 1, 1)};
+    static const Variant<T> v1_32[] = {FL_VAR(T, 32, 1, 8, 8, 1, 1)};
+    static const Variant<T> v1_64[] = {FL_VAR(T, 64, 1, 8, 8, 1, 1)};
+    static const Variant<T> v1_128[] = {FL_VAR(T, 128, 1, 8, 8, 1, 1)};
+    static const Variant<T> v1_256[] = {FL_VAR(T, 256, 1, 8, 8, 1, 1)};
+    static const Variant<T> v1_512[] = {FL_VAR(T, 512, 1, 8, 8, 1, 1)};
+    static const Variant<T> v1_1024[] = {FL_VAR(T, 1024, 1, 8, 8, 1, 1)};
+    static const Variant<T> v1_2048[] = {FL_VAR(T, 2048, 1, 8, 8, 1, 1)};
     static const Variant<T> v2_8[] = {FL_DEF(T, 8, 2)};
     static const Variant<T> v2_16[] = {FL_DEF(T, 16, 2)};
     static const Variant<T> v2_32[] = {FL_DEF(T, 32, 2)};
@@ -623,7 +770,13 @@ template <> const Variant<double> *variants<double>(int P, int d, int *count) {
     static const Variant<T> v3_512[] = {FL_DEF(T, 512, 3), FL_VAR(T, 512, 3, 8, 8, 8, 2),
                                         FL_VAR(T, 512, 3, 8, 8, 4, 2)};
     static const Variant<T> v3_1024[] = {FL_DEF(T, 1024, 3)};
-    if (d == 2) {
+    if (d == 1) {
+        switch (P) {
+            case 8: FL_PICK(v1_8); case 16: FL_PICK(v1_16); case 32: FL_PICK(v1_32); case 64: FL_PICK(v1_64);
+            case 128: FL_PICK(v1_128); case 256: FL_PICK(v1_256); case 512: FL_PICK(v1_512);
+            case 1024: FL_PICK(v1_1024); case 2048: FL_PICK(v1_2048);
+        }
+    } else if (d == 2) {
         switch (P) {
             case 8: FL_PICK(v2_8); case 16: FL_PICK(v2_16); case 32: FL_PICK(v2_32); case 64: FL_PICK(v2_64);
             case 128: FL_PICK(v2_128); case 256: FL_PICK(v2_256); case 512: FL_PICK(v2_512);
@@ -714,13 +867,13 @@ VariantDesc variant_desc(fl_op op, int prec, int k) {
     return k >= 0 && k < n ? v[k].desc : VariantDesc{0, 0, 0, 0};
 }
 
-// tiled lambda for the fused pass: 2D [t][ky][c], 3D [t][ky][kz][c]; zero past
+// tiled lambda for the fused pass: 1D natural order, 2D [t][ky][c], 3D [t][ky][kz][c]; zero past
 // the stored columns.  2D (packed columns): column 0 holds (lambda_0 +
 // lambda_{P/2}) / 2 and Q more entries after the tiles hold
 // (lambda_0 - lambda_{P/2}) / 2, per ky.
 template <typename T>
 __global__ void k_tile_lambda(const double *__restrict__ lam64, T *__restrict__ lt, int d, int Q, int C, int ntiles) {
-    const long tiles = d == 2 ? (long)ntiles * Q * C : (long)ntiles * Q * Q * C;
+    const long tiles = d == 1 ? (long)Q : d == 2 ? (long)ntiles * Q * C : (long)ntiles * Q * Q * C;
     const long total = d == 2 ? tiles + Q : tiles;
     const int N2 = Q - 1;  // P / 2
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -728,7 +881,9 @@ __global__ void k_tile_lambda(const double *__restrict__ lam64, T *__restrict__ 
         const int c = (int)(idx % C);
         long rest = idx / C;
         double v = 0.0;
-        if (d == 2 && idx >= tiles) {
+        if (d == 1) {
+            v = lam64[idx];
+        } else if (d == 2 && idx >= tiles) {
             const long ky = idx - tiles;
             v = 0.5 * (lam64[ky * Q] - lam64[ky * Q + N2]);
         } else if (d == 2) {
@@ -844,10 +999,38 @@ static void symbol_fft(double *cemb, double2 *T, const double2 *tw, hipStream_t 
     }
 }
 
+// 1D symbol: lambda(k) / P = (t_0 + 2 sum_{m=1}^{n-1} t_m cos(2 pi k m / P)) / P for
+// the even generator t_m = -c a_m (zero in the gap), k < Q; a direct cosine sum
+// (n <= 1024 terms per k) with the FP64 twiddle table and a compensated sum
+__global__ __launch_bounds__(256) void k_symbol1d(const double *__restrict__ a, const double2 *__restrict__ tw,
+                                                  double *__restrict__ lam64, int n, int P, double negc) {
+    const int Q = P / 2 + 1;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < Q; k += gridDim.x * blockDim.x) {
+        double s = 0.0, comp = 0.0;
+        for (int m = 1; m <= n - 1; ++m) {
+            const double t = 2.0 * negc * a[m] * tw[(long)k * m % P].x;
+            const double y = s + t;
+            comp += fabs(s) >= fabs(t) ? (s - y) + t : (t - y) + s;
+            s = y;
+        }
+        lam64[k] = (negc * a[0] + (s + comp)) / (double)P;
+    }
+}
+
 template <int P, int D> constexpr int sym_c() { return Shape<double, P, D>::C; }
 
 fl_status build_symbol(fl_op op, hipStream_t s) {
     const int d = op->d, P = op->P, Q = op->Q;
+    if (d == 1) {
+        hipLaunchKernelGGL(k_symbol1d, dim3(cdiv(Q, 256)), dim3(256), 0, s, op->a, op->tw64, op->lam64, op->n, P,
+                           -op->c);
+        fl_status st = select_variant(op, FL_FP32, op->var32, s);
+        if (st == FL_OK) st = select_variant(op, FL_FP64, op->var64, s);
+        FL_TRY(st);
+        FL_HIP_TRY(hipGetLastError());
+        FL_HIP_TRY(hipStreamSynchronize(s));
+        return FL_OK;
+    }
     int C = 0;
 #define FL_SYC(PP)                                           \
     case PP: C = d == 2 ? sym_c<PP, 2>() : sym_c<PP, 3>(); break;

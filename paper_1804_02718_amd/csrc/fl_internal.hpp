@@ -338,12 +338,13 @@ VariantDesc variant_desc(fl_op op, int prec, int k);
 VariantDesc variant_desc_pd(int P, int d, int prec, int k);
 fl_status tile_lambda(fl_op op, int prec, int C, void *lt, hipStream_t s);
 // spectral x-columns kept by the matvec: P/2 in 2D (DC and Nyquist packed in
-// column 0), P/2 + 1 in 3D
+// column 0), P/2 + 1 in 1D and 3D
 inline int spec_cols(int d, int P) { return d == 2 ? P / 2 : P / 2 + 1; }
 // elements of a tiled lambda of tile width C (2D: tiles plus one packed column)
+// entries of lambda laid out for a variant of tile width C (1D: Q in natural order)
 inline long lam_tiled_len(int d, int P, int C) {
     const long Q = P / 2 + 1, nt = (spec_cols(d, P) + C - 1) / C;
-    return d == 2 ? nt * C * Q + Q : nt * C * Q * Q;
+    return d == 1 ? Q : d == 2 ? nt * C * Q + Q : nt * C * Q * Q;
 }
 fl_status select_variant(fl_op op, int prec, int k, hipStream_t s);
 constexpr int kMaxTile = 16;  // largest tile width of any variant

@@ -823,7 +823,7 @@ static fl_status batch_sync_read(BatchClass &c) {
 extern "C" {
 
 fl_status fl_batch_create(int d, int count, const int *N, const double *alpha, const double *h, fl_batch *out) {
-    if (!out || !N || !alpha || !h || count < 1 || (d != 2 && d != 3)) {
+    if (!out || !N || !alpha || !h || count < 1 || d < 1 || d > 3) {
         set_error("bad argument");
         return FL_E_INVAL;
     }

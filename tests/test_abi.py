@@ -31,8 +31,10 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("args,status", [
-    ((1, 1.0, 0.1, 8), fl.FL_E_INVAL),
+    ((0, 1.0, 0.1, 8), fl.FL_E_INVAL),
     ((4, 1.0, 0.1, 8), fl.FL_E_INVAL),
+    ((1, 1.0, 0.1, 1), fl.FL_E_INVAL),
+    ((1, 1.0, 0.1, 1026), fl.FL_E_UNSUPPORTED),
     ((2, 0.0, 0.1, 8), fl.FL_E_INVAL),
     ((2, 2.0, 0.1, 8), fl.FL_E_INVAL),
     ((2, float("nan"), 0.1, 8), fl.FL_E_INVAL),

@@ -43,7 +43,8 @@ def _errs(y, ref, absref):
 # ---------------------------------------------------------------------------
 # coefficients and eigenvalues
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("d,N,alpha", [(2, 2, 1.5), (2, 3, 0.3), (2, 5, 1.9), (2, 17, 1.0), (2, 32, 1.5),
+@pytest.mark.parametrize("d,N,alpha", [(1, 2, 1.5), (1, 3, 0.3), (1, 17, 1.0), (1, 100, 1.9), (1, 1025, 0.7),
+                                       (2, 2, 1.5), (2, 3, 0.3), (2, 5, 1.9), (2, 17, 1.0), (2, 32, 1.5),
                                        (2, 100, 0.7), (2, 257, 1.2), (3, 2, 1.0), (3, 3, 1.7), (3, 6, 0.4),
                                        (3, 9, 1.2), (3, 16, 1.9)])
 def test_coefficients_match_oracle(dev, d, N, alpha):
@@ -58,7 +59,8 @@ def test_coefficients_match_oracle(dev, d, N, alpha):
     op.close()
 
 
-@pytest.mark.parametrize("d,N,alpha", [(2, 5, 1.3), (2, 32, 0.6), (3, 7, 1.5)])
+@pytest.mark.parametrize("d,N,alpha", [(1, 5, 1.3), (1, 300, 0.6), (1, 1025, 1.9), (2, 5, 1.3), (2, 32, 0.6),
+                                       (3, 7, 1.5)])
 def test_symbol_is_fft_of_embedded_generator(dev, d, N, alpha):
     h = 2.0 / N
     op = _fl().Operator(d, alpha, h, N)
@@ -70,7 +72,9 @@ def test_symbol_is_fft_of_embedded_generator(dev, d, N, alpha):
     f = np.where(idx <= n - 1, idx, np.where(idx >= P - (n - 1), P - idx, -1))
     mask = f >= 0
     fi = np.where(mask, f, 0)
-    if d == 2:
+    if d == 1:
+        emb = -c * a[fi] * mask
+    elif d == 2:
         emb = -c * a[np.ix_(fi, fi)] * np.outer(mask, mask)
     else:
         emb = -c * a[np.ix_(fi, fi, fi)] * (mask[:, None, None] & mask[None, :, None] & mask[None, None, :])
@@ -84,7 +88,8 @@ def test_symbol_is_fft_of_embedded_generator(dev, d, N, alpha):
 # ---------------------------------------------------------------------------
 # matvec against the explicit sum
 # ---------------------------------------------------------------------------
-APPLY_CASES = [(2, 2, 1.2), (2, 3, 0.5), (2, 4, 1.9), (2, 5, 1.0), (2, 9, 1.5), (2, 17, 0.2), (2, 32, 1.5),
+APPLY_CASES = [(1, 2, 1.2), (1, 3, 0.5), (1, 9, 1.5), (1, 64, 1.9), (1, 100, 0.8), (1, 513, 1.1), (1, 1025, 0.4),
+               (2, 2, 1.2), (2, 3, 0.5), (2, 4, 1.9), (2, 5, 1.0), (2, 9, 1.5), (2, 17, 0.2), (2, 32, 1.5),
                (2, 33, 1.1), (2, 64, 1.9), (2, 100, 0.8), (3, 2, 1.3), (3, 3, 0.6), (3, 5, 1.9), (3, 8, 1.2),
                (3, 12, 0.4), (3, 17, 1.6)]
 
@@ -402,4 +407,17 @@ def test_box_rejects(dev):
     op.set_preconditioner(net)
     with pytest.raises(fl.FlError):
         op.poisson_solve(torch.ones(36, dtype=torch.float64, device="cuda:0"), solver="fpcg")
+    op.close()
+
+
+
+def test_1d_apply_profiled_single_pass(dev):
+    # d = 1 is one fused pass (forward, lambda, inverse) per vector pair
+    fl = _fl()
+    N = 1024
+    op = fl.Operator(1, 1.3, 2.0 / N, N)
+    u = _t(inputs.uniform(N - 1, seed=3))
+    ms = fl.fl_apply_profiled(op.handle, u, torch.empty_like(u), 5)
+    assert len(ms) == 1 and ms[0] > 0
+    assert len(op.variants("fp32")) == 1 and len(op.variants("fp64")) == 1
     op.close()

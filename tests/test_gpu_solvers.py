@@ -42,8 +42,8 @@ def test_c1_poisson_constant_rhs(fl, solver):
     op.close()
 
 
-@pytest.mark.parametrize("d,N,alpha", [(2, 2, 1.0), (2, 5, 0.3), (2, 12, 1.9), (3, 3, 1.2), (3, 7, 0.8),
-                                       (3, 9, 1.7)])
+@pytest.mark.parametrize("d,N,alpha", [(1, 2, 0.7), (1, 40, 1.3), (1, 257, 1.9), (2, 2, 1.0), (2, 5, 0.3),
+                                       (2, 12, 1.9), (3, 3, 1.2), (3, 7, 0.8), (3, 9, 1.7)])
 @pytest.mark.parametrize("solver", ["cg64", "refine"])
 def test_poisson_small_vs_dense(fl, d, N, alpha, solver):
     h = 2.0 / N
@@ -124,7 +124,7 @@ def test_poisson_warm_start(fl):
     op.close()
 
 
-@pytest.mark.parametrize("d,N", [(2, 8), (3, 6)])
+@pytest.mark.parametrize("d,N", [(1, 50), (2, 8), (3, 6)])
 @pytest.mark.parametrize("theta", [0.5, 1.0])
 @pytest.mark.parametrize("solver", ["auto", "cg64"])
 def test_allen_cahn_steps_vs_oracle(fl, d, N, theta, solver):
@@ -220,6 +220,45 @@ def test_batched_mixed_sizes_match_single_solves_and_oracle(fl):
     torch.cuda.synchronize()
     for i in range(len(Ns)):
         assert torch.equal(us[i], us2[i])
+    b.close()
+
+
+@pytest.mark.parametrize("solver", ["cg64", "refine"])
+def test_1d_poisson_largest_size(fl, solver):
+    # N = 1025 (FFT length 2048), alpha = 1.9: cond(A) near 1e6, so 1e-9 is the tolerance
+    # FP64 CG reaches reliably
+    N, alpha = 1025, 1.9
+    h = 2.0 / N
+    op = fl.Operator(1, alpha, h, N)
+    a = oracle.coeffs(1, alpha, h, N)
+    A = oracle.dense(1, N, alpha, a)
+    f = inputs.gauss_sum(1, N, 4, seed=2)
+    uref = oracle.solve_dense(A, f)
+    u, info = op.poisson_solve(_t(f), tol=1e-9, solver=solver)
+    ug = u.cpu().numpy()
+    assert np.linalg.norm(f - A @ ug) <= 1.05e-9 * np.linalg.norm(f)
+    assert np.abs(ug - uref).max() <= 2e-9 * np.linalg.cond(A) * np.abs(uref).max()
+    op.close()
+
+
+def test_batched_1d_match_single_solves(fl):
+    # a batch of 1D problems of mixed N and alpha: one fused pass per problem per matvec
+    rng = np.random.default_rng(12)
+    Ns = [64, 1024, 64, 300, 1024, 9]
+    alphas = [float(a) for a in rng.uniform(0.2, 1.95, len(Ns))]
+    hs = [2.0 / N for N in Ns]
+    fs_np = [inputs.gauss_sum(1, N, 3, seed=200 + i) for i, N in enumerate(Ns)]
+    fs = [_t(f) for f in fs_np]
+    b = fl.Batch(1, Ns, alphas, hs)
+    assert b.info()["classes"] == 4
+    us, infos = b.solve(fs, tol=1e-10)
+    torch.cuda.synchronize()
+    for i, (N, al) in enumerate(zip(Ns, alphas)):
+        assert infos[i]["status"] == 0 and infos[i]["relres"] <= 1e-10, (i, infos[i])
+        a = oracle.coeffs(1, al, hs[i], N)
+        A = oracle.dense(1, N, al, a)
+        ug = us[i].cpu().numpy()
+        assert np.linalg.norm(fs_np[i] - A @ ug) <= 1.05e-10 * np.linalg.norm(fs_np[i])
     b.close()
 
 
