@@ -421,3 +421,30 @@ def test_1d_apply_profiled_single_pass(dev):
     assert len(ms) == 1 and ms[0] > 0
     assert len(op.variants("fp32")) == 1 and len(op.variants("fp64")) == 1
     op.close()
+
+
+@pytest.mark.parametrize("d,N,alpha", [(2, 1025, 1.3), (3, 300, 1.6), (3, 513, 0.9)])
+def test_apply_largest_sizes_sampled(dev, d, N, alpha):
+    # the largest operators of the built range (2D N = 1025 and 3D N = 513: n = P / 2, the
+    # embedding exactly twice the grid) and a ragged 3D size at FFT length 1024; FP64 and
+    # FP32 against the oracle's explicit sum on a few rows (head, tail and random)
+    fl = _fl()
+    h = 2.0 / N
+    M = (N - 1) ** d
+    op = fl.Operator(d, alpha, h, N)
+    assert op.P == (2048 if d == 2 else 1024)
+    rng = np.random.default_rng(31)
+    rows = np.unique(np.concatenate([np.arange(4), np.arange(M - 4, M), rng.choice(M, 6, replace=False)]))
+    u = inputs.uniform(M, seed=12)
+    a = oracle.coeffs(d, alpha, h, N)
+    ref = oracle.apply_rows(d, N, alpha, a, u, rows)
+    absref = oracle.apply_rows(d, N, alpha, a, u, rows, absmode=True)
+    y = op.apply(_t(u)).cpu().numpy()[rows]
+    e_rel, e_sc = _errs(y, ref, absref)
+    assert e_sc < 1e-14 and e_rel < 1e-12, (e_rel, e_sc)
+    u32 = u.astype(np.float32)
+    ref32 = oracle.apply_rows(d, N, alpha, a, u32.astype(np.float64), rows)
+    y32 = op.apply(_t(u32, torch.float32)).cpu().numpy()[rows].astype(np.float64)
+    e_rel32, e_sc32 = _errs(y32, ref32, absref)
+    assert e_sc32 < 1e-6 and e_rel32 < 1e-5, (e_rel32, e_sc32)
+    op.close()
