@@ -101,14 +101,22 @@ static fl_status create(int d, double alpha, double gamma, double h, int N, cons
         nv *= V;
         ql *= op->Q;
     }
+    const long qrest = ql / op->Q;
     // tiled spectra: ntiles * C <= Q + C - 1 columns per line, sized for the
     // widest tile and 16-byte (FP64) values; lines: the x pass's rows (T1),
-    // the z lines times P y frequencies (T2, 3D)
+    // the z lines times P y frequencies (T2, 3D).  Large operators (FFT length
+    // above the LDS path's) instead hold two P x Qp complex work buffers and
+    // lambda in natural order only.
     const long w32 = op->Q + kMaxTile - 1, w64 = op->Q + kMaxTile - 1;
     const size_t colb = sizeof(double2) * w64;
-    op->T1_bytes = colb * (size_t)op->nk[1] * op->nk[2];
-    op->T2_bytes = d != 3 ? 0 : colb * (size_t)op->nk[2] * op->P;
-    const long qrest = ql / op->Q;
+    const bool large = large_op(op);
+    const long lam64t_len = large ? 0 : qrest * w64, lam32t_len = large ? ql : qrest * w32;
+    if (large) {
+        op->T1_bytes = op->T2_bytes = sizeof(double2) * (size_t)op->P * op->Qp;
+    } else {
+        op->T1_bytes = colb * (size_t)op->nk[1] * op->nk[2];
+        op->T2_bytes = d != 3 ? 0 : colb * (size_t)op->nk[2] * op->P;
+    }
     fl_status st = FL_OK;
     auto fail = [&](fl_status s) {
         destroy(op);
@@ -117,8 +125,8 @@ static fl_status create(int d, double alpha, double gamma, double h, int N, cons
     hipError_t e;
     if ((e = hipMalloc((void **)&op->a, sizeof(double) * nv)) != hipSuccess ||
         (e = hipMalloc((void **)&op->lam64, sizeof(double) * ql)) != hipSuccess ||
-        (e = hipMalloc((void **)&op->lam64t, sizeof(double) * qrest * w64)) != hipSuccess ||
-        (e = hipMalloc((void **)&op->lam32t, sizeof(float) * qrest * w32)) != hipSuccess ||
+        (lam64t_len && (e = hipMalloc((void **)&op->lam64t, sizeof(double) * lam64t_len)) != hipSuccess) ||
+        (e = hipMalloc((void **)&op->lam32t, sizeof(float) * lam32t_len)) != hipSuccess ||
         (e = hipMalloc(&op->T1, op->T1_bytes)) != hipSuccess ||
         (op->T2_bytes && (e = hipMalloc(&op->T2, op->T2_bytes)) != hipSuccess)) {
         set_error("device allocation: %s", hipGetErrorString(e));
@@ -186,7 +194,8 @@ static fl_status check_args(int d, double alpha, double gamma, double h, fl_op *
 
 static fl_status check_N(int d, int N) {
     if (N < 2) { set_error("N must be >= 2 (got %d)", N); return FL_E_INVAL; }
-    const int nmax = d == 3 ? 513 : 1025;
+    // FFT lengths up to 2048 in LDS; 2D up to 16384 by the large-operator passes
+    const int nmax = d == 2 ? 8193 : (d == 3 ? 513 : 1025);
     if (N > nmax) { set_error("N=%d exceeds the built range (N <= %d for d=%d)", N, nmax, d); return FL_E_UNSUPPORTED; }
     return FL_OK;
 }
@@ -259,6 +268,7 @@ fl_status fl_apply_profiled(fl_op op, const void *u, void *y, int prec, int reps
     if (prec != FL_FP64 && prec != FL_FP32) { set_error("prec must be FL_FP64 or FL_FP32"); return FL_E_INVAL; }
     const size_t es = prec == FL_FP64 ? sizeof(double) : sizeof(float);
     if (overlap(u, es * op->M, y, es * op->M)) { set_error("u and y overlap"); return FL_E_INVAL; }
+    if (large_op(op)) { set_error("per-pass timing covers FFT lengths up to %d", kMaxLdsP); return FL_E_UNSUPPORTED; }
     const int np = op->d == 1 ? 1 : op->d == 2 ? 3 : 5;
     hipStream_t s = (hipStream_t)stream;
     constexpr int kChunk = 64;
@@ -322,6 +332,7 @@ fl_status fl_select_variant(fl_op op, int prec, int k) {
 
 fl_status fl_autotune(fl_op op, int prec, int reps, void *stream, int *best, float *ms_out) {
     if (!op || reps < 1 || (prec != FL_FP64 && prec != FL_FP32)) { set_error("bad argument"); return FL_E_INVAL; }
+    if (large_op(op)) { set_error("no kernel variants above FFT length %d", kMaxLdsP); return FL_E_UNSUPPORTED; }
     const int nv = variant_count(op, prec);
     const size_t es = prec == FL_FP64 ? sizeof(double) : sizeof(float);
     hipStream_t s = (hipStream_t)stream;

@@ -819,6 +819,13 @@ template fl_status matvec_ctx<double>(const MvCtx<double> &, int, const double *
 template <typename T>
 fl_status matvec_ex(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
                     hipEvent_t *ev) {
+    if (large_op(op)) {
+        if (done || ep.dpart || ev) {
+            set_error("operators with FFT length above %d support the plain matvec only", kMaxLdsP);
+            return FL_E_UNSUPPORTED;
+        }
+        return large_matvec<T>(op, u, y, ep, s);
+    }
     return matvec_ctx<T>(single_ctx<T>(op), chosen<T>(op), u, y, ep, done, s, ev);
 }
 
@@ -1017,10 +1024,269 @@ __global__ __launch_bounds__(256) void k_symbol1d(const double *__restrict__ a, 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Large 2D operators (FFT length P = 4096 ... 16384): a line no longer fits a
+// workgroup's LDS (16384 FP64 values take 256 KB), so every radix pass of the
+// transforms is a kernel over the whole buffer in HBM (Stockham autosort,
+// out of place, radix 4 with a radix-2 pass when log2 P is odd; the indexing
+// of Govindaraju et al., SC 2008).  The 288 GB of HBM hold the two P x Qp
+// complex work buffers (2.1 GB each in FP64 at P = 16384) with room to spare.
+// Steps of y = A u (u: ny rows of nx values, x fastest):
+//   pack row pairs into complex lines | x forward passes | Hermitian split into
+//   half spectra (ny rows x Q columns, row stride Qp) | y forward passes over
+//   the Q columns | y inverse passes, lambda applied as the first pass loads
+//   (natural order, folded ky) and only ny rows kept | unsplit | x inverse
+//   passes, nx kept | unpack (real part: even row, imaginary: odd row) with
+//   the solver epilogue y = a1 w1 + a2 w2 + scale (A u).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_big_pack(const T *__restrict__ u, C2<T> *__restrict__ lines, int nx, int ny,
+                                                  int P) {
+    const int nl = (ny + 1) / 2;
+    const long total = (long)nl * nx;
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+        const long r = idx / nx;
+        const int p = (int)(idx - r * nx);
+        const T a = u[2 * r * nx + p];
+        const T b = 2 * r + 1 < ny ? u[(2 * r + 1) * nx + p] : T(0);
+        lines[r * P + p] = mk<T>(a, b);
+    }
+}
+
+// one Stockham pass of radix R over nlines transforms of length P: line l,
+// position q at l*lstride + q*pstride.  Positions >= n_in read as 0 (first
+// pass), only positions < n_out are written (last pass), and with LAM the
+// loads are multiplied by lambda[fold(q) * Q + l] (first inverse pass; the
+// forward output is in natural order).  LINE_FAST: consecutive threads take
+// consecutive lines (the column passes, whose lines are adjacent in memory).
+template <typename T, int R, bool INV, bool LINE_FAST, bool LAM>
+__global__ __launch_bounds__(256) void k_big_pass(const C2<T> *__restrict__ in, C2<T> *__restrict__ out, int P, int Ns,
+                                                  int nlines, long lstride, long pstride, int n_in, int n_out,
+                                                  const C2<T> *__restrict__ tw, const T *__restrict__ lam, int Q) {
+    const int PR = P / R;
+    const long total = (long)nlines * PR;
+    for (long g = (long)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (long)gridDim.x * blockDim.x) {
+        long line;
+        int j;
+        if (LINE_FAST) {
+            line = g % nlines;
+            j = (int)(g / nlines);
+        } else {
+            line = g / PR;
+            j = (int)(g - line * PR);
+        }
+        const C2<T> *src = in + line * lstride;
+        C2<T> v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int q = j + r * PR;
+            v[r] = q < n_in ? src[(long)q * pstride] : mk<T>(0, 0);
+            if (LAM) v[r] = cscale<T>(v[r], lam[(long)(q <= P / 2 ? q : P - q) * Q + line]);
+        }
+        // twiddles W^{r m}, W = exp(-+ 2 pi i / (Ns R)): table index r m P / (Ns R) < P
+        const int m = j % Ns, step = P / (Ns * R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            const C2<T> t = tw[r * m * step];
+            v[r] = cmul<T>(v[r], INV ? cconj<T>(t) : t);
+        }
+        if constexpr (R == 2) {
+            const C2<T> a = v[0];
+            v[0] = cadd<T>(a, v[1]);
+            v[1] = csub<T>(a, v[1]);
+        } else {
+            const C2<T> t0 = cadd<T>(v[0], v[2]), t1 = csub<T>(v[0], v[2]);
+            const C2<T> t2 = cadd<T>(v[1], v[3]), t3 = csub<T>(v[1], v[3]);
+            v[0] = cadd<T>(t0, t2);
+            v[2] = csub<T>(t0, t2);
+            // forward: X1 = t1 - i t3, X3 = t1 + i t3; inverse: the signs swap
+            const C2<T> it3 = INV ? cmuli<T, 1>(t3) : cmuli<T, -1>(t3);
+            v[1] = cadd<T>(t1, it3);
+            v[3] = csub<T>(t1, it3);
+        }
+        C2<T> *dst = out + line * lstride;
+        const int base = (j / Ns) * Ns * R + m;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int q = base + r * Ns;
+            if (q < n_out) dst[(long)q * pstride] = v[r];
+        }
+    }
+}
+
+// half spectra of the two real rows in each line: X_a = (Z(k) + conj Z(-k)) / 2
+// to row 2r, X_b = (Z(k) - conj Z(-k)) / (2i) to row 2r + 1, k < Q
+template <typename T>
+__global__ __launch_bounds__(256) void k_big_split(const C2<T> *__restrict__ Z, C2<T> *__restrict__ S, int nrows, int P,
+                                                   int Q, int Qs) {
+    const int nl = (nrows + 1) / 2;
+    const long total = (long)nl * Q;
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+        const long r = idx / Q;
+        const int k = (int)(idx - r * Q);
+        const C2<T> zk = Z[r * P + k];
+        const C2<T> zm = cconj<T>(Z[r * P + ((P - k) & (P - 1))]);
+        S[2 * r * Qs + k] = cscale<T>(cadd<T>(zk, zm), T(0.5));
+        if (2 * r + 1 < nrows) {
+            const C2<T> w = csub<T>(zk, zm);
+            S[(2 * r + 1) * Qs + k] = mk<T>(T(0.5) * w.y, T(-0.5) * w.x);
+        }
+    }
+}
+
+// the inverse of k_big_split: Z(k) = X_a(k) + i X_b(k) on [0, P/2] and
+// Z(P - k) = conj X_a(k) + i conj X_b(k) on (0, P/2)
+template <typename T>
+__global__ __launch_bounds__(256) void k_big_unsplit(const C2<T> *__restrict__ S, C2<T> *__restrict__ Z, int nrows, int P,
+                                                     int Qs) {
+    const int nl = (nrows + 1) / 2, H = P / 2 + 1;
+    const long total = (long)nl * H;
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+        const long r = idx / H;
+        const int k = (int)(idx - r * H);
+        const C2<T> A = S[2 * r * Qs + k];
+        const C2<T> B = 2 * r + 1 < nrows ? S[(2 * r + 1) * Qs + k] : mk<T>(0, 0);
+        Z[r * P + k] = mk<T>(A.x - B.y, A.y + B.x);
+        if (k > 0 && k < P / 2) Z[r * P + P - k] = mk<T>(A.x + B.y, B.x - A.y);
+    }
+}
+
+template <typename T, bool EPI>
+__global__ __launch_bounds__(256) void k_big_unpack(const C2<T> *__restrict__ Z, T *__restrict__ y, int nx, int ny,
+                                                    int P, Epi<T> ep) {
+    const long total = (long)nx * ny;
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+        const long row = idx / nx;
+        const int p = (int)(idx - row * nx);
+        const C2<T> z = Z[(row >> 1) * P + p];
+        T v = (row & 1) ? z.y : z.x;
+        if constexpr (EPI) {
+            v = ep.scale * v;
+            if (ep.w1) v += ep.a1 * ep.w1[idx];
+            if (ep.w2) v += ep.a2 * ep.w2[idx];
+        }
+        y[idx] = v;
+    }
+}
+
+// lambda / P^2 in natural order (ky, kx < Q) from the forward spectrum of the generator
+__global__ __launch_bounds__(256) void k_big_extract(const double2 *__restrict__ F, double *__restrict__ lam64,
+                                                     float *__restrict__ lam32, int P, int Q, int Qs) {
+    const long total = (long)Q * Q;
+    const double inv = 1.0 / ((double)P * (double)P);
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+        const long ky = idx / Q, kx = idx - ky * Q;
+        const double v = F[ky * Qs + kx].x * inv;
+        lam64[idx] = v;
+        lam32[idx] = (float)v;
+    }
+}
+
+static int big_grid(long total) {
+    const long g = (total + 255) / 256;
+    return (int)(g > (1L << 20) ? (1L << 20) : (g < 1 ? 1 : g));
+}
+
+// the passes of one set of transforms (radix 4, then 2 if log2 P is odd),
+// ping-ponging between a and b; returns the buffer that holds the result
+template <typename T, bool INV, bool LINE_FAST>
+static C2<T> *big_fft(C2<T> *a, C2<T> *b, int P, int nlines, long lstride, long pstride, int n_in, int n_out,
+                      const C2<T> *tw, const T *lam, int Q, hipStream_t s) {
+    int Ns = 1;
+    bool first = true;
+    while (Ns < P) {
+        const int R = (P / Ns) % 4 == 0 ? 4 : 2;
+        const bool last = Ns * R == P;
+        const int ni = first ? n_in : P, no = last ? n_out : P;
+        const int g = big_grid((long)nlines * (P / R));
+        const bool withlam = first && lam != nullptr;
+        if (R == 4) {
+            if (withlam)
+                hipLaunchKernelGGL((k_big_pass<T, 4, INV, LINE_FAST, true>), dim3(g), dim3(256), 0, s, a, b, P, Ns, nlines,
+                                   lstride, pstride, ni, no, tw, lam, Q);
+            else
+                hipLaunchKernelGGL((k_big_pass<T, 4, INV, LINE_FAST, false>), dim3(g), dim3(256), 0, s, a, b, P, Ns,
+                                   nlines, lstride, pstride, ni, no, tw, lam, Q);
+        } else {
+            if (withlam)
+                hipLaunchKernelGGL((k_big_pass<T, 2, INV, LINE_FAST, true>), dim3(g), dim3(256), 0, s, a, b, P, Ns, nlines,
+                                   lstride, pstride, ni, no, tw, lam, Q);
+            else
+                hipLaunchKernelGGL((k_big_pass<T, 2, INV, LINE_FAST, false>), dim3(g), dim3(256), 0, s, a, b, P, Ns,
+                                   nlines, lstride, pstride, ni, no, tw, lam, Q);
+        }
+        Ns *= R;
+        first = false;
+        C2<T> *t = a;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+template <typename T> static const T *big_lam(fl_op op);
+template <> const float *big_lam<float>(fl_op op) { return op->lam32t; }
+template <> const double *big_lam<double>(fl_op op) { return op->lam64; }
+
+template <typename T>
+fl_status large_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, hipStream_t s) {
+    const int P = op->P, Q = op->Q, Qs = op->Qp, nx = op->nk[0], ny = op->nk[1];
+    const int nl = (ny + 1) / 2;
+    C2<T> *B0 = (C2<T> *)op->T1, *B1 = (C2<T> *)op->T2;
+    const C2<T> *tw = twid<T>(op);
+    hipLaunchKernelGGL(k_big_pack<T>, dim3(big_grid((long)nl * nx)), dim3(256), 0, s, u, B0, nx, ny, P);
+    // x forward over the nl lines (rows of length P, positions contiguous)
+    C2<T> *X = big_fft<T, false, false>(B0, B1, P, nl, P, 1, nx, P, tw, nullptr, Q, s);
+    C2<T> *S = X == B0 ? B1 : B0;
+    hipLaunchKernelGGL(k_big_split<T>, dim3(big_grid((long)nl * Q)), dim3(256), 0, s, X, S, ny, P, Q, Qs);
+    // y forward over the Q columns (ny rows in, P out), then y inverse with lambda (ny rows out)
+    C2<T> *F = big_fft<T, false, true>(S, X, P, Q, 1, Qs, ny, P, tw, nullptr, Q, s);
+    C2<T> *G = F == B0 ? B1 : B0;
+    C2<T> *I = big_fft<T, true, true>(F, G, P, Q, 1, Qs, P, ny, tw, big_lam<T>(op), Q, s);
+    C2<T> *Z = I == B0 ? B1 : B0;
+    hipLaunchKernelGGL(k_big_unsplit<T>, dim3(big_grid((long)nl * (P / 2 + 1))), dim3(256), 0, s, I, Z, ny, P, Qs);
+    C2<T> *W = I;
+    C2<T> *Rr = big_fft<T, true, false>(Z, W, P, nl, P, 1, P, nx, tw, nullptr, Q, s);
+    if (ep.active())
+        hipLaunchKernelGGL((k_big_unpack<T, true>), dim3(big_grid((long)nx * ny)), dim3(256), 0, s, Rr, y, nx, ny, P, ep);
+    else
+        hipLaunchKernelGGL((k_big_unpack<T, false>), dim3(big_grid((long)nx * ny)), dim3(256), 0, s, Rr, y, nx, ny, P,
+                           ep);
+    FL_HIP_TRY(hipGetLastError());
+    return FL_OK;
+}
+template fl_status large_matvec<float>(fl_op, const float *, float *, const Epi<float> &, hipStream_t);
+template fl_status large_matvec<double>(fl_op, const double *, double *, const Epi<double> &, hipStream_t);
+
+// lambda of a large operator: the generator -c a_{|m|} embedded in P x P
+// (the same embedding as the LDS path), transformed along x (P rows) and y
+// (Q columns) in FP64; the real part / P^2 at ky, kx < Q
+fl_status large_symbol(fl_op op, hipStream_t s) {
+    const int P = op->P, Q = op->Q, Qs = op->Qp;
+    const long total = (long)P * P;
+    double *cemb = nullptr;
+    FL_HIP_TRY(hipMalloc((void **)&cemb, sizeof(double) * total));
+    double2 *B0 = (double2 *)op->T1, *B1 = (double2 *)op->T2;
+    hipLaunchKernelGGL(k_embed, dim3(big_grid(total)), dim3(256), 0, s, op->a, cemb, 2, op->N, P, -op->c);
+    hipLaunchKernelGGL(k_big_pack<double>, dim3(big_grid(total / 2)), dim3(256), 0, s, cemb, B0, P, P, P);
+    double2 *X = big_fft<double, false, false>(B0, B1, P, P / 2, P, 1, P, P, op->tw64, nullptr, Q, s);
+    double2 *S = X == B0 ? B1 : B0;
+    hipLaunchKernelGGL(k_big_split<double>, dim3(big_grid((long)(P / 2) * Q)), dim3(256), 0, s, X, S, P, P, Q, Qs);
+    double2 *F = big_fft<double, false, true>(S, X, P, Q, 1, Qs, P, P, op->tw64, nullptr, Q, s);
+    hipLaunchKernelGGL(k_big_extract, dim3(big_grid((long)Q * Q)), dim3(256), 0, s, F, op->lam64, op->lam32t, P, Q, Qs);
+    hipError_t le = hipGetLastError();
+    hipError_t se = hipStreamSynchronize(s);
+    (void)hipFree(cemb);
+    FL_HIP_TRY(le);
+    FL_HIP_TRY(se);
+    return FL_OK;
+}
+
 template <int P, int D> constexpr int sym_c() { return Shape<double, P, D>::C; }
 
 fl_status build_symbol(fl_op op, hipStream_t s) {
     const int d = op->d, P = op->P, Q = op->Q;
+    if (large_op(op)) return large_symbol(op, s);
     if (d == 1) {
         hipLaunchKernelGGL(k_symbol1d, dim3(cdiv(Q, 256)), dim3(256), 0, s, op->a, op->tw64, op->lam64, op->n, P,
                            -op->c);

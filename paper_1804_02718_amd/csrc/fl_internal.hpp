@@ -348,4 +348,12 @@ inline long lam_tiled_len(int d, int P, int C) {
 }
 fl_status select_variant(fl_op op, int prec, int k, hipStream_t s);
 constexpr int kMaxTile = 16;  // largest tile width of any variant
+// longest FFT whose line a workgroup keeps in LDS; longer 2D embeddings (up to
+// 16384) take the global-memory passes of the large-operator path
+constexpr int kMaxLdsP = 2048;
+inline bool large_op(const fl_op_s *op) { return op->P > kMaxLdsP; }
+// large-operator path: symbol and matvec (fl_apply only; 2D)
+fl_status large_symbol(fl_op op, hipStream_t s);
+template <typename T>
+fl_status large_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, hipStream_t s);
 }  // namespace fl

@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol():
     ((2, 1.0, -1.0, 8), fl.FL_E_INVAL),
     ((2, 1.0, float("inf"), 8), fl.FL_E_INVAL),
     ((2, 1.0, 0.1, 1), fl.FL_E_INVAL),
-    ((2, 1.0, 0.1, 5000), fl.FL_E_UNSUPPORTED),
+    ((2, 1.0, 0.1, 8194), fl.FL_E_UNSUPPORTED),
     ((3, 1.0, 0.1, 1000), fl.FL_E_UNSUPPORTED),
 ])
 def test_coeffs_rejects_invalid_arguments(args, status):

@@ -448,3 +448,57 @@ def test_apply_largest_sizes_sampled(dev, d, N, alpha):
     e_rel32, e_sc32 = _errs(y32, ref32, absref)
     assert e_sc32 < 1e-6 and e_rel32 < 1e-5, (e_rel32, e_sc32)
     op.close()
+
+
+@pytest.mark.parametrize("d,Nk,alpha", [(2, (1100, 1100), 1.3), (2, (2049, 2049), 0.7), (2, (4000, 4000), 1.9),
+                                        (2, (3000, 700), 1.1), (2, (8193, 8193), 1.5)])
+def test_large_operator_sampled(dev, d, Nk, alpha):
+    # 2D operators past the LDS kernels' FFT length (2048): the global-memory passes at
+    # P = 4096, 8192 and 16384 (the largest, N = 8193), a box among them; FP64 and FP32
+    # against the oracle's explicit sum on sampled rows
+    fl = _fl()
+    N = max(Nk)
+    h = 2.0 / N
+    op = fl.Operator(d, alpha, h, None, Nk=Nk)
+    assert op.P > 2048
+    shape = [k - 1 for k in Nk]
+    M = int(np.prod(shape))
+    rows = _sample_rows(M, 8, seed=41)
+    u = inputs.uniform(M, seed=14)
+    a = oracle.coeffs(d, alpha, h, N)
+    a_gpu = op.coeffs()
+    sub = (slice(0, 40), slice(0, 40))
+    assert np.abs(a_gpu[sub] / a[sub] - 1.0).max() < 1e-13
+    assert np.abs(a_gpu[-3:, -3:] / a[-3:, -3:] - 1.0).max() < 1e-13
+    assert a_gpu[0, 0] == pytest.approx(a[0, 0], rel=1e-13)
+    ref = oracle.apply_rows(d, N, alpha, a, u, rows, shape=shape)
+    absref = oracle.apply_rows(d, N, alpha, a, u, rows, absmode=True, shape=shape)
+    y = op.apply(_t(u)).cpu().numpy()[rows]
+    e_rel, e_sc = _errs(y, ref, absref)
+    assert e_sc < 1e-14 and e_rel < 1e-12, (e_rel, e_sc)
+    u32 = u.astype(np.float32)
+    ref32 = oracle.apply_rows(d, N, alpha, a, u32.astype(np.float64), rows, shape=shape)
+    y32 = op.apply(_t(u32, torch.float32)).cpu().numpy()[rows].astype(np.float64)
+    e_rel32, e_sc32 = _errs(y32, ref32, absref)
+    assert e_sc32 < 1e-6 and e_rel32 < 1e-5, (e_rel32, e_sc32)
+    op.close()
+
+
+def test_large_operator_limits(dev):
+    # matvec only: the solvers, per-pass timing and the autotuner refuse FFT lengths above 2048
+    fl = _fl()
+    N = 1100
+    op = fl.Operator(2, 1.0, 2.0 / N, N)
+    f = torch.ones(op.M, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(fl.FlError):
+        op.poisson_solve(f, tol=1e-8)
+    with pytest.raises(fl.FlError):
+        op.allen_cahn_step(f.clone(), 1e-3, 0.05)
+    with pytest.raises(fl.FlError):
+        fl.fl_apply_profiled(op.handle, f, torch.empty_like(f), 2)
+    with pytest.raises(fl.FlError):
+        op.autotune("fp64", reps=1)
+    assert op.variants("fp64") == []
+    with pytest.raises(fl.FlError):
+        fl.Batch(2, [64, 1100], [1.0, 1.0], [2.0 / 64, 2.0 / 1100])
+    op.close()
