@@ -167,6 +167,28 @@ def c3_extra(torch, fl, inputs, autotune, N=256, alpha=1.2):
     return out
 
 
+def large_extra(torch, fl, inputs, N=8192, alpha=1.5, reps=5):
+    """The fine operator of the paper's tables: 2D N = 8192 on (-1, 1)^2 (8191^2 unknowns, FFT length
+    16384, the global-memory passes), one matvec in FP64 and in FP32 on u = ((1-x^2)(1-y^2))^2."""
+    out = {"workload": "2D N=%d (FFT length 16384), alpha=%g, u=((1-x^2)(1-y^2))^2" % (N, alpha)}
+    t0 = time.perf_counter()
+    op = fl.Operator(2, alpha, 2.0 / N, N)
+    torch.cuda.synchronize()
+    out["create_seconds"] = round(time.perf_counter() - t0, 3)
+    u64 = torch.as_tensor(inputs.paper_family(2, N, 2.0), device="cuda:0")
+    for name, u in (("fp64", u64), ("fp32", u64.float())):
+        y = op.apply(u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            op.apply(u, y)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[name] = {"ms": round(dt * 1e3, 3), "gdof_s": round(op.M / dt / 1e9, 3)}
+    op.close()
+    return out
+
+
 def c4_extra(torch, fl, inputs):
     """64 2D Poisson problems, N from {64,128,256,512}, alpha ~ U(0.2,1.95), tol 1e-8:
     one batched solve against the same problems solved one after another."""
@@ -340,6 +362,8 @@ def main():
                          "kernel variant, the fastest one measured for this size)")
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the 3D N=256 workload (matvec in FP32 and FP64, 200 Allen--Cahn steps)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 2D N=8192 operator (FFT length 16384) of the paper's reference grid")
     ap.add_argument("--no-c4", action="store_true",
                     help="skip the batch of 64 mixed-(N, alpha) Poisson solves, batched and one by one")
     ap.add_argument("--no-c5", action="store_true",
@@ -435,6 +459,9 @@ def main():
     if not args.no_extra and not args.no_c3:
         print("bench: 3D N=256 matvec", file=sys.stderr, flush=True)
         extra["c3_matvec"] = c3_extra(torch, fl, inputs, not args.no_autotune)
+    if not args.no_extra and not args.no_large:
+        print("bench: 2D N=8192 operator", file=sys.stderr, flush=True)
+        extra["large_operator"] = large_extra(torch, fl, inputs)
     if not args.no_extra and not args.no_c4:
         print("bench: batched solves", file=sys.stderr, flush=True)
         extra["c4_batch"] = c4_extra(torch, fl, inputs)

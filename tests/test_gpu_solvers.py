@@ -241,6 +241,26 @@ def test_1d_poisson_largest_size(fl, solver):
     op.close()
 
 
+def test_1d_poisson_constant_rhs_closed_form(fl):
+    # d = 1, f = 1 on (-1, 1): the exact solution is u = (1 - x^2)_+^{a/2} / (2^a G(1 + a/2)
+    # G((1 + a)/2) / G(1/2)) (the 1D bump closed form read backwards; the Sec. 5.2 remark
+    # on Example 5.2.3); only Hoelder at x = +-1, so the interior error shrinks slowly
+    import math
+    alpha = 1.2
+    k = 2 ** alpha * math.gamma(1 + alpha / 2) * math.gamma((1 + alpha) / 2) / math.gamma(0.5)
+    errs = []
+    for N in (64, 256, 1024):
+        h = 2.0 / N
+        x = -1.0 + h * np.arange(1, N)
+        op = fl.Operator(1, alpha, h, N)
+        u, info = op.poisson_solve(_t(np.ones(N - 1)), tol=1e-10, solver="cg64")
+        exact = (1.0 - x * x) ** (alpha / 2) / k
+        inner = np.abs(x) <= 0.5 + 1e-12
+        errs.append(np.abs(u.cpu().numpy()[inner] - exact[inner]).max() / exact[inner].max())
+        op.close()
+    assert errs[0] < 0.02 and errs[1] < errs[0] and errs[2] < errs[1], errs
+
+
 def test_batched_1d_match_single_solves(fl):
     # a batch of 1D problems of mixed N and alpha: one fused pass per problem per matvec
     rng = np.random.default_rng(12)
