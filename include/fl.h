@@ -99,7 +99,12 @@ typedef struct {
  * circulant of length P >= 2n - 1 per axis (a power of two, zeros in the gap),
  * and its FFT eigenvalues lambda (FP64 master, FP32 copy).
  *   d: 1, 2 or 3.  alpha: in (0, 2).  h > 0, finite.  N: 2 <= N <= 1025
- *   (d = 1, 2), 2 <= N <= 513 (d = 3) (FFT lengths up to 2048 and 1024).
+ *   (d = 1), 2 <= N <= 8193 (d = 2), 2 <= N <= 513 (d = 3).  FFT lengths up
+ *   to 2048 keep each line in LDS; 2D operators with N > 1025 (FFT length
+ *   4096 to 16384, the paper's h = 2^-12 reference grid) run every radix pass
+ *   over HBM: fl_apply and the single-operator solvers accept them;
+ *   fl_apply_profiled, fl_autotune and fl_batch_create refuse them
+ *   (FL_E_UNSUPPORTED) and they list no kernel variants.
  *   For d = 1 every element integral is one-dimensional, the correction of
  *   gamma = 2 moves the origin element's share to vertex 1, and a_0 =
  *   -sum_{m>=1} W_m / (m h)^2 - 2 L^{-alpha} / alpha.  *out receives a new handle (free with

@@ -820,11 +820,12 @@ template <typename T>
 fl_status matvec_ex(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
                     hipEvent_t *ev) {
     if (large_op(op)) {
-        if (done || ep.dpart || ev) {
-            set_error("operators with FFT length above %d support the plain matvec only", kMaxLdsP);
+        // no fused dot partials (xinv_parts is 0 above the LDS lengths) and no per-pass events
+        if (ep.dpart || ev) {
+            set_error("operators with FFT length above %d take no fused dot or per-pass events", kMaxLdsP);
             return FL_E_UNSUPPORTED;
         }
-        return large_matvec<T>(op, u, y, ep, s);
+        return large_matvec<T>(op, u, y, ep, done, s);
     }
     return matvec_ctx<T>(single_ctx<T>(op), chosen<T>(op), u, y, ep, done, s, ev);
 }
@@ -1041,7 +1042,8 @@ __global__ __launch_bounds__(256) void k_symbol1d(const double *__restrict__ a, 
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_big_pack(const T *__restrict__ u, C2<T> *__restrict__ lines, int nx, int ny,
-                                                  int P) {
+                                                  int P, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
     const int nl = (ny + 1) / 2;
     const long total = (long)nl * nx;
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
@@ -1062,7 +1064,9 @@ __global__ __launch_bounds__(256) void k_big_pack(const T *__restrict__ u, C2<T>
 template <typename T, int R, bool INV, bool LINE_FAST, bool LAM>
 __global__ __launch_bounds__(256) void k_big_pass(const C2<T> *__restrict__ in, C2<T> *__restrict__ out, int P, int Ns,
                                                   int nlines, long lstride, long pstride, int n_in, int n_out,
-                                                  const C2<T> *__restrict__ tw, const T *__restrict__ lam, int Q) {
+                                                  const C2<T> *__restrict__ tw, const T *__restrict__ lam, int Q,
+                                                  const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
     const int PR = P / R;
     const long total = (long)nlines * PR;
     for (long g = (long)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (long)gridDim.x * blockDim.x) {
@@ -1118,7 +1122,8 @@ __global__ __launch_bounds__(256) void k_big_pass(const C2<T> *__restrict__ in, 
 // to row 2r, X_b = (Z(k) - conj Z(-k)) / (2i) to row 2r + 1, k < Q
 template <typename T>
 __global__ __launch_bounds__(256) void k_big_split(const C2<T> *__restrict__ Z, C2<T> *__restrict__ S, int nrows, int P,
-                                                   int Q, int Qs) {
+                                                   int Q, int Qs, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
     const int nl = (nrows + 1) / 2;
     const long total = (long)nl * Q;
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
@@ -1138,7 +1143,8 @@ __global__ __launch_bounds__(256) void k_big_split(const C2<T> *__restrict__ Z, 
 // Z(P - k) = conj X_a(k) + i conj X_b(k) on (0, P/2)
 template <typename T>
 __global__ __launch_bounds__(256) void k_big_unsplit(const C2<T> *__restrict__ S, C2<T> *__restrict__ Z, int nrows, int P,
-                                                     int Qs) {
+                                                     int Qs, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
     const int nl = (nrows + 1) / 2, H = P / 2 + 1;
     const long total = (long)nl * H;
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
@@ -1153,7 +1159,8 @@ __global__ __launch_bounds__(256) void k_big_unsplit(const C2<T> *__restrict__ S
 
 template <typename T, bool EPI>
 __global__ __launch_bounds__(256) void k_big_unpack(const C2<T> *__restrict__ Z, T *__restrict__ y, int nx, int ny,
-                                                    int P, Epi<T> ep) {
+                                                    int P, Epi<T> ep, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
     const long total = (long)nx * ny;
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
         const long row = idx / nx;
@@ -1191,7 +1198,7 @@ static int big_grid(long total) {
 // ping-ponging between a and b; returns the buffer that holds the result
 template <typename T, bool INV, bool LINE_FAST>
 static C2<T> *big_fft(C2<T> *a, C2<T> *b, int P, int nlines, long lstride, long pstride, int n_in, int n_out,
-                      const C2<T> *tw, const T *lam, int Q, hipStream_t s) {
+                      const C2<T> *tw, const T *lam, int Q, const double *done, hipStream_t s) {
     int Ns = 1;
     bool first = true;
     while (Ns < P) {
@@ -1203,17 +1210,17 @@ static C2<T> *big_fft(C2<T> *a, C2<T> *b, int P, int nlines, long lstride, long 
         if (R == 4) {
             if (withlam)
                 hipLaunchKernelGGL((k_big_pass<T, 4, INV, LINE_FAST, true>), dim3(g), dim3(256), 0, s, a, b, P, Ns, nlines,
-                                   lstride, pstride, ni, no, tw, lam, Q);
+                                   lstride, pstride, ni, no, tw, lam, Q, done);
             else
                 hipLaunchKernelGGL((k_big_pass<T, 4, INV, LINE_FAST, false>), dim3(g), dim3(256), 0, s, a, b, P, Ns,
-                                   nlines, lstride, pstride, ni, no, tw, lam, Q);
+                                   nlines, lstride, pstride, ni, no, tw, lam, Q, done);
         } else {
             if (withlam)
                 hipLaunchKernelGGL((k_big_pass<T, 2, INV, LINE_FAST, true>), dim3(g), dim3(256), 0, s, a, b, P, Ns, nlines,
-                                   lstride, pstride, ni, no, tw, lam, Q);
+                                   lstride, pstride, ni, no, tw, lam, Q, done);
             else
                 hipLaunchKernelGGL((k_big_pass<T, 2, INV, LINE_FAST, false>), dim3(g), dim3(256), 0, s, a, b, P, Ns,
-                                   nlines, lstride, pstride, ni, no, tw, lam, Q);
+                                   nlines, lstride, pstride, ni, no, tw, lam, Q, done);
         }
         Ns *= R;
         first = false;
@@ -1229,34 +1236,38 @@ template <> const float *big_lam<float>(fl_op op) { return op->lam32t; }
 template <> const double *big_lam<double>(fl_op op) { return op->lam64; }
 
 template <typename T>
-fl_status large_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, hipStream_t s) {
+fl_status large_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s) {
     const int P = op->P, Q = op->Q, Qs = op->Qp, nx = op->nk[0], ny = op->nk[1];
     const int nl = (ny + 1) / 2;
     C2<T> *B0 = (C2<T> *)op->T1, *B1 = (C2<T> *)op->T2;
     const C2<T> *tw = twid<T>(op);
-    hipLaunchKernelGGL(k_big_pack<T>, dim3(big_grid((long)nl * nx)), dim3(256), 0, s, u, B0, nx, ny, P);
+    hipLaunchKernelGGL(k_big_pack<T>, dim3(big_grid((long)nl * nx)), dim3(256), 0, s, u, B0, nx, ny, P, done);
     // x forward over the nl lines (rows of length P, positions contiguous)
-    C2<T> *X = big_fft<T, false, false>(B0, B1, P, nl, P, 1, nx, P, tw, nullptr, Q, s);
+    C2<T> *X = big_fft<T, false, false>(B0, B1, P, nl, P, 1, nx, P, tw, nullptr, Q, done, s);
     C2<T> *S = X == B0 ? B1 : B0;
-    hipLaunchKernelGGL(k_big_split<T>, dim3(big_grid((long)nl * Q)), dim3(256), 0, s, X, S, ny, P, Q, Qs);
+    hipLaunchKernelGGL(k_big_split<T>, dim3(big_grid((long)nl * Q)), dim3(256), 0, s, X, S, ny, P, Q, Qs, done);
     // y forward over the Q columns (ny rows in, P out), then y inverse with lambda (ny rows out)
-    C2<T> *F = big_fft<T, false, true>(S, X, P, Q, 1, Qs, ny, P, tw, nullptr, Q, s);
+    C2<T> *F = big_fft<T, false, true>(S, X, P, Q, 1, Qs, ny, P, tw, nullptr, Q, done, s);
     C2<T> *G = F == B0 ? B1 : B0;
-    C2<T> *I = big_fft<T, true, true>(F, G, P, Q, 1, Qs, P, ny, tw, big_lam<T>(op), Q, s);
+    C2<T> *I = big_fft<T, true, true>(F, G, P, Q, 1, Qs, P, ny, tw, big_lam<T>(op), Q, done, s);
     C2<T> *Z = I == B0 ? B1 : B0;
-    hipLaunchKernelGGL(k_big_unsplit<T>, dim3(big_grid((long)nl * (P / 2 + 1))), dim3(256), 0, s, I, Z, ny, P, Qs);
+    hipLaunchKernelGGL(k_big_unsplit<T>, dim3(big_grid((long)nl * (P / 2 + 1))), dim3(256), 0, s, I, Z, ny, P, Qs,
+                       done);
     C2<T> *W = I;
-    C2<T> *Rr = big_fft<T, true, false>(Z, W, P, nl, P, 1, P, nx, tw, nullptr, Q, s);
+    C2<T> *Rr = big_fft<T, true, false>(Z, W, P, nl, P, 1, P, nx, tw, nullptr, Q, done, s);
     if (ep.active())
-        hipLaunchKernelGGL((k_big_unpack<T, true>), dim3(big_grid((long)nx * ny)), dim3(256), 0, s, Rr, y, nx, ny, P, ep);
+        hipLaunchKernelGGL((k_big_unpack<T, true>), dim3(big_grid((long)nx * ny)), dim3(256), 0, s, Rr, y, nx, ny, P, ep,
+                           done);
     else
         hipLaunchKernelGGL((k_big_unpack<T, false>), dim3(big_grid((long)nx * ny)), dim3(256), 0, s, Rr, y, nx, ny, P,
-                           ep);
+                           ep, done);
     FL_HIP_TRY(hipGetLastError());
     return FL_OK;
 }
-template fl_status large_matvec<float>(fl_op, const float *, float *, const Epi<float> &, hipStream_t);
-template fl_status large_matvec<double>(fl_op, const double *, double *, const Epi<double> &, hipStream_t);
+template fl_status large_matvec<float>(fl_op, const float *, float *, const Epi<float> &, const double *,
+                                       hipStream_t);
+template fl_status large_matvec<double>(fl_op, const double *, double *, const Epi<double> &, const double *,
+                                        hipStream_t);
 
 // lambda of a large operator: the generator -c a_{|m|} embedded in P x P
 // (the same embedding as the LDS path), transformed along x (P rows) and y
@@ -1268,11 +1279,13 @@ fl_status large_symbol(fl_op op, hipStream_t s) {
     FL_HIP_TRY(hipMalloc((void **)&cemb, sizeof(double) * total));
     double2 *B0 = (double2 *)op->T1, *B1 = (double2 *)op->T2;
     hipLaunchKernelGGL(k_embed, dim3(big_grid(total)), dim3(256), 0, s, op->a, cemb, 2, op->N, P, -op->c);
-    hipLaunchKernelGGL(k_big_pack<double>, dim3(big_grid(total / 2)), dim3(256), 0, s, cemb, B0, P, P, P);
-    double2 *X = big_fft<double, false, false>(B0, B1, P, P / 2, P, 1, P, P, op->tw64, nullptr, Q, s);
+    hipLaunchKernelGGL(k_big_pack<double>, dim3(big_grid(total / 2)), dim3(256), 0, s, cemb, B0, P, P, P,
+                       (const double *)nullptr);
+    double2 *X = big_fft<double, false, false>(B0, B1, P, P / 2, P, 1, P, P, op->tw64, nullptr, Q, nullptr, s);
     double2 *S = X == B0 ? B1 : B0;
-    hipLaunchKernelGGL(k_big_split<double>, dim3(big_grid((long)(P / 2) * Q)), dim3(256), 0, s, X, S, P, P, Q, Qs);
-    double2 *F = big_fft<double, false, true>(S, X, P, Q, 1, Qs, P, P, op->tw64, nullptr, Q, s);
+    hipLaunchKernelGGL(k_big_split<double>, dim3(big_grid((long)(P / 2) * Q)), dim3(256), 0, s, X, S, P, P, Q, Qs,
+                       (const double *)nullptr);
+    double2 *F = big_fft<double, false, true>(S, X, P, Q, 1, Qs, P, P, op->tw64, nullptr, Q, nullptr, s);
     hipLaunchKernelGGL(k_big_extract, dim3(big_grid((long)Q * Q)), dim3(256), 0, s, F, op->lam64, op->lam32t, P, Q, Qs);
     hipError_t le = hipGetLastError();
     hipError_t se = hipStreamSynchronize(s);

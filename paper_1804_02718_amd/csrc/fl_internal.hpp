@@ -352,8 +352,9 @@ constexpr int kMaxTile = 16;  // largest tile width of any variant
 // 16384) take the global-memory passes of the large-operator path
 constexpr int kMaxLdsP = 2048;
 inline bool large_op(const fl_op_s *op) { return op->P > kMaxLdsP; }
-// large-operator path: symbol and matvec (fl_apply only; 2D)
+// large-operator path (2D): symbol and matvec with the solver epilogue and done
+// flag (no fused dot partials)
 fl_status large_symbol(fl_op op, hipStream_t s);
 template <typename T>
-fl_status large_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, hipStream_t s);
+fl_status large_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s);
 }  // namespace fl

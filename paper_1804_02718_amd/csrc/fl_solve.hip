@@ -575,10 +575,6 @@ fl_status fl_poisson_solve_ex(fl_op op, const double *f, double tol, double *u, 
     if (!op || !f || !u) { set_error("NULL argument"); return FL_E_INVAL; }
     if (!(tol > 0.0) || !std::isfinite(tol)) { set_error("tol must be positive"); return FL_E_INVAL; }
     if (f == u) { set_error("f and u must differ"); return FL_E_INVAL; }
-    if (large_op(op)) {
-        set_error("the solvers need FFT length <= %d (2D N <= 1025); larger operators support fl_apply", kMaxLdsP);
-        return FL_E_UNSUPPORTED;
-    }
     fl_solve_opts o = {FL_SOLVE_AUTO, 0, 0, 0, 0.0};
     if (opts) o = *opts;
     if (o.solver < FL_SOLVE_AUTO || o.solver > FL_SOLVE_FPCG) { set_error("unknown solver"); return FL_E_INVAL; }
@@ -619,10 +615,6 @@ fl_status fl_poisson_solve(fl_op op, const double *f, double tol, double *u, fl_
 fl_status fl_allen_cahn_step_gen(fl_op op, double *u, double tau, double kappa, double gamma, double shift,
                                  double theta, double tol, int solver, fl_info *info, void *stream) {
     if (!op || !u) { set_error("NULL argument"); return FL_E_INVAL; }
-    if (large_op(op)) {
-        set_error("the solvers need FFT length <= %d (2D N <= 1025); larger operators support fl_apply", kMaxLdsP);
-        return FL_E_UNSUPPORTED;
-    }
     if (!(tau > 0.0) || !std::isfinite(tau)) { set_error("tau must be positive"); return FL_E_INVAL; }
     if (!(kappa >= 0.0) || !std::isfinite(kappa)) { set_error("kappa must be >= 0"); return FL_E_INVAL; }
     if (!std::isfinite(gamma) || !std::isfinite(shift)) { set_error("gamma and shift must be finite"); return FL_E_INVAL; }

@@ -485,15 +485,11 @@ def test_large_operator_sampled(dev, d, Nk, alpha):
 
 
 def test_large_operator_limits(dev):
-    # matvec only: the solvers, per-pass timing and the autotuner refuse FFT lengths above 2048
+    # per-pass timing, the autotuner and batches refuse FFT lengths above 2048
     fl = _fl()
     N = 1100
     op = fl.Operator(2, 1.0, 2.0 / N, N)
     f = torch.ones(op.M, dtype=torch.float64, device="cuda:0")
-    with pytest.raises(fl.FlError):
-        op.poisson_solve(f, tol=1e-8)
-    with pytest.raises(fl.FlError):
-        op.allen_cahn_step(f.clone(), 1e-3, 0.05)
     with pytest.raises(fl.FlError):
         fl.fl_apply_profiled(op.handle, f, torch.empty_like(f), 2)
     with pytest.raises(fl.FlError):
@@ -501,4 +497,50 @@ def test_large_operator_limits(dev):
     assert op.variants("fp64") == []
     with pytest.raises(fl.FlError):
         fl.Batch(2, [64, 1100], [1.0, 1.0], [2.0 / 64, 2.0 / 1100])
+    op.close()
+
+
+@pytest.mark.parametrize("solver", ["cg64", "refine"])
+def test_large_operator_poisson_sampled_residual(dev, solver):
+    # Poisson on a large operator (FFT length 4096): the library's FP64 residual meets the
+    # tolerance, and the oracle's explicit sum of A u at sampled rows reproduces f there
+    fl = _fl()
+    N, alpha = 1100, 1.3
+    h = 2.0 / N
+    M = (N - 1) ** 2
+    op = fl.Operator(2, alpha, h, N)
+    f = inputs.gauss_sum(2, N, 4, seed=6)
+    u, info = op.poisson_solve(_t(f), tol=1e-10, solver=solver)
+    assert info["relres"] <= 1e-10
+    rows = _sample_rows(M, 16, seed=3)
+    a = oracle.coeffs(2, alpha, h, N)
+    ug = u.cpu().numpy()
+    Au = oracle.apply_rows(2, N, alpha, a, ug, rows)
+    absAu = oracle.apply_rows(2, N, alpha, a, ug, rows, absmode=True)
+    assert np.abs(Au - f[rows]).max() <= 1e-9 * np.abs(absAu).max() + 1e-9 * np.abs(f).max()
+    op.close()
+
+
+def test_large_operator_allen_cahn_step_sampled(dev):
+    # one semi-implicit step on a large operator: at sampled rows the oracle's sums of A u and
+    # A u+ satisfy (I + theta s A) u+ = u - (1 - theta) s A u + tau (u - u^3)
+    fl = _fl()
+    N, alpha, tau, eps, theta = 1100, 1.2, 1e-3, 0.05, 0.5
+    h = 2.0 / N
+    M = (N - 1) ** 2
+    op = fl.Operator(2, alpha, h, N)
+    u0 = inputs.ac_initial(M, seed=3)
+    u = _t(u0)
+    info = op.allen_cahn_step(u, tau, eps, theta=theta, tol=1e-11, solver="cg64")
+    assert info["relres"] <= 1e-11
+    rows = _sample_rows(M, 16, seed=5)
+    a = oracle.coeffs(2, alpha, h, N)
+    u1 = u.cpu().numpy()
+    s = tau * eps * eps
+    Au0 = oracle.apply_rows(2, N, alpha, a, u0, rows)
+    Au1 = oracle.apply_rows(2, N, alpha, a, u1, rows)
+    lhs = u1[rows] + theta * s * Au1
+    rhs = u0[rows] - (1 - theta) * s * Au0 + tau * (u0[rows] - u0[rows] ** 3)
+    scale = np.abs(oracle.apply_rows(2, N, alpha, a, u1, rows, absmode=True)).max() * s + 1.0
+    assert np.abs(lhs - rhs).max() <= 1e-9 * scale
     op.close()
