@@ -243,7 +243,9 @@ fl_status fl_autotune(fl_op op, int prec, int reps, void *stream, int *best, flo
 /*
  * Batched fractional Poisson solves: `count` problems of the same dimension d
  * with their own N[i], alpha[i], h[i] (host arrays).
- *   fl_batch_create         -- builds every operator (as fl_coeffs) and groups
+ *   fl_batch_create         -- builds every operator (as fl_coeffs; FFT length
+ *                              <= 2048, i.e. 2D N <= 1025, else
+ *                              FL_E_UNSUPPORTED) and groups
  *                              the problems into size classes of equal N; each
  *                              class runs all of its problems in every kernel
  *                              launch, and its inner CG iterations are replayed
