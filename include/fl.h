@@ -310,7 +310,11 @@ fl_status fl_batch_destroy(fl_batch b);
  *                          (y - t, A (y - t)) / (t, x0) on the interior, the
  *                          relative A-norm error of the preconditioned
  *                          residual (A t = x0 for an exact pair); one FP32
- *                          matvec per sample and step.
+ *                          matvec per sample and step.  t NULL with ops:
+ *                          the target-free residual loss
+ *                          ||A y - x0||^2 / ||x0||^2 on the interior (A M
+ *                          close to the identity on the inputs shown); two
+ *                          FP32 matvecs per sample and step.
  *   fl_unet_get_weights / fl_unet_set_weights -- FP32 weights, layer by layer,
  *                          each [cout][(ky*ks + kx)*cin + ci] (host).
  *   fl_unet_apply       -- z = rms(r) Net(r/rms(r), alpha) for a residual r on

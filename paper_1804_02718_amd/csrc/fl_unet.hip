@@ -475,6 +475,45 @@ __global__ void k_energy_grad(const float *__restrict__ Ad, const float *__restr
     }
 }
 
+// residual loss ||A y - x0||^2 / ||x0||^2 on the n x n interior (x0 = channel 0
+// of the input, the scaled residual): the preconditioner's own criterion, A M
+// close to the identity on the residuals it is shown.  step 1: y compacted.
+__global__ void k_res_compact(const float *__restrict__ Y, int ys, int n, int W, float *__restrict__ yc) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)n * n; i += (long)gridDim.x * blockDim.x) {
+        const long p = (i / n) * W + i % n;
+        yc[i] = Y[p * ys];
+    }
+}
+// step 2 (one block, after q = A y): q <- e = q - x0 in place; loss = (e, e) / (x0, x0)
+__global__ __launch_bounds__(256) void k_res_loss(float *__restrict__ q, const float *__restrict__ X, int n, int W,
+                                                  float *__restrict__ loss, float *__restrict__ den) {
+    __shared__ double s1[256], s2[256];
+    double a = 0.0, b = 0.0;
+    for (long i = threadIdx.x; i < (long)n * n; i += 256) {
+        const long p = (i / n) * W + i % n;
+        const float x0 = X[2 * p];
+        const float e = q[i] - x0;
+        q[i] = e;
+        a += (double)e * (double)e;
+        b += (double)x0 * (double)x0;
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = b;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) {
+            s1[threadIdx.x] += s1[threadIdx.x + k];
+            s2[threadIdx.x] += s2[threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        loss[0] = (float)(s1[0] / s2[0]);
+        den[0] = (float)s2[0];
+    }
+}
+// step 3 is A e by a matvec; step 4 is k_energy_grad on A e: dY = 2 A e / (den nb)
+
 // minibatch gather: dst[j] = src[idx[j]] for blocks of `len` floats
 __global__ void k_gather(const float *__restrict__ src, const long *__restrict__ idx, int nb, long len,
                          float *__restrict__ dst) {
@@ -867,8 +906,10 @@ static void refresh_bf16(fl_unet u, float lr) {
 
 // forward on A[T_X0] (nb samples); with targets in A[T_TGT]: loss, backward and,
 // for lr > 0, one Adam step.  ops (per sample, may be NULL) selects the
-// energy-norm loss ||y - t||_A^2 / ||t||_A^2 instead of the relative L2 loss.
-static fl_status train_step(fl_unet u, int nb, bool with_target, float lr, const fl_op *ops = nullptr) {
+// energy-norm loss ||y - t||_A^2 / ||t||_A^2 instead of the relative L2 loss,
+// or with `residual` the target-free loss ||A y - x0||^2 / ||x0||^2.
+static fl_status train_step(fl_unet u, int nb, bool with_target, float lr, const fl_op *ops = nullptr,
+                            bool residual = false) {
     const long pix = (long)u->H * u->W;
     hipStream_t s = u->s;
     if (!with_target) {  // inference: fused convolutions
@@ -876,7 +917,20 @@ static fl_status train_step(fl_unet u, int nb, bool with_target, float lr, const
         return FL_OK;
     }
     net_forward(u, nb);
-    if (ops) {
+    if (ops && residual) {
+        float *b0 = u->ebuf, *b1 = u->ebuf + pix;
+        for (int z = 0; z < nb; ++z) {
+            const int n = ops[z]->n;
+            const float *Yz = u->A[T_Y] + z * pix * 16, *Xz = u->A[T_X0] + z * pix * 2;
+            hipLaunchKernelGGL(k_res_compact, dim3(grid1((long)n * n)), dim3(256), 0, s, Yz, 16, n, u->W, b0);
+            FL_TRY(matvec<float>(ops[z], b0, b1, s));
+            hipLaunchKernelGGL(k_res_loss, dim3(1), dim3(256), 0, s, b1, Xz, n, u->W, u->lossbuf + z,
+                               u->ltot + 2 * z + 1);
+            FL_TRY(matvec<float>(ops[z], b1, b0, s));
+            hipLaunchKernelGGL(k_energy_grad, dim3(grid1(pix * 16)), dim3(256), 0, s, b0, u->ltot + 2 * z + 1, n,
+                               u->H, u->W, nb, u->G[T_Y] + z * pix * 16, 16);
+        }
+    } else if (ops) {
         float *d = u->ebuf, *Ad = u->ebuf + pix;
         for (int z = 0; z < nb; ++z) {
             const int n = ops[z]->n;
@@ -1116,7 +1170,8 @@ fl_status fl_unet_pack(fl_unet u, int count, const double *const *r, const doubl
 
 fl_status fl_unet_train(fl_unet u, long count, const float *x, const float *t, const fl_op *ops, int epochs,
                         int batch, float lr, float lr_final, unsigned long long seed, float *epoch_loss) {
-    if (!u || !x || !t || count < 1 || epochs < 1 || batch < 1 || batch > u->nb || !(lr > 0.f) || lr_final < 0.f) {
+    if (!u || !x || (!t && !ops) || count < 1 || epochs < 1 || batch < 1 || batch > u->nb || !(lr > 0.f) ||
+        lr_final < 0.f) {
         set_error("fl_unet_train: bad argument");
         return FL_E_INVAL;
     }
@@ -1147,11 +1202,12 @@ fl_status fl_unet_train(fl_unet u, long count, const float *x, const float *t, c
                                       u->s));
             hipLaunchKernelGGL(k_gather, dim3(grid1(batch * pix * 2)), dim3(256), 0, u->s, x, u->idx, batch, pix * 2,
                                u->A[T_X0]);
-            hipLaunchKernelGGL(k_gather, dim3(grid1(batch * pix)), dim3(256), 0, u->s, t, u->idx, batch, pix,
-                               u->A[T_TGT]);
+            if (t)
+                hipLaunchKernelGGL(k_gather, dim3(grid1(batch * pix)), dim3(256), 0, u->s, t, u->idx, batch, pix,
+                                   u->A[T_TGT]);
             if (ops)
                 for (int z = 0; z < batch; ++z) bops[z] = ops[order[b * batch + z]];
-            FL_TRY(train_step(u, batch, true, lr_k, ops ? bops.data() : nullptr));
+            FL_TRY(train_step(u, batch, true, lr_k, ops ? bops.data() : nullptr, t == nullptr));
             FL_HIP_TRY(hipMemcpyAsync(lossh.data(), u->lossbuf, sizeof(float) * batch, hipMemcpyDeviceToHost, u->s));
             FL_HIP_TRY(hipStreamSynchronize(u->s));
             for (int z = 0; z < batch; ++z) acc += lossh[z];

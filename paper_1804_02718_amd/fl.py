@@ -381,7 +381,8 @@ def fl_unet_pack(u, rs, sols, alphas, n, x, t=None):
 
 def fl_unet_train(u, x, t, epochs, batch, lr, lr_final=0.0, seed=0, ops=None):
     """Train on device samples x [count, H, H, 2], t [count, H, H]; returns the mean loss per epoch.
-    ops: None (relative L2 loss) or one operator handle per sample (energy-norm loss)."""
+    ops: None (relative L2 loss) or one operator handle per sample (energy-norm loss; with t None
+    the target-free residual loss ||A y - x0||^2 / ||x0||^2)."""
     losses = np.zeros(int(epochs), np.float32)
     count = int(x.shape[0])
     opa = None
@@ -389,7 +390,10 @@ def fl_unet_train(u, x, t, epochs, batch, lr, lr_final=0.0, seed=0, ops=None):
         if len(ops) != count:
             raise ValueError("one operator per sample")
         opa = (ctypes.c_void_p * count)(*[o.value if isinstance(o, ctypes.c_void_p) else o for o in ops])
-    _check(load().fl_unet_train(u, count, _ptr(x), _ptr(t), opa, int(epochs), int(batch), float(lr),
+    if t is None and ops is None:
+        raise ValueError("targets or operators are needed")
+    _check(load().fl_unet_train(u, count, _ptr(x), _ptr(t) if t is not None else None, opa, int(epochs),
+                                int(batch), float(lr),
                                 float(lr_final), int(seed), _fptr(losses)))
     return losses
 

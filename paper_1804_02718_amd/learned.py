@@ -8,6 +8,16 @@ Workload (2D, (-1, 1)^2, N = 256, n = 255 interior points padded to a
 Gaussians (centres U(-0.5, 0.5)^2, widths U(0.05, 0.2)); training seeds
 100000 + i, held-out seeds 900000 + i.  A training pair is (f, u) with
 A u = f solved to 1e-8 by the batched mixed-precision solver.
+
+Two recipes:
+  * pairs: (f, u) pairs and the relative L2 loss ||y - u|| / ||u|| (the
+    network learns A^{-1} on smooth right-hand sides only);
+  * residual: target-free inputs (white noise, Gaussian sums, and the
+    residuals f - A x_k of k plain-CG iterations) and the residual loss
+    ||A y - x0||^2 / ||x0||^2, with each operator scaled to a unit diagonal
+    (A(h) = h^-alpha A(1), so a mesh h_s gives -c a_0 = 1).  Flexible PCG is
+    invariant to a constant factor on the preconditioner, so a network trained
+    at unit diagonal serves every mesh of the same N and alpha.
 """
 import time
 
@@ -74,3 +84,52 @@ def compare(net, N, seeds, tol=1e-8, reps=2):
         op.close()
         out.append(row)
     return out
+
+
+def unit_diagonal_operator(alpha, N, L=2.0):
+    """The 2D operator of (alpha, N) scaled to a unit diagonal: A(h) = h^-alpha A(1), so the mesh
+    h_s = h d^(1/alpha) with d = -c a_0 at h = L / N gives -c a_0 = 1."""
+    o = fl.Operator(2, alpha, L / N, N)
+    d0 = -o.c * o.a0
+    o.close()
+    return fl.Operator(2, alpha, (L / N) * d0 ** (1.0 / alpha), N)
+
+
+def make_residual_samples(net, N, count, alphas=None, seed=7, max_cg=80, chunk=64):
+    """Inputs for the residual loss, cycling through `alphas` (17 values over [0.3, 1.9] by default):
+    sample i is white noise U(-1, 1) (seed 500000 + i) when i % 3 == 0, the Gaussian-sum right-hand
+    side of seed 100000 + i when i % 3 == 1, and otherwise that right-hand side's residual
+    f - A x_k after k ~ U{1, ..., max_cg} plain-CG iterations from 0.  Returns (x [count, H, H, 2],
+    per-sample unit-diagonal operators, all operators to keep alive)."""
+    import torch
+    if alphas is None:
+        alphas = np.linspace(0.3, 1.9, 17)
+    H, n = net.H, N - 1
+    rng = np.random.default_rng(seed)
+    scaled = [unit_diagonal_operator(float(a), N) for a in alphas]
+    plain = [fl.Operator(2, float(a), 2.0 / N, N) for a in alphas]
+    x = torch.zeros((count, H, H, 2), dtype=torch.float32, device="cuda:0")
+    ops = []
+    for k0 in range(0, count, chunk):
+        rs, al = [], []
+        for i in range(k0, min(count, k0 + chunk)):
+            j = i % len(alphas)
+            if i % 3 == 0:
+                r = _dev(inputs.uniform(n * n, seed=500000 + i), torch.float64)
+            else:
+                _, f = inputs.learned_problem(100000 + i, N=N)
+                r = _dev(f, torch.float64)
+                if i % 3 == 2:
+                    kit = int(rng.integers(1, max_cg + 1))
+                    u, _ = plain[j].poisson_solve(r, tol=1e-14, solver="cg64", max_iter=kit, raise_on_error=False)
+                    r = r - plain[j].apply(u)
+            rs.append(r)
+            al.append(float(alphas[j]))
+            ops.append(scaled[j])
+        net.pack(rs, None, al, n, x[k0:k0 + len(rs)])
+    return x, ops, scaled + plain
+
+
+def train_residual(net, x, ops, epochs, batch=16, lr=1e-3, lr_final=2e-5, seed=3):
+    """Adam epochs on the residual loss ||A y - x0||^2 / ||x0||^2; mean loss per epoch."""
+    return net.train(x, None, epochs=epochs, batch=batch, lr=lr, lr_final=lr_final, seed=seed, ops=ops)

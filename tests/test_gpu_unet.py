@@ -328,6 +328,48 @@ def test_energy_loss_vs_oracle(fl):
     assert abs(losses[0] - np.mean(ref)) <= 1e-4 * np.mean(ref), (losses[0], np.mean(ref))
 
 
+def test_residual_loss_vs_oracle(fl):
+    """Target-free residual loss ||A y - x0||^2 / ||x0||^2 against the oracle's dense A: the loss
+    value at the initial weights, and the direction of Adam's first step (-lr sign(grad)) against
+    the oracle's autograd gradient."""
+    import torch as T_
+    N, H = 32, 32
+    n = N - 1
+    net = fl.UNet(H, max_batch=4, seed=1, fp32_operands=True)
+    w = _weights(140)
+    net.set_weights(w)
+    alphas = [0.8, 1.5]
+    ops, dense, xs, sops = [], [], [], []
+    for a in alphas:
+        ops.append(fl.Operator(2, a, 2.0 / N, N))
+        dense.append(oracle.dense(2, N, a, oracle.coeffs(2, a, 2.0 / N, N)))
+    for k in range(4):
+        r = inputs.uniform(n * n, seed=141 + k) if k % 2 else inputs.gauss_sum(2, N, 6, 141 + k)
+        xs.append(ounet.net_input(r.reshape(n, n), H, alphas[k % 2]))
+        sops.append(ops[k % 2])
+    X = np.array(xs)
+    # oracle loss and gradient (float64 autograd through the CPU U-Net)
+    wt = T_.tensor(w.astype(np.float64), requires_grad=True)
+    y = ounet.forward_t(wt, T_.as_tensor(X))
+    tot = 0.0
+    for k in range(4):
+        A = T_.as_tensor(dense[k % 2])
+        x0 = T_.as_tensor(X[k, :n, :n, 0]).reshape(-1)
+        e = A @ y[k, :n, :n].reshape(-1) - x0
+        tot = tot + (e @ e) / (x0 @ x0)
+    L = tot / 4
+    L.backward()
+    g = wt.grad.numpy()
+    lr = 1e-3
+    losses = net.train(_f32(X), None, epochs=1, batch=4, lr=lr, lr_final=lr, ops=sops)
+    assert abs(losses[0] - float(L)) <= 1e-4 * float(L), (losses[0], float(L))
+    dw = net.weights() - w
+    big = np.abs(g) > 1e-3 * np.abs(g).max()
+    agree = np.mean(np.sign(dw[big]) == -np.sign(g[big]))
+    assert agree > 0.999, agree
+    assert np.allclose(np.abs(dw[big]), lr, rtol=1e-2)
+
+
 def test_c5_workload_sampled_residual(fl):
     """Learned-preconditioner workload at full size (N = 256): a short training run on solver pairs,
     then flexible PCG on held-out problems.  The converged solution's residual is checked on
@@ -350,3 +392,32 @@ def test_c5_workload_sampled_residual(fl):
         Au = oracle.apply_rows(2, N, alpha, a, ug, rows)
         # each sampled residual entry is bounded by the global residual norm
         assert np.linalg.norm(f[rows] - Au) <= 1.1e-8 * np.linalg.norm(f)
+
+
+def test_residual_recipe_preconditioner_gains_over_cg(fl):
+    """What the trained network gains: after a short residual-loss training (unit-diagonal operators;
+    noise, Gaussian sums and plain-CG residuals as inputs), flexible PCG with the network reaches
+    1e-8 in fewer iterations than plain CG on held-out problems with alpha >= 1, without falling
+    back; the solutions agree with CG's."""
+    from paper_1804_02718_amd import learned
+    N = 128
+    net = fl.UNet(N, max_batch=16, seed=1)
+    x, ops, keep = learned.make_residual_samples(net, N, 768)
+    losses = learned.train_residual(net, x, ops, epochs=6)
+    for o in keep:
+        o.close()
+    assert np.all(np.isfinite(losses)) and losses[-1] < 0.5 and losses[-1] < losses[0]
+    gains = []
+    for alpha, sd in ((1.2, 900100), (1.6, 900101), (1.9, 900102)):
+        _, f = inputs.learned_problem(sd, N=N)
+        op = fl.Operator(2, alpha, 2.0 / N, N)
+        op.set_preconditioner(net)
+        F = _f64(f)
+        u1, i1 = op.poisson_solve(F, tol=1e-8, solver="fpcg")
+        u2, i2 = op.poisson_solve(F, tol=1e-8, solver="cg64")
+        assert i1["fell_back"] == 0 and i1["relres"] <= 1e-8
+        assert float((u1 - u2).norm() / u2.norm()) < 1e-6
+        gains.append(i2["iters"] / i1["iters"])
+        op.close()
+    assert min(gains) > 1.3, gains
+    net.close()
