@@ -1029,8 +1029,8 @@ __global__ __launch_bounds__(256) void k_symbol1d(const double *__restrict__ a, 
 // Large 2D operators (FFT length P = 4096 ... 16384): a line no longer fits a
 // workgroup's LDS (16384 FP64 values take 256 KB), so every radix pass of the
 // transforms is a kernel over the whole buffer in HBM (Stockham autosort,
-// out of place, radix 4 with a radix-2 pass when log2 P is odd; the indexing
-// of Govindaraju et al., SC 2008).  The 288 GB of HBM hold the two P x Qp
+// out of place, radix 16 (as 4 x 4 in registers) then a radix-4 or radix-2
+// pass for the rest of log2 P; the indexing of Govindaraju et al., SC 2008).  The 288 GB of HBM hold the two P x Qp
 // complex work buffers (2.1 GB each in FP64 at P = 16384) with room to spare.
 // Steps of y = A u (u: ny rows of nx values, x fastest):
 //   pack row pairs into complex lines | x forward passes | Hermitian split into
@@ -1053,6 +1053,17 @@ __global__ __launch_bounds__(256) void k_big_pack(const T *__restrict__ u, C2<T>
         const T b = 2 * r + 1 < ny ? u[(2 * r + 1) * nx + p] : T(0);
         lines[r * P + p] = mk<T>(a, b);
     }
+}
+
+// radix-4 DFT in place: forward X1 = t1 - i t3, X3 = t1 + i t3 (inverse: signs swap)
+template <typename T, bool INV>
+__device__ __forceinline__ void big_dft4(C2<T> &a, C2<T> &b, C2<T> &c, C2<T> &d) {
+    const C2<T> t0 = cadd<T>(a, c), t1 = csub<T>(a, c), t2 = cadd<T>(b, d), t3 = csub<T>(b, d);
+    const C2<T> it3 = INV ? cmuli<T, 1>(t3) : cmuli<T, -1>(t3);
+    a = cadd<T>(t0, t2);
+    c = csub<T>(t0, t2);
+    b = cadd<T>(t1, it3);
+    d = csub<T>(t1, it3);
 }
 
 // one Stockham pass of radix R over nlines transforms of length P: line l,
@@ -1098,15 +1109,30 @@ __global__ __launch_bounds__(256) void k_big_pass(const C2<T> *__restrict__ in, 
             const C2<T> a = v[0];
             v[0] = cadd<T>(a, v[1]);
             v[1] = csub<T>(a, v[1]);
+        } else if constexpr (R == 4) {
+            big_dft4<T, INV>(v[0], v[1], v[2], v[3]);
         } else {
-            const C2<T> t0 = cadd<T>(v[0], v[2]), t1 = csub<T>(v[0], v[2]);
-            const C2<T> t2 = cadd<T>(v[1], v[3]), t3 = csub<T>(v[1], v[3]);
-            v[0] = cadd<T>(t0, t2);
-            v[2] = csub<T>(t0, t2);
-            // forward: X1 = t1 - i t3, X3 = t1 + i t3; inverse: the signs swap
-            const C2<T> it3 = INV ? cmuli<T, 1>(t3) : cmuli<T, -1>(t3);
-            v[1] = cadd<T>(t1, it3);
-            v[3] = csub<T>(t1, it3);
+            // 16 = 4 x 4: DFT4 over n1 of x[4 n1 + n2] for each n2, twiddle W16^(n2 k1),
+            // DFT4 over n2 for each k1; X[k1 + 4 k2] lands in v[4 n2 + k1] transposed below
+#pragma unroll
+            for (int n2 = 0; n2 < 4; ++n2) big_dft4<T, INV>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+#pragma unroll
+            for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+                for (int k1 = 1; k1 < 4; ++k1) {
+                    const C2<T> t = tw[n2 * k1 * (P / 16)];
+                    v[4 * k1 + n2] = cmul<T>(v[4 * k1 + n2], INV ? cconj<T>(t) : t);
+                }
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1) big_dft4<T, INV>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+            // v[4 k1 + k2] holds X[k1 + 4 k2]: transpose the 4 x 4 index
+            C2<T> w[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) w[k] = v[k];
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+                for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = w[4 * k1 + k2];
         }
         C2<T> *dst = out + line * lstride;
         const int base = (j / Ns) * Ns * R + m;
@@ -1194,7 +1220,7 @@ static int big_grid(long total) {
     return (int)(g > (1L << 20) ? (1L << 20) : (g < 1 ? 1 : g));
 }
 
-// the passes of one set of transforms (radix 4, then 2 if log2 P is odd),
+// the passes of one set of transforms (radix 16 while it divides, then 4 or 2),
 // ping-ponging between a and b; returns the buffer that holds the result
 template <typename T, bool INV, bool LINE_FAST>
 static C2<T> *big_fft(C2<T> *a, C2<T> *b, int P, int nlines, long lstride, long pstride, int n_in, int n_out,
@@ -1202,26 +1228,24 @@ static C2<T> *big_fft(C2<T> *a, C2<T> *b, int P, int nlines, long lstride, long 
     int Ns = 1;
     bool first = true;
     while (Ns < P) {
-        const int R = (P / Ns) % 4 == 0 ? 4 : 2;
+        const int R = (P / Ns) % 16 == 0 ? 16 : ((P / Ns) % 4 == 0 ? 4 : 2);
         const bool last = Ns * R == P;
         const int ni = first ? n_in : P, no = last ? n_out : P;
         const int g = big_grid((long)nlines * (P / R));
         const bool withlam = first && lam != nullptr;
-        if (R == 4) {
-            if (withlam)
-                hipLaunchKernelGGL((k_big_pass<T, 4, INV, LINE_FAST, true>), dim3(g), dim3(256), 0, s, a, b, P, Ns, nlines,
-                                   lstride, pstride, ni, no, tw, lam, Q, done);
-            else
-                hipLaunchKernelGGL((k_big_pass<T, 4, INV, LINE_FAST, false>), dim3(g), dim3(256), 0, s, a, b, P, Ns,
-                                   nlines, lstride, pstride, ni, no, tw, lam, Q, done);
-        } else {
-            if (withlam)
-                hipLaunchKernelGGL((k_big_pass<T, 2, INV, LINE_FAST, true>), dim3(g), dim3(256), 0, s, a, b, P, Ns, nlines,
-                                   lstride, pstride, ni, no, tw, lam, Q, done);
-            else
-                hipLaunchKernelGGL((k_big_pass<T, 2, INV, LINE_FAST, false>), dim3(g), dim3(256), 0, s, a, b, P, Ns,
-                                   nlines, lstride, pstride, ni, no, tw, lam, Q, done);
-        }
+#define FL_BIGPASS(RR)                                                                                               \
+    do {                                                                                                             \
+        if (withlam)                                                                                                 \
+            hipLaunchKernelGGL((k_big_pass<T, RR, INV, LINE_FAST, true>), dim3(g), dim3(256), 0, s, a, b, P, Ns,     \
+                               nlines, lstride, pstride, ni, no, tw, lam, Q, done);                                  \
+        else                                                                                                         \
+            hipLaunchKernelGGL((k_big_pass<T, RR, INV, LINE_FAST, false>), dim3(g), dim3(256), 0, s, a, b, P, Ns,    \
+                               nlines, lstride, pstride, ni, no, tw, lam, Q, done);                                  \
+    } while (0)
+        if (R == 16) FL_BIGPASS(16);
+        else if (R == 4) FL_BIGPASS(4);
+        else FL_BIGPASS(2);
+#undef FL_BIGPASS
         Ns *= R;
         first = false;
         C2<T> *t = a;
