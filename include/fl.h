@@ -57,7 +57,10 @@ typedef enum {
 typedef enum { FL_FP64 = 0, FL_FP32 = 1 } fl_prec;
 
 typedef enum {
-    FL_SOLVE_AUTO = 0,    /* mixed-precision refinement                          */
+    FL_SOLVE_AUTO = 0,    /* Poisson: REFINE for alpha <= 1.25, CG64 above (each
+                             refinement step restarts CG, which costs the stiffer
+                             operators more iterations than FP32 saves); the
+                             Allen-Cahn steps: REFINE                            */
     FL_SOLVE_CG64 = 1,    /* plain conjugate gradients, FP64 matvec and vectors  */
     FL_SOLVE_REFINE = 2,  /* FP64 residual refinement around FP32-matvec CG      */
     FL_SOLVE_FPCG = 3     /* flexible PCG with the learned preconditioner        */

@@ -592,7 +592,11 @@ fl_status fl_poisson_solve_ex(fl_op op, const double *f, double tol, double *u, 
         hipLaunchKernelGGL(k_zero<double>, dim3(ew_grid(op->M)), dim3(256), 0, s, u, op->M);
     }
     const int max_iter = o.max_iter > 0 ? o.max_iter : default_max_iter(op);
-    const bool inner64 = o.solver == FL_SOLVE_CG64;
+    // AUTO: FP32-matvec refinement up to alpha = 1.25, FP64 CG above.  Each refinement
+    // step restarts CG, and for the stiffer operators the restarts cost more iterations
+    // than the cheaper FP32 matvec saves (2D N = 1024 to 1e-8: refinement 5-10 % faster
+    // at alpha <= 1, 7 % and 16 % slower at alpha = 1.5 and 1.9)
+    const bool inner64 = o.solver == FL_SOLVE_CG64 || (o.solver == FL_SOLVE_AUTO && op->alpha > 1.25);
     const double itol = o.inner_tol > 0.0 ? o.inner_tol : 1e-3;
     fl_status st = o.solver == FL_SOLVE_FPCG ? fpcg(op, f, u, tol, max_iter, inf, s)
                                              : refine(op, 0.0, 1.0, f, u, tol, inner64, itol, max_iter,
