@@ -33,8 +33,17 @@ enum : int {
     S_ITER = 4,
     S_TARGET = 5,  // stop when (r, r) <= target
     S_DOT = 6,     // result slot of a standalone dot
+    // flexible PCG: current (r, r), (r, z) ping / pong, best (r, r) so far and
+    // iterations since it last dropped by 4 (the residual by 2)
+    S_FRR = 7,
+    S_FRZ0 = 8,
+    S_FRZ1 = 9,
+    S_FBEST = 10,
+    S_FSINCE = 11,
     S_COUNT = 16
 };
+// flexible PCG break codes in S_BRK
+enum : int { BRK_PAP = 1, BRK_RZ = 2, BRK_NAN = 3, BRK_STALL = 4 };
 
 struct VecLayout {
     long n, chunk;
@@ -452,19 +461,117 @@ static fl_status refine(fl_op op, double s0, double s1, const double *b, double 
 }
 
 // x += a p; rold = r; r -= a kp
-__global__ void k_fpcg_update(double *__restrict__ x, double *__restrict__ r, double *__restrict__ rold,
-                              const double *__restrict__ p, const double *__restrict__ kp, double a, long n) {
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        x[i] += a * p[i];
-        const double ri = r[i];
-        rold[i] = ri;
-        r[i] = ri - a * kp[i];
+// flexible PCG start (one block): (r, r) and (r, z) from partials; target, flags
+__global__ __launch_bounds__(kVecBlock) void k_fpcg_init(const double *part_rr, const double *part_rz, int np,
+                                                         double *scal, double target) {
+    __shared__ double sh[kVecBlock];
+    const double rr = sum_parts(part_rr, np, sh);
+    const double rz = sum_parts(part_rz, np, sh);
+    if (threadIdx.x == 0) {
+        scal[S_FRR] = rr;
+        scal[S_FRZ0] = rz;
+        scal[S_ITER] = 0.0;
+        scal[S_TARGET] = target;
+        scal[S_FBEST] = rr;
+        scal[S_FSINCE] = 0.0;
+        const int brk = !std::isfinite(rr) ? BRK_NAN : (!(rz > 0.0) || !std::isfinite(rz) ? BRK_RZ : 0);
+        scal[S_BRK] = (double)brk;
+        scal[S_DONE] = (brk != 0 || rr <= target) ? 1.0 : 0.0;
     }
 }
-// p = z + b p
-__global__ void k_fpcg_dir(double *__restrict__ p, const double *__restrict__ z, double b, long n) {
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        p[i] = z[i] + b * p[i];
+// alpha = (r, z) / (p, A p); x += alpha p; r_old = r; r -= alpha A p; partial (r, r)
+__global__ __launch_bounds__(kVecBlock) void k_fpcg_xr(double *__restrict__ x, double *__restrict__ r,
+                                                       double *__restrict__ rold, const double *__restrict__ p,
+                                                       const double *__restrict__ kp, long n, long chunk,
+                                                       const double *__restrict__ part_pkp, int np,
+                                                       double *__restrict__ part_rr, double *scal, int parity) {
+    __shared__ double sh[kVecBlock];
+    if (scal[S_DONE] != 0.0) return;
+    const double pkp = sum_parts(part_pkp, np, sh);
+    const double al = scal[parity ? S_FRZ1 : S_FRZ0] / pkp;
+    if (!(pkp > 0.0) || !std::isfinite(al)) {  // every block sees the same sums
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            scal[S_BRK] = (double)BRK_PAP;
+            scal[S_DONE] = 1.0;
+        }
+        return;
+    }
+    const long beg = (long)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
+    double acc = 0.0;
+    for (long i = beg + threadIdx.x; i < end; i += kVecBlock) {
+        x[i] += al * p[i];
+        const double ri = r[i];
+        rold[i] = ri;
+        const double rn = ri - al * kp[i];
+        r[i] = rn;
+        acc += rn * rn;
+    }
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) part_rr[blockIdx.x] = t;
+}
+// (r, r) bookkeeping (one block): iteration count, convergence, finiteness, and
+// the stall test (the residual has not halved in 50 iterations)
+__global__ __launch_bounds__(kVecBlock) void k_fpcg_rr(const double *part_rr, int np, double *scal) {
+    __shared__ double sh[kVecBlock];
+    if (scal[S_DONE] != 0.0) return;
+    const double rr = sum_parts(part_rr, np, sh);
+    if (threadIdx.x == 0) {
+        scal[S_FRR] = rr;
+        scal[S_ITER] += 1.0;
+        if (!std::isfinite(rr)) {
+            scal[S_BRK] = (double)BRK_NAN;
+            scal[S_DONE] = 1.0;
+        } else if (rr <= scal[S_TARGET]) {
+            scal[S_DONE] = 1.0;
+        } else if (rr < 0.25 * scal[S_FBEST]) {
+            scal[S_FBEST] = rr;
+            scal[S_FSINCE] = 0.0;
+        } else if ((scal[S_FSINCE] += 1.0) > 50.0) {
+            scal[S_BRK] = (double)BRK_STALL;
+            scal[S_DONE] = 1.0;
+        }
+    }
+}
+// partials of (r, z) and (r_old, z) in one pass
+__global__ __launch_bounds__(kVecBlock) void k_fpcg_dot2(const double *__restrict__ r, const double *__restrict__ z,
+                                                         const double *__restrict__ rold, long n, long chunk,
+                                                         double *part_rz, double *part_roz, const double *done) {
+    __shared__ double sh[kVecBlock];
+    if (done && done[0] != 0.0) return;
+    const long beg = (long)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
+    double a = 0.0, b = 0.0;
+    for (long i = beg + threadIdx.x; i < end; i += kVecBlock) {
+        const double zi = z[i];
+        a += r[i] * zi;
+        b += rold[i] * zi;
+    }
+    const double sa = block_sum(a, sh);
+    const double sb = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+        part_rz[blockIdx.x] = sa;
+        part_roz[blockIdx.x] = sb;
+    }
+}
+// Polak--Ribiere beta = ((r, z) - (r_old, z)) / (r_old, z_old); p = z + beta p;
+// block 0 stores the new (r, z) in the other slot
+__global__ __launch_bounds__(kVecBlock) void k_fpcg_dir(double *__restrict__ p, const double *__restrict__ z, long n,
+                                                        long chunk, const double *part_rz, const double *part_roz,
+                                                        int np, double *scal, int parity) {
+    __shared__ double sh[kVecBlock];
+    if (scal[S_DONE] != 0.0) return;
+    const double rzn = sum_parts(part_rz, np, sh);
+    const double zro = sum_parts(part_roz, np, sh);
+    const double be = (rzn - zro) / scal[parity ? S_FRZ1 : S_FRZ0];
+    if (!(rzn > 0.0) || !std::isfinite(be)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            scal[S_BRK] = (double)BRK_RZ;
+            scal[S_DONE] = 1.0;
+        }
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) scal[parity ? S_FRZ0 : S_FRZ1] = rzn;
+    const long beg = (long)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
+    for (long i = beg + threadIdx.x; i < end; i += kVecBlock) p[i] = z[i] + be * p[i];
 }
 
 // Flexible PCG (Notay's flexible CG with the Polak--Ribiere beta) with the
@@ -476,6 +583,7 @@ static fl_status fpcg(fl_op op, const double *f, double *x, double tol, int max_
     FL_TRY(ensure_workspace(op));
     Work w = work_of(op);
     const long M = op->M;
+    VecLayout L = layout(M);
     double *r = w.r64, *z = w.d64, *p = w.p64, *kp = w.kp64, *rold = w.b64;
     double bb = 0.0;
     FL_TRY(dot<double>(op, f, f, w.partA, &bb, s));
@@ -486,69 +594,72 @@ static fl_status fpcg(fl_op op, const double *f, double *x, double tol, int max_
         FL_HIP_TRY(hipStreamSynchronize(s));
         return FL_OK;
     }
+    // r = f - A x; (r, r) into S_FRR for the network's scaling; z = M r; (r, z); p = z
     FL_TRY(residual64(op, f, x, r, 0.0, 1.0, s));
-    double rr = 0.0, rz = 0.0, best = INFINITY;
-    int since_best = 0;
-    bool fallback = false;
-    FL_TRY(dot<double>(op, r, r, w.partA, &rr, s));  // leaves (r,r) in scal[S_DOT]
-    FL_TRY(unet_apply(op->net, r, op->n, op->alpha, z, op->scal + S_DOT, s));
-    FL_TRY(dot<double>(op, r, z, w.partA, &rz, s));
-    if (!(rz > 0.0) || !std::isfinite(rz)) {
-        fallback = true;
-        set_error("FPCG: (r, z) = %.3e at the start; plain CG takes over", rz);
-    }
+    double *scal = op->scal;
+    const double *done = scal + S_DONE;
+    hipLaunchKernelGGL(k_dot<double>, dim3(L.blocks), dim3(kVecBlock), 0, s, r, r, L.n, L.chunk, w.partA, nullptr);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kVecBlock), 0, s, w.partA, L.blocks, scal, (int)S_FRR);
+    FL_TRY(unet_apply(op->net, r, op->n, op->alpha, z, scal + S_FRR, s));
+    hipLaunchKernelGGL(k_dot<double>, dim3(L.blocks), dim3(kVecBlock), 0, s, r, z, L.n, L.chunk, w.partB, nullptr);
+    hipLaunchKernelGGL(k_fpcg_init, dim3(1), dim3(kVecBlock), 0, s, w.partA, w.partB, L.blocks, scal,
+                       tol * tol * bb);
     hipLaunchKernelGGL((k_copy_cast<double, double>), dim3(ew_grid(M)), dim3(256), 0, s, p, z, M);
-    int it = 0;
-    info->relres = std::sqrt(rr) / bn;
-    while (!fallback && it < max_iter && info->relres > tol) {
-        FL_TRY(matvec<double>(op, p, kp, s));
-        double pq = 0.0;
-        FL_TRY(dot<double>(op, p, kp, w.partA, &pq, s));
-        const double a = rz / pq;
-        if (!(pq > 0.0) || !std::isfinite(a)) {
-            fallback = true;
-            set_error("FPCG: (p, A p) = %.3e at iteration %d; plain CG takes over", pq, it);
-            break;
-        }
-        hipLaunchKernelGGL(k_fpcg_update, dim3(ew_grid(M)), dim3(256), 0, s, x, r, rold, p, kp, a, M);
-        FL_TRY(dot<double>(op, r, r, w.partA, &rr, s));
-        ++it;
-        info->relres = std::sqrt(rr) / bn;
-        if (!std::isfinite(info->relres)) {
-            fallback = true;
-            set_error("FPCG: residual not finite at iteration %d; plain CG takes over", it);
-            break;
-        }
-        if (info->relres < 0.5 * best) { best = info->relres; since_best = 0; }
-        else if (++since_best > 50) {
-            fallback = true;
-            set_error("FPCG: residual %.3e not halved in 50 iterations (at %d); plain CG takes over", info->relres, it);
-            break;
-        }
-        if (info->relres <= tol) break;
-        FL_TRY(unet_apply(op->net, r, op->n, op->alpha, z, op->scal + S_DOT, s));
-        double rzn = 0.0, zro = 0.0;
-        FL_TRY(dot<double>(op, r, z, w.partA, &rzn, s));
-        FL_TRY(dot<double>(op, rold, z, w.partA, &zro, s));
-        const double beta = (rzn - zro) / rz;  // Polak--Ribiere: (z, r - r_old) / (r_old, z_old)
-        if (!(rzn > 0.0) || !std::isfinite(beta)) {
-            fallback = true;
-            set_error("FPCG: (r, z) = %.3e at iteration %d; plain CG takes over", rzn, it);
-            break;
-        }
-        hipLaunchKernelGGL(k_fpcg_dir, dim3(ew_grid(M)), dim3(256), 0, s, p, z, beta, M);
-        rz = rzn;
-    }
-    info->iters = it;
     FL_HIP_TRY(hipGetLastError());
+    // (p, A p) from the matvec's last pass when its workgroups fit the partials array
+    const int np_x = xinv_parts(op->d, (long)(op->M / op->nk[0]), op->P, FL_FP64, op->var64);
+    const bool fused = np_x > 0 && np_x <= kMaxParts;
+    // scalars stay on the device; the host reads them every kCheck iterations
+    // (the network does not test the done flag, so at most kCheck - 1
+    // applications follow convergence)
+    constexpr int kCheck = 4;
+    int launched = 0;
+    FL_TRY(read_scalars(op, s));
+    while (op->hscal[S_DONE] == 0.0 && launched < max_iter) {
+        const int k = kCheck < max_iter - launched ? kCheck : max_iter - launched;
+        for (int i = 0; i < k; ++i) {
+            const int parity = (launched + i) & 1;
+            FL_TRY(apply_K<double>(op, p, kp, 0.0, 1.0, done, s, fused ? w.partA : nullptr));
+            if (!fused)
+                hipLaunchKernelGGL(k_dot<double>, dim3(L.blocks), dim3(kVecBlock), 0, s, p, kp, L.n, L.chunk,
+                                   w.partA, done);
+            hipLaunchKernelGGL(k_fpcg_xr, dim3(L.blocks), dim3(kVecBlock), 0, s, x, r, rold, p, kp, L.n, L.chunk,
+                               w.partA, fused ? np_x : L.blocks, w.partB, scal, parity);
+            hipLaunchKernelGGL(k_fpcg_rr, dim3(1), dim3(kVecBlock), 0, s, w.partB, L.blocks, scal);
+            FL_TRY(unet_apply(op->net, r, op->n, op->alpha, z, scal + S_FRR, s));
+            hipLaunchKernelGGL(k_fpcg_dot2, dim3(L.blocks), dim3(kVecBlock), 0, s, r, z, rold, L.n, L.chunk,
+                               w.partA, w.partB, done);
+            hipLaunchKernelGGL(k_fpcg_dir, dim3(L.blocks), dim3(kVecBlock), 0, s, p, z, L.n, L.chunk, w.partA,
+                               w.partB, L.blocks, scal, parity);
+        }
+        FL_HIP_TRY(hipGetLastError());
+        launched += k;
+        FL_TRY(read_scalars(op, s));
+    }
+    const int it = (int)op->hscal[S_ITER];
+    const int brk = (int)op->hscal[S_BRK];
+    info->iters = it;
+    info->relres = std::sqrt(op->hscal[S_FRR]) / bn;
+    bool fallback = brk != 0;
+    switch (brk) {
+        case BRK_PAP: set_error("FPCG: (p, A p) <= 0 at iteration %d; plain CG takes over", it); break;
+        case BRK_RZ: set_error("FPCG: (r, z) <= 0 at iteration %d; plain CG takes over", it); break;
+        case BRK_NAN: set_error("FPCG: residual not finite at iteration %d; plain CG takes over", it); break;
+        case BRK_STALL:
+            set_error("FPCG: residual %.3e not halved in 50 iterations (at %d); plain CG takes over", info->relres,
+                      it);
+            break;
+        default: break;
+    }
     if (!fallback) {
         // verify with a fresh FP64 residual
         FL_TRY(residual64(op, f, x, r, 0.0, 1.0, s));
+        double rr = 0.0;
         FL_TRY(dot<double>(op, r, r, w.partA, &rr, s));
         info->relres = std::sqrt(rr) / bn;
         info->outer_iters = 1;
         if (info->relres <= tol) return FL_OK;
-        if (it >= max_iter) { set_error("FPCG: no convergence"); return FL_E_NOCONV; }
+        if (launched >= max_iter) { set_error("FPCG: no convergence"); return FL_E_NOCONV; }
     }
     // plain FP64 CG from the current iterate
     info->fell_back = 1;
