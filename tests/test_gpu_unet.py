@@ -188,6 +188,25 @@ def test_apply_vs_oracle(fl, H, n):
     assert np.linalg.norm(z - ref) <= 5e-6 * np.linalg.norm(ref)
 
 
+def test_apply_repeated_vs_oracle(fl):
+    """Repeated preconditioner actions on the same buffers with new contents, eager work and
+    synchronisations between them, a weight update and a change of alpha each match the oracle."""
+    H, n = 32, 31
+    net = fl.UNet(H, max_batch=1, seed=1, fp32_operands=True)
+    r_dev = _f64(np.zeros(n * n))
+    z_dev = torch.empty_like(r_dev)
+    for k, (wseed, alpha) in enumerate(((150, 1.3), (150, 1.3), (151, 1.3), (151, 0.6), (151, 0.6))):
+        w = _weights(wseed)
+        net.set_weights(w)
+        r = inputs.gauss_sum(2, n + 1, 6, 160 + k).reshape(n, n) * (1.0 + k)
+        r_dev.copy_(torch.as_tensor(r.ravel(), device="cuda:0"))
+        _ = (r_dev * 2.0).sum().item()  # eager work and a synchronisation between applications
+        net.apply(r_dev, n, alpha, z_dev)
+        ref = ounet.apply(w.astype(np.float64), r, alpha, H)
+        z = z_dev.cpu().numpy().reshape(n, n)
+        assert np.linalg.norm(z - ref) <= 5e-6 * np.linalg.norm(ref), k
+
+
 def test_pack_vs_oracle(fl):
     H, n = 32, 31
     net = fl.UNet(H, max_batch=4, seed=1)
