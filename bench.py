@@ -284,7 +284,7 @@ def c5_extra(torch, fl, pairs, epochs, N=256, res_samples=2048, res_epochs=10):
     torch.cuda.synchronize()
     t_mv = (time.perf_counter() - t0) / 100
     op.close()
-    held = [900000 + j for j in range(8)]
+    held = [900000 + j for j in range(64)]
     rows = learned.compare(net, N, held)
     net.close()
     # the residual recipe: unit-diagonal operators, target-free residual loss on noise, Gaussian
@@ -304,20 +304,38 @@ def c5_extra(torch, fl, pairs, epochs, N=256, res_samples=2048, res_epochs=10):
     rows2 = learned.compare(net2, N, held)
     net2.close()
 
-    def ratio(rs):
-        return round(float(np.mean([r["cg64"]["iters"] / max(1, r["fpcg"]["iters"]) for r in rs])), 3)
+    def summary(rs):
+        """Iteration and time ratios CG / FPCG over the held-out problems, overall and by alpha band,
+        and the compact per-problem rows."""
+        out = {"fell_back": int(sum(r["fpcg"]["fell_back"] for r in rs)),
+               "max_rel_diff_vs_cg": float(max(r["rel_diff"] for r in rs))}
+        for lo, hi in ((0.3, 1.0), (1.0, 1.5), (1.5, 1.91), (0.3, 1.91)):
+            sel = [r for r in rs if lo <= r["alpha"] < hi]
+            if not sel:
+                continue
+            key = "alpha_%.1f_%.1f" % (lo, min(hi, 1.9))
+            out[key] = {"problems": len(sel),
+                        "cg_over_fpcg_iters": round(float(np.mean([r["cg64"]["iters"] / max(1, r["fpcg"]["iters"])
+                                                                   for r in sel])), 3),
+                        "cg_over_fpcg_seconds": round(float(np.mean([r["cg64"]["seconds"] / r["fpcg"]["seconds"]
+                                                                     for r in sel])), 3)}
+        out["rows"] = [[round(r["alpha"], 4), r["fpcg"]["iters"], r["fpcg"]["fell_back"],
+                        round(r["fpcg"]["seconds"] * 1e3, 3), r["cg64"]["iters"], round(r["cg64"]["seconds"] * 1e3, 3)]
+                       for r in rs]
+        out["row_fields"] = ["alpha", "fpcg_iters", "fpcg_fell_back", "fpcg_ms", "cg64_iters", "cg64_ms"]
+        return out
 
     return {"workload": "2D N=256 (255^2 interior on a 256^2 network grid), alpha~U(0.3,1.9), f = 8 Gaussians; "
-                        "held-out seeds 900000..900007",
+                        "held-out seeds 900000..900063, tol 1e-8",
             "pairs": {"recipe": "%d solver pairs (seeds 100000+i), relative L2 loss, %d epochs" % (pairs, epochs),
                       "pair_generation_seconds": round(tgen, 2), "pair_solver_mean_iters": round(mean_it, 1),
                       "training_seconds": round(ttrain, 2), "epoch_loss": [round(float(l), 4) for l in losses],
-                      "cg_over_fpcg_iters": ratio(rows), "solves": rows},
+                      "held_out": summary(rows)},
             "residual": {"recipe": "%d inputs (noise, Gaussian sums, plain-CG residuals), unit-diagonal operators, "
                                    "residual loss, %d epochs" % (res_samples, res_epochs),
                          "sample_seconds": round(tgen2, 2), "training_seconds": round(ttrain2, 2),
                          "epoch_loss": [round(float(l), 4) for l in losses2],
-                         "cg_over_fpcg_iters": ratio(rows2), "solves": rows2},
+                         "held_out": summary(rows2)},
             "net_apply_ms": round(t_apply * 1e3, 4), "net_apply_TFLOP_s": round(3.66e9 / t_apply / 1e12, 2),
             "fp64_matvec_ms": round(t_mv * 1e3, 4)}
 
@@ -513,6 +531,13 @@ def main():
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(N, alpha, h, u_np, args.cpu_seconds)
+        # the oracle's Poisson solve at C2, extrapolated (not measured): one full explicit
+        # matvec at the measured row rate, times the GPU's plain-CG iteration count
+        if "poisson" in extra and cpu.get("value"):
+            mv_s = M / (cpu["value"] * 1e9)
+            extra["poisson"]["oracle_extrapolated"] = {
+                "kind": "extrapolated", "oracle_matvec_seconds": round(mv_s, 1),
+                "cg64_seconds": round(mv_s * extra["poisson"]["cg64"]["iters"], 1)}
 
     line = {"metric": "Toeplitz matvec Gdof/s", "value": round(value, 3), "unit": "Gdof/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),

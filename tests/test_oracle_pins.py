@@ -617,3 +617,14 @@ def test_1d_apply_is_the_toeplitz_sum():
                     for i in range(1, N)])
     y = oracle.apply(1, N, alpha, a, u)
     assert np.allclose(y, ref, rtol=1e-14, atol=1e-14 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("d,N,alpha", [(1, 40, 1.3), (2, 9, 0.7), (2, 12, 1.8), (3, 5, 1.1)])
+def test_coefficients_scale_as_h_to_minus_alpha(d, N, alpha):
+    # every element integral scales as h^{d-q} and |xi_v|^2 as h^2, and D2 as L^{-alpha}:
+    # a(h) = h^{-alpha} a(1) at fixed N (the unit-diagonal rescaling of the learned
+    # preconditioner's training operators rests on this)
+    a1 = oracle.coeffs(d, alpha, 1.0, N)
+    for h in (0.37, 2.0 / N):
+        ah = oracle.coeffs(d, alpha, h, N)
+        assert np.allclose(ah, h ** -alpha * a1, rtol=1e-13, atol=0)
