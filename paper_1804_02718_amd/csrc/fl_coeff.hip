@@ -144,7 +144,7 @@ __global__ __launch_bounds__(256) void k_closed_forms(int d, double alpha, doubl
     s2[threadIdx.x] = a2;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) {
+        if ((int)threadIdx.x < k) {
             s1[threadIdx.x] += s1[threadIdx.x + k];
             s2[threadIdx.x] += s2[threadIdx.x + k];
         }
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(256) void k_sum_partial(const double *__restrict__ 
     s[threadIdx.x] = acc;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
+        if ((int)threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = s[0];
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(256) void k_a0_final(const double *__restrict__ par
     s[threadIdx.x] = acc;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
+        if ((int)threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
         __syncthreads();
     }
     if (threadIdx.x == 0) a[0] = -s[0] - (double)(1 << d) * scal[1];

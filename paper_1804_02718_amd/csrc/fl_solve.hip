@@ -62,7 +62,7 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     sh[threadIdx.x] = v;
     __syncthreads();
     for (int k = kVecBlock / 2; k > 0; k >>= 1) {
-        if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
         __syncthreads();
     }
     double r = sh[0];

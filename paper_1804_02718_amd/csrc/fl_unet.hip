@@ -310,7 +310,7 @@ __global__ __launch_bounds__(256) void k_loss_sums(const float *__restrict__ Y, 
     s2[threadIdx.x] = b;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) {
+        if ((int)threadIdx.x < k) {
             s1[threadIdx.x] += s1[threadIdx.x + k];
             s2[threadIdx.x] += s2[threadIdx.x + k];
         }
@@ -358,7 +358,7 @@ __global__ __launch_bounds__(256) void k_sumsq_part(const double *__restrict__ x
     sh[threadIdx.x] = a;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(256) void k_energy_loss(const float *__restrict__ d
     s2[threadIdx.x] = b;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) {
+        if ((int)threadIdx.x < k) {
             s1[threadIdx.x] += s1[threadIdx.x + k];
             s2[threadIdx.x] += s2[threadIdx.x + k];
         }
@@ -501,7 +501,7 @@ __global__ __launch_bounds__(256) void k_res_loss(float *__restrict__ q, const f
     s2[threadIdx.x] = b;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) {
+        if ((int)threadIdx.x < k) {
             s1[threadIdx.x] += s1[threadIdx.x + k];
             s2[threadIdx.x] += s2[threadIdx.x + k];
         }
