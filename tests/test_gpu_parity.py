@@ -262,7 +262,8 @@ def test_apply_rejects_overlap_and_dtype_mix(dev):
     op.close()
 
 
-@pytest.mark.parametrize("d,N,alpha,gamma", [(2, 33, 0.7, 1.35), (2, 64, 1.5, 1.75), (3, 9, 1.2, 1.6)])
+@pytest.mark.parametrize("d,N,alpha,gamma", [(1, 100, 0.9, 1.4), (2, 33, 0.7, 1.35), (2, 64, 1.5, 1.75),
+                                             (3, 9, 1.2, 1.6)])
 def test_gamma_below_two_coeffs_and_apply(dev, d, N, alpha, gamma):
     """Splitting parameter gamma < 2 (Sec. 2): coefficients and the FP64 matvec against the oracle."""
     fl = _fl()

@@ -282,6 +282,24 @@ def test_batched_1d_match_single_solves(fl):
     b.close()
 
 
+def test_batched_3d_match_oracle(fl):
+    # a batch of 3D problems of mixed N and alpha: each solution against the dense oracle solve
+    Ns = [6, 9, 6, 8]
+    alphas = [0.5, 1.3, 1.9, 1.0]
+    hs = [2.0 / N for N in Ns]
+    fs_np = [inputs.gauss_sum(3, N, 3, seed=300 + i) for i, N in enumerate(Ns)]
+    b = fl.Batch(3, Ns, alphas, hs)
+    assert b.info()["classes"] == 3
+    us, infos = b.solve([_t(f) for f in fs_np], tol=1e-10)
+    torch.cuda.synchronize()
+    for i, (N, al) in enumerate(zip(Ns, alphas)):
+        assert infos[i]["status"] == 0 and infos[i]["relres"] <= 1e-10, (i, infos[i])
+        A = oracle.dense(3, N, al, oracle.coeffs(3, al, hs[i], N))
+        uref = oracle.solve_dense(A, fs_np[i])
+        assert np.abs(us[i].cpu().numpy() - uref).max() <= 1e-8 * np.abs(uref).max(), i
+    b.close()
+
+
 def test_batched_c4_workload(fl):
     # 64 problems, N from {64, 128, 256, 512}, alpha ~ U(0.2, 1.95), 4 Gaussians each, tol 1e-8
     probs = inputs.batch_problems(64, seed=4)

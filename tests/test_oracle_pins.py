@@ -628,3 +628,22 @@ def test_coefficients_scale_as_h_to_minus_alpha(d, N, alpha):
     for h in (0.37, 2.0 / N):
         ah = oracle.coeffs(d, alpha, h, N)
         assert np.allclose(ah, h ** -alpha * a1, rtol=1e-13, atol=0)
+
+
+def test_bump_closed_form_3d():
+    # d = 3, alpha = 1.2: (-Delta)^{a/2} (1-|x|^2)_+^{a/2} = 2^a G(1+a/2) G((3+a)/2) / G(3/2)
+    # = 2.4239654799 on the unit ball; on |x| <= 1/2 the grid error is small and shrinks
+    alpha = 1.2
+    exact = float(2 ** mp.mpf(alpha) * mp.gamma(1 + alpha / 2) * mp.gamma((3 + alpha) / 2) / mp.gamma(1.5))
+    assert exact == pytest.approx(2.4239654799, abs=1e-10)
+    errs = []
+    for N in (16, 32, 64):
+        h = 2.0 / N
+        u = inputs.bump(3, N, alpha)
+        a = oracle.coeffs(3, alpha, h, N)
+        x1, x2, x3 = inputs.grid(3, N)
+        rows = np.nonzero(x1 ** 2 + x2 ** 2 + x3 ** 2 <= 0.25 + 1e-12)[0]
+        rows = rows[:: max(1, rows.size // 30)]
+        y = oracle.apply_rows(3, N, alpha, a, u, rows)
+        errs.append(np.abs(y - exact).max() / exact)
+    assert errs[0] < 1e-3 and errs[1] < errs[0] and errs[2] < errs[1], errs
