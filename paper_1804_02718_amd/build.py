@@ -15,13 +15,14 @@ LIB = os.path.join(HERE, "libfl.so")
 ARCH = "gfx950"
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "-fPIC",
     "--offload-arch=" + ARCH,
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
     "-I" + os.path.join(ROOT, "include"),
 ]
+OBJDIR = os.path.join(ROOT, "_build")
 
 
 def sources():
@@ -29,10 +30,28 @@ def sources():
 
 
 def build(verbose: bool = False) -> str:
-    """Compile all HIP sources into paper_1804_02718_amd/libfl.so; returns its path."""
+    """Compile every HIP source (in parallel, one object each) and link paper_1804_02718_amd/libfl.so;
+    returns its path.  Always recompiles."""
+    from concurrent.futures import ThreadPoolExecutor
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(OBJDIR, exist_ok=True)
+    srcs = sources()
+    objs = [os.path.join(OBJDIR, os.path.splitext(os.path.basename(f))[0] + ".o") for f in srcs]
+
+    def compile_one(pair):
+        src, obj = pair
+        cmd = [hipcc] + FLAGS + ["-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        return subprocess.run(cmd).returncode
+
+    workers = max(1, min(len(srcs), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        codes = list(ex.map(compile_one, zip(srcs, objs)))
+    if any(codes):
+        raise subprocess.CalledProcessError(max(codes), "hipcc -c")
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc] + FLAGS + sources() + ["-o", tmp]
+    cmd = [hipcc, "-shared", "-fPIC", "--offload-arch=" + ARCH] + objs + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     try:
