@@ -432,7 +432,7 @@ def main():
                          "whose known traffic calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(no sharding or inter-GPU collectives); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 

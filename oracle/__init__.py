@@ -23,7 +23,7 @@ Contents (gamma = 2, the paper's default in Sec. 5):
   Cholesky, or plain conjugate gradients on the explicit sum.
 * ``ac_step``                  -- one semi-implicit step of the fractional
   Allen--Cahn equation (Sec. 5.3: Crank--Nicolson on the linear term, the
-  cubic term explicit; readings listed in the design doc).
+  cubic term explicit at the old time level).
 
 Parity of the GPU path is measured against these functions; the functions
 themselves are pinned by ``tests/test_oracle_*.py`` against closed forms,
