@@ -66,6 +66,7 @@ static void destroy(fl_op op) {
     (void)hipFree(op->tw32);
     (void)hipFree(op->T1);
     (void)hipFree(op->T2);
+    (void)hipFree(op->mu64t);
     free_solver_workspace(op);
     delete op;
 }
@@ -260,6 +261,14 @@ fl_status fl_apply(fl_op op, const void *u, void *y, int prec, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     if (prec == FL_FP64) return matvec<double>(op, (const double *)u, (double *)y, s);
     return matvec<float>(op, (const float *)u, (float *)y, s);
+}
+
+fl_status fl_tau_apply(fl_op op, const double *r, double *z, double s0, double s1, void *stream) {
+    if (!op || !r || !z) { set_error("NULL argument"); return FL_E_INVAL; }
+    if (overlap(r, sizeof(double) * op->M, z, sizeof(double) * op->M)) { set_error("r and z overlap"); return FL_E_INVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    FL_TRY(tau_prepare(op, s0, s1, s));
+    return tau_apply(op, r, z, nullptr, s);
 }
 
 fl_status fl_apply_profiled(fl_op op, const void *u, void *y, int prec, int reps, void *stream, float *pass_ms,

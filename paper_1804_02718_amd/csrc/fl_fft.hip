@@ -93,16 +93,12 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xfwd(
     C2<T> tws[num_tw<PN>()];
     load_twiddles<T, P, PN>(tws, table, tl);
     C2<T> v[E];
-    // loads from clamped, always valid addresses; out-of-range values replaced by 0
+    // loads from clamped, always valid addresses; rows past nrows read as 0
     const T *ua = u + (long)(va ? ra : 0) * in_pitch, *ub = u + (long)(vb ? rb : 0) * in_pitch;
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-        const int pos = in_pos<P, PN, 0>(tl, j);
-        const bool in = pos < n_in;
-        const int pc = in ? pos : 0;
-        const T xa = ua[pc], xb = ub[pc];
-        v[j] = mk<T>((va && in) ? xa : T(0), (vb && in) ? xb : T(0));
-    }
+    load_line<T, P, PN>(v, tl, n_in, [&](int i) {
+        const T xa = ua[i], xb = ub[i];
+        return mk<T>(va ? xa : T(0), vb ? xb : T(0));
+    });
     const int base = lp * PL;
     auto lidx = [base](int pos) { return base + padpos(pos); };
     fwd_stages<T, P, PN, 0>(v, lds, tl, tws, lidx);
@@ -304,7 +300,7 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xinv(
 // ---------------------------------------------------------------------------
 template <typename T, int P, int E, int LPB, bool EPI>
 __global__ __launch_bounds__(LPB * (P / E)) void k_conv1d(
-    const T *__restrict__ u, T *__restrict__ y, int nrows, int n, const T *__restrict__ lam,
+    const T *__restrict__ u, T *__restrict__ y, int nrows, int n, int n_in, const T *__restrict__ lam,
     const C2<T> *__restrict__ table, Epi<T> ep, const double *__restrict__ done, BatchStrides bz) {
     const int z = blockIdx.z;
     if (done && done[z * bz.done] != 0.0) return;
@@ -328,14 +324,10 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_conv1d(
     C2<T> v[E];
     // loads from clamped, always valid addresses; out-of-range values replaced by 0
     const T *ua = u + (long)(va ? ra : 0) * n, *ub = u + (long)(vb ? rb : 0) * n;
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-        const int pos = in_pos<P, PN, 0>(tl, j);
-        const bool in = pos < n;
-        const int pc = in ? pos : 0;
-        const T xa = ua[pc], xb = ub[pc];
-        v[j] = mk<T>((va && in) ? xa : T(0), (vb && in) ? xb : T(0));
-    }
+    load_line<T, P, PN>(v, tl, n_in, [&](int i) {
+        const T xa = ua[i], xb = ub[i];
+        return mk<T>(va ? xa : T(0), vb ? xb : T(0));
+    });
     const int base = lp * PL;
     auto lidx = [base](int pos) { return base + padpos(pos); };
     fwd_stages<T, P, PN, 0>(v, lds, tl, tws, lidx);
@@ -469,13 +461,10 @@ void k_strided(
         }
         adj_stages<T, P, PN, L - 1>(v, lds, tl, tws, lidx);
     } else {
-#pragma unroll
-        for (int j = 0; j < E; ++j) {
-            const int pos = in_pos<P, PN, 0>(tl, j);
-            const bool in = pos < n_in;
-            const C2<T> x = src[(in ? pos : 0) * st.line];
-            v[j] = (valid && in) ? x : mk<T>(0, 0);
-        }
+        load_line<T, P, PN>(v, tl, n_in, [&](int i) {
+            const C2<T> x = src[i * st.line];
+            return valid ? x : mk<T>(T(0), T(0));
+        });
         if constexpr (MODE == 2) {
             // lambda at this thread's spectral positions, fetched with the data
             T lv[E];
@@ -570,15 +559,16 @@ static void launch_strided(const C2<T> *in, C2<T> *out, int ncols, int nouter, i
 }
 
 template <typename T, int P, int E, int LPB>
-static void launch_conv1d(const T *u, T *y, int nrows, int n, const T *lam, const C2<T> *tw, const Epi<T> &ep,
-                          const double *done, hipStream_t s, const hipEvent_t *ev, int nb, BatchStrides bz) {
+static void launch_conv1d(const T *u, T *y, int nrows, int n, int n_in, const T *lam, const C2<T> *tw,
+                          const Epi<T> &ep, const double *done, hipStream_t s, const hipEvent_t *ev, int nb,
+                          BatchStrides bz) {
     const int pairs = (nrows + 1) / 2;
     if (ep.active())
         launch(k_conv1d<T, P, E, LPB, true>, dim3(cdiv(pairs, LPB), 1, nb), dim3(LPB * (P / E)), s, ev, u, y, nrows,
-               n, lam, tw, ep, done, bz);
+               n, n_in, lam, tw, ep, done, bz);
     else
         launch(k_conv1d<T, P, E, LPB, false>, dim3(cdiv(pairs, LPB), 1, nb), dim3(LPB * (P / E)), s, ev, u, y,
-               nrows, n, lam, tw, ep, done, bz);
+               nrows, n, n_in, lam, tw, ep, done, bz);
 }
 
 // ---------------------------------------------------------------------------
@@ -624,25 +614,29 @@ static void matvec_v(const MvCtx<T> &cx, const T *u, T *y, const Epi<T> &ep, con
     const long zt1 = cx.zs_t1 / (long)sizeof(C2<T>), zt2 = cx.zs_t2 / (long)sizeof(C2<T>);
     auto E = [&](int i) { return ev ? ev + 2 * i : nullptr; };
     BatchStrides b_in{cx.zs_vec, zt1, 0, cx.zs_done};
+    // values read per line by the forward passes: zero-padded, or (odd) the odd
+    // extension of the sine-transform preconditioner
+    const int ix = cx.odd ? -nx : nx, iy = cx.odd ? -ny : ny, iz = cx.odd ? -nz : nz;
     if constexpr (D == 1) {
-        (void)T1; (void)T2; (void)nt; (void)ny; (void)nz; (void)Q; (void)zt2; (void)b_in;
-        launch_conv1d<T, P, EX, LPB>(u, y, 1, nx, lam, tw, ep, done, s, E(0), nb,
+        (void)T1; (void)T2; (void)nt; (void)ny; (void)nz; (void)Q; (void)zt2; (void)b_in; (void)iy; (void)iz;
+        launch_conv1d<T, P, EX, LPB>(u, y, 1, nx, ix, lam, tw, ep, done, s, E(0), nb,
                                      BatchStrides{cx.zs_vec, cx.zs_vec, cx.zs_lam, cx.zs_done});
     } else if constexpr (D == 2) {
-        launch_xfwd<T, P, EX, C, LPB, true>(u, T1, ny, nx, nx, ny, nt, tw, done, s, E(0), nb, b_in);
+        (void)iz;
+        launch_xfwd<T, P, EX, C, LPB, true>(u, T1, ny, ix, nx, ny, nt, tw, done, s, E(0), nb, b_in);
         Strides sy{0, ny * C, 0, ny * C, C, Q * C, 0, nt * Q * C};
-        launch_strided<T, P, EY, C, 2, true>(T1, T1, P / 2, 1, ny, ny, sy, tw, lam, done, s, E(1), nb,
+        launch_strided<T, P, EY, C, 2, true>(T1, T1, P / 2, 1, iy, ny, sy, tw, lam, done, s, E(1), nb,
                                              BatchStrides{zt1, zt1, cx.zs_lam, cx.zs_done});
         launch_xinv<T, P, EX, C, LPB, true>(T1, y, ny, nx, nx, ny, nt, tw, ep, done, s, E(2), nb,
                                             BatchStrides{zt1, cx.zs_vec, 0, cx.zs_done});
     } else {
         const long rows = (long)ny * nz;
-        launch_xfwd<T, P, EX, C, LPB>(u, T1, (int)rows, nx, nx, ny, nt, tw, done, s, E(0), nb, b_in);
+        launch_xfwd<T, P, EX, C, LPB>(u, T1, (int)rows, ix, nx, ny, nt, tw, done, s, E(0), nb, b_in);
         Strides s1{nt * ny * C, ny * C, nt * P * C, P * C, C, 0, 0};
-        launch_strided<T, P, EY, C, 0>(T1, T2, Q, nz, ny, P, s1, tw, nullptr, done, s, E(1), nb,
+        launch_strided<T, P, EY, C, 0>(T1, T2, Q, nz, iy, P, s1, tw, nullptr, done, s, E(1), nb,
                                        BatchStrides{zt1, zt2, 0, cx.zs_done});
         Strides s2{C, P * C, C, P * C, nt * P * C, Q * Q * C, Q * C};
-        launch_strided<T, P, EY, C, 2>(T2, T2, Q, P, nz, nz, s2, tw, lam, done, s, E(2), nb,
+        launch_strided<T, P, EY, C, 2>(T2, T2, Q, P, iz, nz, s2, tw, lam, done, s, E(2), nb,
                                        BatchStrides{zt2, zt2, cx.zs_lam, cx.zs_done});
         Strides s3{nt * P * C, P * C, nt * ny * C, ny * C, C, 0, 0};
         launch_strided<T, P, EY, C, 1>(T2, T1, Q, nz, P, ny, s3, tw, nullptr, done, s, E(3), nb,
@@ -879,12 +873,29 @@ VariantDesc variant_desc(fl_op op, int prec, int k) {
     return k >= 0 && k < n ? v[k].desc : VariantDesc{0, 0, 0, 0};
 }
 
-// tiled lambda for the fused pass: 1D natural order, 2D [t][ky][c], 3D [t][ky][kz][c]; zero past
-// the stored columns.  2D (packed columns): column 0 holds (lambda_0 +
-// lambda_{P/2}) / 2 and Q more entries after the tiles hold
-// (lambda_0 - lambda_{P/2}) / 2, per ky.
+// value of the tiled symbol at natural-order entry i (frequency kx, ky, kz):
+// lambda itself, or (tau) the sine-transform preconditioner's 1 / (s0 + s1 lambda)
+// on the sine modes (no index 0 or P/2 on any axis) and 0 elsewhere, both with
+// the inverse transform's 1 / P^d
+struct SymMap {
+    int tau = 0;
+    double s0 = 0.0, s1 = 1.0;
+    double Pd = 1.0;  // P^d
+};
+__device__ __forceinline__ double sym_at(const double *__restrict__ lam64, long i, int kx, int ky, int kz, int d,
+                                         int N2, const SymMap &m) {
+    const double l = lam64[i];
+    if (!m.tau) return l;
+    const bool sine = kx != 0 && kx != N2 && (d < 2 || (ky != 0 && ky != N2)) && (d < 3 || (kz != 0 && kz != N2));
+    return sine ? 1.0 / ((m.s0 + m.s1 * (l * m.Pd)) * m.Pd) : 0.0;
+}
+
+// tiled symbol for the fused pass: 1D natural order, 2D [t][ky][c], 3D [t][ky][kz][c]; zero past
+// the stored columns.  2D (packed columns): column 0 holds (s_0 + s_{P/2}) / 2
+// and Q more entries after the tiles hold (s_0 - s_{P/2}) / 2, per ky.
 template <typename T>
-__global__ void k_tile_lambda(const double *__restrict__ lam64, T *__restrict__ lt, int d, int Q, int C, int ntiles) {
+__global__ void k_tile_lambda(const double *__restrict__ lam64, T *__restrict__ lt, int d, int Q, int C, int ntiles,
+                              SymMap m) {
     const long tiles = d == 1 ? (long)Q : d == 2 ? (long)ntiles * Q * C : (long)ntiles * Q * Q * C;
     const long total = d == 2 ? tiles + Q : tiles;
     const int N2 = Q - 1;  // P / 2
@@ -894,24 +905,46 @@ __global__ void k_tile_lambda(const double *__restrict__ lam64, T *__restrict__ 
         long rest = idx / C;
         double v = 0.0;
         if (d == 1) {
-            v = lam64[idx];
+            v = sym_at(lam64, idx, (int)idx, 0, 0, 1, N2, m);
         } else if (d == 2 && idx >= tiles) {
-            const long ky = idx - tiles;
-            v = 0.5 * (lam64[ky * Q] - lam64[ky * Q + N2]);
+            const int ky = (int)(idx - tiles);
+            v = 0.5 * (sym_at(lam64, (long)ky * Q, 0, ky, 0, 2, N2, m) -
+                       sym_at(lam64, (long)ky * Q + N2, N2, ky, 0, 2, N2, m));
         } else if (d == 2) {
-            const long ky = rest % Q, t = rest / Q;
-            const long kx = t * C + c;
-            if (kx == 0) v = 0.5 * (lam64[ky * Q] + lam64[ky * Q + N2]);
-            else if (kx < N2) v = lam64[ky * Q + kx];
+            const int ky = (int)(rest % Q), t = (int)(rest / Q);
+            const int kx = t * C + c;
+            if (kx == 0)
+                v = 0.5 * (sym_at(lam64, (long)ky * Q, 0, ky, 0, 2, N2, m) +
+                           sym_at(lam64, (long)ky * Q + N2, N2, ky, 0, 2, N2, m));
+            else if (kx < N2)
+                v = sym_at(lam64, (long)ky * Q + kx, kx, ky, 0, 2, N2, m);
         } else {
-            const long kz = rest % Q;
+            const int kz = (int)(rest % Q);
             rest /= Q;
-            const long ky = rest % Q, t = rest / Q;
-            const long kx = t * C + c;
-            if (kx < Q) v = lam64[(kz * Q + ky) * Q + kx];
+            const int ky = (int)(rest % Q), t = (int)(rest / Q);
+            const int kx = t * C + c;
+            if (kx < Q) v = sym_at(lam64, ((long)kz * Q + ky) * Q + kx, kx, ky, kz, 3, N2, m);
         }
         lt[idx] = (T)v;
     }
+}
+
+// bad <- 1 where s0 + s1 lambda is not positive and finite on a sine mode
+__global__ void k_tau_check(const double *__restrict__ lam64, int d, int Q, SymMap m, int *bad) {
+    const long total = d == 1 ? (long)Q : d == 2 ? (long)Q * Q : (long)Q * Q * Q;
+    const int N2 = Q - 1;
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (long)gridDim.x * blockDim.x) {
+        const int kx = (int)(idx % Q), ky = d > 1 ? (int)((idx / Q) % Q) : 1, kz = d > 2 ? (int)(idx / Q / Q) : 1;
+        const bool sine = kx != 0 && kx != N2 && ky != 0 && ky != N2 && kz != 0 && kz != N2;
+        if (!sine) continue;
+        const double den = m.s0 + m.s1 * (lam64[idx] * m.Pd);
+        if (!(den > 0.0) || !std::isfinite(den)) *bad = 1;
+    }
+}
+
+__global__ void k_set_int(int *p, int v) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p = v;
 }
 
 // lambda of one operator tiled to width C into lt (FP32 or FP64)
@@ -920,9 +953,11 @@ fl_status tile_lambda(fl_op op, int prec, int C, void *lt, hipStream_t s) {
     const long len = lam_tiled_len(op->d, op->P, C);
     const int g = cdiv(len, 256) > 65536 ? 65536 : cdiv(len, 256);
     if (prec == FL_FP32)
-        hipLaunchKernelGGL(k_tile_lambda<float>, dim3(g), dim3(256), 0, s, op->lam64, (float *)lt, op->d, Q, C, nt);
+        hipLaunchKernelGGL(k_tile_lambda<float>, dim3(g), dim3(256), 0, s, op->lam64, (float *)lt, op->d, Q, C, nt,
+                           SymMap{});
     else
-        hipLaunchKernelGGL(k_tile_lambda<double>, dim3(g), dim3(256), 0, s, op->lam64, (double *)lt, op->d, Q, C, nt);
+        hipLaunchKernelGGL(k_tile_lambda<double>, dim3(g), dim3(256), 0, s, op->lam64, (double *)lt, op->d, Q, C, nt,
+                           SymMap{});
     FL_HIP_TRY(hipGetLastError());
     return FL_OK;
 }
@@ -939,14 +974,97 @@ fl_status select_variant(fl_op op, int prec, int k, hipStream_t s) {
     const long len = lam_tiled_len(op->d, op->P, vd.c);
     const int g = cdiv(len, 256) > 65536 ? 65536 : cdiv(len, 256);
     if (prec == FL_FP32)
-        hipLaunchKernelGGL(k_tile_lambda<float>, dim3(g), dim3(256), 0, s, op->lam64, op->lam32t, op->d, Q, vd.c, nt);
+        hipLaunchKernelGGL(k_tile_lambda<float>, dim3(g), dim3(256), 0, s, op->lam64, op->lam32t, op->d, Q, vd.c, nt,
+                           SymMap{});
     else
         hipLaunchKernelGGL(k_tile_lambda<double>, dim3(g), dim3(256), 0, s, op->lam64, op->lam64t, op->d, Q, vd.c,
-                           nt);
+                           nt, SymMap{});
     FL_HIP_TRY(hipGetLastError());
     if (prec == FL_FP32) op->var32 = k;
     else op->var64 = k;
     return FL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// sine-transform (tau) preconditioner of K = s0 I + s1 A on the square or cube.
+// The n = P/2 - 1 nodes per axis make the sine vectors sin(pi j k / (n + 1))
+// eigenvectors of every matrix S diag(mu) S; with mu the circulant symbol of
+// K at the sine frequencies this is the tau-class matrix of K (K minus its two
+// Hankel corrections).  Its inverse applied to r is the circulant of symbol
+// 1 / mu on the odd extension of r, cropped: the matvec's passes with the
+// odd loads and the inverted symbol.
+// ---------------------------------------------------------------------------
+bool tau_supported(const fl_op_s *op) {
+    if (large_op(op)) return false;
+    for (int k = 0; k < op->d; ++k)
+        if (op->nk[k] != op->P / 2 - 1) return false;
+    return true;
+}
+
+fl_status tau_prepare(fl_op op, double s0, double s1, hipStream_t s) {
+    if (!tau_supported(op)) {
+        set_error("the sine-transform preconditioner needs a square or cubic operator with FFT length <= %d",
+                  kMaxLdsP);
+        return FL_E_UNSUPPORTED;
+    }
+    if (!(s0 >= 0.0) || !(s1 >= 0.0) || !(s0 + s1 > 0.0) || !std::isfinite(s0) || !std::isfinite(s1)) {
+        set_error("preconditioner of s0 I + s1 A needs s0, s1 >= 0, not both 0");
+        return FL_E_INVAL;
+    }
+    if (op->mu64t && op->mu_var == op->var64 && op->mu_s0 == s0 && op->mu_s1 == s1) return FL_OK;
+    const int d = op->d, Q = op->Q;
+    if (!op->mu64t) {
+        long qrest = 1;
+        for (int k = 1; k < d; ++k) qrest *= Q;
+        const long len = qrest * (Q + kMaxTile - 1);
+        hipError_t e = hipMalloc((void **)&op->mu64t, sizeof(double) * len);
+        if (e != hipSuccess) {
+            op->mu64t = nullptr;
+            set_error("preconditioner symbol: %s", hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? FL_E_NOMEM : FL_E_DEVICE;
+        }
+    }
+    SymMap m;
+    m.tau = 1;
+    m.s0 = s0;
+    m.s1 = s1;
+    m.Pd = std::pow((double)op->P, d);
+    // positivity on the sine modes (the workspace T1 holds the flag)
+    int *bad = (int *)op->T1;
+    const long ql = d == 1 ? (long)Q : d == 2 ? (long)Q * Q : (long)Q * Q * Q;
+    const int g = cdiv(ql, 256) > 65536 ? 65536 : cdiv(ql, 256);
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, bad, 0);
+    hipLaunchKernelGGL(k_tau_check, dim3(g), dim3(256), 0, s, op->lam64, d, Q, m, bad);
+    int hbad = 0;
+    FL_HIP_TRY(hipGetLastError());
+    FL_HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    FL_HIP_TRY(hipStreamSynchronize(s));
+    if (hbad) {
+        op->mu_var = -1;
+        set_error("s0 + s1 lambda is not positive on every sine mode: no sine-transform preconditioner");
+        return FL_E_BREAKDOWN;
+    }
+    const VariantDesc vd = variant_desc(op, FL_FP64, op->var64);
+    const int nt = cdiv(spec_cols(d, op->P), vd.c);
+    const long len = lam_tiled_len(d, op->P, vd.c);
+    const int gt = cdiv(len, 256) > 65536 ? 65536 : cdiv(len, 256);
+    hipLaunchKernelGGL(k_tile_lambda<double>, dim3(gt), dim3(256), 0, s, op->lam64, op->mu64t, d, Q, vd.c, nt, m);
+    FL_HIP_TRY(hipGetLastError());
+    op->mu_var = op->var64;
+    op->mu_s0 = s0;
+    op->mu_s1 = s1;
+    return FL_OK;
+}
+
+fl_status tau_apply(fl_op op, const double *r, double *z, const double *done, hipStream_t s) {
+    if (!op->mu64t || op->mu_var != op->var64) {
+        set_error("sine-transform preconditioner not prepared for the selected kernel variant");
+        return FL_E_INVAL;
+    }
+    MvCtx<double> cx = single_ctx<double>(op);
+    cx.lam = op->mu64t;
+    cx.odd = true;
+    return matvec_ctx<double>(cx, op->var64, r, z, Epi<double>{}, done, s);
 }
 
 // ---------------------------------------------------------------------------

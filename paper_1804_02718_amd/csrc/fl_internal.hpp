@@ -168,6 +168,59 @@ template <int P, typename PL, int S> __device__ __forceinline__ int out_pos(int 
     return (b / Ns) * Ns * R + (b % Ns) + (j % R) * Ns;
 }
 
+// First-stage inputs v[j] (positions in_pos<0>) of a forward transform: a line
+// of stored values extended to period P, ld(i) returning stored value i (i is
+// always a valid index).  A thread's slot j lies below P/2 exactly when
+// j mod R[0] < R[0]/2, so the half a slot falls in is known at compile time.
+//   n_in > P/2        zero past n_in;
+//   0 <= n_in <= P/2  zero-padded: the upper half is zero and is not loaded;
+//   n_in < 0          odd extension about -1 of n = -n_in = P/2 - 1 values:
+//                     x[p] for p < n, -x[P - 2 - p] for P/2 <= p <= P - 2,
+//                     zero at p = n and p = P - 1.  Its transform holds only
+//                     the sine modes (the Dirichlet sine basis of n points).
+template <typename T, int P, typename PL, typename Ld>
+__device__ __forceinline__ void load_line(C2<T> *v, int tl, int n_in, Ld ld) {
+    constexpr int R = PL::R[0], E = PL::E;
+    static_assert(R >= 2 && R % 2 == 0, "first radix must be even");
+    const C2<T> zero = mk<T>(T(0), T(0));
+    if (n_in < 0) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int pos = in_pos<P, PL, 0>(tl, j);
+            if ((j % R) < R / 2) {
+                const bool ok = pos < -n_in;
+                const C2<T> x = ld(ok ? pos : 0);
+                v[j] = ok ? x : zero;
+            } else {
+                const int src = P - 2 - pos;
+                const bool ok = src >= 0;
+                const C2<T> x = ld(ok ? src : 0);
+                v[j] = ok ? mk<T>(-x.x, -x.y) : zero;
+            }
+        }
+    } else if (n_in <= P / 2) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            if ((j % R) < R / 2) {
+                const int pos = in_pos<P, PL, 0>(tl, j);
+                const bool ok = pos < n_in;
+                const C2<T> x = ld(ok ? pos : 0);
+                v[j] = ok ? x : zero;
+            } else {
+                v[j] = zero;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int pos = in_pos<P, PL, 0>(tl, j);
+            const bool ok = pos < n_in;
+            const C2<T> x = ld(ok ? pos : 0);
+            v[j] = ok ? x : zero;
+        }
+    }
+}
+
 // every twiddle a thread uses, loaded once from the table exp(-2 pi i m / P)
 template <typename T, int P, typename PL, int S = 1>
 __device__ __forceinline__ void load_twiddles(C2<T> *tws, const C2<T> *__restrict__ table, int tl) {
@@ -276,6 +329,11 @@ struct fl_op_s {
     double *scal = nullptr;       // device scalars of the solvers
     double *hscal = nullptr;      // pinned host mirror
     fl_unet net = nullptr;        // learned preconditioner (not owned)
+    // sine-transform preconditioner of s0 I + s1 A: its symbol, tiled like lam64t
+    // for FP64 variant mu_var (allocated on first use)
+    double *mu64t = nullptr;
+    double mu_s0 = 0.0, mu_s1 = 0.0;
+    int mu_var = -1;
 };
 
 namespace fl {
@@ -313,6 +371,7 @@ template <typename T> struct MvCtx {
     void *T1 = nullptr, *T2 = nullptr;
     const C2<T> *tw = nullptr;
     const T *lam = nullptr;
+    bool odd = false;          // forward loads take the odd extension (sine-transform preconditioner)
     int batch = 1;
     long zs_vec = 0;           // elements between problems' vectors
     long zs_t1 = 0, zs_t2 = 0; // bytes between problems' workspaces
@@ -347,6 +406,13 @@ inline long lam_tiled_len(int d, int P, int C) {
     return d == 1 ? Q : d == 2 ? nt * C * Q + Q : nt * C * Q * Q;
 }
 fl_status select_variant(fl_op op, int prec, int k, hipStream_t s);
+// sine-transform preconditioner of s0 I + s1 A (square or cubic operators with
+// FFT length <= kMaxLdsP): tau_prepare builds its FP64 symbol for the selected
+// FP64 variant (FL_E_BREAKDOWN when s0 + s1 lambda is not positive on a sine
+// mode); tau_apply computes z = M^{-1} r in FP64 (a set `done` flag skips it)
+bool tau_supported(const fl_op_s *op);
+fl_status tau_prepare(fl_op op, double s0, double s1, hipStream_t s);
+fl_status tau_apply(fl_op op, const double *r, double *z, const double *done, hipStream_t s);
 constexpr int kMaxTile = 16;  // largest tile width of any variant
 // longest FFT whose line a workgroup keeps in LDS; longer 2D embeddings (up to
 // 16384) take the global-memory passes of the large-operator path

@@ -237,7 +237,7 @@ static inline int ew_grid(long n) {
 // solver workspace
 // ---------------------------------------------------------------------------
 struct Work {
-    double *r64, *p64, *kp64, *d64, *b64;
+    double *r64, *p64, *kp64, *d64, *b64, *q64;
     float *r32, *p32, *kp32, *d32;
     double *partA, *partB;
 };
@@ -251,7 +251,8 @@ static Work work_of(fl_op op) {
     w.kp64 = w.p64 + M;
     w.d64 = w.kp64 + M;
     w.b64 = w.d64 + M;
-    w.partA = w.b64 + M;
+    w.q64 = w.b64 + M;
+    w.partA = w.q64 + M;
     w.partB = w.partA + kMaxParts;
     float *f = (float *)(w.partB + kMaxParts);
     w.r32 = f;
@@ -273,7 +274,7 @@ void free_solver_workspace(fl_op op) {
 static fl_status ensure_workspace(fl_op op) {
     if (op->sw) return FL_OK;
     const long M = op->M;
-    size_t bytes = sizeof(double) * (5 * M + 2 * kMaxParts) + sizeof(float) * (4 * M + 64);
+    size_t bytes = sizeof(double) * (6 * M + 2 * kMaxParts) + sizeof(float) * (4 * M + 64);
     FL_HIP_TRY(hipMalloc(&op->sw, bytes));
     op->sw_bytes = bytes;
     FL_HIP_TRY(hipMalloc((void **)&op->scal, sizeof(double) * S_COUNT));
@@ -574,17 +575,30 @@ __global__ __launch_bounds__(kVecBlock) void k_fpcg_dir(double *__restrict__ p, 
     for (long i = beg + threadIdx.x; i < end; i += kVecBlock) p[i] = z[i] + be * p[i];
 }
 
-// Flexible PCG (Notay's flexible CG with the Polak--Ribiere beta) with the
-// learned preconditioner z = ||r|| Net(r/||r||, alpha).  Falls back to plain
-// FP64 CG from the current iterate when (r, z) <= 0, a scalar is not finite,
-// or the residual stops decreasing.
-static fl_status fpcg(fl_op op, const double *f, double *x, double tol, int max_iter, fl_info *info,
-                      hipStream_t s) {
+// preconditioners of the flexible PCG
+enum : int {
+    PREC_NET = 0,  // learned: z = ||r|| Net(r / ||r||, alpha)
+    PREC_TAU = 1   // sine-transform (tau) preconditioner of K, prepared by tau_prepare
+};
+
+// z = M r; `done` (optional) turns the application into a no-op once set
+static fl_status apply_prec(fl_op op, int kind, const double *r, double *z, const double *done, hipStream_t s) {
+    if (kind == PREC_TAU) return tau_apply(op, r, z, done, s);
+    return unet_apply(op->net, r, op->n, op->alpha, z, op->scal + S_FRR, s);
+}
+
+// Flexible PCG (Notay's flexible CG with the Polak--Ribiere beta) on
+// K x = f, K = s0 I + s1 A, x holding the initial guess, with the learned or
+// the sine-transform preconditioner.  Falls back to plain FP64 CG from the
+// current iterate when (r, z) <= 0, a scalar is not finite, or the residual
+// stops decreasing.
+static fl_status fpcg(fl_op op, int kind, double s0, double s1, const double *f, double *x, double tol,
+                      int max_iter, fl_info *info, hipStream_t s) {
     FL_TRY(ensure_workspace(op));
     Work w = work_of(op);
     const long M = op->M;
     VecLayout L = layout(M);
-    double *r = w.r64, *z = w.d64, *p = w.p64, *kp = w.kp64, *rold = w.b64;
+    double *r = w.r64, *z = w.d64, *p = w.p64, *kp = w.kp64, *rold = w.q64;
     double bb = 0.0;
     FL_TRY(dot<double>(op, f, f, w.partA, &bb, s));
     const double bn = std::sqrt(bb);
@@ -594,13 +608,13 @@ static fl_status fpcg(fl_op op, const double *f, double *x, double tol, int max_
         FL_HIP_TRY(hipStreamSynchronize(s));
         return FL_OK;
     }
-    // r = f - A x; (r, r) into S_FRR for the network's scaling; z = M r; (r, z); p = z
-    FL_TRY(residual64(op, f, x, r, 0.0, 1.0, s));
+    // r = f - K x; (r, r) into S_FRR for the network's scaling; z = M r; (r, z); p = z
+    FL_TRY(residual64(op, f, x, r, s0, s1, s));
     double *scal = op->scal;
     const double *done = scal + S_DONE;
     hipLaunchKernelGGL(k_dot<double>, dim3(L.blocks), dim3(kVecBlock), 0, s, r, r, L.n, L.chunk, w.partA, nullptr);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(kVecBlock), 0, s, w.partA, L.blocks, scal, (int)S_FRR);
-    FL_TRY(unet_apply(op->net, r, op->n, op->alpha, z, scal + S_FRR, s));
+    FL_TRY(apply_prec(op, kind, r, z, nullptr, s));
     hipLaunchKernelGGL(k_dot<double>, dim3(L.blocks), dim3(kVecBlock), 0, s, r, z, L.n, L.chunk, w.partB, nullptr);
     hipLaunchKernelGGL(k_fpcg_init, dim3(1), dim3(kVecBlock), 0, s, w.partA, w.partB, L.blocks, scal,
                        tol * tol * bb);
@@ -610,7 +624,7 @@ static fl_status fpcg(fl_op op, const double *f, double *x, double tol, int max_
     const int np_x = xinv_parts(op->d, (long)(op->M / op->nk[0]), op->P, FL_FP64, op->var64);
     const bool fused = np_x > 0 && np_x <= kMaxParts;
     // scalars stay on the device; the host reads them every kCheck iterations
-    // (the network does not test the done flag, so at most kCheck - 1
+    // (the network does not test the done flag, so at most kCheck - 1 of its
     // applications follow convergence)
     constexpr int kCheck = 4;
     int launched = 0;
@@ -619,14 +633,14 @@ static fl_status fpcg(fl_op op, const double *f, double *x, double tol, int max_
         const int k = kCheck < max_iter - launched ? kCheck : max_iter - launched;
         for (int i = 0; i < k; ++i) {
             const int parity = (launched + i) & 1;
-            FL_TRY(apply_K<double>(op, p, kp, 0.0, 1.0, done, s, fused ? w.partA : nullptr));
+            FL_TRY(apply_K<double>(op, p, kp, s0, s1, done, s, fused ? w.partA : nullptr));
             if (!fused)
                 hipLaunchKernelGGL(k_dot<double>, dim3(L.blocks), dim3(kVecBlock), 0, s, p, kp, L.n, L.chunk,
                                    w.partA, done);
             hipLaunchKernelGGL(k_fpcg_xr, dim3(L.blocks), dim3(kVecBlock), 0, s, x, r, rold, p, kp, L.n, L.chunk,
                                w.partA, fused ? np_x : L.blocks, w.partB, scal, parity);
             hipLaunchKernelGGL(k_fpcg_rr, dim3(1), dim3(kVecBlock), 0, s, w.partB, L.blocks, scal);
-            FL_TRY(unet_apply(op->net, r, op->n, op->alpha, z, scal + S_FRR, s));
+            FL_TRY(apply_prec(op, kind, r, z, done, s));
             hipLaunchKernelGGL(k_fpcg_dot2, dim3(L.blocks), dim3(kVecBlock), 0, s, r, z, rold, L.n, L.chunk,
                                w.partA, w.partB, done);
             hipLaunchKernelGGL(k_fpcg_dir, dim3(L.blocks), dim3(kVecBlock), 0, s, p, z, L.n, L.chunk, w.partA,
@@ -653,7 +667,7 @@ static fl_status fpcg(fl_op op, const double *f, double *x, double tol, int max_
     }
     if (!fallback) {
         // verify with a fresh FP64 residual
-        FL_TRY(residual64(op, f, x, r, 0.0, 1.0, s));
+        FL_TRY(residual64(op, f, x, r, s0, s1, s));
         double rr = 0.0;
         FL_TRY(dot<double>(op, r, r, w.partA, &rr, s));
         info->relres = std::sqrt(rr) / bn;
@@ -664,7 +678,7 @@ static fl_status fpcg(fl_op op, const double *f, double *x, double tol, int max_
     // plain FP64 CG from the current iterate
     info->fell_back = 1;
     fl_info sub{};
-    fl_status st = refine(op, 0.0, 1.0, f, x, tol, true, 0.0, max_iter, 0, &sub, s);
+    fl_status st = refine(op, s0, s1, f, x, tol, true, 0.0, max_iter, 0, &sub, s);
     info->iters += sub.iters;
     info->outer_iters += sub.outer_iters;
     info->relres = sub.relres;
@@ -688,7 +702,11 @@ fl_status fl_poisson_solve_ex(fl_op op, const double *f, double tol, double *u, 
     if (f == u) { set_error("f and u must differ"); return FL_E_INVAL; }
     fl_solve_opts o = {FL_SOLVE_AUTO, 0, 0, 0, 0.0};
     if (opts) o = *opts;
-    if (o.solver < FL_SOLVE_AUTO || o.solver > FL_SOLVE_FPCG) { set_error("unknown solver"); return FL_E_INVAL; }
+    if (o.solver < FL_SOLVE_AUTO || o.solver > FL_SOLVE_TAU) { set_error("unknown solver"); return FL_E_INVAL; }
+    if (o.solver == FL_SOLVE_TAU && !tau_supported(op)) {
+        set_error("TAU needs a square or cubic operator with FFT length <= %d", kMaxLdsP);
+        return FL_E_INVAL;
+    }
     if (o.solver == FL_SOLVE_FPCG && (!op->net || op->d != 2 || op->n > unet_size(op->net) ||
                                       op->nk[0] != op->n || op->nk[1] != op->n)) {
         set_error("FPCG needs a learned preconditioner attached to a 2D square operator with n <= its grid size");
@@ -703,15 +721,29 @@ fl_status fl_poisson_solve_ex(fl_op op, const double *f, double tol, double *u, 
         hipLaunchKernelGGL(k_zero<double>, dim3(ew_grid(op->M)), dim3(256), 0, s, u, op->M);
     }
     const int max_iter = o.max_iter > 0 ? o.max_iter : default_max_iter(op);
-    // AUTO: FP32-matvec refinement up to alpha = 1.25, FP64 CG above.  Each refinement
-    // step restarts CG, and for the stiffer operators the restarts cost more iterations
-    // than the cheaper FP32 matvec saves (2D N = 1024 to 1e-8: refinement 5-10 % faster
-    // at alpha <= 1, 7 % and 16 % slower at alpha = 1.5 and 1.9)
-    const bool inner64 = o.solver == FL_SOLVE_CG64 || (o.solver == FL_SOLVE_AUTO && op->alpha > 1.25);
-    const double itol = o.inner_tol > 0.0 ? o.inner_tol : 1e-3;
-    fl_status st = o.solver == FL_SOLVE_FPCG ? fpcg(op, f, u, tol, max_iter, inf, s)
-                                             : refine(op, 0.0, 1.0, f, u, tol, inner64, itol, max_iter,
-                                                      o.check_every, inf, s);
+    fl_status st = FL_OK;
+    bool solved = false;
+    // AUTO: the sine-transform preconditioned CG wherever it applies (square and
+    // cubic operators; a handful of iterations at every size, against hundreds
+    // for CG at alpha >= 1)
+    if (o.solver == FL_SOLVE_TAU || (o.solver == FL_SOLVE_AUTO && tau_supported(op))) {
+        st = tau_prepare(op, 0.0, 1.0, s);
+        if (st == FL_OK) st = fpcg(op, PREC_TAU, 0.0, 1.0, f, u, tol, max_iter, inf, s);
+        // AUTO without a positive symbol on the sine modes takes the plain solvers
+        solved = st == FL_OK || o.solver == FL_SOLVE_TAU || st != FL_E_BREAKDOWN;
+    }
+    if (!solved && o.solver == FL_SOLVE_FPCG) {
+        st = fpcg(op, PREC_NET, 0.0, 1.0, f, u, tol, max_iter, inf, s);
+    } else if (!solved) {
+        // otherwise FP32-matvec refinement up to alpha = 1.25, FP64 CG above.  Each
+        // refinement step restarts CG, and for the stiffer operators the restarts cost
+        // more iterations than the cheaper FP32 matvec saves (2D N = 1024 to 1e-8:
+        // refinement 5-10 % faster at alpha <= 1, 7 % and 16 % slower at alpha = 1.5 and 1.9)
+        const bool inner64 = o.solver == FL_SOLVE_CG64 || (o.solver == FL_SOLVE_AUTO && op->alpha > 1.25);
+        const double itol = o.inner_tol > 0.0 ? o.inner_tol : 1e-3;
+        *inf = fl_info{};
+        st = refine(op, 0.0, 1.0, f, u, tol, inner64, itol, max_iter, o.check_every, inf, s);
+    }
     inf->status = st;
     inf->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return st;
@@ -735,8 +767,12 @@ fl_status fl_allen_cahn_step_gen(fl_op op, double *u, double tau, double kappa, 
     if (!std::isfinite(gamma) || !std::isfinite(shift)) { set_error("gamma and shift must be finite"); return FL_E_INVAL; }
     if (!(theta > 0.0 && theta <= 1.0)) { set_error("theta must lie in (0,1]"); return FL_E_INVAL; }
     if (!(tol > 0.0)) { set_error("tol must be positive"); return FL_E_INVAL; }
-    if (solver != FL_SOLVE_AUTO && solver != FL_SOLVE_REFINE && solver != FL_SOLVE_CG64) {
-        set_error("solver must be AUTO, REFINE or CG64");
+    if (solver != FL_SOLVE_AUTO && solver != FL_SOLVE_REFINE && solver != FL_SOLVE_CG64 && solver != FL_SOLVE_TAU) {
+        set_error("solver must be AUTO, REFINE, CG64 or TAU");
+        return FL_E_INVAL;
+    }
+    if (solver == FL_SOLVE_TAU && !tau_supported(op)) {
+        set_error("TAU needs a square or cubic operator with FFT length <= %d", kMaxLdsP);
         return FL_E_INVAL;
     }
     fl_info local;
@@ -752,9 +788,19 @@ fl_status fl_allen_cahn_step_gen(fl_op op, double *u, double tau, double kappa, 
     hipLaunchKernelGGL(k_ac_rhs, dim3(ew_grid(op->M)), dim3(256), 0, s, u, w.kp64, w.b64, w.r64, op->M, tau, sc,
                        theta, gamma, shift);
     FL_HIP_TRY(hipGetLastError());
-    // (I + theta s A) u+ = b, initial guess u, whose residual k_ac_rhs left in r64
-    fl_status st = refine(op, 1.0, theta * sc, w.b64, u, tol, solver == FL_SOLVE_CG64, 1e-4,
-                          default_max_iter(op), 0, inf, s, true);
+    // (I + theta s A) u+ = b, initial guess u: the sine-transform preconditioned CG
+    // (TAU, and AUTO where it applies), else CG or FP32-matvec refinement
+    fl_status st = FL_OK;
+    bool solved = false;
+    if (solver == FL_SOLVE_TAU || (solver == FL_SOLVE_AUTO && tau_supported(op))) {
+        st = tau_prepare(op, 1.0, theta * sc, s);
+        if (st == FL_OK) st = fpcg(op, PREC_TAU, 1.0, theta * sc, w.b64, u, tol, default_max_iter(op), inf, s);
+        solved = st == FL_OK || solver == FL_SOLVE_TAU || st != FL_E_BREAKDOWN;
+    }
+    // the residual of the initial guess u, left in r64 by k_ac_rhs, serves refine
+    if (!solved)
+        st = refine(op, 1.0, theta * sc, w.b64, u, tol, solver == FL_SOLVE_CG64, 1e-4, default_max_iter(op), 0,
+                    inf, s, true);
     inf->status = st;
     inf->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return st;

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libfl.so")
 
 FL_OK, FL_E_INVAL, FL_E_NOMEM, FL_E_DEVICE, FL_E_NOCONV, FL_E_BREAKDOWN, FL_E_UNSUPPORTED = range(7)
 FL_FP64, FL_FP32 = 0, 1
-SOLVERS = {"auto": 0, "cg64": 1, "refine": 2, "fpcg": 3}
+SOLVERS = {"auto": 0, "cg64": 1, "refine": 2, "fpcg": 3, "tau": 4}
 
 EXPORTED = ["fl_coeffs", "fl_apply", "fl_apply_profiled", "fl_variant_count", "fl_variant_info",
             "fl_select_variant", "fl_autotune", "fl_batch_create", "fl_batch_poisson_solve", "fl_batch_info",
@@ -26,7 +26,7 @@ EXPORTED = ["fl_coeffs", "fl_apply", "fl_apply_profiled", "fl_variant_count", "f
             "fl_status_string", "fl_last_error", "fl_unet_create", "fl_unet_destroy", "fl_unet_num_params",
             "fl_unet_step", "fl_unet_get_weights", "fl_unet_set_weights", "fl_unet_apply", "fl_set_preconditioner",
             "fl_gemm_test", "fl_unet_pack", "fl_unet_train", "fl_allen_cahn_step_gen",
-            "fl_coeffs_gamma", "fl_coeffs_box"]
+            "fl_coeffs_gamma", "fl_coeffs_box", "fl_tau_apply"]
 
 
 class FlLibraryMissing(RuntimeError):
@@ -80,6 +80,7 @@ def load(path: str = LIB_PATH):
     lib.fl_coeffs_gamma.argtypes = [ip, dp, dp, dp, ip, ctypes.POINTER(vp)]
     lib.fl_coeffs_box.argtypes = [ip, dp, dp, dp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(vp)]
     lib.fl_apply.argtypes = [vp, vp, vp, ip, vp]
+    lib.fl_tau_apply.argtypes = [vp, vp, vp, dp, dp, vp]
     lib.fl_apply_profiled.argtypes = [vp, vp, vp, ip, ip, vp, ctypes.POINTER(ctypes.c_float),
                                       ctypes.POINTER(ctypes.c_int)]
     lib.fl_variant_count.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int)]
@@ -199,6 +200,14 @@ def fl_apply(op, u, y, stream=None):
         raise TypeError("u and y must both be float32 or both float64")
     _check(load().fl_apply(op, _ptr(u), _ptr(y), prec, _stream(stream)))
     return y
+
+
+def fl_tau_apply(op, r, z, s0=0.0, s1=1.0, stream=None):
+    """z = M^{-1} r, M the sine-transform (tau) preconditioner of s0 I + s1 A (float64 vectors)."""
+    import torch
+    _check(load().fl_tau_apply(op, _ptr(r, torch.float64), _ptr(z, torch.float64), float(s0), float(s1),
+                               _stream(stream)))
+    return z
 
 
 def fl_apply_profiled(op, u, y, reps, stream=None):
@@ -552,6 +561,17 @@ class Operator:
         elif y.numel() != self.M:
             raise ValueError("expected %d entries, got %d" % (self.M, y.numel()))
         return fl_apply(self._op, u, y, stream)
+
+    def tau_apply(self, r, z=None, s0=0.0, s1=1.0, stream=None):
+        """The sine-transform preconditioner of s0 I + s1 A applied to r (float64)."""
+        import torch
+        if r.numel() != self.M:
+            raise ValueError("expected %d entries, got %d" % (self.M, r.numel()))
+        if z is None:
+            z = torch.empty_like(r)
+        elif z.numel() != self.M:
+            raise ValueError("expected %d entries, got %d" % (self.M, z.numel()))
+        return fl_tau_apply(self._op, r, z, s0, s1, stream)
 
     def poisson_solve(self, f, tol=1e-8, u=None, stream=None, **kw):
         import torch

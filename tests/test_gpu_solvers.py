@@ -145,7 +145,7 @@ def test_allen_cahn_steps_vs_oracle(fl, d, N, theta, solver):
 
 
 def test_allen_cahn_default_step_tolerance(fl):
-    # default entry: theta = 1/2, FP32-matvec CG inside FP64 refinement to 1e-8
+    # default entry: theta = 1/2, the AUTO solver (here the sine-transform preconditioned CG) to 1e-8
     N, alpha, tau, eps = 64, 1.2, 1e-3, 0.05
     op = fl.Operator(2, alpha, 2.0 / N, N)
     u0 = inputs.ac_initial((N - 1) ** 2, seed=3)
