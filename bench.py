@@ -224,25 +224,38 @@ def c4_extra(torch, fl, inputs):
             "sequential_max_relres": max(i["relres"] for i in seq)}
 
 
-def poisson_extra(torch, fl, inputs, N=1024, alpha=1.5):
-    """Time-to-1e-8 relative residual for the 2D N=1024 Poisson problem, f = 8 Gaussians."""
+def poisson_extra(torch, fl, inputs, N=1024, alpha=1.5, alphas=(0.5, 1.0, 1.5, 1.9)):
+    """Time-to-1e-8 relative residual for the 2D N=1024 Poisson problem, f = 8 Gaussians: plain FP64
+    CG, FP32-matvec refinement and the sine-transform preconditioned CG (the default solver here) at
+    `alpha`, and CG against the preconditioned solve over `alphas`."""
     h = 2.0 / N
     f = torch.as_tensor(inputs.gauss_sum(2, N, 8, seed=2), dtype=torch.float64, device="cuda:0")
-    op = fl.Operator(2, alpha, h, N)
-    out = {}
-    for solver in ("cg64", "refine"):
+
+    def timed(op, solver):
         u = torch.zeros_like(f)
-        op.poisson_solve(f, tol=1e-8, u=u, solver=solver)  # warm (workspace allocation)
+        op.poisson_solve(f, tol=1e-8, u=u, solver=solver)  # warm (workspace, preconditioner symbol)
         torch.cuda.synchronize()
         u.zero_()
         t0 = time.perf_counter()
         _, info = op.poisson_solve(f, tol=1e-8, u=u, solver=solver)
         torch.cuda.synchronize()
-        out[solver] = {"seconds": time.perf_counter() - t0, "iters": info["iters"],
-                       "outer": info["outer_iters"], "relres": info["relres"]}
+        return {"seconds": time.perf_counter() - t0, "iters": info["iters"], "outer": info["outer_iters"],
+                "relres": info["relres"], "fell_back": info["fell_back"]}
+
+    op = fl.Operator(2, alpha, h, N)
+    out = {solver: timed(op, solver) for solver in ("cg64", "refine", "tau")}
     op.close()
+    sweep = []
+    for a in alphas:
+        op = fl.Operator(2, a, h, N)
+        c, t = timed(op, "cg64"), timed(op, "tau")
+        sweep.append([a, c["iters"], round(c["seconds"] * 1e3, 3), t["iters"], round(t["seconds"] * 1e3, 3),
+                      round(c["seconds"] / t["seconds"], 1)])
+        op.close()
     return {"workload": "2D N=1024 alpha=%.2f, f = sum of 8 seeded Gaussians on (-1,1)^2, tol 1e-8" % alpha,
-            **out}
+            **out, "tau_speedup_over_cg64": round(out["cg64"]["seconds"] / out["tau"]["seconds"], 1),
+            "by_alpha": sweep, "by_alpha_fields": ["alpha", "cg64_iters", "cg64_ms", "tau_iters", "tau_ms",
+                                                   "cg64_over_tau"]}
 
 
 def c5_extra(torch, fl, pairs, epochs, N=256, res_samples=2048, res_epochs=10):
@@ -308,7 +321,10 @@ def c5_extra(torch, fl, pairs, epochs, N=256, res_samples=2048, res_epochs=10):
         """Iteration and time ratios CG / FPCG over the held-out problems, overall and by alpha band,
         and the compact per-problem rows."""
         out = {"fell_back": int(sum(r["fpcg"]["fell_back"] for r in rs)),
-               "max_rel_diff_vs_cg": float(max(r["rel_diff"] for r in rs))}
+               "max_rel_diff_vs_cg": float(max(r["rel_diff"] for r in rs)),
+               "tau_mean_iters": round(float(np.mean([r["tau"]["iters"] for r in rs])), 2),
+               "fpcg_over_tau_seconds": round(float(np.mean([r["fpcg"]["seconds"] / r["tau"]["seconds"]
+                                                             for r in rs])), 2)}
         for lo, hi in ((0.3, 1.0), (1.0, 1.5), (1.5, 1.91), (0.3, 1.91)):
             sel = [r for r in rs if lo <= r["alpha"] < hi]
             if not sel:
@@ -320,9 +336,11 @@ def c5_extra(torch, fl, pairs, epochs, N=256, res_samples=2048, res_epochs=10):
                         "cg_over_fpcg_seconds": round(float(np.mean([r["cg64"]["seconds"] / r["fpcg"]["seconds"]
                                                                      for r in sel])), 3)}
         out["rows"] = [[round(r["alpha"], 4), r["fpcg"]["iters"], r["fpcg"]["fell_back"],
-                        round(r["fpcg"]["seconds"] * 1e3, 3), r["cg64"]["iters"], round(r["cg64"]["seconds"] * 1e3, 3)]
+                        round(r["fpcg"]["seconds"] * 1e3, 3), r["cg64"]["iters"], round(r["cg64"]["seconds"] * 1e3, 3),
+                        r["tau"]["iters"], round(r["tau"]["seconds"] * 1e3, 3)]
                        for r in rs]
-        out["row_fields"] = ["alpha", "fpcg_iters", "fpcg_fell_back", "fpcg_ms", "cg64_iters", "cg64_ms"]
+        out["row_fields"] = ["alpha", "fpcg_iters", "fpcg_fell_back", "fpcg_ms", "cg64_iters", "cg64_ms",
+                             "tau_iters", "tau_ms"]
         return out
 
     return {"workload": "2D N=256 (255^2 interior on a 256^2 network grid), alpha~U(0.3,1.9), f = 8 Gaussians; "
@@ -352,49 +370,43 @@ def paper_ac_extra(torch, fl, inputs, sizes=(128, 256, 512, 1024), alphas=(1.9, 
                    sizes3d=(128, 256)):
     """The paper's two kissing bubbles: u_t = -(-Delta)^{alpha/2} u - delta^-alpha u (u^2 - 1) on (0,1)^d,
     u = -1 outside, delta = 0.03, h = 1/N, tau = 5e-4, 30 Crank--Nicolson steps to t = 0.015 (stepped as
-    ubar = u + 1), each solved to an FP64 residual of 1e-8.  The paper's CPU seconds (2D) are context."""
+    ubar = u + 1), each solved to an FP64 residual of 1e-8 by the default solver (the sine-transform
+    preconditioned CG on these grids) and, for comparison, by FP32-matvec CG in FP64 refinement.  The
+    paper's CPU seconds (2D) are context."""
     delta, tau, steps = 0.03, 5e-4, 30
     out = {"workload": "two kissing bubbles on (0,1)^d, delta=0.03, tau=5e-4, 30 steps to t=0.015, tol 1e-8",
            "runs": []}
-    for alpha in alphas:
-        for N in sizes:
-            h = 1.0 / N
-            op = fl.Operator(2, alpha, h, N)
-            ub = torch.as_tensor(inputs.kissing_bubbles(N, delta), device="cuda:0")
-            gamma = delta ** -alpha
-            op.allen_cahn_step_gen(ub.clone(), tau, 1.0, gamma, 1.0)  # warm (workspaces)
-            torch.cuda.synchronize()
-            iters = 0
-            t0 = time.perf_counter()
-            for _ in range(steps):
-                iters += op.allen_cahn_step_gen(ub, tau, 1.0, gamma, 1.0)["iters"]
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            mass = float((ub - 1.0).abs().sum()) * h * h  # integral of |u| over the box
-            out["runs"].append({"d": 2, "alpha": alpha, "N": N, "seconds": round(dt, 4), "cg_iters": iters,
-                                "mass_in_box": round(mass, 6),
-                                "paper_cpu_seconds": PAPER_AC_SECONDS[alpha][N]})
-            op.close()
-    # the 3D run (alpha = 1.9): the paper states neither its 3D mesh nor a time for
-    # it; h = 1/N at the sizes3d, same delta, tau and end time
-    alpha, gamma = 1.9, delta ** -1.9
-    for N in sizes3d:
+
+    def run(d, alpha, N, centres, solver):
         h = 1.0 / N
-        op = fl.Operator(3, alpha, h, N)
-        ub = torch.as_tensor(inputs.kissing_bubbles(N, delta, ((0.4, 0.6, 0.5), (0.6, 0.4, 0.5))),
-                             device="cuda:0")
-        op.allen_cahn_step_gen(ub.clone(), tau, 1.0, gamma, 1.0)
+        op = fl.Operator(d, alpha, h, N)
+        ub = torch.as_tensor(inputs.kissing_bubbles(N, delta, centres), device="cuda:0")
+        gamma = delta ** -alpha
+        op.allen_cahn_step_gen(ub.clone(), tau, 1.0, gamma, 1.0, solver=solver)  # warm (workspaces)
         torch.cuda.synchronize()
         iters = 0
         t0 = time.perf_counter()
         for _ in range(steps):
-            iters += op.allen_cahn_step_gen(ub, tau, 1.0, gamma, 1.0)["iters"]
+            iters += op.allen_cahn_step_gen(ub, tau, 1.0, gamma, 1.0, solver=solver)["iters"]
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        mass = float((ub - 1.0).abs().sum()) * h ** 3
-        out["runs"].append({"d": 3, "alpha": alpha, "N": N, "seconds": round(dt, 4), "cg_iters": iters,
-                            "mass_in_box": round(mass, 6), "paper_cpu_seconds": None})
         op.close()
+        return ub, dt, iters
+
+    c2, c3 = ((0.4, 0.4), (0.6, 0.6)), ((0.4, 0.6, 0.5), (0.6, 0.4, 0.5))
+    # the 3D run (alpha = 1.9): the paper states neither its 3D mesh nor a time for
+    # it; h = 1/N at the sizes3d, same delta, tau and end time
+    cases = [(2, a, N, c2) for a in alphas for N in sizes] + [(3, 1.9, N, c3) for N in sizes3d]
+    for d, alpha, N, centres in cases:
+        ub, dt, iters = run(d, alpha, N, centres, "auto")
+        ur, dtr, itr = run(d, alpha, N, centres, "refine")
+        mass = float((ub - 1.0).abs().sum()) * (1.0 / N) ** d  # integral of |u| over the box
+        out["runs"].append({"d": d, "alpha": alpha, "N": N, "seconds": round(dt, 4), "iters": iters,
+                            "refine_seconds": round(dtr, 4), "refine_inner_iters": itr,
+                            "max_abs_diff_vs_refine": float((ub - ur).abs().max()),
+                            "mass_in_box": round(mass, 6),
+                            "paper_cpu_seconds": PAPER_AC_SECONDS[alpha][N] if d == 2 else None})
+        del ub, ur
     return out
 
 

@@ -57,20 +57,23 @@ typedef enum {
 typedef enum { FL_FP64 = 0, FL_FP32 = 1 } fl_prec;
 
 typedef enum {
-    FL_SOLVE_AUTO = 0,    /* TAU where it applies (square and cubic operators with
-                             FFT length <= 2048, s0 + s1 lambda > 0 on the sine
-                             modes); otherwise, Poisson: REFINE for alpha <= 1.25,
-                             CG64 above (each refinement step restarts CG, which
-                             costs the stiffer operators more iterations than
-                             FP32 saves); the Allen-Cahn steps: REFINE           */
+    FL_SOLVE_AUTO = 0,    /* TAU where it applies (square and cubic operators, N a
+                             power of two, FFT length 2N <= 2048, s0 + s1 lambda
+                             > 0 on the sine modes; in the Allen-Cahn steps only
+                             when 2 theta tau kappa A_ii > 0.5, else the system
+                             is close to the identity); otherwise, Poisson:
+                             REFINE for alpha <= 1.25, CG64 above (each
+                             refinement step restarts CG, which costs the stiffer
+                             operators more iterations than FP32 saves); the
+                             Allen-Cahn steps: REFINE                            */
     FL_SOLVE_CG64 = 1,    /* plain conjugate gradients, FP64 matvec and vectors  */
     FL_SOLVE_REFINE = 2,  /* FP64 residual refinement around FP32-matvec CG      */
     FL_SOLVE_FPCG = 3,    /* flexible PCG with the learned preconditioner        */
     FL_SOLVE_TAU = 4      /* flexible PCG, all FP64, with the sine-transform
                              (tau) preconditioner of the system matrix (see
-                             fl_tau_apply); square and cubic operators with FFT
-                             length <= 2048 only (else FL_E_INVAL).  Falls back
-                             to CG64 like FPCG                                   */
+                             fl_tau_apply); square and cubic operators with N a
+                             power of two and FFT length 2N <= 2048 only (else
+                             FL_E_INVAL).  Falls back to CG64 like FPCG          */
 } fl_solver;
 
 typedef struct {
@@ -172,12 +175,14 @@ fl_status fl_apply(fl_op op, const void *u, void *y, int prec, void *stream);
  * eigenvalues are the circulant symbol of K at the frequencies pi k / N, i.e.
  * K minus its two Hankel corrections (for the Toeplitz levels of A: entries
  * t_{i+j+2} and t_{2n-i-j}).  Computed by the matvec's passes on the odd
- * extension of r with the symbol 1 / (s0 + s1 lambda), in FP64.  Not part of
+ * extension of r with the symbol 1 / (s0 + s1 lambda), in FP64; the sine basis
+ * needs the FFT length to be exactly 2N (N a power of two, N >= 4).  Not part of
  * the paper's scheme: a preconditioner for its CG solves (Sec. 5.2-5.3).
  * r, z: device double vectors of M entries, not overlapping.  The symbol is
  * rebuilt when (s0, s1) or the FP64 kernel variant change (a synchronising
  * step); then asynchronous on `stream`.  Errors: FL_E_INVAL (null, overlap,
- * s0/s1), FL_E_UNSUPPORTED (box or FFT length above 2048), FL_E_BREAKDOWN
+ * s0/s1), FL_E_UNSUPPORTED (box, N not a power of two, or FFT length above
+ * 2048), FL_E_BREAKDOWN
  * (s0 + s1 lambda not positive on a sine mode), FL_E_NOMEM, FL_E_DEVICE.
  */
 fl_status fl_tau_apply(fl_op op, const double *r, double *z, double s0, double s1,
@@ -206,8 +211,8 @@ fl_status fl_poisson_solve_ex(fl_op op, const double *f, double tol, double *u,
  * the cubic term explicit:
  *     (I + tau eps^2 A / 2) u+ = u - tau eps^2 A u / 2 + tau (u - u^3),
  * solved with initial guess u by FL_SOLVE_AUTO (the sine-transform
- * preconditioned CG on the square and cube, else FP32-matvec CG inside FP64
- * residual refinement) to a relative FP64 residual of 1e-8.  u: device double vector
+ * preconditioned CG where it applies and pays, else FP32-matvec CG inside
+ * FP64 residual refinement) to a relative FP64 residual of 1e-8.  u: device double vector
  * of M entries, updated in place.  tau > 0, eps > 0.
  */
 fl_status fl_allen_cahn_step(fl_op op, double *u, double tau, double eps,

@@ -1003,8 +1003,8 @@ bool tau_supported(const fl_op_s *op) {
 
 fl_status tau_prepare(fl_op op, double s0, double s1, hipStream_t s) {
     if (!tau_supported(op)) {
-        set_error("the sine-transform preconditioner needs a square or cubic operator with FFT length <= %d",
-                  kMaxLdsP);
+        set_error("the sine-transform preconditioner needs a square or cubic operator with N a power of two "
+                  "(FFT length 2N <= %d)", kMaxLdsP);
         return FL_E_UNSUPPORTED;
     }
     if (!(s0 >= 0.0) || !(s1 >= 0.0) || !(s0 + s1 > 0.0) || !std::isfinite(s0) || !std::isfinite(s1)) {

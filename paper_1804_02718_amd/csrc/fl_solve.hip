@@ -592,8 +592,9 @@ static fl_status apply_prec(fl_op op, int kind, const double *r, double *z, cons
 // the sine-transform preconditioner.  Falls back to plain FP64 CG from the
 // current iterate when (r, z) <= 0, a scalar is not finite, or the residual
 // stops decreasing.
+// r_given: w.r64 already holds f - K x for the initial x (saves the first FP64 matvec)
 static fl_status fpcg(fl_op op, int kind, double s0, double s1, const double *f, double *x, double tol,
-                      int max_iter, fl_info *info, hipStream_t s) {
+                      int max_iter, fl_info *info, hipStream_t s, bool r_given = false) {
     FL_TRY(ensure_workspace(op));
     Work w = work_of(op);
     const long M = op->M;
@@ -609,7 +610,7 @@ static fl_status fpcg(fl_op op, int kind, double s0, double s1, const double *f,
         return FL_OK;
     }
     // r = f - K x; (r, r) into S_FRR for the network's scaling; z = M r; (r, z); p = z
-    FL_TRY(residual64(op, f, x, r, s0, s1, s));
+    if (!r_given) FL_TRY(residual64(op, f, x, r, s0, s1, s));
     double *scal = op->scal;
     const double *done = scal + S_DONE;
     hipLaunchKernelGGL(k_dot<double>, dim3(L.blocks), dim3(kVecBlock), 0, s, r, r, L.n, L.chunk, w.partA, nullptr);
@@ -704,7 +705,7 @@ fl_status fl_poisson_solve_ex(fl_op op, const double *f, double tol, double *u, 
     if (opts) o = *opts;
     if (o.solver < FL_SOLVE_AUTO || o.solver > FL_SOLVE_TAU) { set_error("unknown solver"); return FL_E_INVAL; }
     if (o.solver == FL_SOLVE_TAU && !tau_supported(op)) {
-        set_error("TAU needs a square or cubic operator with FFT length <= %d", kMaxLdsP);
+        set_error("TAU needs a square or cubic operator with N a power of two (FFT length 2N <= %d)", kMaxLdsP);
         return FL_E_INVAL;
     }
     if (o.solver == FL_SOLVE_FPCG && (!op->net || op->d != 2 || op->n > unet_size(op->net) ||
@@ -728,9 +729,13 @@ fl_status fl_poisson_solve_ex(fl_op op, const double *f, double tol, double *u, 
     // for CG at alpha >= 1)
     if (o.solver == FL_SOLVE_TAU || (o.solver == FL_SOLVE_AUTO && tau_supported(op))) {
         st = tau_prepare(op, 0.0, 1.0, s);
-        if (st == FL_OK) st = fpcg(op, PREC_TAU, 0.0, 1.0, f, u, tol, max_iter, inf, s);
-        // AUTO without a positive symbol on the sine modes takes the plain solvers
-        solved = st == FL_OK || o.solver == FL_SOLVE_TAU || st != FL_E_BREAKDOWN;
+        if (st == FL_OK) {
+            st = fpcg(op, PREC_TAU, 0.0, 1.0, f, u, tol, max_iter, inf, s);  // falls back to CG itself
+            solved = true;
+        } else {
+            // AUTO without a positive symbol on the sine modes takes the plain solvers
+            solved = o.solver == FL_SOLVE_TAU || st != FL_E_BREAKDOWN;
+        }
     }
     if (!solved && o.solver == FL_SOLVE_FPCG) {
         st = fpcg(op, PREC_NET, 0.0, 1.0, f, u, tol, max_iter, inf, s);
@@ -772,7 +777,7 @@ fl_status fl_allen_cahn_step_gen(fl_op op, double *u, double tau, double kappa, 
         return FL_E_INVAL;
     }
     if (solver == FL_SOLVE_TAU && !tau_supported(op)) {
-        set_error("TAU needs a square or cubic operator with FFT length <= %d", kMaxLdsP);
+        set_error("TAU needs a square or cubic operator with N a power of two (FFT length 2N <= %d)", kMaxLdsP);
         return FL_E_INVAL;
     }
     fl_info local;
@@ -788,16 +793,27 @@ fl_status fl_allen_cahn_step_gen(fl_op op, double *u, double tau, double kappa, 
     hipLaunchKernelGGL(k_ac_rhs, dim3(ew_grid(op->M)), dim3(256), 0, s, u, w.kp64, w.b64, w.r64, op->M, tau, sc,
                        theta, gamma, shift);
     FL_HIP_TRY(hipGetLastError());
-    // (I + theta s A) u+ = b, initial guess u: the sine-transform preconditioned CG
-    // (TAU, and AUTO where it applies), else CG or FP32-matvec refinement
+    // (I + theta s A) u+ = b, initial guess u, whose residual k_ac_rhs left in r64: the
+    // sine-transform preconditioned CG (TAU; AUTO where it applies and the system is
+    // not close to the identity), else CG or FP32-matvec refinement.  The spectral
+    // radius of A is at most 2 A_ii = -2 c a_0 (its symbol is a_0 + sum of the
+    // off-diagonal terms, which sum to at most -a_0); when theta s times that is
+    // small, plain CG converges in a few iterations and the preconditioner's extra
+    // FP64 pass per iteration does not pay (the paper's two-bubble runs at N = 1024:
+    // the preconditioned solve is faster at 1.05, refinement at 0.11).
+    const double spread = theta * sc * 2.0 * (-op->c * op->a0);
     fl_status st = FL_OK;
     bool solved = false;
-    if (solver == FL_SOLVE_TAU || (solver == FL_SOLVE_AUTO && tau_supported(op))) {
+    if (solver == FL_SOLVE_TAU || (solver == FL_SOLVE_AUTO && tau_supported(op) && spread > 0.5)) {
         st = tau_prepare(op, 1.0, theta * sc, s);
-        if (st == FL_OK) st = fpcg(op, PREC_TAU, 1.0, theta * sc, w.b64, u, tol, default_max_iter(op), inf, s);
-        solved = st == FL_OK || solver == FL_SOLVE_TAU || st != FL_E_BREAKDOWN;
+        if (st == FL_OK) {
+            st = fpcg(op, PREC_TAU, 1.0, theta * sc, w.b64, u, tol, default_max_iter(op), inf, s, true);
+            solved = true;
+        } else {
+            // r64 still holds the initial residual for refine
+            solved = solver == FL_SOLVE_TAU || st != FL_E_BREAKDOWN;
+        }
     }
-    // the residual of the initial guess u, left in r64 by k_ac_rhs, serves refine
     if (!solved)
         st = refine(op, 1.0, theta * sc, w.b64, u, tol, solver == FL_SOLVE_CG64, 1e-4, default_max_iter(op), 0,
                     inf, s, true);

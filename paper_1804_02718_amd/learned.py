@@ -60,7 +60,8 @@ def train(net, x, t, epochs, batch=16, lr=3e-4, lr_final=2e-5, seed=0):
 
 
 def compare(net, N, seeds, tol=1e-8, reps=2):
-    """Flexible PCG with the network against plain FP64 CG on held-out problems."""
+    """Flexible PCG with the network against plain FP64 CG and the sine-transform preconditioned CG
+    on held-out problems."""
     import torch
     out = []
     for sd in seeds:
@@ -69,7 +70,7 @@ def compare(net, N, seeds, tol=1e-8, reps=2):
         op.set_preconditioner(net)
         F = _dev(f, torch.float64)
         row = {"seed": sd, "alpha": alpha}
-        for solver in ("fpcg", "cg64"):
+        for solver in ("fpcg", "cg64", "tau"):
             for _ in range(reps):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
@@ -80,7 +81,7 @@ def compare(net, N, seeds, tol=1e-8, reps=2):
                            "seconds": wall}
             row[solver + "_u"] = u
         row["rel_diff"] = float((row["fpcg_u"] - row["cg64_u"]).norm() / row["cg64_u"].norm())
-        del row["fpcg_u"], row["cg64_u"]
+        del row["fpcg_u"], row["cg64_u"], row["tau_u"]
         op.close()
         out.append(row)
     return out
