@@ -224,7 +224,8 @@ def c4_extra(torch, fl, inputs):
             "sequential_max_relres": max(i["relres"] for i in seq)}
 
 
-def poisson_extra(torch, fl, inputs, N=1024, alpha=1.5, alphas=(0.5, 1.0, 1.5, 1.9)):
+def poisson_extra(torch, fl, inputs, N=1024, alpha=1.5, alphas=(0.5, 1.0, 1.5, 1.9),
+                  solvers=("cg64", "refine", "tau")):
     """Time-to-1e-8 relative residual for the 2D N=1024 Poisson problem, f = 8 Gaussians: plain FP64
     CG, FP32-matvec refinement and the sine-transform preconditioned CG (the default solver here) at
     `alpha`, and CG against the preconditioned solve over `alphas`."""
@@ -243,8 +244,11 @@ def poisson_extra(torch, fl, inputs, N=1024, alpha=1.5, alphas=(0.5, 1.0, 1.5, 1
                 "relres": info["relres"], "fell_back": info["fell_back"]}
 
     op = fl.Operator(2, alpha, h, N)
-    out = {solver: timed(op, solver) for solver in ("cg64", "refine", "tau")}
+    out = {solver: timed(op, solver) for solver in solvers}
     op.close()
+    res = {"workload": "2D N=1024 alpha=%.2f, f = sum of 8 seeded Gaussians on (-1,1)^2, tol 1e-8" % alpha, **out}
+    if "cg64" in out and "tau" in out:
+        res["tau_speedup_over_cg64"] = round(out["cg64"]["seconds"] / out["tau"]["seconds"], 1)
     sweep = []
     for a in alphas:
         op = fl.Operator(2, a, h, N)
@@ -252,10 +256,10 @@ def poisson_extra(torch, fl, inputs, N=1024, alpha=1.5, alphas=(0.5, 1.0, 1.5, 1
         sweep.append([a, c["iters"], round(c["seconds"] * 1e3, 3), t["iters"], round(t["seconds"] * 1e3, 3),
                       round(c["seconds"] / t["seconds"], 1)])
         op.close()
-    return {"workload": "2D N=1024 alpha=%.2f, f = sum of 8 seeded Gaussians on (-1,1)^2, tol 1e-8" % alpha,
-            **out, "tau_speedup_over_cg64": round(out["cg64"]["seconds"] / out["tau"]["seconds"], 1),
-            "by_alpha": sweep, "by_alpha_fields": ["alpha", "cg64_iters", "cg64_ms", "tau_iters", "tau_ms",
-                                                   "cg64_over_tau"]}
+    if sweep:
+        res["by_alpha"] = sweep
+        res["by_alpha_fields"] = ["alpha", "cg64_iters", "cg64_ms", "tau_iters", "tau_ms", "cg64_over_tau"]
+    return res
 
 
 def c5_extra(torch, fl, pairs, epochs, N=256, res_samples=2048, res_epochs=10):
@@ -421,6 +425,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner report (the timed matvec always uses the library's default "
                          "kernel variant, the fastest one measured for this size)")
+    ap.add_argument("--poisson-solvers", default="cg64,refine,tau",
+                    help="solvers timed on the 2D N=1024 Poisson problem (comma list of cg64, refine, tau)")
+    ap.add_argument("--no-poisson-sweep", action="store_true",
+                    help="skip CG64 against tau-PCG over alpha in {0.5, 1, 1.5, 1.9}")
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the 3D N=256 workload (matvec in FP32 and FP64, 200 Allen--Cahn steps)")
     ap.add_argument("--no-large", action="store_true",
@@ -520,7 +528,8 @@ def main():
         dt64 = time_matvec(op, u64, y64, max(100, args.steps // 4), 10, torch)
         extra["fp64_gdof_s"] = round(M * max(100, args.steps // 4) / dt64 / 1e9, 3)
         print("bench: poisson solves", file=sys.stderr, flush=True)
-        extra["poisson"] = poisson_extra(torch, fl, inputs)
+        extra["poisson"] = poisson_extra(torch, fl, inputs, solvers=tuple(args.poisson_solvers.split(",")),
+                                         alphas=() if args.no_poisson_sweep else (0.5, 1.0, 1.5, 1.9))
     op.close()
     if not args.no_extra and not args.no_c3:
         print("bench: 3D N=256 matvec", file=sys.stderr, flush=True)
@@ -545,7 +554,7 @@ def main():
         cpu = cpu_baseline(N, alpha, h, u_np, args.cpu_seconds)
         # the oracle's Poisson solve at C2, extrapolated (not measured): one full explicit
         # matvec at the measured row rate, times the GPU's plain-CG iteration count
-        if "poisson" in extra and cpu.get("value"):
+        if "poisson" in extra and "cg64" in extra["poisson"] and cpu.get("value"):
             mv_s = M / (cpu["value"] * 1e9)
             extra["poisson"]["oracle_extrapolated"] = {
                 "kind": "extrapolated", "oracle_matvec_seconds": round(mv_s, 1),
