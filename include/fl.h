@@ -284,7 +284,11 @@ fl_status fl_autotune(fl_op op, int prec, int reps, void *stream, int *best, flo
  *                              the problems into size classes of equal N; each
  *                              class runs all of its problems in every kernel
  *                              launch, and its inner CG iterations are replayed
- *                              from a captured hipGraph.  Synchronises.
+ *                              from a captured hipGraph.  A class of a power-of-
+ *                              two N whose every problem has a positive symbol
+ *                              on the sine modes preconditions its inner CG by
+ *                              the sine transform (FP32, as fl_tau_apply).
+ *                              Synchronises.
  *   fl_batch_poisson_solve  -- solves A_i u_i = f_i to ||f_i - A_i u_i||_2 <=
  *                              tol ||f_i||_2 (FP64 residual refinement around
  *                              FP32 CG) for every i; f, u are host arrays of

@@ -1001,7 +1001,7 @@ bool tau_supported(const fl_op_s *op) {
     return true;
 }
 
-fl_status tau_prepare(fl_op op, double s0, double s1, hipStream_t s) {
+fl_status tau_symbol(fl_op op, double s0, double s1, int prec, int C, void *lt, hipStream_t s) {
     if (!tau_supported(op)) {
         set_error("the sine-transform preconditioner needs a square or cubic operator with N a power of two "
                   "(FFT length 2N <= %d)", kMaxLdsP);
@@ -1011,19 +1011,7 @@ fl_status tau_prepare(fl_op op, double s0, double s1, hipStream_t s) {
         set_error("preconditioner of s0 I + s1 A needs s0, s1 >= 0, not both 0");
         return FL_E_INVAL;
     }
-    if (op->mu64t && op->mu_var == op->var64 && op->mu_s0 == s0 && op->mu_s1 == s1) return FL_OK;
     const int d = op->d, Q = op->Q;
-    if (!op->mu64t) {
-        long qrest = 1;
-        for (int k = 1; k < d; ++k) qrest *= Q;
-        const long len = qrest * (Q + kMaxTile - 1);
-        hipError_t e = hipMalloc((void **)&op->mu64t, sizeof(double) * len);
-        if (e != hipSuccess) {
-            op->mu64t = nullptr;
-            set_error("preconditioner symbol: %s", hipGetErrorString(e));
-            return e == hipErrorOutOfMemory ? FL_E_NOMEM : FL_E_DEVICE;
-        }
-    }
     SymMap m;
     m.tau = 1;
     m.s0 = s0;
@@ -1040,16 +1028,37 @@ fl_status tau_prepare(fl_op op, double s0, double s1, hipStream_t s) {
     FL_HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
     FL_HIP_TRY(hipStreamSynchronize(s));
     if (hbad) {
-        op->mu_var = -1;
         set_error("s0 + s1 lambda is not positive on every sine mode: no sine-transform preconditioner");
         return FL_E_BREAKDOWN;
     }
-    const VariantDesc vd = variant_desc(op, FL_FP64, op->var64);
-    const int nt = cdiv(spec_cols(d, op->P), vd.c);
-    const long len = lam_tiled_len(d, op->P, vd.c);
+    const int nt = cdiv(spec_cols(d, op->P), C);
+    const long len = lam_tiled_len(d, op->P, C);
     const int gt = cdiv(len, 256) > 65536 ? 65536 : cdiv(len, 256);
-    hipLaunchKernelGGL(k_tile_lambda<double>, dim3(gt), dim3(256), 0, s, op->lam64, op->mu64t, d, Q, vd.c, nt, m);
+    if (prec == FL_FP32)
+        hipLaunchKernelGGL(k_tile_lambda<float>, dim3(gt), dim3(256), 0, s, op->lam64, (float *)lt, d, Q, C, nt, m);
+    else
+        hipLaunchKernelGGL(k_tile_lambda<double>, dim3(gt), dim3(256), 0, s, op->lam64, (double *)lt, d, Q, C, nt,
+                           m);
     FL_HIP_TRY(hipGetLastError());
+    return FL_OK;
+}
+
+fl_status tau_prepare(fl_op op, double s0, double s1, hipStream_t s) {
+    if (!tau_supported(op)) return tau_symbol(op, s0, s1, FL_FP64, 1, nullptr, s);  // sets the error
+    if (op->mu64t && op->mu_var == op->var64 && op->mu_s0 == s0 && op->mu_s1 == s1) return FL_OK;
+    if (!op->mu64t) {
+        long qrest = 1;
+        for (int k = 1; k < op->d; ++k) qrest *= op->Q;
+        const long len = qrest * (op->Q + kMaxTile - 1);
+        hipError_t e = hipMalloc((void **)&op->mu64t, sizeof(double) * len);
+        if (e != hipSuccess) {
+            op->mu64t = nullptr;
+            set_error("preconditioner symbol: %s", hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? FL_E_NOMEM : FL_E_DEVICE;
+        }
+    }
+    op->mu_var = -1;
+    FL_TRY(tau_symbol(op, s0, s1, FL_FP64, variant_desc(op, FL_FP64, op->var64).c, op->mu64t, s));
     op->mu_var = op->var64;
     op->mu_s0 = s0;
     op->mu_s1 = s1;

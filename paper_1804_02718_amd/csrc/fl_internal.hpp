@@ -411,6 +411,8 @@ fl_status select_variant(fl_op op, int prec, int k, hipStream_t s);
 // FP64 variant (FL_E_BREAKDOWN when s0 + s1 lambda is not positive on a sine
 // mode); tau_apply computes z = M^{-1} r in FP64 (a set `done` flag skips it)
 bool tau_supported(const fl_op_s *op);
+// the preconditioner's symbol tiled to width C in FP32 or FP64 into lt (lam_tiled_len entries)
+fl_status tau_symbol(fl_op op, double s0, double s1, int prec, int C, void *lt, hipStream_t s);
 fl_status tau_prepare(fl_op op, double s0, double s1, hipStream_t s);
 fl_status tau_apply(fl_op op, const double *r, double *z, const double *done, hipStream_t s);
 constexpr int kMaxTile = 16;  // largest tile width of any variant

@@ -198,6 +198,63 @@ __global__ __launch_bounds__(kVecBlock) void k_cg_p(V *__restrict__ p, const V *
     for (long i = beg + threadIdx.x; i < end; i += kVecBlock) p[i] = r[i] + b * p[i];
 }
 
+// start of a preconditioned CG run (batched: blockIdx.y = problem): the S_RR
+// slots take (r, z), the stop target rel2z[z] * (r, r) (a negative entry marks
+// the problem as finished); (r, z) <= 0 or a non-finite sum is a breakdown
+__global__ __launch_bounds__(kVecBlock) void k_pcg_init(const double *part_rr, const double *part_rz, int np,
+                                                        double *scal, const double *rel2z) {
+    __shared__ double sh[kVecBlock];
+    const int z = blockIdx.y;
+    part_rr += z * kMaxParts;
+    part_rz += z * kMaxParts;
+    scal += z * S_COUNT;
+    const double rel2 = rel2z[z];
+    const double rr = sum_parts(part_rr, np, sh);
+    const double rz = sum_parts(part_rz, np, sh);
+    if (threadIdx.x == 0) {
+        scal[S_RR0] = rz;
+        scal[S_RR1] = rz;
+        scal[S_ITER] = 0.0;
+        const bool bad = !std::isfinite(rr) || !std::isfinite(rz) || !(rz > 0.0);
+        scal[S_BRK] = bad && rr > 0.0 ? 1.0 : 0.0;
+        const double tgt = rel2 * rr;
+        scal[S_TARGET] = tgt;
+        scal[S_DONE] = (rel2 < 0.0 || rr <= tgt || bad) ? 1.0 : 0.0;
+    }
+}
+
+// preconditioned direction: stop on (r, r) <= target; beta = (r, z)_new / (r, z);
+// p = z + beta p; block 0 advances the scalars
+template <typename V>
+__global__ __launch_bounds__(kVecBlock) void k_pcg_p(V *__restrict__ p, const V *__restrict__ zv, long n, long chunk,
+                                                     const double *__restrict__ part_rr,
+                                                     const double *__restrict__ part_rz, int np, double *scal,
+                                                     int parity) {
+    __shared__ double sh[kVecBlock];
+    const int z = blockIdx.y;
+    scal += z * S_COUNT;
+    if (scal[S_DONE] != 0.0) return;
+    p += z * n;
+    zv += z * n;
+    part_rr += z * kMaxParts;
+    part_rz += z * kMaxParts;
+    const double rr_new = sum_parts(part_rr, np, sh);
+    const double rz_new = sum_parts(part_rz, np, sh);
+    const double be = rz_new / scal[parity ? S_RR1 : S_RR0];
+    const bool bad = !std::isfinite(rr_new) || !std::isfinite(be) || !(rz_new > 0.0);
+    const bool stop = rr_new <= scal[S_TARGET] || bad;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        scal[parity ? S_RR0 : S_RR1] = rz_new;
+        scal[S_ITER] += 1.0;
+        if (bad && !(rr_new <= scal[S_TARGET])) scal[S_BRK] = 1.0;
+        if (stop) scal[S_DONE] = 1.0;
+    }
+    if (stop) return;
+    const V b = (V)be;
+    const long beg = (long)blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
+    for (long i = beg + threadIdx.x; i < end; i += kVecBlock) p[i] = zv[i] + b * p[i];
+}
+
 template <typename D, typename S>
 __global__ void k_copy_cast(D *__restrict__ d, const S *__restrict__ s, long n) {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
@@ -846,7 +903,8 @@ fl_status fl_allen_cahn_step(fl_op op, double *u, double tau, double eps, fl_inf
 // ===========================================================================
 namespace fl {
 
-constexpr int kGraphIters = 16;  // inner CG iterations per captured graph (even: parity)
+constexpr int kGraphIters = 16;    // inner CG iterations per captured graph (even: parity)
+constexpr int kGraphItersTau = 4;  // inner preconditioned iterations per graph (they converge in a few)
 
 struct BatchClass {
     int N = 0, n = 0, P = 0, Q = 0, B = 0;
@@ -864,6 +922,14 @@ struct BatchClass {
     hipGraphExec_t chunk = nullptr;
     MvCtx<float> c32;
     MvCtx<double> c64;
+    // sine-transform preconditioned inner CG (power-of-two squares and cubes whose
+    // every problem has a positive symbol on the sine modes): z = M^{-1} r in FP32
+    bool tau = false;
+    int iters_per_chunk = kGraphIters;
+    float *z32 = nullptr;
+    double *partC = nullptr;
+    void *mu32 = nullptr;
+    MvCtx<float> c32t;
 };
 
 }  // namespace fl
@@ -912,6 +978,11 @@ static fl_status batch_alloc(BatchClass &c, int d) {
     const size_t o_t2 = off; off += al((size_t)c.zs_t2 * B);
     const size_t o_l32 = off; off += al(sizeof(float) * c.lamlen32 * B);
     const size_t o_l64 = off; off += al(sizeof(double) * c.lamlen64 * B);
+    // the preconditioned path: z, (r, z) partials and the per-problem FP32 symbols
+    c.tau = tau_supported(c.ops[0]);
+    const size_t o_z32 = off; off += c.tau ? al(sizeof(float) * B * M) : 0;
+    const size_t o_pc = off; off += c.tau ? al(sizeof(double) * B * kMaxParts) : 0;
+    const size_t o_mu = off; off += c.tau ? al(sizeof(float) * c.lamlen32 * B) : 0;
     FL_HIP_TRY(hipMalloc(&c.buf, off));
     char *base = (char *)c.buf;
     c.x = (double *)(base + o_x);
@@ -929,6 +1000,11 @@ static fl_status batch_alloc(BatchClass &c, int d) {
     c.T2 = c.zs_t2 ? (void *)(base + o_t2) : nullptr;
     c.lam32 = base + o_l32;
     c.lam64 = base + o_l64;
+    if (c.tau) {
+        c.z32 = (float *)(base + o_z32);
+        c.partC = (double *)(base + o_pc);
+        c.mu32 = base + o_mu;
+    }
     FL_HIP_TRY(hipHostMalloc((void **)&c.hscal, sizeof(double) * B * S_COUNT, hipHostMallocDefault));
     // per-problem lambda tiled for the class's variants
     for (int z = 0; z < c.B; ++z) {
@@ -945,10 +1021,25 @@ static fl_status batch_alloc(BatchClass &c, int d) {
         cx->T1 = c.T1; cx->T2 = c.T2; cx->lam = (const double *)c.lam64; cx->batch = c.B; cx->zs_vec = M;
         cx->zs_t1 = c.zs_t; cx->zs_t2 = c.zs_t2; cx->zs_lam = c.lamlen64; cx->zs_done = S_COUNT;
     }
+    // every problem's preconditioner symbol, or plain CG for the class if one of
+    // them has no positive symbol on the sine modes
+    for (int z = 0; z < c.B && c.tau; ++z) {
+        fl_status st = tau_symbol(c.ops[z], 0.0, 1.0, FL_FP32, C32, (float *)c.mu32 + z * c.lamlen32, c.s);
+        if (st == FL_E_BREAKDOWN) c.tau = false;
+        else FL_TRY(st);
+    }
+    if (c.tau) {
+        c.c32t = c.c32;
+        c.c32t.lam = (const float *)c.mu32;
+        c.c32t.odd = true;
+        c.iters_per_chunk = kGraphItersTau;
+    }
     return FL_OK;
 }
 
-// launches of kGraphIters inner FP32 CG iterations of a class (captured once)
+// launches of iters_per_chunk inner FP32 (P)CG iterations of a class (captured once).
+// The preconditioned iteration keeps (r, z) in the S_RR slots, so k_cg_xr takes
+// alpha = (r, z) / (p, K p) and leaves the (r, r) partials for the stop test.
 static fl_status batch_chunk_launches(BatchClass &c) {
     VecLayout L = layout(c.M);
     const double *done = c.scal + S_DONE;
@@ -961,7 +1052,7 @@ static fl_status batch_chunk_launches(BatchClass &c) {
         ep.dpart = c.partA;
         ep.dpart_stride = kMaxParts;
     }
-    for (int i = 0; i < kGraphIters; ++i) {
+    for (int i = 0; i < c.iters_per_chunk; ++i) {
         const int parity = i & 1;
         FL_TRY(matvec_ctx<float>(c.c32, c.var32, c.p32, c.kp32, ep, done, c.s));
         if (!fused)
@@ -969,8 +1060,16 @@ static fl_status batch_chunk_launches(BatchClass &c) {
                                L.chunk, c.partA, done);
         hipLaunchKernelGGL(k_cg_xr<float>, dim3(L.blocks, c.B), dim3(kVecBlock), 0, c.s, c.d32, c.r32, c.p32,
                            c.kp32, L.n, L.chunk, c.partA, fused ? np_x : L.blocks, c.partB, c.scal, parity);
-        hipLaunchKernelGGL(k_cg_p<float>, dim3(L.blocks, c.B), dim3(kVecBlock), 0, c.s, c.p32, c.r32, L.n, L.chunk,
-                           c.partB, L.blocks, c.scal, parity);
+        if (c.tau) {
+            FL_TRY(matvec_ctx<float>(c.c32t, c.var32, c.r32, c.z32, Epi<float>{}, done, c.s));
+            hipLaunchKernelGGL(k_dot<float>, dim3(L.blocks, c.B), dim3(kVecBlock), 0, c.s, c.r32, c.z32, L.n,
+                               L.chunk, c.partC, done);
+            hipLaunchKernelGGL(k_pcg_p<float>, dim3(L.blocks, c.B), dim3(kVecBlock), 0, c.s, c.p32, c.z32, L.n,
+                               L.chunk, c.partB, c.partC, L.blocks, c.scal, parity);
+        } else {
+            hipLaunchKernelGGL(k_cg_p<float>, dim3(L.blocks, c.B), dim3(kVecBlock), 0, c.s, c.p32, c.r32, L.n,
+                               L.chunk, c.partB, L.blocks, c.scal, parity);
+        }
     }
     FL_HIP_TRY(hipGetLastError());
     return FL_OK;
@@ -1150,11 +1249,24 @@ fl_status fl_batch_poisson_solve(fl_batch b, const double *const *f, double *con
             const long BM = (long)c.B * c.M;
             hipLaunchKernelGGL((k_copy_cast<float, double>), dim3(ew_grid(BM)), dim3(256), 0, c.s, c.r32, c.r64, BM);
             hipLaunchKernelGGL(k_zero<float>, dim3(ew_grid(BM)), dim3(256), 0, c.s, c.d32, BM);
-            hipLaunchKernelGGL((k_copy_cast<float, float>), dim3(ew_grid(BM)), dim3(256), 0, c.s, c.p32, c.r32, BM);
             hipLaunchKernelGGL(k_dot<float>, dim3(L.blocks, c.B), dim3(kVecBlock), 0, c.s, c.r32, c.r32, L.n, L.chunk,
                                c.partB, (const double *)nullptr);
-            hipLaunchKernelGGL(k_cg_init, dim3(1, c.B), dim3(kVecBlock), 0, c.s, c.partB, L.blocks, c.scal, 0.0, 0.0,
-                               (const double *)c.rel2);
+            if (c.tau) {
+                // z = M^{-1} r, p = z, (r, z) into the S_RR slots
+                if (matvec_ctx<float>(c.c32t, c.var32, c.r32, c.z32, Epi<float>{}, nullptr, c.s) != FL_OK)
+                    st = FL_E_DEVICE;
+                hipLaunchKernelGGL((k_copy_cast<float, float>), dim3(ew_grid(BM)), dim3(256), 0, c.s, c.p32, c.z32,
+                                   BM);
+                hipLaunchKernelGGL(k_dot<float>, dim3(L.blocks, c.B), dim3(kVecBlock), 0, c.s, c.r32, c.z32, L.n,
+                                   L.chunk, c.partC, (const double *)nullptr);
+                hipLaunchKernelGGL(k_pcg_init, dim3(1, c.B), dim3(kVecBlock), 0, c.s, c.partB, c.partC, L.blocks,
+                                   c.scal, (const double *)c.rel2);
+            } else {
+                hipLaunchKernelGGL((k_copy_cast<float, float>), dim3(ew_grid(BM)), dim3(256), 0, c.s, c.p32, c.r32,
+                                   BM);
+                hipLaunchKernelGGL(k_cg_init, dim3(1, c.B), dim3(kVecBlock), 0, c.s, c.partB, L.blocks, c.scal, 0.0,
+                                   0.0, (const double *)c.rel2);
+            }
         }
         std::vector<int> active(b->cls.size(), 1);
         for (int chunk = 0; st == FL_OK; ++chunk) {
@@ -1171,7 +1283,8 @@ fl_status fl_batch_poisson_solve(fl_batch b, const double *const *f, double *con
                 st = batch_sync_read(c);
                 bool done = true;
                 for (int z = 0; z < c.B; ++z)
-                    if (c.hscal[z * S_COUNT + S_DONE] == 0.0 && iters[ci][z] + (chunk + 1) * kGraphIters < cap)
+                    if (c.hscal[z * S_COUNT + S_DONE] == 0.0 &&
+                        iters[ci][z] + (long)(chunk + 1) * c.iters_per_chunk < cap)
                         done = false;
                 if (done) {
                     active[ci] = 0;

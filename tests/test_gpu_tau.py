@@ -188,3 +188,38 @@ def test_tau_rejects(fl):
         fl.fl_tau_apply(sq.handle, f, f)
     assert e.value.status == fl.FL_E_INVAL
     sq.close()
+
+
+def test_tau_batched_classes(fl):
+    # power-of-two classes of a batch take the preconditioned inner FP32 CG (a few
+    # iterations per refinement step); a class of another N keeps plain CG.  Every
+    # solution matches the single solve and, at small N, the dense oracle.
+    rng = np.random.default_rng(21)
+    Ns = [32, 64, 32, 24, 64, 128]
+    alphas = [float(a) for a in rng.uniform(0.3, 1.9, len(Ns))]
+    hs = [2.0 / N for N in Ns]
+    fs_np = [inputs.gauss_sum(2, N, 4, seed=400 + i) for i, N in enumerate(Ns)]
+    fs = [_t(f) for f in fs_np]
+    b = fl.Batch(2, Ns, alphas, hs)
+    us, infos = b.solve(fs, tol=1e-10)
+    torch.cuda.synchronize()
+    for i, (N, al) in enumerate(zip(Ns, alphas)):
+        assert infos[i]["status"] == 0 and infos[i]["relres"] <= 1e-10, (i, infos[i])
+        op = fl.Operator(2, al, hs[i], N)
+        r = fs[i] - op.apply(us[i])
+        assert (torch.linalg.norm(r) / torch.linalg.norm(fs[i])).item() <= 1.05e-10
+        u1, i1 = op.poisson_solve(fs[i], tol=1e-11, solver="cg64")
+        assert (torch.abs(us[i] - u1).max() / torch.abs(u1).max()).item() <= 1e-7
+        if N & (N - 1) == 0:
+            assert infos[i]["iters"] <= 40, (i, infos[i])
+        if N <= 32:
+            a = oracle.coeffs(2, al, hs[i], N)
+            uref = oracle.solve_dense(oracle.dense(2, N, al, a), fs_np[i])
+            assert np.abs(us[i].cpu().numpy() - uref).max() <= 1e-7 * np.abs(uref).max()
+        op.close()
+    # the captured graphs replayed on a second solve give the same answers
+    us2, _ = b.solve(fs, tol=1e-10)
+    torch.cuda.synchronize()
+    for i in range(len(Ns)):
+        assert torch.equal(us[i], us2[i])
+    b.close()
