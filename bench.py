@@ -124,7 +124,7 @@ def cpu_baseline(N, alpha, h, u_np, seconds):
 
 def c3_extra(torch, fl, inputs, autotune, N=256, alpha=1.2):
     """3D N=256 (255^3 unknowns, FFT length 512): matvec Gdof/s and per-pass times in FP32 and FP64,
-    then 200 semi-implicit Allen--Cahn steps."""
+    200 semi-implicit Allen--Cahn steps, and the Poisson problem by the preconditioned and plain CG."""
     import numpy as np
     h = 2.0 / N
     M = (N - 1) ** 3
@@ -163,6 +163,22 @@ def c3_extra(torch, fl, inputs, autotune, N=256, alpha=1.2):
                          "inner_iters_per_step": round(sum(iters) / 200, 2), "outer_per_step": round(sum(outer) / 200, 2),
                          "max_abs_u": round(float(u.abs().max()), 6), "tau": 1e-3, "eps": 0.05, "theta": 0.5,
                          "tol": 1e-8}
+    # the Poisson problem on the same cube (f = 4 seeded Gaussians), to 1e-8: the default
+    # sine-transform preconditioned CG against plain FP64 CG
+    f = torch.as_tensor(inputs.gauss_sum(3, N, 4, seed=5), device="cuda:0")
+    pois = {}
+    for solver in ("tau", "cg64"):
+        uu = torch.zeros_like(f)
+        op.poisson_solve(f, tol=1e-8, u=uu, solver=solver)  # warm
+        uu.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = op.poisson_solve(f, tol=1e-8, u=uu, solver=solver)
+        torch.cuda.synchronize()
+        pois[solver] = {"seconds": round(time.perf_counter() - t0, 4), "iters": info["iters"],
+                        "relres": info["relres"]}
+    out["poisson"] = {"workload": "3D N=%d alpha=%.1f, f = sum of 4 seeded Gaussians on (-1,1)^3, tol 1e-8"
+                                  % (N, alpha), **pois}
     op.close()
     return out
 
