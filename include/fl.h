@@ -57,7 +57,8 @@ typedef enum {
 typedef enum { FL_FP64 = 0, FL_FP32 = 1 } fl_prec;
 
 typedef enum {
-    FL_SOLVE_AUTO = 0,    /* TAU where it applies (square and cubic operators, N a
+    FL_SOLVE_AUTO = 0,    /* TAU, or TAU32 from 2^22 unknowns up, where it applies
+                             (square and cubic operators, N a
                              power of two, FFT length 2N <= 2048, s0 + s1 lambda
                              > 0 on the sine modes; in the Allen-Cahn steps only
                              when 2 theta tau kappa A_ii > 0.5, else the system
@@ -69,11 +70,17 @@ typedef enum {
     FL_SOLVE_CG64 = 1,    /* plain conjugate gradients, FP64 matvec and vectors  */
     FL_SOLVE_REFINE = 2,  /* FP64 residual refinement around FP32-matvec CG      */
     FL_SOLVE_FPCG = 3,    /* flexible PCG with the learned preconditioner        */
-    FL_SOLVE_TAU = 4      /* flexible PCG, all FP64, with the sine-transform
+    FL_SOLVE_TAU = 4,     /* flexible PCG, all FP64, with the sine-transform
                              (tau) preconditioner of the system matrix (see
                              fl_tau_apply); square and cubic operators with N a
                              power of two and FFT length 2N <= 2048 only (else
                              FL_E_INVAL).  Falls back to CG64 like FPCG          */
+    FL_SOLVE_TAU32 = 5    /* FP64 residual refinement around FP32 CG
+                             preconditioned by the same sine transform in FP32
+                             (inner tolerance 1e-4 unless inner_tol is set);
+                             same operators as TAU.  AUTO takes it from 2^22
+                             unknowns up, and falls back to TAU from the
+                             current iterate if it fails                         */
 } fl_solver;
 
 typedef struct {

@@ -67,6 +67,7 @@ static void destroy(fl_op op) {
     (void)hipFree(op->T1);
     (void)hipFree(op->T2);
     (void)hipFree(op->mu64t);
+    (void)hipFree(op->mu32t);
     free_solver_workspace(op);
     delete op;
 }

@@ -1065,6 +1065,39 @@ fl_status tau_prepare(fl_op op, double s0, double s1, hipStream_t s) {
     return FL_OK;
 }
 
+fl_status tau_prepare32(fl_op op, double s0, double s1, hipStream_t s) {
+    if (!tau_supported(op)) return tau_symbol(op, s0, s1, FL_FP32, 1, nullptr, s);  // sets the error
+    if (op->mu32t && op->mu32_var == op->var32 && op->mu32_s0 == s0 && op->mu32_s1 == s1) return FL_OK;
+    if (!op->mu32t) {
+        long qrest = 1;
+        for (int k = 1; k < op->d; ++k) qrest *= op->Q;
+        const long len = qrest * (op->Q + kMaxTile - 1);
+        hipError_t e = hipMalloc((void **)&op->mu32t, sizeof(float) * len);
+        if (e != hipSuccess) {
+            op->mu32t = nullptr;
+            set_error("preconditioner symbol: %s", hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? FL_E_NOMEM : FL_E_DEVICE;
+        }
+    }
+    op->mu32_var = -1;
+    FL_TRY(tau_symbol(op, s0, s1, FL_FP32, variant_desc(op, FL_FP32, op->var32).c, op->mu32t, s));
+    op->mu32_var = op->var32;
+    op->mu32_s0 = s0;
+    op->mu32_s1 = s1;
+    return FL_OK;
+}
+
+fl_status tau_apply32(fl_op op, const float *r, float *z, const double *done, hipStream_t s) {
+    if (!op->mu32t || op->mu32_var != op->var32) {
+        set_error("sine-transform preconditioner not prepared for the selected FP32 kernel variant");
+        return FL_E_INVAL;
+    }
+    MvCtx<float> cx = single_ctx<float>(op);
+    cx.lam = op->mu32t;
+    cx.odd = true;
+    return matvec_ctx<float>(cx, op->var32, r, z, Epi<float>{}, done, s);
+}
+
 fl_status tau_apply(fl_op op, const double *r, double *z, const double *done, hipStream_t s) {
     if (!op->mu64t || op->mu_var != op->var64) {
         set_error("sine-transform preconditioner not prepared for the selected kernel variant");

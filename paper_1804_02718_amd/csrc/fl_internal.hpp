@@ -334,6 +334,10 @@ struct fl_op_s {
     double *mu64t = nullptr;
     double mu_s0 = 0.0, mu_s1 = 0.0;
     int mu_var = -1;
+    // the same symbol in FP32 for FP32 variant mu32_var (the FP32 inner solves)
+    float *mu32t = nullptr;
+    double mu32_s0 = 0.0, mu32_s1 = 0.0;
+    int mu32_var = -1;
 };
 
 namespace fl {
@@ -415,6 +419,9 @@ bool tau_supported(const fl_op_s *op);
 fl_status tau_symbol(fl_op op, double s0, double s1, int prec, int C, void *lt, hipStream_t s);
 fl_status tau_prepare(fl_op op, double s0, double s1, hipStream_t s);
 fl_status tau_apply(fl_op op, const double *r, double *z, const double *done, hipStream_t s);
+// FP32 counterparts for the selected FP32 variant
+fl_status tau_prepare32(fl_op op, double s0, double s1, hipStream_t s);
+fl_status tau_apply32(fl_op op, const float *r, float *z, const double *done, hipStream_t s);
 constexpr int kMaxTile = 16;  // largest tile width of any variant
 // longest FFT whose line a workgroup keeps in LDS; longer 2D embeddings (up to
 // 16384) take the global-memory passes of the large-operator path

@@ -15,6 +15,7 @@
 #include <chrono>
 #include <cmath>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "fl_internal.hpp"
@@ -199,16 +200,17 @@ __global__ __launch_bounds__(kVecBlock) void k_cg_p(V *__restrict__ p, const V *
 }
 
 // start of a preconditioned CG run (batched: blockIdx.y = problem): the S_RR
-// slots take (r, z), the stop target rel2z[z] * (r, r) (a negative entry marks
-// the problem as finished); (r, z) <= 0 or a non-finite sum is a breakdown
+// slots take (r, z), the stop target rel2 * (r, r), rel2z[z] overriding rel2
+// when given (a negative entry marks the problem as finished); (r, z) <= 0 or
+// a non-finite sum is a breakdown
 __global__ __launch_bounds__(kVecBlock) void k_pcg_init(const double *part_rr, const double *part_rz, int np,
-                                                        double *scal, const double *rel2z) {
+                                                        double *scal, double rel2_all, const double *rel2z) {
     __shared__ double sh[kVecBlock];
     const int z = blockIdx.y;
     part_rr += z * kMaxParts;
     part_rz += z * kMaxParts;
     scal += z * S_COUNT;
-    const double rel2 = rel2z[z];
+    const double rel2 = rel2z ? rel2z[z] : rel2_all;
     const double rr = sum_parts(part_rr, np, sh);
     const double rz = sum_parts(part_rz, np, sh);
     if (threadIdx.x == 0) {
@@ -295,8 +297,8 @@ static inline int ew_grid(long n) {
 // ---------------------------------------------------------------------------
 struct Work {
     double *r64, *p64, *kp64, *d64, *b64, *q64;
-    float *r32, *p32, *kp32, *d32;
-    double *partA, *partB;
+    float *r32, *p32, *kp32, *d32, *z32;
+    double *partA, *partB, *partC;
 };
 
 static Work work_of(fl_op op) {
@@ -311,11 +313,13 @@ static Work work_of(fl_op op) {
     w.q64 = w.b64 + M;
     w.partA = w.q64 + M;
     w.partB = w.partA + kMaxParts;
-    float *f = (float *)(w.partB + kMaxParts);
+    w.partC = w.partB + kMaxParts;
+    float *f = (float *)(w.partC + kMaxParts);
     w.r32 = f;
     w.p32 = w.r32 + M;
     w.kp32 = w.p32 + M;
     w.d32 = w.kp32 + M;
+    w.z32 = w.d32 + M;
     return w;
 }
 
@@ -331,7 +335,7 @@ void free_solver_workspace(fl_op op) {
 static fl_status ensure_workspace(fl_op op) {
     if (op->sw) return FL_OK;
     const long M = op->M;
-    size_t bytes = sizeof(double) * (6 * M + 2 * kMaxParts) + sizeof(float) * (4 * M + 64);
+    size_t bytes = sizeof(double) * (6 * M + 3 * kMaxParts) + sizeof(float) * (5 * M + 64);
     FL_HIP_TRY(hipMalloc(&op->sw, bytes));
     op->sw_bytes = bytes;
     FL_HIP_TRY(hipMalloc((void **)&op->scal, sizeof(double) * S_COUNT));
@@ -394,17 +398,31 @@ struct CgResult {
 };
 
 // CG on K d = r from d = 0, in place on (d, r), until (r,r) <= rel^2 (r0,r0)
-// or max_it iterations.
+// or max_it iterations.  tau (FP32 only): preconditioned by the sine transform
+// (prepared by tau_prepare32), with (r, z) in the S_RR slots.
 template <typename V>
 static fl_status cg_run(fl_op op, double s0, double s1, V *d, V *r, V *p, V *kp, double rel, int max_it,
-                        int check_every, const Work &w, hipStream_t s, CgResult *res) {
+                        int check_every, const Work &w, hipStream_t s, CgResult *res, bool tau = false) {
     VecLayout L = layout(op->M);
     const long M = op->M;
     hipLaunchKernelGGL(k_zero<V>, dim3(ew_grid(M)), dim3(256), 0, s, d, M);
-    hipLaunchKernelGGL((k_copy_cast<V, V>), dim3(ew_grid(M)), dim3(256), 0, s, p, r, M);
     hipLaunchKernelGGL(k_dot<V>, dim3(L.blocks), dim3(kVecBlock), 0, s, r, r, L.n, L.chunk, w.partB, nullptr);
-    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(kVecBlock), 0, s, w.partB, L.blocks, op->scal, rel * rel, 0.0,
-                       (const double *)nullptr);
+    if constexpr (std::is_same<V, float>::value) {
+        if (tau) {
+            // z = M^{-1} r, p = z, (r, z)
+            FL_TRY(tau_apply32(op, r, w.z32, nullptr, s));
+            hipLaunchKernelGGL((k_copy_cast<float, float>), dim3(ew_grid(M)), dim3(256), 0, s, p, w.z32, M);
+            hipLaunchKernelGGL(k_dot<float>, dim3(L.blocks), dim3(kVecBlock), 0, s, r, w.z32, L.n, L.chunk, w.partC,
+                               nullptr);
+            hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(kVecBlock), 0, s, w.partB, w.partC, L.blocks, op->scal,
+                               rel * rel, (const double *)nullptr);
+        }
+    }
+    if (!tau) {
+        hipLaunchKernelGGL((k_copy_cast<V, V>), dim3(ew_grid(M)), dim3(256), 0, s, p, r, M);
+        hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(kVecBlock), 0, s, w.partB, L.blocks, op->scal, rel * rel, 0.0,
+                           (const double *)nullptr);
+    }
     FL_HIP_TRY(hipGetLastError());
     const double *done = op->scal + S_DONE;
     // (p, Kp) from the matvec's last pass when its workgroups fit the partials array
@@ -412,7 +430,8 @@ static fl_status cg_run(fl_op op, double s0, double s1, V *d, V *r, V *p, V *kp,
                                 sizeof(V) == 8 ? op->var64 : op->var32);
     const bool fused = np_x > 0 && np_x <= kMaxParts;
     int launched = 0;
-    int chunk = check_every > 0 ? check_every : 8;
+    // the preconditioned solves need a few iterations: check after 4, then every 2
+    int chunk = check_every > 0 ? check_every : (tau ? 4 : 8);
     res->iters = 0;
     res->breakdown = false;
     while (launched < max_it) {
@@ -425,14 +444,24 @@ static fl_status cg_run(fl_op op, double s0, double s1, V *d, V *r, V *p, V *kp,
                                    done);
             hipLaunchKernelGGL(k_cg_xr<V>, dim3(L.blocks), dim3(kVecBlock), 0, s, d, r, p, kp, L.n, L.chunk,
                                w.partA, fused ? np_x : L.blocks, w.partB, op->scal, parity);
-            hipLaunchKernelGGL(k_cg_p<V>, dim3(L.blocks), dim3(kVecBlock), 0, s, p, r, L.n, L.chunk, w.partB,
-                               L.blocks, op->scal, parity);
+            if constexpr (std::is_same<V, float>::value) {
+                if (tau) {
+                    FL_TRY(tau_apply32(op, r, w.z32, done, s));
+                    hipLaunchKernelGGL(k_dot<float>, dim3(L.blocks), dim3(kVecBlock), 0, s, r, w.z32, L.n, L.chunk,
+                                       w.partC, done);
+                    hipLaunchKernelGGL(k_pcg_p<float>, dim3(L.blocks), dim3(kVecBlock), 0, s, p, w.z32, L.n,
+                                       L.chunk, w.partB, w.partC, L.blocks, op->scal, parity);
+                }
+            }
+            if (!tau)
+                hipLaunchKernelGGL(k_cg_p<V>, dim3(L.blocks), dim3(kVecBlock), 0, s, p, r, L.n, L.chunk, w.partB,
+                                   L.blocks, op->scal, parity);
         }
         FL_HIP_TRY(hipGetLastError());
         launched += k;
         FL_TRY(read_scalars(op, s));
         if (op->hscal[S_DONE] != 0.0) break;
-        if (check_every <= 0 && chunk < 128) chunk *= 2;
+        if (check_every <= 0) chunk = tau ? 2 : (chunk < 128 ? 2 * chunk : chunk);
     }
     FL_TRY(read_scalars(op, s));
     res->iters = (int)op->hscal[S_ITER];
@@ -441,12 +470,14 @@ static fl_status cg_run(fl_op op, double s0, double s1, V *d, V *r, V *p, V *kp,
 }
 
 // Solve K x = b to ||b - K x|| <= tol ||b||; x holds the initial guess.
-// inner64: FP64 inner solves (plain CG), else FP32 inner solves.
+// inner64: FP64 inner solves (plain CG), else FP32 inner solves; tau: the FP32
+// inner solves preconditioned by the sine transform.
 // r_given: w.r64 already holds b - K x for the initial x (saves the first FP64 matvec)
 static fl_status refine(fl_op op, double s0, double s1, const double *b, double *x, double tol, bool inner64,
                         double inner_tol, int max_iter, int check_every, fl_info *info, hipStream_t s,
-                        bool r_given = false) {
+                        bool r_given = false, bool tau = false) {
     FL_TRY(ensure_workspace(op));
+    if (tau) FL_TRY(tau_prepare32(op, s0, s1, s));
     Work w = work_of(op);
     const long M = op->M;
     double bb = 0.0;
@@ -506,7 +537,8 @@ static fl_status refine(fl_op op, double s0, double s1, const double *b, double 
             hipLaunchKernelGGL(k_axpy_to64<double>, dim3(ew_grid(M)), dim3(256), 0, s, x, w.d64, M);
         } else {
             hipLaunchKernelGGL((k_copy_cast<float, double>), dim3(ew_grid(M)), dim3(256), 0, s, w.r32, w.r64, M);
-            FL_TRY(cg_run<float>(op, s0, s1, w.d32, w.r32, w.p32, w.kp32, itol, budget, check_every, w, s, &cr));
+            FL_TRY(cg_run<float>(op, s0, s1, w.d32, w.r32, w.p32, w.kp32, itol, budget, check_every, w, s, &cr,
+                                 tau));
             hipLaunchKernelGGL(k_axpy_to64<float>, dim3(ew_grid(M)), dim3(256), 0, s, x, w.d32, M);
         }
         FL_HIP_TRY(hipGetLastError());
@@ -746,6 +778,12 @@ static fl_status fpcg(fl_op op, int kind, double s0, double s1, const double *f,
     return st;
 }
 
+// AUTO takes the FP32 inner solves (TAU32) from this many unknowns up.  Each
+// refinement step costs an FP64 residual and a host check, which the cheaper
+// FP32 passes repay only on large grids: 3D N = 256 (16.6M unknowns) to 1e-8 in
+// 15 ms against 21 ms with TAU; 2D N = 1024 (1M) in 1.5 ms against 1.3 ms.
+constexpr int64_t kTau32Min = (int64_t)1 << 22;
+
 static int default_max_iter(fl_op op) {
     return (int)(50.0 * std::pow((double)op->M, 1.0 / op->d) + 1000.0);
 }
@@ -763,8 +801,8 @@ fl_status fl_poisson_solve_ex(fl_op op, const double *f, double tol, double *u, 
     if (f == u) { set_error("f and u must differ"); return FL_E_INVAL; }
     fl_solve_opts o = {FL_SOLVE_AUTO, 0, 0, 0, 0.0};
     if (opts) o = *opts;
-    if (o.solver < FL_SOLVE_AUTO || o.solver > FL_SOLVE_TAU) { set_error("unknown solver"); return FL_E_INVAL; }
-    if (o.solver == FL_SOLVE_TAU && !tau_supported(op)) {
+    if (o.solver < FL_SOLVE_AUTO || o.solver > FL_SOLVE_TAU32) { set_error("unknown solver"); return FL_E_INVAL; }
+    if ((o.solver == FL_SOLVE_TAU || o.solver == FL_SOLVE_TAU32) && !tau_supported(op)) {
         set_error("TAU needs a square or cubic operator with N a power of two (FFT length 2N <= %d)", kMaxLdsP);
         return FL_E_INVAL;
     }
@@ -786,15 +824,32 @@ fl_status fl_poisson_solve_ex(fl_op op, const double *f, double tol, double *u, 
     bool solved = false;
     // AUTO: the sine-transform preconditioned CG wherever it applies (square and
     // cubic operators; a handful of iterations at every size, against hundreds
-    // for CG at alpha >= 1)
-    if (o.solver == FL_SOLVE_TAU || (o.solver == FL_SOLVE_AUTO && tau_supported(op))) {
-        st = tau_prepare(op, 0.0, 1.0, s);
-        if (st == FL_OK) {
+    // for CG at alpha >= 1): the FP64 flexible solve (TAU), or from kTau32Min
+    // unknowns up FP32 inner solves in FP64 refinement (TAU32), which falls back
+    // to TAU from the current iterate if it fails
+    if (o.solver == FL_SOLVE_TAU || o.solver == FL_SOLVE_TAU32 ||
+        (o.solver == FL_SOLVE_AUTO && tau_supported(op))) {
+        const bool t32 = o.solver == FL_SOLVE_TAU32 || (o.solver == FL_SOLVE_AUTO && op->M >= kTau32Min);
+        st = t32 ? tau_prepare32(op, 0.0, 1.0, s) : tau_prepare(op, 0.0, 1.0, s);
+        if (st == FL_OK && t32) {
+            const double itol = o.inner_tol > 0.0 ? o.inner_tol : 1e-4;
+            st = refine(op, 0.0, 1.0, f, u, tol, false, itol, max_iter, o.check_every, inf, s, false, true);
+            if (st != FL_OK && o.solver == FL_SOLVE_AUTO && std::isfinite(inf->relres) &&
+                tau_prepare(op, 0.0, 1.0, s) == FL_OK) {
+                fl_info sub{};
+                st = fpcg(op, PREC_TAU, 0.0, 1.0, f, u, tol, max_iter, &sub, s);
+                inf->iters += sub.iters;
+                inf->outer_iters += sub.outer_iters;
+                inf->relres = sub.relres;
+                inf->fell_back = 1;
+            }
+            solved = true;
+        } else if (st == FL_OK) {
             st = fpcg(op, PREC_TAU, 0.0, 1.0, f, u, tol, max_iter, inf, s);  // falls back to CG itself
             solved = true;
         } else {
             // AUTO without a positive symbol on the sine modes takes the plain solvers
-            solved = o.solver == FL_SOLVE_TAU || st != FL_E_BREAKDOWN;
+            solved = o.solver != FL_SOLVE_AUTO || st != FL_E_BREAKDOWN;
         }
     }
     if (!solved && o.solver == FL_SOLVE_FPCG) {
@@ -832,11 +887,12 @@ fl_status fl_allen_cahn_step_gen(fl_op op, double *u, double tau, double kappa, 
     if (!std::isfinite(gamma) || !std::isfinite(shift)) { set_error("gamma and shift must be finite"); return FL_E_INVAL; }
     if (!(theta > 0.0 && theta <= 1.0)) { set_error("theta must lie in (0,1]"); return FL_E_INVAL; }
     if (!(tol > 0.0)) { set_error("tol must be positive"); return FL_E_INVAL; }
-    if (solver != FL_SOLVE_AUTO && solver != FL_SOLVE_REFINE && solver != FL_SOLVE_CG64 && solver != FL_SOLVE_TAU) {
-        set_error("solver must be AUTO, REFINE, CG64 or TAU");
+    if (solver != FL_SOLVE_AUTO && solver != FL_SOLVE_REFINE && solver != FL_SOLVE_CG64 && solver != FL_SOLVE_TAU &&
+        solver != FL_SOLVE_TAU32) {
+        set_error("solver must be AUTO, REFINE, CG64, TAU or TAU32");
         return FL_E_INVAL;
     }
-    if (solver == FL_SOLVE_TAU && !tau_supported(op)) {
+    if ((solver == FL_SOLVE_TAU || solver == FL_SOLVE_TAU32) && !tau_supported(op)) {
         set_error("TAU needs a square or cubic operator with N a power of two (FFT length 2N <= %d)", kMaxLdsP);
         return FL_E_INVAL;
     }
@@ -864,14 +920,29 @@ fl_status fl_allen_cahn_step_gen(fl_op op, double *u, double tau, double kappa, 
     const double spread = theta * sc * 2.0 * (-op->c * op->a0);
     fl_status st = FL_OK;
     bool solved = false;
-    if (solver == FL_SOLVE_TAU || (solver == FL_SOLVE_AUTO && tau_supported(op) && spread > 0.5)) {
-        st = tau_prepare(op, 1.0, theta * sc, s);
-        if (st == FL_OK) {
+    if (solver == FL_SOLVE_TAU || solver == FL_SOLVE_TAU32 ||
+        (solver == FL_SOLVE_AUTO && tau_supported(op) && spread > 0.5)) {
+        const bool t32 = solver == FL_SOLVE_TAU32 || (solver == FL_SOLVE_AUTO && op->M >= kTau32Min);
+        st = t32 ? tau_prepare32(op, 1.0, theta * sc, s) : tau_prepare(op, 1.0, theta * sc, s);
+        if (st == FL_OK && t32) {
+            st = refine(op, 1.0, theta * sc, w.b64, u, tol, false, 1e-4, default_max_iter(op), 0, inf, s, true,
+                        true);
+            if (st != FL_OK && solver == FL_SOLVE_AUTO && std::isfinite(inf->relres) &&
+                tau_prepare(op, 1.0, theta * sc, s) == FL_OK) {
+                fl_info sub{};
+                st = fpcg(op, PREC_TAU, 1.0, theta * sc, w.b64, u, tol, default_max_iter(op), &sub, s);
+                inf->iters += sub.iters;
+                inf->outer_iters += sub.outer_iters;
+                inf->relres = sub.relres;
+                inf->fell_back = 1;
+            }
+            solved = true;
+        } else if (st == FL_OK) {
             st = fpcg(op, PREC_TAU, 1.0, theta * sc, w.b64, u, tol, default_max_iter(op), inf, s, true);
             solved = true;
         } else {
             // r64 still holds the initial residual for refine
-            solved = solver == FL_SOLVE_TAU || st != FL_E_BREAKDOWN;
+            solved = solver != FL_SOLVE_AUTO || st != FL_E_BREAKDOWN;
         }
     }
     if (!solved)
@@ -1263,7 +1334,7 @@ fl_status fl_batch_poisson_solve(fl_batch b, const double *const *f, double *con
                 hipLaunchKernelGGL(k_dot<float>, dim3(L.blocks, c.B), dim3(kVecBlock), 0, c.s, c.r32, c.z32, L.n,
                                    L.chunk, c.partC, (const double *)nullptr);
                 hipLaunchKernelGGL(k_pcg_init, dim3(1, c.B), dim3(kVecBlock), 0, c.s, c.partB, c.partC, L.blocks,
-                                   c.scal, (const double *)c.rel2);
+                                   c.scal, 0.0, (const double *)c.rel2);
             } else {
                 hipLaunchKernelGGL((k_copy_cast<float, float>), dim3(ew_grid(BM)), dim3(256), 0, c.s, c.p32, c.r32,
                                    BM);

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libfl.so")
 
 FL_OK, FL_E_INVAL, FL_E_NOMEM, FL_E_DEVICE, FL_E_NOCONV, FL_E_BREAKDOWN, FL_E_UNSUPPORTED = range(7)
 FL_FP64, FL_FP32 = 0, 1
-SOLVERS = {"auto": 0, "cg64": 1, "refine": 2, "fpcg": 3, "tau": 4}
+SOLVERS = {"auto": 0, "cg64": 1, "refine": 2, "fpcg": 3, "tau": 4, "tau32": 5}
 
 EXPORTED = ["fl_coeffs", "fl_apply", "fl_apply_profiled", "fl_variant_count", "fl_variant_info",
             "fl_select_variant", "fl_autotune", "fl_batch_create", "fl_batch_poisson_solve", "fl_batch_info",

@@ -61,18 +61,24 @@ def test_tau_apply_follows_the_selected_variant(fl, d, N):
     op.close()
 
 
+# iteration bounds: TAU counts FP64 flexible-CG iterations; TAU32 the FP32 inner
+# iterations summed over its refinement steps
+ITER_CAP = {"tau": 25, "tau32": 45, "auto": 45}
+
+
 @pytest.mark.parametrize("d,N,alpha", [(1, 4, 0.9), (1, 64, 1.3), (1, 256, 1.9), (2, 4, 0.5), (2, 16, 1.9),
                                        (2, 32, 1.0), (3, 4, 1.6), (3, 8, 1.2), (3, 16, 0.6)])
-def test_tau_poisson_vs_dense(fl, d, N, alpha):
+@pytest.mark.parametrize("solver", ["tau", "tau32"])
+def test_tau_poisson_vs_dense(fl, d, N, alpha, solver):
     h = 2.0 / N
     op = fl.Operator(d, alpha, h, N)
     a = oracle.coeffs(d, alpha, h, N)
     A = oracle.dense(d, N, alpha, a)
     f = inputs.gauss_sum(d, N, 4, seed=2)
     uref = oracle.solve_dense(A, f)
-    u, info = op.poisson_solve(_t(f), tol=1e-11, solver="tau")
+    u, info = op.poisson_solve(_t(f), tol=1e-11, solver=solver)
     ug = u.cpu().numpy()
-    assert info["fell_back"] == 0 and info["iters"] <= 25
+    assert info["fell_back"] == 0 and info["iters"] <= ITER_CAP[solver], info
     assert np.linalg.norm(f - A @ ug) <= 1.05e-11 * np.linalg.norm(f)
     cond = np.linalg.cond(A)
     assert np.abs(ug - uref).max() <= 2e-11 * cond * np.abs(uref).max()
@@ -80,7 +86,7 @@ def test_tau_poisson_vs_dense(fl, d, N, alpha):
 
 
 @pytest.mark.parametrize("alpha", [0.5, 1.5, 1.9])
-@pytest.mark.parametrize("solver", ["tau", "auto"])
+@pytest.mark.parametrize("solver", ["tau", "tau32", "auto"])
 def test_tau_c2_poisson_full_size(fl, alpha, solver):
     # 2D N = 1024 on (-1,1)^2, f = 8 seeded Gaussians, relative residual 1e-8; AUTO
     # takes the preconditioned solve on this square
@@ -91,7 +97,7 @@ def test_tau_c2_poisson_full_size(fl, alpha, solver):
     f = _t(f_np)
     op = fl.Operator(2, alpha, h, N)
     u, info = op.poisson_solve(f, tol=1e-8, solver=solver)
-    assert info["relres"] <= 1e-8 and info["fell_back"] == 0 and info["iters"] <= 25
+    assert info["relres"] <= 1e-8 and info["fell_back"] == 0 and info["iters"] <= ITER_CAP[solver], info
     r = f - op.apply(u)
     assert (torch.linalg.norm(r) / torch.linalg.norm(f)).item() <= 1.01e-8
     # residual rows with the oracle's explicit sum: ||r||_inf <= ||r||_2 <= tol ||f||_2
@@ -106,7 +112,8 @@ def test_tau_c2_poisson_full_size(fl, alpha, solver):
     op.close()
 
 
-def test_tau_c3_poisson_full_size(fl):
+@pytest.mark.parametrize("solver", ["tau", "auto"])
+def test_tau_c3_poisson_full_size(fl, solver):
     # 3D N = 256 (255^3 unknowns), alpha = 1.2, relative residual 1e-8
     N, alpha = 256, 1.2
     h = 2.0 / N
@@ -114,8 +121,8 @@ def test_tau_c3_poisson_full_size(fl):
     f_np = inputs.gauss_sum(3, N, 4, seed=5)
     f = _t(f_np)
     op = fl.Operator(3, alpha, h, N)
-    u, info = op.poisson_solve(f, tol=1e-8, solver="tau")
-    assert info["relres"] <= 1e-8 and info["fell_back"] == 0 and info["iters"] <= 25
+    u, info = op.poisson_solve(f, tol=1e-8, solver=solver)
+    assert info["relres"] <= 1e-8 and info["fell_back"] == 0 and info["iters"] <= ITER_CAP[solver], info
     a = oracle.coeffs(3, alpha, h, N)
     rows = np.random.default_rng(6).choice(M, 6, replace=False)
     res = f_np[rows] - oracle.apply_rows(3, N, alpha, a, u.cpu().numpy(), rows)
@@ -125,7 +132,8 @@ def test_tau_c3_poisson_full_size(fl):
 
 @pytest.mark.parametrize("d,N", [(1, 64), (2, 8), (2, 32), (3, 8)])
 @pytest.mark.parametrize("theta", [0.5, 1.0])
-def test_tau_allen_cahn_steps_vs_oracle(fl, d, N, theta):
+@pytest.mark.parametrize("solver", ["tau", "tau32"])
+def test_tau_allen_cahn_steps_vs_oracle(fl, d, N, theta, solver):
     alpha, tau, eps = 1.2, 1e-3, 0.05
     h = 2.0 / N
     op = fl.Operator(d, alpha, h, N)
@@ -135,14 +143,15 @@ def test_tau_allen_cahn_steps_vs_oracle(fl, d, N, theta):
     ug = _t(u0)
     ur = u0.copy()
     for _ in range(4):
-        info = op.allen_cahn_step(ug, tau, eps, theta=theta, tol=1e-13, solver="tau")
+        info = op.allen_cahn_step(ug, tau, eps, theta=theta, tol=1e-13, solver=solver)
         ur = oracle.ac_step(d, N, alpha, a, ur, tau, eps, theta, A=A)
         assert info["relres"] <= 1e-13 and info["fell_back"] == 0
     assert np.abs(ug.cpu().numpy() - ur).max() < 1e-11
     op.close()
 
 
-def test_tau_allen_cahn_paper_form(fl):
+@pytest.mark.parametrize("solver", ["tau", "tau32"])
+def test_tau_allen_cahn_paper_form(fl, solver):
     # Sec. 5.3's form (u = -1 outside, reaction delta^{-alpha}), in ubar = u + 1
     N, alpha, delta, tau = 32, 1.5, 0.03, 5e-4
     h = 1.0 / N
@@ -154,7 +163,7 @@ def test_tau_allen_cahn_paper_form(fl):
     ug = _t(u0)
     ur = u0.copy()
     for _ in range(3):
-        info = op.allen_cahn_step_gen(ug, tau, 1.0, gamma, 1.0, tol=1e-12, solver="tau")
+        info = op.allen_cahn_step_gen(ug, tau, 1.0, gamma, 1.0, tol=1e-12, solver=solver)
         ur = oracle.ac_step_gen(2, N, alpha, a, ur, tau, 1.0, gamma, 1.0, 0.5, A=A)
         assert info["relres"] <= 1e-12
     assert np.abs(ug.cpu().numpy() - ur).max() < 1e-9 * np.abs(ur).max()
@@ -168,9 +177,10 @@ def test_tau_rejects(fl):
     non_pow2 = fl.Operator(2, 1.2, 2.0 / 12, 12)
     for op in (box, non_pow2):
         f = f2(op.M)
-        with pytest.raises(fl.FlError) as e:
-            op.poisson_solve(f, tol=1e-8, solver="tau")
-        assert e.value.status == fl.FL_E_INVAL
+        for solver in ("tau", "tau32"):
+            with pytest.raises(fl.FlError) as e:
+                op.poisson_solve(f, tol=1e-8, solver=solver)
+            assert e.value.status == fl.FL_E_INVAL
         with pytest.raises(fl.FlError) as e:
             op.tau_apply(f)
         assert e.value.status == fl.FL_E_UNSUPPORTED
