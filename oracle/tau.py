@@ -31,6 +31,15 @@ M = s0 I + s1 tau(T) from the first form; ``tau_matrix_gen`` writes the
 second form out entry by entry.  The tests pin the first against the second,
 and against the central-difference Laplacian, which lies in the class (its
 tau matrix is itself).
+
+Where the circulant embedding of the scheme's matrix (period P per axis, the
+smallest power of two >= max(8, 2n - 1)) is longer than 2(n + 1) -- every N
+that is not a power of two, and every box -- the preconditioner lives on the
+n' = P/2 - 1 nodes whose sine basis the embedding's transforms provide: the
+tau matrix of the n'-node Toeplitz matrix with the same generator (t_m = 0
+for m >= n), inverted, and restricted to the operator's nodes (a principal
+submatrix of an SPD matrix, so SPD).  It requires n <= n' on every axis,
+which fails only for N = 2^k + 1.
 """
 
 import numpy as np
@@ -109,8 +118,30 @@ def generator(d: int, N: int, alpha: float, a: np.ndarray) -> np.ndarray:
     return -const(d, alpha) * a[sl]
 
 
+def embedding_nodes(N: int) -> int:
+    """n' = P/2 - 1 for the embedding period P = the smallest power of two >= max(8, 2n - 1)."""
+    n = N - 1
+    P = 8
+    while P < 2 * n - 1:
+        P *= 2
+    return P // 2 - 1
+
+
 def tau_apply(d: int, N: int, alpha: float, a: np.ndarray, r: np.ndarray, s0: float = 0.0,
-              s1: float = 1.0) -> np.ndarray:
-    """The sine-transform preconditioner of s0 I + s1 A, A the scheme's matrix on the
-    square or cube with N intervals per axis, applied to r."""
-    return tau_apply_gen(generator(d, N, alpha, a), r, s0, s1)
+              s1: float = 1.0, shape=None) -> np.ndarray:
+    """The sine-transform preconditioner of s0 I + s1 A applied to r, A the scheme's
+    matrix with N intervals per axis on the square or cube, or on the box of
+    ``shape`` interior nodes per axis (x first): the tau matrix on the n' nodes of
+    the embedding, inverted and restricted to the operator's nodes."""
+    n = N - 1
+    n2 = embedding_nodes(N)
+    nk = [n] * d if shape is None else [int(k) for k in shape]
+    if max(nk) > n2:
+        raise ValueError("no sine basis of the embedding holds %d nodes (n' = %d)" % (max(nk), n2))
+    t = np.zeros((n2,) * d)
+    t[tuple([slice(0, n)] * d)] = generator(d, N, alpha, a)
+    idx = tuple(slice(0, k) for k in reversed(nk))  # numpy order: the last axis is x
+    R = np.zeros((n2,) * d)
+    R[idx] = np.asarray(r, dtype=np.float64).reshape(tuple(reversed(nk)))
+    z = tau_apply_gen(t, R.ravel(), s0, s1).reshape((n2,) * d)
+    return z[idx].ravel()

@@ -95,3 +95,36 @@ def test_preconditioned_spectrum_is_clustered(N, alpha):
     Minv = np.stack([tau.tau_apply_gen(t, E[:, k]) for k in range(E.shape[0])], 1)
     ev = np.linalg.eigvals(Minv @ A).real
     assert ev.min() > 0.6 and ev.max() < 1.01
+
+
+@pytest.mark.parametrize("d,N,shape", [(1, 12, None), (2, 6, None), (2, 8, (7, 4)), (2, 10, (9, 5)), (3, 6, None),
+                                       (3, 8, (7, 3, 5))])
+def test_restricted_preconditioner_is_a_principal_submatrix(d, N, shape):
+    # off the power-of-two squares the preconditioner is the inverse of the tau matrix on
+    # the embedding's n' nodes, restricted to the operator's nodes: check against the
+    # two-Hankel form of that tau matrix, inverted densely
+    alpha = 1.3
+    a = oracle.coeffs(d, alpha, 2.0 / N, N)
+    n, n2 = N - 1, tau.embedding_nodes(N)
+    nk = [n] * d if shape is None else list(shape)
+    t = np.zeros((n2,) * d)
+    t[tuple([slice(0, n)] * d)] = tau.generator(d, N, alpha, a)
+    Minv = np.linalg.inv(tau.tau_matrix_gen(t))
+    # operator nodes in the n'-grid's flat (numpy) order
+    keep = np.zeros((n2,) * d, dtype=bool)
+    keep[tuple(slice(0, k) for k in reversed(nk))] = True
+    sel = np.flatnonzero(keep.ravel())
+    r = np.random.default_rng(5).standard_normal(int(np.prod(nk)))
+    z = tau.tau_apply(d, N, alpha, a, r, shape=shape)
+    assert np.abs(z - Minv[np.ix_(sel, sel)] @ r).max() < 1e-12 * np.abs(z).max()
+    if shape is None and n == n2:
+        assert np.array_equal(z, tau.tau_apply_gen(tau.generator(d, N, alpha, a), r))
+
+
+def test_embedding_nodes_and_the_excluded_sizes():
+    # P = max(8, 2^ceil(log2(2n - 1))): n' = n on power-of-two N, n' < n only for N = 2^k + 1
+    assert [tau.embedding_nodes(N) for N in (4, 8, 16, 1024)] == [3, 7, 15, 1023]
+    assert [tau.embedding_nodes(N) for N in (6, 12, 100, 700)] == [7, 15, 127, 1023]
+    assert all(tau.embedding_nodes(N) == N - 2 for N in (5, 9, 17, 1025))
+    with pytest.raises(ValueError):
+        tau.tau_apply(2, 17, 1.0, oracle.coeffs(2, 1.0, 2.0 / 17, 17), np.zeros(16 * 16))
