@@ -58,8 +58,8 @@ typedef enum { FL_FP64 = 0, FL_FP32 = 1 } fl_prec;
 
 typedef enum {
     FL_SOLVE_AUTO = 0,    /* TAU, or TAU32 from 2^22 unknowns up, where it applies
-                             (square and cubic operators, N a
-                             power of two, FFT length 2N <= 2048, s0 + s1 lambda
+                             (FFT length P <= 2048, at most P/2 - 1 nodes per
+                             axis, i.e. every N but 2^k + 1, s0 + s1 lambda
                              > 0 on the sine modes; in the Allen-Cahn steps only
                              when 2 theta tau kappa A_ii > 0.5, else the system
                              is close to the identity); otherwise, Poisson:
@@ -72,9 +72,9 @@ typedef enum {
     FL_SOLVE_FPCG = 3,    /* flexible PCG with the learned preconditioner        */
     FL_SOLVE_TAU = 4,     /* flexible PCG, all FP64, with the sine-transform
                              (tau) preconditioner of the system matrix (see
-                             fl_tau_apply); square and cubic operators with N a
-                             power of two and FFT length 2N <= 2048 only (else
-                             FL_E_INVAL).  Falls back to CG64 like FPCG          */
+                             fl_tau_apply); FFT length <= 2048 and at most P/2
+                             - 1 nodes per axis (else FL_E_INVAL).  Falls back
+                             to CG64 like FPCG                                   */
     FL_SOLVE_TAU32 = 5    /* FP64 residual refinement around FP32 CG
                              preconditioned by the same sine transform in FP32
                              (inner tolerance 1e-4 unless inner_tol is set);
@@ -176,21 +176,24 @@ fl_status fl_apply(fl_op op, const void *u, void *y, int prec, void *stream);
 
 /*
  * fl_tau_apply -- z = M^{-1} r for the sine-transform (tau) preconditioner M of
- * K = s0 I + s1 A (s0, s1 >= 0, not both 0).  On the square or cube the n =
- * N - 1 nodes per axis make the sine vectors sin(pi j k / N), k = 1..n, a
- * basis; M is the matrix of the tau class (diagonal in that basis) whose
- * eigenvalues are the circulant symbol of K at the frequencies pi k / N, i.e.
- * K minus its two Hankel corrections (for the Toeplitz levels of A: entries
- * t_{i+j+2} and t_{2n-i-j}).  Computed by the matvec's passes on the odd
- * extension of r with the symbol 1 / (s0 + s1 lambda), in FP64; the sine basis
- * needs the FFT length to be exactly 2N (N a power of two, N >= 4).  Not part of
- * the paper's scheme: a preconditioner for its CG solves (Sec. 5.2-5.3).
+ * K = s0 I + s1 A (s0, s1 >= 0, not both 0).  With P the embedding's FFT
+ * length, the n' = P/2 - 1 nodes per axis make the sine vectors
+ * sin(pi j k / (n' + 1)), k = 1..n', a basis; the tau matrix of K on them
+ * (diagonal in that basis) has the circulant symbol of K at the frequencies
+ * pi k / (n' + 1) as eigenvalues, i.e. K minus its two Hankel corrections
+ * (for the Toeplitz levels of A: entries t_{i+j+2} and t_{2n'-i-j}).  On
+ * power-of-two squares and cubes n' = n and M is that matrix; otherwise (other
+ * N, boxes) M^{-1} is its inverse restricted to the operator's nodes, which
+ * needs at most n' nodes per axis (every N but 2^k + 1).  Computed by the
+ * matvec's passes on the odd extension of r with the symbol 1 / (s0 + s1
+ * lambda), in FP64.  Not part of the paper's scheme: a preconditioner for its
+ * CG solves (Sec. 5.2-5.3).
  * r, z: device double vectors of M entries, not overlapping.  The symbol is
  * rebuilt when (s0, s1) or the FP64 kernel variant change (a synchronising
  * step); then asynchronous on `stream`.  Errors: FL_E_INVAL (null, overlap,
- * s0/s1), FL_E_UNSUPPORTED (box, N not a power of two, or FFT length above
- * 2048), FL_E_BREAKDOWN
- * (s0 + s1 lambda not positive on a sine mode), FL_E_NOMEM, FL_E_DEVICE.
+ * s0/s1), FL_E_UNSUPPORTED (more than P/2 - 1 nodes on an axis, or FFT length
+ * above 2048), FL_E_BREAKDOWN (s0 + s1 lambda not positive on a sine mode),
+ * FL_E_NOMEM, FL_E_DEVICE.
  */
 fl_status fl_tau_apply(fl_op op, const double *r, double *z, double s0, double s1,
                        void *stream);
@@ -291,10 +294,11 @@ fl_status fl_autotune(fl_op op, int prec, int reps, void *stream, int *best, flo
  *                              the problems into size classes of equal N; each
  *                              class runs all of its problems in every kernel
  *                              launch, and its inner CG iterations are replayed
- *                              from a captured hipGraph.  A class of a power-of-
- *                              two N whose every problem has a positive symbol
- *                              on the sine modes preconditions its inner CG by
- *                              the sine transform (FP32, as fl_tau_apply).
+ *                              from a captured hipGraph.  A class whose N is
+ *                              not 2^k + 1 and whose every problem has a
+ *                              positive symbol on the sine modes preconditions
+ *                              its inner CG by the sine transform (FP32, as
+ *                              fl_tau_apply).
  *                              Synchronises.
  *   fl_batch_poisson_solve  -- solves A_i u_i = f_i to ||f_i - A_i u_i||_2 <=
  *                              tol ||f_i||_2 (FP64 residual refinement around

@@ -986,25 +986,27 @@ fl_status select_variant(fl_op op, int prec, int k, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// sine-transform (tau) preconditioner of K = s0 I + s1 A on the square or cube.
-// The n = P/2 - 1 nodes per axis make the sine vectors sin(pi j k / (n + 1))
-// eigenvectors of every matrix S diag(mu) S; with mu the circulant symbol of
-// K at the sine frequencies this is the tau-class matrix of K (K minus its two
+// sine-transform (tau) preconditioner of K = s0 I + s1 A.  On n' = P/2 - 1
+// nodes per axis the sine vectors sin(pi j k / (n' + 1)) are eigenvectors of
+// every matrix S diag(mu) S; with mu the circulant symbol of K at the sine
+// frequencies this is the tau-class matrix of the n'-node K (K minus its two
 // Hankel corrections).  Its inverse applied to r is the circulant of symbol
 // 1 / mu on the odd extension of r, cropped: the matvec's passes with the
-// odd loads and the inverted symbol.
+// odd loads and the inverted symbol.  On power-of-two squares and cubes
+// n' = n; otherwise r is zero-extended to the n' grid and the result
+// restricted to the operator's nodes, which needs n_k <= n' on every axis.
 // ---------------------------------------------------------------------------
 bool tau_supported(const fl_op_s *op) {
     if (large_op(op)) return false;
     for (int k = 0; k < op->d; ++k)
-        if (op->nk[k] != op->P / 2 - 1) return false;
+        if (op->nk[k] > op->P / 2 - 1) return false;
     return true;
 }
 
 fl_status tau_symbol(fl_op op, double s0, double s1, int prec, int C, void *lt, hipStream_t s) {
     if (!tau_supported(op)) {
-        set_error("the sine-transform preconditioner needs a square or cubic operator with N a power of two "
-                  "(FFT length 2N <= %d)", kMaxLdsP);
+        set_error("the sine-transform preconditioner needs at most P/2 - 1 nodes per axis (N not 2^k + 1) and "
+                  "FFT length P <= %d", kMaxLdsP);
         return FL_E_UNSUPPORTED;
     }
     if (!(s0 >= 0.0) || !(s1 >= 0.0) || !(s0 + s1 > 0.0) || !std::isfinite(s0) || !std::isfinite(s1)) {

@@ -174,10 +174,11 @@ template <int P, typename PL, int S> __device__ __forceinline__ int out_pos(int 
 // j mod R[0] < R[0]/2, so the half a slot falls in is known at compile time.
 //   n_in > P/2        zero past n_in;
 //   0 <= n_in <= P/2  zero-padded: the upper half is zero and is not loaded;
-//   n_in < 0          odd extension about -1 of n = -n_in = P/2 - 1 values:
-//                     x[p] for p < n, -x[P - 2 - p] for P/2 <= p <= P - 2,
-//                     zero at p = n and p = P - 1.  Its transform holds only
-//                     the sine modes (the Dirichlet sine basis of n points).
+//   n_in < 0          odd extension about -1, over the P/2 - 1 points of the
+//                     sine basis, of n = -n_in <= P/2 - 1 stored values:
+//                     x[p] for p < n, -x[P - 2 - p] where P - 2 - p < n,
+//                     zero elsewhere.  Its transform holds only the sine modes
+//                     (the Dirichlet sine basis of P/2 - 1 points).
 template <typename T, int P, typename PL, typename Ld>
 __device__ __forceinline__ void load_line(C2<T> *v, int tl, int n_in, Ld ld) {
     constexpr int R = PL::R[0], E = PL::E;
@@ -193,7 +194,7 @@ __device__ __forceinline__ void load_line(C2<T> *v, int tl, int n_in, Ld ld) {
                 v[j] = ok ? x : zero;
             } else {
                 const int src = P - 2 - pos;
-                const bool ok = src >= 0;
+                const bool ok = src >= 0 && src < -n_in;
                 const C2<T> x = ld(ok ? src : 0);
                 v[j] = ok ? mk<T>(-x.x, -x.y) : zero;
             }
@@ -410,8 +411,10 @@ inline long lam_tiled_len(int d, int P, int C) {
     return d == 1 ? Q : d == 2 ? nt * C * Q + Q : nt * C * Q * Q;
 }
 fl_status select_variant(fl_op op, int prec, int k, hipStream_t s);
-// sine-transform preconditioner of s0 I + s1 A (square or cubic operators with
-// FFT length <= kMaxLdsP): tau_prepare builds its FP64 symbol for the selected
+// sine-transform preconditioner of s0 I + s1 A (operators on the LDS path whose
+// every axis has at most P/2 - 1 nodes; on power-of-two squares and cubes the tau
+// matrix itself, elsewhere the inverse of the tau matrix on the embedding's
+// P/2 - 1 nodes restricted to the operator's): tau_prepare builds its FP64 symbol for the selected
 // FP64 variant (FL_E_BREAKDOWN when s0 + s1 lambda is not positive on a sine
 // mode); tau_apply computes z = M^{-1} r in FP64 (a set `done` flag skips it)
 bool tau_supported(const fl_op_s *op);

@@ -170,12 +170,53 @@ def test_tau_allen_cahn_paper_form(fl, solver):
     op.close()
 
 
+@pytest.mark.parametrize("d,N,shape,alpha,s0,s1", [
+    (2, 12, None, 1.2, 0.0, 1.0), (2, 100, None, 1.7, 0.0, 1.0), (2, 32, (31, 11), 0.8, 0.0, 1.0),
+    (2, 64, (40, 63), 1.5, 1.0, 2e-3), (3, 12, None, 1.1, 0.0, 1.0), (3, 16, (15, 6, 9), 1.6, 0.0, 1.0),
+    (1, 100, None, 1.3, 0.0, 1.0)])
+def test_tau_apply_restricted_matches_oracle(fl, d, N, shape, alpha, s0, s1):
+    # off the power-of-two squares: the tau matrix on the embedding's P/2 - 1 nodes,
+    # inverted and restricted to the operator's nodes (boxes, other N)
+    h = 2.0 / N
+    op = fl.Operator(d, alpha, h, N) if shape is None else fl.Operator(d, alpha, h, None, Nk=[k + 1 for k in shape])
+    a = oracle.coeffs(d, alpha, h, N)
+    M = op.M
+    r = np.random.default_rng(N + d).uniform(-1.0, 1.0, M)
+    z = op.tau_apply(_t(r), s0=s0, s1=s1).cpu().numpy()
+    zr = otau.tau_apply(d, N, alpha, a, r, s0, s1, shape=shape)
+    n2 = otau.embedding_nodes(N)
+    t = np.zeros((n2,) * d)
+    t[tuple([slice(0, N - 1)] * d)] = otau.generator(d, N, alpha, a)
+    mu = s0 + s1 * otau.tau_eigenvalues_gen(t)
+    scale = np.linalg.norm(r) / mu.min() + np.linalg.norm(zr)
+    assert np.abs(z - zr).max() <= 1e-12 * scale
+    op.close()
+
+
+@pytest.mark.parametrize("d,N,shape,alpha", [(2, 12, None, 1.9), (2, 24, (23, 10), 1.4), (1, 100, None, 1.6),
+                                             (3, 10, None, 1.2), (3, 12, (11, 7, 5), 0.7)])
+@pytest.mark.parametrize("solver", ["tau", "tau32"])
+def test_tau_restricted_poisson_vs_dense(fl, d, N, shape, alpha, solver):
+    h = 2.0 / N
+    op = fl.Operator(d, alpha, h, N) if shape is None else fl.Operator(d, alpha, h, None, Nk=[k + 1 for k in shape])
+    a = oracle.coeffs(d, alpha, h, N)
+    A = oracle.dense(d, N, alpha, a, shape=shape)
+    f = np.random.default_rng(N).uniform(-1.0, 1.0, op.M)
+    uref = oracle.solve_dense(A, f)
+    u, info = op.poisson_solve(_t(f), tol=1e-11, solver=solver)
+    ug = u.cpu().numpy()
+    assert info["fell_back"] == 0 and info["iters"] <= 2 * ITER_CAP[solver], info
+    assert np.linalg.norm(f - A @ ug) <= 1.05e-11 * np.linalg.norm(f)
+    assert np.abs(ug - uref).max() <= 2e-11 * np.linalg.cond(A) * np.abs(uref).max()
+    op.close()
+
+
 def test_tau_rejects(fl):
     f2 = lambda n: torch.ones(n, dtype=torch.float64, device="cuda:0")
-    # a box, and N not a power of two (FFT length above 2N): no sine basis of the embedding
-    box = fl.Operator(2, 1.2, 1.0 / 16, None, Nk=[16, 8])
-    non_pow2 = fl.Operator(2, 1.2, 2.0 / 12, 12)
-    for op in (box, non_pow2):
+    # N = 2^k + 1: n = P/2 nodes, one more than the sine basis of the embedding holds
+    sq17 = fl.Operator(2, 1.2, 2.0 / 17, 17)
+    box17 = fl.Operator(2, 1.2, 1.0 / 17, None, Nk=[17, 8])
+    for op in (sq17, box17):
         f = f2(op.M)
         for solver in ("tau", "tau32"):
             with pytest.raises(fl.FlError) as e:
@@ -201,11 +242,11 @@ def test_tau_rejects(fl):
 
 
 def test_tau_batched_classes(fl):
-    # power-of-two classes of a batch take the preconditioned inner FP32 CG (a few
-    # iterations per refinement step); a class of another N keeps plain CG.  Every
+    # classes of a batch take the preconditioned inner FP32 CG (a few iterations
+    # per refinement step), except N = 2^k + 1, which keeps plain CG.  Every
     # solution matches the single solve and, at small N, the dense oracle.
     rng = np.random.default_rng(21)
-    Ns = [32, 64, 32, 24, 64, 128]
+    Ns = [32, 64, 32, 24, 64, 128, 17]
     alphas = [float(a) for a in rng.uniform(0.3, 1.9, len(Ns))]
     hs = [2.0 / N for N in Ns]
     fs_np = [inputs.gauss_sum(2, N, 4, seed=400 + i) for i, N in enumerate(Ns)]
@@ -220,8 +261,8 @@ def test_tau_batched_classes(fl):
         assert (torch.linalg.norm(r) / torch.linalg.norm(fs[i])).item() <= 1.05e-10
         u1, i1 = op.poisson_solve(fs[i], tol=1e-11, solver="cg64")
         assert (torch.abs(us[i] - u1).max() / torch.abs(u1).max()).item() <= 1e-7
-        if N & (N - 1) == 0:
-            assert infos[i]["iters"] <= 40, (i, infos[i])
+        if N != 17:
+            assert infos[i]["iters"] <= 60, (i, infos[i])
         if N <= 32:
             a = oracle.coeffs(2, al, hs[i], N)
             uref = oracle.solve_dense(oracle.dense(2, N, al, a), fs_np[i])
