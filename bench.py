@@ -247,6 +247,35 @@ def c4_extra(torch, fl, inputs):
             "sequential_refine_max_inner_iters": max(i["iters"] for i in seq["refine"][1])}
 
 
+def poisson_shapes_extra(torch, fl, inputs, alphas=(1.0, 1.5, 1.9)):
+    """Poisson solves to 1e-8 off the power-of-two squares (the restricted sine-transform
+    preconditioner of the default solver) against plain FP64 CG: a 2D square of N = 700, a 2D box
+    of 1024 x 300 intervals, a 3D cube of N = 200, and N = 1025 (2^k + 1, which keeps the plain
+    solvers); right-hand sides U[-1, 1] from seed 1."""
+    cases = [("2D N=700", 2, 700, None), ("2D box 1024x300", 2, 1024, [1024, 301]),
+             ("3D N=200", 3, 200, None), ("2D N=1025", 2, 1025, None)]
+    rows = []
+    for name, d, N, Nk in cases:
+        for alpha in alphas:
+            h = 2.0 / N
+            op = fl.Operator(d, alpha, h, N) if Nk is None else fl.Operator(d, alpha, h, None, Nk=Nk)
+            f = torch.as_tensor(inputs.uniform(op.M, seed=1, lo=-1.0, hi=1.0), device="cuda:0")
+            row = [name, alpha]
+            for solver in ("auto", "cg64"):
+                u = torch.zeros_like(f)
+                op.poisson_solve(f, tol=1e-8, u=u, solver=solver)  # warm
+                u.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info = op.poisson_solve(f, tol=1e-8, u=u, solver=solver)
+                torch.cuda.synchronize()
+                row += [info["iters"], round((time.perf_counter() - t0) * 1e3, 2)]
+            rows.append(row)
+            op.close()
+    return {"workload": "Poisson to 1e-8, f ~ U[-1,1] (seed 1): 2D N=700, 2D box 1024x300, 3D N=200, 2D N=1025",
+            "rows": rows, "row_fields": ["case", "alpha", "default_iters", "default_ms", "cg64_iters", "cg64_ms"]}
+
+
 def poisson_extra(torch, fl, inputs, N=1024, alpha=1.5, alphas=(0.5, 1.0, 1.5, 1.9),
                   solvers=("cg64", "refine", "tau", "tau32", "auto")):
     """Time-to-1e-8 relative residual for the 2D N=1024 Poisson problem, f = 8 Gaussians: plain FP64
@@ -556,6 +585,8 @@ def main():
         print("bench: poisson solves", file=sys.stderr, flush=True)
         extra["poisson"] = poisson_extra(torch, fl, inputs, solvers=tuple(args.poisson_solvers.split(",")),
                                          alphas=() if args.no_poisson_sweep else (0.5, 1.0, 1.5, 1.9))
+        if not args.no_poisson_sweep:
+            extra["poisson_shapes"] = poisson_shapes_extra(torch, fl, inputs)
     op.close()
     if not args.no_extra and not args.no_c3:
         print("bench: 3D N=256 matvec", file=sys.stderr, flush=True)
