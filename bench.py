@@ -207,7 +207,7 @@ def large_extra(torch, fl, inputs, N=8192, alpha=1.5, reps=5):
 
 def c4_extra(torch, fl, inputs):
     """64 2D Poisson problems, N from {64,128,256,512}, alpha ~ U(0.2,1.95), tol 1e-8: one batched
-    solve (power-of-two classes: FP32 CG preconditioned by the sine transform, inside FP64
+    solve (every class here: FP32 CG preconditioned by the sine transform, inside FP64
     refinement) against the same problems solved one after another with the default solver (the
     preconditioned FP64 flexible CG) and with plain FP32-matvec refinement."""
     probs = inputs.batch_problems(64, seed=4)

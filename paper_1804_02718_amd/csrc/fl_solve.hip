@@ -996,8 +996,8 @@ struct BatchClass {
     hipGraphExec_t chunk = nullptr;
     MvCtx<float> c32;
     MvCtx<double> c64;
-    // sine-transform preconditioned inner CG (power-of-two squares and cubes whose
-    // every problem has a positive symbol on the sine modes): z = M^{-1} r in FP32
+    // sine-transform preconditioned inner CG (every N but 2^k + 1, when every
+    // problem has a positive symbol on the sine modes): z = M^{-1} r in FP32
     bool tau = false;
     int iters_per_chunk = kGraphIters;
     float *z32 = nullptr;
