@@ -201,6 +201,19 @@ def large_extra(torch, fl, inputs, N=8192, alpha=1.5, reps=5):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
         out[name] = {"ms": round(dt * 1e3, 3), "gdof_s": round(op.M / dt / 1e9, 3)}
+    # the Poisson problem on this grid (f = 8 seeded Gaussians), to 1e-8, by the default
+    # solver (the sine-transform preconditioned FP32 inner solves in FP64 refinement here)
+    f = torch.as_tensor(inputs.gauss_sum(2, N, 8, seed=2), device="cuda:0")
+    uu = torch.zeros_like(f)
+    op.poisson_solve(f, tol=1e-8, u=uu)  # warm (workspaces, preconditioner symbol)
+    uu.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info = op.poisson_solve(f, tol=1e-8, u=uu)
+    torch.cuda.synchronize()
+    out["poisson"] = {"seconds": round(time.perf_counter() - t0, 4), "iters": info["iters"],
+                      "outer": info["outer_iters"], "relres": info["relres"],
+                      "workload": "f = 8 seeded Gaussians on (-1,1)^2, tol 1e-8, default solver"}
     op.close()
     return out
 

@@ -58,8 +58,8 @@ typedef enum { FL_FP64 = 0, FL_FP32 = 1 } fl_prec;
 
 typedef enum {
     FL_SOLVE_AUTO = 0,    /* TAU, or TAU32 from 2^22 unknowns up, where it applies
-                             (FFT length P <= 2048, at most P/2 - 1 nodes per
-                             axis, i.e. every N but 2^k + 1, s0 + s1 lambda
+                             (at most P/2 - 1 nodes per axis, i.e. every N but
+                             2^k + 1, s0 + s1 lambda
                              > 0 on the sine modes; in the Allen-Cahn steps only
                              when 2 theta tau kappa A_ii > 0.5, else the system
                              is close to the identity); otherwise, Poisson:
@@ -72,9 +72,8 @@ typedef enum {
     FL_SOLVE_FPCG = 3,    /* flexible PCG with the learned preconditioner        */
     FL_SOLVE_TAU = 4,     /* flexible PCG, all FP64, with the sine-transform
                              (tau) preconditioner of the system matrix (see
-                             fl_tau_apply); FFT length <= 2048 and at most P/2
-                             - 1 nodes per axis (else FL_E_INVAL).  Falls back
-                             to CG64 like FPCG                                   */
+                             fl_tau_apply); at most P/2 - 1 nodes per axis
+                             (else FL_E_INVAL).  Falls back to CG64 like FPCG    */
     FL_SOLVE_TAU32 = 5    /* FP64 residual refinement around FP32 CG
                              preconditioned by the same sine transform in FP32
                              (inner tolerance 1e-4 unless inner_tol is set);
@@ -191,8 +190,8 @@ fl_status fl_apply(fl_op op, const void *u, void *y, int prec, void *stream);
  * r, z: device double vectors of M entries, not overlapping.  The symbol is
  * rebuilt when (s0, s1) or the FP64 kernel variant change (a synchronising
  * step); then asynchronous on `stream`.  Errors: FL_E_INVAL (null, overlap,
- * s0/s1), FL_E_UNSUPPORTED (more than P/2 - 1 nodes on an axis, or FFT length
- * above 2048), FL_E_BREAKDOWN (s0 + s1 lambda not positive on a sine mode),
+ * s0/s1), FL_E_UNSUPPORTED (more than P/2 - 1 nodes on an axis),
+ * FL_E_BREAKDOWN (s0 + s1 lambda not positive on a sine mode),
  * FL_E_NOMEM, FL_E_DEVICE.
  */
 fl_status fl_tau_apply(fl_op op, const double *r, double *z, double s0, double s1,

@@ -929,6 +929,16 @@ __global__ void k_tile_lambda(const double *__restrict__ lam64, T *__restrict__ 
     }
 }
 
+// natural-order (Q x Q, kx fastest) symbol of the large-operator passes
+template <typename T>
+__global__ void k_natural_symbol(const double *__restrict__ lam64, T *__restrict__ out, int Q, SymMap m) {
+    const long total = (long)Q * Q;
+    const int N2 = Q - 1;
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (long)gridDim.x * blockDim.x)
+        out[idx] = (T)sym_at(lam64, idx, (int)(idx % Q), (int)(idx / Q), 0, 2, N2, m);
+}
+
 // bad <- 1 where s0 + s1 lambda is not positive and finite on a sine mode
 __global__ void k_tau_check(const double *__restrict__ lam64, int d, int Q, SymMap m, int *bad) {
     const long total = d == 1 ? (long)Q : d == 2 ? (long)Q * Q : (long)Q * Q * Q;
@@ -997,7 +1007,6 @@ fl_status select_variant(fl_op op, int prec, int k, hipStream_t s) {
 // restricted to the operator's nodes, which needs n_k <= n' on every axis.
 // ---------------------------------------------------------------------------
 bool tau_supported(const fl_op_s *op) {
-    if (large_op(op)) return false;
     for (int k = 0; k < op->d; ++k)
         if (op->nk[k] > op->P / 2 - 1) return false;
     return true;
@@ -1005,8 +1014,7 @@ bool tau_supported(const fl_op_s *op) {
 
 fl_status tau_symbol(fl_op op, double s0, double s1, int prec, int C, void *lt, hipStream_t s) {
     if (!tau_supported(op)) {
-        set_error("the sine-transform preconditioner needs at most P/2 - 1 nodes per axis (N not 2^k + 1) and "
-                  "FFT length P <= %d", kMaxLdsP);
+        set_error("the sine-transform preconditioner needs at most P/2 - 1 nodes per axis (N not 2^k + 1)");
         return FL_E_UNSUPPORTED;
     }
     if (!(s0 >= 0.0) || !(s1 >= 0.0) || !(s0 + s1 > 0.0) || !std::isfinite(s0) || !std::isfinite(s1)) {
@@ -1032,6 +1040,15 @@ fl_status tau_symbol(fl_op op, double s0, double s1, int prec, int C, void *lt, 
     if (hbad) {
         set_error("s0 + s1 lambda is not positive on every sine mode: no sine-transform preconditioner");
         return FL_E_BREAKDOWN;
+    }
+    if (large_op(op)) {  // natural order, as the large-operator passes read lambda
+        const int gn = cdiv(ql, 256) > 65536 ? 65536 : cdiv(ql, 256);
+        if (prec == FL_FP32)
+            hipLaunchKernelGGL(k_natural_symbol<float>, dim3(gn), dim3(256), 0, s, op->lam64, (float *)lt, Q, m);
+        else
+            hipLaunchKernelGGL(k_natural_symbol<double>, dim3(gn), dim3(256), 0, s, op->lam64, (double *)lt, Q, m);
+        FL_HIP_TRY(hipGetLastError());
+        return FL_OK;
     }
     const int nt = cdiv(spec_cols(d, op->P), C);
     const long len = lam_tiled_len(d, op->P, C);
@@ -1094,6 +1111,7 @@ fl_status tau_apply32(fl_op op, const float *r, float *z, const double *done, hi
         set_error("sine-transform preconditioner not prepared for the selected FP32 kernel variant");
         return FL_E_INVAL;
     }
+    if (large_op(op)) return large_matvec<float>(op, r, z, Epi<float>{}, done, s, op->mu32t, true);
     MvCtx<float> cx = single_ctx<float>(op);
     cx.lam = op->mu32t;
     cx.odd = true;
@@ -1105,6 +1123,7 @@ fl_status tau_apply(fl_op op, const double *r, double *z, const double *done, hi
         set_error("sine-transform preconditioner not prepared for the selected kernel variant");
         return FL_E_INVAL;
     }
+    if (large_op(op)) return large_matvec<double>(op, r, z, Epi<double>{}, done, s, op->mu64t, true);
     MvCtx<double> cx = single_ctx<double>(op);
     cx.lam = op->mu64t;
     cx.odd = true;
@@ -1234,7 +1253,9 @@ __device__ __forceinline__ void big_dft4(C2<T> &a, C2<T> &b, C2<T> &c, C2<T> &d)
 
 // one Stockham pass of radix R over nlines transforms of length P: line l,
 // position q at l*lstride + q*pstride.  Positions >= n_in read as 0 (first
-// pass), only positions < n_out are written (last pass), and with LAM the
+// pass; n_in < 0: the odd extension about -1 of -n_in <= P/2 - 1 stored values,
+// x[q] for q < -n_in, -x[P - 2 - q] where P - 2 - q < -n_in, else 0), only
+// positions < n_out are written (last pass), and with LAM the
 // loads are multiplied by lambda[fold(q) * Q + l] (first inverse pass; the
 // forward output is in natural order).  LINE_FAST: consecutive threads take
 // consecutive lines (the column passes, whose lines are adjacent in memory).
@@ -1261,7 +1282,14 @@ __global__ __launch_bounds__(256) void k_big_pass(const C2<T> *__restrict__ in, 
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int q = j + r * PR;
-            v[r] = q < n_in ? src[(long)q * pstride] : mk<T>(0, 0);
+            if (n_in >= 0) {
+                v[r] = q < n_in ? src[(long)q * pstride] : mk<T>(0, 0);
+            } else {
+                const int qs = q < P / 2 ? q : P - 2 - q;  // -1 at q = P - 1
+                const bool ok = qs >= 0 && qs < -n_in;
+                const C2<T> x = src[(long)(ok ? qs : 0) * pstride];
+                v[r] = ok ? (q < P / 2 ? x : mk<T>(-x.x, -x.y)) : mk<T>(0, 0);
+            }
             if (LAM) v[r] = cscale<T>(v[r], lam[(long)(q <= P / 2 ? q : P - q) * Q + line]);
         }
         // twiddles W^{r m}, W = exp(-+ 2 pi i / (Ns R)): table index r m P / (Ns R) < P
@@ -1425,21 +1453,25 @@ template <typename T> static const T *big_lam(fl_op op);
 template <> const float *big_lam<float>(fl_op op) { return op->lam32t; }
 template <> const double *big_lam<double>(fl_op op) { return op->lam64; }
 
+// sym (optional) replaces lambda (natural order, Q x Q); odd: the forward passes
+// read the odd extensions (the sine-transform preconditioner)
 template <typename T>
-fl_status large_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s) {
+fl_status large_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
+                       const T *sym, bool odd) {
     const int P = op->P, Q = op->Q, Qs = op->Qp, nx = op->nk[0], ny = op->nk[1];
+    const int ix = odd ? -nx : nx, iy = odd ? -ny : ny;
     const int nl = (ny + 1) / 2;
     C2<T> *B0 = (C2<T> *)op->T1, *B1 = (C2<T> *)op->T2;
     const C2<T> *tw = twid<T>(op);
     hipLaunchKernelGGL(k_big_pack<T>, dim3(big_grid((long)nl * nx)), dim3(256), 0, s, u, B0, nx, ny, P, done);
     // x forward over the nl lines (rows of length P, positions contiguous)
-    C2<T> *X = big_fft<T, false, false>(B0, B1, P, nl, P, 1, nx, P, tw, nullptr, Q, done, s);
+    C2<T> *X = big_fft<T, false, false>(B0, B1, P, nl, P, 1, ix, P, tw, nullptr, Q, done, s);
     C2<T> *S = X == B0 ? B1 : B0;
     hipLaunchKernelGGL(k_big_split<T>, dim3(big_grid((long)nl * Q)), dim3(256), 0, s, X, S, ny, P, Q, Qs, done);
     // y forward over the Q columns (ny rows in, P out), then y inverse with lambda (ny rows out)
-    C2<T> *F = big_fft<T, false, true>(S, X, P, Q, 1, Qs, ny, P, tw, nullptr, Q, done, s);
+    C2<T> *F = big_fft<T, false, true>(S, X, P, Q, 1, Qs, iy, P, tw, nullptr, Q, done, s);
     C2<T> *G = F == B0 ? B1 : B0;
-    C2<T> *I = big_fft<T, true, true>(F, G, P, Q, 1, Qs, P, ny, tw, big_lam<T>(op), Q, done, s);
+    C2<T> *I = big_fft<T, true, true>(F, G, P, Q, 1, Qs, P, ny, tw, sym ? sym : big_lam<T>(op), Q, done, s);
     C2<T> *Z = I == B0 ? B1 : B0;
     hipLaunchKernelGGL(k_big_unsplit<T>, dim3(big_grid((long)nl * (P / 2 + 1))), dim3(256), 0, s, I, Z, ny, P, Qs,
                        done);
@@ -1455,9 +1487,9 @@ fl_status large_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, const doubl
     return FL_OK;
 }
 template fl_status large_matvec<float>(fl_op, const float *, float *, const Epi<float> &, const double *,
-                                       hipStream_t);
+                                       hipStream_t, const float *, bool);
 template fl_status large_matvec<double>(fl_op, const double *, double *, const Epi<double> &, const double *,
-                                        hipStream_t);
+                                        hipStream_t, const double *, bool);
 
 // lambda of a large operator: the generator -c a_{|m|} embedded in P x P
 // (the same embedding as the LDS path), transformed along x (P rows) and y

@@ -411,8 +411,8 @@ inline long lam_tiled_len(int d, int P, int C) {
     return d == 1 ? Q : d == 2 ? nt * C * Q + Q : nt * C * Q * Q;
 }
 fl_status select_variant(fl_op op, int prec, int k, hipStream_t s);
-// sine-transform preconditioner of s0 I + s1 A (operators on the LDS path whose
-// every axis has at most P/2 - 1 nodes; on power-of-two squares and cubes the tau
+// sine-transform preconditioner of s0 I + s1 A (operators whose every axis has
+// at most P/2 - 1 nodes, the large 2D ones included; on power-of-two squares and cubes the tau
 // matrix itself, elsewhere the inverse of the tau matrix on the embedding's
 // P/2 - 1 nodes restricted to the operator's): tau_prepare builds its FP64 symbol for the selected
 // FP64 variant (FL_E_BREAKDOWN when s0 + s1 lambda is not positive on a sine
@@ -434,5 +434,6 @@ inline bool large_op(const fl_op_s *op) { return op->P > kMaxLdsP; }
 // flag (no fused dot partials)
 fl_status large_symbol(fl_op op, hipStream_t s);
 template <typename T>
-fl_status large_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s);
+fl_status large_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
+                       const T *sym = nullptr, bool odd = false);
 }  // namespace fl

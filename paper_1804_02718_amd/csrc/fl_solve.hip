@@ -803,7 +803,7 @@ fl_status fl_poisson_solve_ex(fl_op op, const double *f, double tol, double *u, 
     if (opts) o = *opts;
     if (o.solver < FL_SOLVE_AUTO || o.solver > FL_SOLVE_TAU32) { set_error("unknown solver"); return FL_E_INVAL; }
     if ((o.solver == FL_SOLVE_TAU || o.solver == FL_SOLVE_TAU32) && !tau_supported(op)) {
-        set_error("TAU needs at most P/2 - 1 nodes per axis (N not 2^k + 1) and FFT length P <= %d", kMaxLdsP);
+        set_error("TAU needs at most P/2 - 1 nodes per axis (N not 2^k + 1)");
         return FL_E_INVAL;
     }
     if (o.solver == FL_SOLVE_FPCG && (!op->net || op->d != 2 || op->n > unet_size(op->net) ||
@@ -893,7 +893,7 @@ fl_status fl_allen_cahn_step_gen(fl_op op, double *u, double tau, double kappa, 
         return FL_E_INVAL;
     }
     if ((solver == FL_SOLVE_TAU || solver == FL_SOLVE_TAU32) && !tau_supported(op)) {
-        set_error("TAU needs at most P/2 - 1 nodes per axis (N not 2^k + 1) and FFT length P <= %d", kMaxLdsP);
+        set_error("TAU needs at most P/2 - 1 nodes per axis (N not 2^k + 1)");
         return FL_E_INVAL;
     }
     fl_info local;

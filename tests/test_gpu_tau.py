@@ -274,3 +274,41 @@ def test_tau_batched_classes(fl):
     for i in range(len(Ns)):
         assert torch.equal(us[i], us2[i])
     b.close()
+
+
+@pytest.mark.parametrize("N,alpha,s0,s1", [(2048, 1.5, 0.0, 1.0), (1500, 1.1, 0.0, 1.0), (2048, 0.8, 1.0, 1e-3)])
+def test_tau_apply_large_operator_matches_oracle(fl, N, alpha, s0, s1):
+    # FFT length 4096: the global-memory passes with the odd loads and the natural-order symbol
+    h = 2.0 / N
+    op = fl.Operator(2, alpha, h, N)
+    a = oracle.coeffs(2, alpha, h, N)
+    r = np.random.default_rng(N).uniform(-1.0, 1.0, op.M)
+    z = op.tau_apply(_t(r), s0=s0, s1=s1).cpu().numpy()
+    zr = otau.tau_apply(2, N, alpha, a, r, s0, s1)
+    n2 = otau.embedding_nodes(N)
+    t = np.zeros((n2, n2))
+    t[:N - 1, :N - 1] = otau.generator(2, N, alpha, a)
+    mu = s0 + s1 * otau.tau_eigenvalues_gen(t)
+    scale = np.linalg.norm(r) / mu.min() + np.linalg.norm(zr)
+    assert np.abs(z - zr).max() <= 1e-12 * scale
+    op.close()
+
+
+@pytest.mark.parametrize("N,alpha,solver", [(2048, 1.5, "tau"), (2048, 1.9, "tau32"), (1500, 1.2, "auto"),
+                                            (8192, 1.5, "auto")])
+def test_tau_large_operator_poisson(fl, N, alpha, solver):
+    # 2D on the large-operator path, up to the paper's reference grid h = 2^-12
+    h = 2.0 / N
+    op = fl.Operator(2, alpha, h, N)
+    M = op.M
+    f_np = inputs.gauss_sum(2, N, 8, seed=2)
+    f = _t(f_np)
+    u, info = op.poisson_solve(f, tol=1e-8, solver=solver)
+    assert info["relres"] <= 1e-8 and info["fell_back"] == 0 and info["iters"] <= 120, info
+    r = f - op.apply(u)
+    assert (torch.linalg.norm(r) / torch.linalg.norm(f)).item() <= 1.01e-8
+    a = oracle.coeffs(2, alpha, h, N)
+    rows = np.random.default_rng(7).choice(M, 3, replace=False)
+    res = f_np[rows] - oracle.apply_rows(2, N, alpha, a, u.cpu().numpy(), rows)
+    assert np.abs(res).max() <= 1.01e-8 * np.linalg.norm(f_np)
+    op.close()
