@@ -312,3 +312,27 @@ def test_tau_large_operator_poisson(fl, N, alpha, solver):
     res = f_np[rows] - oracle.apply_rows(2, N, alpha, a, u.cpu().numpy(), rows)
     assert np.abs(res).max() <= 1.01e-8 * np.linalg.norm(f_np)
     op.close()
+
+
+def test_tau_edge_cases(fl):
+    # a box one node thick, and kappa = 0 (K = I: the symbol is 1 / s0 on every sine mode)
+    N, alpha = 16, 1.3
+    h = 1.0 / N
+    box = fl.Operator(2, alpha, h, None, Nk=[16, 2])
+    a = oracle.coeffs(2, alpha, h, N)
+    r = np.random.default_rng(3).uniform(-1.0, 1.0, box.M)
+    z = box.tau_apply(_t(r)).cpu().numpy()
+    zr = otau.tau_apply(2, N, alpha, a, r, shape=(15, 1))
+    assert np.abs(z - zr).max() <= 1e-12 * np.abs(zr).max()
+    A = oracle.dense(2, N, alpha, a, shape=(15, 1))
+    u, info = box.poisson_solve(_t(r), tol=1e-11, solver="tau")
+    assert np.linalg.norm(r - A @ u.cpu().numpy()) <= 1.05e-11 * np.linalg.norm(r)
+    box.close()
+    sq = fl.Operator(2, alpha, 2.0 / N, N)
+    u0 = inputs.ac_initial(sq.M, seed=4)
+    ug = _t(u0)
+    info = sq.allen_cahn_step_gen(ug, 1e-3, 0.0, 1.0, 0.0, tol=1e-13, solver="tau")
+    # kappa = 0: u+ = u + tau (u - u^3) exactly (up to the solve's tolerance)
+    assert np.abs(ug.cpu().numpy() - (u0 + 1e-3 * (u0 - u0 ** 3))).max() < 1e-12
+    assert info["iters"] <= 2
+    sq.close()
