@@ -816,8 +816,14 @@ fl_status fl_poisson_solve_ex(fl_op op, const double *f, double tol, double *u, 
     *inf = fl_info{};
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = (hipStream_t)stream;
-    if (!o.use_x0) {
+    // from x0 = 0 the initial residual is f itself: the solvers take it as given
+    // instead of spending an FP64 matvec on f - A 0
+    const bool r0 = !o.use_x0;
+    if (r0) {
+        FL_TRY(ensure_workspace(op));
         hipLaunchKernelGGL(k_zero<double>, dim3(ew_grid(op->M)), dim3(256), 0, s, u, op->M);
+        hipLaunchKernelGGL((k_copy_cast<double, double>), dim3(ew_grid(op->M)), dim3(256), 0, s, work_of(op).r64, f,
+                           op->M);
     }
     const int max_iter = o.max_iter > 0 ? o.max_iter : default_max_iter(op);
     fl_status st = FL_OK;
@@ -833,7 +839,7 @@ fl_status fl_poisson_solve_ex(fl_op op, const double *f, double tol, double *u, 
         st = t32 ? tau_prepare32(op, 0.0, 1.0, s) : tau_prepare(op, 0.0, 1.0, s);
         if (st == FL_OK && t32) {
             const double itol = o.inner_tol > 0.0 ? o.inner_tol : 1e-4;
-            st = refine(op, 0.0, 1.0, f, u, tol, false, itol, max_iter, o.check_every, inf, s, false, true);
+            st = refine(op, 0.0, 1.0, f, u, tol, false, itol, max_iter, o.check_every, inf, s, r0, true);
             if (st != FL_OK && o.solver == FL_SOLVE_AUTO && std::isfinite(inf->relres) &&
                 tau_prepare(op, 0.0, 1.0, s) == FL_OK) {
                 fl_info sub{};
@@ -845,7 +851,7 @@ fl_status fl_poisson_solve_ex(fl_op op, const double *f, double tol, double *u, 
             }
             solved = true;
         } else if (st == FL_OK) {
-            st = fpcg(op, PREC_TAU, 0.0, 1.0, f, u, tol, max_iter, inf, s);  // falls back to CG itself
+            st = fpcg(op, PREC_TAU, 0.0, 1.0, f, u, tol, max_iter, inf, s, r0);  // falls back to CG itself
             solved = true;
         } else {
             // AUTO without a positive symbol on the sine modes takes the plain solvers
@@ -853,7 +859,7 @@ fl_status fl_poisson_solve_ex(fl_op op, const double *f, double tol, double *u, 
         }
     }
     if (!solved && o.solver == FL_SOLVE_FPCG) {
-        st = fpcg(op, PREC_NET, 0.0, 1.0, f, u, tol, max_iter, inf, s);
+        st = fpcg(op, PREC_NET, 0.0, 1.0, f, u, tol, max_iter, inf, s, r0);
     } else if (!solved) {
         // otherwise FP32-matvec refinement up to alpha = 1.25, FP64 CG above.  Each
         // refinement step restarts CG, and for the stiffer operators the restarts cost
@@ -862,7 +868,7 @@ fl_status fl_poisson_solve_ex(fl_op op, const double *f, double tol, double *u, 
         const bool inner64 = o.solver == FL_SOLVE_CG64 || (o.solver == FL_SOLVE_AUTO && op->alpha > 1.25);
         const double itol = o.inner_tol > 0.0 ? o.inner_tol : 1e-3;
         *inf = fl_info{};
-        st = refine(op, 0.0, 1.0, f, u, tol, inner64, itol, max_iter, o.check_every, inf, s);
+        st = refine(op, 0.0, 1.0, f, u, tol, inner64, itol, max_iter, o.check_every, inf, s, r0);
     }
     inf->status = st;
     inf->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
