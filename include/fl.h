@@ -13,6 +13,9 @@
  * Theorems 3 and 4 hold for any d >= 1).  The stiffness matrix A is symmetric
  * positive definite multilevel Toeplitz (Toeplitz in 1D; Sec. 2 block form,
  * Sec. 4 three-level form) and is applied by circulant embedding and FFT.
+ * The solves (Sec. 5.2 Poisson, Sec. 5.3 Allen-Cahn) run CG; by default
+ * preconditioned by the sine-transform (tau) matrix of the same operator,
+ * which is not part of the paper (fl_tau_apply, FL_SOLVE_TAU).
  *
  * Conventions shared by every call:
  *   - N >= 2 intervals per axis, n = N - 1 interior nodes per axis,
