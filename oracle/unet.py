@@ -149,3 +149,13 @@ def apply(w, r, alpha, H, bf16=False):
     rms = np.sqrt((r * r).sum()) / n
     y = forward(w, net_input(r, H, alpha)[None], bf16)[0]
     return (rms if rms > 0 else 1.0) * y[:n, :n]
+
+
+def forward_fp32(w, x):
+    """The same network evaluated in FP32 on the CPU (torch float32 ops, the FP32 weights and
+    inputs as given): an independent FP32 evaluation whose distance from the FP64 forward
+    shows what FP32 arithmetic alone costs on a given input."""
+    with torch.no_grad():
+        wt = torch.as_tensor(np.asarray(w, np.float32))
+        xt = torch.as_tensor(np.asarray(x, np.float32))
+        return forward_t(wt, xt).to(torch.float64).numpy()

@@ -46,7 +46,8 @@ def _errs(y, ref, absref):
 @pytest.mark.parametrize("d,N,alpha", [(1, 2, 1.5), (1, 3, 0.3), (1, 17, 1.0), (1, 100, 1.9), (1, 1025, 0.7),
                                        (2, 2, 1.5), (2, 3, 0.3), (2, 5, 1.9), (2, 17, 1.0), (2, 32, 1.5),
                                        (2, 100, 0.7), (2, 257, 1.2), (3, 2, 1.0), (3, 3, 1.7), (3, 6, 0.4),
-                                       (3, 9, 1.2), (3, 16, 1.9)])
+                                       (3, 9, 1.2), (3, 16, 1.9), (1, 40, 0.05), (1, 40, 1.99), (2, 33, 0.05),
+                                       (2, 33, 1.99), (3, 9, 0.05), (3, 9, 1.99)])
 def test_coefficients_match_oracle(dev, d, N, alpha):
     h = 2.0 / N
     op = _fl().Operator(d, alpha, h, N)
@@ -91,7 +92,10 @@ def test_symbol_is_fft_of_embedded_generator(dev, d, N, alpha):
 APPLY_CASES = [(1, 2, 1.2), (1, 3, 0.5), (1, 9, 1.5), (1, 64, 1.9), (1, 100, 0.8), (1, 513, 1.1), (1, 1025, 0.4),
                (2, 2, 1.2), (2, 3, 0.5), (2, 4, 1.9), (2, 5, 1.0), (2, 9, 1.5), (2, 17, 0.2), (2, 32, 1.5),
                (2, 33, 1.1), (2, 64, 1.9), (2, 100, 0.8), (3, 2, 1.3), (3, 3, 0.6), (3, 5, 1.9), (3, 8, 1.2),
-               (3, 12, 0.4), (3, 17, 1.6)]
+               (3, 12, 0.4), (3, 17, 1.6),
+               # the ends of (0, 2): A near the identity, and near the 5- and 7-point Laplacians
+               (1, 40, 0.05), (1, 40, 1.99), (2, 33, 0.05), (2, 33, 1.99), (2, 100, 0.05), (2, 100, 1.99),
+               (3, 9, 0.05), (3, 9, 1.99)]
 
 
 @pytest.mark.parametrize("d,N,alpha", APPLY_CASES)
@@ -181,6 +185,36 @@ def test_apply_c2_full_size_sampled(dev, alpha):
         if lo == -1.0:  # random input: well conditioned, the literal gates hold
             assert e_rel < 1e-12 and e_rel32 < 1e-5, (e_rel, e_rel32)
         op.close()
+
+
+@pytest.mark.timeout(900)
+def test_apply_c2_as_benched_all_rows(dev):
+    # The benchmark's workload exactly: 2D N = 1024 on (-4,4)^2, alpha = 1.5, u = exp(-|x|^2),
+    # default kernel variants, against the oracle's explicit sum on every one of the 1,046,529
+    # rows.  Both precisions take the FP32-rounded input, so one oracle sum serves both.
+    # u >= 0, so |A||u| = 2 A_ii u - A u (the identity the oracle's |A||u| mode is pinned by).
+    fl = _fl()
+    N, alpha = 1024, 1.5
+    h = 8.0 / N
+    op = fl.Operator(2, alpha, h, N)
+    u32 = inputs.gaussian(2, N).astype(np.float32)
+    u = u32.astype(np.float64)
+    y64 = op.apply(_t(u)).cpu().numpy()
+    y32 = op.apply(_t(u32, torch.float32)).cpu().numpy().astype(np.float64)
+    a = oracle.coeffs(2, alpha, h, N)
+    print("oracle: explicit sum over all rows on %d threads" % oracle.num_threads(), flush=True)
+    ref = oracle.apply(2, N, alpha, a, u)
+    absref = 2.0 * (-oracle.const(2, alpha) * a[0, 0]) * u - ref
+    kappa = np.abs(absref).max() / np.abs(ref).max()
+    e_rel, e_sc = _errs(y64, ref, absref)
+    e_rel32, e_sc32 = _errs(y32, ref, absref)
+    print("C2 all rows: kappa_mv %.1f  fp64 e_rel %.3e e_sc %.3e  fp32 e_rel %.3e e_sc %.3e"
+          % (kappa, e_rel, e_sc, e_rel32, e_sc32), flush=True)
+    assert e_sc < 1e-14 and e_rel < 1e-12, (e_rel, e_sc)
+    # FP32: the scaled gate; the literal relative error is kappa_mv times it (kappa_mv ~ 3e3 here)
+    assert e_sc32 < 1e-6, (e_rel32, e_sc32)
+    assert e_rel32 <= kappa * 1e-6
+    op.close()
 
 
 @pytest.mark.parametrize("N,alpha,nrows", [(130, 0.7, 24), (256, 1.2, 12)])

@@ -2,9 +2,12 @@
 against the CPU U-Net (oracle/unet.py) and the FP64 oracle of the operator.
 
 Tolerances.  fp32-operand mode: the GPU sums in FP32 (MFMA accumulation,
-FP32 activations) what the oracle sums in FP64, so a K-term dot product
-carries about sqrt(K) * 2^-24 relative error per layer; over 11 layers with
-K <= 864 this stays below 1e-5 of the output norm.  bf16 mode: operands are
+FP32 activations) what the oracle sums in FP64.  The worst-case running error
+bound (gamma_K |W| |a| per layer, carried through |W|) exceeds the output
+itself by a factor near 10^6 for these random weights, so it cannot set a gate.
+The forward gates are set instead against an independent FP32 evaluation of
+the same network (torch float32 on the CPU), whose own error is checked in the
+same test; the gradient gates keep 2e-5 of each layer's norm.  bf16 mode: operands are
 rounded to 8 significant bits on both sides, but an FP32 activation and its
 FP64 counterpart can straddle a rounding boundary; each such flip moves one
 operand by up to 2^-8 relative, which leaves the outputs within a few 1e-3.
@@ -99,8 +102,16 @@ def test_forward_fp32_mode(fl, H, nb):
     x, _ = _samples(H + nb, nb, H)
     y = net.forward(_f32(x)).cpu().numpy()
     ref = ounet.forward(w.astype(np.float64), x)
-    assert np.linalg.norm(y - ref) <= 5e-6 * np.linalg.norm(ref)
-    assert np.abs(y - ref).max() <= 2e-5 * np.abs(ref).max()
+    e_norm = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    e_max = np.abs(y - ref).max() / np.abs(ref).max()
+    # a plain FP32 evaluation of the same network on the CPU, for scale: on these inputs it
+    # lands at 4e-7 .. 1.1e-6 (norm) and 6e-7 .. 1.6e-6 (max), so the gates below leave a
+    # factor of about 5 (norm) and 13 (max) for the GPU's other summation order
+    y32 = ounet.forward_fp32(w, x)
+    c_norm = np.linalg.norm(y32 - ref) / np.linalg.norm(ref)
+    c_max = np.abs(y32 - ref).max() / np.abs(ref).max()
+    assert e_norm <= 5e-6 and e_max <= 2e-5, (e_norm, e_max, c_norm, c_max)
+    assert e_norm <= 8 * c_norm and e_max <= 16 * c_max, (e_norm, e_max, c_norm, c_max)
 
 
 @pytest.mark.parametrize("H,nb", [(16, 2), (32, 2), (48, 1), (64, 1)])

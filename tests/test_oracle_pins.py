@@ -647,3 +647,50 @@ def test_bump_closed_form_3d():
         y = oracle.apply_rows(3, N, alpha, a, u, rows)
         errs.append(np.abs(y - exact).max() / exact)
     assert errs[0] < 1e-3 and errs[1] < errs[0] and errs[2] < errs[1], errs
+
+
+@pytest.mark.parametrize("d,N,alpha,shape", [(1, 30, 1.5, None), (2, 9, 0.05, None), (2, 12, 1.7, None),
+                                             (2, 11, 1.99, (10, 6)), (3, 6, 1.2, None), (3, 7, 0.6, (6, 3, 4))])
+def test_absmode_is_abs_matrix_times_abs_vector(d, N, alpha, shape):
+    # The oracle's |A||u| mode (the denominator of every scaled matvec error) against two
+    # independent definitions.  (1) The dense matrix of Sec. 2 / Sec. 4 in numpy:
+    # (|A| |u|)_i = sum_j |A_ij| |u_j|.  (2) For u >= 0 only the normal mode is needed: the
+    # diagonal -c a_0 is positive and every off-diagonal -c a_v is negative (a_v > 0), so
+    # sum_j |A_ij| u_j = 2 A_ii u_i - (A u)_i.
+    h = 2.0 / N
+    a = oracle.coeffs(d, alpha, h, N)
+    c = oracle.const(d, alpha)
+    nk = [N - 1] * d if shape is None else list(shape)
+    M = int(np.prod(nk))
+    u = inputs.uniform(M, seed=31)
+    ab = oracle.apply(d, N, alpha, a, u, absmode=True, shape=shape)
+    A = oracle.dense(d, N, alpha, a, shape=shape)
+    ref = np.abs(A) @ np.abs(u)
+    assert np.allclose(ab, ref, rtol=1e-14, atol=0)
+    up = np.abs(u)
+    y = oracle.apply(d, N, alpha, a, up, shape=shape)
+    ab_p = oracle.apply(d, N, alpha, a, up, absmode=True, shape=shape)
+    diag = -c * a.flat[0]
+    assert diag > 0
+    assert np.allclose(ab_p, 2.0 * diag * up - y, rtol=1e-13, atol=0)
+    # |A||u| depends on u only through |u|
+    assert np.array_equal(ab, ab_p)
+
+
+@pytest.mark.parametrize("d,alpha,e", [(2, 0.4, (130, 0)), (2, 1.5, (128, 97)), (2, 1.95, (140, 141)),
+                                       (3, 0.8, (129, 0, 0)), (3, 1.6, (128, 64, 3))])
+def test_elements_far_from_origin_vs_high_precision(d, alpha, e):
+    # Elements whose largest index is at least 128 take the oracle's coarsest rule (4 nodes per
+    # axis, FP64 integrand, long-double sums).  Against mpmath at 30 digits, to 1e-15 relative.
+    h = 1.0
+    q = mp.mpf(d + alpha - 2.0)
+    N = max(e) + 1
+    E = oracle.elements(d, alpha, h, N)
+    if d == 2:
+        ref = mp.quad(lambda x, y: (x * x + y * y) ** (-q / 2), [e[0], e[0] + 1], [e[1], e[1] + 1])
+        got = E[e[1], e[0]]
+    else:
+        ref = mp.quad(lambda x, y, z: (x * x + y * y + z * z) ** (-q / 2), [e[0], e[0] + 1],
+                      [e[1], e[1] + 1], [e[2], e[2] + 1])
+        got = E[e[2], e[1], e[0]]
+    assert abs(got - float(ref)) <= 1e-15 * float(ref), (got, float(ref))

@@ -181,3 +181,19 @@ def test_apply_scale_invariance():
     assert np.abs(z2 - 7.0 * z1).max() <= 1e-13 * np.abs(z2).max()
     x = unet.net_input(r, 16, 1.2)
     assert abs(np.mean(x[:15, :15, 0] ** 2) - 1.0) < 1e-14 and np.all(x[15, :, 0] == 0) and np.all(x[..., 1] == 1.2)
+
+
+def test_fp32_evaluation_is_the_same_network():
+    # the FP32 CPU evaluation (the scale the GPU's fp32-operand gates are set against) computes
+    # the same network: its distance from the FP64 forward is FP32 rounding only, and the
+    # distance grows when the weights and inputs are rounded further (to bf16)
+    rng = np.random.default_rng(5)
+    w = np.concatenate([rng.normal(0.0, np.sqrt(2.0 / (ks * ks * cin)), cout * ks * ks * cin)
+                        for cin, cout, ks in unet.LAYERS]).astype(np.float32)
+    x = rng.normal(size=(2, 32, 32, 2)).astype(np.float32)
+    ref = unet.forward(w.astype(np.float64), x)
+    y32 = unet.forward_fp32(w, x)
+    e = np.linalg.norm(y32 - ref) / np.linalg.norm(ref)
+    assert 1e-9 < e < 3e-6, e
+    eb = np.linalg.norm(unet.forward(w.astype(np.float64), x, bf16=True) - ref) / np.linalg.norm(ref)
+    assert eb > 100 * e
