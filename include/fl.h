@@ -177,6 +177,22 @@ fl_status fl_coeffs_box(int d, double alpha, double gamma, double h, const int *
 fl_status fl_apply(fl_op op, const void *u, void *y, int prec, void *stream);
 
 /*
+ * fl_apply_noalloc -- fl_apply for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and kernel variant, with the spectra
+ * workspaces taken from one static 64 MiB device array per GPU instead of the
+ * operator's.  It calls no hipMalloc, hipFree or allocating routine; its
+ * first call on a GPU looks up that GPU's copy of the array.  Every call on a
+ * GPU shares the array, so calls that overlap in time on one GPU race; nothing
+ * in it needs clearing between calls.  Arguments, layout and ownership as
+ * fl_apply.  Errors: as fl_apply; FL_E_INVAL when the matvec's workspace
+ * exceeds 64 MiB (it covers every 2D operator up to FFT length 2048, 3D up to
+ * FFT length 256 in FP32 and 128 in FP64); FL_E_UNSUPPORTED for the large 2D
+ * operators (FFT length above 2048).
+ */
+fl_status fl_apply_noalloc(fl_op op, const void *u, void *y, int prec, void *stream);
+
+/*
  * fl_tau_apply -- z = M^{-1} r for the sine-transform (tau) preconditioner M of
  * K = s0 I + s1 A (s0, s1 >= 0, not both 0).  With P the embedding's FFT
  * length, the n' = P/2 - 1 nodes per axis make the sine vectors

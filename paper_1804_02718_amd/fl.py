@@ -26,7 +26,7 @@ EXPORTED = ["fl_coeffs", "fl_apply", "fl_apply_profiled", "fl_variant_count", "f
             "fl_status_string", "fl_last_error", "fl_unet_create", "fl_unet_destroy", "fl_unet_num_params",
             "fl_unet_step", "fl_unet_get_weights", "fl_unet_set_weights", "fl_unet_apply", "fl_set_preconditioner",
             "fl_gemm_test", "fl_unet_pack", "fl_unet_train", "fl_allen_cahn_step_gen",
-            "fl_coeffs_gamma", "fl_coeffs_box", "fl_tau_apply"]
+            "fl_coeffs_gamma", "fl_coeffs_box", "fl_tau_apply", "fl_apply_noalloc"]
 
 
 class FlLibraryMissing(RuntimeError):
@@ -80,6 +80,7 @@ def load(path: str = LIB_PATH):
     lib.fl_coeffs_gamma.argtypes = [ip, dp, dp, dp, ip, ctypes.POINTER(vp)]
     lib.fl_coeffs_box.argtypes = [ip, dp, dp, dp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(vp)]
     lib.fl_apply.argtypes = [vp, vp, vp, ip, vp]
+    lib.fl_apply_noalloc.argtypes = [vp, vp, vp, ip, vp]
     lib.fl_tau_apply.argtypes = [vp, vp, vp, dp, dp, vp]
     lib.fl_apply_profiled.argtypes = [vp, vp, vp, ip, ip, vp, ctypes.POINTER(ctypes.c_float),
                                       ctypes.POINTER(ctypes.c_int)]
@@ -199,6 +200,16 @@ def fl_apply(op, u, y, stream=None):
     if u.dtype not in (torch.float32, torch.float64) or y.dtype != u.dtype:
         raise TypeError("u and y must both be float32 or both float64")
     _check(load().fl_apply(op, _ptr(u), _ptr(y), prec, _stream(stream)))
+    return y
+
+
+def fl_apply_noalloc(op, u, y, stream=None):
+    """fl_apply with the spectra workspaces in the library's static per-GPU array (no allocation)."""
+    import torch
+    prec = FL_FP64 if u.dtype == torch.float64 else FL_FP32
+    if u.dtype not in (torch.float32, torch.float64) or y.dtype != u.dtype:
+        raise TypeError("u and y must both be float32 or both float64")
+    _check(load().fl_apply_noalloc(op, _ptr(u), _ptr(y), prec, _stream(stream)))
     return y
 
 
