@@ -33,7 +33,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2_fp32.json")
-KERNEL_SOURCES = ["paper_1804_02718_amd/csrc/fl_fft.hip", "paper_1804_02718_amd/csrc/fl_internal.hpp"]
+KERNEL_SOURCES = ["paper_1804_02718_amd/csrc/fl_fft.hip", "paper_1804_02718_amd/csrc/fl_internal.hpp",
+                  "paper_1804_02718_amd/csrc/fl_wave2d.hpp"]
 
 
 def kernel_source_sha():
@@ -66,6 +67,10 @@ def kernel_instance(pass_name, T, P, var, d=2):
     """Template instance of the kernel that runs a pass for a variant (as rocprofv3 names it);
     the 2D path keeps packed DC/Nyquist columns (last template argument true)."""
     ex, ey, c, lpb = var["ex"], var["ey"], var["tile"], var["row_pairs"]
+    if var.get("kind", 0) == 1:  # 2D, one wavefront per FFT line
+        return {"x_fwd": "k_w2_xfwd<%s, %d, %d>" % (T, P, c),
+                "y_fused": "k_w2_yfused<%s, %d, %d, true>" % (T, P, c),
+                "x_inv": "k_w2_xinv<%s, %d, %d, false>" % (T, P, c)}[pass_name]
     pack = "true" if d == 2 else "false"
     if pass_name == "x_fwd":
         return "k_xfwd<%s, %d, %d, %d, %d, %s>" % (T, P, ex, c, lpb, pack)
@@ -99,6 +104,57 @@ def traffic_entry(dominant_kernel):
     return k.get("bytes_per_launch")
 
 
+def host_cpu():
+    """The host CPU model (lscpu's "Model name", from /proc/cpuinfo) and thread settings."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def cpu_oracle_extra(inputs):
+    """The oracle on the other workloads, on this host: the C1 grid (2D N=32, alpha=1.5) applied in full
+    and solved by dense Cholesky (measured), and the 3D N=256 matvec timed on 4096 seeded rows and
+    extrapolated to all 16.6M rows (labelled extrapolated)."""
+    import numpy as np
+
+    import oracle
+    out = {}
+    N, alpha = 32, 1.5
+    h = 2.0 / N
+    t0 = time.perf_counter()
+    a = oracle.coeffs(2, alpha, h, N)
+    t1 = time.perf_counter()
+    y = oracle.apply(2, N, alpha, a, inputs.bump(2, N, alpha))
+    t2 = time.perf_counter()
+    A = oracle.dense(2, N, alpha, a)
+    u = oracle.solve_dense(A, np.ones((N - 1) ** 2))
+    t3 = time.perf_counter()
+    out["c1"] = {"kind": "measured", "coeff_seconds": round(t1 - t0, 4), "apply_seconds": round(t2 - t1, 4),
+                 "dense_solve_seconds": round(t3 - t2, 4), "u_max": float(u.max()), "y_centre": float(y[len(y) // 2])}
+    N3, a3 = 256, 1.2
+    h3 = 2.0 / N3
+    M3 = (N3 - 1) ** 3
+    t0 = time.perf_counter()
+    c3 = oracle.coeffs(3, a3, h3, N3)
+    t1 = time.perf_counter()
+    rows = np.random.default_rng(12).choice(M3, size=4096, replace=False)
+    oracle.apply_rows(3, N3, a3, c3, inputs.ac_initial(M3, seed=3), rows)
+    t2 = time.perf_counter()
+    per_row = (t2 - t1) / rows.size
+    out["c3"] = {"kind": "extrapolated", "rows_timed": int(rows.size), "seconds_timed": round(t2 - t1, 2),
+                 "coeff_seconds": round(t1 - t0, 2), "matvec_seconds_extrapolated": round(per_row * M3, 1),
+                 "gdof_s_extrapolated": round(1.0 / per_row / 1e9, 9)}
+    return out
+
+
 def cpu_baseline(N, alpha, h, u_np, seconds):
     import numpy as np
 
@@ -117,6 +173,7 @@ def cpu_baseline(N, alpha, h, u_np, seconds):
         batch = min(batch * 2, 8192)
     dt = time.perf_counter() - t0
     return {"value": done / dt / 1e9, "unit": "Gdof/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "host": host_cpu(),
             "sample": "explicit O(M^2) FP64 sum (long-double accumulation) on %d seeded random rows of the "
                       "%d-row N=1024 matvec in %.1f s, rate = rows/s (coefficient setup excluded)"
                       % (done, M, dt)}
@@ -235,6 +292,7 @@ def c4_extra(torch, fl, inputs):
     us, infos = b.solve(fs, tol=1e-8)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
+    bstats = b.stats()
     b.close()
     ops = [fl.Operator(2, p["alpha"], p["h"], p["N"]) for p in probs]
     seq = {}
@@ -253,6 +311,9 @@ def c4_extra(torch, fl, inputs):
     return {"workload": "64 problems, N in {64,128,256,512}, alpha~U(0.2,1.95), 4 Gaussians, tol 1e-8",
             "unknowns": dofs, "batched_seconds": round(tb, 4), "sequential_seconds": round(ts, 4),
             "speedup": round(ts / tb, 2), "setup_seconds": round(setup, 3),
+            "host_waits_per_solve": bstats["host_waits"], "graph_replays_per_solve": bstats["graph_launches"],
+            "class_variants": {"fp32": bstats["var32"], "fp64": bstats["var64"]},
+            "max_outer_iters": max(i["outer_iters"] for i in infos),
             "max_relres": max(i["relres"] for i in infos),
             "max_inner_iters": max(i["iters"] for i in infos),
             "sequential_max_relres": max(i["relres"] for i in seq_infos),
@@ -622,6 +683,8 @@ def main():
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(N, alpha, h, u_np, args.cpu_seconds)
+        if not args.no_extra:
+            extra["cpu_oracle"] = cpu_oracle_extra(inputs)
         # the oracle's Poisson solve at C2, extrapolated (not measured): one full explicit
         # matvec at the measured row rate, times the GPU's plain-CG iteration count
         if "poisson" in extra and "cg64" in extra["poisson"] and cpu.get("value"):

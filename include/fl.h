@@ -88,7 +88,9 @@ typedef enum {
 typedef struct {
     int iters;            /* CG iterations (all inner iterations for REFINE)     */
     int outer_iters;      /* FP64 residual evaluations / refinement steps        */
-    int fell_back;        /* 1 if the requested method fell back to FP64 CG      */
+    int fell_back;        /* 1 if the requested method gave up and a fallback
+                             finished the solve from the current iterate: plain
+                             FP64 CG after FPCG or TAU, TAU after TAU32         */
     int status;           /* fl_status of the solve                              */
     double relres;        /* final ||f - A u||_2 / ||f||_2, FP64 matvec          */
     double seconds;       /* host wall time of the call                          */
@@ -193,6 +195,16 @@ fl_status fl_apply(fl_op op, const void *u, void *y, int prec, void *stream);
 fl_status fl_apply_noalloc(fl_op op, const void *u, void *y, int prec, void *stream);
 
 /*
+ * fl_residual -- r = f - A u in FP64 (the residual of the Sec. 5.2 Poisson
+ * problem), the FP64 matvec with f folded into its last pass.  f, u, r:
+ * device double vectors of M entries; r may be f itself (each entry of f is
+ * read before the same entry of r is written) but must not overlap u.
+ * Asynchronous on `stream`.  Errors: FL_E_INVAL (null, u and r overlap),
+ * FL_E_DEVICE.
+ */
+fl_status fl_residual(fl_op op, const double *f, const double *u, double *r, void *stream);
+
+/*
  * fl_tau_apply -- z = M^{-1} r for the sine-transform (tau) preconditioner M of
  * K = s0 I + s1 A (s0, s1 >= 0, not both 0).  With P the embedding's FFT
  * length, the n' = P/2 - 1 nodes per axis make the sine vectors
@@ -289,8 +301,11 @@ fl_status fl_apply_profiled(fl_op op, const void *u, void *y, int prec, int reps
  * and strided passes (radix plan), spectrum tile width and rows per block;
  * variant 0 is the built-in default.  They all compute the same y = A u.
  *   fl_variant_count  -- number of variants for prec (host int).
- *   fl_variant_info   -- desc4 (host, 4 ints) = {row points per thread,
- *                        strided points per thread, tile width, row pairs per block}.
+ *   fl_variant_info   -- desc (host, 5 ints) = {row points per thread,
+ *                        strided points per thread, tile width, row pairs per
+ *                        block, kind}; kind 0: a workgroup per line block,
+ *                        kind 1 (2D): one wavefront per FFT line, four rows per
+ *                        row-pass workgroup.
  *   fl_select_variant -- use variant k for prec on this operator (synchronises).
  *   fl_autotune       -- time every variant (reps matvecs each, HIP events, on
  *                        `stream`, scratch vectors allocated and freed inside),
@@ -299,9 +314,21 @@ fl_status fl_apply_profiled(fl_op op, const void *u, void *y, int prec, int reps
  *                        average milliseconds per matvec of each variant.
  */
 fl_status fl_variant_count(fl_op op, int prec, int *count);
-fl_status fl_variant_info(fl_op op, int prec, int k, int *desc4);
+fl_status fl_variant_info(fl_op op, int prec, int k, int *desc);
 fl_status fl_select_variant(fl_op op, int prec, int k);
 fl_status fl_autotune(fl_op op, int prec, int reps, void *stream, int *best, float *ms_per_variant);
+
+/*
+ * fl_tune -- select the variant the on-disk tuning cache holds for this
+ * operator's (d, FFT length, prec), timing every variant (fl_autotune, 10
+ * matvecs each) and recording the fastest on a miss; its index in *variant
+ * (host int).  The cache is the text file $FL_TUNE_CACHE, else
+ * $HOME/.cache/fl_tune_gfx950.txt, one line per tuning; an empty
+ * FL_TUNE_CACHE disables it (variant 0 is selected).  fl_batch_create takes
+ * every class's variants from it.  Synchronises.  Errors: FL_E_INVAL,
+ * FL_E_NOMEM, FL_E_DEVICE.
+ */
+fl_status fl_tune(fl_op op, int prec, int *variant);
 
 /*
  * Batched fractional Poisson solves: `count` problems of the same dimension d
@@ -311,8 +338,14 @@ fl_status fl_autotune(fl_op op, int prec, int reps, void *stream, int *best, flo
  *                              FL_E_UNSUPPORTED) and groups
  *                              the problems into size classes of equal N; each
  *                              class runs all of its problems in every kernel
- *                              launch, and its inner CG iterations are replayed
- *                              from a captured hipGraph.  A class whose N is
+ *                              launch; one captured hipGraph holds a chunk
+ *                              of inner CG iterations of every class (each on
+ *                              its own branch) and is replayed in rounds of
+ *                              1, 2, 4, ... with one host wait per round
+ *                              (device done flags turn finished problems'
+ *                              launches into no-ops).  Each class's kernel
+ *                              variants come from the tuning cache (fl_tune).
+ *                              A class whose N is
  *                              not 2^k + 1 and whose every problem has a
  *                              positive symbol on the sine modes preconditions
  *                              its inner CG by the sine transform (FP32, as
@@ -338,6 +371,10 @@ fl_status fl_batch_create(int d, int count, const int *N, const double *alpha, c
 fl_status fl_batch_poisson_solve(fl_batch b, const double *const *f, double *const *u, double tol,
                                  int max_iter, fl_info *infos, void *stream);
 fl_status fl_batch_info(fl_batch b, int *nclasses, int *max_batch);
+/* Of the last fl_batch_poisson_solve: the times the host waited for the GPU
+ * and the replays of the all-class iteration graph; per class (host arrays of
+ * nclasses ints, may be NULL) the FP32 and FP64 kernel variants in use. */
+fl_status fl_batch_stats(fl_batch b, int *host_waits, int *graph_launches, int *var32, int *var64);
 fl_status fl_batch_destroy(fl_batch b);
 
 /*

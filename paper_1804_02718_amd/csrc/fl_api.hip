@@ -3,8 +3,14 @@
 #include <cmath>
 #include <cstdarg>
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <vector>
+
+#include <sys/stat.h>
 
 #include "fl_internal.hpp"
 
@@ -165,6 +171,80 @@ static bool overlap(const void *a, size_t na, const void *b, size_t nb) {
 
 using namespace fl;
 
+// ---------------------------------------------------------------------------
+// the autotuner's choices on disk, keyed by (d, FFT length, precision): one
+// line "fl-tune 1 <d> <P> <prec> <variants> <best> <ms>" per tuning.  The file
+// is $FL_TUNE_CACHE, else $HOME/.cache/fl_tune_gfx950.txt; an empty
+// FL_TUNE_CACHE turns caching and tuning off (variant 0).  A line whose
+// variant count differs from the built tables is ignored; the last matching
+// line wins.  Appends are whole lines, so concurrent writers at worst repeat a key.
+// ---------------------------------------------------------------------------
+static std::mutex g_tune_mu;
+
+static bool tune_path(std::string *path) {
+    const char *env = std::getenv("FL_TUNE_CACHE");
+    if (env) {
+        *path = env;
+        return !path->empty();
+    }
+    const char *home = std::getenv("HOME");
+    if (!home || !*home) return false;
+    *path = std::string(home) + "/.cache/fl_tune_gfx950.txt";
+    return true;
+}
+
+static int tune_lookup(const std::string &path, int d, int P, int prec, int nv) {
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return -1;
+    int found = -1;
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        int ver = 0, dd = 0, pp = 0, pr = 0, n = 0, best = 0;
+        float ms = 0.f;
+        if (std::sscanf(line, "fl-tune %d %d %d %d %d %d %f", &ver, &dd, &pp, &pr, &n, &best, &ms) == 7 && ver == 1 &&
+            dd == d && pp == P && pr == prec && n == nv && best >= 0 && best < nv)
+            found = best;
+    }
+    std::fclose(f);
+    return found;
+}
+
+static void tune_record(const std::string &path, int d, int P, int prec, int nv, int best, float ms) {
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos && slash > 0) (void)mkdir(path.substr(0, slash).c_str(), 0755);
+    FILE *f = std::fopen(path.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "fl-tune 1 %d %d %d %d %d %.6f\n", d, P, prec, nv, best, ms);
+    std::fclose(f);
+}
+
+namespace fl {
+// the variant to use for (op's d and P, prec): from the cache, else timed now
+// (fl_autotune, 10 matvecs per variant) and recorded; selects it on op
+fl_status tuned_variant(fl_op op, int prec, int *k) {
+    *k = 0;
+    if (large_op(op)) return FL_OK;
+    const int nv = variant_count(op, prec);
+    std::string path;
+    if (nv <= 1 || !tune_path(&path)) return fl_select_variant(op, prec, 0);
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    int best = tune_lookup(path, op->d, op->P, prec, nv);
+    if (best >= 0) {
+        *k = best;
+        return fl_select_variant(op, prec, best);
+    }
+    std::vector<float> ms(nv);
+    hipStream_t s = nullptr;
+    FL_HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    fl_status st = fl_autotune(op, prec, 10, s, &best, ms.data());
+    (void)hipStreamDestroy(s);
+    FL_TRY(st);
+    tune_record(path, op->d, op->P, prec, nv, best, ms[best]);
+    *k = best;
+    return FL_OK;
+}
+}  // namespace fl
+
 extern "C" {
 
 const char *fl_last_error(void) { return g_err; }
@@ -264,6 +344,16 @@ fl_status fl_apply(fl_op op, const void *u, void *y, int prec, void *stream) {
     return matvec<float>(op, (const float *)u, (float *)y, s);
 }
 
+fl_status fl_residual(fl_op op, const double *f, const double *u, double *r, void *stream) {
+    if (!op || !f || !u || !r) { set_error("NULL argument"); return FL_E_INVAL; }
+    if (overlap(u, sizeof(double) * op->M, r, sizeof(double) * op->M)) { set_error("u and r overlap"); return FL_E_INVAL; }
+    Epi<double> ep;
+    ep.w1 = f;
+    ep.a1 = 1.0;
+    ep.scale = -1.0;
+    return matvec_ex<double>(op, u, r, ep, nullptr, (hipStream_t)stream);
+}
+
 fl_status fl_tau_apply(fl_op op, const double *r, double *z, double s0, double s1, void *stream) {
     if (!op || !r || !z) { set_error("NULL argument"); return FL_E_INVAL; }
     if (overlap(r, sizeof(double) * op->M, z, sizeof(double) * op->M)) { set_error("r and z overlap"); return FL_E_INVAL; }
@@ -325,6 +415,7 @@ fl_status fl_variant_info(fl_op op, int prec, int k, int *desc4) {
     desc4[1] = v.ey;
     desc4[2] = v.c;
     desc4[3] = v.lpb;
+    desc4[4] = v.kind;
     return FL_OK;
 }
 
@@ -382,6 +473,11 @@ fl_status fl_autotune(fl_op op, int prec, int reps, void *stream, int *best, flo
     if (st != FL_OK) return st;
     if (best) *best = bi;
     return FL_OK;
+}
+
+fl_status fl_tune(fl_op op, int prec, int *variant) {
+    if (!op || !variant || (prec != FL_FP64 && prec != FL_FP32)) { set_error("bad argument"); return FL_E_INVAL; }
+    return tuned_variant(op, prec, variant);
 }
 
 fl_status fl_get_coeffs(fl_op op, double *a_host) {

@@ -131,11 +131,11 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xfwd(
             if (PACK && kx == 0) {
                 // X_0 and X_{P/2} of a real row are real: (Re or Im of Z_0, of Z_{P/2})
                 const C2<T> zn = lds[pb + padpos(P / 2)];
-                orow[0] = (rr & 1) ? mk<T>(zk.y, zn.y) : mk<T>(zk.x, zn.x);
+                st_stream(orow, (rr & 1) ? mk<T>(zk.y, zn.y) : mk<T>(zk.x, zn.x));
                 continue;
             }
-            orow[t * tstride] = (rr & 1) ? mk<T>(T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x))
-                                         : mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
+            st_stream(orow + t * tstride, (rr & 1) ? mk<T>(T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x))
+                                                   : mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)));
         }
     } else {
         for (int idx = threadIdx.x; idx < ntiles * RW * C; idx += NTH) {
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xfwd(
                 const C2<T> zn = lds[pb + padpos(P / 2)];
                 o = (rr & 1) ? mk<T>(zk.y, zn.y) : mk<T>(zk.x, zn.x);
             }
-            out[tiled_rowbase(row, nj, ntiles, C) + t * tstride + c] = o;
+            st_stream(out + tiled_rowbase(row, nj, ntiles, C) + t * tstride + c, o);
         }
     }
 }
@@ -269,8 +269,8 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xinv(
                         if (vb) acc += (double)b * (double)ep.dotw[ib2];
                     }
                 }
-                ya[pos] = a;
-                if (vb) yb[pos] = b;
+                st_stream(ya + pos, a);
+                if (vb) st_stream(yb + pos, b);
             }
         }
     }
@@ -357,8 +357,8 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_conv1d(
                         if (vb) acc += (double)b * (double)ep.dotw[ib2];
                     }
                 }
-                ya[pos] = a;
-                if (vb) yb[pos] = b;
+                st_stream(ya + pos, a);
+                if (vb) st_stream(yb + pos, b);
             }
         }
     }
@@ -503,13 +503,13 @@ void k_strided(
 #pragma unroll
         for (int j = 0; j < E; ++j) {
             const int pos = out_pos<P, PN, L - 1>(tl, j);
-            if (pos < n_out) dst[pos * st.line] = v[j];
+            if (pos < n_out) st_stream(dst + pos * st.line, v[j]);
         }
     } else {
 #pragma unroll
         for (int j = 0; j < E; ++j) {
             const int pos = in_pos<P, PN, 0>(tl, j);
-            if (pos < n_out) dst[pos * st.line] = v[j];
+            if (pos < n_out) st_stream(dst + pos * st.line, v[j]);
         }
     }
 }
@@ -646,6 +646,33 @@ static void matvec_v(const MvCtx<T> &cx, const T *u, T *y, const Epi<T> &ep, con
     }
 }
 
+#include "fl_wave2d.hpp"
+
+// the 2D matvec with one wavefront per FFT line (fl_wave2d.hpp): X forward,
+// Y fused, X inverse over the same tiled spectra (tiles of C columns)
+template <typename T, int P, int C>
+static void matvec_w2(const MvCtx<T> &cx, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
+                      const hipEvent_t *ev) {
+    const int nx = cx.nk[0], ny = cx.nk[1], Q = cx.Q;
+    const int nt = cdiv(spec_cols(2, P), C);
+    C2<T> *T1 = (C2<T> *)cx.T1;
+    const long zt1 = cx.zs_t1 / (long)sizeof(C2<T>);
+    const int nb = cx.batch;
+    auto E = [&](int i) { return ev ? ev + 2 * i : nullptr; };
+    const int ix = cx.odd ? -nx : nx, iy = cx.odd ? -ny : ny;
+    const int blocks = cdiv(ny, 4);
+    launch(k_w2_xfwd<T, P, C>, dim3(blocks, 1, nb), dim3(256), s, E(0), u, T1, ny, ix, (long)nx, ny, nt, cx.tw,
+           done, BatchStrides{cx.zs_vec, zt1, 0, cx.zs_done});
+    launch(k_w2_yfused<T, P, C, true>, dim3(nt, 1, nb), dim3(64 * C), s, E(1), T1, iy, ny, ny, cx.tw, cx.lam,
+           Q * C, nt * Q * C, done, BatchStrides{zt1, zt1, cx.zs_lam, cx.zs_done});
+    if (ep.active())
+        launch(k_w2_xinv<T, P, C, true>, dim3(blocks, 1, nb), dim3(256), s, E(2), T1, y, ny, nx, (long)nx, ny, nt,
+               cx.tw, ep, done, BatchStrides{zt1, cx.zs_vec, 0, cx.zs_done});
+    else
+        launch(k_w2_xinv<T, P, C, false>, dim3(blocks, 1, nb), dim3(256), s, E(2), T1, y, ny, nx, (long)nx, ny,
+               nt, cx.tw, ep, done, BatchStrides{zt1, cx.zs_vec, 0, cx.zs_done});
+}
+
 template <typename T> struct Variant {
     VariantDesc desc;
     void (*fn)(const MvCtx<T> &, const T *, T *, const Epi<T> &, const double *, hipStream_t, const hipEvent_t *);
@@ -653,6 +680,8 @@ template <typename T> struct Variant {
 
 #define FL_VAR(T, P, D, EX, EY, C, LPB) \
     { {EX, EY, C, LPB}, &matvec_v<T, P, D, EX, EY, C, LPB> }
+#define FL_VARW(T, P, C) \
+    { {P / 128, P / 64, C, 2, 1}, &matvec_w2<T, P, C> }
 #define FL_DEF(T, P, D)                                                                      \
     FL_VAR(T, P, D, (Shape<T, P, D>::E), (Shape<T, P, D>::E), (Shape<T, P, D>::C), (Shape<T, P, D>::LPB))
 
@@ -686,7 +715,7 @@ template <> const Variant<float> *variants<float>(int P, int d, int *count) {
                                          FL_VAR(T, 1024, 2, 8, 16, 4, 2)};
     // measured fastest first (MI355X, 2D N=1024): 8 points per thread in the row
     // passes, 16 in the fused pass over 256 tiles of 4 columns (one per CU)
-    static const Variant<T> v2_2048[] = {FL_VAR(T, 2048, 2, 8, 16, 4, 1), FL_VAR(T, 2048, 2, 8, 8, 2, 1),
+    static const Variant<T> v2_2048[] = {FL_VAR(T, 2048, 2, 8, 16, 4, 1), FL_VARW(T, 2048, 4), FL_VAR(T, 2048, 2, 8, 8, 2, 1),
                                          FL_DEF(T, 2048, 2),             FL_VAR(T, 2048, 2, 8, 8, 4, 1),
                                          FL_VAR(T, 2048, 2, 8, 8, 2, 4), FL_VAR(T, 2048, 2, 4, 4, 2, 1),
                                          FL_VAR(T, 2048, 2, 4, 8, 2, 1), FL_VAR(T, 2048, 2, 16, 8, 2, 2)};
@@ -754,7 +783,7 @@ template <> const Variant<double> *variants<double>(int P, int d, int *count) {
     static const Variant<T> v2_1024[] = {FL_DEF(T, 1024, 2), FL_VAR(T, 1024, 2, 8, 8, 2, 2),
                                          FL_VAR(T, 1024, 2, 4, 4, 2, 1)};
     // measured fastest first (MI355X, 2D N=1024)
-    static const Variant<T> v2_2048[] = {FL_VAR(T, 2048, 2, 8, 16, 2, 1), FL_DEF(T, 2048, 2),
+    static const Variant<T> v2_2048[] = {FL_VAR(T, 2048, 2, 8, 16, 2, 1), FL_VARW(T, 2048, 2), FL_DEF(T, 2048, 2),
                                          FL_VAR(T, 2048, 2, 8, 8, 2, 1), FL_VAR(T, 2048, 2, 8, 8, 2, 2),
                                          FL_VAR(T, 2048, 2, 4, 4, 2, 1)};
     static const Variant<T> v3_8[] = {FL_DEF(T, 8, 3)};

@@ -55,17 +55,20 @@ template <typename T, int S> __device__ __forceinline__ C2<T> cmuli(C2<T> a) {
     return S > 0 ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x);
 }
 
-// cos / sin of 2 pi k / 16, k = 0..4 (the 16th roots the butterflies need)
-constexpr double kCos16[5] = {1.0, 0.92387953251128675613, 0.70710678118654752440,
-                                         0.38268343236508977173, 0.0};
+// cos(2 pi k / 32), k = 0..8 (the first-quadrant 32nd roots the butterflies need)
+constexpr double kCos32[9] = {1.0,
+                              0.98078528040323044913, 0.92387953251128675613, 0.83146961230254523708,
+                              0.70710678118654752440, 0.55557023301960222474, 0.38268343236508977173,
+                              0.19509032201612826785, 0.0};
 
-// w = exp(DIR * 2 pi i k / R) as an exact constant, k < R <= 16
+// w = exp(DIR * 2 pi i k / R) as an exact constant, k < R <= 32
 template <typename T, int R, int DIR, int K>
 __device__ __forceinline__ C2<T> root() {
-    constexpr int m = (K * 16 / R) & 15;  // in 16ths of a turn
-    // cos(2 pi m/16), sin(2 pi m/16) from the first-quadrant table
-    constexpr int q = m / 4, r = m % 4;
-    constexpr double c0 = kCos16[r], s0 = kCos16[4 - r];
+    static_assert(R <= 32 && 32 % R == 0, "roots up to the 32nd");
+    constexpr int m = (K * 32 / R) & 31;  // in 32nds of a turn
+    // cos(2 pi m/32), sin(2 pi m/32) from the first-quadrant table
+    constexpr int q = m / 8, r = m % 8;
+    constexpr double c0 = kCos32[r], s0 = kCos32[8 - r];
     constexpr double c = q == 0 ? c0 : q == 1 ? -s0 : q == 2 ? -c0 : s0;
     constexpr double s = q == 0 ? s0 : q == 1 ? c0 : q == 2 ? -s0 : -c0;
     return mk<T>((T)c, (T)(DIR * s));
@@ -74,16 +77,16 @@ __device__ __forceinline__ C2<T> root() {
 // v * exp(DIR 2 pi i K / R) with the trivial rotations done exactly
 template <typename T, int R, int DIR, int K>
 __device__ __forceinline__ C2<T> rot(C2<T> v) {
-    constexpr int m = (K * 16 / R) & 15;
+    constexpr int m = (K * 32 / R) & 31;
     if constexpr (m == 0) return v;
-    else if constexpr (m == 4) return cmuli<T, DIR>(v);
-    else if constexpr (m == 8) return mk<T>(-v.x, -v.y);
-    else if constexpr (m == 12) return cmuli<T, -DIR>(v);
+    else if constexpr (m == 8) return cmuli<T, DIR>(v);
+    else if constexpr (m == 16) return mk<T>(-v.x, -v.y);
+    else if constexpr (m == 24) return cmuli<T, -DIR>(v);
     else return cmul<T>(v, root<T, R, DIR, K>());
 }
 
 // ---------------------------------------------------------------------------
-// in-register DFT of length R (R = 1, 2, 4, 8, 16), natural order in and out:
+// in-register DFT of length R (R = 1, 2, 4, 8, 16, 32), natural order in and out:
 //   v[k] <- sum_r v[r] exp(DIR 2 pi i r k / R)
 // radix-2 decimation in time, fully unrolled.
 // ---------------------------------------------------------------------------
@@ -116,6 +119,25 @@ template <typename T, int DIR> struct Dft<T, 2, DIR> {
         v[1] = csub<T>(a, b);
     }
 };
+
+// ---------------------------------------------------------------------------
+// streaming stores of pass outputs: the next pass reads them on other XCDs,
+// so they bypass this XCD's L2 (non-temporal), which also keeps the end of
+// the kernel from waiting on dirty L2 lines
+// ---------------------------------------------------------------------------
+typedef float fvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st_stream(float *p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_stream(double *p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_stream(float2 *p, float2 v) {
+    fvec2 t = {v.x, v.y};
+    __builtin_nontemporal_store(t, (fvec2 *)p);
+}
+__device__ __forceinline__ void st_stream(double2 *p, double2 v) {
+    dvec2 t = {v.x, v.y};
+    __builtin_nontemporal_store(t, (dvec2 *)p);
+}
 
 // ---------------------------------------------------------------------------
 // FFT plans: length P (a power of two), E points per thread (TL = P / E
@@ -394,8 +416,10 @@ fl_status unet_apply(fl_unet u, const double *r, int n, double alpha, double *z,
 int unet_size(fl_unet u);
 // kernel variants of a matvec: points per thread in the row / strided passes,
 // spectrum tile width, line pairs per row block
+// kind 0: workgroup-per-tile kernels; kind 1 (2D only): one wavefront per FFT
+// line, four rows per row-pass workgroup (ex, ey: points per lane)
 struct VariantDesc {
-    int ex, ey, c, lpb;
+    int ex, ey, c, lpb, kind;
 };
 int variant_count(fl_op op, int prec);
 VariantDesc variant_desc(fl_op op, int prec, int k);
@@ -411,6 +435,9 @@ inline long lam_tiled_len(int d, int P, int C) {
     return d == 1 ? Q : d == 2 ? nt * C * Q + Q : nt * C * Q * Q;
 }
 fl_status select_variant(fl_op op, int prec, int k, hipStream_t s);
+// the variant for (op's d and FFT length, prec) from the on-disk tuning cache
+// (timed and recorded on a miss), selected on op
+fl_status tuned_variant(fl_op op, int prec, int *k);
 // sine-transform preconditioner of s0 I + s1 A (operators whose every axis has
 // at most P/2 - 1 nodes, the large 2D ones included; on power-of-two squares and cubes the tau
 // matrix itself, elsewhere the inverse of the tau matrix on the embedding's

@@ -999,7 +999,7 @@ struct BatchClass {
     void *T1 = nullptr, *T2 = nullptr, *lam32 = nullptr, *lam64 = nullptr;
     long zs_t = 0, zs_t2 = 0, lamlen32 = 0, lamlen64 = 0;
     hipStream_t s = nullptr;
-    hipGraphExec_t chunk = nullptr;
+    double *hrel2 = nullptr;  // pinned: per-problem inner targets for the device
     MvCtx<float> c32;
     MvCtx<double> c64;
     // sine-transform preconditioned inner CG (every N but 2^k + 1, when every
@@ -1017,15 +1017,27 @@ struct BatchClass {
 struct fl_batch_s {
     int d = 2, count = 0;
     std::vector<fl::BatchClass> cls;
+    // one graph holding a chunk of inner iterations of every class, each class
+    // on its own branch (captured from the class streams forked off `main`)
+    hipStream_t main = nullptr;
+    hipGraphExec_t all = nullptr;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> joins;
+    // the last solve: host waits on the GPU, graph launches
+    int host_waits = 0, graph_launches = 0;
 };
 
 namespace fl {
 
 static void batch_free(fl_batch b) {
     if (!b) return;
+    if (b->all) (void)hipGraphExecDestroy(b->all);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    for (hipEvent_t e : b->joins) (void)hipEventDestroy(e);
+    if (b->main) (void)hipStreamDestroy(b->main);
     for (auto &c : b->cls) {
-        if (c.chunk) (void)hipGraphExecDestroy(c.chunk);
         if (c.s) (void)hipStreamDestroy(c.s);
+        if (c.hrel2) (void)hipHostFree(c.hrel2);
         if (c.buf) (void)hipFree(c.buf);
         if (c.hscal) (void)hipHostFree(c.hscal);
         for (fl_op o : c.ops) fl_op_destroy(o);
@@ -1086,6 +1098,7 @@ static fl_status batch_alloc(BatchClass &c, int d) {
         c.mu32 = base + o_mu;
     }
     FL_HIP_TRY(hipHostMalloc((void **)&c.hscal, sizeof(double) * B * S_COUNT, hipHostMallocDefault));
+    FL_HIP_TRY(hipHostMalloc((void **)&c.hrel2, sizeof(double) * B, hipHostMallocDefault));
     // per-problem lambda tiled for the class's variants
     for (int z = 0; z < c.B; ++z) {
         FL_TRY(tile_lambda(c.ops[z], FL_FP32, C32, (float *)c.lam32 + z * c.lamlen32, c.s));
@@ -1155,22 +1168,34 @@ static fl_status batch_chunk_launches(BatchClass &c) {
     return FL_OK;
 }
 
-static fl_status batch_capture(BatchClass &c) {
+// the all-class chunk graph: fork every class stream off `main`, capture each
+// class's chunk of inner iterations on its own stream, join back into `main`
+static fl_status batch_capture_all(fl_batch b) {
     hipGraph_t g = nullptr;
-    FL_HIP_TRY(hipStreamBeginCapture(c.s, hipStreamCaptureModeThreadLocal));
-    fl_status st = batch_chunk_launches(c);
-    hipError_t e = hipStreamEndCapture(c.s, &g);
+    FL_HIP_TRY(hipStreamBeginCapture(b->main, hipStreamCaptureModeThreadLocal));
+    fl_status st = FL_OK;
+    if (hipEventRecord(b->fork, b->main) != hipSuccess) st = FL_E_DEVICE;
+    for (size_t ci = 0; ci < b->cls.size() && st == FL_OK; ++ci) {
+        BatchClass &c = b->cls[ci];
+        if (hipStreamWaitEvent(c.s, b->fork, 0) != hipSuccess) st = FL_E_DEVICE;
+        if (st == FL_OK) st = batch_chunk_launches(c);
+        if (st == FL_OK && (hipEventRecord(b->joins[ci], c.s) != hipSuccess ||
+                            hipStreamWaitEvent(b->main, b->joins[ci], 0) != hipSuccess))
+            st = FL_E_DEVICE;
+    }
+    hipError_t e = hipStreamEndCapture(b->main, &g);
     FL_TRY(st);
     FL_HIP_TRY(e);
-    e = hipGraphInstantiate(&c.chunk, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&b->all, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     FL_HIP_TRY(e);
     return FL_OK;
 }
 
-static fl_status batch_sync_read(BatchClass &c) {
-    FL_HIP_TRY(hipMemcpyAsync(c.hscal, c.scal, sizeof(double) * c.B * S_COUNT, hipMemcpyDeviceToHost, c.s));
-    FL_HIP_TRY(hipStreamSynchronize(c.s));
+// `to` waits for everything issued on `from` so far
+static fl_status stream_after(hipStream_t to, hipStream_t from, hipEvent_t e) {
+    FL_HIP_TRY(hipEventRecord(e, from));
+    FL_HIP_TRY(hipStreamWaitEvent(to, e, 0));
     return FL_OK;
 }
 
@@ -1219,15 +1244,25 @@ fl_status fl_batch_create(int d, int count, const int *N, const double *alpha, c
         c.Q = o->Q;
         c.M = o->M;
         c.B = (int)c.ops.size();
-        c.var32 = o->var32;
-        c.var64 = o->var64;
+        // kernel variants of the class's FFT length from the tuning cache
+        st = tuned_variant(o, FL_FP32, &c.var32);
+        if (st == FL_OK) st = tuned_variant(o, FL_FP64, &c.var64);
+        if (st != FL_OK) break;
         if (hipStreamCreateWithFlags(&c.s, hipStreamNonBlocking) != hipSuccess) {
             st = FL_E_DEVICE;
             break;
         }
         st = batch_alloc(c, d);
-        if (st == FL_OK) st = batch_capture(c);
         if (st == FL_OK && hipStreamSynchronize(c.s) != hipSuccess) st = FL_E_DEVICE;
+    }
+    if (st == FL_OK) {
+        b->joins.assign(b->cls.size(), nullptr);
+        if (hipStreamCreateWithFlags(&b->main, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
+            st = FL_E_DEVICE;
+        for (auto &e : b->joins)
+            if (st == FL_OK && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) st = FL_E_DEVICE;
+        if (st == FL_OK) st = batch_capture_all(b);
     }
     if (st != FL_OK) {
         batch_free(b);
@@ -1273,19 +1308,36 @@ fl_status fl_batch_poisson_solve(fl_batch b, const double *const *f, double *con
                            c.partA, (const double *)nullptr);
         hipLaunchKernelGGL(k_finish, dim3(1, c.B), dim3(kVecBlock), 0, c.s, c.partA, L.blocks, c.scal, (int)S_DOT);
     }
-    for (size_t ci = 0; ci < b->cls.size() && st == FL_OK; ++ci) {
+    const int cap = max_iter > 0 ? max_iter : 1 << 30;
+    const size_t nc = b->cls.size();
+    b->host_waits = 0;
+    b->graph_launches = 0;
+    // every class's scalars to the host, one wait for all of them (on `main`)
+    auto read_all = [&]() -> fl_status {
+        for (size_t ci = 0; ci < nc; ++ci) {
+            BatchClass &c = b->cls[ci];
+            FL_TRY(stream_after(b->main, c.s, b->joins[ci]));
+        }
+        for (auto &c : b->cls)
+            FL_HIP_TRY(hipMemcpyAsync(c.hscal, c.scal, sizeof(double) * c.B * S_COUNT, hipMemcpyDeviceToHost,
+                                      b->main));
+        FL_HIP_TRY(hipStreamSynchronize(b->main));
+        b->host_waits += 1;
+        return FL_OK;
+    };
+    if (st == FL_OK) st = read_all();
+    for (size_t ci = 0; ci < nc && st == FL_OK; ++ci) {
         BatchClass &c = b->cls[ci];
-        st = batch_sync_read(c);
         for (int z = 0; z < c.B && st == FL_OK; ++z) {
             bn[ci][z] = std::sqrt(c.hscal[z * S_COUNT + S_DOT]);
             if (!std::isfinite(bn[ci][z])) st = FL_E_BREAKDOWN;
             if (bn[ci][z] == 0.0) { fin[ci][z] = 1; rel[ci][z] = 0.0; }
         }
     }
-    const int cap = max_iter > 0 ? max_iter : 1 << 30;
+    int rounds = 1;  // chunk replays before the next wait (grows; carried to the next step)
     for (int outer_it = 0; st == FL_OK && outer_it < 200; ++outer_it) {
         // FP64 residuals of every class
-        for (size_t ci = 0; ci < b->cls.size() && st == FL_OK; ++ci) {
+        for (size_t ci = 0; ci < nc && st == FL_OK; ++ci) {
             BatchClass &c = b->cls[ci];
             Epi<double> ep;
             ep.w1 = c.b;
@@ -1298,32 +1350,33 @@ fl_status fl_batch_poisson_solve(fl_batch b, const double *const *f, double *con
             hipLaunchKernelGGL(k_finish, dim3(1, c.B), dim3(kVecBlock), 0, c.s, c.partA, L.blocks, c.scal,
                                (int)S_DOT);
         }
+        if (st == FL_OK) st = read_all();
         bool all = true;
-        for (size_t ci = 0; ci < b->cls.size() && st == FL_OK; ++ci) {
+        for (size_t ci = 0; ci < nc && st == FL_OK; ++ci) {
             BatchClass &c = b->cls[ci];
-            st = batch_sync_read(c);
-            std::vector<double> r2(c.B);
             for (int z = 0; z < c.B; ++z) {
-                if (fin[ci][z]) { r2[z] = -1.0; continue; }
+                double &r2 = c.hrel2[z];
+                if (fin[ci][z]) { r2 = -1.0; continue; }
                 const double r = std::sqrt(c.hscal[z * S_COUNT + S_DOT]) / bn[ci][z];
                 rel[ci][z] = r;
                 outer[ci][z] += 1;
                 if (!std::isfinite(r)) { st = FL_E_BREAKDOWN; break; }
-                if (r <= tol || iters[ci][z] >= cap) { fin[ci][z] = 1; r2[z] = -1.0; continue; }
+                if (r <= tol || iters[ci][z] >= cap) { fin[ci][z] = 1; r2 = -1.0; continue; }
                 double want = 0.5 * tol / r;
                 double itol = want > inner_tol ? want : inner_tol;
                 if (itol >= 1.0) itol = 0.5;
-                r2[z] = itol * itol;
+                r2 = itol * itol;
                 all = false;
             }
+            // hrel2 is pinned and not written again before the next wait
             if (st == FL_OK &&
-                hipMemcpyAsync(c.rel2, r2.data(), sizeof(double) * c.B, hipMemcpyHostToDevice, c.s) != hipSuccess)
+                hipMemcpyAsync(c.rel2, c.hrel2, sizeof(double) * c.B, hipMemcpyHostToDevice, c.s) != hipSuccess)
                 st = FL_E_DEVICE;
-            if (st == FL_OK) st = batch_sync_read(c);  // r2 lives on the host stack
         }
         if (st != FL_OK || all) break;
-        // inner FP32 CG of every class: init, then captured chunks until done
-        for (size_t ci = 0; ci < b->cls.size(); ++ci) {
+        // inner FP32 CG of every class: init on the class streams, then the
+        // all-class chunk graph replayed on `main` until every problem is done
+        for (size_t ci = 0; ci < nc; ++ci) {
             BatchClass &c = b->cls[ci];
             VecLayout L = layout(c.M);
             const long BM = (long)c.B * c.M;
@@ -1347,33 +1400,37 @@ fl_status fl_batch_poisson_solve(fl_batch b, const double *const *f, double *con
                 hipLaunchKernelGGL(k_cg_init, dim3(1, c.B), dim3(kVecBlock), 0, c.s, c.partB, L.blocks, c.scal, 0.0,
                                    0.0, (const double *)c.rel2);
             }
+            if (st == FL_OK) st = stream_after(b->main, c.s, b->joins[ci]);
         }
-        std::vector<int> active(b->cls.size(), 1);
-        for (int chunk = 0; st == FL_OK; ++chunk) {
-            bool any = false;
-            for (size_t ci = 0; ci < b->cls.size(); ++ci)
-                if (active[ci]) {
-                    if (hipGraphLaunch(b->cls[ci].chunk, b->cls[ci].s) != hipSuccess) st = FL_E_DEVICE;
-                    any = true;
-                }
-            if (!any) break;
-            for (size_t ci = 0; ci < b->cls.size() && st == FL_OK; ++ci) {
-                if (!active[ci]) continue;
+        int launched = 0;  // chunk replays this step
+        while (st == FL_OK) {
+            for (int r = 0; r < rounds && st == FL_OK; ++r)
+                if (hipGraphLaunch(b->all, b->main) != hipSuccess) st = FL_E_DEVICE;
+            launched += rounds;
+            b->graph_launches += rounds;
+            if (st == FL_OK) st = read_all();
+            if (st != FL_OK) break;
+            bool done = true;
+            for (size_t ci = 0; ci < nc && done; ++ci) {
                 BatchClass &c = b->cls[ci];
-                st = batch_sync_read(c);
-                bool done = true;
                 for (int z = 0; z < c.B; ++z)
                     if (c.hscal[z * S_COUNT + S_DONE] == 0.0 &&
-                        iters[ci][z] + (long)(chunk + 1) * c.iters_per_chunk < cap)
+                        iters[ci][z] + (long)launched * c.iters_per_chunk < cap) {
                         done = false;
-                if (done) {
-                    active[ci] = 0;
-                    for (int z = 0; z < c.B; ++z)
-                        if (!fin[ci][z]) iters[ci][z] += (int)c.hscal[z * S_COUNT + S_ITER];
-                    const long BM = (long)c.B * c.M;
-                    hipLaunchKernelGGL(k_axpy_to64<float>, dim3(ew_grid(BM)), dim3(256), 0, c.s, c.x, c.d32, BM);
-                }
+                        break;
+                    }
             }
+            if (done) break;
+            if (rounds < 64) rounds *= 2;
+        }
+        // the class streams continue after the graph replays
+        for (size_t ci = 0; ci < nc && st == FL_OK; ++ci) {
+            BatchClass &c = b->cls[ci];
+            st = stream_after(c.s, b->main, b->fork);
+            for (int z = 0; z < c.B; ++z)
+                if (!fin[ci][z]) iters[ci][z] += (int)c.hscal[z * S_COUNT + S_ITER];
+            const long BM = (long)c.B * c.M;
+            hipLaunchKernelGGL(k_axpy_to64<float>, dim3(ew_grid(BM)), dim3(256), 0, c.s, c.x, c.d32, BM);
         }
     }
     // scatter solutions
@@ -1412,6 +1469,17 @@ fl_status fl_batch_poisson_solve(fl_batch b, const double *const *f, double *con
     }
     if (worst == FL_E_NOCONV) set_error("some problems did not reach the tolerance");
     return worst;
+}
+
+fl_status fl_batch_stats(fl_batch b, int *host_waits, int *graph_launches, int *var32, int *var64) {
+    if (!b) { set_error("NULL batch"); return FL_E_INVAL; }
+    if (host_waits) *host_waits = b->host_waits;
+    if (graph_launches) *graph_launches = b->graph_launches;
+    for (size_t ci = 0; ci < b->cls.size(); ++ci) {
+        if (var32) var32[ci] = b->cls[ci].var32;
+        if (var64) var64[ci] = b->cls[ci].var64;
+    }
+    return FL_OK;
 }
 
 fl_status fl_batch_info(fl_batch b, int *nclasses, int *max_batch) {

@@ -26,7 +26,7 @@ EXPORTED = ["fl_coeffs", "fl_apply", "fl_apply_profiled", "fl_variant_count", "f
             "fl_status_string", "fl_last_error", "fl_unet_create", "fl_unet_destroy", "fl_unet_num_params",
             "fl_unet_step", "fl_unet_get_weights", "fl_unet_set_weights", "fl_unet_apply", "fl_set_preconditioner",
             "fl_gemm_test", "fl_unet_pack", "fl_unet_train", "fl_allen_cahn_step_gen",
-            "fl_coeffs_gamma", "fl_coeffs_box", "fl_tau_apply", "fl_apply_noalloc"]
+            "fl_coeffs_gamma", "fl_coeffs_box", "fl_tau_apply", "fl_apply_noalloc", "fl_residual", "fl_tune", "fl_batch_stats"]
 
 
 class FlLibraryMissing(RuntimeError):
@@ -81,6 +81,7 @@ def load(path: str = LIB_PATH):
     lib.fl_coeffs_box.argtypes = [ip, dp, dp, dp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(vp)]
     lib.fl_apply.argtypes = [vp, vp, vp, ip, vp]
     lib.fl_apply_noalloc.argtypes = [vp, vp, vp, ip, vp]
+    lib.fl_residual.argtypes = [vp, vp, vp, vp, vp]
     lib.fl_tau_apply.argtypes = [vp, vp, vp, dp, dp, vp]
     lib.fl_apply_profiled.argtypes = [vp, vp, vp, ip, ip, vp, ctypes.POINTER(ctypes.c_float),
                                       ctypes.POINTER(ctypes.c_int)]
@@ -93,6 +94,9 @@ def load(path: str = LIB_PATH):
     lib.fl_batch_poisson_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), dp, ip,
                                            ctypes.POINTER(fl_info), vp]
     lib.fl_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.fl_batch_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.fl_tune.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int)]
     lib.fl_batch_destroy.argtypes = [vp]
     lib.fl_poisson_solve.argtypes = [vp, vp, dp, vp, ctypes.POINTER(fl_info), vp]
     lib.fl_poisson_solve_ex.argtypes = [vp, vp, dp, vp, ctypes.POINTER(fl_solve_opts), ctypes.POINTER(fl_info), vp]
@@ -213,6 +217,14 @@ def fl_apply_noalloc(op, u, y, stream=None):
     return y
 
 
+def fl_residual(op, f, u, r, stream=None):
+    """r = f - A u in FP64 (float64 device vectors; r may be f)."""
+    import torch
+    _check(load().fl_residual(op, _ptr(f, torch.float64), _ptr(u, torch.float64), _ptr(r, torch.float64),
+                              _stream(stream)))
+    return r
+
+
 def fl_tau_apply(op, r, z, s0=0.0, s1=1.0, stream=None):
     """z = M^{-1} r, M the sine-transform (tau) preconditioner of s0 I + s1 A (float64 vectors)."""
     import torch
@@ -243,9 +255,9 @@ def fl_variant_count(op, prec) -> int:
 
 
 def fl_variant_info(op, prec, k) -> dict:
-    d = (ctypes.c_int * 4)()
+    d = (ctypes.c_int * 5)()
     _check(load().fl_variant_info(op, _prec(prec), int(k), d))
-    return {"ex": d[0], "ey": d[1], "tile": d[2], "row_pairs": d[3]}
+    return {"ex": d[0], "ey": d[1], "tile": d[2], "row_pairs": d[3], "kind": d[4]}
 
 
 def fl_select_variant(op, prec, k):
@@ -350,6 +362,22 @@ def fl_batch_info(b):
     nc, mb = ctypes.c_int(), ctypes.c_int()
     _check(load().fl_batch_info(b, ctypes.byref(nc), ctypes.byref(mb)))
     return {"classes": nc.value, "max_batch": mb.value}
+
+
+def fl_batch_stats(b):
+    """Host waits and graph replays of the last batched solve, and each class's variants."""
+    nc = fl_batch_info(b)["classes"]
+    hw, gl = ctypes.c_int(), ctypes.c_int()
+    v32, v64 = (ctypes.c_int * nc)(), (ctypes.c_int * nc)()
+    _check(load().fl_batch_stats(b, ctypes.byref(hw), ctypes.byref(gl), v32, v64))
+    return {"host_waits": hw.value, "graph_launches": gl.value, "var32": list(v32), "var64": list(v64)}
+
+
+def fl_tune(op, prec):
+    """Select (and return) the cached, or newly timed, fastest variant for prec."""
+    k = ctypes.c_int()
+    _check(load().fl_tune(op, _prec(prec), ctypes.byref(k)))
+    return k.value
 
 
 def fl_batch_destroy(b):
@@ -523,6 +551,9 @@ class Batch:
     def info(self):
         return fl_batch_info(self._b)
 
+    def stats(self):
+        return fl_batch_stats(self._b)
+
     def close(self):
         if getattr(self, "_b", None):
             fl_batch_destroy(self._b)
@@ -573,6 +604,16 @@ class Operator:
             raise ValueError("expected %d entries, got %d" % (self.M, y.numel()))
         return fl_apply(self._op, u, y, stream)
 
+    def residual(self, f, u, r=None, stream=None):
+        """r = f - A u (float64); a new vector unless r is given (r may be f)."""
+        import torch
+        for t in (f, u):
+            if t.numel() != self.M:
+                raise ValueError("expected %d entries, got %d" % (self.M, t.numel()))
+        if r is None:
+            r = torch.empty_like(f)
+        return fl_residual(self._op, f, u, r, stream)
+
     def tau_apply(self, r, z=None, s0=0.0, s1=1.0, stream=None):
         """The sine-transform preconditioner of s0 I + s1 A applied to r (float64)."""
         import torch
@@ -610,6 +651,10 @@ class Operator:
 
     def select_variant(self, prec, k):
         fl_select_variant(self._op, prec, k)
+
+    def tune(self, prec):
+        """The variant for this operator's (d, FFT length, prec) from the on-disk tuning cache."""
+        return fl_tune(self._op, prec)
 
     def autotune(self, prec, reps=20, stream=None):
         return fl_autotune(self._op, prec, reps, stream)

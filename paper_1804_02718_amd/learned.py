@@ -80,7 +80,8 @@ def compare(net, N, seeds, tol=1e-8, reps=2):
             row[solver] = {"iters": info["iters"], "relres": info["relres"], "fell_back": info["fell_back"],
                            "seconds": wall}
             row[solver + "_u"] = u
-        row["rel_diff"] = float((row["fpcg_u"] - row["cg64_u"]).norm() / row["cg64_u"].norm())
+        uf, uc = row["fpcg_u"].cpu().numpy(), row["cg64_u"].cpu().numpy()
+        row["rel_diff"] = float(np.linalg.norm(uf - uc) / np.linalg.norm(uc))
         del row["fpcg_u"], row["cg64_u"], row["tau_u"]
         op.close()
         out.append(row)
@@ -123,7 +124,7 @@ def make_residual_samples(net, N, count, alphas=None, seed=7, max_cg=80, chunk=6
                 if i % 3 == 2:
                     kit = int(rng.integers(1, max_cg + 1))
                     u, _ = plain[j].poisson_solve(r, tol=1e-14, solver="cg64", max_iter=kit, raise_on_error=False)
-                    r = r - plain[j].apply(u)
+                    r = plain[j].residual(r, u, r)
             rs.append(r)
             al.append(float(alphas[j]))
             ops.append(scaled[j])

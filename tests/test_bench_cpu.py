@@ -25,6 +25,10 @@ def test_kernel_instance_names():
     assert bench.kernel_instance("x_inv", "float", 2048, var) == "k_xinv<float, 2048, 8, 4, 1, false, true>"
     assert bench.kernel_instance("z_fused", "float", 512, var, d=3) == "k_strided<float, 512, 16, 4, 2, false>"
     assert bench.kernel_instance("y_inv", "double", 512, var, d=3) == "k_strided<double, 512, 16, 4, 1, false>"
+    wv = {"ex": 16, "ey": 32, "tile": 4, "row_pairs": 2, "kind": 1}
+    assert bench.kernel_instance("y_fused", "float", 2048, wv) == "k_w2_yfused<float, 2048, 4, true>"
+    assert bench.kernel_instance("x_fwd", "float", 2048, wv) == "k_w2_xfwd<float, 2048, 4>"
+    assert bench.kernel_instance("x_inv", "double", 2048, dict(wv, tile=2)) == "k_w2_xinv<double, 2048, 2, false>"
 
 
 def test_traffic_file_schema():

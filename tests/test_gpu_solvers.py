@@ -317,6 +317,57 @@ def test_batched_c4_workload(fl):
     b.close()
 
 
+def test_batch_tuning_cache_and_host_waits(fl, tmp_path, monkeypatch):
+    # every class takes its kernel variants from the on-disk tuning cache: the first batch
+    # records one line per (d, FFT length, precision), a second batch and a single operator
+    # read them back; the solve waits on the GPU once per round of graph replays
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("FL_TUNE_CACHE", str(cache))
+    Ns = [64, 128, 256, 64, 128]
+    alphas = [0.6, 1.4, 1.9, 1.1, 0.3]
+    hs = [2.0 / N for N in Ns]
+    fs_np = [inputs.gauss_sum(2, N, 4, seed=400 + i) for i, N in enumerate(Ns)]
+    fs = [_t(f) for f in fs_np]
+    b = fl.Batch(2, Ns, alphas, hs)
+    st = b.stats()
+    lines = [ln.split() for ln in cache.read_text().splitlines()]
+    rec = {(int(w[2]), int(w[3]), int(w[4])): int(w[6]) for w in lines}
+    # classes are made in order of first appearance: N = 64, 128, 256 (FFT lengths 128, 256, 512)
+    for ci, P in enumerate((128, 256, 512)):
+        for prec, key in ((fl.FL_FP32, "var32"), (fl.FL_FP64, "var64")):
+            if (2, P, prec) in rec:
+                assert st[key][ci] == rec[(2, P, prec)]
+    assert len(rec) >= 3
+    us, infos = b.solve(fs, tol=1e-9)
+    torch.cuda.synchronize()
+    st = b.stats()
+    outer = max(i["outer_iters"] for i in infos)
+    assert all(i["status"] == 0 and i["relres"] <= 1e-9 for i in infos), infos
+    # one wait for the norms, one per refinement step's residuals, a few per inner solve
+    assert 1 + outer <= st["host_waits"] <= 1 + outer * 6, (st, outer)
+    assert st["graph_launches"] >= outer - 1
+    for i, (N, al) in enumerate(zip(Ns, alphas)):
+        A = oracle.dense(2, N, al, oracle.coeffs(2, al, hs[i], N)) if N <= 64 else None
+        if A is not None:
+            ug = us[i].cpu().numpy()
+            assert np.linalg.norm(fs_np[i] - A @ ug) <= 1.05e-9 * np.linalg.norm(fs_np[i])
+    b.close()
+    before = cache.read_text()
+    b2 = fl.Batch(2, Ns, alphas, hs)
+    assert b2.stats()["var32"] == st["var32"] and b2.stats()["var64"] == st["var64"]
+    assert cache.read_text() == before  # read back, nothing tuned again
+    b2.close()
+    op = fl.Operator(2, 1.0, 2.0 / 256, 256)
+    if (2, 512, fl.FL_FP32) in rec:
+        assert op.tune("fp32") == rec[(2, 512, fl.FL_FP32)]
+    op.close()
+    # an empty cache path turns tuning off: variant 0 everywhere
+    monkeypatch.setenv("FL_TUNE_CACHE", "")
+    b3 = fl.Batch(2, Ns, alphas, hs)
+    assert set(b3.stats()["var32"]) == {0} and set(b3.stats()["var64"]) == {0}
+    b3.close()
+
+
 @pytest.mark.parametrize("alpha", [0.7, 1.5])
 def test_allen_cahn_general_paper_form(fl, alpha):
     # Sec. 5.3's equation on (0,1)^2 with u = -1 outside, as the shifted field ubar = u + 1:
