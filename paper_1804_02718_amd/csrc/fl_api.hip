@@ -55,6 +55,10 @@ static fl_status make_twiddles(fl_op op) {
     }
     FL_HIP_TRY(hipMalloc((void **)&op->tw64, sizeof(double2) * P));
     FL_HIP_TRY(hipMalloc((void **)&op->tw32, sizeof(float2) * P));
+    if (!large_op(op)) {
+        FL_HIP_TRY(hipMalloc((void **)&op->sch64, sizeof(double2) * sched_len(P)));
+        FL_HIP_TRY(hipMalloc((void **)&op->sch32, sizeof(float2) * sched_len(P)));
+    }
     FL_HIP_TRY(hipMemcpy(op->tw64, t64.data(), sizeof(double2) * P, hipMemcpyHostToDevice));
     FL_HIP_TRY(hipMemcpy(op->tw32, t32.data(), sizeof(float2) * P, hipMemcpyHostToDevice));
     return FL_OK;
@@ -70,6 +74,8 @@ static void destroy(fl_op op) {
     (void)hipFree(op->lam32t);
     (void)hipFree(op->tw64);
     (void)hipFree(op->tw32);
+    (void)hipFree(op->sch64);
+    (void)hipFree(op->sch32);
     (void)hipFree(op->T1);
     (void)hipFree(op->T2);
     (void)hipFree(op->mu64t);
@@ -146,7 +152,8 @@ static fl_status create(int d, double alpha, double gamma, double h, int N, cons
         set_error("stream creation failed");
         return fail(FL_E_DEVICE);
     }
-    st = build_coeffs(op, s);
+    st = make_schedules(op, s);
+    if (st == FL_OK) st = build_coeffs(op, s);
     if (st == FL_OK) st = build_symbol(op, s);
     if (st == FL_OK) {
         e = hipMemcpyAsync(&op->a0, op->a, sizeof(double), hipMemcpyDeviceToHost, s);

@@ -91,7 +91,7 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xfwd(
     const int ra = 2 * (bx * LPB + lp), rb = ra + 1;
     const bool va = ra < nrows, vb = rb < nrows;
     C2<T> tws[num_tw<PN>()];
-    load_twiddles<T, P, PN>(tws, table, tl);
+    load_twiddles_lanes<T, P, PN>(tws, table, tl);
     C2<T> v[E];
     // loads from clamped, always valid addresses; rows past nrows read as 0
     const T *ua = u + (long)(va ? ra : 0) * in_pitch, *ub = u + (long)(vb ? rb : 0) * in_pitch;
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xinv(
     const int ra = 2 * (bx * LPB + lp), rb = ra + 1;
     const bool va = ra < nrows, vb = rb < nrows;
     C2<T> tws[num_tw<PN>()];
-    load_twiddles<T, P, PN>(tws, table, tl);
+    load_twiddles_lanes<T, P, PN>(tws, table, tl);
     // the block's rows, tile by tile (contiguous runs), into LDS: row pair p,
     // member w at p*LL + w*Q + kx
     constexpr int RW = 2 * LPB, NTH = LPB * TL;
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_conv1d(
     const int ra = 2 * (bx * LPB + lp), rb = ra + 1;
     const bool va = ra < nrows, vb = rb < nrows;
     C2<T> tws[num_tw<PN>()];
-    load_twiddles<T, P, PN>(tws, table, tl);
+    load_twiddles_lanes<T, P, PN>(tws, table, tl);
     C2<T> v[E];
     // loads from clamped, always valid addresses; out-of-range values replaced by 0
     const T *ua = u + (long)(va ? ra : 0) * n, *ub = u + (long)(vb ? rb : 0) * n;
@@ -448,7 +448,7 @@ void k_strided(
     const C2<T> *src = in + (o * st.in_outer + t * st.in_tile + c);
     C2<T> *dst = out + (o * st.out_outer + t * st.out_tile + c);
     C2<T> tws[num_tw<PN>()];
-    load_twiddles<T, P, PN>(tws, table, tl);
+    load_twiddles_lanes<T, P, PN>(tws, table, tl);
     C2<T> v[E];
     auto lidx = [c](int pos) { return padpos(pos) * C + c; };
     if constexpr (MODE == 1) {
@@ -534,7 +534,7 @@ static void launch_xfwd(const T *u, C2<T> *out, int nrows, int n_in, long in_pit
                         BatchStrides bz = BatchStrides{}) {
     const int pairs = (nrows + 1) / 2;
     launch(k_xfwd<T, P, E, C, LPB, PACK>, dim3(cdiv(pairs, LPB), 1, nb), dim3(LPB * (P / E)), s, ev, u, out, nrows, n_in,
-           in_pitch, nj, ntiles, tw, done, bz);
+           in_pitch, nj, ntiles, tw + sched_off(P, E), done, bz);
 }
 
 template <typename T, int P, int E, int C, int LPB, bool PACK = false>
@@ -544,10 +544,10 @@ static void launch_xinv(const C2<T> *in, T *y, int nrows, int n_out, long out_pi
     const int pairs = (nrows + 1) / 2;
     if (ep.active())
         launch(k_xinv<T, P, E, C, LPB, true, PACK>, dim3(cdiv(pairs, LPB), 1, nb), dim3(LPB * (P / E)), s, ev, in,
-               y, nrows, n_out, out_pitch, nj, ntiles, tw, ep, done, bz);
+               y, nrows, n_out, out_pitch, nj, ntiles, tw + sched_off(P, E), ep, done, bz);
     else
         launch(k_xinv<T, P, E, C, LPB, false, PACK>, dim3(cdiv(pairs, LPB), 1, nb), dim3(LPB * (P / E)), s, ev, in,
-               y, nrows, n_out, out_pitch, nj, ntiles, tw, ep, done, bz);
+               y, nrows, n_out, out_pitch, nj, ntiles, tw + sched_off(P, E), ep, done, bz);
 }
 
 template <typename T, int P, int E, int C, int MODE, bool PACK = false>
@@ -555,7 +555,7 @@ static void launch_strided(const C2<T> *in, C2<T> *out, int ncols, int nouter, i
                            const Strides &st, const C2<T> *tw, const T *lam, const double *done, hipStream_t s,
                            const hipEvent_t *ev, int nb = 1, BatchStrides bz = BatchStrides{}) {
     launch(k_strided<T, P, E, C, MODE, PACK>, dim3(cdiv(ncols, C), nouter, nb), dim3(C * (P / E)), s, ev, in, out, ncols,
-           n_in, n_out, st, tw, lam, done, bz);
+           n_in, n_out, st, tw + sched_off(P, E), lam, done, bz);
 }
 
 template <typename T, int P, int E, int LPB>
@@ -565,10 +565,10 @@ static void launch_conv1d(const T *u, T *y, int nrows, int n, int n_in, const T 
     const int pairs = (nrows + 1) / 2;
     if (ep.active())
         launch(k_conv1d<T, P, E, LPB, true>, dim3(cdiv(pairs, LPB), 1, nb), dim3(LPB * (P / E)), s, ev, u, y, nrows,
-               n, n_in, lam, tw, ep, done, bz);
+               n, n_in, lam, tw + sched_off(P, E), ep, done, bz);
     else
         launch(k_conv1d<T, P, E, LPB, false>, dim3(cdiv(pairs, LPB), 1, nb), dim3(LPB * (P / E)), s, ev, u, y,
-               nrows, n, n_in, lam, tw, ep, done, bz);
+               nrows, n, n_in, lam, tw + sched_off(P, E), ep, done, bz);
 }
 
 // ---------------------------------------------------------------------------
@@ -578,6 +578,9 @@ static void launch_conv1d(const T *u, T *y, int nrows, int n, int n_in, const T 
 template <typename T> static const C2<T> *twid(fl_op op);
 template <> const float2 *twid<float>(fl_op op) { return op->tw32; }
 template <> const double2 *twid<double>(fl_op op) { return op->tw64; }
+template <typename T> static const C2<T> *scht(fl_op op);
+template <> const float2 *scht<float>(fl_op op) { return op->sch32; }
+template <> const double2 *scht<double>(fl_op op) { return op->sch64; }
 template <typename T> static const T *lamt(fl_op op);
 template <> const float *lamt<float>(fl_op op) { return op->lam32t; }
 template <> const double *lamt<double>(fl_op op) { return op->lam64t; }
@@ -592,6 +595,7 @@ template <typename T> MvCtx<T> single_ctx(fl_op op) {
     c.T1 = op->T1;
     c.T2 = op->T2;
     c.tw = twid<T>(op);
+    c.tws = scht<T>(op);
     c.lam = lamt<T>(op);
     return c;
 }
@@ -607,7 +611,7 @@ static void matvec_v(const MvCtx<T> &cx, const T *u, T *y, const Epi<T> &ep, con
     const int nt = cdiv(spec_cols(D, P), C);
     C2<T> *T1 = (C2<T> *)cx.T1;
     C2<T> *T2 = (C2<T> *)cx.T2;
-    const C2<T> *tw = cx.tw;
+    const C2<T> *tw = cx.tws;  // the launchers take each plan's lane-ordered table from here
     const T *lam = cx.lam;
     const int nb = cx.batch;
     // element strides between problems: vectors, tiled spectra (in complex values), lambda
@@ -1240,6 +1244,56 @@ __global__ __launch_bounds__(256) void k_symbol1d(const double *__restrict__ a, 
 }
 
 // ---------------------------------------------------------------------------
+// lane-ordered twiddle tables: thread tl of plan (P, E) gathers its twiddles
+// from the natural-order table exactly as load_twiddles does and stores them
+// at k * TL + tl
+// ---------------------------------------------------------------------------
+template <typename T, int P, int E>
+__global__ __launch_bounds__(256) void k_make_sched(const C2<T> *__restrict__ table, C2<T> *__restrict__ sched) {
+    using PN = Plan<P, E>;
+    constexpr int TL = P / E;
+    const int tl = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tl >= TL) return;
+    if constexpr (PN::L > 1) {
+        C2<T> tws[num_tw<PN>()];
+        load_twiddles<T, P, PN>(tws, table, tl);
+        C2<T> *out = sched + sched_off(P, E);
+#pragma unroll
+        for (int k = 0; k < num_tw<PN>(); ++k) out[(long)k * TL + tl] = tws[k];
+    }
+}
+
+template <typename T, int P, int E = 2>
+static void make_sched_all(const C2<T> *table, C2<T> *sched, hipStream_t s) {
+    if constexpr (E <= 32) {
+        if constexpr (plan_ok(P, E)) {
+            constexpr int TL = P / E;
+            hipLaunchKernelGGL((k_make_sched<T, P, E>), dim3(cdiv(TL, 256)), dim3(256), 0, s, table, sched);
+        }
+        make_sched_all<T, P, 2 * E>(table, sched, s);
+    }
+}
+
+fl_status make_schedules(fl_op op, hipStream_t s) {
+    if (large_op(op)) return FL_OK;
+    switch (op->P) {
+#define FL_SCHED(PP)                                                  \
+    case PP:                                                          \
+        make_sched_all<double, PP>(op->tw64, op->sch64, s);           \
+        make_sched_all<float, PP>(op->tw32, op->sch32, s);            \
+        break;
+        FL_SCHED(8) FL_SCHED(16) FL_SCHED(32) FL_SCHED(64) FL_SCHED(128) FL_SCHED(256) FL_SCHED(512)
+        FL_SCHED(1024) FL_SCHED(2048)
+#undef FL_SCHED
+        default:
+            set_error("no twiddle tables for FFT length %d", op->P);
+            return FL_E_UNSUPPORTED;
+    }
+    FL_HIP_TRY(hipGetLastError());
+    return FL_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Large 2D operators (FFT length P = 4096 ... 16384): a line no longer fits a
 // workgroup's LDS (16384 FP64 values take 256 KB), so every radix pass of the
 // transforms is a kernel over the whole buffer in HBM (Stockham autosort,
@@ -1586,12 +1640,12 @@ fl_status build_symbol(fl_op op, hipStream_t s) {
     hipLaunchKernelGGL(k_embed, dim3(grid(total)), dim3(256), 0, s, op->a, cemb, d, op->N, P, -op->c);
 #define FL_SY(PP)                                                          \
     case PP:                                                               \
-        if (d == 2) symbol_fft<PP, 2>(cemb, T, op->tw64, s);               \
-        else symbol_fft<PP, 3>(cemb, T, op->tw64, s);                      \
+        if (d == 2) symbol_fft<PP, 2>(cemb, T, op->sch64, s);              \
+        else symbol_fft<PP, 3>(cemb, T, op->sch64, s);                     \
         break;
     switch (P) {
         FL_SY(8) FL_SY(16) FL_SY(32) FL_SY(64) FL_SY(128) FL_SY(256) FL_SY(512) FL_SY(1024)
-        case 2048: symbol_fft<2048, 2>(cemb, T, op->tw64, s); break;
+        case 2048: symbol_fft<2048, 2>(cemb, T, op->sch64, s); break;
     }
 #undef FL_SY
     const long ql = d == 2 ? (long)Q * Q : (long)Q * Q * Q;

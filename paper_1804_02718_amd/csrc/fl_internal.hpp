@@ -259,6 +259,46 @@ __device__ __forceinline__ void load_twiddles(C2<T> *tws, const C2<T> *__restric
     }
 }
 
+// Lane-ordered twiddles.  For the plan of length P with E points per thread
+// (TL = P / E threads per line), entry k * TL + tl of the plan's table holds the
+// k-th twiddle thread tl needs, in the order load_twiddles gathers them; a
+// wavefront's k-th twiddle load then reads consecutive entries.  One buffer
+// holds the tables of every E = 2, 4, ..., 32 (E <= P), at sched_off(P, E).
+constexpr int plan_stages(int P, int E) {
+    int l = 0;
+    for (int rem = P; rem > 1; rem /= (rem < E ? rem : E)) ++l;
+    return l;
+}
+constexpr int plan_radix(int P, int E, int s) {
+    int rem = P;
+    for (int i = 0; i < s; ++i) rem /= (rem < E ? rem : E);
+    return rem < E ? rem : E;
+}
+constexpr int plan_tw(int P, int E) {
+    int o = 0;
+    for (int s = 1; s < plan_stages(P, E); ++s) o += E - E / plan_radix(P, E, s);
+    return o > 0 ? o : 1;
+}
+// the plans the kernels instantiate: at most 6 stages, at most 32 points per thread
+constexpr bool plan_ok(int P, int E) { return E >= 2 && E <= P && E <= 32 && plan_stages(P, E) <= 6; }
+constexpr long sched_off(int P, int E) {
+    long off = 0;
+    for (int e = 2; e < E; e *= 2)
+        if (plan_ok(P, e)) off += (long)plan_tw(P, e) * (P / e);
+    return off;
+}
+constexpr long sched_len(int P) { return sched_off(P, 64); }
+
+template <typename T, int P, typename PL>
+__device__ __forceinline__ void load_twiddles_lanes(C2<T> *tws, const C2<T> *__restrict__ sched, int tl) {
+    static_assert(plan_tw(P, PL::E) == num_tw<PL>() && plan_stages(P, PL::E) == PL::L, "plan tables");
+    constexpr int TL = P / PL::E;
+    if constexpr (PL::L > 1) {
+#pragma unroll
+        for (int k = 0; k < num_tw<PL>(); ++k) tws[k] = sched[k * TL + tl];
+    }
+}
+
 // forward butterflies of stage S (twiddle, then DFT with exp(-2 pi i ...))
 template <typename T, typename PL, int S>
 __device__ __forceinline__ void fwd_bfly(C2<T> *v, const C2<T> *tws) {
@@ -343,6 +383,8 @@ struct fl_op_s {
     int var32 = 0, var64 = 0;     // selected kernel variants (0 = default)
     double2 *tw64 = nullptr;      // exp(-2 pi i m / P), m < P
     float2 *tw32 = nullptr;
+    double2 *sch64 = nullptr;     // lane-ordered twiddles of every plan (sched_len(P) entries)
+    float2 *sch32 = nullptr;
     void *T1 = nullptr;           // spectra workspaces (sized for FP64)
     void *T2 = nullptr;
     size_t T1_bytes = 0, T2_bytes = 0;
@@ -396,7 +438,8 @@ template <typename T> struct MvCtx {
     int d = 2, n = 0, P = 0, Q = 0;
     int nk[3] = {0, 0, 0};     // interior nodes per axis, x first
     void *T1 = nullptr, *T2 = nullptr;
-    const C2<T> *tw = nullptr;
+    const C2<T> *tw = nullptr;   // exp(-2 pi i m / P)
+    const C2<T> *tws = nullptr;  // lane-ordered twiddles of every plan
     const T *lam = nullptr;
     bool odd = false;          // forward loads take the odd extension (sine-transform preconditioner)
     int batch = 1;
@@ -410,6 +453,8 @@ template <typename T>
 fl_status matvec_ctx(const MvCtx<T> &cx, int variant, const T *u, T *y, const Epi<T> &ep, const double *done,
                      hipStream_t s, hipEvent_t *ev = nullptr);
 fl_status build_symbol(fl_op op, hipStream_t s);
+// the lane-ordered twiddle tables of op's FFT length (LDS path) from tw64 / tw32
+fl_status make_schedules(fl_op op, hipStream_t s);
 int kernel_p_supported(int P);
 fl_status unet_apply(fl_unet u, const double *r, int n, double alpha, double *z, const double *rr_dev,
                      hipStream_t s);

@@ -694,3 +694,29 @@ def test_elements_far_from_origin_vs_high_precision(d, alpha, e):
                       [e[1], e[1] + 1], [e[2], e[2] + 1])
         got = E[e[2], e[1], e[0]]
     assert abs(got - float(ref)) <= 1e-15 * float(ref), (got, float(ref))
+
+
+@pytest.mark.parametrize("alpha", [0.5, 1.0, 1.5])
+def test_poisson_constant_rhs_between_disk_solutions(alpha):
+    # Sec. 5.2, Example 5.2.3 (f = 1 on (-1,1)^2, zero outside) has no closed form, but the
+    # comparison principle brackets it: B_1 lies inside the square, which lies inside
+    # B_sqrt2, and on a ball B_R the solution is (R^2 - |x|^2)_+^{a/2} / K with
+    # K = 2^a G(1 + a/2) G((d + a)/2) / G(d/2) (the bump closed form, scaled).  So
+    # (1 - |x|^2)_+^{a/2} / K <= u(x) <= (2 - |x|^2)^{a/2} / K, and the discrete solution (an
+    # M-matrix system) must sit in that band up to its O(h^{a/2}) error near the edges.
+    N = 64
+    h = 2.0 / N
+    a = oracle.coeffs(2, alpha, h, N)
+    A = oracle.dense(2, N, alpha, a)
+    u = oracle.solve_dense(A, np.ones((N - 1) ** 2))
+    K = float(2 ** mp.mpf(alpha) * mp.gamma(1 + mp.mpf(alpha) / 2) ** 2)
+    x1, x2 = inputs.grid(2, N)
+    r2 = x1 * x1 + x2 * x2
+    lo = np.maximum(0.0, 1.0 - r2) ** (alpha / 2) / K
+    hi = (2.0 - r2) ** (alpha / 2) / K
+    inner = r2 <= 0.25
+    assert np.all(u[inner] >= lo[inner] * (1 - 0.02)), (u[inner] / lo[inner]).min()
+    assert np.all(u <= hi * (1 + 0.02)), (u / hi).max()
+    # the centre value lies strictly inside the band: the square is neither ball
+    c = np.argmin(r2)
+    assert lo[c] * 1.01 < u[c] < hi[c] * 0.99, (lo[c], u[c], hi[c])
