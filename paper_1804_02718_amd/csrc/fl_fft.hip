@@ -90,8 +90,6 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xfwd(
     const int bx = xcd_block(blockIdx.x, gridDim.x);
     const int ra = 2 * (bx * LPB + lp), rb = ra + 1;
     const bool va = ra < nrows, vb = rb < nrows;
-    C2<T> tws[num_tw<PN>()];
-    load_twiddles_lanes<T, P, PN>(tws, table, tl);
     C2<T> v[E];
     // loads from clamped, always valid addresses; rows past nrows read as 0
     const T *ua = u + (long)(va ? ra : 0) * in_pitch, *ub = u + (long)(vb ? rb : 0) * in_pitch;
@@ -99,6 +97,9 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xfwd(
         const T xa = ua[i], xb = ub[i];
         return mk<T>(va ? xa : T(0), vb ? xb : T(0));
     });
+    // twiddles after the data: the first stage needs none of them
+    C2<T> tws[num_tw<PN>()];
+    load_twiddles_lanes<T, P, PN>(tws, table, tl);
     const int base = lp * PL;
     auto lidx = [base](int pos) { return base + padpos(pos); };
     fwd_stages<T, P, PN, 0>(v, lds, tl, tws, lidx);
@@ -206,7 +207,7 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xinv(
                 const int t = t0 + it * ST;
                 const int kx = t * C + c;
                 if (t >= NT || kx >= (PACK ? P / 2 : Q)) continue;
-                const C2<T> x = rv ? irow[t * tstride] : mk<T>(0, 0);
+                const C2<T> x = keep<T>(rv, irow[t * tstride]);
                 if (PACK && kx == 0) {
                     lrow[0] = mk<T>(x.x, 0);
                     lrow[P / 2] = mk<T>(x.y, 0);
@@ -219,7 +220,8 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xinv(
                 const int c = idx % C, rr = (idx / C) % RW, t = idx / (C * RW);
                 const int kx = t * C + c, row = r0 + rr;
                 if (kx >= (PACK ? P / 2 : Q)) continue;
-                const C2<T> x = row < nrows ? in[tiled_rowbase(row, nj, ntiles, C) + t * tstride + c] : mk<T>(0, 0);
+                const bool rv = row < nrows;
+                const C2<T> x = keep<T>(rv, in[tiled_rowbase(rv ? row : 0, nj, ntiles, C) + t * tstride + c]);
                 C2<T> *lrow = lds + (rr >> 1) * LL + (rr & 1) * Q;
                 if (PACK && kx == 0) {
                     lrow[0] = mk<T>(x.x, 0);
@@ -448,7 +450,6 @@ void k_strided(
     const C2<T> *src = in + (o * st.in_outer + t * st.in_tile + c);
     C2<T> *dst = out + (o * st.out_outer + t * st.out_tile + c);
     C2<T> tws[num_tw<PN>()];
-    load_twiddles_lanes<T, P, PN>(tws, table, tl);
     C2<T> v[E];
     auto lidx = [c](int pos) { return padpos(pos) * C + c; };
     if constexpr (MODE == 1) {
@@ -456,28 +457,35 @@ void k_strided(
         for (int j = 0; j < E; ++j) {
             const int pos = out_pos<P, PN, L - 1>(tl, j);
             const bool in = pos < n_in;
-            const C2<T> x = src[(in ? pos : 0) * st.line];
-            v[j] = (valid && in) ? x : mk<T>(0, 0);
+            v[j] = keep<T>(valid && in, src[(in ? pos : 0) * st.line]);
         }
+        load_twiddles_lanes<T, P, PN>(tws, table, tl);
         adj_stages<T, P, PN, L - 1>(v, lds, tl, tws, lidx);
     } else {
-        load_line<T, P, PN>(v, tl, n_in, [&](int i) {
-            const C2<T> x = src[i * st.line];
-            return valid ? x : mk<T>(T(0), T(0));
-        });
+        load_line<T, P, PN>(v, tl, n_in, [&](int i) { return keep<T>(valid, src[i * st.line]); });
+        // twiddles after the data: the first stage needs none of them
+        load_twiddles_lanes<T, P, PN>(tws, table, tl);
         if constexpr (MODE == 2) {
             // lambda at this thread's spectral positions, fetched with the data
             T lv[E];
             const T *lo = lam + (t * st.lam_tile + fold<P>(o) * st.lam_outer + c);
 #pragma unroll
             for (int j = 0; j < E; ++j) lv[j] = lo[fold<P>(out_pos<P, PN, L - 1>(tl, j)) * C];
+            // the packed column's second symbol d, fetched with the first so its
+            // latency overlaps the forward transform; zero off column 0
+            T ldv[E];
+            if (PACK && t == 0) {
+#pragma unroll
+                for (int j = 0; j < E; ++j) {
+                    const T d = lam[st.lam_pack + fold<P>(out_pos<P, PN, L - 1>(tl, j))];
+                    ldv[j] = c == 0 ? d : T(0);
+                }
+            }
             fwd_stages<T, P, PN, 0>(v, lds, tl, tws, lidx);
             if (PACK && t == 0) {  // block-uniform: the tile holding the packed column
-                T ldv[E];
-#pragma unroll
-                for (int j = 0; j < E; ++j)
-                    ldv[j] = c == 0 ? lam[st.lam_pack + fold<P>(out_pos<P, PN, L - 1>(tl, j))] : T(0);
-                __syncthreads();
+                // every lane exchanges and applies s Z(k) + d conj Z(-k) without a
+                // branch (d = 0 off column 0); the forward stages end with all of
+                // their LDS reads behind a barrier, so the writes need none before
 #pragma unroll
                 for (int j = 0; j < E; ++j) lds[lidx(out_pos<P, PN, L - 1>(tl, j))] = v[j];
                 __syncthreads();
@@ -485,8 +493,7 @@ void k_strided(
                 for (int j = 0; j < E; ++j) {
                     const int pos = out_pos<P, PN, L - 1>(tl, j);
                     const C2<T> zm = lds[lidx((P - pos) & (P - 1))];
-                    v[j] = c == 0 ? mk<T>(lv[j] * v[j].x + ldv[j] * zm.x, lv[j] * v[j].y - ldv[j] * zm.y)
-                                  : cscale<T>(v[j], lv[j]);
+                    v[j] = mk<T>(lv[j] * v[j].x + ldv[j] * zm.x, lv[j] * v[j].y - ldv[j] * zm.y);
                 }
                 __syncthreads();
             } else {
@@ -1366,12 +1373,13 @@ __global__ __launch_bounds__(256) void k_big_pass(const C2<T> *__restrict__ in, 
         for (int r = 0; r < R; ++r) {
             const int q = j + r * PR;
             if (n_in >= 0) {
-                v[r] = q < n_in ? src[(long)q * pstride] : mk<T>(0, 0);
+                const bool ok = q < n_in;
+                v[r] = keep<T>(ok, src[(long)(ok ? q : 0) * pstride]);
             } else {
                 const int qs = q < P / 2 ? q : P - 2 - q;  // -1 at q = P - 1
                 const bool ok = qs >= 0 && qs < -n_in;
                 const C2<T> x = src[(long)(ok ? qs : 0) * pstride];
-                v[r] = ok ? (q < P / 2 ? x : mk<T>(-x.x, -x.y)) : mk<T>(0, 0);
+                v[r] = keep<T>(ok, q < P / 2 ? x : mk<T>(-x.x, -x.y));
             }
             if (LAM) v[r] = cscale<T>(v[r], lam[(long)(q <= P / 2 ? q : P - q) * Q + line]);
         }

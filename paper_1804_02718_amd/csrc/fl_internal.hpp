@@ -49,6 +49,12 @@ template <typename T> __device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
     return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 template <typename T> __device__ __forceinline__ C2<T> cscale(C2<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+// x where b holds, else zero, as two scalar selects: a conditional over the
+// vector type compiles to a branch around the load that produced x, and one
+// such branch per element serialises a thread's loads behind exec-mask jumps
+template <typename T> __device__ __forceinline__ C2<T> keep(bool b, C2<T> x) {
+    return mk<T>(b ? x.x : T(0), b ? x.y : T(0));
+}
 template <typename T> __device__ __forceinline__ C2<T> cconj(C2<T> a) { return mk<T>(a.x, -a.y); }
 // multiply by s*i, s = +1 or -1 (exact)
 template <typename T, int S> __device__ __forceinline__ C2<T> cmuli(C2<T> a) {
@@ -212,13 +218,12 @@ __device__ __forceinline__ void load_line(C2<T> *v, int tl, int n_in, Ld ld) {
             const int pos = in_pos<P, PL, 0>(tl, j);
             if ((j % R) < R / 2) {
                 const bool ok = pos < -n_in;
-                const C2<T> x = ld(ok ? pos : 0);
-                v[j] = ok ? x : zero;
+                v[j] = keep<T>(ok, ld(ok ? pos : 0));
             } else {
                 const int src = P - 2 - pos;
                 const bool ok = src >= 0 && src < -n_in;
                 const C2<T> x = ld(ok ? src : 0);
-                v[j] = ok ? mk<T>(-x.x, -x.y) : zero;
+                v[j] = keep<T>(ok, mk<T>(-x.x, -x.y));
             }
         }
     } else if (n_in <= P / 2) {
@@ -227,8 +232,7 @@ __device__ __forceinline__ void load_line(C2<T> *v, int tl, int n_in, Ld ld) {
             if ((j % R) < R / 2) {
                 const int pos = in_pos<P, PL, 0>(tl, j);
                 const bool ok = pos < n_in;
-                const C2<T> x = ld(ok ? pos : 0);
-                v[j] = ok ? x : zero;
+                v[j] = keep<T>(ok, ld(ok ? pos : 0));
             } else {
                 v[j] = zero;
             }
@@ -238,8 +242,7 @@ __device__ __forceinline__ void load_line(C2<T> *v, int tl, int n_in, Ld ld) {
         for (int j = 0; j < E; ++j) {
             const int pos = in_pos<P, PL, 0>(tl, j);
             const bool ok = pos < n_in;
-            const C2<T> x = ld(ok ? pos : 0);
-            v[j] = ok ? x : zero;
+            v[j] = keep<T>(ok, ld(ok ? pos : 0));
         }
     }
 }

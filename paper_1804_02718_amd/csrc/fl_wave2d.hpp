@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1))) void k
             } else {
                 x = mk<T>(ur[2 * m], 2 * m + 1 < n_in ? ur[2 * m + 1] : T(0));
             }
-            return rv ? x : mk<T>(T(0), T(0));
+            return keep<T>(rv, x);
         });
     } else {
         // odd extension e[p] about -1 of n = -n_in values: x[p] for p < n,
@@ -329,19 +329,20 @@ __global__ __launch_bounds__(64 * C) __attribute__((amdgpu_waves_per_eu(1))) voi
     C2<T> tws[num_tw<PN>()];
     wave_twiddles<T, P, PN, 1>(tws, table, tl);
     // lambda at this lane's spectral positions
-    T lv[E];
+    T lv[E], ldv[E];
     const T *lo = lam + (t * lam_tile + c);
 #pragma unroll
     for (int j = 0; j < E; ++j) lv[j] = lo[fold<P>(out_pos<P, PN, L - 1>(tl, j)) * C];
+    if (PACK && t == 0 && c == 0) {  // the packed column's second symbol, fetched early
+#pragma unroll
+        for (int j = 0; j < E; ++j) ldv[j] = lam[lam_pack + fold<P>(out_pos<P, PN, L - 1>(tl, j))];
+    }
     __syncthreads();
     C2<T> v[E];
     load_line<T, P, PN>(v, tl, n_in, [&](int i) { return wl[li(i)]; });
     wave_lds_sync();
     wave_fwd<T, P, PN, 0>(v, wl, tl, tws);
     if (PACK && t == 0 && c == 0) {  // wavefront-uniform: the packed DC / Nyquist column
-        T ldv[E];
-#pragma unroll
-        for (int j = 0; j < E; ++j) ldv[j] = lam[lam_pack + fold<P>(out_pos<P, PN, L - 1>(tl, j))];
 #pragma unroll
         for (int j = 0; j < E; ++j) wl[li(out_pos<P, PN, L - 1>(tl, j))] = v[j];
         wave_lds_sync();
