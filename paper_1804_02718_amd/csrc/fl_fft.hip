@@ -969,15 +969,7 @@ __global__ void k_tile_lambda(const double *__restrict__ lam64, T *__restrict__ 
     }
 }
 
-// natural-order (Q x Q, kx fastest) symbol of the large-operator passes
-template <typename T>
-__global__ void k_natural_symbol(const double *__restrict__ lam64, T *__restrict__ out, int Q, SymMap m) {
-    const long total = (long)Q * Q;
-    const int N2 = Q - 1;
-    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (long)gridDim.x * blockDim.x)
-        out[idx] = (T)sym_at(lam64, idx, (int)(idx % Q), (int)(idx / Q), 0, 2, N2, m);
-}
+#include "fl_fourstep.hpp"
 
 // bad <- 1 where s0 + s1 lambda is not positive and finite on a sine mode
 __global__ void k_tau_check(const double *__restrict__ lam64, int d, int Q, SymMap m, int *bad) {
@@ -1081,12 +1073,15 @@ fl_status tau_symbol(fl_op op, double s0, double s1, int prec, int C, void *lt, 
         set_error("s0 + s1 lambda is not positive on every sine mode: no sine-transform preconditioner");
         return FL_E_BREAKDOWN;
     }
-    if (large_op(op)) {  // natural order, as the large-operator passes read lambda
+    if (large_op(op)) {  // the column order of the four-step passes
         const int gn = cdiv(ql, 256) > 65536 ? 65536 : cdiv(ql, 256);
+        int P1 = 0, P2 = 0;
+        fs_split(op->P, P1, P2);
         if (prec == FL_FP32)
-            hipLaunchKernelGGL(k_natural_symbol<float>, dim3(gn), dim3(256), 0, s, op->lam64, (float *)lt, Q, m);
+            hipLaunchKernelGGL(k_fs_permute<float>, dim3(gn), dim3(256), 0, s, op->lam64, (float *)lt, Q, P1, P2, m);
         else
-            hipLaunchKernelGGL(k_natural_symbol<double>, dim3(gn), dim3(256), 0, s, op->lam64, (double *)lt, Q, m);
+            hipLaunchKernelGGL(k_fs_permute<double>, dim3(gn), dim3(256), 0, s, op->lam64, (double *)lt, Q, P1, P2,
+                               m);
         FL_HIP_TRY(hipGetLastError());
         return FL_OK;
     }
@@ -1281,8 +1276,24 @@ static void make_sched_all(const C2<T> *table, C2<T> *sched, hipStream_t s) {
     }
 }
 
+// twiddles exp(-2 pi i m / L) of the four-step's short transforms (L = 128 at
+// fs_tw_off(128), L = 64 at fs_tw_off(64)), taken from the length-P table
+template <typename T>
+__global__ void k_fs_subtw(const C2<T> *__restrict__ tw, C2<T> *__restrict__ sub, int P) {
+    const int i = threadIdx.x;
+    if (i < 128) sub[fs_tw_off(128) + i] = tw[i * (P / 128)];
+    if (i < 64) sub[fs_tw_off(64) + i] = tw[i * (P / 64)];
+}
+
 fl_status make_schedules(fl_op op, hipStream_t s) {
-    if (large_op(op)) return FL_OK;
+    if (large_op(op)) {
+        FL_HIP_TRY(hipMalloc((void **)&op->sch64, sizeof(double2) * kFsTwLen));
+        FL_HIP_TRY(hipMalloc((void **)&op->sch32, sizeof(float2) * kFsTwLen));
+        hipLaunchKernelGGL(k_fs_subtw<double>, dim3(1), dim3(128), 0, s, op->tw64, op->sch64, op->P);
+        hipLaunchKernelGGL(k_fs_subtw<float>, dim3(1), dim3(128), 0, s, op->tw32, op->sch32, op->P);
+        FL_HIP_TRY(hipGetLastError());
+        return FL_OK;
+    }
     switch (op->P) {
 #define FL_SCHED(PP)                                                  \
     case PP:                                                          \
@@ -1301,24 +1312,17 @@ fl_status make_schedules(fl_op op, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Large 2D operators (FFT length P = 4096 ... 16384): a line no longer fits a
-// workgroup's LDS (16384 FP64 values take 256 KB), so every radix pass of the
-// transforms is a kernel over the whole buffer in HBM (Stockham autosort,
-// out of place, radix 16 (as 4 x 4 in registers) then a radix-4 or radix-2
-// pass for the rest of log2 P; the indexing of Govindaraju et al., SC 2008).  The 288 GB of HBM hold the two P x Qp
-// complex work buffers (2.1 GB each in FP64 at P = 16384) with room to spare.
-// Steps of y = A u (u: ny rows of nx values, x fastest):
-//   pack row pairs into complex lines | x forward passes | Hermitian split into
-//   half spectra (ny rows x Q columns, row stride Qp) | y forward passes over
-//   the Q columns | y inverse passes, lambda applied as the first pass loads
-//   (natural order, folded ky) and only ny rows kept | unsplit | x inverse
-//   passes, nx kept | unpack (real part: even row, imaginary: odd row) with
-//   the solver epilogue y = a1 w1 + a2 w2 + scale (A u).
+// Symbol of a large 2D operator (FFT length P = 4096 ... 16384), built once:
+// the generator embedded in P x P, transformed along x (P/2 row pairs packed
+// as complex lines, then split into half spectra) and along y over the Q
+// columns, every radix pass a kernel over the whole buffer in HBM (Stockham
+// autosort, out of place, radix 16 as 4 x 4 in registers, then radix 4 or 2
+// for the rest of log2 P; the indexing of Govindaraju et al., SC 2008).  The
+// matvec itself runs the four-step passes of fl_fourstep.hpp.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_big_pack(const T *__restrict__ u, C2<T> *__restrict__ lines, int nx, int ny,
-                                                  int P, const double *__restrict__ done) {
-    if (done && *done != 0.0) return;
+                                                  int P) {
     const int nl = (ny + 1) / 2;
     const long total = (long)nl * nx;
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
@@ -1330,31 +1334,23 @@ __global__ __launch_bounds__(256) void k_big_pack(const T *__restrict__ u, C2<T>
     }
 }
 
-// radix-4 DFT in place: forward X1 = t1 - i t3, X3 = t1 + i t3 (inverse: signs swap)
-template <typename T, bool INV>
+// forward radix-4 DFT in place: X1 = t1 - i t3, X3 = t1 + i t3
+template <typename T>
 __device__ __forceinline__ void big_dft4(C2<T> &a, C2<T> &b, C2<T> &c, C2<T> &d) {
     const C2<T> t0 = cadd<T>(a, c), t1 = csub<T>(a, c), t2 = cadd<T>(b, d), t3 = csub<T>(b, d);
-    const C2<T> it3 = INV ? cmuli<T, 1>(t3) : cmuli<T, -1>(t3);
+    const C2<T> it3 = cmuli<T, -1>(t3);
     a = cadd<T>(t0, t2);
     c = csub<T>(t0, t2);
     b = cadd<T>(t1, it3);
     d = csub<T>(t1, it3);
 }
 
-// one Stockham pass of radix R over nlines transforms of length P: line l,
-// position q at l*lstride + q*pstride.  Positions >= n_in read as 0 (first
-// pass; n_in < 0: the odd extension about -1 of -n_in <= P/2 - 1 stored values,
-// x[q] for q < -n_in, -x[P - 2 - q] where P - 2 - q < -n_in, else 0), only
-// positions < n_out are written (last pass), and with LAM the
-// loads are multiplied by lambda[fold(q) * Q + l] (first inverse pass; the
-// forward output is in natural order).  LINE_FAST: consecutive threads take
+// one forward Stockham pass of radix R over nlines transforms of length P: line
+// l, position q at l*lstride + q*pstride.  LINE_FAST: consecutive threads take
 // consecutive lines (the column passes, whose lines are adjacent in memory).
-template <typename T, int R, bool INV, bool LINE_FAST, bool LAM>
+template <typename T, int R, bool LINE_FAST>
 __global__ __launch_bounds__(256) void k_big_pass(const C2<T> *__restrict__ in, C2<T> *__restrict__ out, int P, int Ns,
-                                                  int nlines, long lstride, long pstride, int n_in, int n_out,
-                                                  const C2<T> *__restrict__ tw, const T *__restrict__ lam, int Q,
-                                                  const double *__restrict__ done) {
-    if (done && *done != 0.0) return;
+                                                  int nlines, long lstride, long pstride, const C2<T> *__restrict__ tw) {
     const int PR = P / R;
     const long total = (long)nlines * PR;
     for (long g = (long)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (long)gridDim.x * blockDim.x) {
@@ -1370,46 +1366,28 @@ __global__ __launch_bounds__(256) void k_big_pass(const C2<T> *__restrict__ in, 
         const C2<T> *src = in + line * lstride;
         C2<T> v[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int q = j + r * PR;
-            if (n_in >= 0) {
-                const bool ok = q < n_in;
-                v[r] = keep<T>(ok, src[(long)(ok ? q : 0) * pstride]);
-            } else {
-                const int qs = q < P / 2 ? q : P - 2 - q;  // -1 at q = P - 1
-                const bool ok = qs >= 0 && qs < -n_in;
-                const C2<T> x = src[(long)(ok ? qs : 0) * pstride];
-                v[r] = keep<T>(ok, q < P / 2 ? x : mk<T>(-x.x, -x.y));
-            }
-            if (LAM) v[r] = cscale<T>(v[r], lam[(long)(q <= P / 2 ? q : P - q) * Q + line]);
-        }
-        // twiddles W^{r m}, W = exp(-+ 2 pi i / (Ns R)): table index r m P / (Ns R) < P
+        for (int r = 0; r < R; ++r) v[r] = src[(long)(j + r * PR) * pstride];
+        // twiddles W^{r m}, W = exp(-2 pi i / (Ns R)): table index r m P / (Ns R) < P
         const int m = j % Ns, step = P / (Ns * R);
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-            const C2<T> t = tw[r * m * step];
-            v[r] = cmul<T>(v[r], INV ? cconj<T>(t) : t);
-        }
+        for (int r = 1; r < R; ++r) v[r] = cmul<T>(v[r], tw[r * m * step]);
         if constexpr (R == 2) {
             const C2<T> a = v[0];
             v[0] = cadd<T>(a, v[1]);
             v[1] = csub<T>(a, v[1]);
         } else if constexpr (R == 4) {
-            big_dft4<T, INV>(v[0], v[1], v[2], v[3]);
+            big_dft4<T>(v[0], v[1], v[2], v[3]);
         } else {
             // 16 = 4 x 4: DFT4 over n1 of x[4 n1 + n2] for each n2, twiddle W16^(n2 k1),
             // DFT4 over n2 for each k1; X[k1 + 4 k2] lands in v[4 n2 + k1] transposed below
 #pragma unroll
-            for (int n2 = 0; n2 < 4; ++n2) big_dft4<T, INV>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+            for (int n2 = 0; n2 < 4; ++n2) big_dft4<T>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
 #pragma unroll
             for (int n2 = 1; n2 < 4; ++n2)
 #pragma unroll
-                for (int k1 = 1; k1 < 4; ++k1) {
-                    const C2<T> t = tw[n2 * k1 * (P / 16)];
-                    v[4 * k1 + n2] = cmul<T>(v[4 * k1 + n2], INV ? cconj<T>(t) : t);
-                }
+                for (int k1 = 1; k1 < 4; ++k1) v[4 * k1 + n2] = cmul<T>(v[4 * k1 + n2], tw[n2 * k1 * (P / 16)]);
 #pragma unroll
-            for (int k1 = 0; k1 < 4; ++k1) big_dft4<T, INV>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+            for (int k1 = 0; k1 < 4; ++k1) big_dft4<T>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
             // v[4 k1 + k2] holds X[k1 + 4 k2]: transpose the 4 x 4 index
             C2<T> w[16];
 #pragma unroll
@@ -1422,10 +1400,7 @@ __global__ __launch_bounds__(256) void k_big_pass(const C2<T> *__restrict__ in, 
         C2<T> *dst = out + line * lstride;
         const int base = (j / Ns) * Ns * R + m;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int q = base + r * Ns;
-            if (q < n_out) dst[(long)q * pstride] = v[r];
-        }
+        for (int r = 0; r < R; ++r) dst[(long)(base + r * Ns) * pstride] = v[r];
     }
 }
 
@@ -1433,8 +1408,7 @@ __global__ __launch_bounds__(256) void k_big_pass(const C2<T> *__restrict__ in, 
 // to row 2r, X_b = (Z(k) - conj Z(-k)) / (2i) to row 2r + 1, k < Q
 template <typename T>
 __global__ __launch_bounds__(256) void k_big_split(const C2<T> *__restrict__ Z, C2<T> *__restrict__ S, int nrows, int P,
-                                                   int Q, int Qs, const double *__restrict__ done) {
-    if (done && *done != 0.0) return;
+                                                   int Q, int Qs) {
     const int nl = (nrows + 1) / 2;
     const long total = (long)nl * Q;
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
@@ -1450,53 +1424,14 @@ __global__ __launch_bounds__(256) void k_big_split(const C2<T> *__restrict__ Z, 
     }
 }
 
-// the inverse of k_big_split: Z(k) = X_a(k) + i X_b(k) on [0, P/2] and
-// Z(P - k) = conj X_a(k) + i conj X_b(k) on (0, P/2)
-template <typename T>
-__global__ __launch_bounds__(256) void k_big_unsplit(const C2<T> *__restrict__ S, C2<T> *__restrict__ Z, int nrows, int P,
-                                                     int Qs, const double *__restrict__ done) {
-    if (done && *done != 0.0) return;
-    const int nl = (nrows + 1) / 2, H = P / 2 + 1;
-    const long total = (long)nl * H;
-    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
-        const long r = idx / H;
-        const int k = (int)(idx - r * H);
-        const C2<T> A = S[2 * r * Qs + k];
-        const C2<T> B = 2 * r + 1 < nrows ? S[(2 * r + 1) * Qs + k] : mk<T>(0, 0);
-        Z[r * P + k] = mk<T>(A.x - B.y, A.y + B.x);
-        if (k > 0 && k < P / 2) Z[r * P + P - k] = mk<T>(A.x + B.y, B.x - A.y);
-    }
-}
-
-template <typename T, bool EPI>
-__global__ __launch_bounds__(256) void k_big_unpack(const C2<T> *__restrict__ Z, T *__restrict__ y, int nx, int ny,
-                                                    int P, Epi<T> ep, const double *__restrict__ done) {
-    if (done && *done != 0.0) return;
-    const long total = (long)nx * ny;
-    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
-        const long row = idx / nx;
-        const int p = (int)(idx - row * nx);
-        const C2<T> z = Z[(row >> 1) * P + p];
-        T v = (row & 1) ? z.y : z.x;
-        if constexpr (EPI) {
-            v = ep.scale * v;
-            if (ep.w1) v += ep.a1 * ep.w1[idx];
-            if (ep.w2) v += ep.a2 * ep.w2[idx];
-        }
-        y[idx] = v;
-    }
-}
-
 // lambda / P^2 in natural order (ky, kx < Q) from the forward spectrum of the generator
-__global__ __launch_bounds__(256) void k_big_extract(const double2 *__restrict__ F, double *__restrict__ lam64,
-                                                     float *__restrict__ lam32, int P, int Q, int Qs) {
+__global__ __launch_bounds__(256) void k_big_extract(const double2 *__restrict__ F, double *__restrict__ lam64, int P,
+                                                     int Q, int Qs) {
     const long total = (long)Q * Q;
     const double inv = 1.0 / ((double)P * (double)P);
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
         const long ky = idx / Q, kx = idx - ky * Q;
-        const double v = F[ky * Qs + kx].x * inv;
-        lam64[idx] = v;
-        lam32[idx] = (float)v;
+        lam64[idx] = F[ky * Qs + kx].x * inv;
     }
 }
 
@@ -1505,34 +1440,24 @@ static int big_grid(long total) {
     return (int)(g > (1L << 20) ? (1L << 20) : (g < 1 ? 1 : g));
 }
 
-// the passes of one set of transforms (radix 16 while it divides, then 4 or 2),
-// ping-ponging between a and b; returns the buffer that holds the result
-template <typename T, bool INV, bool LINE_FAST>
-static C2<T> *big_fft(C2<T> *a, C2<T> *b, int P, int nlines, long lstride, long pstride, int n_in, int n_out,
-                      const C2<T> *tw, const T *lam, int Q, const double *done, hipStream_t s) {
-    int Ns = 1;
-    bool first = true;
-    while (Ns < P) {
+// the forward passes of one set of transforms (radix 16 while it divides, then
+// 4 or 2), ping-ponging between a and b; returns the buffer that holds the result
+template <typename T, bool LINE_FAST>
+static C2<T> *big_fft(C2<T> *a, C2<T> *b, int P, int nlines, long lstride, long pstride, const C2<T> *tw,
+                      hipStream_t s) {
+    for (int Ns = 1; Ns < P;) {
         const int R = (P / Ns) % 16 == 0 ? 16 : ((P / Ns) % 4 == 0 ? 4 : 2);
-        const bool last = Ns * R == P;
-        const int ni = first ? n_in : P, no = last ? n_out : P;
         const int g = big_grid((long)nlines * (P / R));
-        const bool withlam = first && lam != nullptr;
-#define FL_BIGPASS(RR)                                                                                               \
-    do {                                                                                                             \
-        if (withlam)                                                                                                 \
-            hipLaunchKernelGGL((k_big_pass<T, RR, INV, LINE_FAST, true>), dim3(g), dim3(256), 0, s, a, b, P, Ns,     \
-                               nlines, lstride, pstride, ni, no, tw, lam, Q, done);                                  \
-        else                                                                                                         \
-            hipLaunchKernelGGL((k_big_pass<T, RR, INV, LINE_FAST, false>), dim3(g), dim3(256), 0, s, a, b, P, Ns,    \
-                               nlines, lstride, pstride, ni, no, tw, lam, Q, done);                                  \
-    } while (0)
-        if (R == 16) FL_BIGPASS(16);
-        else if (R == 4) FL_BIGPASS(4);
-        else FL_BIGPASS(2);
-#undef FL_BIGPASS
+        if (R == 16)
+            hipLaunchKernelGGL((k_big_pass<T, 16, LINE_FAST>), dim3(g), dim3(256), 0, s, a, b, P, Ns, nlines, lstride,
+                               pstride, tw);
+        else if (R == 4)
+            hipLaunchKernelGGL((k_big_pass<T, 4, LINE_FAST>), dim3(g), dim3(256), 0, s, a, b, P, Ns, nlines, lstride,
+                               pstride, tw);
+        else
+            hipLaunchKernelGGL((k_big_pass<T, 2, LINE_FAST>), dim3(g), dim3(256), 0, s, a, b, P, Ns, nlines, lstride,
+                               pstride, tw);
         Ns *= R;
-        first = false;
         C2<T> *t = a;
         a = b;
         b = t;
@@ -1542,38 +1467,26 @@ static C2<T> *big_fft(C2<T> *a, C2<T> *b, int P, int nlines, long lstride, long 
 
 template <typename T> static const T *big_lam(fl_op op);
 template <> const float *big_lam<float>(fl_op op) { return op->lam32t; }
-template <> const double *big_lam<double>(fl_op op) { return op->lam64; }
+template <> const double *big_lam<double>(fl_op op) { return op->lam64t; }
+template <typename T> static const C2<T> *fs_subtw(fl_op op);
+template <> const float2 *fs_subtw<float>(fl_op op) { return op->sch32; }
+template <> const double2 *fs_subtw<double>(fl_op op) { return op->sch64; }
 
-// sym (optional) replaces lambda (natural order, Q x Q); odd: the forward passes
-// read the odd extensions (the sine-transform preconditioner)
+// sym (optional) replaces lambda (Q x Q in the four-step column order); odd:
+// the forward passes read the odd extensions (the sine-transform preconditioner)
 template <typename T>
 fl_status large_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
                        const T *sym, bool odd) {
-    const int P = op->P, Q = op->Q, Qs = op->Qp, nx = op->nk[0], ny = op->nk[1];
-    const int ix = odd ? -nx : nx, iy = odd ? -ny : ny;
-    const int nl = (ny + 1) / 2;
-    C2<T> *B0 = (C2<T> *)op->T1, *B1 = (C2<T> *)op->T2;
-    const C2<T> *tw = twid<T>(op);
-    hipLaunchKernelGGL(k_big_pack<T>, dim3(big_grid((long)nl * nx)), dim3(256), 0, s, u, B0, nx, ny, P, done);
-    // x forward over the nl lines (rows of length P, positions contiguous)
-    C2<T> *X = big_fft<T, false, false>(B0, B1, P, nl, P, 1, ix, P, tw, nullptr, Q, done, s);
-    C2<T> *S = X == B0 ? B1 : B0;
-    hipLaunchKernelGGL(k_big_split<T>, dim3(big_grid((long)nl * Q)), dim3(256), 0, s, X, S, ny, P, Q, Qs, done);
-    // y forward over the Q columns (ny rows in, P out), then y inverse with lambda (ny rows out)
-    C2<T> *F = big_fft<T, false, true>(S, X, P, Q, 1, Qs, iy, P, tw, nullptr, Q, done, s);
-    C2<T> *G = F == B0 ? B1 : B0;
-    C2<T> *I = big_fft<T, true, true>(F, G, P, Q, 1, Qs, P, ny, tw, sym ? sym : big_lam<T>(op), Q, done, s);
-    C2<T> *Z = I == B0 ? B1 : B0;
-    hipLaunchKernelGGL(k_big_unsplit<T>, dim3(big_grid((long)nl * (P / 2 + 1))), dim3(256), 0, s, I, Z, ny, P, Qs,
-                       done);
-    C2<T> *W = I;
-    C2<T> *Rr = big_fft<T, true, false>(Z, W, P, nl, P, 1, P, nx, tw, nullptr, Q, done, s);
-    if (ep.active())
-        hipLaunchKernelGGL((k_big_unpack<T, true>), dim3(big_grid((long)nx * ny)), dim3(256), 0, s, Rr, y, nx, ny, P, ep,
-                           done);
-    else
-        hipLaunchKernelGGL((k_big_unpack<T, false>), dim3(big_grid((long)nx * ny)), dim3(256), 0, s, Rr, y, nx, ny, P,
-                           ep, done);
+    const T *lam = sym ? sym : big_lam<T>(op);
+    const C2<T> *tw = twid<T>(op), *sub = fs_subtw<T>(op);
+    switch (op->P) {
+        case 4096: fs_matvec<T, 64, 64>(op, u, y, ep, done, s, lam, odd, tw, sub); break;
+        case 8192: fs_matvec<T, 64, 128>(op, u, y, ep, done, s, lam, odd, tw, sub); break;
+        case 16384: fs_matvec<T, 128, 128>(op, u, y, ep, done, s, lam, odd, tw, sub); break;
+        default:
+            set_error("no four-step plan for FFT length %d", op->P);
+            return FL_E_UNSUPPORTED;
+    }
     FL_HIP_TRY(hipGetLastError());
     return FL_OK;
 }
@@ -1592,14 +1505,19 @@ fl_status large_symbol(fl_op op, hipStream_t s) {
     FL_HIP_TRY(hipMalloc((void **)&cemb, sizeof(double) * total));
     double2 *B0 = (double2 *)op->T1, *B1 = (double2 *)op->T2;
     hipLaunchKernelGGL(k_embed, dim3(big_grid(total)), dim3(256), 0, s, op->a, cemb, 2, op->N, P, -op->c);
-    hipLaunchKernelGGL(k_big_pack<double>, dim3(big_grid(total / 2)), dim3(256), 0, s, cemb, B0, P, P, P,
-                       (const double *)nullptr);
-    double2 *X = big_fft<double, false, false>(B0, B1, P, P / 2, P, 1, P, P, op->tw64, nullptr, Q, nullptr, s);
+    hipLaunchKernelGGL(k_big_pack<double>, dim3(big_grid(total / 2)), dim3(256), 0, s, cemb, B0, P, P, P);
+    double2 *X = big_fft<double, false>(B0, B1, P, P / 2, P, 1, op->tw64, s);
     double2 *S = X == B0 ? B1 : B0;
-    hipLaunchKernelGGL(k_big_split<double>, dim3(big_grid((long)(P / 2) * Q)), dim3(256), 0, s, X, S, P, P, Q, Qs,
-                       (const double *)nullptr);
-    double2 *F = big_fft<double, false, true>(S, X, P, Q, 1, Qs, P, P, op->tw64, nullptr, Q, nullptr, s);
-    hipLaunchKernelGGL(k_big_extract, dim3(big_grid((long)Q * Q)), dim3(256), 0, s, F, op->lam64, op->lam32t, P, Q, Qs);
+    hipLaunchKernelGGL(k_big_split<double>, dim3(big_grid((long)(P / 2) * Q)), dim3(256), 0, s, X, S, P, P, Q, Qs);
+    double2 *F = big_fft<double, true>(S, X, P, Q, 1, Qs, op->tw64, s);
+    hipLaunchKernelGGL(k_big_extract, dim3(big_grid((long)Q * Q)), dim3(256), 0, s, F, op->lam64, P, Q, Qs);
+    // FP64 and FP32 copies in the column order of the four-step passes
+    int P1 = 0, P2 = 0;
+    fs_split(P, P1, P2);
+    hipLaunchKernelGGL(k_fs_permute<double>, dim3(big_grid((long)Q * Q)), dim3(256), 0, s, op->lam64, op->lam64t, Q,
+                       P1, P2, SymMap{});
+    hipLaunchKernelGGL(k_fs_permute<float>, dim3(big_grid((long)Q * Q)), dim3(256), 0, s, op->lam64, op->lam32t, Q,
+                       P1, P2, SymMap{});
     hipError_t le = hipGetLastError();
     hipError_t se = hipStreamSynchronize(s);
     (void)hipFree(cemb);
