@@ -105,7 +105,7 @@ static fl_status create(int d, double alpha, double gamma, double h, int N, cons
     op->P = next_pow2(2L * op->n - 1);
     if (op->P < 8) op->P = 8;
     op->Q = op->P / 2 + 1;
-    op->Qp = ((op->Q + 15) / 16) * 16;
+    op->Qp = ((op->Q + 31) / 32) * 32;  // a whole number of the four-step passes' 32-column groups
     for (int k = 0; k < 3; ++k) op->nk[k] = k >= d ? 1 : (Nk ? Nk[k] - 1 : op->n);
     op->M = (int64_t)op->nk[0] * op->nk[1] * op->nk[2];
     (void)hipGetDevice(&op->device);

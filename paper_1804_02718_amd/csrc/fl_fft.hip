@@ -1479,14 +1479,14 @@ fl_status large_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, const doubl
                        const T *sym, bool odd) {
     const T *lam = sym ? sym : big_lam<T>(op);
     const C2<T> *tw = twid<T>(op), *sub = fs_subtw<T>(op);
+    fl_status st = FL_E_UNSUPPORTED;
     switch (op->P) {
-        case 4096: fs_matvec<T, 64, 64>(op, u, y, ep, done, s, lam, odd, tw, sub); break;
-        case 8192: fs_matvec<T, 64, 128>(op, u, y, ep, done, s, lam, odd, tw, sub); break;
-        case 16384: fs_matvec<T, 128, 128>(op, u, y, ep, done, s, lam, odd, tw, sub); break;
-        default:
-            set_error("no four-step plan for FFT length %d", op->P);
-            return FL_E_UNSUPPORTED;
+        case 4096: st = fs_matvec<T, 64, 64>(op, u, y, ep, done, s, lam, odd, tw, sub); break;
+        case 8192: st = fs_matvec<T, 64, 128>(op, u, y, ep, done, s, lam, odd, tw, sub); break;
+        case 16384: st = fs_matvec<T, 128, 128>(op, u, y, ep, done, s, lam, odd, tw, sub); break;
+        default: set_error("no four-step plan for FFT length %d", op->P);
     }
+    if (st != FL_OK) return st;
     FL_HIP_TRY(hipGetLastError());
     return FL_OK;
 }

@@ -25,10 +25,10 @@
 // run of consecutive addresses; lambda is stored in the same column order.
 
 template <int L> struct FsPlan;
-template <> struct FsPlan<128> { using PN = Plan<128, 16>; };
+template <> struct FsPlan<128> { using PN = Plan<128, 8>; };
 template <> struct FsPlan<64> { using PN = Plan<64, 8>; };
 // short transforms per workgroup (lines); P1 and P2 are multiples of it
-constexpr int kFsLines = 16;
+constexpr int kFsLines = 32;
 template <int L> constexpr int fs_threads() { return kFsLines * (L / FsPlan<L>::PN::E); }
 // the short transforms' twiddle tables exp(-2 pi i m / L) in one buffer
 constexpr int fs_tw_off(int L) { return L == 128 ? 0 : 128; }
@@ -150,8 +150,11 @@ __global__ __launch_bounds__(fs_threads<P2>()) void k_fs_xb(
         const C2<T> zk = lds[lidx(k2)];
         const C2<T> zq = lds[cm * PLL + padpos(m2)];  // Z(-k) = zq; conj Z(-k) = (zq.x, -zq.y)
         const int col = fs_col(P1, P2, k1, k2);
-        st_stream(sa + col, mk<T>(T(0.5) * (zk.x + zq.x), T(0.5) * (zk.y - zq.y)));
-        if (hb) st_stream(sb + col, mk<T>(T(0.5) * (zk.y + zq.y), T(-0.5) * (zk.x - zq.x)));
+        // plain stores: a line's threads write TL consecutive columns per
+        // step, and the L2 merges the steps' runs before they reach HBM (measured
+        // 1.5x faster here than streaming stores)
+        sa[col] = mk<T>(T(0.5) * (zk.x + zq.x), T(0.5) * (zk.y - zq.y));
+        if (hb) sb[col] = mk<T>(T(0.5) * (zk.y + zq.y), T(-0.5) * (zk.x - zq.x));
     }
 }
 
@@ -167,7 +170,7 @@ __global__ __launch_bounds__(fs_threads<P1>()) void k_fs_ya(
     constexpr int E = PN::E, L = PN::L, NL = kFsLines, R0 = PN::R[0], P = P1 * P2;
     __shared__ C2<T> lds[NL * padded_len<P1>()];
     const int c = threadIdx.x % NL, tl = threadIdx.x / NL;
-    const int col = blockIdx.x * NL + c;  // < Qs, a multiple of kFsLines
+    const int col = blockIdx.x * NL + c;  // < Qs (the row stride), a multiple of kFsLines
     const int n2 = blockIdx.y;
     C2<T> v[E];
 #pragma unroll
@@ -378,9 +381,14 @@ inline void fs_split(int P, int &P1, int &P2) {
 }
 
 template <typename T, int P1, int P2>
-static void fs_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
+static fl_status fs_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
                       const T *lam, bool odd, const C2<T> *tw, const C2<T> *subtw) {
     const int Q = op->Q, Qs = op->Qp, nx = op->nk[0], ny = op->nk[1], P = P1 * P2;
+    static_assert(P1 % kFsLines == 0 && P2 % kFsLines == 0, "whole workgroups of lines");
+    if (Qs % kFsLines != 0 || Qs < Q) {  // the row stride covers whole column groups (set at creation)
+        set_error("row stride %d of the large-operator spectra is not a multiple of %d", Qs, kFsLines);
+        return FL_E_UNSUPPORTED;
+    }
     const int nl = (ny + 1) / 2;
     C2<T> *Tb = (C2<T> *)op->T1;
     C2<T> *Lb = (C2<T> *)op->T2;
@@ -408,4 +416,5 @@ static void fs_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, const double
     else
         hipLaunchKernelGGL((k_fs_xai<T, P1, P2, false>), dim3(P2 / kFsLines, nl), b1, 0, s, Lb, y, nx, ny, subtw,
                            ep, done);
+    return FL_OK;
 }
