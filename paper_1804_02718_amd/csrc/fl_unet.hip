@@ -394,27 +394,6 @@ __global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__re
     }
 }
 
-// network input from a residual: channel 0 = r / rms(r) at the interior n x n
-// (zero in the padding), channel 1 = alpha; rms(r) = ||r|| / n from `nrm` = ||r||^2
-__global__ void k_net_input(const double *__restrict__ r, int n, int H, int W, float alpha, const double *nrm,
-                            float *__restrict__ X) {
-    const double s = (nrm && nrm[0] > 0.0) ? (double)n / sqrt(nrm[0]) : 1.0;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)H * W; i += (long)gridDim.x * blockDim.x) {
-        const int x = (int)(i % W), y = (int)(i / W);
-        X[2 * i] = (x < n && y < n) ? (float)(s * r[(long)y * n + x]) : 0.f;
-        X[2 * i + 1] = alpha;
-    }
-}
-// z = rms(r) * y (channel 0, pitch ys) at the interior
-__global__ void k_net_output(const float *__restrict__ Y, int ys, int n, int W, const double *nrm,
-                             double *__restrict__ z) {
-    const double s = (nrm && nrm[0] > 0.0) ? sqrt(nrm[0]) / (double)n : 1.0;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)n * n; i += (long)gridDim.x * blockDim.x) {
-        const int x = (int)(i % n), y = (int)(i / n);
-        z[i] = s * (double)Y[((long)y * W + x) * ys];
-    }
-}
-
 // training sample from a (residual, solution) pair: x = (r / rms(r), alpha) and
 // t = sol / rms(r) on the top-left n x n of the H x W grid, zero elsewhere
 __global__ void k_pack_sample(const double *__restrict__ r, const double *__restrict__ sol, int n, int H, int W,
@@ -643,6 +622,263 @@ __global__ __launch_bounds__(256) void k_conv_fused(ConvSrc src, int H, int W, c
             if (relu) v = v > 0.f ? v : 0.f;
             Y[(((long)b * H + y) * W + x) * COUTP + n0 + 16 * j + r] = v;
         }
+}
+
+// ---------------------------------------------------------------------------
+// Two 3x3 convolutions of one U-Net level in one launch (inference).  A
+// workgroup owns a TS x TS output tile.  It stages the (TS+4)^2 input halo in
+// LDS (formed on the fly as in k_conv_fused, or from the residual: channel 0
+// = r / rms(r) on the interior n x n, channel 1 = alpha), computes the first
+// convolution + ReLU on the (TS+2)^2 ring the second one reads into LDS (zero
+// outside the image: the second convolution's padding), then the second
+// convolution + ReLU on the tile.  LAST also applies the final 1x1 convolution
+// and writes z = rms(r) * Net at the interior.  Operands: gfx950's
+// v_mfma_f32_16x16x32_bf16 (fp32 mode: eight v_mfma_f32_16x16x4_f32 per k
+// step), lane (r, q) supplying row r and k = 8q .. 8q+7 of each 32-wide step,
+// with k = tap * cin + ci as in k_conv_fused.
+// ---------------------------------------------------------------------------
+enum { SRC_RESID = 3 };
+struct PairSrc {
+    ConvSrc c;
+    const double *r = nullptr;    // SRC_RESID: the residual (n x n, row-major) ...
+    const double *nrm = nullptr;  // ... and its squared norm (device)
+    int n = 0;
+    float alpha = 0.f;
+    double *z = nullptr;          // LAST: the preconditioned residual (n x n)
+};
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef float v8f __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// acc[j] (output channels 16j + r of M-tile mt, pixels 16 mt + 4q + i) of the
+// 3x3 convolution of the LDS tile `in` (IW x IW pixels of CIN channels, pixel
+// pitch CP) over an
+// OW x OW output region whose pixel (oy, ox) reads in at (oy + ty, ox + tx);
+// weights W [cout][ldw] (global or LDS), k past Kw reads as zero
+template <typename T, int CIN, int CP, int COUT, int IW, int OW>
+__device__ __forceinline__ void conv3_tile(const T *in, const T *W, int ldw, int Kw, int mt, int lane, v4f *acc) {
+    constexpr int K = 9 * CIN, K32 = (K + 31) / 32 * 32, NTN = COUT / 16;
+    using V = typename std::conditional<sizeof(T) == 2, v8s, v8f>::type;
+    const int r = lane & 15, q = lane >> 4;
+    const int m0 = 16 * mt + r;
+    const int m = m0 < OW * OW ? m0 : OW * OW - 1;  // rows past the region: any pixel, results unused
+    const int pbase = ((m / OW) * IW + (m % OW)) * CP;
+#pragma unroll
+    for (int j = 0; j < NTN; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 3
+    for (int k0 = 0; k0 < K32; k0 += 32) {
+        const int k = k0 + 8 * q;
+        V a;
+        if constexpr (CIN % 8 == 0) {
+            // k .. k+7 lie in one tap; past K (zero weights) any tap in range is read
+            const int kk = k < K ? k : 0;
+            const int tap = kk / CIN;
+            a = *(const V *)(in + pbase + ((tap / 3) * IW + tap % 3) * CP + (kk - tap * CIN));
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int kk = k + i < K ? k + i : 0;
+                const int tap = kk / CIN;
+                const T t = in[pbase + ((tap / 3) * IW + tap % 3) * CP + (kk - tap * CIN)];
+                if constexpr (sizeof(T) == 2) a[i] = (short)t;
+                else a[i] = t;
+            }
+        }
+        const bool wk = k < Kw;  // 8-aligned and Kw a multiple of 16: all 8 or none
+        V b[NTN];
+#pragma unroll
+        for (int j = 0; j < NTN; ++j) {
+            const V w = *(const V *)(W + (16 * j + r) * ldw + (wk ? k : 0));
+            b[j] = wk ? w : V{};
+        }
+#pragma unroll
+        for (int j = 0; j < NTN; ++j) {
+            if constexpr (sizeof(T) == 2) {
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
+                                                                 __builtin_bit_cast(v8bf, b[j]), acc[j], 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b[j][e], acc[j], 0, 0, 0);
+            }
+        }
+    }
+}
+
+// LDS row stride of a staged weight matrix with rows of Kw operands: a multiple
+// of 8 operands whose byte length is 16 mod 128, so the 16 rows one k step reads
+// (16 bytes each) spread over the LDS banks
+template <typename T> constexpr int wstride(int Kw) {
+    const int b = Kw * (int)sizeof(T);
+    return (Kw * (int)sizeof(T) + ((16 - b % 128) + 128) % 128) / (int)sizeof(T);
+}
+
+// threads of a k_conv_pair workgroup (8 waves)
+constexpr int kPairThreads = 512;
+
+// copy a [ROWS][K] bf16 matrix from global memory into LDS rows of stride S,
+// in 16-byte chunks, a thread's loads all issued before its stores
+template <int ROWS, int K, int S>
+__device__ __forceinline__ void stage_rows(const bf16 *__restrict__ src, bf16 *dst) {
+    constexpr int NC = ROWS * (K / 8), NIT = (NC + kPairThreads - 1) / kPairThreads;
+    v8s c[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int e = threadIdx.x + kPairThreads * it, ec = e < NC ? e : 0;
+        c[it] = *(const v8s *)(src + (long)(ec / (K / 8)) * K + 8 * (ec % (K / 8)));
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int e = threadIdx.x + kPairThreads * it;
+        if (e < NC) *(v8s *)(dst + (e / (K / 8)) * S + 8 * (e % (K / 8))) = c[it];
+    }
+}
+
+template <typename T, int MODE, int CIN, int CMID, int COUT, int TS, bool LAST>
+__global__ __launch_bounds__(kPairThreads) void k_conv_pair(PairSrc ps, int H, const T *__restrict__ WA,
+                                                   const T *__restrict__ WB, const T *__restrict__ WL,
+                                                   float *__restrict__ Y) {
+    constexpr int IW = TS + 4, MW = TS + 2, CV = CIN % 4 == 0 ? 4 : 1;
+    // pixel pitches in LDS: 16 bytes past the channels, so the 16 pixels of a
+    // k step's A operand (16 bytes each) fall on distinct banks
+    constexpr int CPI = CIN % 8 == 0 ? CIN + 8 : CIN, CPM = CMID + 8;
+    static_assert(!LAST || COUT == 16, "the final 1x1 convolution reads 16 channels");
+    // bf16 operands: both weight matrices staged in LDS once (fp32 mode reads them from global)
+    constexpr bool WL_LDS = sizeof(T) == 2;
+    constexpr int KA = (9 * CIN + 15) / 16 * 16, KB = (9 * CMID + 15) / 16 * 16;
+    constexpr int SA = wstride<T>(KA), SB = wstride<T>(KB);
+    __shared__ __attribute__((aligned(32))) T tin[IW * IW * CPI > TS * TS * 16 ? IW * IW * CPI : TS * TS * 16];
+    __shared__ __attribute__((aligned(32))) T tmid[MW * MW * CPM];
+    __shared__ __attribute__((aligned(32))) T wla[WL_LDS ? CMID * SA : 1];
+    __shared__ __attribute__((aligned(32))) T wlb[WL_LDS ? COUT * SB : 1];
+    if constexpr (WL_LDS) {
+        // 16-byte chunks, every load of a thread issued before its first LDS store;
+        // KA, KB are multiples of 16 operands (the host's padding)
+        stage_rows<CMID, KA, SA>(WA, wla);
+        stage_rows<COUT, KB, SB>(WB, wlb);
+    }
+    const T *wa = WL_LDS ? (const T *)wla : WA;
+    const T *wb = WL_LDS ? (const T *)wlb : WB;
+    const int lda = WL_LDS ? SA : KA, ldb = WL_LDS ? SB : KB;
+    const int W = H;
+    const int b = blockIdx.z;
+    const int tx0 = blockIdx.x * TS, ty0 = blockIdx.y * TS;
+    const ConvSrc &src = ps.c;
+    double s_in = 1.0;
+    if constexpr (MODE == SRC_RESID) s_in = (ps.nrm && ps.nrm[0] > 0.0) ? (double)ps.n / sqrt(ps.nrm[0]) : 1.0;
+    // stage the input halo, CV channels per task: all of a thread's loads (from
+    // clamped, always valid addresses) before its LDS stores
+    constexpr int NE = IW * IW * (CIN / CV), NIT = (NE + kPairThreads - 1) / kPairThreads;
+    float v[NIT][CV];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int e = threadIdx.x + kPairThreads * it;
+        const int cg = e % (CIN / CV), pix = (e < NE ? e : 0) / (CIN / CV);
+        const int y = ty0 + pix / IW - 2, x = tx0 + pix % IW - 2;
+        const bool ok = e < NE && y >= 0 && y < H && x >= 0 && x < W;
+        const int yc = ok ? y : 0, xc = ok ? x : 0;
+        const int ci = cg * CV;
+        if constexpr (MODE == SRC_RESID) {
+            // CIN = 2, CV = 1: r / rms(r) on the interior n x n, alpha elsewhere in the image
+            const bool inr = ok && ci == 0 && yc < ps.n && xc < ps.n;
+            const double rv = ps.r[inr ? (long)yc * ps.n + xc : 0];
+            v[it][0] = !ok ? 0.f : (ci == 0 ? (inr ? (float)(s_in * rv) : 0.f) : ps.alpha);
+        } else if constexpr (MODE == SRC_PLAIN) {
+            const float *q = src.a + (((long)b * H + yc) * W + xc) * src.csa + ci;
+#pragma unroll
+            for (int i = 0; i < CV; ++i) v[it][i] = ok ? q[i] : 0.f;
+        } else if constexpr (MODE == SRC_POOL) {
+            const int W2 = 2 * W;
+            const float *q = src.a + (((long)b * 2 * H + 2 * yc) * W2 + 2 * xc) * src.csa + ci;
+            const long dy = (long)W2 * src.csa;
+#pragma unroll
+            for (int i = 0; i < CV; ++i) {
+                const float t = 0.25f * (q[i] + q[src.csa + i] + q[dy + i] + q[dy + src.csa + i]);
+                v[it][i] = ok ? t : 0.f;
+            }
+        } else {
+            const float *q = ci < src.ca
+                                 ? src.a + (((long)b * (H / 2) + yc / 2) * (W / 2) + xc / 2) * src.csa + ci
+                                 : src.b + (((long)b * H + yc) * W + xc) * src.csb + (ci - src.ca);
+#pragma unroll
+            for (int i = 0; i < CV; ++i) v[it][i] = ok ? q[i] : 0.f;
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int e = threadIdx.x + kPairThreads * it;
+        if (e < NE) {
+            const int cg = e % (CIN / CV), pix = e / (CIN / CV);
+            if constexpr (CV == 4) {  // one 4-operand store (8 or 16 bytes, aligned)
+                typedef T T4 __attribute__((ext_vector_type(4)));
+                T4 w;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) w[i] = to_op<T>(v[it][i]);
+                *(T4 *)(tin + pix * CPI + cg * 4) = w;
+            } else {
+                tin[pix * CPI + cg] = to_op<T>(v[it][0]);
+            }
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    // first convolution on the MW x MW ring, ReLU, zero outside the image
+    {
+        constexpr int NMT = (MW * MW + 15) / 16, NTN = CMID / 16;
+        for (int mt = wave; mt < NMT; mt += kPairThreads / 64) {
+            v4f acc[NTN];
+            conv3_tile<T, CIN, CPI, CMID, IW, MW>(tin, wa, lda, KA, mt, lane, acc);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = 16 * mt + 4 * q + i;
+                if (m >= MW * MW) continue;
+                const int gy = ty0 - 1 + m / MW, gx = tx0 - 1 + m % MW;
+                const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+#pragma unroll
+                for (int j = 0; j < NTN; ++j) {
+                    const float v = acc[j][i];
+                    tmid[m * CPM + 16 * j + r] = to_op<T>(in && v > 0.f ? v : 0.f);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // second convolution on the tile, ReLU
+    {
+        constexpr int NMT = TS * TS / 16, NTN = COUT / 16;
+        for (int mt = wave; mt < NMT; mt += kPairThreads / 64) {
+            v4f acc[NTN];
+            conv3_tile<T, CMID, CPM, COUT, MW, TS>(tmid, wb, ldb, KB, mt, lane, acc);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = 16 * mt + 4 * q + i;
+                const int oy = m / TS, ox = m % TS;
+#pragma unroll
+                for (int j = 0; j < NTN; ++j) {
+                    const float v = acc[j][i] > 0.f ? acc[j][i] : 0.f;
+                    if constexpr (LAST) {
+                        tin[m * 16 + r] = to_op<T>(v);  // the input tile is no longer read
+                    } else {
+                        const int y = ty0 + oy, x = tx0 + ox;
+                        if (y < H && x < W) Y[(((long)b * H + y) * W + x) * COUT + 16 * j + r] = v;
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (LAST) {
+        __syncthreads();
+        // final 1x1 convolution (one output channel) and z = rms(r) * y at the interior
+        const double s_out = (ps.nrm && ps.nrm[0] > 0.0) ? sqrt(ps.nrm[0]) / (double)ps.n : 1.0;
+        for (int m = threadIdx.x; m < TS * TS; m += kPairThreads) {
+            const int y = ty0 + m / TS, x = tx0 + m % TS;
+            if (y >= ps.n || x >= ps.n) continue;
+            float t = 0.f;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) t += op_to_f<T>(WL[c]) * op_to_f<T>(tin[m * 16 + c]);
+            ps.z[(long)b * ps.n * ps.n + (long)y * ps.n + x] = s_out * (double)t;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -889,6 +1125,45 @@ static void net_forward_fused_t(fl_unet u, int nb) {
 static void net_forward_fused(fl_unet u, int nb) {
     if (u->fp32) net_forward_fused_t<float>(u, nb);
     else net_forward_fused_t<bf16>(u, nb);
+}
+
+// the preconditioner action z = rms(r) * Net(r / rms(r), alpha) for one
+// sample in five launches, two convolutions each (the last also the 1x1 head):
+// level 0 down, 1 down, 2, 1 up, 0 up; only S1, S2, B3 and B4 go through HBM.
+// The kernels take each weight row length (k padded to 16) from the layer shape,
+// as fl_unet_create lays the operand copies out.
+template <typename T>
+static void net_apply_pairs_t(fl_unet u, const PairSrc &io, hipStream_t s) {
+    const int H = u->H;
+    auto *A = u->A.data();
+    auto Wt = [&](int li) { return (const T *)wb_of<T>(u, li); };
+    auto grid = [](int h, int ts) { return dim3((h + ts - 1) / ts, (h + ts - 1) / ts, 1); };
+    PairSrc p = io;
+    hipLaunchKernelGGL((k_conv_pair<T, SRC_RESID, 2, 16, 16, 16, false>), grid(H, 16), dim3(kPairThreads), 0, s, p, H, Wt(0),
+                       Wt(1), (const T *)nullptr, A[T_S1]);
+    p.c = ConvSrc{};
+    p.c.a = A[T_S1];
+    p.c.csa = 16;
+    hipLaunchKernelGGL((k_conv_pair<T, SRC_POOL, 16, 32, 32, 8, false>), grid(H / 2, 8), dim3(kPairThreads), 0, s, p, H / 2,
+                       Wt(2), Wt(3), (const T *)nullptr, A[T_S2]);
+    p.c.a = A[T_S2];
+    p.c.csa = 32;
+    hipLaunchKernelGGL((k_conv_pair<T, SRC_POOL, 32, 64, 64, 8, false>), grid(H / 4, 8), dim3(kPairThreads), 0, s, p, H / 4,
+                       Wt(4), Wt(5), (const T *)nullptr, A[T_B3]);
+    p.c.a = A[T_B3];
+    p.c.csa = 64;
+    p.c.ca = 64;
+    p.c.b = A[T_S2];
+    p.c.csb = 32;
+    hipLaunchKernelGGL((k_conv_pair<T, SRC_CATUP, 96, 32, 32, 8, false>), grid(H / 2, 8), dim3(kPairThreads), 0, s, p, H / 2,
+                       Wt(6), Wt(7), (const T *)nullptr, A[T_B4]);
+    p.c.a = A[T_B4];
+    p.c.csa = 32;
+    p.c.ca = 32;
+    p.c.b = A[T_S1];
+    p.c.csb = 16;
+    hipLaunchKernelGGL((k_conv_pair<T, SRC_CATUP, 48, 16, 16, 16, true>), grid(H, 16), dim3(kPairThreads), 0, s, p, H, Wt(8),
+                       Wt(9), Wt(10), (float *)nullptr);
 }
 
 static void net_forward(fl_unet u, int nb) {
@@ -1223,20 +1498,19 @@ fl_status fl_unet_train(fl_unet u, long count, const float *x, const float *t, c
 
 namespace fl {
 int unet_size(fl_unet u) { return u->H; }
-// z = rms(r) * Net(r / rms(r), alpha) on the stream s (r, z: n x n, n <= H); the
-// squared norm of r is computed into u->nrm first.  Used inside flexible PCG.
+// z = rms(r) * Net(r / rms(r), alpha) on the stream s (r, z: n x n, n <= H), with
+// rr_dev the squared norm of r on the device.  Used inside flexible PCG.
 fl_status unet_apply(fl_unet u, const double *r, int n, double alpha, double *z, const double *rr_dev,
                      hipStream_t s) {
-    const int H = u->H;
-    hipEvent_t e = u->ev;
-    FL_HIP_TRY(hipEventRecord(e, s));
-    FL_HIP_TRY(hipStreamWaitEvent(u->s, e, 0));
-    hipLaunchKernelGGL(k_net_input, dim3(grid1((long)H * H)), dim3(256), 0, u->s, r, n, H, H, (float)alpha, rr_dev,
-                       u->A[T_X0]);
-    net_forward_fused(u, 1);
-    hipLaunchKernelGGL(k_net_output, dim3(grid1((long)n * n)), dim3(256), 0, u->s, u->A[T_Y], 16, n, H, rr_dev, z);
-    FL_HIP_TRY(hipEventRecord(e, u->s));
-    FL_HIP_TRY(hipStreamWaitEvent(s, e, 0));
+    PairSrc io;
+    io.r = r;
+    io.nrm = rr_dev;
+    io.n = n;
+    io.alpha = (float)alpha;
+    io.z = z;
+    // on the caller's stream: the action is ordered with the solver's own work
+    if (u->fp32) net_apply_pairs_t<float>(u, io, s);
+    else net_apply_pairs_t<bf16>(u, io, s);
     FL_HIP_TRY(hipGetLastError());
     return FL_OK;
 }
