@@ -424,6 +424,11 @@ fl_status fl_batch_destroy(fl_batch b);
  *                          each [cout][(ky*ks + kx)*cin + ci] (host).
  *   fl_unet_apply       -- z = rms(r) Net(r/rms(r), alpha) for a residual r on
  *                          the n x n interior (device doubles, n <= H).
+ *                          Asynchronous on `stream`: the norm of r and five
+ *                          launches, each computing the two 3x3 convolutions
+ *                          of one U-Net level (the last one also the 1x1 head
+ *                          and the output scaling).  Calls on one network
+ *                          share its workspaces: do not overlap them.
  *   fl_set_preconditioner -- attach (or detach with NULL) a network to a 2D
  *                          operator for FL_SOLVE_FPCG; not owned.
  *   fl_gemm_test        -- C = A B^T (host arrays [M][K], [N][K], [M][N];

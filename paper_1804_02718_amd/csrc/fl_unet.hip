@@ -1571,7 +1571,6 @@ fl_status fl_unet_apply(fl_unet u, const double *r, int n, double alpha, double 
     hipLaunchKernelGGL(k_sumsq_part, dim3(kSqParts), dim3(256), 0, s, r, (long)n * n, u->sqpart);
     hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(64), 0, s, u->sqpart, kSqParts, u->nrm);
     FL_TRY(unet_apply(u, r, n, alpha, z, u->nrm, s));
-    FL_HIP_TRY(hipStreamSynchronize(s));
     return FL_OK;
 }
 
