@@ -120,11 +120,11 @@ static fl_status create(int d, double alpha, double gamma, double h, int N, cons
     // widest tile and 16-byte (FP64) values; lines: the x pass's rows (T1),
     // the z lines times P y frequencies (T2, 3D).  Large operators (FFT length
     // above the LDS path's) instead hold two P x Qp complex work buffers and
-    // lambda (Q x Q) in the four-step passes' column order in both precisions.
+    // lambda in natural order only (Q x Q, with an FP32 copy).
     const long w32 = op->Q + kMaxTile - 1, w64 = op->Q + kMaxTile - 1;
     const size_t colb = sizeof(double2) * w64;
     const bool large = large_op(op);
-    const long lam64t_len = large ? ql : qrest * w64, lam32t_len = large ? ql : qrest * w32;
+    const long lam64t_len = large ? 0 : qrest * w64, lam32t_len = large ? ql : qrest * w32;
     if (large) {
         op->T1_bytes = op->T2_bytes = sizeof(double2) * (size_t)op->P * op->Qp;
     } else {

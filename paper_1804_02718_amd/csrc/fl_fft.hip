@@ -1073,15 +1073,12 @@ fl_status tau_symbol(fl_op op, double s0, double s1, int prec, int C, void *lt, 
         set_error("s0 + s1 lambda is not positive on every sine mode: no sine-transform preconditioner");
         return FL_E_BREAKDOWN;
     }
-    if (large_op(op)) {  // the column order of the four-step passes
+    if (large_op(op)) {  // natural order, as the large-operator passes read lambda
         const int gn = cdiv(ql, 256) > 65536 ? 65536 : cdiv(ql, 256);
-        int P1 = 0, P2 = 0;
-        fs_split(op->P, P1, P2);
         if (prec == FL_FP32)
-            hipLaunchKernelGGL(k_fs_permute<float>, dim3(gn), dim3(256), 0, s, op->lam64, (float *)lt, Q, P1, P2, m);
+            hipLaunchKernelGGL(k_large_symbol<float>, dim3(gn), dim3(256), 0, s, op->lam64, (float *)lt, Q, m);
         else
-            hipLaunchKernelGGL(k_fs_permute<double>, dim3(gn), dim3(256), 0, s, op->lam64, (double *)lt, Q, P1, P2,
-                               m);
+            hipLaunchKernelGGL(k_large_symbol<double>, dim3(gn), dim3(256), 0, s, op->lam64, (double *)lt, Q, m);
         FL_HIP_TRY(hipGetLastError());
         return FL_OK;
     }
@@ -1276,13 +1273,13 @@ static void make_sched_all(const C2<T> *table, C2<T> *sched, hipStream_t s) {
     }
 }
 
-// twiddles exp(-2 pi i m / L) of the four-step's short transforms (L = 128 at
-// fs_tw_off(128), L = 64 at fs_tw_off(64)), taken from the length-P table
+// twiddles exp(-2 pi i m / L) of the large-operator passes' short transforms
+// (L = 16 ... 128 at fs_tw_off(L)), taken from the length-P table
 template <typename T>
 __global__ void k_fs_subtw(const C2<T> *__restrict__ tw, C2<T> *__restrict__ sub, int P) {
     const int i = threadIdx.x;
-    if (i < 128) sub[fs_tw_off(128) + i] = tw[i * (P / 128)];
-    if (i < 64) sub[fs_tw_off(64) + i] = tw[i * (P / 64)];
+    for (int L = 16; L <= 128; L *= 2)
+        if (i < L) sub[fs_tw_off(L) + i] = tw[i * (P / L)];
 }
 
 fl_status make_schedules(fl_op op, hipStream_t s) {
@@ -1467,13 +1464,13 @@ static C2<T> *big_fft(C2<T> *a, C2<T> *b, int P, int nlines, long lstride, long 
 
 template <typename T> static const T *big_lam(fl_op op);
 template <> const float *big_lam<float>(fl_op op) { return op->lam32t; }
-template <> const double *big_lam<double>(fl_op op) { return op->lam64t; }
+template <> const double *big_lam<double>(fl_op op) { return op->lam64; }
 template <typename T> static const C2<T> *fs_subtw(fl_op op);
 template <> const float2 *fs_subtw<float>(fl_op op) { return op->sch32; }
 template <> const double2 *fs_subtw<double>(fl_op op) { return op->sch64; }
 
-// sym (optional) replaces lambda (Q x Q in the four-step column order); odd:
-// the forward passes read the odd extensions (the sine-transform preconditioner)
+// sym (optional) replaces lambda (Q x Q, natural order); odd: the forward
+// passes read the odd extensions (the sine-transform preconditioner)
 template <typename T>
 fl_status large_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
                        const T *sym, bool odd) {
@@ -1511,13 +1508,9 @@ fl_status large_symbol(fl_op op, hipStream_t s) {
     hipLaunchKernelGGL(k_big_split<double>, dim3(big_grid((long)(P / 2) * Q)), dim3(256), 0, s, X, S, P, P, Q, Qs);
     double2 *F = big_fft<double, true>(S, X, P, Q, 1, Qs, op->tw64, s);
     hipLaunchKernelGGL(k_big_extract, dim3(big_grid((long)Q * Q)), dim3(256), 0, s, F, op->lam64, P, Q, Qs);
-    // FP64 and FP32 copies in the column order of the four-step passes
-    int P1 = 0, P2 = 0;
-    fs_split(P, P1, P2);
-    hipLaunchKernelGGL(k_fs_permute<double>, dim3(big_grid((long)Q * Q)), dim3(256), 0, s, op->lam64, op->lam64t, Q,
-                       P1, P2, SymMap{});
-    hipLaunchKernelGGL(k_fs_permute<float>, dim3(big_grid((long)Q * Q)), dim3(256), 0, s, op->lam64, op->lam32t, Q,
-                       P1, P2, SymMap{});
+    // the FP32 copy the FP32 passes read (the FP64 passes read lam64 itself)
+    hipLaunchKernelGGL(k_large_symbol<float>, dim3(big_grid((long)Q * Q)), dim3(256), 0, s, op->lam64, op->lam32t, Q,
+                       SymMap{});
     hipError_t le = hipGetLastError();
     hipError_t se = hipStreamSynchronize(s);
     (void)hipFree(cemb);

@@ -1,160 +1,250 @@
-// Large 2D operators (FFT length P = 4096 ... 16384) by the four-step
-// factorisation P = P1 * P2 (P1, P2 in {64, 128}).  Included inside namespace
-// fl by fl_fft.hip, after the plan, stage and twiddle helpers.
+// Large 2D operators (FFT length P = 4096 ... 16384).  Included inside
+// namespace fl by fl_fft.hip, after the plan, stage and twiddle helpers.
 //
-// A line of P values no longer fits a workgroup's LDS, but its transform splits
-// into short transforms that do.  With n = P2 n1 + n2 and k = k1 + P1 k2,
+// y = A u in five passes over HBM:
+//   xrow  one real row per workgroup, whole in LDS: the P/2-point complex
+//         transform of z[m] = x[2m] + i x[2m+1] and the split into the row's
+//         half spectrum X[0..P/2], written in natural column order
+//   ya    y step 1 over the Q half-spectrum columns, twiddle
+//   ymid  y step 2, lambda, the inverse of y step 2 (in place)
+//   yai   conjugate twiddle, inverse y step 1, the ny rows kept
+//   xrowi one row per workgroup: the inverse of xrow and the solver epilogue
+// A column of P values does not fit a workgroup's LDS (the y passes carry
+// kFsLines adjacent columns to keep every access contiguous), so the y
+// transform is split by the four-step factorisation P = P1 P2 (P1, P2 in
+// {64, 128}): with n = P2 n1 + n2 and k = k1 + P1 k2,
 //   X[k1 + P1 k2] = sum_n2 W_P2^(n2 k2) W_P^(n2 k1) sum_n1 x[P2 n1 + n2] W_P1^(n1 k1),
-// so a transform is one pass of P1-point transforms over n1 (a stride of P2)
-// with the twiddle W_P^(n2 k1), then one pass of P2-point transforms over the
-// contiguous n2, and the inverse runs the same steps backwards with conjugate
-// twiddles.  The spectrum stays in that transposed order (k1 major).
-//
-// y = A u takes seven passes over HBM, each a set of short transforms in LDS:
-//   xa   row pairs packed as complex lines, x step 1 (P1-point), twiddle
-//   xb   x step 2 (P2-point) and the Hermitian split into the half spectra of
-//        the two rows; lines k1 and P1 - k1 share a workgroup, so each finds
-//        its mirror Z(-k) in LDS
-//   ya   y step 1 over the Q half-spectrum columns, twiddle
-//   ymid y step 2, lambda, the inverse of y step 2 (in place)
-//   yai  conjugate twiddle, inverse y step 1, the ny rows kept
-//   xbi  unsplit and inverse x step 2, conjugate twiddle
-//   xai  inverse x step 1, unpack to the two rows, solver epilogue
-// The half-spectrum columns are stored in the permuted order fs_col below
-// (k1-major, mirror lines adjacent), which keeps every access of every pass a
-// run of consecutive addresses; lambda is stored in the same column order.
+// one pass of P1-point transforms over n1 with the twiddle W_P^(n2 k1), one of
+// P2-point transforms over n2, and the inverse the same steps backwards with
+// conjugate twiddles; between them the spectrum stays in that transposed
+// order.  A row's P/2-point transform is the same factorisation inside one
+// workgroup's LDS, P/2 = M1 x 128.
 
 template <int L> struct FsPlan;
 template <> struct FsPlan<128> { using PN = Plan<128, 8>; };
 template <> struct FsPlan<64> { using PN = Plan<64, 8>; };
-// short transforms per workgroup (lines); P1 and P2 are multiples of it
+template <> struct FsPlan<32> { using PN = Plan<32, 8>; };
+template <> struct FsPlan<16> { using PN = Plan<16, 8>; };
+// short column transforms per workgroup of the y passes (lines); P1, P2 are multiples of it
 constexpr int kFsLines = 32;
 template <int L> constexpr int fs_threads() { return kFsLines * (L / FsPlan<L>::PN::E); }
-// the short transforms' twiddle tables exp(-2 pi i m / L) in one buffer
-constexpr int fs_tw_off(int L) { return L == 128 ? 0 : 128; }
-constexpr int kFsTwLen = 192;
+// the short transforms' twiddle tables exp(-2 pi i m / L), L = 128, 64, 32, 16, in one buffer
+constexpr int fs_tw_off(int L) { return L == 128 ? 0 : L == 64 ? 128 : L == 32 ? 192 : 224; }
+constexpr int kFsTwLen = 240;
 
-// column of half-spectrum frequency kx = k1 + P1 k2 (kx <= P / 2):
-//   k1 = 0:       k2 in [0, P2/2]      -> columns [0, P2/2]
-//   k1 = P1/2:    k2 in [0, P2/2)      -> columns (P2/2, P2]
-//   the pair p = min(k1, P1 - k1) in [1, P1/2): line p, then line P1 - p,
-//                 P2/2 columns each from P2 + 1 + (p - 1) P2
-__host__ __device__ inline int fs_col(int P1, int P2, int k1, int k2) {
-    if (k1 == 0) return k2;
-    if (k1 == P1 / 2) return P2 / 2 + 1 + k2;
-    const bool lo = k1 < P1 / 2;
-    const int p = lo ? k1 : P1 - k1;
-    return P2 + 1 + (2 * (p - 1) + (lo ? 0 : 1)) * (P2 / 2) + k2;
+// ---------------------------------------------------------------------------
+// x passes: a real row of the P-periodic line (zero-padded, or for ODD its odd
+// extension: e[p] = x[p] for p < nx, -x[P - 2 - p] where P - 2 - p < nx) as
+// z[m] = e[2m] + i e[2m+1], m < M = P/2.  With Z = FFT_M(z), E and O the
+// transforms of the even and odd samples, Z = E + i O and
+//   E[k] = (Z[k] + conj Z[M - k]) / 2,  O[k] = (Z[k] - conj Z[M - k]) / (2i),
+//   X[k] = E[k] + W_P^k O[k],  k = 0 .. M   (Z of period M).
+// The inverse forms Z'[k] = (X[k] + conj X[M - k]) + i W_P^-k (X[k] - conj X[M - k]),
+// k < M, whose unnormalised inverse M-point transform is e[2m] + i e[2m+1].
+// LDS holds z as M1 lines of 128 (index m = 128 a + b at xr_addr(a, b));
+// step A transforms the lines b over a (M1 points), step B the lines a over b.
+// ---------------------------------------------------------------------------
+template <int M1> constexpr int xr_threads() { return M1 >= 32 ? 512 : 256; }
+// line stride: one more than the padded line, so consecutive lines start on
+// different banks (the split reads the lines k mod M1 for consecutive k)
+constexpr int kXrLS = padded_len<128>() + 1;
+__device__ __forceinline__ int xr_addr(int a, int b) { return a * kXrLS + padpos(b); }
+
+// z of one row (zero-padded, or its odd extension, to P) into registers: slot i
+// holds m = threadIdx.x + NTH i; without ODD only m < M/2 can be nonzero (nx <= P/2)
+template <typename T, int NTH, int NL, int P, bool ODD>
+__device__ __forceinline__ void xr_load_z(C2<T> (&zl)[NL], const T *__restrict__ ur, int nx) {
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int m = threadIdx.x + NTH * i;
+        T e2[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int p = 2 * m + h;
+            if constexpr (!ODD) {
+                if (i < NL / 2) {
+                    const bool ok = p < nx;
+                    const T x = ur[ok ? p : 0];
+                    e2[h] = ok ? x : T(0);
+                } else {
+                    e2[h] = T(0);
+                }
+            } else {
+                const int q = P - 2 - p;
+                const bool lo = p < nx, hi = q >= 0 && q < nx;
+                const T x = ur[lo ? p : (hi ? q : 0)];
+                e2[h] = lo ? x : (hi ? -x : T(0));
+            }
+        }
+        zl[i] = mk<T>(e2[0], e2[1]);
+    }
 }
-// the frequency kx of a column (the inverse of fs_col)
-__host__ __device__ inline int fs_kx(int P1, int P2, int col) {
-    if (col <= P2 / 2) return P1 * col;
-    if (col <= P2) return P1 / 2 + P1 * (col - (P2 / 2 + 1));
-    const int c = col - (P2 + 1), g = c / (P2 / 2), k2 = c - g * (P2 / 2);
-    const int p = g / 2 + 1;
-    return ((g & 1) ? P1 - p : p) + P1 * k2;
-}
-// line of a workgroup of xb / xbi: pair pi = 0 holds the self-mirrored lines
-// k1 = 0 and P1/2, pair pi > 0 the lines pi and P1 - pi
-__device__ __forceinline__ int fs_pair_line(int P1, int pi, int which) {
-    return pi == 0 ? (which ? P1 / 2 : 0) : (which ? P1 - pi : pi);
+// the LDS transform of both row kernels, in place on buf: step A (M1-point
+// transforms over a of the lines b, then W_M^(b k1) = W_P^(2 b k1)) and step B
+// (128-point transforms over b of the lines k1); leaves Z[k1 + M1 k2] at
+// xr_addr(k1, k2).  INV: the adjoint steps in reverse order (B', then the
+// conjugate twiddle, then A'), from Z' at xr_addr(k1, k2) to z[128 a + b] at
+// xr_addr(a, b).  Starts and ends with buf complete (callers barrier around it).
+template <typename T, int M1, int NTH, bool INV>
+__device__ __forceinline__ void xr_transform(C2<T> *buf, const C2<T> *__restrict__ tw, const C2<T> *__restrict__ subtw) {
+    constexpr int M2 = 128;
+    using PA = typename FsPlan<M1>::PN;
+    using PB = typename FsPlan<M2>::PN;
+    constexpr int EA = PA::E, TLA = M1 / EA, LA = PA::L, EB = PB::E, TLB = M2 / EB, LB = PB::L;
+    constexpr int LPA = NTH / TLA, RA = M2 / LPA, LPB = NTH / TLB, RB = M1 / LPB;
+    static_assert(RA >= 1 && RB >= 1 && RA * LPA == M2 && RB * LPB == M1, "rounds");
+    auto step_a = [&]() {
+        const int c = threadIdx.x % LPA, tl = threadIdx.x / LPA;
+        C2<T> tws[num_tw<PA>()];
+        load_twiddles<T, M1, PA>(tws, subtw + fs_tw_off(M1), tl);
+#pragma unroll
+        for (int rr = 0; rr < RA; ++rr) {
+            const int b = rr * LPA + c;
+            C2<T> v[EA];
+            auto lidx = [b](int pos) { return xr_addr(pos, b); };
+            if constexpr (!INV) {
+#pragma unroll
+                for (int j = 0; j < EA; ++j) v[j] = buf[lidx(in_pos<M1, PA, 0>(tl, j))];
+                __syncthreads();  // in registers before the line's exchanges overwrite it
+                fwd_stages<T, M1, PA, 0>(v, buf, tl, tws, lidx);
+#pragma unroll
+                for (int j = 0; j < EA; ++j) {
+                    const int k1 = out_pos<M1, PA, LA - 1>(tl, j);
+                    buf[lidx(k1)] = cmul<T>(v[j], tw[2 * b * k1]);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < EA; ++j) v[j] = buf[lidx(out_pos<M1, PA, LA - 1>(tl, j))];
+                __syncthreads();
+                adj_stages<T, M1, PA, LA - 1>(v, buf, tl, tws, lidx);
+#pragma unroll
+                for (int j = 0; j < EA; ++j) buf[lidx(in_pos<M1, PA, 0>(tl, j))] = v[j];
+            }
+        }
+    };
+    auto step_b = [&]() {
+        const int tl = threadIdx.x % TLB, c = threadIdx.x / TLB;
+        C2<T> tws[num_tw<PB>()];
+        load_twiddles<T, M2, PB>(tws, subtw + fs_tw_off(M2), tl);
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) {
+            const int k1 = rr * LPB + c;
+            C2<T> v[EB];
+            auto lidx = [k1](int pos) { return xr_addr(k1, pos); };
+            if constexpr (!INV) {
+#pragma unroll
+                for (int j = 0; j < EB; ++j) v[j] = buf[lidx(in_pos<M2, PB, 0>(tl, j))];
+                __syncthreads();
+                fwd_stages<T, M2, PB, 0>(v, buf, tl, tws, lidx);
+#pragma unroll
+                for (int j = 0; j < EB; ++j) buf[lidx(out_pos<M2, PB, LB - 1>(tl, j))] = v[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < EB; ++j) v[j] = buf[lidx(out_pos<M2, PB, LB - 1>(tl, j))];
+                __syncthreads();
+                adj_stages<T, M2, PB, LB - 1>(v, buf, tl, tws, lidx);
+#pragma unroll
+                for (int j = 0; j < EB; ++j) {
+                    const int b = in_pos<M2, PB, 0>(tl, j);
+                    buf[lidx(b)] = cmul<T>(v[j], cconj<T>(tw[2 * b * k1]));
+                }
+            }
+        }
+    };
+    if constexpr (!INV) {
+        step_a();
+        __syncthreads();
+        step_b();
+    } else {
+        step_b();
+        __syncthreads();
+        step_a();
+    }
 }
 
-// xa: row pair r of u (ny rows of nx values) as the complex line
-// u[2r] + i u[2r+1], zero-padded (ODD: the odd extensions of the rows);
-// P1-point transforms over n1 for the workgroup's kFsLines values of n2, times
-// W_P^(n2 k1), to line r of Lb at P2 k1 + n2
-template <typename T, int P1, int P2, bool ODD>
-__global__ __launch_bounds__(fs_threads<P1>()) void k_fs_xa(
-    const T *__restrict__ u, C2<T> *__restrict__ Lb, int nx, int ny, const C2<T> *__restrict__ tw,
+// x forward: one row per workgroup (blockIdx.x)
+template <typename T, int M1, bool ODD>
+__global__ __launch_bounds__(xr_threads<M1>()) void k_fs_xrow(
+    const T *__restrict__ u, C2<T> *__restrict__ S, int nx, int Qs, const C2<T> *__restrict__ tw,
     const C2<T> *__restrict__ subtw, const double *__restrict__ done) {
     if (done && *done != 0.0) return;
-    using PN = typename FsPlan<P1>::PN;
-    constexpr int E = PN::E, L = PN::L, NL = kFsLines, R0 = PN::R[0], P = P1 * P2;
-    __shared__ C2<T> lds[NL * padded_len<P1>()];
-    const int c = threadIdx.x % NL, tl = threadIdx.x / NL;
-    const int n2 = blockIdx.x * NL + c;
-    const long r = blockIdx.y;
-    const bool hb = 2 * r + 1 < ny;
-    const T *ua = u + 2 * r * nx, *ub = u + (hb ? 2 * r + 1 : 2 * r) * nx;
-    C2<T> v[E];
+    constexpr int NTH = xr_threads<M1>(), M2 = 128, M = M1 * M2, P = 2 * M, NL = M / NTH;
+    static_assert(NL * NTH == M, "whole rows per thread set");
+    __shared__ C2<T> buf[M1 * kXrLS];
+    const long row = blockIdx.x;
+    {
+        C2<T> zl[NL];
+        xr_load_z<T, NTH, NL, P, ODD>(zl, u + row * nx, nx);
 #pragma unroll
-    for (int j = 0; j < E; ++j) {
-        const int p = P2 * in_pos<P1, PN, 0>(tl, j) + n2;
-        if constexpr (!ODD) {
-            // n1 >= P1/2 (p >= P/2 >= nx) is the zero padding: known per slot
-            if ((j % R0) < R0 / 2) {
-                const bool ok = p < nx;
-                const T a = ua[ok ? p : 0], b = ub[ok ? p : 0];
-                v[j] = mk<T>(ok ? a : T(0), (ok && hb) ? b : T(0));
-            } else {
-                v[j] = mk<T>(T(0), T(0));
-            }
-        } else {
-            // x[p] for p < nx, -x[P - 2 - p] where P - 2 - p < nx, zero elsewhere
-            const int q = P - 2 - p;
-            const bool lo = p < nx, hi = q >= 0 && q < nx;
-            const int s = lo ? p : (hi ? q : 0);
-            const T a = ua[s], b = ub[s];
-            const T sg = lo ? T(1) : (hi ? T(-1) : T(0));
-            v[j] = mk<T>(sg * a, hb ? sg * b : T(0));
+        for (int i = 0; i < NL; ++i) {
+            const int m = threadIdx.x + NTH * i;
+            buf[xr_addr(m / M2, m % M2)] = zl[i];
         }
     }
-    C2<T> tws[num_tw<PN>()];
-    load_twiddles<T, P1, PN>(tws, subtw + fs_tw_off(P1), tl);
-    auto lidx = [c](int pos) { return padpos(pos) * NL + c; };
-    fwd_stages<T, P1, PN, 0>(v, lds, tl, tws, lidx);
-    C2<T> *dst = Lb + r * P + n2;
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-        const int k1 = out_pos<P1, PN, L - 1>(tl, j);
-        st_stream(dst + P2 * k1, cmul<T>(v[j], tw[n2 * k1]));
+    __syncthreads();
+    xr_transform<T, M1, NTH, false>(buf, tw, subtw);
+    __syncthreads();
+    // the row's half spectrum, natural column order
+    C2<T> *srow = S + row * Qs;
+    for (int k = threadIdx.x; k <= M; k += NTH) {
+        const int kk = k == M ? 0 : k, km = k == 0 ? 0 : M - k;
+        const C2<T> zk = buf[xr_addr(kk % M1, kk / M1)];
+        const C2<T> zm = buf[xr_addr(km % M1, km / M1)];
+        const C2<T> ev = mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
+        const C2<T> od = mk<T>(T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x));
+        st_stream(srow + k, cadd<T>(ev, cmul<T>(od, tw[k])));
     }
 }
 
-// xb: P2-point transforms over the contiguous n2 of lines k1 (pairs k1, P1 - k1
-// in one workgroup), then the half spectra of rows 2r and 2r + 1:
-// X_a = (Z(k) + conj Z(-k)) / 2, X_b = (Z(k) - conj Z(-k)) / (2i), k <= P/2,
-// to columns fs_col of S (row stride Qs)
-template <typename T, int P1, int P2>
-__global__ __launch_bounds__(fs_threads<P2>()) void k_fs_xb(
-    const C2<T> *__restrict__ Lb, C2<T> *__restrict__ S, int ny, int Qs, const C2<T> *__restrict__ subtw,
-    const double *__restrict__ done) {
+// x inverse: one row per workgroup; X[0..M] of the row -> Z' -> the inverse
+// transform -> y[2m] = Re z[m], y[2m + 1] = Im z[m] below nx, with the epilogue
+template <typename T, int M1, bool EPI>
+__global__ __launch_bounds__(xr_threads<M1>()) void k_fs_xrowi(
+    const C2<T> *__restrict__ S, T *__restrict__ y, int nx, int Qs, const C2<T> *__restrict__ tw,
+    const C2<T> *__restrict__ subtw, Epi<T> ep, const double *__restrict__ done) {
     if (done && *done != 0.0) return;
-    using PN = typename FsPlan<P2>::PN;
-    constexpr int E = PN::E, TL = P2 / E, L = PN::L, NL = kFsLines, H = NL / 2, PLL = padded_len<P2>();
-    constexpr int P = P1 * P2;
-    __shared__ C2<T> lds[NL * PLL];
-    const int tl = threadIdx.x % TL, c = threadIdx.x / TL;
-    const int pi = blockIdx.x * H + c % H;
-    const int k1 = fs_pair_line(P1, pi, c / H);
-    const long r = blockIdx.y;
-    const C2<T> *src = Lb + r * P + P2 * k1;
-    C2<T> v[E];
+    constexpr int NTH = xr_threads<M1>(), M2 = 128, M = M1 * M2, NL = M / NTH;
+    static_assert(NL * NTH == M, "whole rows per thread set");
+    __shared__ C2<T> buf[M1 * kXrLS];
+    const long row = blockIdx.x;
+    const C2<T> *srow = S + row * Qs;
+    {
+        // Z'[k] = (X[k] + conj X[M-k]) + i W_P^-k (X[k] - conj X[M-k]), k < M, straight from the row
+        C2<T> zl[NL];
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = src[in_pos<P2, PN, 0>(tl, j)];
-    C2<T> tws[num_tw<PN>()];
-    load_twiddles<T, P2, PN>(tws, subtw + fs_tw_off(P2), tl);
-    auto lidx = [c](int pos) { return c * PLL + padpos(pos); };
-    fwd_stages<T, P2, PN, 0>(v, lds, tl, tws, lidx);
-    // the forward stages end with their LDS reads behind a barrier
+        for (int i = 0; i < NL; ++i) {
+            const int k = threadIdx.x + NTH * i;
+            const C2<T> a = srow[k], b = srow[M - k];
+            const C2<T> sm = mk<T>(a.x + b.x, a.y - b.y);
+            const C2<T> df = mk<T>(a.x - b.x, a.y + b.y);
+            const C2<T> wd = cmul<T>(df, cconj<T>(tw[k]));
+            zl[i] = mk<T>(sm.x - wd.y, sm.y + wd.x);
+        }
 #pragma unroll
-    for (int j = 0; j < E; ++j) lds[lidx(out_pos<P2, PN, L - 1>(tl, j))] = v[j];
+        for (int i = 0; i < NL; ++i) {
+            const int k = threadIdx.x + NTH * i;
+            buf[xr_addr(k % M1, k / M1)] = zl[i];
+        }
+    }
     __syncthreads();
-    const int cm = pi == 0 ? c : (c + H) % NL;  // the line holding Z(-k)
-    const int cnt = k1 == 0 ? P2 / 2 + 1 : P2 / 2;
-    const bool hb = 2 * r + 1 < ny;
-    C2<T> *sa = S + 2 * r * Qs, *sb = S + (2 * r + 1) * Qs;
-    for (int k2 = tl; k2 < cnt; k2 += TL) {
-        const int m2 = k1 == 0 ? (P2 - k2) & (P2 - 1) : P2 - 1 - k2;
-        const C2<T> zk = lds[lidx(k2)];
-        const C2<T> zq = lds[cm * PLL + padpos(m2)];  // Z(-k) = zq; conj Z(-k) = (zq.x, -zq.y)
-        const int col = fs_col(P1, P2, k1, k2);
-        // plain stores: a line's threads write TL consecutive columns per
-        // step, and the L2 merges the steps' runs before they reach HBM (measured
-        // 1.5x faster here than streaming stores)
-        sa[col] = mk<T>(T(0.5) * (zk.x + zq.x), T(0.5) * (zk.y - zq.y));
-        if (hb) sb[col] = mk<T>(T(0.5) * (zk.y + zq.y), T(-0.5) * (zk.x - zq.x));
+    xr_transform<T, M1, NTH, true>(buf, tw, subtw);
+    __syncthreads();
+    T *yr = y + row * nx;
+    for (int m = threadIdx.x; 2 * m < nx; m += NTH) {
+        const C2<T> z = buf[xr_addr(m / M2, m % M2)];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int p = 2 * m + h;
+            if (p >= nx) break;
+            T v = h ? z.y : z.x;
+            if constexpr (EPI) {
+                const long idx = row * nx + p;
+                v *= ep.scale;
+                if (ep.w1) v += ep.a1 * ep.w1[idx];
+                if (ep.w2) v += ep.a2 * ep.w2[idx];
+            }
+            yr[p] = v;
+        }
     }
 }
 
@@ -203,7 +293,7 @@ __global__ __launch_bounds__(fs_threads<P1>()) void k_fs_ya(
 
 // ymid: for one k1 and kFsLines adjacent columns, y step 2 over rows
 // P2 k1 + n2 (P2-point), lambda at ky = k1 + P1 k2 (row fold(ky) of lam,
-// columns in fs_col order, row stride Q), and the inverse of y step 2, in place
+// natural columns, row stride Q), and the inverse of y step 2, in place
 template <typename T, int P1, int P2>
 __global__ __launch_bounds__(fs_threads<P2>()) void k_fs_ymid(
     C2<T> *__restrict__ Tb, int Q, int Qs, const T *__restrict__ lam, const C2<T> *__restrict__ subtw,
@@ -270,109 +360,14 @@ __global__ __launch_bounds__(fs_threads<P1>()) void k_fs_yai(
     }
 }
 
-// xbi: the full spectrum Z(k) = X_a(k) + i X_b(k) of lines k1 (pairs k1, P1 - k1
-// in one workgroup) from the half spectra of rows 2r and 2r + 1 (k > P/2 from
-// the mirror: Z(k) = conj X_a(P - k) + i conj X_b(P - k)), inverse P2-point
-// transforms over k2, times W_P^(-n2 k1), to line r of Lb at P2 k1 + n2
-template <typename T, int P1, int P2>
-__global__ __launch_bounds__(fs_threads<P2>()) void k_fs_xbi(
-    const C2<T> *__restrict__ S, C2<T> *__restrict__ Lb, int ny, int Qs, const C2<T> *__restrict__ tw,
-    const C2<T> *__restrict__ subtw, const double *__restrict__ done) {
-    if (done && *done != 0.0) return;
-    using PN = typename FsPlan<P2>::PN;
-    constexpr int E = PN::E, TL = P2 / E, L = PN::L, NL = kFsLines, H = NL / 2, PLL = padded_len<P2>();
-    constexpr int P = P1 * P2;
-    __shared__ C2<T> lds[NL * PLL];
-    const int tl = threadIdx.x % TL, c = threadIdx.x / TL;
-    const int pi = blockIdx.x * H + c % H;
-    const int k1 = fs_pair_line(P1, pi, c / H);
-    const long r = blockIdx.y;
-    const bool hb = 2 * r + 1 < ny;
-    const C2<T> *sa = S + 2 * r * Qs, *sb = S + (hb ? 2 * r + 1 : 2 * r) * Qs;
-    C2<T> v[E];
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-        const int k2 = out_pos<P2, PN, L - 1>(tl, j);
-        const bool dir = k1 == 0 ? k2 <= P2 / 2 : k2 < P2 / 2;
-        const int m1 = dir ? k1 : (P1 - k1) & (P1 - 1);
-        const int m2 = dir ? k2 : (k1 == 0 ? P2 - k2 : P2 - 1 - k2);
-        const int col = fs_col(P1, P2, m1, m2);
-        const C2<T> A = sa[col];
-        const C2<T> B = keep<T>(hb, sb[col]);
-        v[j] = dir ? mk<T>(A.x - B.y, A.y + B.x) : mk<T>(A.x + B.y, B.x - A.y);
-    }
-    C2<T> tws[num_tw<PN>()];
-    load_twiddles<T, P2, PN>(tws, subtw + fs_tw_off(P2), tl);
-    auto lidx = [c](int pos) { return c * PLL + padpos(pos); };
-    adj_stages<T, P2, PN, L - 1>(v, lds, tl, tws, lidx);
-    C2<T> *dst = Lb + r * P + P2 * k1;
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-        const int n2 = in_pos<P2, PN, 0>(tl, j);
-        st_stream(dst + n2, cmul<T>(v[j], cconj<T>(tw[n2 * k1])));
-    }
-}
-
-// xai: inverse P1-point transforms over k1 of line r (kFsLines values of n2),
-// positions P2 n1 + n2 < nx unpacked to rows 2r (real part) and 2r + 1
-// (imaginary part) of y, with the solver epilogue y = a1 w1 + a2 w2 + scale (A u)
-template <typename T, int P1, int P2, bool EPI>
-__global__ __launch_bounds__(fs_threads<P1>()) void k_fs_xai(
-    const C2<T> *__restrict__ Lb, T *__restrict__ y, int nx, int ny, const C2<T> *__restrict__ subtw, Epi<T> ep,
-    const double *__restrict__ done) {
-    if (done && *done != 0.0) return;
-    using PN = typename FsPlan<P1>::PN;
-    constexpr int E = PN::E, L = PN::L, NL = kFsLines, R0 = PN::R[0], P = P1 * P2;
-    __shared__ C2<T> lds[NL * padded_len<P1>()];
-    const int c = threadIdx.x % NL, tl = threadIdx.x / NL;
-    const int n2 = blockIdx.x * NL + c;
-    const long r = blockIdx.y;
-    const C2<T> *src = Lb + r * P + n2;
-    C2<T> v[E];
-#pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = src[P2 * out_pos<P1, PN, L - 1>(tl, j)];
-    C2<T> tws[num_tw<PN>()];
-    load_twiddles<T, P1, PN>(tws, subtw + fs_tw_off(P1), tl);
-    auto lidx = [c](int pos) { return padpos(pos) * NL + c; };
-    adj_stages<T, P1, PN, L - 1>(v, lds, tl, tws, lidx);
-    const bool hb = 2 * r + 1 < ny;
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-        if ((j % R0) < R0 / 2) {  // n1 >= P1/2 lies past nx
-            const int p = P2 * in_pos<P1, PN, 0>(tl, j) + n2;
-            if (p < nx) {
-                const long ia = 2 * r * nx + p, ib = ia + nx;
-                T a = v[j].x, b = v[j].y;
-                if constexpr (EPI) {
-                    a *= ep.scale;
-                    b *= ep.scale;
-                    if (ep.w1) {
-                        a += ep.a1 * ep.w1[ia];
-                        if (hb) b += ep.a1 * ep.w1[ib];
-                    }
-                    if (ep.w2) {
-                        a += ep.a2 * ep.w2[ia];
-                        if (hb) b += ep.a2 * ep.w2[ib];
-                    }
-                }
-                y[ia] = a;
-                if (hb) y[ib] = b;
-            }
-        }
-    }
-}
-
-// lambda (and the preconditioner's symbol) of a large operator in the fs_col
-// column order: out[ky * Q + col] = f(lam64[ky * Q + fs_kx(col)]) for ky, col < Q
+// lambda (or the preconditioner's symbol) of a large operator in natural order,
+// Q x Q (kx fastest), as the y passes read it
 template <typename T>
-__global__ void k_fs_permute(const double *__restrict__ lam64, T *__restrict__ out, int Q, int P1, int P2, SymMap m) {
+__global__ void k_large_symbol(const double *__restrict__ lam64, T *__restrict__ out, int Q, SymMap m) {
     const long total = (long)Q * Q;
     const int N2 = Q - 1;
-    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
-        const int ky = (int)(idx / Q), col = (int)(idx - (long)ky * Q);
-        const int kx = fs_kx(P1, P2, col);
-        out[idx] = (T)sym_at(lam64, (long)ky * Q + kx, kx, ky, 0, 2, N2, m);
-    }
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x)
+        out[idx] = (T)sym_at(lam64, idx, (int)(idx % Q), (int)(idx / Q), 0, 2, N2, m);
 }
 
 inline void fs_split(int P, int &P1, int &P2) {
@@ -382,25 +377,21 @@ inline void fs_split(int P, int &P1, int &P2) {
 
 template <typename T, int P1, int P2>
 static fl_status fs_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
-                      const T *lam, bool odd, const C2<T> *tw, const C2<T> *subtw) {
-    const int Q = op->Q, Qs = op->Qp, nx = op->nk[0], ny = op->nk[1], P = P1 * P2;
+                           const T *lam, bool odd, const C2<T> *tw, const C2<T> *subtw) {
+    const int Q = op->Q, Qs = op->Qp, nx = op->nk[0], ny = op->nk[1];
+    constexpr int P = P1 * P2, M1 = P / 256;
     static_assert(P1 % kFsLines == 0 && P2 % kFsLines == 0, "whole workgroups of lines");
     if (Qs % kFsLines != 0 || Qs < Q) {  // the row stride covers whole column groups (set at creation)
         set_error("row stride %d of the large-operator spectra is not a multiple of %d", Qs, kFsLines);
         return FL_E_UNSUPPORTED;
     }
-    const int nl = (ny + 1) / 2;
-    C2<T> *Tb = (C2<T> *)op->T1;
-    C2<T> *Lb = (C2<T> *)op->T2;
-    C2<T> *S = Lb + (long)nl * P;  // nl P + ny Qs <= P Qs complex values
-    const dim3 b1(fs_threads<P1>()), b2(fs_threads<P2>());
+    C2<T> *Tb = (C2<T> *)op->T1;  // P x Qs: the y passes' transposed-order spectra
+    C2<T> *S = (C2<T> *)op->T2;   // ny x Qs: the rows' half spectra
+    const dim3 b1(fs_threads<P1>()), b2(fs_threads<P2>()), bx(xr_threads<M1>());
     if (odd)
-        hipLaunchKernelGGL((k_fs_xa<T, P1, P2, true>), dim3(P2 / kFsLines, nl), b1, 0, s, u, Lb, nx, ny, tw, subtw,
-                           done);
+        hipLaunchKernelGGL((k_fs_xrow<T, M1, true>), dim3(ny), bx, 0, s, u, S, nx, Qs, tw, subtw, done);
     else
-        hipLaunchKernelGGL((k_fs_xa<T, P1, P2, false>), dim3(P2 / kFsLines, nl), b1, 0, s, u, Lb, nx, ny, tw, subtw,
-                           done);
-    hipLaunchKernelGGL((k_fs_xb<T, P1, P2>), dim3(P1 / kFsLines, nl), b2, 0, s, Lb, S, ny, Qs, subtw, done);
+        hipLaunchKernelGGL((k_fs_xrow<T, M1, false>), dim3(ny), bx, 0, s, u, S, nx, Qs, tw, subtw, done);
     if (odd)
         hipLaunchKernelGGL((k_fs_ya<T, P1, P2, true>), dim3(Qs / kFsLines, P2), b1, 0, s, S, Tb, ny, Qs, tw, subtw,
                            done);
@@ -409,12 +400,9 @@ static fl_status fs_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, const d
                            done);
     hipLaunchKernelGGL((k_fs_ymid<T, P1, P2>), dim3(Qs / kFsLines, P1), b2, 0, s, Tb, Q, Qs, lam, subtw, done);
     hipLaunchKernelGGL((k_fs_yai<T, P1, P2>), dim3(Qs / kFsLines, P2), b1, 0, s, Tb, S, ny, Qs, tw, subtw, done);
-    hipLaunchKernelGGL((k_fs_xbi<T, P1, P2>), dim3(P1 / kFsLines, nl), b2, 0, s, S, Lb, ny, Qs, tw, subtw, done);
     if (ep.active())
-        hipLaunchKernelGGL((k_fs_xai<T, P1, P2, true>), dim3(P2 / kFsLines, nl), b1, 0, s, Lb, y, nx, ny, subtw, ep,
-                           done);
+        hipLaunchKernelGGL((k_fs_xrowi<T, M1, true>), dim3(ny), bx, 0, s, S, y, nx, Qs, tw, subtw, ep, done);
     else
-        hipLaunchKernelGGL((k_fs_xai<T, P1, P2, false>), dim3(P2 / kFsLines, nl), b1, 0, s, Lb, y, nx, ny, subtw,
-                           ep, done);
+        hipLaunchKernelGGL((k_fs_xrowi<T, M1, false>), dim3(ny), bx, 0, s, S, y, nx, Qs, tw, subtw, ep, done);
     return FL_OK;
 }
