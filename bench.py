@@ -34,7 +34,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2_fp32.json")
 KERNEL_SOURCES = ["paper_1804_02718_amd/csrc/fl_fft.hip", "paper_1804_02718_amd/csrc/fl_internal.hpp",
-                  "paper_1804_02718_amd/csrc/fl_wave2d.hpp"]
+                  "paper_1804_02718_amd/csrc/fl_wave2d.hpp", "paper_1804_02718_amd/csrc/fl_fourstep.hpp"]
 
 
 def kernel_source_sha():
@@ -257,7 +257,14 @@ def large_extra(torch, fl, inputs, N=8192, alpha=1.5, reps=5):
             op.apply(u, y)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
-        out[name] = {"ms": round(dt * 1e3, 3), "gdof_s": round(op.M / dt / 1e9, 3)}
+        # pass model: each of x forward, the fused y pass and x inverse reads its input and writes its
+        # output once, lambda read once (s bytes per real; n^2 unknowns, n x Q half spectra)
+        s = 8 if name == "fp64" else 4
+        n, Q = N - 1, op.desc["Q"]
+        model = 2 * s * n * n + 8 * s * n * Q + s * Q * Q
+        out[name] = {"ms": round(dt * 1e3, 3), "gdof_s": round(op.M / dt / 1e9, 3),
+                     "pass_model_GB": round(model / 1e9, 3), "GB_per_s": round(model / dt / 1e9, 1),
+                     "roofline_frac": round(model / dt / 1e9 / HBM_PEAK_GBS, 4)}
     # the Poisson problem on this grid (f = 8 seeded Gaussians), to 1e-8, by the default
     # solver (the sine-transform preconditioned FP32 inner solves in FP64 refinement here)
     f = torch.as_tensor(inputs.gauss_sum(2, N, 8, seed=2), device="cuda:0")
@@ -577,6 +584,11 @@ def main():
     ap.add_argument("--c5-res-samples", type=int, default=2048,
                     help="inputs for the residual-loss recipe of the learned preconditioner")
     ap.add_argument("--c5-res-epochs", type=int, default=10)
+    ap.add_argument("--large-only", action="store_true",
+                    help="run only the 2D N=8192 operator (FFT length 16384) leg and print its JSON (for profiling)")
+    ap.add_argument("--net-apply-only", action="store_true",
+                    help="only time 50 applications of the learned preconditioner at 256^2 (untrained weights; "
+                         "for profiling the network's kernels)")
     ap.add_argument("--c5-only", action="store_true",
                     help="run only the learned-preconditioner workload and print its JSON (for profiling)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -594,6 +606,26 @@ def main():
     from paper_1804_02718_amd import fl, inputs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.net_apply_only:
+        N = 256
+        net = fl.UNet(N, max_batch=1, seed=1)
+        r = torch.as_tensor(inputs.gauss_sum(2, N, 8, 5), device="cuda:0")
+        z = torch.empty_like(r)
+        for _ in range(3):
+            net.apply(r, N - 1, 1.2, z)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(50):
+            net.apply(r, N - 1, 1.2, z)
+        e1.record()
+        torch.cuda.synchronize()
+        print(json.dumps({"net_apply_ms": round(e0.elapsed_time(e1) / 50, 4)}), flush=True)
+        net.close()
+        return
+    if args.large_only:
+        print(json.dumps({"large_operator": large_extra(torch, fl, inputs)}), flush=True)
+        return
     if args.c5_only:
         print(json.dumps({"c5_learned": c5_extra(torch, fl, args.c5_pairs, args.c5_epochs,
                                                  res_samples=args.c5_res_samples,
