@@ -155,7 +155,11 @@ def cpu_oracle_extra(inputs):
     return out
 
 
-def cpu_baseline(N, alpha, h, u_np, seconds):
+def cpu_baseline(N, alpha, h, u_np, seconds, gpu_y=None):
+    """The oracle's explicit FP64 sum on seeded random rows of the C2 matvec for about `seconds`,
+    as rows per second.  gpu_y ({"fp64": y, "fp32": y} host arrays of the library's matvec of the
+    same u, FP32 on u rounded to FP32): its sampled rows are compared with the oracle's, e_rel
+    against |Au| and e_sc against the oracle's |A||u| on the first 1024 sampled rows."""
     import numpy as np
 
     import oracle
@@ -165,18 +169,36 @@ def cpu_baseline(N, alpha, h, u_np, seconds):
     order = rng.permutation(M)
     done = 0
     batch = 256
+    refs = []
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < seconds and done < M:
         rows = order[done:done + batch]
-        oracle.apply_rows(2, N, alpha, a, u_np, rows)
+        refs.append(oracle.apply_rows(2, N, alpha, a, u_np, rows))
         done += rows.size
         batch = min(batch * 2, 8192)
     dt = time.perf_counter() - t0
-    return {"value": done / dt / 1e9, "unit": "Gdof/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "host": host_cpu(),
-            "sample": "explicit O(M^2) FP64 sum (long-double accumulation) on %d seeded random rows of the "
-                      "%d-row N=1024 matvec in %.1f s, rate = rows/s (coefficient setup excluded)"
-                      % (done, M, dt)}
+    out = {"value": done / dt / 1e9, "unit": "Gdof/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "host": host_cpu(),
+           "sample": "explicit O(M^2) FP64 sum (long-double accumulation) on %d seeded random rows of the "
+                     "%d-row N=1024 matvec in %.1f s, rate = rows/s (coefficient setup excluded)"
+                     % (done, M, dt)}
+    if gpu_y is not None:
+        rows = order[:done]
+        ref = np.concatenate(refs)
+        sub = rows[:1024]
+        absref = oracle.apply_rows(2, N, alpha, a, u_np, sub, absmode=True)
+        u32 = u_np.astype(np.float32).astype(np.float64)
+        ref32 = oracle.apply_rows(2, N, alpha, a, u32, sub)
+        par = {"rows": int(done), "abs_rows": int(sub.size)}
+        for prec, y in gpu_y.items():
+            d = y[rows] - ref
+            ds = y[sub] - (ref[:sub.size] if prec == "fp64" else ref32)
+            par[prec] = {"e_rel": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+                         "e_sc": float(np.linalg.norm(ds) / np.linalg.norm(absref))}
+        par["note"] = ("e_rel: ||y - A u|| / ||A u|| on all sampled rows (fp32 against the FP64 u); e_sc: "
+                       "||y - A u|| / || |A||u| || on the first 1024 (fp32 against u rounded to FP32)")
+        out["parity_on_sample"] = par
+    return out
 
 
 def c3_extra(torch, fl, inputs, autotune, N=256, alpha=1.2):
@@ -696,6 +718,15 @@ def main():
                                          alphas=() if args.no_poisson_sweep else (0.5, 1.0, 1.5, 1.9))
         if not args.no_poisson_sweep:
             extra["poisson_shapes"] = poisson_shapes_extra(torch, fl, inputs)
+    gpu_y = None
+    if not args.no_cpu_baseline:
+        # the matvec the oracle's sample is compared with: FP64 on the unrounded u, FP32 on u rounded
+        u64n = torch.as_tensor(u_np, dtype=torch.float64, device="cuda:0")
+        y64n = torch.empty_like(u64n)
+        op.apply(u64n, y64n)
+        op.apply(u32, y32)
+        gpu_y = {"fp64": y64n.cpu().numpy(), "fp32": y32.cpu().numpy().astype(np.float64)}
+        del u64n, y64n
     op.close()
     if not args.no_extra and not args.no_c3:
         print("bench: 3D N=256 matvec", file=sys.stderr, flush=True)
@@ -717,7 +748,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(N, alpha, h, u_np, args.cpu_seconds)
+        cpu = cpu_baseline(N, alpha, h, u_np, args.cpu_seconds, gpu_y)
         if not args.no_extra:
             extra["cpu_oracle"] = cpu_oracle_extra(inputs)
         # the oracle's Poisson solve at C2, extrapolated (not measured): one full explicit
