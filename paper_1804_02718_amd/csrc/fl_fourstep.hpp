@@ -50,53 +50,95 @@ template <int M1> constexpr int xr_threads() { return M1 >= 32 ? 512 : 256; }
 constexpr int kXrLS = padded_len<128>() + 1;
 __device__ __forceinline__ int xr_addr(int a, int b) { return a * kXrLS + padpos(b); }
 
-// z of one row (zero-padded, or its odd extension, to P) into registers: slot i
-// holds m = threadIdx.x + NTH i; without ODD only m < M/2 can be nonzero (nx <= P/2)
-template <typename T, int NTH, int NL, int P, bool ODD>
-__device__ __forceinline__ void xr_load_z(C2<T> (&zl)[NL], const T *__restrict__ ur, int nx) {
-#pragma unroll
-    for (int i = 0; i < NL; ++i) {
-        const int m = threadIdx.x + NTH * i;
-        T e2[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int p = 2 * m + h;
-            if constexpr (!ODD) {
-                if (i < NL / 2) {
-                    const bool ok = p < nx;
-                    const T x = ur[ok ? p : 0];
-                    e2[h] = ok ? x : T(0);
-                } else {
-                    e2[h] = T(0);
-                }
-            } else {
-                const int q = P - 2 - p;
-                const bool lo = p < nx, hi = q >= 0 && q < nx;
-                const T x = ur[lo ? p : (hi ? q : 0)];
-                e2[h] = lo ? x : (hi ? -x : T(0));
-            }
-        }
-        zl[i] = mk<T>(e2[0], e2[1]);
-    }
+// the row kernels' twiddles, copied to LDS once per workgroup: the short
+// transforms' tables exp(-2 pi i m / L) at fs_tw_off(L), then W_M^e and W_P^e
+// for e < 128; a twiddle of the M- or P-point transform is the product of two
+// entries, so no global load is left between a row's loads and its stores
+constexpr int kXrTw = kFsTwLen + 256;
+template <typename T>
+__device__ __forceinline__ void xr_load_tw(C2<T> *twl, const C2<T> *__restrict__ tw, const C2<T> *__restrict__ subtw) {
+    for (int i = threadIdx.x; i < kXrTw; i += blockDim.x)
+        twl[i] = i < kFsTwLen ? subtw[i] : (i < kFsTwLen + 128 ? tw[2 * (i - kFsTwLen)] : tw[i - kFsTwLen - 128]);
 }
-// the LDS transform of both row kernels, in place on buf: step A (M1-point
-// transforms over a of the lines b, then W_M^(b k1) = W_P^(2 b k1)) and step B
-// (128-point transforms over b of the lines k1); leaves Z[k1 + M1 k2] at
-// xr_addr(k1, k2).  INV: the adjoint steps in reverse order (B', then the
-// conjugate twiddle, then A'), from Z' at xr_addr(k1, k2) to z[128 a + b] at
-// xr_addr(a, b).  Starts and ends with buf complete (callers barrier around it).
-template <typename T, int M1, int NTH, bool INV>
-__device__ __forceinline__ void xr_transform(C2<T> *buf, const C2<T> *__restrict__ tw, const C2<T> *__restrict__ subtw) {
-    constexpr int M2 = 128;
+// W_M^e, e < M = 128 M1: W_M1^(e / 128) W_M^(e mod 128)
+template <typename T, int M1> __device__ __forceinline__ C2<T> xr_wm(const C2<T> *twl, int e) {
+    return cmul<T>(twl[fs_tw_off(M1) + (e >> 7)], twl[kFsTwLen + (e & 127)]);
+}
+// W_P^k, k <= M = P / 2: W_(2 M1)^(k / 128) W_P^(k mod 128)
+template <typename T, int M1> __device__ __forceinline__ C2<T> xr_wp(const C2<T> *twl, int k) {
+    return cmul<T>(twl[fs_tw_off(2 * M1) + (k >> 7)], twl[kFsTwLen + 128 + (k & 127)]);
+}
+
+// Step A's layout of a row in registers: thread (c, tl) = (threadIdx.x mod LPA,
+// threadIdx.x / LPA) holds, in slot rr * EA + j, the point m = 128 a + b of
+// line b = rr * LPA + c at a = in_pos<M1, PA, 0>(tl, j) -- the inputs of its
+// step-A butterflies going forward and their outputs coming back.
+template <int M1, int NTH> struct XrShape {
     using PA = typename FsPlan<M1>::PN;
-    using PB = typename FsPlan<M2>::PN;
-    constexpr int EA = PA::E, TLA = M1 / EA, LA = PA::L, EB = PB::E, TLB = M2 / EB, LB = PB::L;
-    constexpr int LPA = NTH / TLA, RA = M2 / LPA, LPB = NTH / TLB, RB = M1 / LPB;
-    static_assert(RA >= 1 && RB >= 1 && RA * LPA == M2 && RB * LPB == M1, "rounds");
+    using PB = typename FsPlan<128>::PN;
+    static constexpr int EA = PA::E, TLA = M1 / EA, LA = PA::L, EB = PB::E, TLB = 128 / EB, LB = PB::L;
+    static constexpr int LPA = NTH / TLA, RA = 128 / LPA, LPB = NTH / TLB, RB = M1 / LPB;
+    static constexpr int NR = RA * EA;  // register slots of a row
+    static_assert(RA >= 1 && RB >= 1 && RA * LPA == 128 && RB * LPB == M1, "rounds");
+    // point of slot (rr, j); only slots with j mod R0 < R0 / 2 lie below M / 2
+    static __device__ __forceinline__ int point(int rr, int j) {
+        const int c = threadIdx.x % LPA, tl = threadIdx.x / LPA;
+        return 128 * in_pos<M1, PA, 0>(tl, j) + rr * LPA + c;
+    }
+    static constexpr bool low(int j) { return (j % PA::R[0]) < PA::R[0] / 2; }
+};
+
+// z of one row (zero-padded, or its odd extension, to P) into step A's registers
+template <typename T, int M1, int NTH, bool ODD>
+__device__ __forceinline__ void xr_load_za(C2<T> *zl, const T *__restrict__ ur, int nx) {
+    using S = XrShape<M1, NTH>;
+    constexpr int P = 256 * M1;
+#pragma unroll
+    for (int rr = 0; rr < S::RA; ++rr)
+#pragma unroll
+        for (int j = 0; j < S::EA; ++j) {
+            const int m = S::point(rr, j);
+            T e2[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int p = 2 * m + h;
+                if constexpr (!ODD) {
+                    if (S::low(j)) {
+                        const bool ok = p < nx;
+                        const T x = ur[ok ? p : 0];
+                        e2[h] = ok ? x : T(0);
+                    } else {
+                        e2[h] = T(0);  // m >= P/4: past every stored value
+                    }
+                } else {
+                    const int q = P - 2 - p;
+                    const bool lo = p < nx, hi = q >= 0 && q < nx;
+                    const T x = ur[lo ? p : (hi ? q : 0)];
+                    e2[h] = lo ? x : (hi ? -x : T(0));
+                }
+            }
+            zl[rr * S::EA + j] = mk<T>(e2[0], e2[1]);
+        }
+}
+
+// The LDS transform of both row kernels.  Forward: step A (M1-point
+// transforms over a of the lines b, from the registers zr, then
+// W_M^(b k1) = W_P^(2 b k1)), mid(), step B (128-point transforms over b of
+// the lines k1); leaves Z[k1 + M1 k2] at xr_addr(k1, k2).  INV: the adjoint
+// steps in reverse order (B', the conjugate twiddle, mid(), A') from Z' at
+// xr_addr(k1, k2) to z in the registers zr.  Callers barrier before it (buf
+// free, or Z' complete) and after it.
+template <typename T, int M1, int NTH, bool INV, typename Mid>
+__device__ __forceinline__ void xr_transform(C2<T> *buf, const C2<T> *twl, C2<T> *zr, Mid mid) {
+    using S = XrShape<M1, NTH>;
+    using PA = typename S::PA;
+    using PB = typename S::PB;
+    constexpr int M2 = 128, EA = S::EA, LA = S::LA, EB = S::EB, LB = S::LB, LPA = S::LPA, RA = S::RA;
+    constexpr int LPB = S::LPB, RB = S::RB, TLB = S::TLB;
     auto step_a = [&]() {
         const int c = threadIdx.x % LPA, tl = threadIdx.x / LPA;
         C2<T> tws[num_tw<PA>()];
-        load_twiddles<T, M1, PA>(tws, subtw + fs_tw_off(M1), tl);
+        load_twiddles<T, M1, PA>(tws, twl + fs_tw_off(M1), tl);
 #pragma unroll
         for (int rr = 0; rr < RA; ++rr) {
             const int b = rr * LPA + c;
@@ -104,28 +146,27 @@ __device__ __forceinline__ void xr_transform(C2<T> *buf, const C2<T> *__restrict
             auto lidx = [b](int pos) { return xr_addr(pos, b); };
             if constexpr (!INV) {
 #pragma unroll
-                for (int j = 0; j < EA; ++j) v[j] = buf[lidx(in_pos<M1, PA, 0>(tl, j))];
-                __syncthreads();  // in registers before the line's exchanges overwrite it
+                for (int j = 0; j < EA; ++j) v[j] = zr[rr * EA + j];
                 fwd_stages<T, M1, PA, 0>(v, buf, tl, tws, lidx);
 #pragma unroll
                 for (int j = 0; j < EA; ++j) {
                     const int k1 = out_pos<M1, PA, LA - 1>(tl, j);
-                    buf[lidx(k1)] = cmul<T>(v[j], tw[2 * b * k1]);
+                    buf[lidx(k1)] = cmul<T>(v[j], xr_wm<T, M1>(twl, b * k1));
                 }
             } else {
 #pragma unroll
                 for (int j = 0; j < EA; ++j) v[j] = buf[lidx(out_pos<M1, PA, LA - 1>(tl, j))];
-                __syncthreads();
+                __syncthreads();  // in registers before the line's exchanges overwrite it
                 adj_stages<T, M1, PA, LA - 1>(v, buf, tl, tws, lidx);
 #pragma unroll
-                for (int j = 0; j < EA; ++j) buf[lidx(in_pos<M1, PA, 0>(tl, j))] = v[j];
+                for (int j = 0; j < EA; ++j) zr[rr * EA + j] = v[j];
             }
         }
     };
     auto step_b = [&]() {
         const int tl = threadIdx.x % TLB, c = threadIdx.x / TLB;
         C2<T> tws[num_tw<PB>()];
-        load_twiddles<T, M2, PB>(tws, subtw + fs_tw_off(M2), tl);
+        load_twiddles<T, M2, PB>(tws, twl + fs_tw_off(M2), tl);
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr) {
             const int k1 = rr * LPB + c;
@@ -146,106 +187,179 @@ __device__ __forceinline__ void xr_transform(C2<T> *buf, const C2<T> *__restrict
 #pragma unroll
                 for (int j = 0; j < EB; ++j) {
                     const int b = in_pos<M2, PB, 0>(tl, j);
-                    buf[lidx(b)] = cmul<T>(v[j], cconj<T>(tw[2 * b * k1]));
+                    buf[lidx(b)] = cmul<T>(v[j], cconj<T>(xr_wm<T, M1>(twl, b * k1)));
                 }
             }
         }
     };
     if constexpr (!INV) {
         step_a();
+        mid();
         __syncthreads();
         step_b();
     } else {
         step_b();
+        mid();
         __syncthreads();
         step_a();
     }
 }
 
-// x forward: one row per workgroup (blockIdx.x)
+// The row kernels take rows b, b + gridDim.x, ... (workgroup b).  With PF
+// (FP64 at P = 16384: one 145 KB workgroup per CU) the next row's loads are
+// issued once step A has consumed the current row's registers and arrive
+// during step B and the split; the transform reads its twiddles from LDS, so
+// no other global load waits behind them.  Without PF (two or more workgroups
+// per CU overlap instead) a workgroup takes one row.
+template <typename T, int M1, bool ODD, bool INV> constexpr bool xr_prefetch() {
+    return sizeof(T) == 8 && M1 == 64 && !ODD && !INV;
+}
+
+// x forward: z of the row into step A's registers, the transform, the split
+// into X[0..M].  Split twiddles: for k = t + NTH i (t = threadIdx.x),
+// W_P^k = W_P^t W_(P/NTH)^i.
 template <typename T, int M1, bool ODD>
 __global__ __launch_bounds__(xr_threads<M1>()) void k_fs_xrow(
-    const T *__restrict__ u, C2<T> *__restrict__ S, int nx, int Qs, const C2<T> *__restrict__ tw,
+    const T *__restrict__ u, C2<T> *__restrict__ S, int nx, int ny, int Qs, const C2<T> *__restrict__ tw,
     const C2<T> *__restrict__ subtw, const double *__restrict__ done) {
     if (done && *done != 0.0) return;
-    constexpr int NTH = xr_threads<M1>(), M2 = 128, M = M1 * M2, P = 2 * M, NL = M / NTH;
-    static_assert(NL * NTH == M, "whole rows per thread set");
+    constexpr int NTH = xr_threads<M1>(), M = M1 * 128, P = 2 * M, NR = XrShape<M1, NTH>::NR;
+    constexpr int NS = (M + 1 + NTH - 1) / NTH;  // split outputs X[0..M] per thread
+    constexpr bool PF = xr_prefetch<T, M1, ODD, false>();
+    static_assert(NR * NTH == M && P / NTH <= 32, "whole rows per thread set");
     __shared__ C2<T> buf[M1 * kXrLS];
-    const long row = blockIdx.x;
-    {
-        C2<T> zl[NL];
-        xr_load_z<T, NTH, NL, P, ODD>(zl, u + row * nx, nx);
-#pragma unroll
-        for (int i = 0; i < NL; ++i) {
-            const int m = threadIdx.x + NTH * i;
-            buf[xr_addr(m / M2, m % M2)] = zl[i];
+    __shared__ C2<T> twl[kXrTw];
+    xr_load_tw<T>(twl, tw, subtw);
+    __syncthreads();
+    const C2<T> wt = xr_wp<T, M1>(twl, threadIdx.x);
+    C2<T> zl[NR];
+    auto body = [&](int row, auto mid) {
+        xr_transform<T, M1, NTH, false>(buf, twl, zl, mid);
+        __syncthreads();
+        C2<T> *srow = S + (long)row * Qs;
+#pragma unroll 1
+        for (int i = 0; i < NS; ++i) {
+            const int k = threadIdx.x + NTH * i;
+            if (k <= M) {
+                const int kk = k == M ? 0 : k, km = k == 0 ? 0 : M - k;
+                const C2<T> zk = buf[xr_addr(kk % M1, kk / M1)];
+                const C2<T> zm = buf[xr_addr(km % M1, km / M1)];
+                const C2<T> ev = mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
+                const C2<T> od = mk<T>(T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x));
+                const C2<T> w = cmul<T>(wt, twl[fs_tw_off(P / NTH) + i]);
+                st_stream(srow + k, cadd<T>(ev, cmul<T>(od, w)));
+            }
         }
-    }
-    __syncthreads();
-    xr_transform<T, M1, NTH, false>(buf, tw, subtw);
-    __syncthreads();
-    // the row's half spectrum, natural column order
-    C2<T> *srow = S + row * Qs;
-    for (int k = threadIdx.x; k <= M; k += NTH) {
-        const int kk = k == M ? 0 : k, km = k == 0 ? 0 : M - k;
-        const C2<T> zk = buf[xr_addr(kk % M1, kk / M1)];
-        const C2<T> zm = buf[xr_addr(km % M1, km / M1)];
-        const C2<T> ev = mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
-        const C2<T> od = mk<T>(T(0.5) * (zk.y + zm.y), T(-0.5) * (zk.x - zm.x));
-        st_stream(srow + k, cadd<T>(ev, cmul<T>(od, tw[k])));
+    };
+    if constexpr (!PF) {
+        xr_load_za<T, M1, NTH, ODD>(zl, u + (long)blockIdx.x * nx, nx);
+        body(blockIdx.x, [] {});
+    } else {
+        int row = blockIdx.x;
+        if (row < ny) xr_load_za<T, M1, NTH, ODD>(zl, u + (long)row * nx, nx);
+        for (; row < ny; row += gridDim.x) {
+            // keeps the LDS twiddle reads inside the loop (hoisted, they would
+            // hold registers across rows)
+            asm volatile("" ::: "memory");
+            const int next = row + gridDim.x;
+            body(row, [&] {
+                if (next < ny) xr_load_za<T, M1, NTH, ODD>(zl, u + (long)next * nx, nx);
+            });
+            __syncthreads();  // the split's reads before the next row's transform
+        }
     }
 }
 
-// x inverse: one row per workgroup; X[0..M] of the row -> Z' -> the inverse
-// transform -> y[2m] = Re z[m], y[2m + 1] = Im z[m] below nx, with the epilogue
+// x inverse: X[0..M] of the row -> Z' -> the inverse transform into step A's
+// registers -> y[2m] = Re z[m], y[2m + 1] = Im z[m] below nx, with the
+// epilogue (its reads issued before the last step).  A thread reads X[k] and
+// X[M - k] (k < M/2) once for both of
+//   Z'[k]     = (X[k] + conj X[M-k]) + i W_P^-k (X[k] - conj X[M-k]),
+//   Z'[M - k] = (X[M-k] + conj X[k]) - i W_P^k (X[M-k] - conj X[k])   (k > 0),
+// since W_P^-(M-k) = -W_P^k; thread 0 also takes k = M/2.
 template <typename T, int M1, bool EPI>
 __global__ __launch_bounds__(xr_threads<M1>()) void k_fs_xrowi(
-    const C2<T> *__restrict__ S, T *__restrict__ y, int nx, int Qs, const C2<T> *__restrict__ tw,
+    const C2<T> *__restrict__ S, T *__restrict__ y, int nx, int ny, int Qs, const C2<T> *__restrict__ tw,
     const C2<T> *__restrict__ subtw, Epi<T> ep, const double *__restrict__ done) {
     if (done && *done != 0.0) return;
-    constexpr int NTH = xr_threads<M1>(), M2 = 128, M = M1 * M2, NL = M / NTH;
-    static_assert(NL * NTH == M, "whole rows per thread set");
+    constexpr int NTH = xr_threads<M1>(), M = M1 * 128, P = 2 * M;
+    using SH = XrShape<M1, NTH>;
+    constexpr int NR = SH::NR, NP = NR / 2;
+    constexpr int RA = SH::RA, EA = SH::EA;
+    static_assert(NR * NTH == M && P / NTH <= 32, "whole rows per thread set");
     __shared__ C2<T> buf[M1 * kXrLS];
-    const long row = blockIdx.x;
-    const C2<T> *srow = S + row * Qs;
-    {
-        // Z'[k] = (X[k] + conj X[M-k]) + i W_P^-k (X[k] - conj X[M-k]), k < M, straight from the row
-        C2<T> zl[NL];
+    __shared__ C2<T> twl[kXrTw];
+    xr_load_tw<T>(twl, tw, subtw);
+    const int row = blockIdx.x;
+    const C2<T> *srow = S + (long)row * Qs;
+    C2<T> xa[NP], xb[NP];
 #pragma unroll
-        for (int i = 0; i < NL; ++i) {
-            const int k = threadIdx.x + NTH * i;
-            const C2<T> a = srow[k], b = srow[M - k];
-            const C2<T> sm = mk<T>(a.x + b.x, a.y - b.y);
-            const C2<T> df = mk<T>(a.x - b.x, a.y + b.y);
-            const C2<T> wd = cmul<T>(df, cconj<T>(tw[k]));
-            zl[i] = mk<T>(sm.x - wd.y, sm.y + wd.x);
-        }
+    for (int i = 0; i < NP; ++i) {
+        const int k = threadIdx.x + NTH * i;
+        xa[i] = srow[k];
+        xb[i] = srow[M - k];
+    }
+    const C2<T> xh = srow[M / 2];
+    __syncthreads();  // twl complete
+    const C2<T> wt = xr_wp<T, M1>(twl, threadIdx.x);
 #pragma unroll
-        for (int i = 0; i < NL; ++i) {
-            const int k = threadIdx.x + NTH * i;
-            buf[xr_addr(k % M1, k / M1)] = zl[i];
+    for (int i = 0; i < NP; ++i) {
+        const int k = threadIdx.x + NTH * i;
+        const C2<T> a = xa[i], b = xb[i], w = cmul<T>(wt, twl[fs_tw_off(P / NTH) + i]);
+        const C2<T> wd = cmul<T>(mk<T>(a.x - b.x, a.y + b.y), cconj<T>(w));
+        buf[xr_addr(k % M1, k / M1)] = mk<T>(a.x + b.x - wd.y, a.y - b.y + wd.x);
+        if (k > 0) {
+            const C2<T> we = cmul<T>(mk<T>(b.x - a.x, b.y + a.y), w);
+            const int km = M - k;
+            buf[xr_addr(km % M1, km / M1)] = mk<T>(b.x + a.x + we.y, b.y - a.y - we.x);
         }
     }
+    if (threadIdx.x == 0) {
+        const C2<T> wd = cmul<T>(mk<T>(T(0), xh.y + xh.y), cconj<T>(xr_wp<T, M1>(twl, M / 2)));
+        buf[xr_addr((M / 2) % M1, (M / 2) / M1)] = mk<T>(xh.x + xh.x - wd.y, wd.x);
+    }
     __syncthreads();
-    xr_transform<T, M1, NTH, true>(buf, tw, subtw);
-    __syncthreads();
-    T *yr = y + row * nx;
-    for (int m = threadIdx.x; 2 * m < nx; m += NTH) {
-        const C2<T> z = buf[xr_addr(m / M2, m % M2)];
+    // epilogue reads at the thread's output positions (slots below M/2 only)
+    const long r0 = (long)row * nx;
+    T e1[RA][EA][2], e2[RA][EA][2];
+    auto epi_loads = [&] {
+        if constexpr (EPI) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int p = 2 * m + h;
-            if (p >= nx) break;
-            T v = h ? z.y : z.x;
-            if constexpr (EPI) {
-                const long idx = row * nx + p;
-                v *= ep.scale;
-                if (ep.w1) v += ep.a1 * ep.w1[idx];
-                if (ep.w2) v += ep.a2 * ep.w2[idx];
+            for (int rr = 0; rr < RA; ++rr)
+#pragma unroll
+                for (int j = 0; j < EA; ++j) {
+                    if (!SH::low(j)) continue;
+                    const int m = SH::point(rr, j);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int p = 2 * m + h;
+                        const bool ok = p < nx;
+                        e1[rr][j][h] = ep.w1 ? ep.w1[r0 + (ok ? p : 0)] : T(0);
+                        e2[rr][j][h] = ep.w2 ? ep.w2[r0 + (ok ? p : 0)] : T(0);
+                    }
+                }
+        }
+    };
+    C2<T> zo[NR];
+    xr_transform<T, M1, NTH, true>(buf, twl, zo, epi_loads);
+    T *yr = y + r0;
+#pragma unroll
+    for (int rr = 0; rr < RA; ++rr)
+#pragma unroll
+        for (int j = 0; j < EA; ++j) {
+            if (!SH::low(j)) continue;  // m >= M/2: past nx
+            const int m = SH::point(rr, j);
+            const C2<T> z = zo[rr * EA + j];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int p = 2 * m + h;
+                if (p < nx) {
+                    T v = h ? z.y : z.x;
+                    if constexpr (EPI) v = v * ep.scale + ep.a1 * e1[rr][j][h] + ep.a2 * e2[rr][j][h];
+                    yr[p] = v;
+                }
             }
-            yr[p] = v;
         }
-    }
 }
 
 // ya: y step 1 over the columns (a workgroup: kFsLines adjacent columns and one
@@ -375,6 +489,22 @@ inline void fs_split(int P, int &P1, int &P2) {
     P1 = P / P2;
 }
 
+// workgroups of a persistent launch over `items`: as many as the device keeps
+// resident (from the occupancy calculator, cached per device), at most items
+template <auto K> static int fs_grid(int threads, int items) {
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (cache[dev] == 0) {
+        int cus = 0, per = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, K, threads, 0) != hipSuccess || cus * per <= 0)
+            return items;  // one workgroup per item: correct at any grid
+        cache[dev] = cus * per;
+    }
+    return cache[dev] < items ? cache[dev] : items;
+}
+
 template <typename T, int P1, int P2>
 static fl_status fs_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, const double *done, hipStream_t s,
                            const T *lam, bool odd, const C2<T> *tw, const C2<T> *subtw) {
@@ -388,10 +518,15 @@ static fl_status fs_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, const d
     C2<T> *Tb = (C2<T> *)op->T1;  // P x Qs: the y passes' transposed-order spectra
     C2<T> *S = (C2<T> *)op->T2;   // ny x Qs: the rows' half spectra
     const dim3 b1(fs_threads<P1>()), b2(fs_threads<P2>()), bx(xr_threads<M1>());
-    if (odd)
-        hipLaunchKernelGGL((k_fs_xrow<T, M1, true>), dim3(ny), bx, 0, s, u, S, nx, Qs, tw, subtw, done);
-    else
-        hipLaunchKernelGGL((k_fs_xrow<T, M1, false>), dim3(ny), bx, 0, s, u, S, nx, Qs, tw, subtw, done);
+    // row kernels with prefetch: as many workgroups as stay resident, each
+    // looping over rows; without it one row per workgroup
+    if (odd) {
+        const int g = xr_prefetch<T, M1, true, false>() ? fs_grid<k_fs_xrow<T, M1, true>>(xr_threads<M1>(), ny) : ny;
+        hipLaunchKernelGGL((k_fs_xrow<T, M1, true>), dim3(g), bx, 0, s, u, S, nx, ny, Qs, tw, subtw, done);
+    } else {
+        const int g = xr_prefetch<T, M1, false, false>() ? fs_grid<k_fs_xrow<T, M1, false>>(xr_threads<M1>(), ny) : ny;
+        hipLaunchKernelGGL((k_fs_xrow<T, M1, false>), dim3(g), bx, 0, s, u, S, nx, ny, Qs, tw, subtw, done);
+    }
     if (odd)
         hipLaunchKernelGGL((k_fs_ya<T, P1, P2, true>), dim3(Qs / kFsLines, P2), b1, 0, s, S, Tb, ny, Qs, tw, subtw,
                            done);
@@ -401,8 +536,8 @@ static fl_status fs_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, const d
     hipLaunchKernelGGL((k_fs_ymid<T, P1, P2>), dim3(Qs / kFsLines, P1), b2, 0, s, Tb, Q, Qs, lam, subtw, done);
     hipLaunchKernelGGL((k_fs_yai<T, P1, P2>), dim3(Qs / kFsLines, P2), b1, 0, s, Tb, S, ny, Qs, tw, subtw, done);
     if (ep.active())
-        hipLaunchKernelGGL((k_fs_xrowi<T, M1, true>), dim3(ny), bx, 0, s, S, y, nx, Qs, tw, subtw, ep, done);
+        hipLaunchKernelGGL((k_fs_xrowi<T, M1, true>), dim3(ny), bx, 0, s, S, y, nx, ny, Qs, tw, subtw, ep, done);
     else
-        hipLaunchKernelGGL((k_fs_xrowi<T, M1, false>), dim3(ny), bx, 0, s, S, y, nx, Qs, tw, subtw, ep, done);
+        hipLaunchKernelGGL((k_fs_xrowi<T, M1, false>), dim3(ny), bx, 0, s, S, y, nx, ny, Qs, tw, subtw, ep, done);
     return FL_OK;
 }
