@@ -73,9 +73,11 @@ template <typename T, int M1> __device__ __forceinline__ C2<T> xr_wp(const C2<T>
 // threadIdx.x / LPA) holds, in slot rr * EA + j, the point m = 128 a + b of
 // line b = rr * LPA + c at a = in_pos<M1, PA, 0>(tl, j) -- the inputs of its
 // step-A butterflies going forward and their outputs coming back.
+// At M1 = 64 (512 threads) both steps take 16 points per thread: one round of
+// 128 (64) lines and one LDS exchange per step; shorter rows take 8.
 template <int M1, int NTH> struct XrShape {
-    using PA = typename FsPlan<M1>::PN;
-    using PB = typename FsPlan<128>::PN;
+    using PA = Plan<M1, M1 == 64 ? 16 : 8>;
+    using PB = Plan<128, M1 == 64 ? 16 : 8>;
     static constexpr int EA = PA::E, TLA = M1 / EA, LA = PA::L, EB = PB::E, TLB = 128 / EB, LB = PB::L;
     static constexpr int LPA = NTH / TLA, RA = 128 / LPA, LPB = NTH / TLB, RB = M1 / LPB;
     static constexpr int NR = RA * EA;  // register slots of a row
