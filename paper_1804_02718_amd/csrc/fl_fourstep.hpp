@@ -90,7 +90,10 @@ template <int M1, int NTH> struct XrShape {
     static constexpr bool low(int j) { return (j % PA::R[0]) < PA::R[0] / 2; }
 };
 
-// z of one row (zero-padded, or its odd extension, to P) into step A's registers
+// z of one row (zero-padded, or its odd extension, to P) into step A's
+// registers, in two parts: xr_load_za issues the loads (clamped addresses, the
+// raw values), xr_fix_za zeroes or negates what lies outside the stored values.
+// Split so that a prefetch's loads are not waited for where they are issued.
 template <typename T, int M1, int NTH, bool ODD>
 __device__ __forceinline__ void xr_load_za(C2<T> *zl, const T *__restrict__ ur, int nx) {
     using S = XrShape<M1, NTH>;
@@ -99,27 +102,48 @@ __device__ __forceinline__ void xr_load_za(C2<T> *zl, const T *__restrict__ ur, 
     for (int rr = 0; rr < S::RA; ++rr)
 #pragma unroll
         for (int j = 0; j < S::EA; ++j) {
+            if (!ODD && !S::low(j)) continue;  // m >= P/4: past every stored value
             const int m = S::point(rr, j);
             T e2[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int p = 2 * m + h;
                 if constexpr (!ODD) {
-                    if (S::low(j)) {
-                        const bool ok = p < nx;
-                        const T x = ur[ok ? p : 0];
-                        e2[h] = ok ? x : T(0);
-                    } else {
-                        e2[h] = T(0);  // m >= P/4: past every stored value
-                    }
+                    e2[h] = ur[p < nx ? p : 0];
                 } else {
                     const int q = P - 2 - p;
-                    const bool lo = p < nx, hi = q >= 0 && q < nx;
-                    const T x = ur[lo ? p : (hi ? q : 0)];
-                    e2[h] = lo ? x : (hi ? -x : T(0));
+                    e2[h] = ur[p < nx ? p : (q >= 0 && q < nx ? q : 0)];
                 }
             }
             zl[rr * S::EA + j] = mk<T>(e2[0], e2[1]);
+        }
+}
+template <typename T, int M1, int NTH, bool ODD>
+__device__ __forceinline__ void xr_fix_za(C2<T> *zl, int nx) {
+    using S = XrShape<M1, NTH>;
+    constexpr int P = 256 * M1;
+#pragma unroll
+    for (int rr = 0; rr < S::RA; ++rr)
+#pragma unroll
+        for (int j = 0; j < S::EA; ++j) {
+            C2<T> &z = zl[rr * S::EA + j];
+            if (!ODD && !S::low(j)) {
+                z = mk<T>(T(0), T(0));
+                continue;
+            }
+            const int m = S::point(rr, j);
+            T e2[2] = {z.x, z.y};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int p = 2 * m + h;
+                if constexpr (!ODD) {
+                    e2[h] = p < nx ? e2[h] : T(0);
+                } else {
+                    const int q = P - 2 - p;
+                    e2[h] = p < nx ? e2[h] : (q >= 0 && q < nx ? -e2[h] : T(0));
+                }
+            }
+            z = mk<T>(e2[0], e2[1]);
         }
 }
 
@@ -236,6 +260,7 @@ __global__ __launch_bounds__(xr_threads<M1>()) void k_fs_xrow(
     const C2<T> wt = xr_wp<T, M1>(twl, threadIdx.x);
     C2<T> zl[NR];
     auto body = [&](int row, auto mid) {
+        xr_fix_za<T, M1, NTH, ODD>(zl, nx);
         xr_transform<T, M1, NTH, false>(buf, twl, zl, mid);
         __syncthreads();
         C2<T> *srow = S + (long)row * Qs;
