@@ -90,6 +90,10 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xfwd(
     const int bx = xcd_block(blockIdx.x, gridDim.x);
     const int ra = 2 * (bx * LPB + lp), rb = ra + 1;
     const bool va = ra < nrows, vb = rb < nrows;
+    // twiddles first: the waits for the data below (each value is masked as
+    // it arrives) then cover their latency too
+    C2<T> tws[num_tw<PN>()];
+    load_twiddles_lanes<T, P, PN>(tws, table, tl);
     C2<T> v[E];
     // loads from clamped, always valid addresses; rows past nrows read as 0
     const T *ua = u + (long)(va ? ra : 0) * in_pitch, *ub = u + (long)(vb ? rb : 0) * in_pitch;
@@ -97,9 +101,6 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xfwd(
         const T xa = ua[i], xb = ub[i];
         return mk<T>(va ? xa : T(0), vb ? xb : T(0));
     });
-    // twiddles after the data: the first stage needs none of them
-    C2<T> tws[num_tw<PN>()];
-    load_twiddles_lanes<T, P, PN>(tws, table, tl);
     const int base = lp * PL;
     auto lidx = [base](int pos) { return base + padpos(pos); };
     fwd_stages<T, P, PN, 0>(v, lds, tl, tws, lidx);
@@ -202,12 +203,21 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xinv(
             C2<T> *lrow = lds + (rr >> 1) * LL + (rr & 1) * Q;
             constexpr int NT = ((PACK ? P / 2 : P / 2 + 1) + C - 1) / C, ST = NTH / (C * RW);
             const int t0 = threadIdx.x / (C * RW);
+            // every load issued (clamped addresses) before the first is used
+            constexpr int NIT = (NT + ST - 1) / ST;
+            C2<T> xs[NIT];
 #pragma unroll
-            for (int it = 0; it < (NT + ST - 1) / ST; ++it) {
+            for (int it = 0; it < NIT; ++it) {
+                const int t = t0 + it * ST;
+                const bool ok = t < NT && t * C + c < (PACK ? P / 2 : Q);
+                xs[it] = irow[(ok ? t : 0) * tstride];
+            }
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
                 const int t = t0 + it * ST;
                 const int kx = t * C + c;
                 if (t >= NT || kx >= (PACK ? P / 2 : Q)) continue;
-                const C2<T> x = keep<T>(rv, irow[t * tstride]);
+                const C2<T> x = keep<T>(rv, xs[it]);
                 if (PACK && kx == 0) {
                     lrow[0] = mk<T>(x.x, 0);
                     lrow[P / 2] = mk<T>(x.y, 0);
@@ -462,25 +472,23 @@ void k_strided(
         load_twiddles_lanes<T, P, PN>(tws, table, tl);
         adj_stages<T, P, PN, L - 1>(v, lds, tl, tws, lidx);
     } else {
-        load_line<T, P, PN>(v, tl, n_in, [&](int i) { return keep<T>(valid, src[i * st.line]); });
-        // twiddles after the data: the first stage needs none of them
+        // twiddles and (MODE 2) lambda first: the waits for the data below
+        // (each value is masked as it arrives) then cover their latency too
         load_twiddles_lanes<T, P, PN>(tws, table, tl);
+        T lv[E], ldv[E];
         if constexpr (MODE == 2) {
-            // lambda at this thread's spectral positions, fetched with the data
-            T lv[E];
+            // lambda at this thread's spectral positions
             const T *lo = lam + (t * st.lam_tile + fold<P>(o) * st.lam_outer + c);
 #pragma unroll
             for (int j = 0; j < E; ++j) lv[j] = lo[fold<P>(out_pos<P, PN, L - 1>(tl, j)) * C];
-            // the packed column's second symbol d, fetched with the first so its
-            // latency overlaps the forward transform; zero off column 0
-            T ldv[E];
+            // the packed column's second symbol d (applied on column 0 only)
             if (PACK && t == 0) {
 #pragma unroll
-                for (int j = 0; j < E; ++j) {
-                    const T d = lam[st.lam_pack + fold<P>(out_pos<P, PN, L - 1>(tl, j))];
-                    ldv[j] = c == 0 ? d : T(0);
-                }
+                for (int j = 0; j < E; ++j) ldv[j] = lam[st.lam_pack + fold<P>(out_pos<P, PN, L - 1>(tl, j))];
             }
+        }
+        load_line<T, P, PN>(v, tl, n_in, [&](int i) { return keep<T>(valid, src[i * st.line]); });
+        if constexpr (MODE == 2) {
             fwd_stages<T, P, PN, 0>(v, lds, tl, tws, lidx);
             if (PACK && t == 0) {  // block-uniform: the tile holding the packed column
                 // every lane exchanges and applies s Z(k) + d conj Z(-k) without a
@@ -493,7 +501,8 @@ void k_strided(
                 for (int j = 0; j < E; ++j) {
                     const int pos = out_pos<P, PN, L - 1>(tl, j);
                     const C2<T> zm = lds[lidx((P - pos) & (P - 1))];
-                    v[j] = mk<T>(lv[j] * v[j].x + ldv[j] * zm.x, lv[j] * v[j].y - ldv[j] * zm.y);
+                    const T d = c == 0 ? ldv[j] : T(0);
+                    v[j] = mk<T>(lv[j] * v[j].x + d * zm.x, lv[j] * v[j].y - d * zm.y);
                 }
                 __syncthreads();
             } else {
