@@ -331,8 +331,13 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_conv1d(
     const int bx = blockIdx.x;
     const int ra = 2 * (bx * LPB + lp), rb = ra + 1;
     const bool va = ra < nrows, vb = rb < nrows;
+    // twiddles and lambda first: the waits for the data below (each value is
+    // masked as it arrives) then cover their latency too
     C2<T> tws[num_tw<PN>()];
     load_twiddles_lanes<T, P, PN>(tws, table, tl);
+    T lv[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) lv[j] = lam[fold<P>(out_pos<P, PN, L - 1>(tl, j))];
     C2<T> v[E];
     // loads from clamped, always valid addresses; out-of-range values replaced by 0
     const T *ua = u + (long)(va ? ra : 0) * n, *ub = u + (long)(vb ? rb : 0) * n;
@@ -344,7 +349,7 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_conv1d(
     auto lidx = [base](int pos) { return base + padpos(pos); };
     fwd_stages<T, P, PN, 0>(v, lds, tl, tws, lidx);
 #pragma unroll
-    for (int j = 0; j < E; ++j) v[j] = cscale<T>(v[j], lam[fold<P>(out_pos<P, PN, L - 1>(tl, j))]);
+    for (int j = 0; j < E; ++j) v[j] = cscale<T>(v[j], lv[j]);
     adj_stages<T, P, PN, L - 1>(v, lds, tl, tws, lidx);
     double acc = 0.0;  // epilogue dot (dotw, y) over this thread's outputs
     if (va) {
@@ -802,9 +807,10 @@ template <> const Variant<double> *variants<double>(int P, int d, int *count) {
                                         FL_VAR(T, 512, 2, 8, 8, 2, 2)};
     static const Variant<T> v2_1024[] = {FL_DEF(T, 1024, 2), FL_VAR(T, 1024, 2, 8, 8, 2, 2),
                                          FL_VAR(T, 1024, 2, 4, 4, 2, 1)};
-    // measured fastest first (MI355X, 2D N=1024)
-    static const Variant<T> v2_2048[] = {FL_VAR(T, 2048, 2, 8, 16, 2, 1), FL_VARW(T, 2048, 2), FL_DEF(T, 2048, 2),
-                                         FL_VAR(T, 2048, 2, 8, 8, 2, 1), FL_VAR(T, 2048, 2, 8, 8, 2, 2),
+    // measured fastest first (MI355X, 2D N=1024): 8 points per thread in every
+    // pass, tiles of 2 columns
+    static const Variant<T> v2_2048[] = {FL_VAR(T, 2048, 2, 8, 8, 2, 1), FL_VARW(T, 2048, 2), FL_DEF(T, 2048, 2),
+                                         FL_VAR(T, 2048, 2, 8, 16, 2, 1), FL_VAR(T, 2048, 2, 8, 8, 2, 2),
                                          FL_VAR(T, 2048, 2, 4, 4, 2, 1)};
     static const Variant<T> v3_8[] = {FL_DEF(T, 8, 3)};
     static const Variant<T> v3_16[] = {FL_DEF(T, 16, 3)};
