@@ -102,11 +102,11 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xfwd(
         return mk<T>(va ? xa : T(0), vb ? xb : T(0));
     });
     const int base = lp * PL;
-    auto lidx = [base](int pos) { return base + padpos(pos); };
+    auto lidx = [base](auto pos) { return base + padpos(pos); };
     fwd_stages<T, P, PN, 0>(v, lds, tl, tws, lidx);
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < E; ++j) lds[lidx(out_pos<P, PN, L - 1>(tl, j))] = v[j];
+    for (int j = 0; j < E; ++j) lds[lidx(out_split<P, PN, L - 1>(tl, j))] = v[j];
     __syncthreads();
     // Hermitian split, written tile by tile: consecutive threads cover the
     // block's rows of one tile, which are contiguous in the tiled layout
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_xinv(
     }
     __syncthreads();
     const int base = lp * LL;
-    auto lidx = [base](int pos) { return base + padpos(pos); };
+    auto lidx = [base](auto pos) { return base + padpos(pos); };
     adj_stages<T, P, PN, L - 1>(v, lds, tl, tws, lidx);
     double acc = 0.0;  // epilogue dot (dotw, y) over this thread's outputs
     if (va) {
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(LPB * (P / E)) void k_conv1d(
         return mk<T>(va ? xa : T(0), vb ? xb : T(0));
     });
     const int base = lp * PL;
-    auto lidx = [base](int pos) { return base + padpos(pos); };
+    auto lidx = [base](auto pos) { return base + padpos(pos); };
     fwd_stages<T, P, PN, 0>(v, lds, tl, tws, lidx);
 #pragma unroll
     for (int j = 0; j < E; ++j) v[j] = cscale<T>(v[j], lv[j]);
@@ -466,7 +466,7 @@ void k_strided(
     C2<T> *dst = out + (o * st.out_outer + t * st.out_tile + c);
     C2<T> tws[num_tw<PN>()];
     C2<T> v[E];
-    auto lidx = [c](int pos) { return padpos(pos) * C + c; };
+    auto lidx = [c](auto pos) { return padpos(pos) * C + c; };
     if constexpr (MODE == 1) {
 #pragma unroll
         for (int j = 0; j < E; ++j) {
@@ -500,7 +500,7 @@ void k_strided(
                 // branch (d = 0 off column 0); the forward stages end with all of
                 // their LDS reads behind a barrier, so the writes need none before
 #pragma unroll
-                for (int j = 0; j < E; ++j) lds[lidx(out_pos<P, PN, L - 1>(tl, j))] = v[j];
+                for (int j = 0; j < E; ++j) lds[lidx(out_split<P, PN, L - 1>(tl, j))] = v[j];
                 __syncthreads();
 #pragma unroll
                 for (int j = 0; j < E; ++j) {

@@ -197,23 +197,23 @@ __device__ __forceinline__ void xr_transform(C2<T> *buf, const C2<T> *twl, C2<T>
         for (int rr = 0; rr < RB; ++rr) {
             const int k1 = rr * LPB + c;
             C2<T> v[EB];
-            auto lidx = [k1](int pos) { return xr_addr(k1, pos); };
+            auto lidx = [k1](auto pos) { return k1 * kXrLS + padpos(pos); };
             if constexpr (!INV) {
 #pragma unroll
-                for (int j = 0; j < EB; ++j) v[j] = buf[lidx(in_pos<M2, PB, 0>(tl, j))];
+                for (int j = 0; j < EB; ++j) v[j] = buf[lidx(in_split<M2, PB, 0>(tl, j))];
                 __syncthreads();
                 fwd_stages<T, M2, PB, 0>(v, buf, tl, tws, lidx);
 #pragma unroll
-                for (int j = 0; j < EB; ++j) buf[lidx(out_pos<M2, PB, LB - 1>(tl, j))] = v[j];
+                for (int j = 0; j < EB; ++j) buf[lidx(out_split<M2, PB, LB - 1>(tl, j))] = v[j];
             } else {
 #pragma unroll
-                for (int j = 0; j < EB; ++j) v[j] = buf[lidx(out_pos<M2, PB, LB - 1>(tl, j))];
+                for (int j = 0; j < EB; ++j) v[j] = buf[lidx(out_split<M2, PB, LB - 1>(tl, j))];
                 __syncthreads();
                 adj_stages<T, M2, PB, LB - 1>(v, buf, tl, tws, lidx);
 #pragma unroll
                 for (int j = 0; j < EB; ++j) {
                     const int b = in_pos<M2, PB, 0>(tl, j);
-                    buf[lidx(b)] = cmul<T>(v[j], cconj<T>(xr_wm<T, M1>(twl, b * k1)));
+                    buf[lidx(in_split<M2, PB, 0>(tl, j))] = cmul<T>(v[j], cconj<T>(xr_wm<T, M1>(twl, b * k1)));
                 }
             }
         }
@@ -423,7 +423,7 @@ __global__ __launch_bounds__(fs_threads<P1>()) void k_fs_ya(
     }
     C2<T> tws[num_tw<PN>()];
     load_twiddles<T, P1, PN>(tws, subtw + fs_tw_off(P1), tl);
-    auto lidx = [c](int pos) { return padpos(pos) * NL + c; };
+    auto lidx = [c](auto pos) { return padpos(pos) * NL + c; };
     fwd_stages<T, P1, PN, 0>(v, lds, tl, tws, lidx);
 #pragma unroll
     for (int j = 0; j < E; ++j) {
@@ -460,7 +460,7 @@ __global__ __launch_bounds__(fs_threads<P2>()) void k_fs_ymid(
         const int ky = k1 + P1 * out_pos<P2, PN, L - 1>(tl, j);
         lv[j] = lc[(long)(ky <= P / 2 ? ky : P - ky) * Q];
     }
-    auto lidx = [c](int pos) { return padpos(pos) * NL + c; };
+    auto lidx = [c](auto pos) { return padpos(pos) * NL + c; };
     fwd_stages<T, P2, PN, 0>(v, lds, tl, tws, lidx);
 #pragma unroll
     for (int j = 0; j < E; ++j) v[j] = cscale<T>(v[j], lv[j]);
@@ -490,7 +490,7 @@ __global__ __launch_bounds__(fs_threads<P1>()) void k_fs_yai(
     }
     C2<T> tws[num_tw<PN>()];
     load_twiddles<T, P1, PN>(tws, subtw + fs_tw_off(P1), tl);
-    auto lidx = [c](int pos) { return padpos(pos) * NL + c; };
+    auto lidx = [c](auto pos) { return padpos(pos) * NL + c; };
     adj_stages<T, P1, PN, L - 1>(v, lds, tl, tws, lidx);
 #pragma unroll
     for (int j = 0; j < E; ++j) {

@@ -302,6 +302,43 @@ __device__ __forceinline__ void load_twiddles_lanes(C2<T> *tws, const C2<T> *__r
     }
 }
 
+// LDS padding: one slot per 16 positions breaks the stride-R bank pattern of
+// the early stages' stores
+__device__ __forceinline__ int padpos(int pos) { return pos + (pos >> 4); }
+template <int P> constexpr int padded_len() { return P + P / 16; }
+
+// A stage position split as a + k: a from the thread index, k constant once
+// the register slot j is (the slot loops unroll).  When a or k is a multiple
+// of 16, padpos(a + k) = padpos(a) + padpos(k), so every slot's LDS address
+// is one per-thread base plus an immediate offset.
+struct SplitPos {
+    int a, k;
+    bool exact;
+    __device__ operator int() const { return a + k; }
+};
+__device__ __forceinline__ int padpos(SplitPos p) { return p.exact ? padpos(p.a) + padpos(p.k) : padpos(p.a + p.k); }
+template <int P, typename PL, int S> __device__ __forceinline__ SplitPos in_split(int tl, int j) {
+    constexpr int R = PL::R[S], TL = P / PL::E;
+    const int k = (j / R) * TL + (j % R) * (P / R);
+    return SplitPos{tl, k, k % 16 == 0};
+}
+template <int P, typename PL, int S> __device__ __forceinline__ SplitPos out_split(int tl, int j) {
+    constexpr int R = PL::R[S], TL = P / PL::E, Ns = stage_ns<PL>(S), NB = PL::E / R;
+    const int i = j / R, r = j % R;
+    if constexpr (TL % Ns == 0) {
+        // b = tl + i TL: b / Ns = tl / Ns + i TL / Ns, b mod Ns = tl mod Ns
+        const int k = i * TL * R + r * Ns;
+        constexpr bool a16 = Ns == 1 && R % 16 == 0;  // a = tl R
+        return SplitPos{(tl / Ns) * Ns * R + tl % Ns, k, a16 || k % 16 == 0};
+    } else if constexpr (Ns % TL == 0 && NB * TL <= Ns) {
+        // b = tl + i TL < Ns: the position is b + r Ns
+        const int k = i * TL + r * Ns;
+        return SplitPos{tl, k, k % 16 == 0};
+    } else {
+        return SplitPos{out_pos<P, PL, S>(tl, j), 0, true};
+    }
+}
+
 // forward butterflies of stage S (twiddle, then DFT with exp(-2 pi i ...))
 template <typename T, typename PL, int S>
 __device__ __forceinline__ void fwd_bfly(C2<T> *v, const C2<T> *tws) {
@@ -338,10 +375,10 @@ __device__ __forceinline__ void fwd_stages(C2<T> *v, C2<T> *lds, int tl, const C
     if constexpr (S + 1 < PL::L) {
         constexpr int E = PL::E;
 #pragma unroll
-        for (int j = 0; j < E; ++j) lds[lidx(out_pos<P, PL, S>(tl, j))] = v[j];
+        for (int j = 0; j < E; ++j) lds[lidx(out_split<P, PL, S>(tl, j))] = v[j];
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < E; ++j) v[j] = lds[lidx(in_pos<P, PL, S + 1>(tl, j))];
+        for (int j = 0; j < E; ++j) v[j] = lds[lidx(in_split<P, PL, S + 1>(tl, j))];
         __syncthreads();
         fwd_stages<T, P, PL, S + 1>(v, lds, tl, tws, lidx);
     }
@@ -353,19 +390,15 @@ __device__ __forceinline__ void adj_stages(C2<T> *v, C2<T> *lds, int tl, const C
     if constexpr (S > 0) {
         constexpr int E = PL::E;
 #pragma unroll
-        for (int j = 0; j < E; ++j) lds[lidx(in_pos<P, PL, S>(tl, j))] = v[j];
+        for (int j = 0; j < E; ++j) lds[lidx(in_split<P, PL, S>(tl, j))] = v[j];
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < E; ++j) v[j] = lds[lidx(out_pos<P, PL, S - 1>(tl, j))];
+        for (int j = 0; j < E; ++j) v[j] = lds[lidx(out_split<P, PL, S - 1>(tl, j))];
         __syncthreads();
         adj_stages<T, P, PL, S - 1>(v, lds, tl, tws, lidx);
     }
 }
 
-// LDS padding: one slot per 16 positions breaks the stride-R bank pattern of
-// the early stages' stores
-__device__ __forceinline__ int padpos(int pos) { return pos + (pos >> 4); }
-template <int P> constexpr int padded_len() { return P + P / 16; }
 
 }  // namespace fl
 
