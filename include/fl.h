@@ -307,11 +307,13 @@ fl_status fl_apply_profiled(fl_op op, const void *u, void *y, int prec, int reps
  *                        kind 1 (2D): one wavefront per FFT line, four rows per
  *                        row-pass workgroup.
  *   fl_select_variant -- use variant k for prec on this operator (synchronises).
- *   fl_autotune       -- time every variant (reps matvecs each, HIP events, on
- *                        `stream`, scratch vectors allocated and freed inside),
- *                        select the fastest, return its index in *best and, if
- *                        ms_per_variant (host, count floats) is non-null, the
- *                        average milliseconds per matvec of each variant.
+ *   fl_autotune       -- time every variant (two rounds over the variants of
+ *                        reps matvecs each, HIP events, on `stream`, scratch
+ *                        vectors allocated and freed inside), select the
+ *                        fastest, return its index in *best and, if
+ *                        ms_per_variant (host, count floats) is non-null, each
+ *                        variant's average milliseconds per matvec (the
+ *                        smaller of its two rounds).
  */
 fl_status fl_variant_count(fl_op op, int prec, int *count);
 fl_status fl_variant_info(fl_op op, int prec, int k, int *desc);

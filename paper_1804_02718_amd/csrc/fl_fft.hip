@@ -750,9 +750,9 @@ template <> const Variant<float> *variants<float>(int P, int d, int *count) {
     static const Variant<T> v3_64[] = {FL_DEF(T, 64, 3)};
     static const Variant<T> v3_128[] = {FL_DEF(T, 128, 3)};
     static const Variant<T> v3_256[] = {FL_DEF(T, 256, 3), FL_VAR(T, 256, 3, 8, 8, 16, 2)};
-    // measured fastest first (MI355X, 3D N=256: 8 points per thread in the row passes,
-    // 16 in the strided passes over tiles of 8 columns)
-    static const Variant<T> v3_512[] = {FL_VAR(T, 512, 3, 8, 16, 8, 4), FL_VAR(T, 512, 3, 16, 16, 8, 4),
+    // measured fastest first (MI355X, 3D N=256: 16 points per thread in every pass,
+    // tiles of 8 columns)
+    static const Variant<T> v3_512[] = {FL_VAR(T, 512, 3, 16, 16, 8, 4), FL_VAR(T, 512, 3, 8, 16, 8, 4),
                                         FL_VAR(T, 512, 3, 8, 8, 8, 4), FL_DEF(T, 512, 3),
                                         FL_VAR(T, 512, 3, 8, 8, 16, 4), FL_VAR(T, 512, 3, 16, 8, 16, 8),
                                         FL_VAR(T, 512, 3, 8, 16, 16, 4)};
@@ -818,9 +818,10 @@ template <> const Variant<double> *variants<double>(int P, int d, int *count) {
     static const Variant<T> v3_64[] = {FL_DEF(T, 64, 3)};
     static const Variant<T> v3_128[] = {FL_DEF(T, 128, 3)};
     static const Variant<T> v3_256[] = {FL_DEF(T, 256, 3)};
-    // measured fastest first (MI355X, 3D N=256)
-    static const Variant<T> v3_512[] = {FL_VAR(T, 512, 3, 8, 16, 4, 2), FL_VAR(T, 512, 3, 8, 8, 4, 2),
-                                        FL_VAR(T, 512, 3, 8, 16, 8, 2), FL_DEF(T, 512, 3),
+    // measured fastest first (MI355X, 3D N=256: the default shape, 16 points per
+    // thread in every pass over tiles of 8 columns)
+    static const Variant<T> v3_512[] = {FL_DEF(T, 512, 3), FL_VAR(T, 512, 3, 8, 16, 4, 2),
+                                        FL_VAR(T, 512, 3, 8, 8, 4, 2), FL_VAR(T, 512, 3, 8, 16, 8, 2),
                                         FL_VAR(T, 512, 3, 8, 8, 8, 2)};
     static const Variant<T> v3_1024[] = {FL_DEF(T, 1024, 3)};
     if (d == 1) {
