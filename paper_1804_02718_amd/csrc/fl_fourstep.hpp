@@ -231,15 +231,15 @@ __device__ __forceinline__ void xr_transform(C2<T> *buf, const C2<T> *twl, C2<T>
     }
 }
 
-// The row kernels take rows b, b + gridDim.x, ... (workgroup b).  With PF
-// (FP64 at P = 16384: one 145 KB workgroup per CU) the next row's loads are
-// issued once step A has consumed the current row's registers and arrive
-// during step B and the split; the transform reads its twiddles from LDS, so
-// no other global load waits behind them.  Without PF (two or more workgroups
-// per CU overlap instead) a workgroup takes one row.
-template <typename T, int M1, bool ODD, bool INV> constexpr bool xr_prefetch() {
-    return sizeof(T) == 8 && M1 == 64 && !ODD && !INV;
-}
+// PF: the forward row kernel's workgroups take rows b, b + gridDim.x, ...
+// (FP64 at P = 16384, zero-padded rows: one 145 KB workgroup per CU) and the
+// next row's loads are issued once step A has consumed the current row's
+// registers, arriving during step B and the split; the transform reads its
+// twiddles from LDS, so no other global load waits behind them.  Otherwise
+// (two or more workgroups per CU overlap instead, or the odd extension's
+// loads would not fit the registers) a workgroup takes one row, as the
+// inverse always does (a prefetch of its spectra would not fit either).
+template <typename T, int M1, bool ODD> constexpr bool xr_prefetch() { return sizeof(T) == 8 && M1 == 64 && !ODD; }
 
 // x forward: z of the row into step A's registers, the transform, the split
 // into X[0..M].  Split twiddles: for k = t + NTH i (t = threadIdx.x),
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(xr_threads<M1>()) void k_fs_xrow(
     if (done && *done != 0.0) return;
     constexpr int NTH = xr_threads<M1>(), M = M1 * 128, P = 2 * M, NR = XrShape<M1, NTH>::NR;
     constexpr int NS = (M + 1 + NTH - 1) / NTH;  // split outputs X[0..M] per thread
-    constexpr bool PF = xr_prefetch<T, M1, ODD, false>();
+    constexpr bool PF = xr_prefetch<T, M1, ODD>();
     static_assert(NR * NTH == M && P / NTH <= 32, "whole rows per thread set");
     __shared__ C2<T> buf[M1 * kXrLS];
     __shared__ C2<T> twl[kXrTw];
@@ -548,10 +548,10 @@ static fl_status fs_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, const d
     // row kernels with prefetch: as many workgroups as stay resident, each
     // looping over rows; without it one row per workgroup
     if (odd) {
-        const int g = xr_prefetch<T, M1, true, false>() ? fs_grid<k_fs_xrow<T, M1, true>>(xr_threads<M1>(), ny) : ny;
+        const int g = xr_prefetch<T, M1, true>() ? fs_grid<k_fs_xrow<T, M1, true>>(xr_threads<M1>(), ny) : ny;
         hipLaunchKernelGGL((k_fs_xrow<T, M1, true>), dim3(g), bx, 0, s, u, S, nx, ny, Qs, tw, subtw, done);
     } else {
-        const int g = xr_prefetch<T, M1, false, false>() ? fs_grid<k_fs_xrow<T, M1, false>>(xr_threads<M1>(), ny) : ny;
+        const int g = xr_prefetch<T, M1, false>() ? fs_grid<k_fs_xrow<T, M1, false>>(xr_threads<M1>(), ny) : ny;
         hipLaunchKernelGGL((k_fs_xrow<T, M1, false>), dim3(g), bx, 0, s, u, S, nx, ny, Qs, tw, subtw, done);
     }
     if (odd)
