@@ -1532,6 +1532,9 @@ fl_status large_symbol(fl_op op, hipStream_t s) {
     (void)hipFree(cemb);
     FL_HIP_TRY(le);
     FL_HIP_TRY(se);
+    // the persistent row kernel's grid from the occupancy calculator, cached now
+    // so that no matvec (possibly under a caller's graph capture) queries it
+    if (P == 16384) (void)fs_grid<k_fs_xrow<double, 64, false>>(xr_threads<64>(), 1);
     return FL_OK;
 }
 
