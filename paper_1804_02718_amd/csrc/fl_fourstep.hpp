@@ -445,7 +445,11 @@ __global__ __launch_bounds__(fs_threads<P2>()) void k_fs_ymid(
     __shared__ C2<T> lds[NL * padded_len<P2>()];
     const int c = threadIdx.x % NL, tl = threadIdx.x / NL;
     const int col = blockIdx.x * NL + c;
-    const int k1 = blockIdx.y;
+    // k1 in the order 0, P1/2, 1, P1 - 1, 2, P1 - 2, ...: k1 and P1 - k1 read the
+    // same rows of lambda, and launched one after the other the second finds
+    // them in the last-level cache
+    const int q = blockIdx.y, qj = q >> 1;
+    const int k1 = q == 0 ? 0 : (q == 1 ? P1 / 2 : ((q & 1) ? P1 - qj : qj));
     C2<T> *base = Tb + (long)P2 * k1 * Qs + col;
     C2<T> v[E];
 #pragma unroll
