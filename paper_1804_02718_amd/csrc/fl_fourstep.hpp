@@ -20,14 +20,18 @@
 // order.  A row's P/2-point transform is the same factorisation inside one
 // workgroup's LDS, P/2 = M1 x 128.
 
-template <int L> struct FsPlan;
-template <> struct FsPlan<128> { using PN = Plan<128, 8>; };
-template <> struct FsPlan<64> { using PN = Plan<64, 8>; };
-template <> struct FsPlan<32> { using PN = Plan<32, 8>; };
-template <> struct FsPlan<16> { using PN = Plan<16, 8>; };
+// the y passes' short transforms: 16 points per thread at L = 128 (one LDS
+// exchange), except in the FP64 middle pass (MID), whose registers would then
+// halve its resident waves; 8 points below L = 128
+template <int L, bool MID = false, typename T = float> struct FsPlan {
+    static constexpr int E = L == 128 && !(MID && sizeof(T) == 8) ? 16 : 8;
+    using PN = Plan<L, E>;
+};
 // short column transforms per workgroup of the y passes (lines); P1, P2 are multiples of it
 constexpr int kFsLines = 32;
-template <int L> constexpr int fs_threads() { return kFsLines * (L / FsPlan<L>::PN::E); }
+template <int L, bool MID = false, typename T = float> constexpr int fs_threads() {
+    return kFsLines * (L / FsPlan<L, MID, T>::PN::E);
+}
 // the short transforms' twiddle tables exp(-2 pi i m / L), L = 128, 64, 32, 16, in one buffer
 constexpr int fs_tw_off(int L) { return L == 128 ? 0 : L == 64 ? 128 : L == 32 ? 192 : 224; }
 constexpr int kFsTwLen = 240;
@@ -436,11 +440,11 @@ __global__ __launch_bounds__(fs_threads<P1>()) void k_fs_ya(
 // P2 k1 + n2 (P2-point), lambda at ky = k1 + P1 k2 (row fold(ky) of lam,
 // natural columns, row stride Q), and the inverse of y step 2, in place
 template <typename T, int P1, int P2>
-__global__ __launch_bounds__(fs_threads<P2>()) void k_fs_ymid(
+__global__ __launch_bounds__((fs_threads<P2, true, T>())) void k_fs_ymid(
     C2<T> *__restrict__ Tb, int Q, int Qs, const T *__restrict__ lam, const C2<T> *__restrict__ subtw,
     const double *__restrict__ done) {
     if (done && *done != 0.0) return;
-    using PN = typename FsPlan<P2>::PN;
+    using PN = typename FsPlan<P2, true, T>::PN;
     constexpr int E = PN::E, L = PN::L, NL = kFsLines, P = P1 * P2;
     __shared__ C2<T> lds[NL * padded_len<P2>()];
     const int c = threadIdx.x % NL, tl = threadIdx.x / NL;
@@ -548,7 +552,7 @@ static fl_status fs_matvec(fl_op op, const T *u, T *y, const Epi<T> &ep, const d
     }
     C2<T> *Tb = (C2<T> *)op->T1;  // P x Qs: the y passes' transposed-order spectra
     C2<T> *S = (C2<T> *)op->T2;   // ny x Qs: the rows' half spectra
-    const dim3 b1(fs_threads<P1>()), b2(fs_threads<P2>()), bx(xr_threads<M1>());
+    const dim3 b1(fs_threads<P1>()), b2(fs_threads<P2, true, T>()), bx(xr_threads<M1>());
     // row kernels with prefetch: as many workgroups as stay resident, each
     // looping over rows; without it one row per workgroup
     if (odd) {
